@@ -1,0 +1,443 @@
+"""FP64 CPU oracle for fast multivariate kernel regression -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares no code with the HIP path and
+never imports the product package.  It computes what the paper's method
+computes, by the plain definitions, slowly and in FP64:
+
+* ``grid_points``   the uniform grid of eq. (6), spacing (hi - lo)/(M - 1).
+* ``moments``       the kernel-weighted moment sums of eq. (9) by direct
+                    O(N * G) summation (C library ``fkr_oracle.c``).
+* ``solve``         the local-polynomial normal equations of eq. (3)/(11):
+                    A_bc = s_{b+c}, rhs_b = t_b, equilibrated by the bandwidth
+                    and solved by LAPACK's pivoted LU (``numpy.linalg.solve``);
+                    the fit is the intercept (e_1 of eq. 3).
+* ``interp``        multilinear interpolation of a grid function (the linear
+                    ``griddedInterpolant`` setting of Sec. 5).
+* ``philox4x64``    the Philox4x64-10 counter-based generator (Salmon et al.,
+                    SC'11) and ``probes``: Box-Muller normals from it, the
+                    Gaussian probe vectors of Sec. 2.1 step i.
+* ``dof``           Girard's fast Monte-Carlo estimate of (1/N) tr(I - S_h),
+                    Sec. 2.1 steps i-iii.
+* ``gcv``           the GCV criterion of eq. (22); ``rgcv_select`` the relaxed
+                    selection rule of Table 1 (``dstd``).
+* ``variance``      the conditional-variance second pass of Sec. 3: the
+                    log-residual fit of eq. (24)-(26) (default) or the direct
+                    residual fit of eq. (23).
+* ``get_hlist``     the bandwidth list helper of Sec. 4.
+
+Readings taken where the paper is silent or garbled (each one is listed in
+the design notes):  the bandwidth ``h_j`` is the per-dimension kernel standard
+deviation (H = diag(h^2)); the kernel is the normalised Gaussian; the
+displacement is z = x_i - g; the design row holds every monomial of total
+degree <= l in graded order; the Girard estimate is the mean over probes of
+per-probe ratios; a grid point is ill-posed (NaN) when s_0 < 1e-300 or the
+equilibrated moment matrix has condition number above 1e12.
+
+Parity pins for every function here live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fkr_oracle.c")
+_LIB = os.path.join(_HERE, "libfkr_oracle.so")
+_lib = None
+
+ILL_S0 = 1e-300
+ILL_COND = 1e12
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (OpenMP, FP64, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int64, P, ctypes.c_int, P, P,
+                                    ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int64, P,
+                                    P, P, ctypes.c_int]
+        lib.orc_moments.restype = ctypes.c_int
+        lib.orc_nudft.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_int, P, P, P]
+        lib.orc_nudft.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Grid and monomials
+# ---------------------------------------------------------------------------
+
+def multi_indices(d: int, deg: int) -> list:
+    """All exponent tuples of total degree <= deg: degree ascending; within a
+    degree, the exponent of dimension 0 descending, then dimension 1, ...
+    (eq. (4)/(14): the row [1, x^T, vech(x x^T), ...])."""
+    out = []
+
+    def rec(prefix, left, dims):
+        if dims == 1:
+            out.append(tuple(prefix + [left]))
+            return
+        for a in range(left, -1, -1):
+            rec(prefix + [a], left - a, dims - 1)
+
+    for t in range(deg + 1):
+        rec([], t, d)
+    return out
+
+
+def grid_axes(M: Sequence[int], lo: Sequence[float], hi: Sequence[float]) -> list:
+    """Per-dimension grid coordinates g_k = lo + k * (hi - lo) / (M - 1)
+    (eq. (6) with the spacing of Sec. 1.1)."""
+    return [lo[j] + np.arange(M[j]) * ((hi[j] - lo[j]) / (M[j] - 1)) for j in range(len(M))]
+
+
+def grid_points(M, lo, hi) -> np.ndarray:
+    """All grid points, flattened with the index of dimension 0 fastest."""
+    ax = grid_axes(M, lo, hi)
+    mesh = np.meshgrid(*ax[::-1], indexing="ij")
+    return np.stack([m.ravel() for m in mesh[::-1]], axis=1)
+
+
+def flat_index(k: Sequence[int], M: Sequence[int]) -> int:
+    idx, stride = 0, 1
+    for j in range(len(M)):
+        idx += int(k[j]) * stride
+        stride *= int(M[j])
+    return idx
+
+
+# ---------------------------------------------------------------------------
+# Moments (eq. 9) and the normal-equation solve (eq. 3 / 11)
+# ---------------------------------------------------------------------------
+
+def moments(X: np.ndarray, W: Optional[np.ndarray], h: Sequence[float], order: int,
+            gpts: np.ndarray, cutoff: bool = True):
+    """s_a(g) for |a| <= 2 order and t_{w,b}(g) for |b| <= order, weights W
+    (N x nw, real).  Returns S (G x n_s) and T (G x nw x n_t)."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    N, d = X.shape
+    if W is None:
+        W = np.zeros((N, 0))
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(N, -1)
+    nw = W.shape[1]
+    gpts = np.ascontiguousarray(gpts, dtype=np.float64).reshape(-1, d)
+    G = gpts.shape[0]
+    es = np.ascontiguousarray(multi_indices(d, 2 * order), dtype=np.int32)
+    et = np.ascontiguousarray(multi_indices(d, order), dtype=np.int32)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    S = np.zeros((G, len(es)))
+    T = np.zeros((G, nw, len(et)))
+    rc = lib.orc_moments(d, N, _ptr(X), nw, _ptr(W), _ptr(h), len(es), _ptr(es), len(et),
+                         _ptr(et), G, _ptr(gpts), _ptr(S), _ptr(T), 1 if cutoff else 0)
+    if rc != 0:
+        raise ValueError(f"orc_moments failed ({rc})")
+    return S, T
+
+
+def assemble(S: np.ndarray, h: Sequence[float], order: int, d: int) -> np.ndarray:
+    """Equilibrated moment matrix A~_bc = s_{b+c} / h^{b+c} (G x P x P)."""
+    es = multi_indices(d, 2 * order)
+    et = multi_indices(d, order)
+    pos = {a: i for i, a in enumerate(es)}
+    h = np.asarray(h, dtype=np.float64)
+    P = len(et)
+    A = np.empty((S.shape[0], P, P))
+    for b in range(P):
+        for c in range(P):
+            a = tuple(et[b][j] + et[c][j] for j in range(d))
+            A[:, b, c] = S[:, pos[a]] / np.prod(h ** np.array(a))
+    return A
+
+
+def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int):
+    """Per grid point: solve A c = t (eq. 3 / 11) and return
+    mhat (G x nw) = c_0, r0 (G x P) = row 0 of the inverse of the
+    equilibrated matrix, and the ill-posed mask (G,)."""
+    et = multi_indices(d, order)
+    h = np.asarray(h, dtype=np.float64)
+    scale = np.array([np.prod(h ** np.array(b)) for b in et])
+    A = assemble(S, h, order, d)
+    rhs = T / scale[None, None, :]
+    G, nw, P = rhs.shape
+    ill = ~(S[:, 0] >= ILL_S0)
+    ok = ~ill
+    if P > 1 and ok.any():
+        cond = np.full(G, np.inf)
+        cond[ok] = np.linalg.cond(A[ok])
+        ill |= ~(cond <= ILL_COND)
+        ok = ~ill
+    mhat = np.full((G, nw), np.nan)
+    r0 = np.full((G, P), np.nan)
+    if ok.any():
+        Ainv = np.linalg.inv(A[ok])
+        r0[ok] = Ainv[:, 0, :]
+        if nw:
+            c = np.linalg.solve(A[ok], np.transpose(rhs[ok], (0, 2, 1)))
+            mhat[ok] = c[:, 0, :]
+    return mhat, r0, ill
+
+
+def _split_complex(Y: np.ndarray):
+    Y = np.asarray(Y)
+    if Y.ndim == 1:
+        Y = Y[:, None]
+    if np.iscomplexobj(Y):
+        return np.concatenate([Y.real, Y.imag], axis=1), True
+    return Y.astype(np.float64), False
+
+
+def fit(X, Y, h, order, gpts, return_all: bool = False):
+    """m_hat(g; l) of eq. (11) at the given grid points, for each response
+    column (complex responses: real and imaginary parts share the real moment
+    matrix).  Returns mhat (G x q) [, S, T, r0, ill]."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    d = X.shape[1]
+    W, cplx = _split_complex(Y)
+    S, T = moments(X, W, h, order, gpts)
+    mhat, r0, ill = solve(S, T, h, order, d)
+    if cplx:
+        q = W.shape[1] // 2
+        mhat = mhat[:, :q] + 1j * mhat[:, q:]
+    if return_all:
+        return mhat, S, T, r0, ill
+    return mhat
+
+
+# ---------------------------------------------------------------------------
+# Interpolation (Sec. 1.1 end, Sec. 5: linear griddedInterpolant)
+# ---------------------------------------------------------------------------
+
+def interp(values: np.ndarray, M, lo, hi, Xq: np.ndarray) -> np.ndarray:
+    """Multilinear interpolation of grid values (G x k, or G) at Xq (n x d).
+    The cell of x is floor((x - lo)/Delta) clamped to [0, M - 2], so a point on
+    hi uses the last cell with weight 1 on its upper corner."""
+    Xq = np.asarray(Xq, dtype=np.float64)
+    if Xq.ndim == 1:
+        Xq = Xq[:, None]
+    d = Xq.shape[1]
+    vals = np.asarray(values)
+    squeeze = vals.ndim == 1
+    vals = vals.reshape(int(np.prod(M)), -1)
+    cell, frac = [], []
+    for j in range(d):
+        delta = (hi[j] - lo[j]) / (M[j] - 1)
+        t = (Xq[:, j] - lo[j]) / delta
+        k = np.clip(np.floor(t).astype(np.int64), 0, M[j] - 2)
+        cell.append(k)
+        frac.append(t - k)
+    out = np.zeros((Xq.shape[0], vals.shape[1]), dtype=vals.dtype)
+    for corner in itertools.product((0, 1), repeat=d):
+        wgt = np.ones(Xq.shape[0])
+        idx = np.zeros(Xq.shape[0], dtype=np.int64)
+        stride = 1
+        for j in range(d):
+            wgt = wgt * (frac[j] if corner[j] else (1.0 - frac[j]))
+            idx += (cell[j] + corner[j]) * stride
+            stride *= M[j]
+        out += wgt[:, None] * vals[idx]
+    return out[:, 0] if squeeze else out
+
+
+# ---------------------------------------------------------------------------
+# Probes: Philox4x64-10 + Box-Muller (Sec. 2.1 step i)
+# ---------------------------------------------------------------------------
+
+_PH_M0 = np.uint64(0xD2E7470EE14C6C93)
+_PH_M1 = np.uint64(0xCA5A826395121157)
+_PH_W0 = np.uint64(0x9E3779B97F4A7C15)
+_PH_W1 = np.uint64(0xBB67AE8584CAA73B)
+_LO32 = np.uint64(0xFFFFFFFF)
+_S32 = np.uint64(32)
+
+
+def _mulhilo64(a: np.ndarray, b: np.uint64):
+    a0, a1 = a & _LO32, a >> _S32
+    b0, b1 = b & _LO32, b >> _S32
+    p00, p01, p10, p11 = a0 * b0, a0 * b1, a1 * b0, a1 * b1
+    mid = (p00 >> _S32) + (p01 & _LO32) + (p10 & _LO32)
+    lo = (p00 & _LO32) | (mid << _S32)
+    hi = p11 + (p01 >> _S32) + (p10 >> _S32) + (mid >> _S32)
+    return hi, lo
+
+
+def philox4x64(ctr: np.ndarray, key: Sequence[int], rounds: int = 10) -> np.ndarray:
+    """Philox4x64 with the published multipliers and Weyl key increments.
+    ctr: (n, 4) uint64; key: two uint64.  Returns (n, 4) uint64."""
+    c = [np.array(ctr[:, i], dtype=np.uint64) for i in range(4)]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    with np.errstate(over="ignore"):
+        for _ in range(rounds):
+            hi0, lo0 = _mulhilo64(c[0], _PH_M0)
+            hi1, lo1 = _mulhilo64(c[2], _PH_M1)
+            c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+            k0 = k0 + _PH_W0
+            k1 = k1 + _PH_W1
+    return np.stack(c, axis=1)
+
+
+def probes(seed: int, N: int, Np: int, index: Optional[np.ndarray] = None) -> np.ndarray:
+    """N x Np standard normal probes.  Sample i, probe p = 4 g + r uses the
+    Philox4x64-10 block with counter (i, g, 0, 0) and key (seed, 0); its four
+    words x_k map to uniforms u_k = (floor(x_k / 2^11) + 1) 2^-53 in (0, 1] and
+    Box-Muller gives sqrt(-2 ln u0) (cos, sin)(2 pi u1) for r = 0, 1 and
+    sqrt(-2 ln u2) (cos, sin)(2 pi u3) for r = 2, 3."""
+    idx = np.arange(N, dtype=np.uint64) if index is None else np.asarray(index, dtype=np.uint64)
+    out = np.empty((idx.size, Np))
+    for g in range((Np + 3) // 4):
+        ctr = np.zeros((idx.size, 4), dtype=np.uint64)
+        ctr[:, 0] = idx
+        ctr[:, 1] = g
+        x = philox4x64(ctr, (np.uint64(seed), np.uint64(0)))
+        u = ((x >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+        r0 = np.sqrt(-2.0 * np.log(u[:, 0]))
+        r1 = np.sqrt(-2.0 * np.log(u[:, 2]))
+        z = [r0 * np.cos(2 * np.pi * u[:, 1]), r0 * np.sin(2 * np.pi * u[:, 1]),
+             r1 * np.cos(2 * np.pi * u[:, 3]), r1 * np.sin(2 * np.pi * u[:, 3])]
+        for r in range(4):
+            p = 4 * g + r
+            if p < Np:
+                out[:, p] = z[r]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# DF (Sec. 2.1), GCV (eq. 22), relaxed selection (Table 1, dstd)
+# ---------------------------------------------------------------------------
+
+def girard_ratios(Wp: np.ndarray, What: np.ndarray) -> np.ndarray:
+    """rho_p = w_p^T (w_p - w_hat_p) / (w_p^T w_p) for each probe column."""
+    return np.einsum("ip,ip->p", Wp, Wp - What) / np.einsum("ip,ip->p", Wp, Wp)
+
+
+def dof(X, h, order, M, lo, hi, Wp):
+    """Fast Monte-Carlo DF (Sec. 2.1): each probe is pushed through the grid
+    smoother (moments -> solve -> interpolation back to the samples).
+    Returns (rho per probe, mean rho ~ (1/N) tr(I - S), DF = N (1 - mean))."""
+    X = np.asarray(X, dtype=np.float64).reshape(len(Wp), -1)
+    gp = grid_points(M, lo, hi)
+    mh = fit(X, Wp, h, order, gp)
+    What = interp(mh, M, lo, hi, X)
+    rho = girard_ratios(Wp, What)
+    m = float(np.mean(rho))
+    return rho, m, X.shape[0] * (1.0 - m)
+
+
+def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float) -> np.ndarray:
+    """eq. (22): (1/N) ||y - yhat||^2 / [(1/N) tr(I - S)]^2 per response column
+    (|.|^2 for complex responses)."""
+    r = np.asarray(y) - np.asarray(yhat)
+    r = r.reshape(r.shape[0], -1)
+    return np.mean(np.abs(r) ** 2, axis=0) / rho_mean ** 2
+
+
+def rgcv_select(gcv_values: Sequence[float], dstd: float = 0.0) -> int:
+    """Index of the selected bandwidth: the last (largest, for an ascending
+    list) h whose GCV is within dstd * std(GCV) of the minimum; dstd = 0 is
+    the plain argmin with ties going to the larger h.  std uses N - 1."""
+    g = np.asarray(gcv_values, dtype=np.float64)
+    thr = np.min(g) + (dstd * np.std(g, ddof=1) if dstd > 0 and g.size > 1 else 0.0)
+    return int(np.nonzero(g <= thr)[0][-1])
+
+
+def get_hlist(n, rng, kind: str = "log") -> np.ndarray:
+    """Bandwidth candidates (Sec. 4, get_hList).  1-D: n values over rng =
+    [a, b], inclusive of both ends, log- or linearly spaced.  d-D: n and rng
+    per dimension; the result is every combination (dimension 0 fastest),
+    one row per candidate."""
+    n = np.atleast_1d(n).astype(int)
+    rng = np.atleast_2d(np.asarray(rng, dtype=np.float64))
+    axes = []
+    for j in range(len(n)):
+        a, b = rng[j]
+        if kind == "log":
+            axes.append(np.logspace(np.log10(a), np.log10(b), n[j]))
+        elif kind == "lin":
+            axes.append(np.linspace(a, b, n[j]))
+        else:
+            raise ValueError(kind)
+    if len(axes) == 1:
+        return axes[0][:, None]
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")
+    return np.stack([m.ravel() for m in mesh[::-1]], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Conditional variance (Sec. 3)
+# ---------------------------------------------------------------------------
+
+def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
+             gpts: Optional[np.ndarray] = None):
+    """Second pass on squared residuals r_i = |y_i - yhat(x_i)|^2.
+
+    mode "log" (eq. 24-26): v = local fit of log(r_i + 1/N); kappa =
+    [mean_i r_i exp(-v(x_i))]^-1 with v(x_i) interpolated from the full grid;
+    sigma^2(g) = exp(v(g)) / kappa.
+    mode "direct" (eq. 23): sigma^2(g) = local fit of r_i.
+    Returns (sigma2 at gpts (or the full grid), extras dict)."""
+    X = np.asarray(X, dtype=np.float64).reshape(len(yhat_at_samples), -1)
+    N = X.shape[0]
+    r = np.abs(np.asarray(y).reshape(N) - np.asarray(yhat_at_samples).reshape(N)) ** 2
+    full = grid_points(M, lo, hi)
+    if mode == "direct":
+        s2 = fit(X, r, h, order, full if gpts is None else gpts)[:, 0]
+        return s2, {"r": r}
+    z = np.log(r + 1.0 / N)
+    v_full = fit(X, z, h, order, full)[:, 0]
+    v_i = interp(v_full, M, lo, hi, X)
+    kappa = 1.0 / np.mean(r * np.exp(-v_i))
+    v = v_full if gpts is None else fit(X, z, h, order, gpts)[:, 0]
+    return np.exp(v) / kappa, {"r": r, "z": z, "v": v_full, "kappa": kappa}
+
+
+# ---------------------------------------------------------------------------
+# Stage oracle for the NUFFT (type-1 definition, Sec. 1.2)
+# ---------------------------------------------------------------------------
+
+def nudft(X, W, lo, period, K) -> np.ndarray:
+    """c(n) = sum_i w_i exp(-i sum_j 2 pi n_j (x_ij - lo_j)/T_j) for
+    n_j = -K_j..K_j.  W: N x nw (complex allowed).  Returns an array of shape
+    (2K_{d-1}+1, ..., 2K_0+1, nw) (n_0 fastest before the weight index)."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    N, d = X.shape
+    Wc = np.asarray(W).reshape(N, -1).astype(np.complex128)
+    nw = Wc.shape[1]
+    Wri = np.ascontiguousarray(Wc.view(np.float64).reshape(N, nw, 2))
+    K = np.ascontiguousarray(K, dtype=np.int32)
+    B = int(np.prod(2 * K + 1))
+    out = np.zeros((B, nw, 2))
+    rc = lib.orc_nudft(d, N, _ptr(X), _ptr(np.ascontiguousarray(lo, dtype=np.float64)),
+                       _ptr(np.ascontiguousarray(period, dtype=np.float64)), nw, _ptr(Wri),
+                       _ptr(K), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_nudft failed")
+    c = out[..., 0] + 1j * out[..., 1]
+    return c.reshape(tuple((2 * K + 1)[::-1]) + (nw,))

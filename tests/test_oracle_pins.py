@@ -1,0 +1,386 @@
+"""Pins for the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests re-types the oracle's own formula.  Each one checks it
+against an independent fact:  Gaussian moment integrals (Poisson summation on
+a dense lattice), weighted least squares by ``numpy.linalg.lstsq`` on the
+explicit design matrix of eq. (3)-(5), polynomial reproduction, the OLS limit,
+``numpy.fft`` on lattice samples, ``numpy.random.Philox``, exact smoother traces
+and the Girard moments (Sec. 2.1), the printed ``get_hList`` values (Sec. 4.1),
+and the closed-form invariants of the variance estimator (Sec. 3).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gauss_moment(a: int, h: float) -> float:
+    """E[Z^a] for Z ~ N(0, h^2): 0 for odd a, h^a (a-1)!! for even a."""
+    if a % 2:
+        return 0.0
+    return h ** a * float(np.prod(np.arange(a - 1, 0, -2))) if a else 1.0
+
+
+# ---------------------------------------------------------------------------
+# eq. (9) moments
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,order", [(1, 0), (1, 2), (2, 1), (2, 2), (3, 1)])
+def test_moments_match_gaussian_integrals_on_dense_lattice(orc, d, order):
+    """A unit-weight lattice with spacing delta << h turns s_a(g) delta^d into
+    the Gaussian moment integral, exactly up to exp(-2 pi^2 h^2/delta^2)."""
+    h = np.array([0.11, 0.07, 0.09][:d])
+    delta = h / 3.0
+    g = np.array([0.013, -0.021, 0.004][:d])  # off-lattice evaluation point
+    axes = [np.arange(-14 * 3, 14 * 3 + 1) * delta[j] for j in range(d)]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    X = np.stack([m.ravel() for m in mesh], axis=1)
+    S, _ = orc.moments(X, None, h, order, g[None, :], cutoff=False)
+    exps = orc.multi_indices(d, 2 * order)
+    vol = float(np.prod(delta))
+    for m, a in enumerate(exps):
+        expect = np.prod([_gauss_moment(a[j], h[j]) for j in range(d)])
+        scale = np.prod([h[j] ** a[j] for j in range(d)])
+        assert abs(S[0, m] * vol - expect) <= 1e-12 * scale, (a, S[0, m] * vol, expect)
+
+
+def test_moments_sign_and_index_convention_single_sample(orc):
+    """One sample: s_a / s_0 = (x - g)^a (z = x_i - g, eq. 2-4), with each
+    exponent attached to its own dimension."""
+    h = np.array([0.2, 0.3, 0.25])
+    x = np.array([[0.31, 0.47, 0.52]])
+    g = np.array([[0.25, 0.55, 0.50]])
+    S, T = orc.moments(x, np.array([[2.5]]), h, 1, g, cutoff=False)
+    z = (x - g)[0]
+    for m, a in enumerate(orc.multi_indices(3, 2)):
+        assert np.isclose(S[0, m] / S[0, 0], np.prod(z ** np.array(a)), rtol=1e-13, atol=0)
+    for m, a in enumerate(orc.multi_indices(3, 1)):
+        assert np.isclose(T[0, 0, m] / S[0, 0], 2.5 * np.prod(z ** np.array(a)), rtol=1e-13)
+    assert S[0, 1] > 0 and S[0, 2] < 0  # x0 > g0, x1 < g1
+
+
+def test_moment_cutoff_changes_nothing_at_fp64(orc):
+    rng = np.random.default_rng(7)
+    X = rng.random((300, 2))
+    W = rng.standard_normal((300, 2))
+    gp = orc.grid_points((9, 7), (0, 0), (1, 1))
+    S1, T1 = orc.moments(X, W, [0.03, 0.05], 1, gp, cutoff=True)
+    S2, T2 = orc.moments(X, W, [0.03, 0.05], 1, gp, cutoff=False)
+    assert np.allclose(S1, S2, rtol=1e-14, atol=1e-300)
+    assert np.allclose(T1, T2, rtol=1e-13, atol=1e-14 * np.abs(T2).max())
+
+
+def test_kde_integrates_to_n(orc):
+    """sum_g s_0(g) Delta^d -> N (eq. 8: the KDE integrates to one) when the
+    grid is much finer than h and covers the kernel's support."""
+    rng = np.random.default_rng(3)
+    X = 0.35 + 0.3 * rng.random((50, 2))
+    M = (161, 161)
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    S, _ = orc.moments(X, None, [0.03, 0.04], 0, gp)
+    assert abs(S[:, 0].sum() * (1 / 160) ** 2 - 50) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# eq. (3) solve
+# ---------------------------------------------------------------------------
+
+def _wls_intercept(X, y, g, h, order):
+    """m(g) of eq. (3) from the explicit design matrix D (eq. 4) and kernel
+    weights (eq. 5), solved by lstsq on sqrt(W) D."""
+    d = X.shape[1]
+    exps = [a for a in itertools.product(range(order + 1), repeat=d) if sum(a) <= order]
+    exps.sort(key=lambda a: (sum(a), [-v for v in a]))
+    Z = X - g
+    D = np.stack([np.prod(Z ** np.array(a), axis=1) for a in exps], axis=1)
+    w = np.exp(-0.5 * ((Z / h) ** 2).sum(axis=1))
+    sw = np.sqrt(w)
+    coef, *_ = np.linalg.lstsq(sw[:, None] * D, sw * y, rcond=None)
+    return coef[0]
+
+
+@pytest.mark.parametrize("d,order", [(1, 0), (1, 1), (1, 2), (2, 1), (2, 2), (3, 1)])
+def test_fit_equals_weighted_least_squares(orc, d, order):
+    rng = np.random.default_rng(10 + d * 3 + order)
+    N = 80
+    X = rng.random((N, d))
+    y = np.sin(3 * X).sum(axis=1) + 0.1 * rng.standard_normal(N)
+    h = np.array([0.3, 0.25, 0.35][:d])
+    gp = rng.random((6, d))
+    mh = orc.fit(X, y, h, order, gp)[:, 0]
+    ref = np.array([_wls_intercept(X, y, g, h, order) for g in gp])
+    assert np.allclose(mh, ref, rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("d,order", [(1, 0), (1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2)])
+def test_polynomial_reproduction(orc, d, order):
+    """A polynomial response of degree <= l is reproduced exactly."""
+    rng = np.random.default_rng(100 + 7 * d + order)
+    X = rng.random((120, d))
+    coef = {a: rng.standard_normal() for a in orc.multi_indices(d, order)}
+
+    def p(P):
+        return sum(c * np.prod(P ** np.array(a), axis=1) for a, c in coef.items())
+
+    gp = rng.random((10, d))
+    mh = orc.fit(X, p(X), [0.2] * d, order, gp)[:, 0]
+    assert np.allclose(mh, p(gp), rtol=1e-8, atol=1e-9)
+
+
+def test_nw_of_constant_is_constant(orc):
+    rng = np.random.default_rng(4)
+    X = rng.random((200, 2))
+    gp = orc.grid_points((5, 5), (0, 0), (1, 1))
+    mh = orc.fit(X, np.ones(200), [0.05, 0.08], 0, gp)[:, 0]
+    assert np.allclose(mh, 1.0, rtol=1e-14)
+
+
+def test_local_linear_1d_closed_form(orc):
+    """1-D local linear: m = (s2 t0 - s1 t1) / (s0 s2 - s1^2)."""
+    rng = np.random.default_rng(5)
+    X = rng.random((150, 1))
+    y = np.cos(4 * X[:, 0]) + 0.2 * rng.standard_normal(150)
+    gp = np.linspace(0, 1, 11)[:, None]
+    mh, S, T, _, _ = orc.fit(X, y, [0.1], 1, gp, return_all=True)
+    s0, s1, s2 = S[:, 0], S[:, 1], S[:, 2]
+    t0, t1 = T[:, 0, 0], T[:, 0, 1]
+    assert np.allclose(mh[:, 0], (s2 * t0 - s1 * t1) / (s0 * s2 - s1 ** 2), rtol=1e-10)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_large_bandwidth_tends_to_global_ols(orc, d):
+    rng = np.random.default_rng(11 + d)
+    X = rng.random((90, d))
+    y = rng.standard_normal(90)
+    D = np.concatenate([np.ones((90, 1)), X], axis=1)
+    beta, *_ = np.linalg.lstsq(D, y, rcond=None)
+    gp = rng.random((4, d))
+    mh = orc.fit(X, y, [1e3] * d, 1, gp)[:, 0]
+    assert np.allclose(mh, beta[0] + gp @ beta[1:], rtol=1e-5, atol=1e-6)
+
+
+def test_complex_response_is_real_plus_imaginary(orc):
+    rng = np.random.default_rng(6)
+    X = rng.random((100, 2))
+    yr, yi = rng.standard_normal(100), rng.standard_normal(100)
+    gp = rng.random((5, 2))
+    mc = orc.fit(X, yr + 1j * yi, [0.2, 0.2], 2, gp)[:, 0]
+    assert np.allclose(mc.real, orc.fit(X, yr, [0.2, 0.2], 2, gp)[:, 0], rtol=1e-12)
+    assert np.allclose(mc.imag, orc.fit(X, yi, [0.2, 0.2], 2, gp)[:, 0], rtol=1e-12)
+
+
+def test_empty_region_is_ill_posed(orc):
+    X = np.array([[0.1], [0.12], [0.15]])
+    gp = np.array([[0.13], [0.9]])
+    mh, S, T, r0, ill = orc.fit(X, np.ones(3), [0.005], 1, gp, return_all=True)
+    assert not ill[0] and ill[1] and np.isnan(mh[1, 0])
+
+
+# ---------------------------------------------------------------------------
+# Type-1 NUDFT stage oracle (Sec. 1.2)
+# ---------------------------------------------------------------------------
+
+def test_nudft_on_lattice_equals_fft(orc):
+    """Samples on a lattice of the period turn the NUDFT into numpy's FFT."""
+    rng = np.random.default_rng(8)
+    L0, L1 = 24, 20
+    T = np.array([1.3, 1.1])
+    m = np.stack([rng.integers(0, L0, 60), rng.integers(0, L1, 60)], axis=1)
+    X = m * (T / np.array([L0, L1]))
+    w = rng.standard_normal(60) + 1j * rng.standard_normal(60)
+    grid = np.zeros((L1, L0), dtype=complex)
+    np.add.at(grid, (m[:, 1], m[:, 0]), w)
+    F = np.fft.fft2(grid)
+    K = np.array([5, 4])
+    c = orc.nudft(X, w, [0, 0], T, K)[..., 0]
+    for n1 in range(-K[1], K[1] + 1):
+        for n0 in range(-K[0], K[0] + 1):
+            assert np.isclose(c[n1 + K[1], n0 + K[0]], F[n1 % L1, n0 % L0], rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Interpolation
+# ---------------------------------------------------------------------------
+
+def test_interp_exact_on_multilinear_functions(orc):
+    rng = np.random.default_rng(9)
+    M, lo, hi = (7, 6, 5), (0, -1, 2), (1, 1, 3)
+    c = rng.standard_normal(8)
+
+    def f(P):
+        x, y, z = P[:, 0], P[:, 1], P[:, 2]
+        return (c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * y * z
+                + c[6] * x * z + c[7] * x * y * z)
+
+    gp = orc.grid_points(M, lo, hi)
+    Xq = np.stack([rng.uniform(lo[j], hi[j], 50) for j in range(3)], axis=1)
+    Xq[0] = hi
+    Xq[1] = lo
+    assert np.allclose(orc.interp(f(gp), M, lo, hi, Xq), f(Xq), rtol=1e-12, atol=1e-12)
+    assert np.allclose(orc.interp(f(gp), M, lo, hi, gp), f(gp), rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Probes
+# ---------------------------------------------------------------------------
+
+def test_philox_matches_numpy_bit_generator(orc):
+    """numpy's Philox (4x64, 10 rounds) increments its counter before each
+    block, so its first block uses counter + 1."""
+    for key, ctr in [((0, 0), (0, 0, 0, 0)), ((1234567, 987654321), (5, 17, 3, 2**63 + 11)),
+                     ((2**64 - 1, 2**64 - 1), (2**64 - 2, 2**64 - 1, 2**64 - 1, 2**64 - 1))]:
+        bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                              counter=np.array(ctr, dtype=np.uint64))
+        ref = bg.random_raw(4)
+        c1 = list(ctr)
+        c1[0] = (c1[0] + 1) % 2**64
+        if c1[0] == 0:
+            c1[1] = (c1[1] + 1) % 2**64
+        got = orc.philox4x64(np.array([c1], dtype=np.uint64), key)[0]
+        assert [int(v) for v in got] == [int(v) for v in ref]
+
+
+def test_probes_are_standard_normal_and_reproducible(orc):
+    P = orc.probes(1234, 50_000, 6)
+    assert P.shape == (50_000, 6)
+    for p in range(6):
+        assert stats.kstest(P[:, p], "norm").pvalue > 1e-4
+    C = np.corrcoef(P.T)
+    assert np.abs(C - np.eye(6)).max() < 0.03
+    sub = orc.probes(1234, 0, 6, index=np.array([17, 49_999]))
+    assert np.array_equal(sub, P[[17, 49_999]])
+    assert not np.array_equal(orc.probes(1235, 10, 6), P[:10])
+
+
+# ---------------------------------------------------------------------------
+# DF (Sec. 2.1) and GCV (eq. 22)
+# ---------------------------------------------------------------------------
+
+def _smoother_matrix(orc, X, h, order, M, lo, hi):
+    gp = orc.grid_points(M, lo, hi)
+    N = X.shape[0]
+    mh = orc.fit(X, np.eye(N), h, order, gp)
+    return orc.interp(mh, M, lo, hi, X)  # column j = S e_j
+
+
+def test_dof_identity_smoother_gives_zero(orc):
+    """Samples on the grid nodes, tiny h: the smoother is the identity, so
+    every Girard ratio is 0 and DF = N."""
+    M = (33,)
+    X = orc.grid_points(M, (0,), (1,))
+    Wp = orc.probes(5, 33, 8)
+    rho, m, df = orc.dof(X, [1.0 / 32 / 20], 0, M, (0,), (1,), Wp)
+    assert np.all(np.abs(rho) < 1e-12) and abs(df - 33) < 1e-9
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_dof_large_bandwidth_is_ols_projection(orc, d):
+    """h -> infinity with l = 1: the smoother projects onto linear functions,
+    so rho_p = ||(I - H) w_p||^2 / ||w_p||^2 with H the OLS hat matrix."""
+    rng = np.random.default_rng(20 + d)
+    N = 60
+    X = rng.random((N, d))
+    M, lo, hi = (9,) * d, (0,) * d, (1,) * d
+    Wp = orc.probes(77, N, 5)
+    rho, m, df = orc.dof(X, [1e3] * d, 1, M, lo, hi, Wp)
+    D = np.concatenate([np.ones((N, 1)), X], axis=1)
+    res = Wp - D @ np.linalg.lstsq(D, Wp, rcond=None)[0]
+    assert np.allclose(rho, (res ** 2).sum(0) / (Wp ** 2).sum(0), rtol=1e-5)
+
+
+def test_girard_estimator_mean_matches_exact_trace(orc):
+    """E rho_p = tr(I - S)/N exactly for Gaussian probes, with
+    Var rho_p = 2 (tr B^2 - (tr B)^2/N) / (N (N + 2)), B = sym(I - S)."""
+    rng = np.random.default_rng(31)
+    N, M = 40, (16,)
+    X = rng.random((N, 1))
+    S = _smoother_matrix(orc, X, [0.08], 1, M, (0,), (1,))
+    B = np.eye(N) - S
+    Bs = 0.5 * (B + B.T)
+    exact = np.trace(B) / N
+    var = 2 * (np.trace(Bs @ Bs) - np.trace(Bs) ** 2 / N) / (N * (N + 2))
+    Np = 3000
+    Wp = orc.probes(99, N, Np)
+    rho, m, df = orc.dof(X, [0.08], 1, M, (0,), (1,), Wp)
+    assert abs(m - exact) < 4 * math.sqrt(var / Np)
+    assert abs(np.var(rho, ddof=1) / var - 1) < 0.15
+
+
+def test_gcv_of_ols_fit(orc):
+    """With the exact trace of the OLS hat matrix, eq. (22) is the classical
+    GCV: (RSS/N) / (1 - P/N)^2."""
+    rng = np.random.default_rng(40)
+    N = 50
+    X = rng.random((N, 1))
+    y = 2 + 3 * X[:, 0] + rng.standard_normal(N)
+    D = np.concatenate([np.ones((N, 1)), X], axis=1)
+    beta, rss, *_ = np.linalg.lstsq(D, y, rcond=None)
+    g = orc.gcv(y, D @ beta, 1 - 2 / N)
+    assert np.isclose(g[0], rss[0] / N / (1 - 2 / N) ** 2, rtol=1e-12)
+
+
+def test_rgcv_selection_rule(orc):
+    g = [5.0, 3.0, 2.0, 2.05, 2.5, 4.0]
+    assert orc.rgcv_select(g, 0.0) == 2
+    assert orc.rgcv_select([3.0, 1.0, 1.0, 2.0], 0.0) == 2  # tie -> larger h
+    sd = np.std(g, ddof=1)
+    assert orc.rgcv_select(g, 0.5 / sd) == 4  # threshold 2.5 includes index 4
+    assert orc.rgcv_select(g, 0.01 / sd) == 2
+
+
+def test_get_hlist_printed_values():
+    from oracle import oracle as orc
+    with open(os.path.join(GOLD, "get_hlist_paper.json")) as f:
+        gold = json.load(f)
+    hl = orc.get_hlist(gold["n"], gold["range"], gold["kind"])[:, 0]
+    for item in gold["printed"]:
+        v = hl[item["position_1based"] - 1]
+        assert float(f"{v:.{item['digits']}g}") == item["value"]
+    assert hl[0] == 0.01 and np.isclose(hl[-1], 1.0)
+    h2 = orc.get_hlist([3, 2], [[0.1, 0.3], [1, 2]], "lin")
+    assert h2.shape == (6, 2) and np.allclose(h2[:3, 0], [0.1, 0.2, 0.3])
+
+
+# ---------------------------------------------------------------------------
+# Variance (Sec. 3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_variance_constant_residuals(orc, order):
+    """|y - yhat|^2 = c everywhere: v = log(c + 1/N) exactly, kappa =
+    (c + 1/N)/c, so sigma^2 = c on every grid point (eq. 24-26); the direct
+    fit of eq. (23) also gives c."""
+    rng = np.random.default_rng(50)
+    N, c = 200, 0.37
+    X = rng.random((N, 2))
+    yhat = rng.standard_normal(N)
+    y = yhat + np.sqrt(c) * np.where(rng.random(N) < 0.5, -1, 1)
+    M = (6, 5)
+    s2, ex = orc.variance(X, y, yhat, [0.2, 0.2], order, M, (0, 0), (1, 1))
+    assert np.allclose(s2, c, rtol=1e-10)
+    assert np.isclose(ex["kappa"], (c + 1 / N) / c, rtol=1e-12)
+    s2d, _ = orc.variance(X, y, yhat, [0.2, 0.2], order, M, (0, 0), (1, 1), mode="direct")
+    assert np.allclose(s2d, c, rtol=1e-10)
+
+
+def test_variance_log_linear_reproduction(orc):
+    """If log(r + 1/N) is linear in x, the local-linear v reproduces it."""
+    rng = np.random.default_rng(51)
+    N = 300
+    X = rng.random((N, 1))
+    v_true = -1.0 + 2.0 * X[:, 0]
+    r = np.exp(v_true) - 1.0 / N
+    yhat = np.zeros(N)
+    y = np.sqrt(r)
+    M = (11,)
+    s2, ex = orc.variance(X, y, yhat, [0.15], 1, M, (0,), (1,))
+    g = np.linspace(0, 1, 11)
+    assert np.allclose(ex["v"], -1.0 + 2.0 * g, rtol=1e-9, atol=1e-9)
+    kappa = 1.0 / np.mean(r * np.exp(-v_true))
+    assert np.allclose(s2, np.exp(-1.0 + 2.0 * g) / kappa, rtol=1e-9)
