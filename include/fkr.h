@@ -1,0 +1,239 @@
+/*
+ * fkr.h -- C ABI of the MI355X (gfx950) fast multivariate kernel regression
+ * library: binned local-polynomial kernel regression on a uniform grid through
+ * a type-1 non-uniform FFT, with the per-grid-point normal-equation solve,
+ * Girard's Monte-Carlo degrees of freedom, GCV and the conditional-variance
+ * second pass of Wang et al., "FKreg: A MATLAB toolbox for fast multivariate
+ * kernel regression" (arXiv 2204.07716).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch-allocated
+ *    HBM); every other pointer is host memory.  The library never allocates
+ *    device memory: the caller owns all inputs, outputs and the workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is enqueued on it and is asynchronous; outputs are
+ *    valid once the stream has been synchronised.  Argument errors are found on
+ *    the host before anything is enqueued, and then nothing is enqueued.
+ *  - Samples X are N x d, row-major (x_i0, ..., x_i,d-1 contiguous), element
+ *    type FKR_F32 or FKR_F64.  They must lie inside the grid box [lo, hi]
+ *    (up to a relative 1e-12 of the box width); samples outside are counted in
+ *    the diagnostics and reported by fkr_get_diagnostics as FKR_E_DOMAIN.
+ *  - Real responses Y are N x q row-major.  Complex responses (y_complex = 1)
+ *    are N x q complex numbers stored as interleaved (re, im) pairs.
+ *  - Grid functions (fits, moments, variance) are laid out with the index of
+ *    dimension 0 fastest: flat(k) = k_0 + M_0 (k_1 + M_1 k_2).  The grid of
+ *    eq. (6) has g_k = lo + k * (hi - lo) / (M - 1) per dimension (both ends on
+ *    the grid).
+ *  - Bandwidths: h is the per-dimension standard deviation of the Gaussian
+ *    kernel, i.e. the bandwidth matrix of eq. (2) is diag(h_j^2).  A call with
+ *    nh bandwidths takes a host array of nh x d doubles.  Every h_j must lie
+ *    within the plan's [h_min_j, h_max_j].
+ *  - Monomials / moment channels are ordered by total degree, then by the
+ *    exponent of dimension 0 descending, then dimension 1, ...: for d = 2 the
+ *    design row of eq. (4)/(14) is [1, z0, z1, z0^2, z0 z1, z1^2, ...].
+ *  - Nothing is printed; no exception crosses the ABI.  One plan serves one
+ *    stream at a time (calls on one plan must not overlap).
+ */
+#ifndef FKR_H
+#define FKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FKR_OK = 0,
+    FKR_WARN_ILLPOSED = 1,   /* some grid points had no well-posed solve (NaN) */
+    FKR_E_ARG = -1,          /* invalid argument (host-detected, nothing enqueued) */
+    FKR_E_DOMAIN = -2,       /* samples outside [lo, hi] (device-detected) */
+    FKR_E_WORKSPACE = -3,    /* workspace missing or too small */
+    FKR_E_DEVICE = -4,       /* a HIP runtime call failed */
+    FKR_E_UNSUPPORTED = -5,  /* a valid request this library does not implement */
+    FKR_E_STATE = -6         /* call order violated (e.g. no points set) */
+} fkr_status;
+
+enum { FKR_F32 = 0, FKR_F64 = 1 };             /* element types */
+enum { FKR_KERNEL_ES = 0, FKR_KERNEL_GAUSS = 1 }; /* spreading (gridding) kernel */
+enum { FKR_VAR_LOG = 0, FKR_VAR_DIRECT = 1 };   /* variance estimator */
+enum { FKR_TP_SAME = 0, FKR_TP_F32 = 1, FKR_TP_F64 = 2 }; /* transform precision */
+
+#define FKR_MAX_D 3
+#define FKR_MAX_ORDER 2
+#define FKR_MAX_H 64        /* bandwidths per call */
+
+typedef struct fkr_plan fkr_plan;
+
+/* Plan description; mirrors the options of Table 1 that concern the fast
+ * path.  Zero-initialise and fill in the fields you need. */
+typedef struct {
+    int d;                  /* dimension, 1..3 */
+    int order;              /* local polynomial order l (eq. 2), 0..2 */
+    int64_t M[FKR_MAX_D];   /* grid points per dimension, >= 2 (Table 1 "M") */
+    double lo[FKR_MAX_D];   /* grid box; both ends are grid points (eq. 6) */
+    double hi[FKR_MAX_D];
+    double h_min[FKR_MAX_D];/* bandwidth range the plan must serve; sets the */
+    double h_max[FKR_MAX_D];/* spectral band (h_min) and the zero padding (h_max) */
+    double eps;             /* requested relative accuracy of the moment sums,
+                               in (0, 1) (replaces Table 1 "accuracy") */
+    int precision;          /* FKR_F64 or FKR_F32: spreading (kernel values and
+                               LDS accumulation) and, unless transform_precision
+                               says otherwise, FFTs and channel grids; the
+                               normal-equation solves are always FP64 */
+    int spread_kernel;      /* FKR_KERNEL_ES (default) or FKR_KERNEL_GAUSS (the
+                               paper's fast Gaussian gridding, Sec. 1.2) */
+    double sigma;           /* fine-grid oversampling over the spectral band;
+                               0 selects 2 (eq. 17: M_r = 2 L) */
+    int64_t n_max;          /* largest N passed to fkr_set_points */
+    int max_weights;        /* largest number of real weight vectors one call
+                               spreads, counting the density: 1 + q (real y) or
+                               1 + 2q (complex y), plus Np probes for DF calls */
+    int max_h;              /* largest nh per call, 1..FKR_MAX_H */
+    int transform_precision;/* FKR_TP_SAME (follow `precision`), FKR_TP_F32 or
+                               FKR_TP_F64: element type of the fine grid, the
+                               FFTs, the spectra and the channel grids; with
+                               precision FKR_F32 and FKR_TP_F64 the spreading
+                               runs in FP32 and everything after it in FP64 */
+} fkr_plan_desc;
+
+/* Geometry chosen by the planner (read-only). */
+typedef struct {
+    int d, order;
+    int n_s, n_t;            /* moment channels: C(d+2l, 2l) and P = C(d+l, l) */
+    int64_t M[FKR_MAX_D];
+    int64_t L[FKR_MAX_D];    /* periodic length in grid steps (zero padding, eq. 18) */
+    int64_t K[FKR_MAX_D];    /* retained modes n = -K..K per dimension */
+    int64_t Mr[FKR_MAX_D];   /* fine (spreading) grid length per dimension */
+    int64_t tile[FKR_MAX_D]; /* spreading tile edge, fine cells */
+    double delta[FKR_MAX_D]; /* grid spacing */
+    double period[FKR_MAX_D];/* T_j = L_j * delta_j */
+    int w;                   /* spreading kernel width, fine cells */
+    double kparam;           /* ES beta, or the Gaussian's exp coefficient per cell^2 */
+    int64_t n_tiles;
+    size_t workspace_bytes;
+} fkr_geometry;
+
+typedef struct {
+    int64_t n_points;        /* N of the last fkr_set_points */
+    int64_t out_of_domain;   /* samples outside [lo, hi] */
+    int64_t ill_posed;       /* grid-point solves reported as NaN (last call) */
+    int64_t n_jobs;          /* spreading work items of the last fkr_set_points */
+    int64_t max_tile_count;  /* most samples in one tile */
+} fkr_diag;
+
+/* Create a plan: grid geometry, spectral band, spreading kernel and tables
+ * (Sec. 4 fkreg_create; Table 1).  Host only.  Errors: FKR_E_ARG for d, order,
+ * M, box, bandwidth range, eps or sizes out of range; FKR_E_UNSUPPORTED when a
+ * transform or a spreading tile would not fit the LDS of one workgroup (very
+ * small h_min relative to the box, very large M, or a wide kernel in 3-D
+ * FP64).  *out is owned by the caller and released with fkr_plan_destroy. */
+fkr_status fkr_plan_create(const fkr_plan_desc* desc, fkr_plan** out);
+void fkr_plan_destroy(fkr_plan* plan);
+fkr_status fkr_plan_geometry(const fkr_plan* plan, fkr_geometry* out);
+
+/* Device workspace: size in bytes for the plan's maxima, then bind a buffer
+ * of at least that size (256-byte aligned).  fkr_set_workspace uploads the
+ * plan's constant tables with a synchronous copy. */
+fkr_status fkr_workspace_size(const fkr_plan* plan, size_t* bytes);
+fkr_status fkr_set_workspace(fkr_plan* plan, void* ws_dev, size_t bytes);
+
+/* Bin and sort the samples by spreading tile (part of the O(N) gridding of
+ * Sec. 1.2, eq. 16-17); reused by every later call until the next
+ * fkr_set_points.  X_dev: N x d of type x_type.  N may be 0. */
+fkr_status fkr_set_points(fkr_plan* plan, int64_t N, const void* X_dev, int x_type,
+                          void* stream);
+
+/* Type-1 NUFFT stage (eq. 16-20): for nw real weight vectors W (N x nw,
+ * row-major, type w_type; NULL with nw = 1 means the unit weights of the
+ * delta train), the deconvolved spectrum
+ *     c(n) = sum_i w_i exp(-i sum_j 2 pi n_j (x_ij - lo_j) / T_j)
+ * for n_j = -K_j..K_j.  out_dev: complex128 array (re, im interleaved) of
+ * shape [nw][2K_{d-1}+1]...[2K_0+1]. */
+fkr_status fkr_spectrum(fkr_plan* plan, int nw, const void* W_dev, int w_type,
+                        double* out_dev, void* stream);
+
+/* Moment sums of eq. (9) on the grid, through spreading, FFT, deconvolution,
+ * multiplication by the kernel-moment spectra and inverse FFT (eq. 12-13,
+ * 16-21).  Channels are equilibrated by the bandwidth: S_dev receives
+ * s_a(g) / h^a for |a| <= 2l ([nh][n_s][M^d] doubles) and T_dev receives
+ * t_{w,b}(g) / h^b for |b| <= l ([nh][nw][n_t][M^d] doubles); either may be
+ * NULL.  W as in fkr_spectrum (NULL with nw = 0 gives only S). */
+fkr_status fkr_moments(fkr_plan* plan, int nh, const double* h, int nw, const void* W_dev,
+                       int w_type, double* S_dev, double* T_dev, void* stream);
+
+/* Binned local-polynomial fit of eq. (11): per grid point the P x P system
+ * A_bc = s_{b+c}, rhs_b = t_b, solved in FP64 (Cholesky of the
+ * bandwidth-equilibrated matrix); mhat = intercept.  Y: N x q (real or
+ * complex).  mhat_dev: [nh][q][M^d] doubles (complex: [nh][q][M^d][2]).
+ * s0_dev (optional, [nh][M^d] doubles): s_0, the unnormalised KDE of eq. (8).
+ * Grid points whose system is ill-posed (s_0 below the method's noise floor or
+ * a Cholesky pivot below 1e-12 of its diagonal) get NaN and are counted. */
+fkr_status fkr_fit(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
+                   const void* Y_dev, int y_type, double* mhat_dev, double* s0_dev,
+                   void* stream);
+
+/* Multilinear interpolation (the linear griddedInterpolant of Sec. 1.1/5) of
+ * nv grid functions G_dev ([nv][M^d] doubles) at Nq query points Xq_dev
+ * (Nq x d, type x_type) -> out_dev ([nv][Nq] doubles).  The cell of a point
+ * is floor((x - lo)/delta) clamped to [0, M-2]. */
+fkr_status fkr_interp(fkr_plan* plan, int nv, const double* G_dev, int64_t Nq,
+                      const void* Xq_dev, int x_type, double* out_dev, void* stream);
+
+/* Fast Monte-Carlo DF (Sec. 2.1, Girard): Np Gaussian probes w_p pushed
+ * through the grid smoother (moments -> solve -> interpolation to the
+ * samples).  rho_dev: [nh][Np] doubles, rho_p = w_p^T (w_p - w_hat_p) /
+ * (w_p^T w_p); their mean estimates (1/N) tr(I - S_h).  Probes come from
+ * probes_dev (N x Np, type w_type) or, when it is NULL, from the Philox4x64-10
+ * generator: sample i, probe 4g + r uses the block with counter (i, g, 0, 0)
+ * and key (seed, 0), uniforms (floor(x/2^11) + 1) 2^-53 and Box-Muller. */
+fkr_status fkr_dof(fkr_plan* plan, int nh, const double* h, int Np, uint64_t seed,
+                   const void* probes_dev, int w_type, double* rho_dev, void* stream);
+
+/* Batched cross-validation (Sec. 2 and Fig. 3, cv_fkreg): for every h, the
+ * fit of all q responses and the DF from Np probes share one spreading and
+ * one forward FFT of every weight vector.  Outputs (any may be NULL):
+ * mhat_dev as in fkr_fit; rho_dev [nh][Np]; rss_dev [nh][q] = sum_i
+ * |y_i - yhat(x_i)|^2; gcv_dev [nh][q] = (rss/N) / mean_p(rho_p)^2 (eq. 22;
+ * needs Np >= 1). */
+fkr_status fkr_cv(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
+                  const void* Y_dev, int y_type, int Np, uint64_t seed,
+                  const void* probes_dev, double* mhat_dev, double* rho_dev,
+                  double* rss_dev, double* gcv_dev, void* stream);
+
+/* Conditional-variance second pass (Sec. 3) at one bandwidth h (d doubles):
+ * residuals r_i = |y_i - mhat(x_i)|^2 from the mean fit's grid mhat_dev
+ * (output of fkr_fit for this Y, one column: [M^d] doubles, or [M^d][2] for
+ * complex y), then
+ *   FKR_VAR_LOG (eq. 24-26): v = fit of log(r_i + 1/N); kappa =
+ *       [mean_i r_i exp(-v(x_i))]^-1; sigma^2(g) = exp(v(g)) / kappa;
+ *   FKR_VAR_DIRECT (eq. 23): sigma^2(g) = fit of r_i.
+ * The fit uses the plan's order.  sigma2_dev: [M^d] doubles; vhat_dev
+ * (optional, FKR_VAR_LOG) [M^d]; kappa_dev (optional) 1 double. */
+fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const void* Y_dev,
+                        int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
+                        double* vhat_dev, double* kappa_dev, void* stream);
+
+/* Bandwidth candidates (Sec. 4, get_hList), host only: n values from a to b
+ * inclusive, log-spaced (kind 0, a > 0) or linearly spaced (kind 1). */
+fkr_status fkr_hlist(int n, double a, double b, int kind, double* out);
+
+/* Relaxed GCV selection (Table 1, dstd), host only: the largest index k with
+ * gcv[k] <= min(gcv) + dstd * std(gcv) (std normalised by nh - 1; dstd = 0 is
+ * the argmin with ties going to the later, larger bandwidth).  NaN entries are
+ * skipped; FKR_E_ARG if all are NaN. */
+fkr_status fkr_select_bandwidth(int nh, const double* gcv, double dstd, int* index);
+
+/* Synchronises the stream of the last call and reports the device-side
+ * counters.  Returns FKR_E_DOMAIN if samples were outside the box,
+ * FKR_WARN_ILLPOSED if the last solve produced NaN points, else FKR_OK. */
+fkr_status fkr_get_diagnostics(fkr_plan* plan, fkr_diag* out);
+
+const char* fkr_status_string(fkr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FKR_H */

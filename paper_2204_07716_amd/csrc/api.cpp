@@ -1,0 +1,576 @@
+// C ABI of the fast kernel-regression library: argument checks, workspace
+// binding and the order of device stages for each call (declared in fkr.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fkr_internal.h"
+#include "kernels.h"
+
+using namespace fkr;
+
+namespace {
+
+#define FKR_HIP(call)                                      \
+    do {                                                   \
+        if ((call) != hipSuccess) return FKR_E_DEVICE;     \
+    } while (0)
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+template <typename P> P* at(fkr_plan* p, size_t off) { return reinterpret_cast<P*>(p->ws + off); }
+
+Geo make_geo(const fkr_plan* p) {
+    Geo g{};
+    g.d = p->d;
+    g.w = p->w;
+    for (int j = 0; j < 3; ++j) {
+        g.M[j] = p->M[j]; g.Mr[j] = p->Mr[j]; g.ts[j] = p->ts[j]; g.nt[j] = p->nt[j];
+        g.pe[j] = p->pe[j]; g.B[j] = p->B[j]; g.K[j] = p->K[j];
+        g.lo[j] = p->lo[j]; g.hi[j] = p->hi[j]; g.delta[j] = p->delta[j];
+        g.inv_delta[j] = j < p->d ? 1.0 / p->delta[j] : 1.0;
+        g.inv_hf[j] = p->inv_hf[j];
+        g.tol[j] = j < p->d ? 1e-12 * (p->hi[j] - p->lo[j]) : 0.0;
+    }
+    g.n_tiles = p->n_tiles; g.Psub = p->Psub; g.Mtot = p->Mtot; g.Btot = p->Btot; g.Mrtot = p->Mrtot;
+    g.kparam = p->kparam;
+    g.chunk = p->chunk;
+    g.tsp = p->tsp;
+    g.ncell = p->ncell;
+    return g;
+}
+
+bool valid_type(int t) { return t == FKR_F32 || t == FKR_F64; }
+
+fkr_status check_h(const fkr_plan* p, int nh, const double* h) {
+    if (nh < 1 || nh > p->max_h || !h) return FKR_E_ARG;
+    for (int q = 0; q < nh; ++q)
+        for (int j = 0; j < p->d; ++j) {
+            const double v = h[q * p->d + j];
+            if (!(v >= p->h_min[j] * (1 - 1e-12) && v <= p->h_max[j] * (1 + 1e-12))) return FKR_E_ARG;
+        }
+    return FKR_OK;
+}
+
+fkr_status ready(const fkr_plan* p) {
+    if (!p) return FKR_E_ARG;
+    if (!p->ws_ready) return FKR_E_WORKSPACE;
+    if (!p->points_set) return FKR_E_STATE;
+    return FKR_OK;
+}
+
+WSrc src_one() { WSrc w{}; w.kind = W_ONE; return w; }
+WSrc src_zero() { WSrc w{}; w.kind = W_ZERO; return w; }
+WSrc src_array(const void* ptr, int type, int64_t stride, int64_t col) {
+    WSrc w{}; w.kind = W_ARRAY; w.type = type; w.ptr = ptr; w.stride = stride; w.col = col; return w;
+}
+WSrc src_philox(uint64_t seed, int probe) { WSrc w{}; w.kind = W_PHILOX; w.seed = seed; w.probe = probe; return w; }
+
+const int* dev_es(fkr_plan* p) { return at<int>(p, p->lay.consts + 64); }
+const int* dev_et(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 512); }
+const int* dev_pidx(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 1024); }
+const double* dev_periods(fkr_plan* p) { return at<double>(p, p->lay.consts); }
+
+// Spread + fold + forward FFT of every weight pair -> spec [band][npairs].
+fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs, hipStream_t s) {
+    const Geo g = make_geo(p);
+    const int nr = (int)srcs.size();
+    const int npairs = (nr + 1) / 2;
+    if (npairs > p->npairs_max) return FKR_E_ARG;
+    const size_t csz = 2 * elem_size(p->prec);
+    for (int p0 = 0; p0 < npairs; p0 += p->pairs_per_spread) {
+        const int gp = std::min(p->pairs_per_spread, npairs - p0);
+        SpreadSrc src{};
+        src.npairs = gp;
+        for (int q = 0; q < gp; ++q) {
+            const int r0 = 2 * (p0 + q), r1 = r0 + 1;
+            src.w[2 * q] = srcs[r0];
+            src.w[2 * q + 1] = r1 < nr ? srcs[r1] : src_zero();
+        }
+        launch_spread(g, p->prec, p->kernel, src, at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
+                      at<int32_t>(p, p->lay.perm), at<int32_t>(p, p->lay.jobs), p->n_jobs_max,
+                      p->ws + p->lay.subgrid, s);
+        launch_fold(g, p->prec, p->tprec, gp, at<int32_t>(p, p->lay.cover), at<int32_t>(p, p->lay.job_off),
+                    p->ws + p->lay.subgrid, p->ws + p->lay.fine, s);
+        const void* in = p->ws + p->lay.fine;
+        int64_t done_B = 1;
+        for (int j = 0; j < p->d; ++j) {
+            FftPass f{};
+            int64_t rest = 1;
+            for (int i = j + 1; i < p->d; ++i) rest *= p->Mr[i];
+            f.rows = done_B * gp * rest;
+            f.n_in = p->Mr[j];
+            f.F = p->Mr[j];
+            f.n_out = p->B[j];
+            f.K = p->K[j];
+            f.in_band = 0;
+            f.out_band = 1;
+            f.nfac = p->fMr[j].nfac;
+            for (int q = 0; q < p->fMr[j].nfac; ++q) f.fac[q] = p->fMr[j].fac[q];
+            f.tw = at<double>(p, p->fMr[j].tw_off);
+            size_t doff = p->lay.deconv;
+            for (int i = 0; i < j; ++i) doff += p->B[i] * 8;
+            f.fac_out = at<double>(p, doff);
+            void* out;
+            if (j == p->d - 1) {
+                out = p->ws + p->lay.spec;
+                f.out_estride = done_B * npairs;
+                f.out_roff = p0;
+                f.out_rdiv = gp;
+                f.out_rmul = npairs;
+            } else {
+                out = p->ws + ((j % 2 == 0) ? p->lay.fftA : p->lay.fftB);
+                f.out_estride = f.rows;
+                f.out_roff = 0;
+                f.out_rdiv = f.rows;
+                f.out_rmul = 0;
+            }
+            launch_fft(p->tprec, false, f, in, out, s);
+            in = out;
+            done_B *= p->B[j];
+        }
+        (void)csz;
+    }
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+// Channels of bandwidth index hi: expand + inverse FFT -> chan [M][ncp].
+fkr_status run_channels(fkr_plan* p, int hidx, int nr, hipStream_t s) {
+    const int nreal = p->n_s + p->n_t * (nr - 1);
+    const int ncp = (nreal + 1) / 2;
+    if (ncp > p->ncp_max) return FKR_E_ARG;
+    ExpandArgs a{};
+    a.d = p->d; a.n_s = p->n_s; a.n_t = p->n_t; a.nreal = nreal; a.ncp = ncp;
+    a.npairs = (nr + 1) / 2;
+    int64_t per_h = 0;
+    for (int j = 0; j < 3; ++j) { a.B[j] = p->B[j]; a.K[j] = p->K[j]; }
+    for (int j = 0; j < p->d; ++j) { a.mult_off[j] = per_h; per_h += (2 * p->order + 1) * p->B[j]; }
+    a.Btot = p->Btot;
+    a.mult = at<double>(p, p->lay.mult) + (int64_t)hidx * per_h;
+    launch_expand2(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftA, s);
+    const void* in = p->ws + p->lay.fftA;
+    int64_t done_M = 1;
+    for (int j = 0; j < p->d; ++j) {
+        FftPass f{};
+        int64_t rest = 1;
+        for (int i = j + 1; i < p->d; ++i) rest *= p->B[i];
+        f.rows = done_M * ncp * rest;
+        f.n_in = p->B[j];
+        f.F = p->L[j];
+        f.n_out = p->M[j];
+        f.K = p->K[j];
+        f.in_band = 1;
+        f.out_band = 0;
+        f.nfac = p->fL[j].nfac;
+        for (int q = 0; q < p->fL[j].nfac; ++q) f.fac[q] = p->fL[j].fac[q];
+        f.tw = at<double>(p, p->fL[j].tw_off);
+        f.fac_out = nullptr;
+        f.out_estride = f.rows;
+        f.out_roff = 0;
+        f.out_rdiv = f.rows;
+        f.out_rmul = 0;
+        void* out;
+        if (j == p->d - 1) out = p->ws + p->lay.chan;
+        else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);
+        launch_fft(p->tprec, true, f, in, out, s);
+        in = out;
+        done_M *= p->M[j];
+    }
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+double s0_floor(const fkr_plan* p, const double* h) {
+    // Below this the round-off of the spreading and the transforms is a
+    // sizeable part of s_0: 30 unit round-offs (of the spreading precision) of
+    // N * K_h(0), the largest value s_0 can take.
+    double k0 = 1.0;
+    for (int j = 0; j < p->d; ++j) k0 *= 1.0 / (h[j] * std::sqrt(2.0 * M_PI));
+    const double u = p->prec == FKR_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+    return std::max(1e-300, 30.0 * u * (double)std::max<int64_t>(p->N, 1) * k0);
+}
+
+SolveArgs solve_args(fkr_plan* p, int nr, int ny, int y_cplx, const double* h) {
+    SolveArgs a{};
+    a.P = p->n_t; a.n_s = p->n_s; a.n_t = p->n_t;
+    a.ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;
+    a.nr = nr; a.ny = ny; a.y_cplx = y_cplx;
+    a.Mtot = p->Mtot;
+    a.s0_floor = s0_floor(p, h);
+    a.ill_count = at<unsigned long long>(p, p->lay.diag + 2 * 8);
+    return a;
+}
+
+// Response sources: each real column (or re/im of complex columns).
+void add_response_sources(std::vector<WSrc>* v, int q, int y_cplx, const void* Y, int y_type) {
+    const int cpl = y_cplx ? 2 : 1;
+    for (int c = 0; c < q; ++c)
+        for (int part = 0; part < cpl; ++part) v->push_back(src_array(Y, y_type, (int64_t)q * cpl, c * cpl + part));
+}
+
+void add_probe_sources(std::vector<WSrc>* v, int Np, uint64_t seed, const void* probes, int w_type) {
+    for (int pr = 0; pr < Np; ++pr)
+        v->push_back(probes ? src_array(probes, w_type, Np, pr) : src_philox(seed, pr));
+}
+
+fkr_status common_fit_checks(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y,
+                             int y_type) {
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if ((st = check_h(p, nh, h)) != FKR_OK) return st;
+    if (q < 0 || (q > 0 && !Y && p->N > 0) || (y_complex != 0 && y_complex != 1)) return FKR_E_ARG;
+    if (q > 0 && !valid_type(y_type)) return FKR_E_ARG;
+    return FKR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fkr_status_string(fkr_status s) {
+    switch (s) {
+        case FKR_OK: return "ok";
+        case FKR_WARN_ILLPOSED: return "some grid points are ill-posed (NaN)";
+        case FKR_E_ARG: return "invalid argument";
+        case FKR_E_DOMAIN: return "samples outside the grid box";
+        case FKR_E_WORKSPACE: return "workspace missing or too small";
+        case FKR_E_DEVICE: return "HIP runtime error";
+        case FKR_E_UNSUPPORTED: return "unsupported configuration";
+        case FKR_E_STATE: return "call order violated (no points set)";
+    }
+    return "unknown status";
+}
+
+fkr_status fkr_plan_create(const fkr_plan_desc* desc, fkr_plan** out) {
+    if (!desc || !out) return FKR_E_ARG;
+    *out = nullptr;
+    fkr_plan* p = new (std::nothrow) fkr_plan();
+    if (!p) return FKR_E_ARG;
+    const fkr_status st = build_plan(desc, p);
+    if (st != FKR_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FKR_OK;
+}
+
+void fkr_plan_destroy(fkr_plan* p) { delete p; }
+
+fkr_status fkr_plan_geometry(const fkr_plan* p, fkr_geometry* g) {
+    if (!p || !g) return FKR_E_ARG;
+    std::memset(g, 0, sizeof(*g));
+    g->d = p->d; g->order = p->order; g->n_s = p->n_s; g->n_t = p->n_t;
+    for (int j = 0; j < FKR_MAX_D; ++j) {
+        const bool on = j < p->d;
+        g->M[j] = on ? p->M[j] : 1; g->L[j] = on ? p->L[j] : 1; g->K[j] = on ? p->K[j] : 0;
+        g->Mr[j] = on ? p->Mr[j] : 1; g->tile[j] = on ? p->ts[j] : 1;
+        g->delta[j] = on ? p->delta[j] : 0; g->period[j] = on ? p->T[j] : 0;
+    }
+    g->w = p->w;
+    g->kparam = p->kparam;
+    g->n_tiles = p->n_tiles;
+    g->workspace_bytes = p->lay.total;
+    return FKR_OK;
+}
+
+fkr_status fkr_workspace_size(const fkr_plan* p, size_t* bytes) {
+    if (!p || !bytes) return FKR_E_ARG;
+    *bytes = p->lay.total;
+    return FKR_OK;
+}
+
+fkr_status fkr_set_workspace(fkr_plan* p, void* ws, size_t bytes) {
+    if (!p || !ws) return FKR_E_ARG;
+    if (bytes < p->lay.total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return FKR_E_WORKSPACE;
+    p->ws = static_cast<unsigned char*>(ws);
+    p->ws_bytes = bytes;
+    p->ws_ready = false;
+    p->points_set = false;
+    std::vector<unsigned char> consts(4096, 0);
+    double* per = reinterpret_cast<double*>(consts.data());
+    for (int j = 0; j < p->d; ++j) per[j] = p->T[j];
+    int* es = reinterpret_cast<int*>(consts.data() + 64);
+    int* et = reinterpret_cast<int*>(consts.data() + 64 + 512);
+    int* pi = reinterpret_cast<int*>(consts.data() + 64 + 1024);
+    for (int c = 0; c < p->n_s; ++c) for (int j = 0; j < 3; ++j) es[3 * c + j] = p->es[c][j];
+    for (int c = 0; c < p->n_t; ++c) for (int j = 0; j < 3; ++j) et[3 * c + j] = p->et[c][j];
+    for (int b = 0; b < kMaxP; ++b) for (int c = 0; c < kMaxP; ++c) pi[b * kMaxP + c] = p->pair_index[b][c];
+    FKR_HIP(hipMemcpy(p->ws + p->lay.consts, consts.data(), consts.size(), hipMemcpyHostToDevice));
+    size_t off = p->lay.deconv;
+    for (int j = 0; j < p->d; ++j) {
+        FKR_HIP(hipMemcpy(p->ws + off, p->deconv[j].data(), p->deconv[j].size() * 8, hipMemcpyHostToDevice));
+        off += p->deconv[j].size() * 8;
+        std::vector<double> tw;
+        twiddle_table(p->Mr[j], &tw);
+        FKR_HIP(hipMemcpy(p->ws + p->fMr[j].tw_off, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+        twiddle_table(p->L[j], &tw);
+        FKR_HIP(hipMemcpy(p->ws + p->fL[j].tw_off, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+    }
+    off = p->lay.cover;
+    for (int j = 0; j < p->d; ++j) {
+        FKR_HIP(hipMemcpy(p->ws + off, p->cover[j].data(), p->cover[j].size() * 4, hipMemcpyHostToDevice));
+        off += p->cover[j].size() * 4;
+    }
+    FKR_HIP(hipMemset(p->ws + p->lay.diag, 0, 16 * 8));
+    FKR_HIP(hipDeviceSynchronize());
+    p->ws_ready = true;
+    return FKR_OK;
+}
+
+fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, void* stream) {
+    if (!p) return FKR_E_ARG;
+    if (!p->ws_ready) return FKR_E_WORKSPACE;
+    if (N < 0 || N > p->n_max || (N > 0 && !X) || !valid_type(x_type)) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    const Geo g = make_geo(p);
+    launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
+    launch_zero(p->ws + p->lay.diag, 16 * 8, s);
+    launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.tile_of), at<int32_t>(p, p->lay.cell_of),
+                     at<int32_t>(p, p->lay.counts), at<long long>(p, p->lay.diag), s);
+    launch_scan(g, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
+                at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.cursor),
+                at<long long>(p, p->lay.diag), s);
+    launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_of),
+                      at<int32_t>(p, p->lay.cell_of), at<int32_t>(p, p->lay.tile_off),
+                      at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.cursor),
+                      at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.order), at<int32_t>(p, p->lay.cnt),
+                      at<int32_t>(p, p->lay.coff), at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
+                      at<int32_t>(p, p->lay.perm), p->ws + p->lay.xs, at<long long>(p, p->lay.diag), s);
+    if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
+    p->N = N;
+    p->points_set = true;
+    p->last_stream = stream;
+    return FKR_OK;
+}
+
+fkr_status fkr_spectrum(fkr_plan* p, int nw, const void* W, int w_type, double* out, void* stream) {
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if (nw < 1 || nw > p->max_weights || !out) return FKR_E_ARG;
+    if (!W && nw != 1) return FKR_E_ARG;
+    if (W && !valid_type(w_type)) return FKR_E_ARG;
+    std::vector<WSrc> srcs;
+    for (int r = 0; r < nw; ++r) srcs.push_back(W ? src_array(W, w_type, nw, r) : src_one());
+    const hipStream_t s = S(stream);
+    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    launch_unpack_spec(p->tprec, p->Btot, p->B, p->d, (nw + 1) / 2, nw, p->ws + p->lay.spec, out, s);
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_moments(fkr_plan* p, int nh, const double* h, int nw, const void* W, int w_type,
+                       double* Sout, double* Tout, void* stream) {
+    fkr_status st = common_fit_checks(p, nh, h, nw, 0, W, w_type);
+    if (st != FKR_OK) return st;
+    if (1 + nw > p->max_weights) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    std::vector<WSrc> srcs{src_one()};
+    for (int r = 0; r < nw; ++r) srcs.push_back(src_array(W, w_type, nw, r));
+    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    const Geo g = make_geo(p);
+    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    const int nr = 1 + nw;
+    const int ncp = (p->n_s + p->n_t * nw + 1) / 2;
+    for (int hi = 0; hi < nh; ++hi) {
+        if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
+        launch_chan_out(p->tprec, p->Mtot, ncp, p->n_s, p->n_t, nw, p->ws + p->lay.chan,
+                        Sout ? Sout + (int64_t)hi * p->n_s * p->Mtot : nullptr,
+                        Tout ? Tout + (int64_t)hi * nw * p->n_t * p->Mtot : nullptr, s);
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_fit(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y, int y_type,
+                   double* mhat, double* s0, void* stream) {
+    fkr_status st = common_fit_checks(p, nh, h, q, y_complex, Y, y_type);
+    if (st != FKR_OK) return st;
+    if (q < 1 || !mhat) return FKR_E_ARG;
+    const int ny = q * (y_complex ? 2 : 1);
+    if (1 + ny > p->max_weights) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    std::vector<WSrc> srcs{src_one()};
+    add_response_sources(&srcs, q, y_complex, Y, y_type);
+    launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
+    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    const Geo g = make_geo(p);
+    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    const int nr = (int)srcs.size();
+    for (int hi = 0; hi < nh; ++hi) {
+        if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
+        SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
+        a.y_out = mhat + (int64_t)hi * ny * p->Mtot;
+        a.s0_out = s0 ? s0 + (int64_t)hi * p->Mtot : nullptr;
+        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_interp(fkr_plan* p, int nv, const double* G, int64_t Nq, const void* Xq, int x_type,
+                      double* out, void* stream) {
+    if (!p) return FKR_E_ARG;
+    if (nv < 1 || !G || Nq < 0 || (Nq > 0 && (!Xq || !out)) || !valid_type(x_type)) return FKR_E_ARG;
+    launch_interp(make_geo(p), nv, G, Nq, Xq, x_type, out, S(stream));
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y, int y_type,
+                  int Np, uint64_t seed, const void* probes, double* mhat, double* rho, double* rss,
+                  double* gcv, void* stream) {
+    fkr_status st = common_fit_checks(p, nh, h, q, y_complex, Y, y_type);
+    if (st != FKR_OK) return st;
+    if (Np < 0 || (q == 0 && Np == 0)) return FKR_E_ARG;
+    if (gcv && (Np < 1 || q < 1)) return FKR_E_ARG;
+    const int cpl = y_complex ? 2 : 1;
+    const int ny = q * cpl;
+    if (1 + ny + Np > p->max_weights) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    if (probes && !valid_type(y_type)) return FKR_E_ARG;
+    const int ptype = y_type;
+    std::vector<WSrc> srcs{src_one()};
+    add_response_sources(&srcs, q, y_complex, Y, y_type);
+    add_probe_sources(&srcs, Np, seed, probes, ptype);
+    launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
+    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    const Geo g = make_geo(p);
+    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    const int nr = (int)srcs.size();
+    double* internal = at<double>(p, p->lay.mhat);
+    double* pfit = internal + (int64_t)ny * p->Mtot;
+    double* red = at<double>(p, p->lay.red);
+    double* partial = at<double>(p, p->lay.partial);
+    const int n_items = q + Np;
+    const int ngroups = (n_items + kItemsPerGroup - 1) / kItemsPerGroup;
+    for (int hi = 0; hi < nh; ++hi) {
+        if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
+        SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
+        double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
+        a.y_out = yfit;
+        a.probe_out = pfit;
+        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+        ReduceItemArgs r{};
+        r.d = p->d; r.n_items = n_items; r.ny_cols = q; r.y_cplx = y_complex;
+        r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs; r.perm = at<int32_t>(p, p->lay.perm);
+        r.Y = Y; r.y_type = y_type; r.y_stride = (int64_t)q * cpl;
+        r.yfit = yfit; r.pfit = pfit;
+        r.partial = partial;
+        for (int gi = 0; gi < ngroups; ++gi) {
+            r.item0 = gi * kItemsPerGroup;
+            for (int it = 0; it < kItemsPerGroup; ++it) {
+                const int item = r.item0 + it;
+                r.probe[it] = (item >= q && item < n_items) ? srcs[1 + ny + (item - q)] : src_zero();
+            }
+            launch_reduce_items(g, r, 1, s);
+        }
+        launch_reduce_final(partial, 2 * n_items, red, s);
+        launch_finalize_cv(hi, Np, q, p->N, red, n_items, q, rho, rss, gcv, s);
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_dof(fkr_plan* p, int nh, const double* h, int Np, uint64_t seed, const void* probes,
+                   int w_type, double* rho, void* stream) {
+    if (!p) return FKR_E_ARG;
+    if (Np < 1 || !rho) return FKR_E_ARG;
+    if (probes && !valid_type(w_type)) return FKR_E_ARG;
+    // q = 0: only the density and the probes are spread.
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if ((st = check_h(p, nh, h)) != FKR_OK) return st;
+    return fkr_cv(p, nh, h, 0, 0, probes, w_type, Np, seed, probes, nullptr, rho, nullptr, nullptr, stream);
+}
+
+fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type,
+                        const double* mhat, int mode, double* sigma2, double* vhat, double* kappa,
+                        void* stream) {
+    fkr_status st = common_fit_checks(p, 1, h, 1, y_complex, Y, y_type);
+    if (st != FKR_OK) return st;
+    if (!mhat || !sigma2 || (mode != FKR_VAR_LOG && mode != FKR_VAR_DIRECT)) return FKR_E_ARG;
+    if (p->max_weights < 2) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    const Geo g = make_geo(p);
+    double* wbuf = at<double>(p, p->lay.wbuf);
+    launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
+    launch_resid(g, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
+                 y_complex, mhat, wbuf, s);
+    std::vector<WSrc> srcs{src_one(), src_array(wbuf, FKR_F64, 1, 0)};
+    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    launch_mult_tables(g, p->order, 1, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    if ((st = run_channels(p, 0, 2, s)) != FKR_OK) return st;
+    SolveArgs a = solve_args(p, 2, 1, 0, h);
+    double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
+    a.y_out = v;
+    launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    if (mode == FKR_VAR_LOG) {
+        double* partial = at<double>(p, p->lay.partial);
+        double* red = at<double>(p, p->lay.red);
+        launch_kappa_partial(g, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), v,
+                             wbuf + p->N, partial, s);
+        launch_reduce_final(partial, 1, red, s);
+        launch_sigma2(p->Mtot, p->N, v, red, sigma2, kappa, s);
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_hlist(int n, double a, double b, int kind, double* out) {
+    if (n < 1 || !out || !std::isfinite(a) || !std::isfinite(b) || (kind != 0 && kind != 1)) return FKR_E_ARG;
+    if (kind == 0 && !(a > 0.0 && b > 0.0)) return FKR_E_ARG;
+    for (int k = 0; k < n; ++k) {
+        const double t = n == 1 ? 1.0 : (double)k / (double)(n - 1);
+        if (kind == 0) out[k] = std::pow(10.0, std::log10(a) + t * (std::log10(b) - std::log10(a)));
+        else out[k] = a + t * (b - a);
+    }
+    out[0] = a;
+    if (n > 1) out[n - 1] = b;
+    return FKR_OK;
+}
+
+fkr_status fkr_select_bandwidth(int nh, const double* gcv, double dstd, int* index) {
+    if (nh < 1 || !gcv || !index || !(dstd >= 0.0)) return FKR_E_ARG;
+    double mn = INFINITY, sum = 0.0;
+    int cnt = 0;
+    for (int k = 0; k < nh; ++k)
+        if (std::isfinite(gcv[k])) { mn = std::min(mn, gcv[k]); sum += gcv[k]; ++cnt; }
+    if (cnt == 0) return FKR_E_ARG;
+    double thr = mn;
+    if (dstd > 0.0 && cnt > 1) {
+        const double mean = sum / cnt;
+        double ss = 0.0;
+        for (int k = 0; k < nh; ++k)
+            if (std::isfinite(gcv[k])) ss += (gcv[k] - mean) * (gcv[k] - mean);
+        thr += dstd * std::sqrt(ss / (cnt - 1));
+    }
+    int best = -1;
+    for (int k = 0; k < nh; ++k)
+        if (std::isfinite(gcv[k]) && gcv[k] <= thr) best = k;
+    *index = best;
+    return FKR_OK;
+}
+
+fkr_status fkr_get_diagnostics(fkr_plan* p, fkr_diag* out) {
+    if (!p || !out) return FKR_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    if (!p->ws_ready) return FKR_E_WORKSPACE;
+    FKR_HIP(hipStreamSynchronize(S(p->last_stream)));
+    long long d[16];
+    FKR_HIP(hipMemcpy(d, p->ws + p->lay.diag, sizeof(d), hipMemcpyDeviceToHost));
+    out->n_points = p->N;
+    out->out_of_domain = d[1];
+    out->ill_posed = d[2];
+    out->n_jobs = d[3];
+    out->max_tile_count = d[4];
+    if (d[5] != 0) return FKR_E_DEVICE;
+    if (d[1] != 0) return FKR_E_DOMAIN;
+    if (d[2] != 0) return FKR_WARN_ILLPOSED;
+    return FKR_OK;
+}
+
+}  // extern "C"

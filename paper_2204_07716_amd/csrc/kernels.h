@@ -1,0 +1,137 @@
+// Launch interfaces of the device kernels (kernels.hip), used by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fkr_internal.h"
+
+namespace fkr {
+
+constexpr int kMaxPairsPerSpread = 8;
+constexpr int kItemsPerGroup = 8;     // interpolation-reduction items per launch row
+constexpr int kRedBlocks = 1024;      // fixed grid of the two-stage reductions
+constexpr int kSortChunk = 4096;      // samples per block in the binning kernels
+constexpr int kLdsHistMax = 16384;    // tiles counted in LDS (else global atomics)
+constexpr int kSpreadBlock = 256;     // threads per spreading workgroup
+
+struct Geo {                          // geometry passed by value to kernels
+    int d, w;
+    int64_t M[3], Mr[3], ts[3], nt[3], pe[3], B[3], K[3];
+    double lo[3], hi[3], delta[3], inv_delta[3], inv_hf[3], tol[3];
+    int64_t n_tiles, Psub, Mtot, Btot, Mrtot;
+    int tsp, ncell;                   // tile pitch for cell ids, cells per tile
+    double kparam;
+    int chunk;
+};
+
+// One real weight vector for spreading / reductions.
+enum : int { W_ZERO = 0, W_ONE = 1, W_ARRAY = 2, W_PHILOX = 3 };
+struct WSrc {
+    int kind;
+    int type;          // FKR_F32 / FKR_F64 for arrays
+    const void* ptr;
+    int64_t stride;    // element stride between samples
+    int64_t col;       // element offset of this vector
+    uint64_t seed;
+    int probe;         // probe index (Philox)
+};
+
+struct SpreadSrc {
+    int npairs;
+    WSrc w[2 * kMaxPairsPerSpread];
+};
+
+struct FftPass {
+    int64_t rows;      // number of rows
+    int64_t n_in;      // input row length
+    int64_t F;         // transform length
+    int64_t n_out;     // outputs per row
+    int64_t K;         // band half-width (band input/output modes)
+    int64_t out_estride, out_roff;
+    int64_t out_rdiv, out_rmul;   // output row map: (r / rdiv) * rmul + r % rdiv
+    int in_band;       // input row holds modes -K..K (zero-padded to F)
+    int out_band;      // output = modes -K..K (else indices 0..n_out-1)
+    int nfac;
+    int fac[kMaxFactors];
+    const double* tw;  // exp(-2 pi i k / F), FP64 pairs
+    const double* fac_out;  // optional real factor per output element
+    int rows_per_block;
+};
+
+struct ExpandArgs {
+    int d, n_s, n_t, nreal, ncp, npairs;
+    int64_t B[3], K[3], Btot;
+    const double* mult;      // [dim][a][e] tables for this bandwidth
+    int64_t mult_off[3];     // offset of dim j's tables (a-major, B_j each)
+};
+
+struct SolveArgs {
+    int P, n_s, n_t, ncp, nr;      // nr real weights incl. density
+    int ny, y_cplx;                // real weights 1..ny are responses
+    int64_t Mtot;
+    double s0_floor;
+    double* y_out;                 // [q][M][(2)] per bandwidth (may be null)
+    double* probe_out;             // [nr-1-ny][M] (may be null)
+    double* s0_out;                // [M] (may be null)
+    unsigned long long* ill_count;
+};
+
+struct ReduceItemArgs {
+    int d;
+    int n_items, ny_cols, y_cplx; // items: y columns first, then probes
+    int64_t N;
+    int x_type;                   // element type of the sorted coordinates
+    const void* X;                // sorted coordinates [N][d]
+    const int32_t* perm;          // sorted position -> original sample index
+    // y columns
+    const void* Y; int y_type; int64_t y_stride;
+    const double* yfit;           // [q][M] or [q][M][2]
+    // probes
+    WSrc probe[kItemsPerGroup];
+    const double* pfit;           // [Np][M]
+    int item0;                    // first item of this launch
+    double* partial;              // [slot][kRedBlocks]
+};
+
+void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* tile_of,
+                      int32_t* cell_of, int32_t* counts, long long* diag, hipStream_t s);
+void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off,
+                 int32_t* jobs, int32_t* cursor, long long* diag, hipStream_t s);
+void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N,
+                       int64_t n_jobs_max, const int32_t* tile_of, const int32_t* cell_of,
+                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor,
+                       const int32_t* jobs, int32_t* order, int32_t* cnt, int32_t* off, uint32_t* loc,
+                       void* frac, int32_t* perm, void* xs, long long* diag, hipStream_t s);
+void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, const uint32_t* loc,
+                   const void* frac, const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max,
+                   void* subgrid, hipStream_t s);
+void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* cover, const int32_t* job_off,
+                 const void* subgrid, void* fine, hipStream_t s);
+void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
+                hipStream_t s);
+void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, const double* T,
+                        double* mult, hipStream_t s);
+void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
+                    void* out, hipStream_t s);
+void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);
+void launch_unpack_spec(int prec, int64_t Btot, const int64_t* B, int d, int npairs, int nw,
+                        const void* spec, double* out, hipStream_t s);
+void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, const void* chan,
+                     double* S, double* T, hipStream_t s);
+void launch_reduce_items(const Geo& g, const ReduceItemArgs& a, int nslots, hipStream_t s);
+void launch_reduce_final(const double* partial, int nslots, double* out, hipStream_t s);
+void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void* X,
+                   int x_type, double* out, hipStream_t s);
+void launch_finalize_cv(int nh_index, int Np, int q, int64_t N, const double* red, int n_items,
+                        int ny_cols, double* rho_out, double* rss_out, double* gcv_out,
+                        hipStream_t s);
+void launch_resid(const Geo& g, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
+                  int y_type, const void* Y, int y_cplx, const double* mhat, double* wbuf,
+                  hipStream_t s);
+void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, const int32_t* perm,
+                          const double* vhat, const double* r, double* partial, hipStream_t s);
+void launch_sigma2(int64_t Mtot, int64_t N, const double* vhat, const double* kappa_sum,
+                   double* sigma2, double* kappa_out, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace fkr

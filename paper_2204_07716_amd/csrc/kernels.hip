@@ -1,0 +1,1422 @@
+// Device kernels of the fast kernel-regression path for gfx950 (CDNA4, wave64).
+//
+// Stages (Sec. 1.2 and Sec. 2 of the paper):
+//   bin / scan / scatter   sort samples by spreading tile (once per X)
+//   spread                 gridding of eq. (16)-(17): every sample adds its
+//                          kernel footprint into an LDS copy of its padded tile
+//                          (no global atomics)
+//   fold                   sums the padded tiles into the periodic fine grid
+//   fft pass               mixed-radix Stockham FFT along one axis in LDS,
+//                          forward (eq. 19, keeping the retained band and
+//                          dividing by the gridding kernel's transform, eq. 20)
+//                          or inverse (eq. 21, zero-padded band -> grid rows)
+//   expand                 kernel-moment spectra x data spectrum (eq. 12-13 in
+//                          the frequency domain), two real channels per complex
+//   solve                  per-grid-point FP64 normal equations (eq. 3 / 11)
+//   reduce items           interpolation to the samples with the Girard and
+//                          residual dot products (Sec. 2.1, eq. 22)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace fkr {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+// a * (sgn i)
+template <typename C> __device__ __forceinline__ C cmuli(C a, int sgn) { C r; r.x = -sgn * a.y; r.y = sgn * a.x; return r; }
+
+__device__ __forceinline__ double load_as_double(const void* p, int type, int64_t i) {
+    return type == FKR_F64 ? static_cast<const double*>(p)[i] : (double)static_cast<const float*>(p)[i];
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) + Box-Muller probes
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += W0; k1 += W1;
+    }
+}
+
+__device__ double probe_value(uint64_t seed, uint64_t i, int p) {
+    uint64_t c[4] = {i, (uint64_t)(p >> 2), 0, 0};
+    philox4x64_10(c, seed, 0);
+    const int r = p & 3;
+    const uint64_t xa = r < 2 ? c[0] : c[2];
+    const uint64_t xb = r < 2 ? c[1] : c[3];
+    const double ua = ((double)(xa >> 11) + 1.0) * 0x1p-53;
+    const double ub = ((double)(xb >> 11) + 1.0) * 0x1p-53;
+    const double rad = sqrt(-2.0 * log(ua));
+    double sn, cs;
+    sincospi(2.0 * ub, &sn, &cs);
+    return (r & 1) ? rad * sn : rad * cs;
+}
+
+__device__ __forceinline__ double wval(const WSrc& s, int64_t i) {
+    switch (s.kind) {
+        case W_ONE: return 1.0;
+        case W_ARRAY: return load_as_double(s.ptr, s.type, i * s.stride + s.col);
+        case W_PHILOX: return probe_value(s.seed, (uint64_t)i, s.probe);
+        default: return 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sample binning (once per X)
+// ---------------------------------------------------------------------------
+struct Binned {
+    int64_t c0[3];    // first footprint cell, wrapped into [0, Mr)
+    double frac[3];   // u - first cell, in [w/2 - 1, w/2)
+    int tile;
+    int cell;         // first cell within the tile, pitch g.tsp
+    bool outside;
+};
+
+template <int D>
+__device__ __forceinline__ Binned bin_sample(const Geo& g, int x_type, const void* X, int64_t i) {
+    Binned b;
+    b.outside = false;
+    int tile = 0, stride = 1, cell = 0, cstride = 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double x = load_as_double(X, x_type, i * D + j);
+        if (!(x >= g.lo[j] - g.tol[j] && x <= g.hi[j] + g.tol[j])) b.outside = true;
+        x = fmin(fmax(x, g.lo[j]), g.hi[j]);
+        const double u = (x - g.lo[j]) * g.inv_hf[j];
+        const double cf = floor(u - 0.5 * g.w) + 1.0;
+        int64_t c0 = (int64_t)cf;
+        b.frac[j] = u - cf;
+        c0 = ((c0 % g.Mr[j]) + g.Mr[j]) % g.Mr[j];
+        b.c0[j] = c0;
+        const int tj = (int)(c0 / g.ts[j]);
+        tile += tj * stride;
+        stride *= (int)g.nt[j];
+        cell += (int)(c0 - (int64_t)tj * g.ts[j]) * cstride;
+        cstride *= g.tsp;
+    }
+    b.tile = tile;
+    b.cell = cell;
+    return b;
+}
+
+// Tile histogram: per-block LDS counts, then one global add per touched tile.
+template <int D>
+__global__ __launch_bounds__(256) void k_bin_count(Geo g, int x_type, const void* X, int64_t N,
+                                                   int32_t* tile_of, int32_t* cell_of,
+                                                   int32_t* counts, long long* diag) {
+    extern __shared__ int32_t hist[];   // n_tiles entries when use_lds
+    const bool use_lds = g.n_tiles <= kLdsHistMax;
+    if (use_lds)
+        for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x) hist[t] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * kSortChunk;
+    const int64_t end = min<int64_t>(N, beg + kSortChunk);
+    unsigned long long outside = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        Binned b = bin_sample<D>(g, x_type, X, i);
+        tile_of[i] = b.tile;
+        cell_of[i] = b.cell;
+        if (use_lds) atomicAdd(&hist[b.tile], 1);
+        else atomicAdd(&counts[b.tile], 1);
+        outside += b.outside ? 1ull : 0ull;
+    }
+    if (outside) atomicAdd((unsigned long long*)&diag[1], outside);
+    __syncthreads();
+    if (use_lds)
+        for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
+            if (hist[t]) atomicAdd(&counts[t], hist[t]);
+}
+
+// Single-block exclusive scans of the tile counts and of the job counts;
+// writes tile_off, job_off, the job table and resets the scatter cursors.
+__global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32_t* counts,
+                                               int32_t* tile_off, int32_t* job_off, int32_t* jobs,
+                                               int32_t* cursor, long long* diag) {
+    __shared__ int64_t sa[1024], sb[1024];
+    __shared__ int64_t smax[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n_tiles + 1023) / 1024;
+    const int64_t beg = min<int64_t>(n_tiles, t * per), end = min<int64_t>(n_tiles, beg + per);
+    int64_t a = 0, b = 0, mx = 0;
+    for (int64_t k = beg; k < end; ++k) {
+        const int64_t c = counts[k];
+        a += c;
+        b += (c + chunk - 1) / chunk;
+        mx = c > mx ? c : mx;
+    }
+    sa[t] = a; sb[t] = b; smax[t] = mx;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t va = t >= off ? sa[t - off] : 0, vb = t >= off ? sb[t - off] : 0;
+        int64_t vm = t >= off ? smax[t - off] : 0;
+        __syncthreads();
+        sa[t] += va; sb[t] += vb; smax[t] = vm > smax[t] ? vm : smax[t];
+        __syncthreads();
+    }
+    int64_t ra = sa[t] - a, rb = sb[t] - b;
+    for (int64_t k = beg; k < end; ++k) {
+        const int64_t c = counts[k];
+        tile_off[k] = (int32_t)ra;
+        job_off[k] = (int32_t)rb;
+        ra += c;
+        rb += (c + chunk - 1) / chunk;
+    }
+    if (t == 1023) {
+        tile_off[n_tiles] = (int32_t)sa[1023];
+        job_off[n_tiles] = (int32_t)sb[1023];
+        jobs[0] = (int32_t)sb[1023];   // job count in the table header
+        diag[3] = sb[1023];
+        diag[4] = smax[1023];
+    }
+    __syncthreads();
+    // job table entries: (tile, start, end, 0) at jobs[4 + 4 * job]
+    for (int64_t k = t; k < n_tiles; k += 1024) {
+        const int64_t c = counts[k];
+        const int64_t nj = (c + chunk - 1) / chunk;
+        const int64_t j0 = job_off[k], s0 = tile_off[k];
+        for (int64_t q = 0; q < nj; ++q) {
+            int32_t* e = jobs + 4 + 4 * (j0 + q);
+            e[0] = (int32_t)k;
+            e[1] = (int32_t)(s0 + q * chunk);
+            e[2] = (int32_t)min<int64_t>(s0 + (q + 1) * chunk, s0 + c);
+            e[3] = 0;
+        }
+        cursor[k] = 0;
+    }
+}
+
+// Scatter into tile order: each block ranks its samples per tile in LDS,
+// reserves a range per touched tile with one global add, and writes the
+// sample index at its tile-ordered position.
+template <int D>
+__global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int64_t N, const int32_t* tile_of,
+                                                       const int32_t* tile_off, int32_t* cursor,
+                                                       int32_t* order) {
+    extern __shared__ int32_t lcount[];   // [n_tiles] local counts, then bases
+    const bool use_lds = g.n_tiles <= kLdsHistMax;
+    if (use_lds)
+        for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x) lcount[t] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * kSortChunk;
+    const int64_t end = min<int64_t>(N, beg + kSortChunk);
+    constexpr int kPer = kSortChunk / 256;
+    int rank[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t i = beg + threadIdx.x + (int64_t)q * 256;
+        rank[q] = 0;
+        if (i < end) {
+            const int t = tile_of[i];
+            rank[q] = use_lds ? atomicAdd(&lcount[t], 1) : atomicAdd(&cursor[t], 1);
+        }
+    }
+    __syncthreads();
+    if (use_lds)
+        for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x) {
+            const int c = lcount[t];
+            lcount[t] = c ? atomicAdd(&cursor[t], c) : 0;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t i = beg + threadIdx.x + (int64_t)q * 256;
+        if (i >= end) continue;
+        const int t = tile_of[i];
+        const int64_t pos = tile_off[t] + (use_lds ? lcount[t] : 0) + rank[q];
+        if (pos < tile_off[t + 1]) order[pos] = (int32_t)i;
+    }
+}
+
+// Per job (a tile-ordered range of at most one chunk): counts per cell of the
+// tile, cnt[job][cell].
+__global__ __launch_bounds__(256) void k_cell_count(Geo g, const int32_t* jobs, const int32_t* order,
+                                                    const int32_t* cell_of, int32_t* cnt) {
+    extern __shared__ int32_t hist[];
+    const int job = blockIdx.x;
+    if (job >= jobs[0]) return;
+    const int32_t* jd = jobs + 4 + 4 * job;
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+    for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) atomicAdd(&hist[cell_of[order[s]]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cnt[(int64_t)job * g.ncell + c] = hist[c];
+}
+
+// Per tile: cell-major, job-minor exclusive offsets off[job][cell] of the
+// final (tile, cell) order.
+__global__ __launch_bounds__(1024) void k_cell_scan(Geo g, const int32_t* tile_off, const int32_t* job_off,
+                                                    const int32_t* cnt, int32_t* off) {
+    extern __shared__ uint32_t sh[];   // [ncell] totals, then [256] scan scratch
+    const int t = blockIdx.x;
+    const int j0 = job_off[t], j1 = job_off[t + 1];
+    if (j0 == j1) return;
+    uint32_t* tot = sh;
+    uint32_t* tmp = sh + g.ncell;
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+        uint32_t s = 0;
+        int j = j0;
+        for (; j + 8 <= j1; j += 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(int64_t)(j + u) * g.ncell + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; j < j1; ++j) s += cnt[(int64_t)j * g.ncell + c];
+        tot[c] = s;
+    }
+    __syncthreads();
+    // inclusive scan of tot (ncell <= 4 * blockDim)
+    const int per = (g.ncell + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int beg = threadIdx.x * per, end = min(g.ncell, beg + per);
+    uint32_t run = 0;
+    for (int c = beg; c < end; ++c) { run += tot[c]; tot[c] = run; }
+    tmp[threadIdx.x] = run;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const uint32_t v = (int)threadIdx.x >= o ? tmp[threadIdx.x - o] : 0u;
+        __syncthreads();
+        tmp[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const uint32_t before = threadIdx.x ? tmp[threadIdx.x - 1] : 0u;
+    for (int c = beg; c < end; ++c) tot[c] += before;
+    __syncthreads();
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
+        int64_t run2 = tile_off[t] + (c ? tot[c - 1] : 0u);
+        int j = j0;
+        for (; j + 8 <= j1; j += 8) {
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(int64_t)(j + u) * g.ncell + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                off[(int64_t)(j + u) * g.ncell + c] = (int32_t)run2;
+                run2 += v[u];
+            }
+        }
+        for (; j < j1; ++j) {
+            off[(int64_t)j * g.ncell + c] = (int32_t)run2;
+            run2 += cnt[(int64_t)j * g.ncell + c];
+        }
+    }
+}
+
+// Per job: place every sample at its (tile, cell) position and write the
+// records the spreading and the reductions read: packed first-cell offsets,
+// fractions, clamped coordinates and the permutation.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cell_scatter(Geo g, int x_type, const void* X,
+                                                      const int32_t* jobs, const int32_t* order,
+                                                      const int32_t* cell_of, const int32_t* off,
+                                                      uint32_t* loc, T* frac, int32_t* perm, T* xs,
+                                                      long long* diag) {
+    extern __shared__ int32_t cur[];
+    const int job = blockIdx.x;
+    if (job >= jobs[0]) return;
+    const int32_t* jd = jobs + 4 + 4 * job;
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = off[(int64_t)job * g.ncell + c];
+    __syncthreads();
+    const int t = jd[0];
+    for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
+        const int64_t i = order[s];
+        Binned b = bin_sample<D>(g, x_type, X, i);
+        // the slot follows the counted cell, so positions stay inside the tile
+        const int64_t pos = atomicAdd(&cur[cell_of[i]], 1);
+        if (b.tile != t || b.cell != cell_of[i]) {   // cannot happen: identical binning
+            atomicAdd((unsigned long long*)&diag[5], 1ull);
+            continue;
+        }
+        uint32_t l = 0;
+        int64_t rem = t;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int64_t tj = rem % g.nt[j];
+            rem /= g.nt[j];
+            l |= (uint32_t)(b.c0[j] - tj * g.ts[j]) << (10 * j);
+            frac[pos * D + j] = (T)b.frac[j];
+            const double x = load_as_double(X, x_type, i * D + j);
+            xs[pos * D + j] = (T)fmin(fmax(x, g.lo[j]), g.hi[j]);
+        }
+        loc[pos] = l;
+        perm[pos] = (int32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Spreading into LDS tiles (eq. 16-17)
+// ---------------------------------------------------------------------------
+// Spreading kernel value at distance t (fine cells).  FP32 uses the hardware
+// exp2 / sqrt approximations (about 1 ulp), FP64 the accurate library ones.
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double fast_exp(double x) { return exp(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+
+template <typename T, int KER>
+__device__ __forceinline__ T kernel_value(T t, int w, T kp) {
+    if (KER == FKR_KERNEL_ES) {
+        const T s = t * ((T)2 / (T)w);
+        const T q = (T)1 - s * s;
+        return q > (T)0 ? fast_exp(kp * (fast_sqrt(q) - (T)1)) : (T)0;
+    } else {
+        return fast_exp(-kp * t * t);
+    }
+}
+
+// Both real weights of a pair; two probes 4g+2m, 4g+2m+1 share one Philox
+// block and one Box-Muller transform.
+__device__ __forceinline__ void wval_pair(const WSrc& a, const WSrc& b, int64_t i, double* wa,
+                                          double* wb) {
+    if (a.kind == W_PHILOX && b.kind == W_PHILOX && a.seed == b.seed && (a.probe & 1) == 0 &&
+        b.probe == a.probe + 1) {
+        uint64_t c[4] = {(uint64_t)i, (uint64_t)(a.probe >> 2), 0, 0};
+        philox4x64_10(c, a.seed, 0);
+        const bool hi = (a.probe & 2) != 0;
+        const uint64_t xa = hi ? c[2] : c[0], xb = hi ? c[3] : c[1];
+        const double ua = ((double)(xa >> 11) + 1.0) * 0x1p-53;
+        const double ub = ((double)(xb >> 11) + 1.0) * 0x1p-53;
+        const double rad = sqrt(-2.0 * log(ua));
+        double sn, cs;
+        sincospi(2.0 * ub, &sn, &cs);
+        *wa = rad * cs;
+        *wb = rad * sn;
+        return;
+    }
+    *wa = wval(a, i);
+    *wb = wval(b, i);
+}
+
+// Kernel values psi(k - f), k = 0..W-1, of one dimension.
+template <int W, typename T, int KER>
+__device__ __forceinline__ void kernel_row(T f, T kp, T (&kv)[W]) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) kv[k] = kernel_value<T, KER>((T)k - f, W, kp);
+}
+
+// One job = a range of at most one chunk of samples of one tile, sorted by
+// first footprint cell.  The job is cut into equal
+// segments of consecutive samples; segment NWAVE * l + v goes to lane l of
+// wave v, so the lanes of a wave hold segments far apart and rarely share a
+// cell.  With ACC (1-D, and 2-D FP32 with W^2 <= 64) a thread sums the
+// footprints of consecutive samples that share a first cell in registers and
+// adds them to the tile when the cell changes; otherwise every sample's
+// footprint is added directly.  The tile accumulates in FP64 in LDS (LDS FP64
+// atomics are an order of magnitude faster than FP32 ones on gfx950) with the
+// compile-time pitch PE = TS + W - 1 and is written out in the element type T,
+// one pair of weight vectors at a time.
+template <int D, int W, typename T, int KER>
+__global__ __launch_bounds__(kSpreadBlock) void k_spread(Geo g, SpreadSrc src, const uint32_t* loc,
+                                                         const T* frac, const int32_t* perm,
+                                                         const int32_t* jobs, T* subgrid) {
+    constexpr int TS = spread_tile_edge(D, W);
+    constexpr int PE = TS + W - 1;
+    constexpr int PSUB = D == 1 ? PE : (D == 2 ? PE * PE : PE * PE * PE);
+    constexpr bool ACC = D == 1 || (D == 2 && W * W * (int)sizeof(T) <= 256);
+    constexpr int NWAVE = kSpreadBlock / 64;
+    __shared__ double tile[2 * PSUB];
+    const int njobs = jobs[0];
+    const int np = src.npairs;
+    const T kp = (T)g.kparam;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int segid = lane * NWAVE + wave;
+    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+        const int32_t* jd = jobs + 4 + 4 * job;
+        const int s_beg = jd[1];
+        const int n = jd[2] - jd[1];
+        const int seg = (n + kSpreadBlock - 1) / kSpreadBlock;
+        const int q0 = min(n, segid * seg), q1 = min(n, q0 + seg);
+        for (int p = 0; p < np; ++p) {
+            for (int q = threadIdx.x; q < 2 * PSUB; q += blockDim.x) tile[q] = 0.0;
+            __syncthreads();
+            if (ACC) {
+                T ar[D == 1 ? W : W * W], ai[D == 1 ? W : W * W];
+#pragma unroll
+                for (int k = 0; k < (D == 1 ? W : W * W); ++k) ar[k] = ai[k] = (T)0;
+                int cur_base = -1;
+                for (int q = q0; q <= q1; ++q) {
+                    int base = -1;
+                    if (q < q1) {
+                        const uint32_t l = loc[s_beg + q];
+                        base = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0);
+                    }
+                    if (base != cur_base && cur_base >= 0) {   // flush the running cell
+                        double* re = tile + cur_base;
+                        double* im = re + PSUB;
+                        if (D == 1) {
+#pragma unroll
+                            for (int k0 = 0; k0 < W; ++k0) {
+                                atomicAdd(re + k0, (double)ar[k0]);
+                                atomicAdd(im + k0, (double)ai[k0]);
+                                ar[k0] = ai[k0] = (T)0;
+                            }
+                        } else {
+#pragma unroll
+                            for (int k1 = 0; k1 < W; ++k1)
+#pragma unroll
+                                for (int k0 = 0; k0 < W; ++k0) {
+                                    atomicAdd(re + k1 * PE + k0, (double)ar[k1 * W + k0]);
+                                    atomicAdd(im + k1 * PE + k0, (double)ai[k1 * W + k0]);
+                                    ar[k1 * W + k0] = ai[k1 * W + k0] = (T)0;
+                                }
+                        }
+                    }
+                    if (q == q1) break;
+                    cur_base = base;
+                    const int64_t s = s_beg + q;
+                    double dwa, dwb;
+                    wval_pair(src.w[2 * p], src.w[2 * p + 1], perm[s], &dwa, &dwb);
+                    const T wa = (T)dwa, wb = (T)dwb;
+                    T kv0[W];
+                    kernel_row<W, T, KER>(frac[s * D], kp, kv0);
+                    if (D == 1) {
+#pragma unroll
+                        for (int k0 = 0; k0 < W; ++k0) {
+                            ar[k0] += kv0[k0] * wa;
+                            ai[k0] += kv0[k0] * wb;
+                        }
+                    } else {
+                        T kv1[W];
+                        kernel_row<W, T, KER>(frac[s * D + 1], kp, kv1);
+#pragma unroll
+                        for (int k1 = 0; k1 < W; ++k1) {
+                            const T a = kv1[k1] * wa, b = kv1[k1] * wb;
+#pragma unroll
+                            for (int k0 = 0; k0 < W; ++k0) {
+                                ar[k1 * W + k0] += kv0[k0] * a;
+                                ai[k1 * W + k0] += kv0[k0] * b;
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (int q = q0; q < q1; ++q) {
+                    const int64_t s = s_beg + q;
+                    const uint32_t l = loc[s];
+                    const int base = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0) +
+                                     (D > 2 ? PE * PE * (int)((l >> 20) & 1023) : 0);
+                    double dwa, dwb;
+                    wval_pair(src.w[2 * p], src.w[2 * p + 1], perm[s], &dwa, &dwb);
+                    const T wa = (T)dwa, wb = (T)dwb;
+                    T kv0[W], kv1[W];
+                    kernel_row<W, T, KER>(frac[s * D], kp, kv0);
+                    if (D > 1) kernel_row<W, T, KER>(frac[s * D + 1], kp, kv1);
+                    double* re = tile + base;
+                    double* im = re + PSUB;
+                    if (D == 2) {
+#pragma unroll
+                        for (int k1 = 0; k1 < W; ++k1) {
+                            const double a = (double)(kv1[k1] * wa), b = (double)(kv1[k1] * wb);
+#pragma unroll
+                            for (int k0 = 0; k0 < W; ++k0) {
+                                atomicAdd(re + k1 * PE + k0, (double)kv0[k0] * a);
+                                atomicAdd(im + k1 * PE + k0, (double)kv0[k0] * b);
+                            }
+                        }
+                    } else if (D == 3) {
+                        const T f2 = frac[s * D + 2];
+                        for (int k2 = 0; k2 < W; ++k2) {
+                            const T v2 = kernel_value<T, KER>((T)k2 - f2, W, kp);
+                            const double a2 = (double)(v2 * wa), b2 = (double)(v2 * wb);
+                            double* re2 = re + k2 * PE * PE;
+                            double* im2 = im + k2 * PE * PE;
+#pragma unroll
+                            for (int k1 = 0; k1 < W; ++k1) {
+                                const double a = (double)kv1[k1] * a2, b = (double)kv1[k1] * b2;
+#pragma unroll
+                                for (int k0 = 0; k0 < W; ++k0) {
+                                    atomicAdd(re2 + k1 * PE + k0, (double)kv0[k0] * a);
+                                    atomicAdd(im2 + k1 * PE + k0, (double)kv0[k0] * b);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // subgrid layout [job][pair][cell][re, im]
+            T* dst = subgrid + ((int64_t)job * np + p) * PSUB * 2;
+            for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
+                dst[2 * c] = (T)tile[c];
+                dst[2 * c + 1] = (T)tile[PSUB + c];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Fine cell (c_0, .., c_{d-1}) of pair p = sum over the padded tiles that
+// cover it and over the jobs of each such tile, in a fixed order
+// (deterministic).  A block handles 64 (cell, pair) items; its 4 waves take
+// the jobs of each covering tile round-robin and the 4 partial sums are added
+// in LDS.  Output layout [pair][cell].
+template <int D, typename T, typename TO>
+__global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cover,
+                                              const int32_t* job_off, const T* subgrid, TO* fine) {
+    __shared__ double red[2][4][64];
+    const int slot = threadIdx.x & 63, phase = threadIdx.x >> 6;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + slot;
+    double re = 0, im = 0;
+    if (idx < g.Mrtot * np) {
+        const int64_t cell = idx % g.Mrtot;
+        const int p = (int)(idx / g.Mrtot);
+        const int cs = 1 + 2 * kCoverSlots;
+        const int32_t* cv[3];
+        int64_t rem = cell, cov_base = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (j < D) {
+                const int64_t c = rem % g.Mr[j];
+                rem /= g.Mr[j];
+                cv[j] = cover + cov_base + c * cs;
+                cov_base += g.Mr[j] * cs;
+            }
+        }
+        const int64_t lsize = g.Psub * np * 2;
+        const int n0 = cv[0][0];
+        const int n1 = D > 1 ? cv[1][0] : 1;
+        const int n2 = D > 2 ? cv[2][0] : 1;
+        for (int a2 = 0; a2 < n2; ++a2)
+            for (int a1 = 0; a1 < n1; ++a1)
+                for (int a0 = 0; a0 < n0; ++a0) {
+                    int64_t tile = cv[0][1 + 2 * a0];
+                    int64_t off = cv[0][2 + 2 * a0];
+                    if (D > 1) {
+                        tile += g.nt[0] * cv[1][1 + 2 * a1];
+                        off += g.pe[0] * cv[1][2 + 2 * a1];
+                    }
+                    if (D > 2) {
+                        tile += g.nt[0] * g.nt[1] * cv[2][1 + 2 * a2];
+                        off += g.pe[0] * g.pe[1] * cv[2][2 + 2 * a2];
+                    }
+                    const int64_t jb = job_off[tile] + phase, je = job_off[tile + 1];
+                    const T* sg = subgrid + jb * lsize + (p * g.Psub + off) * 2;
+                    int64_t jj = jb;
+                    double r4[4] = {0, 0, 0, 0}, i4[4] = {0, 0, 0, 0};
+                    for (; jj + 12 < je; jj += 16, sg += 16 * lsize) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            r4[u] += (double)sg[4 * u * lsize];
+                            i4[u] += (double)sg[4 * u * lsize + 1];
+                        }
+                    }
+                    for (; jj < je; jj += 4, sg += 4 * lsize) {
+                        r4[0] += (double)sg[0];
+                        i4[0] += (double)sg[1];
+                    }
+                    re += (r4[0] + r4[1]) + (r4[2] + r4[3]);
+                    im += (i4[0] + i4[1]) + (i4[2] + i4[3]);
+                }
+    }
+    red[0][phase][slot] = re;
+    red[1][phase][slot] = im;
+    __syncthreads();
+    if (phase == 0 && idx < g.Mrtot * np) {
+        const double sr = (red[0][0][slot] + red[0][1][slot]) + (red[0][2][slot] + red[0][3][slot]);
+        const double si = (red[1][0][slot] + red[1][1][slot]) + (red[1][2][slot] + red[1][3][slot]);
+        fine[idx * 2] = (TO)sr;
+        fine[idx * 2 + 1] = (TO)si;
+    }
+}
+
+// One radix-RAD Stockham stage (Govindaraju et al., SC'08 formulation):
+// butterfly j reads a[j + q F/RAD], twiddles by W_F^(q k F/(Ns RAD)) with
+// k = j mod Ns, and writes b[(j/Ns) Ns RAD + k + q Ns].
+template <typename T, bool INV, int RAD>
+__device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typename V2<T>::t* b,
+                                               int F, int Ns, int t, int tpr, const double* tw) {
+    using C = typename V2<T>::t;
+    const int sgn = INV ? 1 : -1;
+    const int nb = F / RAD;
+    const int tws = F / (Ns * RAD);
+    for (int j = t; j < nb; j += tpr) {
+        const int k = j % Ns;
+        C v[RAD];
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) v[q] = a[j + q * nb];
+        if (Ns > 1) {
+#pragma unroll
+            for (int q = 1; q < RAD; ++q) {
+                const double2 w = reinterpret_cast<const double2*>(tw)[q * k * tws];
+                C c;
+                c.x = (T)w.x;
+                c.y = (T)(INV ? -w.y : w.y);
+                v[q] = cmul(v[q], c);
+            }
+        }
+        C y[RAD];
+        if (RAD == 2) {
+            y[0] = cadd(v[0], v[1]);
+            y[1] = csub(v[0], v[1]);
+        } else if (RAD == 4) {
+            const C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+            const C t2 = cadd(v[1], v[3]), t3 = cmuli(csub(v[1], v[3]), sgn);
+            y[0] = cadd(t0, t2);
+            y[2] = csub(t0, t2);
+            y[1] = cadd(t1, t3);
+            y[3] = csub(t1, t3);
+        } else if (RAD == 3) {
+            const T c3 = (T)0.86602540378443864676;
+            const C tt = cadd(v[1], v[2]);
+            const C u = cmuli(cscale(csub(v[1], v[2]), c3), sgn);
+            const C m = csub(v[0], cscale(tt, (T)0.5));
+            y[0] = cadd(v[0], tt);
+            y[1] = cadd(m, u);
+            y[2] = csub(m, u);
+        } else {
+            const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+            const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+            const C a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+            const C b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+            y[0] = cadd(v[0], cadd(a1, a2));
+            const C r1 = cadd(v[0], cadd(cscale(a1, c1), cscale(a2, c2)));
+            const C r2 = cadd(v[0], cadd(cscale(a1, c2), cscale(a2, c1)));
+            const C i1 = cmuli(cadd(cscale(b1, s1), cscale(b2, s2)), sgn);
+            const C i2 = cmuli(csub(cscale(b1, s2), cscale(b2, s1)), sgn);
+            y[1] = cadd(r1, i1);
+            y[4] = csub(r1, i1);
+            y[2] = cadd(r2, i2);
+            y[3] = csub(r2, i2);
+        }
+        const int base = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) b[base + q * Ns] = y[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stockham FFT along the contiguous axis of `rows` rows, in LDS.
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict__ in,
+                                             typename V2<T>::t* __restrict__ out, FftPass f) {
+    using C = typename V2<T>::t;
+    extern __shared__ unsigned char smem_raw[];
+    const int R = f.rows_per_block;
+    const int64_t row0 = (int64_t)blockIdx.x * R;
+    const int nr = (int)min<int64_t>(R, f.rows - row0);
+    const int F = (int)f.F;
+    C* buf0 = reinterpret_cast<C*>(smem_raw);
+    C* buf1 = buf0 + (int64_t)R * F;
+    const int tpr = blockDim.x / R;
+    const int rl = threadIdx.x / tpr, t = threadIdx.x % tpr;
+    const int64_t n_in = f.n_in;
+    if (f.in_band) {
+        // Modes n = e - K, e < n_in, placed at n mod F; modes that coincide
+        // modulo F (band wider than the transform) are summed, which is exact
+        // for the values at the F output points.
+        for (int64_t q = threadIdx.x; q < (int64_t)nr * F; q += blockDim.x) {
+            const int64_t r = q / F, pos = q - r * F;
+            C acc;
+            acc.x = 0;
+            acc.y = 0;
+            for (int64_t e = (pos + f.K) % F; e < n_in; e += F) acc = cadd(acc, in[(row0 + r) * n_in + e]);
+            buf0[q] = acc;
+        }
+    } else {
+        for (int64_t q = threadIdx.x; q < nr * n_in; q += blockDim.x) {
+            const int64_t r = q / n_in, e = q - r * n_in;
+            buf0[r * F + e] = in[(row0 + r) * n_in + e];
+        }
+    }
+    __syncthreads();
+
+    C* src = buf0;
+    C* dst = buf1;
+    int Ns = 1;
+    for (int s = 0; s < f.nfac; ++s) {
+        const int rad = f.fac[s];
+        if (rl < nr) {
+            const C* a = src + (int64_t)rl * F;
+            C* b = dst + (int64_t)rl * F;
+            switch (rad) {
+                case 4: stockham_stage<T, INV, 4>(a, b, F, Ns, t, tpr, f.tw); break;
+                case 2: stockham_stage<T, INV, 2>(a, b, F, Ns, t, tpr, f.tw); break;
+                case 3: stockham_stage<T, INV, 3>(a, b, F, Ns, t, tpr, f.tw); break;
+                default: stockham_stage<T, INV, 5>(a, b, F, Ns, t, tpr, f.tw); break;
+            }
+        }
+        __syncthreads();
+        C* tmp = src; src = dst; dst = tmp;
+        Ns *= rad;
+    }
+
+    const int64_t n_out = f.n_out;
+    for (int64_t q = threadIdx.x; q < n_out * nr; q += blockDim.x) {
+        const int64_t e = q / nr, r = q - e * nr;
+        const int64_t pos = f.out_band ? (e - f.K + F) % F : e;
+        C v = src[r * F + pos];
+        if (f.fac_out) v = cscale(v, (T)f.fac_out[e]);
+        const int64_t row = row0 + r;
+        out[e * f.out_estride + f.out_roff + (row / f.out_rdiv) * f.out_rmul + row % f.out_rdiv] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-moment spectra (Hermite form of the Gaussian's moment transforms):
+// mult[h][dim j][a][e] = He_a(h_j w) exp(-(h_j w)^2/2) / T_j, w = 2 pi (e-K_j)/T_j.
+// The phase i^a is applied in k_expand; the division by h^a (equilibration)
+// is implicit in using He_a(h w) without the h^a factor.
+// ---------------------------------------------------------------------------
+struct HList { double h[FKR_MAX_H * 3]; };
+
+__global__ void k_mult_tables(Geo g, int na, int nh, HList hl, const double* T, double* mult,
+                              int64_t per_h) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per_h * nh) return;
+    const int hi = (int)(idx / per_h);
+    int64_t r = idx - hi * per_h;
+    int j = 0;
+    while (j < g.d - 1 && r >= na * g.B[j]) { r -= na * g.B[j]; ++j; }
+    const int a = (int)(r / g.B[j]);
+    const int64_t e = r - a * g.B[j];
+    const double Tj = T[j];
+    const double om = 2.0 * M_PI * (double)(e - g.K[j]) / Tj;
+    const double u = hl.h[hi * 3 + j] * om;
+    double hm = 1.0, he = u;
+    if (a == 0) he = 1.0;
+    for (int k = 1; k < a; ++k) { const double hn = u * he - k * hm; hm = he; he = hn; }
+    mult[idx] = he * exp(-0.5 * u * u) / Tj;
+}
+
+// Y_c(n) = X_{2c}(n) + i X_{2c+1}(n), X_ch = C_r(n) i^{|a|} prod_j mult_j[a_j](n_j),
+// with C_r unpacked from the pair spectra Z_p = C_{2p} + i C_{2p+1}.
+template <typename T>
+__global__ __launch_bounds__(256) void k_expand(ExpandArgs a, const int* es, const int* et,
+                                                const typename V2<T>::t* spec,
+                                                typename V2<T>::t* out) {
+    using C = typename V2<T>::t;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.Btot * a.ncp) return;
+    const int c = (int)(idx / a.Btot);
+    const int64_t n = idx - (int64_t)c * a.Btot;
+    int64_t e[3] = {0, 0, 0}, nn = 0, rem = n, stride = 1;
+    for (int j = 0; j < a.d; ++j) {
+        e[j] = rem % a.B[j];
+        rem /= a.B[j];
+        nn += (a.B[j] - 1 - e[j]) * stride;
+        stride *= a.B[j];
+    }
+    double acc_re = 0.0, acc_im = 0.0;
+    for (int half = 0; half < 2; ++half) {
+        const int ch = 2 * c + half;
+        if (ch >= a.nreal) break;
+        int r;
+        const int* ex;
+        if (ch < a.n_s) { r = 0; ex = es + 3 * ch; }
+        else { r = 1 + (ch - a.n_s) / a.n_t; ex = et + 3 * ((ch - a.n_s) % a.n_t); }
+        const int p = r >> 1;
+        const C zn = spec[n * a.npairs + p];
+        const C zm = spec[nn * a.npairs + p];
+        double cr, ci;
+        if ((r & 1) == 0) { cr = 0.5 * ((double)zn.x + (double)zm.x); ci = 0.5 * ((double)zn.y - (double)zm.y); }
+        else { cr = 0.5 * ((double)zn.y + (double)zm.y); ci = -0.5 * ((double)zn.x - (double)zm.x); }
+        double m = 1.0;
+        int deg = 0;
+        for (int j = 0; j < a.d; ++j) {
+            m *= a.mult[a.mult_off[j] + ex[j] * a.B[j] + e[j]];
+            deg += ex[j];
+        }
+        double xr = cr * m, xi = ci * m;
+        switch (deg & 3) {   // multiply by i^deg
+            case 1: { const double t0 = xr; xr = -xi; xi = t0; break; }
+            case 2: xr = -xr; xi = -xi; break;
+            case 3: { const double t0 = xr; xr = xi; xi = -t0; break; }
+            default: break;
+        }
+        if (half == 0) { acc_re += xr; acc_im += xi; }
+        else { acc_re -= xi; acc_im += xr; }   // + i * X
+    }
+    C o;
+    o.x = (T)acc_re;
+    o.y = (T)acc_im;
+    out[idx] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Per-grid-point solve (eq. 3 / 11) in FP64.
+// ---------------------------------------------------------------------------
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, const T* chan) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.Mtot) return;
+    const T* ch = chan + k * 2 * a.ncp;
+    double A[P][P];
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+#pragma unroll
+        for (int c = 0; c <= b; ++c) A[b][c] = (double)ch[pidx[b * kMaxP + c]];
+    const double s0 = (double)ch[0];
+    bool ill = !(s0 > a.s0_floor) || !isfinite(s0);
+    // Cholesky A = L L^T (lower triangle in place).
+    double diag0[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) diag0[b] = A[b][b];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        double v = A[c][c];
+#pragma unroll
+        for (int q = 0; q < c; ++q) v -= A[c][q] * A[c][q];
+        if (!(v > 1e-12 * diag0[c])) ill = true;
+        const double l = sqrt(fmax(v, 1e-300));
+        A[c][c] = l;
+        const double il = 1.0 / l;
+#pragma unroll
+        for (int b = c + 1; b < P; ++b) {
+            double u = A[b][c];
+#pragma unroll
+            for (int q = 0; q < c; ++q) u -= A[b][q] * A[c][q];
+            A[b][c] = u * il;
+        }
+    }
+    // r0 = A^{-1} e_0 (row 0 of the symmetric inverse).
+    double y[P], r0[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+        double v = b == 0 ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < b; ++q) v -= A[b][q] * y[q];
+        y[b] = v / A[b][b];
+    }
+#pragma unroll
+    for (int b = P - 1; b >= 0; --b) {
+        double v = y[b];
+#pragma unroll
+        for (int q = b + 1; q < P; ++q) v -= A[q][b] * r0[q];
+        r0[b] = v / A[b][b];
+    }
+    const double nan = __builtin_nan("");
+    if (a.s0_out) a.s0_out[k] = s0;
+    if (ill && a.ill_count) atomicAdd(a.ill_count, 1ull);
+    for (int r = 1; r < a.nr; ++r) {
+        const T* t = ch + a.n_s + (r - 1) * a.n_t;
+        double m = 0.0;
+#pragma unroll
+        for (int b = 0; b < P; ++b) m += r0[b] * (double)t[b];
+        if (ill) m = nan;
+        if (r <= a.ny) {
+            if (a.y_out) {
+                const int cpl = a.y_cplx ? 2 : 1;
+                const int col = (r - 1) / cpl, part = (r - 1) % cpl;
+                a.y_out[(col * a.Mtot + k) * cpl + part] = m;
+            }
+        } else if (a.probe_out) {
+            a.probe_out[(int64_t)(r - 1 - a.ny) * a.Mtot + k] = m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Multilinear interpolation helpers
+// ---------------------------------------------------------------------------
+template <int D>
+struct Corners {
+    int64_t idx[1 << D];
+    double w[1 << D];
+};
+
+template <int D>
+__device__ __forceinline__ Corners<D> corners(const Geo& g, int x_type, const void* X, int64_t i) {
+    int64_t cell[3];
+    double fr[3];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double x = load_as_double(X, x_type, i * D + j);
+        const double t = (x - g.lo[j]) * g.inv_delta[j];
+        double fl = floor(t);
+        fl = fmin(fmax(fl, 0.0), (double)(g.M[j] - 2));
+        cell[j] = (int64_t)fl;
+        fr[j] = t - fl;
+    }
+    Corners<D> c;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) {
+        double w = 1.0;
+        int64_t id = 0, stride = 1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int bit = (q >> j) & 1;
+            w *= bit ? fr[j] : 1.0 - fr[j];
+            id += (cell[j] + bit) * stride;
+            stride *= g.M[j];
+        }
+        c.idx[q] = id;
+        c.w[q] = w;
+    }
+    return c;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_interp(Geo g, int nv, const double* G, int64_t Nq,
+                                                const void* X, int x_type, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nq) return;
+    const Corners<D> c = corners<D>(g, x_type, X, i);
+    for (int v = 0; v < nv; ++v) {
+        const double* gv = G + (int64_t)v * g.Mtot;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < (1 << D); ++q) s += c.w[q] * gv[c.idx[q]];
+        out[(int64_t)v * Nq + i] = s;
+    }
+}
+
+// Per-block sums of a fixed-size accumulator vector; thread 0 of the block
+// holds the result afterwards (LDS tree, fixed order).
+template <int NA>
+__device__ __forceinline__ void block_sum(double (&acc)[NA], double* sh) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) sh[q * 256 + threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) sh[q * 256 + threadIdx.x] += sh[q * 256 + threadIdx.x + off];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = sh[q * 256];
+}
+
+// Items: y columns (slot 2 it: sum |y - yhat|^2) and probes
+// (slots 2 it, 2 it + 1: sum w^2, sum w * w_hat).
+template <int D>
+__global__ __launch_bounds__(256) void k_reduce_items(Geo g, ReduceItemArgs a) {
+    __shared__ double sh[2 * kItemsPerGroup * 256];
+    double acc[2 * kItemsPerGroup];
+#pragma unroll
+    for (int q = 0; q < 2 * kItemsPerGroup; ++q) acc[q] = 0.0;
+    const int it0 = a.item0 + blockIdx.y * kItemsPerGroup;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
+        const int64_t i = a.perm[s];
+#pragma unroll
+        for (int it = 0; it < kItemsPerGroup; ++it) {
+            const int item = it0 + it;
+            if (item >= a.n_items) break;
+            if (item < a.ny_cols) {
+                if (a.y_cplx) {
+                    double fr = 0.0, fi = 0.0;
+                    const double* gv = a.yfit + (int64_t)item * g.Mtot * 2;
+#pragma unroll
+                    for (int q = 0; q < (1 << D); ++q) { fr += c.w[q] * gv[2 * c.idx[q]]; fi += c.w[q] * gv[2 * c.idx[q] + 1]; }
+                    const double yr = load_as_double(a.Y, a.y_type, i * a.y_stride + 2 * item);
+                    const double yi = load_as_double(a.Y, a.y_type, i * a.y_stride + 2 * item + 1);
+                    acc[2 * it] += (yr - fr) * (yr - fr) + (yi - fi) * (yi - fi);
+                } else {
+                    double f = 0.0;
+                    const double* gv = a.yfit + (int64_t)item * g.Mtot;
+#pragma unroll
+                    for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
+                    const double y = load_as_double(a.Y, a.y_type, i * a.y_stride + item);
+                    acc[2 * it] += (y - f) * (y - f);
+                }
+            } else {
+                const double wv = wval(a.probe[it], i);
+                const double* gv = a.pfit + (int64_t)(item - a.ny_cols) * g.Mtot;
+                double f = 0.0;
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
+                acc[2 * it] += wv * wv;
+                acc[2 * it + 1] += wv * f;
+            }
+        }
+    }
+    block_sum<2 * kItemsPerGroup>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int it = 0; it < kItemsPerGroup; ++it) {
+            const int item = it0 + it;
+            if (item >= a.n_items) break;
+            a.partial[(int64_t)(2 * item) * kRedBlocks + blockIdx.x] = acc[2 * it];
+            a.partial[(int64_t)(2 * item + 1) * kRedBlocks + blockIdx.x] = acc[2 * it + 1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* partial, double* out) {
+    __shared__ double sh[256];
+    const int slot = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < kRedBlocks; b += 256) v += partial[(int64_t)slot * kRedBlocks + b];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[slot] = sh[0];
+}
+
+__global__ void k_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, int ny_cols,
+                              double* rho_out, double* rss_out, double* gcv_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double mean = 0.0;
+    for (int p = 0; p < Np; ++p) {
+        const int item = ny_cols + p;
+        const double ww = red[2 * item], wh = red[2 * item + 1];
+        const double rho = (ww - wh) / ww;
+        if (rho_out) rho_out[(int64_t)hidx * Np + p] = rho;
+        mean += rho;
+    }
+    mean = Np > 0 ? mean / Np : __builtin_nan("");
+    for (int c = 0; c < q; ++c) {
+        const double rss = red[2 * c];
+        if (rss_out) rss_out[(int64_t)hidx * q + c] = rss;
+        if (gcv_out) gcv_out[(int64_t)hidx * q + c] = (rss / (double)N) / (mean * mean);
+    }
+}
+
+// Residuals of the mean fit for the variance pass (Sec. 3): wbuf[i] = the
+// response of the second fit (log(r + 1/N) or r), wbuf[N + i] = r.
+template <int D>
+__global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x_type, const void* xs,
+                                               const int32_t* perm, int y_type, const void* Y,
+                                               int y_cplx, const double* mhat, double* wbuf) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const Corners<D> c = corners<D>(g, x_type, xs, s);
+    const int64_t i = perm[s];
+    double r;
+    if (y_cplx) {
+        double fr = 0.0, fi = 0.0;
+#pragma unroll
+        for (int q = 0; q < (1 << D); ++q) { fr += c.w[q] * mhat[2 * c.idx[q]]; fi += c.w[q] * mhat[2 * c.idx[q] + 1]; }
+        const double yr = load_as_double(Y, y_type, 2 * i) - fr;
+        const double yi = load_as_double(Y, y_type, 2 * i + 1) - fi;
+        r = yr * yr + yi * yi;
+    } else {
+        double f = 0.0;
+#pragma unroll
+        for (int q = 0; q < (1 << D); ++q) f += c.w[q] * mhat[c.idx[q]];
+        const double e = load_as_double(Y, y_type, i) - f;
+        r = e * e;
+    }
+    wbuf[i] = mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r;
+    wbuf[N + i] = r;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_kappa_partial(Geo g, int64_t N, int x_type, const void* xs,
+                                                       const int32_t* perm, const double* vhat,
+                                                       const double* r, double* partial) {
+    __shared__ double sh[256];
+    double acc[1] = {0.0};
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const Corners<D> c = corners<D>(g, x_type, xs, s);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < (1 << D); ++q) v += c.w[q] * vhat[c.idx[q]];
+        acc[0] += r[perm[s]] * exp(-v);
+    }
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+}
+
+__global__ __launch_bounds__(256) void k_sigma2(int64_t Mtot, int64_t N, const double* vhat,
+                                                const double* ksum, double* sigma2,
+                                                double* kappa_out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double kappa = (double)N / ksum[0];
+    if (k == 0 && kappa_out) kappa_out[0] = kappa;
+    if (k >= Mtot) return;
+    sigma2[k] = exp(vhat[k]) / kappa;
+}
+
+__global__ void k_zero(uint32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Per-weight spectra C_r(n) (complex128, [r][n]) from the pair spectra.
+template <typename T>
+__global__ void k_unpack_spec(int64_t Btot, int d, int64_t B0, int64_t B1, int64_t B2, int npairs,
+                              int nw, const typename V2<T>::t* spec, double* out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Btot * nw) return;
+    const int r = (int)(idx / Btot);
+    const int64_t n = idx - (int64_t)r * Btot;
+    const int64_t B[3] = {B0, B1, B2};
+    int64_t rem = n, nn = 0, stride = 1;
+    for (int j = 0; j < d; ++j) {
+        const int64_t e = rem % B[j];
+        rem /= B[j];
+        nn += (B[j] - 1 - e) * stride;
+        stride *= B[j];
+    }
+    const int p = r >> 1;
+    const auto zn = spec[n * npairs + p];
+    const auto zm = spec[nn * npairs + p];
+    double cr, ci;
+    if ((r & 1) == 0) { cr = 0.5 * ((double)zn.x + (double)zm.x); ci = 0.5 * ((double)zn.y - (double)zm.y); }
+    else { cr = 0.5 * ((double)zn.y + (double)zm.y); ci = -0.5 * ((double)zn.x - (double)zm.x); }
+    out[2 * idx] = cr;
+    out[2 * idx + 1] = ci;
+}
+
+// Channel grids [k][ncp] complex -> S [n_s][M] and T [nw][n_t][M] (FP64).
+template <typename T>
+__global__ void k_chan_out(int64_t Mtot, int ncp, int n_s, int n_t, int nw, const T* chan,
+                           double* S, double* Tt) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nreal = n_s + n_t * nw;
+    if (idx >= Mtot * nreal) return;
+    const int ch = (int)(idx / Mtot);
+    const int64_t k = idx - (int64_t)ch * Mtot;
+    const double v = (double)chan[k * 2 * ncp + ch];
+    if (ch < n_s) { if (S) S[(int64_t)ch * Mtot + k] = v; }
+    else if (Tt) Tt[(int64_t)(ch - n_s) * Mtot + k] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n > 0) k_zero<<<nblk(n), 256, 0, s>>>(static_cast<uint32_t*>(p), n);
+}
+
+void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* tile_of,
+                      int32_t* cell_of, int32_t* counts, long long* diag, hipStream_t s) {
+    if (N == 0) return;
+    const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
+    const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
+    switch (g.d) {
+        case 1: k_bin_count<1><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_of, cell_of, counts, diag); break;
+        case 2: k_bin_count<2><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_of, cell_of, counts, diag); break;
+        default: k_bin_count<3><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_of, cell_of, counts, diag); break;
+    }
+}
+
+void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
+                 int32_t* cursor, long long* diag, hipStream_t s) {
+    k_scan<<<1, 1024, 0, s>>>(g.n_tiles, g.chunk, counts, tile_off, job_off, jobs, cursor, diag);
+}
+
+void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N,
+                       int64_t n_jobs_max, const int32_t* tile_of, const int32_t* cell_of,
+                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor,
+                       const int32_t* jobs, int32_t* order, int32_t* cnt, int32_t* off, uint32_t* loc,
+                       void* frac, int32_t* perm, void* xs, long long* diag, hipStream_t s) {
+    if (N == 0) return;
+    const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
+    const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
+    k_scatter_tiles<1><<<nb, 256, lds, s>>>(g, N, tile_of, tile_off, cursor, order);
+    const unsigned nj = (unsigned)n_jobs_max;
+    k_cell_count<<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, order, cell_of, cnt);
+    k_cell_scan<<<(unsigned)g.n_tiles, 1024, ((size_t)g.ncell + 1024) * 4, s>>>(g, tile_off, job_off, cnt, off);
+#define FKR_CSCAT(D, T) k_cell_scatter<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, x_type, X, jobs, order, cell_of, off, loc, static_cast<T*>(frac), perm, static_cast<T*>(xs), diag)
+    if (prec == FKR_F64) {
+        if (g.d == 1) FKR_CSCAT(1, double); else if (g.d == 2) FKR_CSCAT(2, double); else FKR_CSCAT(3, double);
+    } else {
+        if (g.d == 1) FKR_CSCAT(1, float); else if (g.d == 2) FKR_CSCAT(2, float); else FKR_CSCAT(3, float);
+    }
+#undef FKR_CSCAT
+}
+
+template <int D, int W, typename T, int KER>
+static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
+                     const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max, void* subgrid,
+                     hipStream_t s) {
+    if constexpr (spread_tile_edge(D, W) > 0) {
+        const unsigned nb = (unsigned)std::min<int64_t>(n_jobs_max, 256 * 8);
+        k_spread<D, W, T, KER><<<nb, kSpreadBlock, 0, s>>>(g, src, loc, static_cast<const T*>(frac),
+                                                           perm, jobs, static_cast<T*>(subgrid));
+    }
+}
+
+template <int D, typename T, int KER>
+static void spread_d(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
+                     const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max, void* subgrid,
+                     hipStream_t s) {
+    switch (g.w) {
+        case 6: spread_w<D, 6, T, KER>(g, src, loc, frac, perm, jobs, n_jobs_max, subgrid, s); break;
+        case 8: spread_w<D, 8, T, KER>(g, src, loc, frac, perm, jobs, n_jobs_max, subgrid, s); break;
+        case 12: spread_w<D, 12, T, KER>(g, src, loc, frac, perm, jobs, n_jobs_max, subgrid, s); break;
+        case 16: spread_w<D, 16, T, KER>(g, src, loc, frac, perm, jobs, n_jobs_max, subgrid, s); break;
+        default: spread_w<D, 24, T, KER>(g, src, loc, frac, perm, jobs, n_jobs_max, subgrid, s); break;
+    }
+}
+
+void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, const uint32_t* loc,
+                   const void* frac, const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max,
+                   void* subgrid, hipStream_t s) {
+#define FKR_SPREAD(D, T, KER) spread_d<D, T, KER>(g, src, loc, frac, perm, jobs, n_jobs_max, subgrid, s)
+#define FKR_SPREAD_K(D, T) do { if (kernel == FKR_KERNEL_ES) FKR_SPREAD(D, T, FKR_KERNEL_ES); else FKR_SPREAD(D, T, FKR_KERNEL_GAUSS); } while (0)
+    if (prec == FKR_F64) {
+        if (g.d == 1) FKR_SPREAD_K(1, double); else if (g.d == 2) FKR_SPREAD_K(2, double); else FKR_SPREAD_K(3, double);
+    } else {
+        if (g.d == 1) FKR_SPREAD_K(1, float); else if (g.d == 2) FKR_SPREAD_K(2, float); else FKR_SPREAD_K(3, float);
+    }
+#undef FKR_SPREAD_K
+#undef FKR_SPREAD
+}
+
+void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* cover,
+                 const int32_t* job_off, const void* subgrid, void* fine, hipStream_t s) {
+    const int64_t n = g.Mrtot * npairs;
+#define FKR_FOLD(D, T, TO) k_fold<D, T, TO><<<nblk(n, 64), 256, 0, s>>>(g, npairs, cover, job_off, static_cast<const T*>(subgrid), static_cast<TO*>(fine))
+#define FKR_FOLD_D(T, TO) do { if (g.d == 1) FKR_FOLD(1, T, TO); else if (g.d == 2) FKR_FOLD(2, T, TO); else FKR_FOLD(3, T, TO); } while (0)
+    if (prec == FKR_F64) FKR_FOLD_D(double, double);
+    else if (tprec == FKR_F64) FKR_FOLD_D(float, double);
+    else FKR_FOLD_D(float, float);
+#undef FKR_FOLD_D
+#undef FKR_FOLD
+}
+
+void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void* out, hipStream_t s) {
+    FftPass f = f0;
+    const size_t csz = prec == FKR_F64 ? 16 : 8;
+    int R = 64;
+    while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;
+    while (R > 1 && f.rows < R) R >>= 1;
+    f.rows_per_block = R;
+    const size_t lds = (size_t)2 * R * f.F * csz;
+    const unsigned nb = (unsigned)((f.rows + R - 1) / R);
+    if (nb == 0) return;
+    if (prec == FKR_F64) {
+        if (inverse) k_fft<double, true><<<nb, 256, lds, s>>>(static_cast<const double2*>(in), static_cast<double2*>(out), f);
+        else k_fft<double, false><<<nb, 256, lds, s>>>(static_cast<const double2*>(in), static_cast<double2*>(out), f);
+    } else {
+        if (inverse) k_fft<float, true><<<nb, 256, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
+        else k_fft<float, false><<<nb, 256, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
+    }
+}
+
+void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, const double* T,
+                        double* mult, hipStream_t s) {
+    HList hl;
+    for (int q = 0; q < FKR_MAX_H * 3; ++q) hl.h[q] = 0.0;
+    for (int q = 0; q < nh; ++q)
+        for (int j = 0; j < g.d; ++j) hl.h[q * 3 + j] = h_host[q * g.d + j];
+    const int na = 2 * order + 1;
+    int64_t per_h = 0;
+    for (int j = 0; j < g.d; ++j) per_h += na * g.B[j];
+    const int64_t n = per_h * nh;
+    k_mult_tables<<<nblk(n), 256, 0, s>>>(g, na, nh, hl, T, mult, per_h);
+}
+
+
+void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
+                    void* out, hipStream_t s) {
+    const int64_t n = a.Btot * a.ncp;
+    if (prec == FKR_F64)
+        k_expand<double><<<nblk(n), 256, 0, s>>>(a, es, et, static_cast<const double2*>(spec), static_cast<double2*>(out));
+    else
+        k_expand<float><<<nblk(n), 256, 0, s>>>(a, es, et, static_cast<const float2*>(spec), static_cast<float2*>(out));
+}
+
+void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s) {
+    const unsigned nb = nblk(a.Mtot);
+#define FKR_SOLVE(P, T) k_solve<P, T><<<nb, 256, 0, s>>>(a, pidx, static_cast<const T*>(chan))
+#define FKR_SOLVE_P(T) do { switch (a.P) { case 1: FKR_SOLVE(1, T); break; case 2: FKR_SOLVE(2, T); break; \
+    case 3: FKR_SOLVE(3, T); break; case 4: FKR_SOLVE(4, T); break; case 6: FKR_SOLVE(6, T); break; \
+    default: FKR_SOLVE(10, T); break; } } while (0)
+    if (prec == FKR_F64) FKR_SOLVE_P(double); else FKR_SOLVE_P(float);
+#undef FKR_SOLVE_P
+#undef FKR_SOLVE
+}
+
+void launch_unpack_spec(int prec, int64_t Btot, const int64_t* B, int d, int npairs, int nw,
+                        const void* spec, double* out, hipStream_t s) {
+    const int64_t n = Btot * nw;
+    if (n == 0) return;
+    const int64_t b1 = d > 1 ? B[1] : 1, b2 = d > 2 ? B[2] : 1;
+    if (prec == FKR_F64)
+        k_unpack_spec<double><<<nblk(n), 256, 0, s>>>(Btot, d, B[0], b1, b2, npairs, nw, static_cast<const double2*>(spec), out);
+    else
+        k_unpack_spec<float><<<nblk(n), 256, 0, s>>>(Btot, d, B[0], b1, b2, npairs, nw, static_cast<const float2*>(spec), out);
+}
+
+void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, const void* chan,
+                     double* S, double* T, hipStream_t s) {
+    const int64_t n = Mtot * (n_s + n_t * nw);
+    if (prec == FKR_F64)
+        k_chan_out<double><<<nblk(n), 256, 0, s>>>(Mtot, ncp, n_s, n_t, nw, static_cast<const double*>(chan), S, T);
+    else
+        k_chan_out<float><<<nblk(n), 256, 0, s>>>(Mtot, ncp, n_s, n_t, nw, static_cast<const float*>(chan), S, T);
+}
+
+void launch_reduce_items(const Geo& g, const ReduceItemArgs& a, int ngroups, hipStream_t s) {
+    dim3 grid(kRedBlocks, (unsigned)ngroups);
+    switch (g.d) {
+        case 1: k_reduce_items<1><<<grid, 256, 0, s>>>(g, a); break;
+        case 2: k_reduce_items<2><<<grid, 256, 0, s>>>(g, a); break;
+        default: k_reduce_items<3><<<grid, 256, 0, s>>>(g, a); break;
+    }
+}
+
+void launch_reduce_final(const double* partial, int nslots, double* out, hipStream_t s) {
+    if (nslots > 0) k_reduce_final<<<(unsigned)nslots, 256, 0, s>>>(partial, out);
+}
+
+void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void* X, int x_type,
+                   double* out, hipStream_t s) {
+    if (Nq == 0) return;
+    switch (g.d) {
+        case 1: k_interp<1><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
+        case 2: k_interp<2><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
+        default: k_interp<3><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
+    }
+}
+
+void launch_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, int n_items,
+                        int ny_cols, double* rho_out, double* rss_out, double* gcv_out,
+                        hipStream_t s) {
+    (void)n_items;
+    k_finalize_cv<<<1, 64, 0, s>>>(hidx, Np, q, N, red, ny_cols, rho_out, rss_out, gcv_out);
+}
+
+void launch_resid(const Geo& g, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
+                  int y_type, const void* Y, int y_cplx, const double* mhat, double* wbuf,
+                  hipStream_t s) {
+    if (N == 0) return;
+    switch (g.d) {
+        case 1: k_resid<1><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, mhat, wbuf); break;
+        case 2: k_resid<2><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, mhat, wbuf); break;
+        default: k_resid<3><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, mhat, wbuf); break;
+    }
+}
+
+void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, const int32_t* perm,
+                          const double* vhat, const double* r, double* partial, hipStream_t s) {
+    switch (g.d) {
+        case 1: k_kappa_partial<1><<<kRedBlocks, 256, 0, s>>>(g, N, x_type, xs, perm, vhat, r, partial); break;
+        case 2: k_kappa_partial<2><<<kRedBlocks, 256, 0, s>>>(g, N, x_type, xs, perm, vhat, r, partial); break;
+        default: k_kappa_partial<3><<<kRedBlocks, 256, 0, s>>>(g, N, x_type, xs, perm, vhat, r, partial); break;
+    }
+}
+
+void launch_sigma2(int64_t Mtot, int64_t N, const double* vhat, const double* kappa_sum,
+                   double* sigma2, double* kappa_out, hipStream_t s) {
+    k_sigma2<<<nblk(Mtot), 256, 0, s>>>(Mtot, N, vhat, kappa_sum, sigma2, kappa_out);
+}
+
+}  // namespace fkr

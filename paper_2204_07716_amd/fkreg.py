@@ -1,0 +1,247 @@
+"""Python binding of the fast kernel-regression library (include/fkr.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the method runs in the HIP kernels of ``libfkr.so``.
+Grid outputs are flat with the index of dimension 0 fastest (shape ``(..., M_tot)``);
+``grid_shape`` gives the C-order shape ``(M_{d-1}, ..., M_0)`` to reshape them.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+__all__ = ["Plan", "get_hlist", "select_bandwidth"]
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return _lib.FKR_F64
+    if t.dtype == torch.float32:
+        return _lib.FKR_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _real_view(Y: torch.Tensor):
+    """(tensor of reals, q, y_complex)."""
+    if Y.dim() == 1:
+        Y = Y[:, None]
+    if Y.is_complex():
+        q = Y.shape[1]
+        return torch.view_as_real(Y.contiguous()).contiguous(), q, 1
+    return Y.contiguous(), Y.shape[1], 0
+
+
+def _hbuf(h, d: int) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(-1, d))
+    return a
+
+
+def _hptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def get_hlist(n: int, lo: float, hi: float, kind: str = "log") -> np.ndarray:
+    """Bandwidth candidates (Sec. 4 get_hList), both ends included."""
+    out = np.zeros(n)
+    check(_lib.load().fkr_hlist(n, lo, hi, 0 if kind == "log" else 1, _hptr(out)), "fkr_hlist")
+    return out
+
+
+def select_bandwidth(gcv: Sequence[float], dstd: float = 0.0) -> int:
+    """Relaxed GCV selection (Table 1, dstd)."""
+    g = np.ascontiguousarray(np.asarray(gcv, dtype=np.float64).ravel())
+    idx = ctypes.c_int(-1)
+    check(_lib.load().fkr_select_bandwidth(g.size, _hptr(g), float(dstd), ctypes.byref(idx)),
+          "fkr_select_bandwidth")
+    return idx.value
+
+
+class Plan:
+    """A plan bound to one device workspace (fkr_plan_create + fkr_set_workspace)."""
+
+    def __init__(self, d: int, order: int, M: Sequence[int], lo: Sequence[float],
+                 hi: Sequence[float], h_min: Sequence[float], h_max: Sequence[float],
+                 eps: float, precision: str = "fp32", kernel: str = "es", sigma: float = 0.0,
+                 n_max: int = 0, max_weights: int = 2, max_h: int = 1, device="cuda",
+                 transform_precision: str = "same"):
+        self.lib = _lib.load()
+        desc = _lib.PlanDesc()
+        desc.d, desc.order = d, order
+        for j in range(d):
+            desc.M[j] = int(M[j])
+            desc.lo[j], desc.hi[j] = float(lo[j]), float(hi[j])
+            desc.h_min[j], desc.h_max[j] = float(h_min[j]), float(h_max[j])
+        desc.eps = float(eps)
+        desc.precision = _lib.FKR_F64 if precision == "fp64" else _lib.FKR_F32
+        desc.spread_kernel = _lib.FKR_KERNEL_ES if kernel == "es" else _lib.FKR_KERNEL_GAUSS
+        desc.sigma = float(sigma)
+        desc.n_max = int(n_max)
+        desc.max_weights = int(max_weights)
+        desc.max_h = int(max_h)
+        desc.transform_precision = {"same": _lib.FKR_TP_SAME, "fp32": _lib.FKR_TP_F32,
+                                    "fp64": _lib.FKR_TP_F64}[transform_precision]
+        self.desc = desc
+        self.d, self.order = d, order
+        self.M = tuple(int(m) for m in M)
+        self.Mtot = int(np.prod(self.M))
+        self.grid_shape = tuple(reversed(self.M))
+        self._plan = ctypes.c_void_p()
+        check(self.lib.fkr_plan_create(ctypes.byref(desc), ctypes.byref(self._plan)), "fkr_plan_create")
+        g = _lib.Geometry()
+        check(self.lib.fkr_plan_geometry(self._plan, ctypes.byref(g)), "fkr_plan_geometry")
+        self.geometry = g
+        self.n_s, self.n_t = g.n_s, g.n_t
+        self.workspace = torch.empty(int(g.workspace_bytes) + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        check(self.lib.fkr_set_workspace(self._plan, ctypes.c_void_p(self._ws_ptr),
+                                         ctypes.c_size_t(int(g.workspace_bytes))), "fkr_set_workspace")
+        self.device = self.workspace.device
+        self.N = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None) and self._plan.value:
+                self.lib.fkr_plan_destroy(self._plan)
+                self._plan = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    @property
+    def band(self):
+        return tuple(2 * self.geometry.K[j] + 1 for j in range(self.d))
+
+    # -- a2 -------------------------------------------------------------
+    def set_points(self, X: torch.Tensor) -> None:
+        X = X.contiguous()
+        if X.dim() == 1:
+            X = X[:, None]
+        assert X.shape[1] == self.d
+        self._X = X  # keep alive for the async kernels
+        check(self.lib.fkr_set_points(self._plan, X.shape[0], _ptr(X), _dtype_code(X), _stream()),
+              "fkr_set_points")
+        self.N = X.shape[0]
+
+    # -- a3-a5 ----------------------------------------------------------
+    def spectrum(self, W: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nw = 1 if W is None else (W.shape[1] if W.dim() == 2 else 1)
+        if W is not None:
+            W = W.reshape(W.shape[0], nw).contiguous()
+        out = torch.empty((nw,) + tuple(reversed(self.band)) + (2,), dtype=torch.float64,
+                          device=self.device)
+        check(self.lib.fkr_spectrum(self._plan, nw, _ptr(W), _dtype_code(W) if W is not None else 1,
+                                    _ptr(out), _stream()), "fkr_spectrum")
+        return torch.view_as_complex(out)
+
+    # -- a3-a6 ----------------------------------------------------------
+    def moments(self, h, W: Optional[torch.Tensor] = None):
+        hb = _hbuf(h, self.d)
+        nh = hb.shape[0]
+        nw = 0 if W is None else (W.shape[1] if W.dim() == 2 else 1)
+        if W is not None:
+            W = W.reshape(W.shape[0], nw).contiguous()
+        S = torch.empty((nh, self.n_s, self.Mtot), dtype=torch.float64, device=self.device)
+        T = torch.empty((nh, max(nw, 1), self.n_t, self.Mtot), dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_moments(self._plan, nh, _hptr(hb), nw, _ptr(W),
+                                   _dtype_code(W) if W is not None else 1, _ptr(S),
+                                   _ptr(T) if nw else None, _stream()), "fkr_moments")
+        return S, (T if nw else None)
+
+    # -- a3-a7 ----------------------------------------------------------
+    def fit(self, h, Y: torch.Tensor, want_s0: bool = False):
+        hb = _hbuf(h, self.d)
+        nh = hb.shape[0]
+        Yr, q, cplx = _real_view(Y)
+        shape = (nh, q, self.Mtot) + ((2,) if cplx else ())
+        mhat = torch.empty(shape, dtype=torch.float64, device=self.device)
+        s0 = torch.empty((nh, self.Mtot), dtype=torch.float64, device=self.device) if want_s0 else None
+        check(self.lib.fkr_fit(self._plan, nh, _hptr(hb), q, cplx, _ptr(Yr), _dtype_code(Yr),
+                               _ptr(mhat), _ptr(s0), _stream()), "fkr_fit")
+        if cplx:
+            mhat = torch.view_as_complex(mhat)
+        return (mhat, s0) if want_s0 else mhat
+
+    # -- a8 -------------------------------------------------------------
+    def interp(self, G: torch.Tensor, Xq: torch.Tensor) -> torch.Tensor:
+        G = G.reshape(-1, self.Mtot).contiguous()
+        Xq = Xq.contiguous()
+        if Xq.dim() == 1:
+            Xq = Xq[:, None]
+        out = torch.empty((G.shape[0], Xq.shape[0]), dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_interp(self._plan, G.shape[0], _ptr(G), Xq.shape[0], _ptr(Xq),
+                                  _dtype_code(Xq), _ptr(out), _stream()), "fkr_interp")
+        return out
+
+    # -- a9 -------------------------------------------------------------
+    def dof(self, h, Np: int, seed: int = 0, probes: Optional[torch.Tensor] = None) -> torch.Tensor:
+        hb = _hbuf(h, self.d)
+        nh = hb.shape[0]
+        rho = torch.empty((nh, Np), dtype=torch.float64, device=self.device)
+        if probes is not None:
+            probes = probes.contiguous()
+        check(self.lib.fkr_dof(self._plan, nh, _hptr(hb), Np, ctypes.c_uint64(seed), _ptr(probes),
+                               _dtype_code(probes) if probes is not None else 1, _ptr(rho),
+                               _stream()), "fkr_dof")
+        return rho
+
+    # -- a7-a10 batched -------------------------------------------------
+    def cv(self, h, Y: torch.Tensor, Np: int, seed: int = 0,
+           probes: Optional[torch.Tensor] = None, want_mhat: bool = True):
+        hb = _hbuf(h, self.d)
+        nh = hb.shape[0]
+        Yr, q, cplx = _real_view(Y)
+        if probes is not None:
+            probes = probes.to(Yr.dtype).contiguous()
+        mhat = (torch.empty((nh, q, self.Mtot) + ((2,) if cplx else ()), dtype=torch.float64,
+                            device=self.device) if want_mhat else None)
+        rho = torch.empty((nh, Np), dtype=torch.float64, device=self.device) if Np else None
+        rss = torch.empty((nh, q), dtype=torch.float64, device=self.device)
+        gcv = torch.empty((nh, q), dtype=torch.float64, device=self.device) if Np else None
+        check(self.lib.fkr_cv(self._plan, nh, _hptr(hb), q, cplx, _ptr(Yr), _dtype_code(Yr), Np,
+                              ctypes.c_uint64(seed), _ptr(probes), _ptr(mhat), _ptr(rho), _ptr(rss),
+                              _ptr(gcv), _stream()), "fkr_cv")
+        if mhat is not None and cplx:
+            mhat = torch.view_as_complex(mhat)
+        return {"mhat": mhat, "rho": rho, "rss": rss, "gcv": gcv}
+
+    # -- a11 ------------------------------------------------------------
+    def variance(self, h, Y: torch.Tensor, mhat: torch.Tensor, mode: str = "log"):
+        hb = _hbuf(h, self.d)
+        Yr, q, cplx = _real_view(Y)
+        assert q == 1, "one response column"
+        m = torch.view_as_real(mhat).contiguous() if mhat.is_complex() else mhat.contiguous()
+        sigma2 = torch.empty(self.Mtot, dtype=torch.float64, device=self.device)
+        vhat = torch.empty(self.Mtot, dtype=torch.float64, device=self.device)
+        kappa = torch.empty(1, dtype=torch.float64, device=self.device)
+        md = _lib.FKR_VAR_LOG if mode == "log" else _lib.FKR_VAR_DIRECT
+        check(self.lib.fkr_variance(self._plan, _hptr(hb), cplx, _ptr(Yr), _dtype_code(Yr), _ptr(m),
+                                    md, _ptr(sigma2), _ptr(vhat), _ptr(kappa), _stream()),
+              "fkr_variance")
+        return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
+
+    def diagnostics(self, allow_warn: bool = True) -> dict:
+        dg = _lib.Diag()
+        st = self.lib.fkr_get_diagnostics(self._plan, ctypes.byref(dg))
+        return {"status": st, "n_points": dg.n_points, "out_of_domain": dg.out_of_domain,
+                "ill_posed": dg.ill_posed, "n_jobs": dg.n_jobs, "max_tile_count": dg.max_tile_count}

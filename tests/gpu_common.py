@@ -1,0 +1,47 @@
+"""Helpers shared by the GPU parity tests (not collected by pytest)."""
+import numpy as np
+import torch
+
+from oracle import oracle as orc
+
+
+def rel_err(gpu, ref, mask=None) -> float:
+    """max |gpu - ref| / max |ref| over the mask (the error metric of the
+    design notes: FFT errors are relative to a channel's global magnitude)."""
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    if mask is not None:
+        gpu = gpu[mask]
+        ref = ref[mask]
+    scale = np.abs(ref).max()
+    if scale == 0:
+        return float(np.abs(gpu).max())
+    return float(np.abs(gpu - ref).max() / scale)
+
+
+def density_mask(s0: np.ndarray, rho: float = 1e-3) -> np.ndarray:
+    return s0 >= rho * s0.max()
+
+
+def make_plan(d, order, M, h_min, h_max, eps, precision, n_max, max_weights=2, max_h=1,
+              kernel="es", lo=None, hi=None, sigma=0.0, tprec="same"):
+    from paper_2204_07716_amd import Plan
+    lo = lo or (0.0,) * d
+    hi = hi or (1.0,) * d
+    return Plan(d, order, M, lo, hi, h_min, h_max, eps, precision=precision, kernel=kernel,
+                sigma=sigma, n_max=n_max, max_weights=max_weights, max_h=max_h,
+                transform_precision=tprec)
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def equilibrate_oracle(S, T, h, order, d):
+    """Oracle moments divided by h^a (the library returns equilibrated channels)."""
+    es = orc.multi_indices(d, 2 * order)
+    et = orc.multi_indices(d, order)
+    h = np.asarray(h, dtype=np.float64)
+    Se = S / np.array([np.prod(h ** np.array(a)) for a in es])[None, :]
+    Te = T / np.array([np.prod(h ** np.array(b)) for b in et])[None, None, :]
+    return Se, Te
