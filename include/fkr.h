@@ -86,7 +86,8 @@ typedef struct {
     int spread_kernel;      /* FKR_KERNEL_ES (default) or FKR_KERNEL_GAUSS (the
                                paper's fast Gaussian gridding, Sec. 1.2) */
     double sigma;           /* fine-grid oversampling over the spectral band;
-                               0 selects 2 (eq. 17: M_r = 2 L) */
+                               0 selects 4 for d <= 2 and 2 for d = 3 (eq. 17
+                               uses M_r = 2 L) */
     int64_t n_max;          /* largest N passed to fkr_set_points */
     int max_weights;        /* largest number of real weight vectors one call
                                spreads, counting the density: 1 + q (real y) or
@@ -169,8 +170,13 @@ fkr_status fkr_moments(fkr_plan* plan, int nh, const double* h, int nw, const vo
  * bandwidth-equilibrated matrix); mhat = intercept.  Y: N x q (real or
  * complex).  mhat_dev: [nh][q][M^d] doubles (complex: [nh][q][M^d][2]).
  * s0_dev (optional, [nh][M^d] doubles): s_0, the unnormalised KDE of eq. (8).
- * Grid points whose system is ill-posed (s_0 below the method's noise floor or
- * a Cholesky pivot below 1e-12 of its diagonal) get NaN and are counted. */
+ * Grid points whose system is ill-posed get NaN and are counted: some
+ * Cholesky pivot c of the equilibrated matrix (s_0 is the first) is at most
+ * max(1e-12 A_cc, e N K_h(0)), where K_h(0) = prod_j 1/(h_j sqrt(2 pi)) and
+ * e = max(eps, unit round-off of the transform precision, 30 unit round-offs
+ * of the spreading precision): the moments are only known to about
+ * e N K_h(0).  NaN grid values propagate into the DF, RSS and GCV of any
+ * sample whose interpolation cell touches them. */
 fkr_status fkr_fit(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
                    const void* Y_dev, int y_type, double* mhat_dev, double* s0_dev,
                    void* stream);

@@ -31,8 +31,12 @@ the design notes):  the bandwidth ``h_j`` is the per-dimension kernel standard
 deviation (H = diag(h^2)); the kernel is the normalised Gaussian; the
 displacement is z = x_i - g; the design row holds every monomial of total
 degree <= l in graded order; the Girard estimate is the mean over probes of
-per-probe ratios; a grid point is ill-posed (NaN) when s_0 < 1e-300 or the
-equilibrated moment matrix has condition number above 1e12.
+per-probe ratios; a grid point is ill-posed (NaN) when some pivot of the
+equilibrated moment matrix (s_0 is the first) is at most max(1e-12 times its
+diagonal entry, ``floor``), the floor being a caller-chosen absolute noise
+level (0 by default, i.e. only exact or near-exact singularity); NaN fit values
+propagate into the DF and GCV of samples whose interpolation cell touches
+them, and ``rgcv_select`` skips NaN GCV values.
 
 Parity pins for every function here live in ``tests/test_oracle_*.py``.
 """
@@ -51,8 +55,7 @@ _SRC = os.path.join(_HERE, "fkr_oracle.c")
 _LIB = os.path.join(_HERE, "libfkr_oracle.so")
 _lib = None
 
-ILL_S0 = 1e-300
-ILL_COND = 1e12
+ILL_REL = 1e-12
 
 
 def build(force: bool = True) -> str:
@@ -173,23 +176,41 @@ def assemble(S: np.ndarray, h: Sequence[float], order: int, d: int) -> np.ndarra
     return A
 
 
-def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int):
+def pivots(A: np.ndarray) -> np.ndarray:
+    """Pivots of the triangular (Cholesky / LDL^T) factorisation of each
+    symmetric matrix in A (G x P x P), from their definition as ratios of
+    leading principal minors: pivot_c = det A[:c+1, :c+1] / det A[:c, :c].
+    Each matrix is scaled by its (0, 0) entry first to keep the
+    determinants in range; rows with A_00 <= 0 give NaN."""
+    G, P, _ = A.shape
+    a00 = A[:, 0, 0]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        B = A / a00[:, None, None]
+        minors = np.ones((G, P + 1))
+        for c in range(1, P + 1):
+            minors[:, c] = np.linalg.det(B[:, :c, :c])
+        pv = minors[:, 1:] / minors[:, :-1] * a00[:, None]
+    pv[~(a00 > 0)] = np.nan
+    return pv
+
+
+def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int,
+          floor: float = 0.0):
     """Per grid point: solve A c = t (eq. 3 / 11) and return
     mhat (G x nw) = c_0, r0 (G x P) = row 0 of the inverse of the
-    equilibrated matrix, and the ill-posed mask (G,)."""
+    equilibrated matrix, and the ill-posed mask (G,): some pivot of the
+    equilibrated matrix is at most max(1e-12 A_cc, floor)."""
     et = multi_indices(d, order)
     h = np.asarray(h, dtype=np.float64)
     scale = np.array([np.prod(h ** np.array(b)) for b in et])
     A = assemble(S, h, order, d)
     rhs = T / scale[None, None, :]
     G, nw, P = rhs.shape
-    ill = ~(S[:, 0] >= ILL_S0)
+    pv = pivots(A)
+    thr = np.maximum(ILL_REL * np.diagonal(A, axis1=1, axis2=2), floor)
+    with np.errstate(invalid="ignore"):
+        ill = ~np.all(pv > thr, axis=1)
     ok = ~ill
-    if P > 1 and ok.any():
-        cond = np.full(G, np.inf)
-        cond[ok] = np.linalg.cond(A[ok])
-        ill |= ~(cond <= ILL_COND)
-        ok = ~ill
     mhat = np.full((G, nw), np.nan)
     r0 = np.full((G, P), np.nan)
     if ok.any():
@@ -210,17 +231,18 @@ def _split_complex(Y: np.ndarray):
     return Y.astype(np.float64), False
 
 
-def fit(X, Y, h, order, gpts, return_all: bool = False):
+def fit(X, Y, h, order, gpts, return_all: bool = False, floor: float = 0.0):
     """m_hat(g; l) of eq. (11) at the given grid points, for each response
     column (complex responses: real and imaginary parts share the real moment
-    matrix).  Returns mhat (G x q) [, S, T, r0, ill]."""
+    matrix); ``floor`` is the absolute pivot floor of ``solve``.
+    Returns mhat (G x q) [, S, T, r0, ill]."""
     X = np.asarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X[:, None]
     d = X.shape[1]
     W, cplx = _split_complex(Y)
     S, T = moments(X, W, h, order, gpts)
-    mhat, r0, ill = solve(S, T, h, order, d)
+    mhat, r0, ill = solve(S, T, h, order, d, floor)
     if cplx:
         q = W.shape[1] // 2
         mhat = mhat[:, :q] + 1j * mhat[:, q:]
@@ -335,13 +357,13 @@ def girard_ratios(Wp: np.ndarray, What: np.ndarray) -> np.ndarray:
     return np.einsum("ip,ip->p", Wp, Wp - What) / np.einsum("ip,ip->p", Wp, Wp)
 
 
-def dof(X, h, order, M, lo, hi, Wp):
+def dof(X, h, order, M, lo, hi, Wp, floor: float = 0.0):
     """Fast Monte-Carlo DF (Sec. 2.1): each probe is pushed through the grid
     smoother (moments -> solve -> interpolation back to the samples).
     Returns (rho per probe, mean rho ~ (1/N) tr(I - S), DF = N (1 - mean))."""
     X = np.asarray(X, dtype=np.float64).reshape(len(Wp), -1)
     gp = grid_points(M, lo, hi)
-    mh = fit(X, Wp, h, order, gp)
+    mh = fit(X, Wp, h, order, gp, floor=floor)
     What = interp(mh, M, lo, hi, X)
     rho = girard_ratios(Wp, What)
     m = float(np.mean(rho))
@@ -359,10 +381,14 @@ def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float) -> np.ndarray:
 def rgcv_select(gcv_values: Sequence[float], dstd: float = 0.0) -> int:
     """Index of the selected bandwidth: the last (largest, for an ascending
     list) h whose GCV is within dstd * std(GCV) of the minimum; dstd = 0 is
-    the plain argmin with ties going to the larger h.  std uses N - 1."""
+    the plain argmin with ties going to the larger h.  std uses N - 1 and,
+    like the minimum, only the finite entries."""
     g = np.asarray(gcv_values, dtype=np.float64)
-    thr = np.min(g) + (dstd * np.std(g, ddof=1) if dstd > 0 and g.size > 1 else 0.0)
-    return int(np.nonzero(g <= thr)[0][-1])
+    f = g[np.isfinite(g)]
+    if f.size == 0:
+        raise ValueError("no finite GCV value")
+    thr = np.min(f) + (dstd * np.std(f, ddof=1) if dstd > 0 and f.size > 1 else 0.0)
+    return int(np.nonzero(np.isfinite(g) & (g <= thr))[0][-1])
 
 
 def get_hlist(n, rng, kind: str = "log") -> np.ndarray:
@@ -392,7 +418,7 @@ def get_hlist(n, rng, kind: str = "log") -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
-             gpts: Optional[np.ndarray] = None):
+             gpts: Optional[np.ndarray] = None, floor: float = 0.0):
     """Second pass on squared residuals r_i = |y_i - yhat(x_i)|^2.
 
     mode "log" (eq. 24-26): v = local fit of log(r_i + 1/N); kappa =
@@ -405,13 +431,13 @@ def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
     r = np.abs(np.asarray(y).reshape(N) - np.asarray(yhat_at_samples).reshape(N)) ** 2
     full = grid_points(M, lo, hi)
     if mode == "direct":
-        s2 = fit(X, r, h, order, full if gpts is None else gpts)[:, 0]
+        s2 = fit(X, r, h, order, full if gpts is None else gpts, floor=floor)[:, 0]
         return s2, {"r": r}
     z = np.log(r + 1.0 / N)
-    v_full = fit(X, z, h, order, full)[:, 0]
+    v_full = fit(X, z, h, order, full, floor=floor)[:, 0]
     v_i = interp(v_full, M, lo, hi, X)
     kappa = 1.0 / np.mean(r * np.exp(-v_i))
-    v = v_full if gpts is None else fit(X, z, h, order, gpts)[:, 0]
+    v = v_full if gpts is None else fit(X, z, h, order, gpts, floor=floor)[:, 0]
     return np.exp(v) / kappa, {"r": r, "z": z, "v": v_full, "kappa": kappa}
 
 

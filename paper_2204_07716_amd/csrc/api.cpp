@@ -75,8 +75,30 @@ const int* dev_et(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 512); }
 const int* dev_pidx(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 1024); }
 const double* dev_periods(fkr_plan* p) { return at<double>(p, p->lay.consts); }
 
+// Weight vectors staged in sorted order (one pass per call): returns sources
+// that read the staged copy, [N][nr] in the spreading precision.
+std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipStream_t s) {
+    const int nr = (int)srcs.size();
+    void* buf = p->ws + p->lay.wsort;
+    for (int r0 = 0; r0 < nr; r0 += 2 * kMaxPairsPerSpread) {
+        SpreadSrc chunk{};
+        const int n = std::min(2 * kMaxPairsPerSpread, nr - r0);
+        for (int q = 0; q < n; ++q) chunk.w[q] = srcs[r0 + q];
+        launch_stage_weights(p->prec, chunk, n, r0, nr, p->N, at<int32_t>(p, p->lay.perm), buf, s);
+    }
+    std::vector<WSrc> out(nr);
+    for (int r = 0; r < nr; ++r) {
+        if (srcs[r].kind == W_ONE || srcs[r].kind == W_ZERO) { out[r] = srcs[r]; continue; }
+        WSrc w{};
+        w.kind = W_SORTED; w.type = p->prec; w.ptr = buf; w.stride = nr; w.col = r;
+        out[r] = w;
+    }
+    return out;
+}
+
 // Spread + fold + forward FFT of every weight pair -> spec [band][npairs].
-fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs, hipStream_t s) {
+fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_t s) {
+    const std::vector<WSrc> srcs = stage_weights(p, srcs_in, s);
     const Geo g = make_geo(p);
     const int nr = (int)srcs.size();
     const int npairs = (nr + 1) / 2;
@@ -184,13 +206,19 @@ fkr_status run_channels(fkr_plan* p, int hidx, int nr, hipStream_t s) {
 }
 
 double s0_floor(const fkr_plan* p, const double* h) {
-    // Below this the round-off of the spreading and the transforms is a
-    // sizeable part of s_0: 30 unit round-offs (of the spreading precision) of
-    // N * K_h(0), the largest value s_0 can take.
+    // Noise floor of the moment matrix.  Every channel is known only to a
+    // relative accuracy e of N K_h(0), the largest value s_0 can take: e is
+    // the NUFFT tolerance, or the round-off of the transforms, or 30 unit
+    // round-offs of the spreading arithmetic, whichever is coarsest.  A
+    // Cholesky pivot (s_0 is the first) at or below e N K_h(0) cannot be told
+    // apart from a singular system.
     double k0 = 1.0;
     for (int j = 0; j < p->d; ++j) k0 *= 1.0 / (h[j] * std::sqrt(2.0 * M_PI));
-    const double u = p->prec == FKR_F64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
-    return std::max(1e-300, 30.0 * u * (double)std::max<int64_t>(p->N, 1) * k0);
+    const double u32 = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
+    const double us = p->prec == FKR_F64 ? u64 : u32;
+    const double ut = p->tprec == FKR_F64 ? u64 : u32;
+    const double e = std::max(std::max(p->eps, ut), 30.0 * us);
+    return std::max(1e-300, e * (double)std::max<int64_t>(p->N, 1) * k0);
 }
 
 SolveArgs solve_args(fkr_plan* p, int nr, int ny, int y_cplx, const double* h) {
@@ -456,16 +484,12 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
         ReduceItemArgs r{};
         r.d = p->d; r.n_items = n_items; r.ny_cols = q; r.y_cplx = y_complex;
-        r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs; r.perm = at<int32_t>(p, p->lay.perm);
-        r.Y = Y; r.y_type = y_type; r.y_stride = (int64_t)q * cpl;
+        r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
+        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.nr = nr;
         r.yfit = yfit; r.pfit = pfit;
         r.partial = partial;
         for (int gi = 0; gi < ngroups; ++gi) {
             r.item0 = gi * kItemsPerGroup;
-            for (int it = 0; it < kItemsPerGroup; ++it) {
-                const int item = r.item0 + it;
-                r.probe[it] = (item >= q && item < n_items) ? srcs[1 + ny + (item - q)] : src_zero();
-            }
             launch_reduce_items(g, r, 1, s);
         }
         launch_reduce_final(partial, 2 * n_items, red, s);

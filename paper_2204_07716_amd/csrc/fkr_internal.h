@@ -13,7 +13,7 @@ constexpr int kMaxD = FKR_MAX_D;
 constexpr int kMaxFactors = 20;      // radix stages of one FFT length
 constexpr int kMaxChannels = 36;     // s-channels C(d+2l, 2l) <= 35 for d <= 3, l <= 2
 constexpr int kMaxP = 10;            // P = C(d+l, l) <= 10
-constexpr int kCoverSlots = 4;       // spreading tiles covering one fine cell (per dimension)
+constexpr int kCoverSlots = 5;       // spreading tiles covering one fine cell (per dimension)
 constexpr int kMaxW = 24;            // widest spreading kernel (fine cells)
 
 // Spreading kernel widths compiled into the library; the planner rounds the
@@ -21,10 +21,11 @@ constexpr int kMaxW = 24;            // widest spreading kernel (fine cells)
 constexpr int kWidths[] = {6, 8, 12, 16, 24};
 
 // Interior edge of a spreading tile (fine cells) for dimension D and kernel
-// width W; 0 when unsupported.  The padded tile (TS + W - 1)^D of one complex
-// pair accumulates in FP64 in LDS and must fit beside the job's sort arrays.
+// width W; 0 when unsupported.  One workgroup spreads all samples of one tile
+// into the padded tile (TS + W - 1)^D, accumulated in FP64 in LDS, so tiles
+// are small (many workgroups, no partial tiles to add up).
 constexpr int spread_tile_edge(int D, int W) {
-    return D == 1 ? 256 : (D == 2 ? (W <= 16 ? 32 : 16) : (W <= 8 ? 8 : (W <= 12 ? 4 : 0)));
+    return D <= 2 ? 8 : (W <= 8 ? 8 : (W <= 16 ? 4 : 0));
 }
 
 constexpr int kMaxPairsInLaunch = 8;   // weight pairs per spreading launch
@@ -48,7 +49,7 @@ struct Layout {                      // byte offsets into the workspace
     size_t counts = 0, tile_off = 0, cursor = 0, job_off = 0, jobs = 0;
     size_t loc = 0, frac = 0, perm = 0, xs = 0;
     size_t subgrid = 0, fine = 0, fftA = 0, fftB = 0, spec = 0, mult = 0;
-    size_t chan = 0, mhat = 0, partial = 0, wbuf = 0, red = 0;
+    size_t chan = 0, mhat = 0, partial = 0, wbuf = 0, red = 0, wsort = 0;
     size_t total = 0;
     // element capacities (for checks)
     int64_t cap_jobs = 0, cap_fft = 0, cap_spec = 0, cap_chan = 0, cap_mhat = 0;

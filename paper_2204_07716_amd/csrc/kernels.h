@@ -25,7 +25,8 @@ struct Geo {                          // geometry passed by value to kernels
 };
 
 // One real weight vector for spreading / reductions.
-enum : int { W_ZERO = 0, W_ONE = 1, W_ARRAY = 2, W_PHILOX = 3 };
+// W_ARRAY is indexed by the original sample index, W_SORTED by the sorted position.
+enum : int { W_ZERO = 0, W_ONE = 1, W_ARRAY = 2, W_PHILOX = 3, W_SORTED = 4 };
 struct WSrc {
     int kind;
     int type;          // FKR_F32 / FKR_F64 for arrays
@@ -69,7 +70,7 @@ struct SolveArgs {
     int P, n_s, n_t, ncp, nr;      // nr real weights incl. density
     int ny, y_cplx;                // real weights 1..ny are responses
     int64_t Mtot;
-    double s0_floor;
+    double s0_floor;               // absolute floor for every Cholesky pivot (s_0 first)
     double* y_out;                 // [q][M][(2)] per bandwidth (may be null)
     double* probe_out;             // [nr-1-ny][M] (may be null)
     double* s0_out;                // [M] (may be null)
@@ -82,12 +83,9 @@ struct ReduceItemArgs {
     int64_t N;
     int x_type;                   // element type of the sorted coordinates
     const void* X;                // sorted coordinates [N][d]
-    const int32_t* perm;          // sorted position -> original sample index
-    // y columns
-    const void* Y; int y_type; int64_t y_stride;
+    const void* wsorted;          // staged weights [N][nr] in sorted order
+    int w_type, nr;               // their element type and count (column 0 = density)
     const double* yfit;           // [q][M] or [q][M][2]
-    // probes
-    WSrc probe[kItemsPerGroup];
     const double* pfit;           // [Np][M]
     int item0;                    // first item of this launch
     double* partial;              // [slot][kRedBlocks]
@@ -133,5 +131,7 @@ void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, c
 void launch_sigma2(int64_t Mtot, int64_t N, const double* vhat, const double* kappa_sum,
                    double* sigma2, double* kappa_out, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t N,
+                          const int32_t* perm, void* out, hipStream_t s);
 
 }  // namespace fkr

@@ -387,27 +387,15 @@ __device__ __forceinline__ T kernel_value(T t, int w, T kp) {
     }
 }
 
-// Both real weights of a pair; two probes 4g+2m, 4g+2m+1 share one Philox
-// block and one Box-Muller transform.
-__device__ __forceinline__ void wval_pair(const WSrc& a, const WSrc& b, int64_t i, double* wa,
-                                          double* wb) {
-    if (a.kind == W_PHILOX && b.kind == W_PHILOX && a.seed == b.seed && (a.probe & 1) == 0 &&
-        b.probe == a.probe + 1) {
-        uint64_t c[4] = {(uint64_t)i, (uint64_t)(a.probe >> 2), 0, 0};
-        philox4x64_10(c, a.seed, 0);
-        const bool hi = (a.probe & 2) != 0;
-        const uint64_t xa = hi ? c[2] : c[0], xb = hi ? c[3] : c[1];
-        const double ua = ((double)(xa >> 11) + 1.0) * 0x1p-53;
-        const double ub = ((double)(xb >> 11) + 1.0) * 0x1p-53;
-        const double rad = sqrt(-2.0 * log(ua));
-        double sn, cs;
-        sincospi(2.0 * ub, &sn, &cs);
-        *wa = rad * cs;
-        *wb = rad * sn;
-        return;
+// A weight read from memory or a constant (the spreading reads weights that
+// k_stage_weights has put in sorted order; generated probes never reach it).
+__device__ __forceinline__ double wval_mem(const WSrc& s, int64_t sp, int64_t i) {
+    switch (s.kind) {
+        case W_ONE: return 1.0;
+        case W_ARRAY: return load_as_double(s.ptr, s.type, i * s.stride + s.col);
+        case W_SORTED: return load_as_double(s.ptr, s.type, sp * s.stride + s.col);
+        default: return 0.0;
     }
-    *wa = wval(a, i);
-    *wb = wval(b, i);
 }
 
 // Kernel values psi(k - f), k = 0..W-1, of one dimension.
@@ -437,6 +425,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Geo g, SpreadSrc src, c
     constexpr int PSUB = D == 1 ? PE : (D == 2 ? PE * PE : PE * PE * PE);
     constexpr bool ACC = D == 1 || (D == 2 && W * W * (int)sizeof(T) <= 256);
     constexpr int NWAVE = kSpreadBlock / 64;
+    constexpr int SB = 2;   // samples loaded per batch
     __shared__ double tile[2 * PSUB];
     const int njobs = jobs[0];
     const int np = src.npairs;
@@ -457,99 +446,154 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Geo g, SpreadSrc src, c
 #pragma unroll
                 for (int k = 0; k < (D == 1 ? W : W * W); ++k) ar[k] = ai[k] = (T)0;
                 int cur_base = -1;
-                for (int q = q0; q <= q1; ++q) {
-                    int base = -1;
-                    if (q < q1) {
-                        const uint32_t l = loc[s_beg + q];
-                        base = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0);
+                // Batches of SB samples: all loads of a batch are issued before
+                // any of its samples is used (memory-level parallelism).
+                for (int qb = q0; qb < q1; qb += SB) {
+                    int bb[SB];
+                    int64_t ip[SB];
+                    T f0[SB], f1[SB], wr[SB], wi[SB];
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        const int q = qb + u;
+                        bb[u] = -1;
+                        if (q < q1) {
+                            const int64_t s = s_beg + q;
+                            const uint32_t l = loc[s];
+                            bb[u] = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0);
+                            f0[u] = frac[s * D];
+                            f1[u] = D > 1 ? frac[s * D + 1] : (T)0;
+                            ip[u] = perm[s];
+                            wr[u] = (T)wval_mem(src.w[2 * p], s, ip[u]);
+                            wi[u] = (T)wval_mem(src.w[2 * p + 1], s, ip[u]);
+                        }
                     }
-                    if (base != cur_base && cur_base >= 0) {   // flush the running cell
-                        double* re = tile + cur_base;
-                        double* im = re + PSUB;
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        if (bb[u] < 0) break;
+                        if (bb[u] != cur_base && cur_base >= 0) {   // flush the running cell
+                            double* re = tile + cur_base;
+                            double* im = re + PSUB;
+                            if (D == 1) {
+#pragma unroll
+                                for (int k0 = 0; k0 < W; ++k0) {
+                                    atomicAdd(re + k0, (double)ar[k0]);
+                                    atomicAdd(im + k0, (double)ai[k0]);
+                                    ar[k0] = ai[k0] = (T)0;
+                                }
+                            } else {
+#pragma unroll
+                                for (int k1 = 0; k1 < W; ++k1)
+#pragma unroll
+                                    for (int k0 = 0; k0 < W; ++k0) {
+                                        atomicAdd(re + k1 * PE + k0, (double)ar[k1 * W + k0]);
+                                        atomicAdd(im + k1 * PE + k0, (double)ai[k1 * W + k0]);
+                                        ar[k1 * W + k0] = ai[k1 * W + k0] = (T)0;
+                                    }
+                            }
+                        }
+                        cur_base = bb[u];
+                        T kv0[W];
+                        kernel_row<W, T, KER>(f0[u], kp, kv0);
                         if (D == 1) {
 #pragma unroll
                             for (int k0 = 0; k0 < W; ++k0) {
-                                atomicAdd(re + k0, (double)ar[k0]);
-                                atomicAdd(im + k0, (double)ai[k0]);
-                                ar[k0] = ai[k0] = (T)0;
+                                ar[k0] += kv0[k0] * wr[u];
+                                ai[k0] += kv0[k0] * wi[u];
                             }
                         } else {
+                            T kv1[W];
+                            kernel_row<W, T, KER>(f1[u], kp, kv1);
 #pragma unroll
-                            for (int k1 = 0; k1 < W; ++k1)
+                            for (int k1 = 0; k1 < W; ++k1) {
+                                const T a = kv1[k1] * wr[u], b = kv1[k1] * wi[u];
 #pragma unroll
                                 for (int k0 = 0; k0 < W; ++k0) {
-                                    atomicAdd(re + k1 * PE + k0, (double)ar[k1 * W + k0]);
-                                    atomicAdd(im + k1 * PE + k0, (double)ai[k1 * W + k0]);
-                                    ar[k1 * W + k0] = ai[k1 * W + k0] = (T)0;
+                                    ar[k1 * W + k0] += kv0[k0] * a;
+                                    ai[k1 * W + k0] += kv0[k0] * b;
                                 }
-                        }
-                    }
-                    if (q == q1) break;
-                    cur_base = base;
-                    const int64_t s = s_beg + q;
-                    double dwa, dwb;
-                    wval_pair(src.w[2 * p], src.w[2 * p + 1], perm[s], &dwa, &dwb);
-                    const T wa = (T)dwa, wb = (T)dwb;
-                    T kv0[W];
-                    kernel_row<W, T, KER>(frac[s * D], kp, kv0);
-                    if (D == 1) {
-#pragma unroll
-                        for (int k0 = 0; k0 < W; ++k0) {
-                            ar[k0] += kv0[k0] * wa;
-                            ai[k0] += kv0[k0] * wb;
-                        }
-                    } else {
-                        T kv1[W];
-                        kernel_row<W, T, KER>(frac[s * D + 1], kp, kv1);
-#pragma unroll
-                        for (int k1 = 0; k1 < W; ++k1) {
-                            const T a = kv1[k1] * wa, b = kv1[k1] * wb;
-#pragma unroll
-                            for (int k0 = 0; k0 < W; ++k0) {
-                                ar[k1 * W + k0] += kv0[k0] * a;
-                                ai[k1 * W + k0] += kv0[k0] * b;
                             }
                         }
                     }
                 }
-            } else {
-                for (int q = q0; q < q1; ++q) {
-                    const int64_t s = s_beg + q;
-                    const uint32_t l = loc[s];
-                    const int base = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0) +
-                                     (D > 2 ? PE * PE * (int)((l >> 20) & 1023) : 0);
-                    double dwa, dwb;
-                    wval_pair(src.w[2 * p], src.w[2 * p + 1], perm[s], &dwa, &dwb);
-                    const T wa = (T)dwa, wb = (T)dwb;
-                    T kv0[W], kv1[W];
-                    kernel_row<W, T, KER>(frac[s * D], kp, kv0);
-                    if (D > 1) kernel_row<W, T, KER>(frac[s * D + 1], kp, kv1);
-                    double* re = tile + base;
+                if (cur_base >= 0) {   // flush the last cell
+                    double* re = tile + cur_base;
                     double* im = re + PSUB;
-                    if (D == 2) {
+                    if (D == 1) {
 #pragma unroll
-                        for (int k1 = 0; k1 < W; ++k1) {
-                            const double a = (double)(kv1[k1] * wa), b = (double)(kv1[k1] * wb);
+                        for (int k0 = 0; k0 < W; ++k0) {
+                            atomicAdd(re + k0, (double)ar[k0]);
+                            atomicAdd(im + k0, (double)ai[k0]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k1 = 0; k1 < W; ++k1)
 #pragma unroll
                             for (int k0 = 0; k0 < W; ++k0) {
-                                atomicAdd(re + k1 * PE + k0, (double)kv0[k0] * a);
-                                atomicAdd(im + k1 * PE + k0, (double)kv0[k0] * b);
+                                atomicAdd(re + k1 * PE + k0, (double)ar[k1 * W + k0]);
+                                atomicAdd(im + k1 * PE + k0, (double)ai[k1 * W + k0]);
                             }
+                    }
+                }
+            } else {
+                for (int qb = q0; qb < q1; qb += SB) {
+                    int bb[SB];
+                    int64_t ip[SB];
+                    T f0[SB], f1[SB], f2[SB], wr[SB], wi[SB];
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        const int q = qb + u;
+                        bb[u] = -1;
+                        if (q < q1) {
+                            const int64_t s = s_beg + q;
+                            const uint32_t l = loc[s];
+                            bb[u] = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0) +
+                                    (D > 2 ? PE * PE * (int)((l >> 20) & 1023) : 0);
+                            f0[u] = frac[s * D];
+                            f1[u] = D > 1 ? frac[s * D + 1] : (T)0;
+                            f2[u] = D > 2 ? frac[s * D + 2] : (T)0;
+                            ip[u] = perm[s];
+                            wr[u] = (T)wval_mem(src.w[2 * p], s, ip[u]);
+                            wi[u] = (T)wval_mem(src.w[2 * p + 1], s, ip[u]);
                         }
-                    } else if (D == 3) {
-                        const T f2 = frac[s * D + 2];
-                        for (int k2 = 0; k2 < W; ++k2) {
-                            const T v2 = kernel_value<T, KER>((T)k2 - f2, W, kp);
-                            const double a2 = (double)(v2 * wa), b2 = (double)(v2 * wb);
-                            double* re2 = re + k2 * PE * PE;
-                            double* im2 = im + k2 * PE * PE;
+                    }
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        if (bb[u] < 0) break;
+                        T kv0[W], kv1[W];
+                        kernel_row<W, T, KER>(f0[u], kp, kv0);
+                        if (D > 1) kernel_row<W, T, KER>(f1[u], kp, kv1);
+                        double* re = tile + bb[u];
+                        double* im = re + PSUB;
+                        if (D == 1) {
+#pragma unroll
+                            for (int k0 = 0; k0 < W; ++k0) {
+                                atomicAdd(re + k0, (double)(kv0[k0] * wr[u]));
+                                atomicAdd(im + k0, (double)(kv0[k0] * wi[u]));
+                            }
+                        } else if (D == 2) {
 #pragma unroll
                             for (int k1 = 0; k1 < W; ++k1) {
-                                const double a = (double)kv1[k1] * a2, b = (double)kv1[k1] * b2;
+                                const double a = (double)(kv1[k1] * wr[u]), b = (double)(kv1[k1] * wi[u]);
 #pragma unroll
                                 for (int k0 = 0; k0 < W; ++k0) {
-                                    atomicAdd(re2 + k1 * PE + k0, (double)kv0[k0] * a);
-                                    atomicAdd(im2 + k1 * PE + k0, (double)kv0[k0] * b);
+                                    atomicAdd(re + k1 * PE + k0, (double)kv0[k0] * a);
+                                    atomicAdd(im + k1 * PE + k0, (double)kv0[k0] * b);
+                                }
+                            }
+                        } else {
+                            for (int k2 = 0; k2 < W; ++k2) {
+                                const T v2 = kernel_value<T, KER>((T)k2 - f2[u], W, kp);
+                                const double a2 = (double)(v2 * wr[u]), b2 = (double)(v2 * wi[u]);
+                                double* re2 = re + k2 * PE * PE;
+                                double* im2 = im + k2 * PE * PE;
+#pragma unroll
+                                for (int k1 = 0; k1 < W; ++k1) {
+                                    const double a = (double)kv1[k1] * a2, b = (double)kv1[k1] * b2;
+#pragma unroll
+                                    for (int k0 = 0; k0 < W; ++k0) {
+                                        atomicAdd(re2 + k1 * PE + k0, (double)kv0[k0] * a);
+                                        atomicAdd(im2 + k1 * PE + k0, (double)kv0[k0] * b);
+                                    }
                                 }
                             }
                         }
@@ -870,7 +914,8 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
 #pragma unroll
         for (int c = 0; c <= b; ++c) A[b][c] = (double)ch[pidx[b * kMaxP + c]];
     const double s0 = (double)ch[0];
-    bool ill = !(s0 > a.s0_floor) || !isfinite(s0);
+    // s_0 is the first pivot; every pivot must clear the plan's noise floor.
+    bool ill = !isfinite(s0);
     // Cholesky A = L L^T (lower triangle in place).
     double diag0[P];
 #pragma unroll
@@ -880,7 +925,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
         double v = A[c][c];
 #pragma unroll
         for (int q = 0; q < c; ++q) v -= A[c][q] * A[c][q];
-        if (!(v > 1e-12 * diag0[c])) ill = true;
+        if (!(v > fmax(1e-12 * diag0[c], a.s0_floor))) ill = true;
         const double l = sqrt(fmax(v, 1e-300));
         A[c][c] = l;
         const double il = 1.0 / l;
@@ -1013,30 +1058,31 @@ __global__ __launch_bounds__(256) void k_reduce_items(Geo g, ReduceItemArgs a) {
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N;
          s += (int64_t)gridDim.x * blockDim.x) {
         const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
-        const int64_t i = a.perm[s];
 #pragma unroll
         for (int it = 0; it < kItemsPerGroup; ++it) {
             const int item = it0 + it;
             if (item >= a.n_items) break;
+            const int64_t row = s * a.nr;
             if (item < a.ny_cols) {
                 if (a.y_cplx) {
                     double fr = 0.0, fi = 0.0;
                     const double* gv = a.yfit + (int64_t)item * g.Mtot * 2;
 #pragma unroll
                     for (int q = 0; q < (1 << D); ++q) { fr += c.w[q] * gv[2 * c.idx[q]]; fi += c.w[q] * gv[2 * c.idx[q] + 1]; }
-                    const double yr = load_as_double(a.Y, a.y_type, i * a.y_stride + 2 * item);
-                    const double yi = load_as_double(a.Y, a.y_type, i * a.y_stride + 2 * item + 1);
+                    const double yr = load_as_double(a.wsorted, a.w_type, row + 1 + 2 * item);
+                    const double yi = load_as_double(a.wsorted, a.w_type, row + 2 + 2 * item);
                     acc[2 * it] += (yr - fr) * (yr - fr) + (yi - fi) * (yi - fi);
                 } else {
                     double f = 0.0;
                     const double* gv = a.yfit + (int64_t)item * g.Mtot;
 #pragma unroll
                     for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
-                    const double y = load_as_double(a.Y, a.y_type, i * a.y_stride + item);
+                    const double y = load_as_double(a.wsorted, a.w_type, row + 1 + item);
                     acc[2 * it] += (y - f) * (y - f);
                 }
             } else {
-                const double wv = wval(a.probe[it], i);
+                const int ycols = a.ny_cols * (a.y_cplx ? 2 : 1);
+                const double wv = load_as_double(a.wsorted, a.w_type, row + 1 + ycols + (item - a.ny_cols));
                 const double* gv = a.pfit + (int64_t)(item - a.ny_cols) * g.Mtot;
                 double f = 0.0;
 #pragma unroll
@@ -1153,6 +1199,48 @@ __global__ void k_zero(uint32_t* p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Weight vectors in sorted order: out[s * nr + r0 + q] = source q at sample
+// perm[s].  Probes of one Philox block (indices 4g .. 4g+3) share the block and
+// its two Box-Muller transforms.
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, int r0, int nr,
+                                                       int64_t N, const int32_t* perm, T* out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int64_t i = perm[s];
+    uint64_t cached_seed = 0, cached_g = ~0ull;
+    double z[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 2 * kMaxPairsPerSpread; ++q) {
+        if (q >= nsrc) break;
+        const WSrc& w = src.w[q];
+        double v;
+        if (w.kind == W_PHILOX) {
+            const uint64_t gq = (uint64_t)(w.probe >> 2);
+            if (gq != cached_g || w.seed != cached_seed) {
+                uint64_t c[4] = {(uint64_t)i, gq, 0, 0};
+                philox4x64_10(c, w.seed, 0);
+                double sn, cs;
+                const double u0 = ((double)(c[0] >> 11) + 1.0) * 0x1p-53, u1 = ((double)(c[1] >> 11) + 1.0) * 0x1p-53;
+                const double u2 = ((double)(c[2] >> 11) + 1.0) * 0x1p-53, u3 = ((double)(c[3] >> 11) + 1.0) * 0x1p-53;
+                const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
+                sincospi(2.0 * u1, &sn, &cs);
+                z[0] = ra * cs;
+                z[1] = ra * sn;
+                sincospi(2.0 * u3, &sn, &cs);
+                z[2] = rb * cs;
+                z[3] = rb * sn;
+                cached_g = gq;
+                cached_seed = w.seed;
+            }
+            v = z[w.probe & 3];
+        } else {
+            v = wval_mem(w, s, i);
+        }
+        out[s * nr + r0 + q] = (T)v;
+    }
+}
+
 // Per-weight spectra C_r(n) (complex128, [r][n]) from the pair spectra.
 template <typename T>
 __global__ void k_unpack_spec(int64_t Btot, int d, int64_t B0, int64_t B1, int64_t B2, int npairs,
@@ -1197,6 +1285,15 @@ __global__ void k_chan_out(int64_t Mtot, int ncp, int n_s, int n_t, int nw, cons
 // Launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t N,
+                          const int32_t* perm, void* out, hipStream_t s) {
+    if (N == 0) return;
+    if (prec == FKR_F64)
+        k_stage_weights<double><<<nblk(N), 256, 0, s>>>(src, nsrc, r0, nr, N, perm, static_cast<double*>(out));
+    else
+        k_stage_weights<float><<<nblk(N), 256, 0, s>>>(src, nsrc, r0, nr, N, perm, static_cast<float*>(out));
+}
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 4);
@@ -1246,7 +1343,7 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
                      const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max, void* subgrid,
                      hipStream_t s) {
     if constexpr (spread_tile_edge(D, W) > 0) {
-        const unsigned nb = (unsigned)std::min<int64_t>(n_jobs_max, 256 * 8);
+        const unsigned nb = (unsigned)std::min<int64_t>(n_jobs_max, 65535);
         k_spread<D, W, T, KER><<<nb, kSpreadBlock, 0, s>>>(g, src, loc, static_cast<const T*>(frac),
                                                            perm, jobs, static_cast<T*>(subgrid));
     }
@@ -1294,9 +1391,10 @@ void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* c
 void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void* out, hipStream_t s) {
     FftPass f = f0;
     const size_t csz = prec == FKR_F64 ? 16 : 8;
+    // rows per workgroup: enough workgroups to fill the chip first
     int R = 64;
     while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;
-    while (R > 1 && f.rows < R) R >>= 1;
+    while (R > 1 && f.rows < (int64_t)R * 1024) R >>= 1;
     f.rows_per_block = R;
     const size_t lds = (size_t)2 * R * f.F * csz;
     const unsigned nb = (unsigned)((f.rows + R - 1) / R);

@@ -230,6 +230,7 @@ static void layout(fkr_plan* p) {
     L.partial = take(L.cap_partial * 8);
     L.cap_wbuf = 2 * N;
     L.wbuf = take(L.cap_wbuf * 8);
+    L.wsort = take((size_t)N * p->max_weights * sz);
     L.red = take((size_t)p->max_h * (2 * p->max_weights + 4) * 8);
     L.total = off;
 }
@@ -254,7 +255,9 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
              : D.transform_precision == FKR_TP_F32 ? FKR_F32 : D.precision;
     p->kernel = D.spread_kernel;
     p->eps = D.eps;
-    p->sigma = D.sigma == 0.0 ? 2.0 : D.sigma;
+    // Default oversampling: 4 in 1-D and 2-D (narrower kernel, sparser fine
+    // cells; the fine grid stays small), 2 in 3-D.
+    p->sigma = D.sigma == 0.0 ? (D.d <= 2 ? 4.0 : 2.0) : D.sigma;
     p->n_max = D.n_max;
     p->max_weights = D.max_weights;
     p->max_h = D.max_h;
@@ -288,7 +291,9 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
     const double tol_k = std::max(tol, p->prec == FKR_F32 ? 1e-9 : 1e-16);
 
     if (p->kernel == FKR_KERNEL_ES) {
-        p->w = (int)std::ceil(-std::log10(tol_k)) + 1;
+        // ES width for oversampling sigma (Barnett, Magland, af Klinteberg):
+        // w = ceil(ln(1/tol) / (pi sqrt(1 - 1/sigma))), i.e. digits + 1 at sigma = 2.
+        p->w = (int)std::ceil(-std::log(tol_k) / (M_PI * std::sqrt(1.0 - 1.0 / p->sigma)));
         p->w = std::min(std::max(p->w, 2), 16);
         p->kparam = 0.97 * M_PI * (1.0 - 0.5 / p->sigma) * p->w;
     } else {
@@ -372,8 +377,9 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
     for (int j = 0; j < p->d; ++j) {
         const int stride = 1 + 2 * kCoverSlots;
         p->cover[j].assign((size_t)p->Mr[j] * stride, 0);
-        for (int64_t b = 0; b < p->nt[j]; ++b)
-            for (int64_t o = 0; o < p->ts[j] + p->w - 1; ++o) {
+        for (int64_t b = 0; b < p->nt[j]; ++b) {
+            const int64_t interior = std::min<int64_t>(p->ts[j], p->Mr[j] - b * p->ts[j]);
+            for (int64_t o = 0; o < interior + p->w - 1; ++o) {
                 int64_t c = (b * p->ts[j] + o) % p->Mr[j];
                 int32_t* e = &p->cover[j][(size_t)c * stride];
                 if (e[0] >= kCoverSlots) return FKR_E_UNSUPPORTED;
@@ -381,15 +387,12 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
                 e[2 + 2 * e[0]] = (int32_t)o;
                 e[0]++;
             }
+        }
     }
 
-    // Samples per spreading job: about 1024 jobs for n_max samples (four
-    // workgroups per CU), within [256, 4096].
-    {
-        int64_t c = 256;
-        while (c < 4096 && c * 1024 < p->n_max) c *= 2;
-        p->chunk = (int)c;
-    }
+    // Spreading jobs: a tile's samples, cut into pieces of at most 2048 so
+    // that dense tiles do not serialise on one workgroup.
+    p->chunk = 2048;
     p->n_jobs_max = p->n_tiles + (p->n_max + p->chunk - 1) / p->chunk + 1;
     p->npairs_max = (p->max_weights + 1) / 2;
     const int nreal = p->n_s + p->n_t * (p->max_weights - 1);

@@ -1,0 +1,235 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every function that include/fkr.h declares, the planner's geometry obeys the
+design rules of the band-limited transform, bad descriptors are rejected, and
+the host-only helpers (bandwidth list, relaxed GCV selection) agree with the
+oracle and with the values the paper prints.
+"""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fkr.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2204_07716_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2204_07716_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fkr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    from paper_2204_07716_amd import _lib
+    assert _declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_library_has_no_torch_dependency():
+    """The C ABI takes plain pointers; the shared library links no torch."""
+    from paper_2204_07716_amd import _lib
+    with open(_lib.LIB_PATH, "rb") as f:
+        blob = f.read()
+    assert b"libtorch" not in blob and b"libc10" not in blob
+
+
+def _desc(d=2, order=1, M=(64, 48), h_min=(0.05, 0.05), h_max=(0.1, 0.1), eps=1e-6,
+          precision=0, kernel=0, sigma=0.0, n_max=1000, max_weights=2, max_h=1, tprec=0,
+          lo=None, hi=None):
+    from paper_2204_07716_amd import _lib
+    D = _lib.PlanDesc()
+    D.d, D.order = d, order
+    for j in range(d):
+        D.M[j] = M[j]
+        D.lo[j] = 0.0 if lo is None else lo[j]
+        D.hi[j] = 1.0 if hi is None else hi[j]
+        D.h_min[j], D.h_max[j] = h_min[j], h_max[j]
+    D.eps, D.precision, D.spread_kernel, D.sigma = eps, precision, kernel, sigma
+    D.n_max, D.max_weights, D.max_h, D.transform_precision = n_max, max_weights, max_h, tprec
+    return D
+
+
+def _plan(lib, D):
+    from paper_2204_07716_amd import _lib
+    p = ctypes.c_void_p()
+    st = lib.fkr_plan_create(ctypes.byref(D), ctypes.byref(p))
+    if st != 0:
+        return st, None
+    g = _lib.Geometry()
+    assert lib.fkr_plan_geometry(p, ctypes.byref(g)) == 0
+    ws = ctypes.c_size_t()
+    assert lib.fkr_workspace_size(p, ctypes.byref(ws)) == 0
+    assert ws.value == g.workspace_bytes
+    lib.fkr_plan_destroy(p)
+    return 0, g
+
+
+def _smooth(n):
+    for q in (2, 3, 5):
+        while n % q == 0:
+            n //= q
+    return n == 1
+
+
+CASES = [
+    dict(d=1, order=0, M=(1024,), h_min=(0.02,), h_max=(0.02,), eps=1e-9, precision=1),
+    dict(d=2, order=1, M=(256, 256), h_min=(0.03, 0.05), h_max=(0.03, 0.05), eps=1e-6),
+    dict(d=2, order=1, M=(256, 256), h_min=(0.01, 0.01), h_max=(0.2, 0.2), eps=1e-6, max_h=32),
+    dict(d=3, order=1, M=(128, 128, 128), h_min=(0.05,) * 3, h_max=(0.05,) * 3, eps=1e-6),
+    dict(d=2, order=2, M=(512, 512), h_min=(0.02, 0.02), h_max=(0.02, 0.02), eps=1e-6),
+    dict(d=2, order=1, M=(37, 29), h_min=(0.11, 0.13), h_max=(0.11, 0.13), eps=1e-9, precision=1),
+    dict(d=1, order=1, M=(96,), h_min=(0.045,), h_max=(0.045,), eps=1e-9, precision=1, kernel=1),
+    dict(d=2, order=1, M=(40, 33), h_min=(0.09, 0.11), h_max=(0.09, 0.11), eps=1e-6, sigma=2.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"d{c['d']}l{c['order']}M{c['M'][0]}")
+def test_planner_geometry_invariants(lib, case):
+    """Band-limited NUFFT design (Sec. 1.2, eq. 16-20): the period covers the
+    grid plus the kernel's reach at h_max, so the circular convolution has no
+    wrap-around; the kept band reaches far enough that the Gaussian multiplier
+    has decayed below eps at its edge for h_min; the fine grid oversamples the
+    band by sigma and has 2,3,5-smooth sizes; tiles cover the fine grid."""
+    st, g = _plan(lib, _desc(**case))
+    assert st == 0
+    d = case["d"]
+    eps = case["eps"]
+    order = case["order"]
+    sigma = case.get("sigma", 0.0) or (4.0 if d <= 2 else 2.0)
+    assert g.n_s == math.comb(d + 2 * order, 2 * order)
+    assert g.n_t == math.comb(d + order, order)
+    for j in range(d):
+        M, L, K, Mr = g.M[j], g.L[j], g.K[j], g.Mr[j]
+        delta = 1.0 / (M - 1)
+        assert math.isclose(g.delta[j], delta, rel_tol=1e-14)
+        assert math.isclose(g.period[j], L * delta, rel_tol=1e-14)
+        assert _smooth(L) and _smooth(Mr)
+        # spatial reach: Gaussian moment kernel of degree 2l below eps/10 past
+        # the grid, |z|^{2l} e^{-z^2/2} at z = (L - M + 1) delta / h_max
+        z = (L - M + 1) * delta / case["h_max"][j]
+        assert z ** (2 * order) * math.exp(-z * z / 2) <= 0.1 * eps
+        # spectral reach: |t|^{2l} e^{-t^2/2} at t = h_min * 2 pi K / T
+        t = case["h_min"][j] * 2 * math.pi * K / g.period[j]
+        assert t ** (2 * order) * math.exp(-t * t / 2) <= 0.1 * eps
+        # ... and not wastefully far: one mode less would violate the tail
+        t1 = case["h_min"][j] * 2 * math.pi * (K - 2) / g.period[j]
+        assert t1 < t
+        assert Mr >= sigma * (2 * K + 1)
+        assert g.tile[j] >= 1 and g.tile[j] <= Mr
+    n_tiles = 1
+    for j in range(d):
+        n_tiles *= -(-g.Mr[j] // g.tile[j])
+    assert g.n_tiles == n_tiles
+    assert g.w in (6, 8, 12, 16, 24)
+    assert g.workspace_bytes > 0
+
+
+def test_workspace_grows_with_capacity(lib):
+    _, g1 = _plan(lib, _desc(n_max=1000))
+    _, g2 = _plan(lib, _desc(n_max=1_000_000))
+    _, g3 = _plan(lib, _desc(n_max=1000, max_weights=12))
+    assert g2.workspace_bytes > g1.workspace_bytes + 1_000_000 * 8
+    assert g3.workspace_bytes > g1.workspace_bytes
+
+
+def test_tolerance_drives_kernel_width(lib):
+    ws = [_plan(lib, _desc(eps=e, precision=1))[1].w for e in (1e-3, 1e-6, 1e-9, 1e-12)]
+    assert ws == sorted(ws) and ws[0] < ws[-1]
+
+
+BAD = [
+    dict(d=0), dict(d=4), dict(order=-1), dict(order=9), dict(eps=0.0), dict(eps=1.0),
+    dict(eps=float("nan")), dict(precision=7), dict(kernel=5), dict(tprec=9), dict(n_max=-1),
+    dict(max_weights=0), dict(max_h=0), dict(max_h=100000), dict(sigma=1.0), dict(sigma=8.0),
+    dict(M=(1, 48)), dict(h_min=(0.0, 0.05)), dict(h_min=(0.2, 0.05), h_max=(0.1, 0.1)),
+    dict(lo=(0.0, 1.0), hi=(1.0, 1.0)), dict(lo=(float("nan"), 0.0), hi=(1.0, 1.0)),
+    dict(h_max=(0.1, float("inf"))),
+]
+
+
+@pytest.mark.parametrize("bad", BAD, ids=lambda b: ",".join(f"{k}={v}" for k, v in b.items()))
+def test_bad_descriptors_are_rejected(lib, bad):
+    args = dict(d=2)
+    args.update(bad)
+    st, _ = _plan(lib, _desc(**args) if args["d"] in (1, 2, 3) else _desc_raw(args))
+    assert st == -1
+
+
+def _desc_raw(args):
+    D = _desc()
+    D.d = args["d"]
+    return D
+
+
+def test_null_arguments_are_rejected(lib):
+    from paper_2204_07716_amd import _lib
+    p = ctypes.c_void_p()
+    assert lib.fkr_plan_create(None, ctypes.byref(p)) == -1
+    assert lib.fkr_plan_geometry(None, ctypes.byref(_lib.Geometry())) == -1
+    assert lib.fkr_set_points(None, 10, None, 0, None) == -1
+    assert lib.fkr_get_diagnostics(None, ctypes.byref(_lib.Diag())) == -1
+    # a plan without a workspace refuses device work before touching the GPU
+    D = _desc()
+    assert lib.fkr_plan_create(ctypes.byref(D), ctypes.byref(p)) == 0
+    assert lib.fkr_set_points(p, 10, ctypes.c_void_p(8), 0, None) == -3
+    h = (ctypes.c_double * 2)(0.05, 0.05)
+    assert lib.fkr_fit(p, 1, h, 1, 0, ctypes.c_void_p(8), 0, ctypes.c_void_p(8), None, None) == -3
+    assert lib.fkr_set_workspace(p, None, 0) == -1
+    lib.fkr_plan_destroy(p)
+
+
+def test_status_strings(lib):
+    for s in (0, 1, -1, -2, -3, -4, -5, -6, 99):
+        assert lib.fkr_status_string(s)
+
+
+def test_hlist_matches_oracle_and_paper(lib):
+    from oracle import oracle as orc
+    from paper_2204_07716_amd import get_hlist
+    for n, a, b, kind in [(10, 0.01, 1.0, "log"), (32, 0.01, 0.2, "log"), (7, 0.1, 0.5, "lin"),
+                          (1, 0.3, 0.7, "log"), (2, 0.05, 0.2, "lin")]:
+        ref = orc.get_hlist(n, [a, b], kind)[:, 0]
+        out = get_hlist(n, a, b, kind)
+        assert np.allclose(out, ref, rtol=1e-14, atol=0), (n, kind)
+        assert out[0] == a and (n == 1 or out[-1] == b)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "get_hlist_paper.json")))
+    out = get_hlist(gold["n"], gold["range"][0], gold["range"][1], "log")
+    for item in gold["printed"]:
+        v = out[item["position_1based"] - 1]
+        assert float(f"{v:.{item['digits']}g}") == item["value"]
+
+
+def test_select_bandwidth_matches_oracle(lib):
+    from oracle import oracle as orc
+    from paper_2204_07716_amd import select_bandwidth
+    rng = np.random.default_rng(80)
+    for trial in range(200):
+        n = int(rng.integers(1, 40))
+        g = rng.random(n) * 10.0 ** rng.uniform(-2, 2)
+        if trial % 3 == 0 and n > 2:
+            g[rng.integers(0, n, size=2)] = np.nan
+        if trial % 5 == 0:
+            g[rng.integers(0, n)] = np.nanmin(g) if np.isfinite(g).any() else 1.0
+        if not np.isfinite(g).any():
+            continue
+        for dstd in (0.0, 0.1, 0.5, 1.0):
+            assert select_bandwidth(g, dstd) == orc.rgcv_select(g, dstd), (g, dstd)

@@ -1,0 +1,123 @@
+"""GPU parity of the Monte-Carlo DF (Sec. 2.1), GCV (eq. 22) and the
+conditional-variance pass (Sec. 3) against the FP64 oracle.
+
+The DF path uses identical probes on both sides: the GPU generates them with
+Philox4x64-10 + Box-Muller from the sample index and the oracle's generator
+(pinned against numpy's Philox) produces the same numbers; a second case
+passes the oracle's probes in as an array.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import density_mask, make_plan, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _data(seed, N, d):
+    rng = np.random.default_rng(seed)
+    X = rng.random((N, d))
+    y = np.sin(3 * X).sum(axis=1) + 0.3 * rng.standard_normal(N)
+    return X, y
+
+
+@pytest.mark.parametrize("d,order,prec,tprec", [(1, 1, "fp64", "same"), (2, 1, "fp32", "fp64"),
+                                                 (2, 0, "fp32", "fp32"), (3, 1, "fp32", "fp64")])
+def test_dof_matches_oracle_with_identical_probes(orc, d, order, prec, tprec):
+    N, Np, seed = 2500, 6, 11
+    X, y = _data(400 + d, N, d)
+    M, h = {1: ((80,), (0.05,)), 2: ((36, 30), (0.1, 0.12)), 3: ((12, 11, 10), (0.17, 0.16, 0.18))}[d]
+    plan = make_plan(d, order, M, h, h, 1e-9 if prec == "fp64" else 1e-6, prec, n_max=N,
+                     max_weights=2 + Np, tprec=tprec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    plan.set_points(to_dev(X, dt))
+    rho = plan.dof(h, Np, seed=seed).cpu().numpy()[0]
+    probes = orc.probes(seed, N, Np)
+    ref, mean, df = orc.dof(X, h, order, M, (0,) * d, (1,) * d, probes)
+    bar = 1e-9 if prec == "fp64" else (1e-6 if tprec == "fp64" else 2e-5)
+    assert np.abs(rho - ref).max() < bar, (rho, ref)
+    # the same probes passed in as an array
+    rho2 = plan.dof(h, Np, probes=to_dev(probes, dt)).cpu().numpy()[0]
+    assert np.abs(rho2 - ref).max() < bar
+
+
+def test_cv_gcv_matches_oracle(orc):
+    """Batched cross-validation (fit + DF + GCV sharing the spreads) over a
+    bandwidth list, with rGCV selection, against the oracle."""
+    N, Np, seed = 3000, 8, 5
+    X, y = _data(410, N, 2)
+    M = (40, 36)
+    hs = np.stack([orc.get_hlist(4, [0.06, 0.2], "log")[:, 0]] * 2, axis=1)
+    plan = make_plan(2, 1, M, hs[0], hs[-1], 1e-6, "fp32", n_max=N, max_weights=2 + Np,
+                     max_h=len(hs), tprec="fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    out = plan.cv(hs, to_dev(y[:, None], torch.float32), Np, seed=seed)
+    gcv = out["gcv"].cpu().numpy()[:, 0]
+    rss = out["rss"].cpu().numpy()[:, 0]
+    rho = out["rho"].cpu().numpy()
+    probes = orc.probes(seed, N, Np)
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    for k, h in enumerate(hs):
+        mh = orc.fit(X, y, h, 1, gp)
+        yhat = orc.interp(mh[:, 0], M, (0, 0), (1, 1), X)
+        r_ref, mean, _ = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+        assert np.abs(rho[k] - r_ref).max() < 1e-6
+        rss_ref = np.sum((y - yhat) ** 2)
+        assert abs(rss[k] / rss_ref - 1) < 1e-5
+        g_ref = orc.gcv(y, yhat, mean)[0]
+        assert abs(gcv[k] / g_ref - 1) < 1e-5
+    from paper_2204_07716_amd import select_bandwidth
+    assert select_bandwidth(gcv, 0.0) == orc.rgcv_select(gcv, 0.0)
+    assert select_bandwidth(gcv, 0.5) == orc.rgcv_select(gcv, 0.5)
+
+
+@pytest.mark.parametrize("mode", ["log", "direct"])
+def test_variance_matches_oracle(orc, mode):
+    """Second pass on squared residuals: the mean grid comes from the GPU
+    (stage isolation); the oracle repeats eq. 24-26 (or eq. 23) on it."""
+    N = 4000
+    rng = np.random.default_rng(420)
+    X = rng.random((N, 2))
+    y = (X ** 2).sum(axis=1) + (0.1 + 0.5 * X[:, 0]) * rng.standard_normal(N)
+    M, h = (32, 30), (0.12, 0.12)
+    plan = make_plan(2, 1, M, h, h, 1e-6, "fp32", n_max=N, max_weights=3, tprec="fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    Yd = to_dev(y[:, None], torch.float32)
+    mh = plan.fit(h, Yd)[0, 0]
+    s2, vhat, kappa = plan.variance(h, Yd, mh, mode=mode)
+    s2 = s2.cpu().numpy()
+    mh_np = mh.cpu().numpy()
+    yhat = orc.interp(mh_np, M, (0, 0), (1, 1), X)
+    y32 = y.astype(np.float32).astype(np.float64)
+    ref, extra = orc.variance(X, y32, yhat, h, 1, M, (0, 0), (1, 1),
+                              mode="log" if mode == "log" else "direct")
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    S, _ = orc.moments(X, None, h, 1, gp)
+    mask = density_mask(S[:, 0])
+    assert rel_err(s2, ref, mask) < 1e-5
+    if mode == "log":
+        assert abs(kappa.item() / extra["kappa"] - 1) < 1e-6
+        assert rel_err(vhat.cpu().numpy(), extra["v"], mask) < 1e-5
+
+
+def test_complex_response_cv(orc):
+    """Complex y: real and imaginary parts share the moment matrix; the GCV
+    uses |y - yhat|^2."""
+    N, Np = 2500, 4
+    rng = np.random.default_rng(430)
+    X = rng.random((N, 2))
+    y = np.exp(2j * np.pi * X[:, 0]) * (1 + X[:, 1]) + 0.2 * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
+    M, h = (34, 30), (0.12, 0.1)
+    plan = make_plan(2, 2, M, h, h, 1e-6, "fp32", n_max=N, max_weights=3 + Np, tprec="fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    out = plan.cv(h, torch.as_tensor(y[:, None].astype(np.complex64), device="cuda"), Np, seed=3)
+    mh = out["mhat"].cpu().numpy()[0, 0]
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    y32 = y.astype(np.complex64).astype(np.complex128)
+    ref, S, T, r0, ill = orc.fit(X, y32, h, 2, gp, return_all=True)
+    mask = density_mask(S[:, 0])
+    assert rel_err(mh, ref[:, 0], mask) < 1e-5
+    yhat = orc.interp(ref[:, 0], M, (0, 0), (1, 1), X)
+    rss_ref = np.sum(np.abs(y32 - yhat) ** 2)
+    assert abs(out["rss"].cpu().numpy()[0, 0] / rss_ref - 1) < 1e-5

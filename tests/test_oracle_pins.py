@@ -384,3 +384,53 @@ def test_variance_log_linear_reproduction(orc):
     assert np.allclose(ex["v"], -1.0 + 2.0 * g, rtol=1e-9, atol=1e-9)
     kappa = 1.0 / np.mean(r * np.exp(-v_true))
     assert np.allclose(s2, np.exp(-1.0 + 2.0 * g) / kappa, rtol=1e-9)
+
+
+def test_pivots_equal_squared_cholesky_diagonal(orc):
+    """The minor-ratio pivots are the squares of the diagonal of numpy's
+    Cholesky factor (a different algorithm for the same quantity)."""
+    rng = np.random.default_rng(70)
+    for P in (1, 3, 6, 10):
+        B = rng.standard_normal((20, P, P))
+        A = B @ np.transpose(B, (0, 2, 1)) + 0.1 * np.eye(P) * rng.random((20, 1, 1))
+        A *= 10.0 ** rng.uniform(-3, 5, (20, 1, 1))
+        L = np.linalg.cholesky(A)
+        ref = np.diagonal(L, axis1=1, axis2=2) ** 2
+        assert np.allclose(orc.pivots(A), ref, rtol=1e-8)
+
+
+def test_collinear_design_is_ill_posed(orc):
+    """Samples on the line x1 = 0.5: the local-linear system is singular at
+    every grid point; a generic design is not."""
+    rng = np.random.default_rng(71)
+    X = np.stack([rng.random(300), np.full(300, 0.5)], axis=1)
+    gp = rng.random((10, 2))
+    mh, S, T, r0, ill = orc.fit(X, rng.standard_normal(300), [0.1, 0.1], 1, gp, return_all=True)
+    assert ill.all() and np.isnan(mh).all()
+    X2 = rng.random((300, 2))
+    gp2 = 0.2 + 0.6 * rng.random((10, 2))
+    mh, S, T, r0, ill = orc.fit(X2, rng.standard_normal(300), [0.1, 0.1], 1, gp2, return_all=True)
+    assert not ill.any()
+
+
+def test_pivot_floor_flags_sparse_points(orc):
+    """An absolute floor flags exactly the points whose smallest pivot is at
+    or below it; floor 0 keeps every well-posed point."""
+    rng = np.random.default_rng(72)
+    X = rng.random((200, 1)) * 0.5
+    gp = np.linspace(0, 1, 21)[:, None]
+    mh0, S, T, r0, ill0 = orc.fit(X, np.ones(200), [0.03], 1, gp, return_all=True)
+    A = orc.assemble(S, [0.03], 1, 1)
+    pmin = orc.pivots(A).min(axis=1)
+    fl = np.nanmedian(pmin[~ill0])
+    mh1, S1, T1, r01, ill1 = orc.fit(X, np.ones(200), [0.03], 1, gp, return_all=True, floor=fl)
+    assert (ill1 == (ill0 | ~(pmin > fl))).all()
+    assert ill1.sum() > ill0.sum()
+
+
+def test_rgcv_select_skips_nan(orc):
+    g = np.array([np.nan, 3.0, 1.0, 1.05, np.nan, 2.0])
+    assert orc.rgcv_select(g, 0.0) == 2
+    f = g[np.isfinite(g)]
+    thr = f.min() + 0.1 * np.std(f, ddof=1)
+    assert orc.rgcv_select(g, 0.1) == max(k for k in range(6) if np.isfinite(g[k]) and g[k] <= thr)
