@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the fast kernel-regression hot path on one MI355X.
+
+Workload: the 2-D local-linear mixture regression (N = 1e6 samples from a
+4-component Gaussian mixture clipped to the unit square, y = sin(4 x1)
+cos(3 x2) + 0.2 e, h = (0.03, 0.05), M = 256^2 grid, order 1, eps = 1e-6,
+FP32 spreading, FP64 transforms by default, FP64 3x3 solves), seeded and
+synthetic.  One step is one pass of the whole path:
+
+  set_points   bin and sort the samples (once per X)
+  cv           spread of density, y and 10 Philox probes -> forward FFTs ->
+               moment channels -> FP64 solves -> interpolation -> Girard DF,
+               RSS and GCV (Sec. 2.1, eq. 22)
+  variance     log-residual second pass (eq. 24-26): residuals, spread,
+               FFTs, solves, kappa, sigma^2 on the grid
+
+The headline value is samples/s = N x fits / step time, where a fit is one
+weight vector through spread + FFT + solve (1 response + 10 probes + 1
+variance pass = 12 per step).  The ``roofline`` object reports the spreading
+kernel (the largest single kernel of the step) against HBM bandwidth with its
+algorithmic bytes per launch, timed with HIP events that the library records
+on the launch stream; ``cpu_baseline`` times the FP64 oracle on a bounded
+sample of grid points and extrapolates to the full grid; ``accuracy`` compares
+the GPU grids with the oracle on that same sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--transform fp64|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_spread_ll2d_counters.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_07716_amd", "csrc", "kernels.hip")
+
+
+def _args():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--transform", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the FFTs and moment channels (spreading is FP32)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-points", type=int, default=1024,
+                    help="grid points in the oracle's timed sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the run, copy a 256 MiB buffer once (counter calibration)")
+    return ap.parse_args()
+
+
+def _kernel_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _traffic(launches_per_step: int):
+    """HBM bytes per spread launch from the committed counter run, or None when
+    the kernel source has changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256") != _kernel_hash():
+        return None
+    per_step = (c["fetch_kib_per_step"] * 1024 * c["copy_fetch_scale"]
+                + c["write_kib_per_step"] * 1024 * c["copy_write_scale"])
+    return per_step / launches_per_step
+
+
+def main() -> int:
+    args = _args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the path is not "
+                          "sharded across GPUs", "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2204_07716_amd import Plan
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    dev = torch.device("cuda:0")
+    w = workloads.make("ll2d")
+    N, M, h = w.N, w.M, w.h[0]
+    Np, seed = w.n_probes, w.probe_seed
+    Xd = torch.as_tensor(w.X.astype(np.float32), device=dev)
+    Yd = torch.as_tensor(w.Y.astype(np.float32), device=dev)
+    plan = Plan(2, 1, M, w.lo, w.hi, h, h, w.eps, precision="fp32", n_max=N,
+                max_weights=2 + Np, max_h=1, transform_precision=args.transform)
+    g = plan.geometry
+    torch.cuda.synchronize()
+
+    def step():
+        plan.set_points(Xd)
+        out = plan.cv(h, Yd, Np, seed=seed)
+        s2, vhat, kappa = plan.variance(h, Yd, out["mhat"][0, 0], mode="log")
+        return out, s2, vhat, kappa
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = plan.profile_read()
+    plan.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    n_fits = (1 + Np) + 1
+    value = N * n_fits / (ms_per_step * 1e-3)
+
+    # Roofline of the spreading kernel: algorithmic bytes (positions and
+    # weights read once, the oversampled grid written once per weight pair).
+    Mr2 = g.Mr[0] * g.Mr[1]
+    bx, bw, bc = 4, 4, 8
+    nw_launch = [2 + Np, 2]              # cv (density, y, probes), variance (density, z)
+    bytes_step = sum(N * (2 * bx + nw * bw) + ((nw + 1) // 2) * Mr2 * bc for nw in nw_launch)
+    spread_ms, spread_n = stages["spread"]
+    launches_per_step = spread_n / args.steps
+    achieved = bytes_step * args.steps / (spread_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_spread", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _traffic(launches_per_step),
+                "algorithmic_bytes_per_launch": bytes_step / launches_per_step,
+                "avg_launch_us": round(spread_ms * 1e3 / max(spread_n, 1), 2),
+                "launches_per_step": launches_per_step}
+
+    out, s2, vhat, kappa = res
+    line = {
+        "metric": "samples/s (spread+FFT+solve) at stated rel err vs FP64 oracle; % of HBM BW",
+        "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 spread, %s transforms, f64 solves" % ("f64" if args.transform == "fp64" else "f32"),
+        "data": "synthetic (seeded 4-component Gaussian mixture, N=1e6)",
+        "config": {"workload": "2-D local linear, N=1e6 mixture, h=(0.03,0.05), M=256x256, "
+                               "eps=1e-6, 10 Philox probes, log-variance pass",
+                   "N": N, "M": list(M), "order": 1, "fits_per_step": n_fits,
+                   "grid_points_per_s": round(M[0] * M[1] * n_fits / (ms_per_step * 1e-3), 1),
+                   "L": [g.L[0], g.L[1]], "Mr": [g.Mr[0], g.Mr[1]], "K": [g.K[0], g.K[1]],
+                   "spread_width": g.w},
+        "roofline": roofline,
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        "gcv": float(out["gcv"][0, 0]), "df": float(N * (1 - out["rho"][0].mean())),
+    }
+
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = a.numel() * 4
+
+    if not args.no_cpu_baseline:
+        line.update(_cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, value))
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, gpu_value):
+    """The oracle on G seeded grid points (plus the corners): the fits of y and
+    the 10 probes and the log-variance fit, timed on the host cores and
+    extrapolated to the full grid; its values at those points check the GPU
+    grids (density mask s_0 >= 1e-3 max s_0 over the sample)."""
+    import numpy as np
+
+    from oracle import oracle as orc
+
+    N, M, h = w.N, w.M, w.h[0]
+    G = max(16, int(args.cpu_points))
+    rng = np.random.default_rng(2024)
+    flat = rng.choice(M[0] * M[1], size=G, replace=False)
+    flat[:4] = [0, M[0] - 1, M[0] * (M[1] - 1), M[0] * M[1] - 1]
+    gp = orc.grid_points(M, w.lo, w.hi)[flat]
+    X = w.X.astype(np.float32).astype(np.float64)
+    y = w.Y[:, 0].astype(np.float32).astype(np.float64)
+    probes = orc.probes(w.probe_seed, N, w.n_probes).astype(np.float32).astype(np.float64)
+    mh_gpu = out["mhat"][0, 0].cpu().numpy()
+    # the variance pass's input: residuals against the GPU mean grid
+    r = (y - orc.interp(mh_gpu, M, w.lo, w.hi, X)) ** 2
+    z = np.log(r + 1.0 / N)
+    Wfit = np.concatenate([y[:, None], probes], axis=1)
+    orc.fit(X[:1000], Wfit[:1000], h, 1, gp[:2])          # load / warm the library
+    t0 = time.perf_counter()
+    ref, S, T, r0, ill = orc.fit(X, Wfit, h, 1, gp, return_all=True)
+    v_ref = orc.fit(X, z, h, 1, gp)[:, 0]
+    t_sample = time.perf_counter() - t0
+    t_full = t_sample * (M[0] * M[1]) / G
+    cpu_value = N * n_fits / t_full
+    mask = S[:, 0] >= 1e-3 * S[:, 0].max()
+
+    def rel(a, b):
+        a, b = a[mask], b[mask]
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    return {
+        "cpu_baseline": {
+            "value": round(cpu_value, 2), "unit": "samples/s", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 direct sums of the 12 fits at {G} of {M[0] * M[1]} grid points "
+                      f"(N={N}), {t_sample:.2f} s, extrapolated x{M[0] * M[1] / G:.0f} to the grid",
+            "gpu_over_cpu": round(gpu_value / cpu_value, 1)},
+        "accuracy": {"mhat_rel_err": rel(mh_gpu[flat], ref[:, 0]),
+                     "vhat_rel_err": rel(vhat.cpu().numpy()[flat], v_ref),
+                     "mask": "s0 >= 1e-3 max s0", "points": int(mask.sum()),
+                     "bar": 1e-5},
+    }
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -232,6 +232,29 @@ fkr_status fkr_hlist(int n, double a, double b, int kind, double* out);
  * skipped; FKR_E_ARG if all are NaN. */
 fkr_status fkr_select_bandwidth(int nh, const double* gcv, double dstd, int* index);
 
+/* Stage timing, for measurement (no part of the method).  While enabled, every
+ * launch of a stage is bracketed by a pair of HIP events recorded on the
+ * stream of the call that launches it.  fkr_profile_read waits for the
+ * recorded events of one stage, returns their summed device time (ms) and
+ * the number of bracketed launches since the previous read, and forgets
+ * them.  FKR_STAGE_SPREAD brackets exactly one kernel per launch (the tiled
+ * spread); the others may bracket a few.  Disabling drops unread records.
+ * Events are created on first use and destroyed with the plan. */
+typedef enum {
+    FKR_STAGE_SORT = 0,      /* set_points: bin, scan, two-level scatter    */
+    FKR_STAGE_WEIGHTS = 1,   /* weights gathered into sorted order          */
+    FKR_STAGE_SPREAD = 2,    /* spreading onto tile subgrids (eq. 16-17)    */
+    FKR_STAGE_FOLD = 3,      /* subgrids summed into the fine grid          */
+    FKR_STAGE_FFT_FWD = 4,   /* forward FFT passes + deconvolution (eq. 19-20) */
+    FKR_STAGE_EXPAND = 5,    /* moment multipliers per channel (eq. 12-13)  */
+    FKR_STAGE_FFT_INV = 6,   /* inverse FFT passes + crop (eq. 21)          */
+    FKR_STAGE_SOLVE = 7,     /* per-grid-point solves (eq. 3 / 11)          */
+    FKR_STAGE_REDUCE = 8,    /* interpolation + DF/RSS/variance reductions  */
+    FKR_N_STAGES = 9
+} fkr_stage;
+fkr_status fkr_profile_enable(fkr_plan* plan, int on);
+fkr_status fkr_profile_read(fkr_plan* plan, int stage, double* ms, int64_t* launches);
+
 /* Synchronises the stream of the last call and reports the device-side
  * counters.  Returns FKR_E_DOMAIN if samples were outside the box,
  * FKR_WARN_ILLPOSED if the last solve produced NaN points, else FKR_OK. */

@@ -29,6 +29,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -133,3 +134,6 @@ int orc_nudft(int d, int64_t N, const double* X, const double* lo, const double*
     }
     return 0;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void) { return omp_get_max_threads(); }

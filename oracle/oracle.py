@@ -81,8 +81,15 @@ def _load():
         lib.orc_moments.restype = ctypes.c_int
         lib.orc_nudft.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_int, P, P, P]
         lib.orc_nudft.restype = ctypes.c_int
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads used by the C loops."""
+    return int(_load().orc_threads())
 
 
 def _ptr(a: np.ndarray):

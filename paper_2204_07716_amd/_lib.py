@@ -46,7 +46,10 @@ class Diag(ctypes.Structure):
 EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_workspace_size",
            "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit",
            "fkr_interp", "fkr_dof", "fkr_cv", "fkr_variance", "fkr_get_diagnostics",
-           "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth"]
+           "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
+           "fkr_profile_read"]
+
+STAGES = ["sort", "weights", "spread", "fold", "fft_fwd", "expand", "fft_inv", "solve", "reduce"]
 
 _lib = None
 
@@ -87,6 +90,8 @@ def load() -> ctypes.CDLL:
         "fkr_status_string": ([I], ctypes.c_char_p),
         "fkr_hlist": ([I, D, D, I, pD], I),
         "fkr_select_bandwidth": ([I, pD, D, ctypes.POINTER(I)], I),
+        "fkr_profile_enable": ([P, I], I),
+        "fkr_profile_read": ([P, I, pD, ctypes.POINTER(I64)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -24,6 +24,38 @@ inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
 template <typename P> P* at(fkr_plan* p, size_t off) { return reinterpret_cast<P*>(p->ws + off); }
 
+// Stage timing: an event pair around the launches of one scope.
+hipEvent_t record_event(fkr_plan* p, hipStream_t s) {
+    hipEvent_t e = nullptr;
+    if (!p->ev_free.empty()) {
+        e = p->ev_free.back();
+        p->ev_free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, s) != hipSuccess) {
+        p->ev_free.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+struct StageTimer {
+    fkr_plan* p;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageTimer(fkr_plan* p_, int stage_, hipStream_t s_) : p(p_), stage(stage_), s(s_) {
+        if (p->prof_on) a = record_event(p, s);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = record_event(p, s);
+        if (b) p->ev_pairs[stage].emplace_back(a, b);
+        else p->ev_free.push_back(a);
+    }
+};
+
 Geo make_geo(const fkr_plan* p) {
     Geo g{};
     g.d = p->d;
@@ -84,6 +116,7 @@ std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipS
         SpreadSrc chunk{};
         const int n = std::min(2 * kMaxPairsPerSpread, nr - r0);
         for (int q = 0; q < n; ++q) chunk.w[q] = srcs[r0 + q];
+        StageTimer t(p, FKR_STAGE_WEIGHTS, s);
         launch_stage_weights(p->prec, chunk, n, r0, nr, p->N, at<int32_t>(p, p->lay.perm), buf, s);
     }
     std::vector<WSrc> out(nr);
@@ -113,11 +146,18 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
             src.w[2 * q] = srcs[r0];
             src.w[2 * q + 1] = r1 < nr ? srcs[r1] : src_zero();
         }
-        launch_spread(g, p->prec, p->kernel, src, at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
-                      at<int32_t>(p, p->lay.perm), at<int32_t>(p, p->lay.jobs), p->n_jobs_max,
-                      p->ws + p->lay.subgrid, s);
-        launch_fold(g, p->prec, p->tprec, gp, at<int32_t>(p, p->lay.cover), at<int32_t>(p, p->lay.job_off),
-                    p->ws + p->lay.subgrid, p->ws + p->lay.fine, s);
+        {
+            StageTimer t(p, FKR_STAGE_SPREAD, s);
+            launch_spread(g, p->prec, p->kernel, src, at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
+                          at<int32_t>(p, p->lay.perm), at<int32_t>(p, p->lay.jobs), p->n_jobs_max,
+                          p->ws + p->lay.subgrid, s);
+        }
+        {
+            StageTimer t(p, FKR_STAGE_FOLD, s);
+            launch_fold(g, p->prec, p->tprec, gp, at<int32_t>(p, p->lay.cover),
+                        at<int32_t>(p, p->lay.job_off), p->ws + p->lay.subgrid, p->ws + p->lay.fine, s);
+        }
+        StageTimer tf(p, FKR_STAGE_FFT_FWD, s);
         const void* in = p->ws + p->lay.fine;
         int64_t done_B = 1;
         for (int j = 0; j < p->d; ++j) {
@@ -173,7 +213,11 @@ fkr_status run_channels(fkr_plan* p, int hidx, int nr, hipStream_t s) {
     for (int j = 0; j < p->d; ++j) { a.mult_off[j] = per_h; per_h += (2 * p->order + 1) * p->B[j]; }
     a.Btot = p->Btot;
     a.mult = at<double>(p, p->lay.mult) + (int64_t)hidx * per_h;
-    launch_expand2(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftA, s);
+    {
+        StageTimer t(p, FKR_STAGE_EXPAND, s);
+        launch_expand2(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftA, s);
+    }
+    StageTimer tf(p, FKR_STAGE_FFT_INV, s);
     const void* in = p->ws + p->lay.fftA;
     int64_t done_M = 1;
     for (int j = 0; j < p->d; ++j) {
@@ -355,6 +399,7 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     if (N < 0 || N > p->n_max || (N > 0 && !X) || !valid_type(x_type)) return FKR_E_ARG;
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
+    StageTimer t(p, FKR_STAGE_SORT, s);
     launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
     launch_zero(p->ws + p->lay.diag, 16 * 8, s);
     launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.tile_of), at<int32_t>(p, p->lay.cell_of),
@@ -433,7 +478,10 @@ fkr_status fkr_fit(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
         SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
         a.y_out = mhat + (int64_t)hi * ny * p->Mtot;
         a.s0_out = s0 ? s0 + (int64_t)hi * p->Mtot : nullptr;
-        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+        {
+            StageTimer t(p, FKR_STAGE_SOLVE, s);
+            launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+        }
     }
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
@@ -481,13 +529,17 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
         a.y_out = yfit;
         a.probe_out = pfit;
-        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+        {
+            StageTimer t(p, FKR_STAGE_SOLVE, s);
+            launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+        }
         ReduceItemArgs r{};
         r.d = p->d; r.n_items = n_items; r.ny_cols = q; r.y_cplx = y_complex;
         r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
         r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.nr = nr;
         r.yfit = yfit; r.pfit = pfit;
         r.partial = partial;
+        StageTimer t(p, FKR_STAGE_REDUCE, s);
         for (int gi = 0; gi < ngroups; ++gi) {
             r.item0 = gi * kItemsPerGroup;
             launch_reduce_items(g, r, 1, s);
@@ -522,8 +574,11 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     const Geo g = make_geo(p);
     double* wbuf = at<double>(p, p->lay.wbuf);
     launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
-    launch_resid(g, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
-                 y_complex, mhat, wbuf, s);
+    {
+        StageTimer t(p, FKR_STAGE_REDUCE, s);
+        launch_resid(g, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
+                     y_complex, mhat, wbuf, s);
+    }
     std::vector<WSrc> srcs{src_one(), src_array(wbuf, FKR_F64, 1, 0)};
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
     launch_mult_tables(g, p->order, 1, h, dev_periods(p), at<double>(p, p->lay.mult), s);
@@ -531,8 +586,12 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
     a.y_out = v;
-    launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    {
+        StageTimer t(p, FKR_STAGE_SOLVE, s);
+        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    }
     if (mode == FKR_VAR_LOG) {
+        StageTimer t(p, FKR_STAGE_REDUCE, s);
         double* partial = at<double>(p, p->lay.partial);
         double* red = at<double>(p, p->lay.red);
         launch_kappa_partial(g, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), v,
@@ -577,6 +636,42 @@ fkr_status fkr_select_bandwidth(int nh, const double* gcv, double dstd, int* ind
         if (std::isfinite(gcv[k]) && gcv[k] <= thr) best = k;
     *index = best;
     return FKR_OK;
+}
+
+fkr_status fkr_profile_enable(fkr_plan* p, int on) {
+    if (!p || (on != 0 && on != 1)) return FKR_E_ARG;
+    if (!on) {
+        for (auto& v : p->ev_pairs) {
+            for (auto& e : v) {
+                (void)hipEventSynchronize(e.second);
+                p->ev_free.push_back(e.first);
+                p->ev_free.push_back(e.second);
+            }
+            v.clear();
+        }
+    }
+    p->prof_on = on != 0;
+    return FKR_OK;
+}
+
+fkr_status fkr_profile_read(fkr_plan* p, int stage, double* ms, int64_t* launches) {
+    if (!p || stage < 0 || stage >= FKR_N_STAGES || !ms || !launches) return FKR_E_ARG;
+    double total = 0.0;
+    fkr_status st = FKR_OK;
+    auto& v = p->ev_pairs[stage];
+    for (auto& e : v) {
+        float t = 0.0f;
+        if (hipEventSynchronize(e.second) != hipSuccess ||
+            hipEventElapsedTime(&t, e.first, e.second) != hipSuccess)
+            st = FKR_E_DEVICE;
+        total += (double)t;
+        p->ev_free.push_back(e.first);
+        p->ev_free.push_back(e.second);
+    }
+    *ms = total;
+    *launches = (int64_t)v.size();
+    v.clear();
+    return st;
 }
 
 fkr_status fkr_get_diagnostics(fkr_plan* p, fkr_diag* out) {

@@ -1,8 +1,11 @@
 // Internal definitions shared by the host planner, the launchers and the C ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "../../include/fkr.h"
@@ -100,6 +103,15 @@ struct fkr_plan {
     bool points_set = false;
     int64_t N = 0;
     void* last_stream = nullptr;
+    // stage timing (fkr_profile_enable / fkr_profile_read)
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[FKR_N_STAGES];
+    ~fkr_plan() {
+        for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+        for (auto& v : ev_pairs)
+            for (auto& e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
 };
 
 namespace fkr {

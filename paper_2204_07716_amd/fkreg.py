@@ -240,6 +240,21 @@ class Plan:
               "fkr_variance")
         return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
 
+    # -- stage timing ---------------------------------------------------
+    def profile(self, on: bool = True) -> None:
+        check(self.lib.fkr_profile_enable(self._plan, 1 if on else 0), "fkr_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{stage: (device ms, launches)} since the previous read."""
+        out = {}
+        for k, name in enumerate(_lib.STAGES):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            check(self.lib.fkr_profile_read(self._plan, k, ctypes.byref(ms), ctypes.byref(n)),
+                  "fkr_profile_read")
+            out[name] = (ms.value, n.value)
+        return out
+
     def diagnostics(self, allow_warn: bool = True) -> dict:
         dg = _lib.Diag()
         st = self.lib.fkr_get_diagnostics(self._plan, ctypes.byref(dg))
