@@ -109,21 +109,26 @@ const double* dev_periods(fkr_plan* p) { return at<double>(p, p->lay.consts); }
 
 // Weight vectors staged in sorted order (one pass per call): returns sources
 // that read the staged copy, [N][nr] in the spreading precision.
+// Every weight vector of a call, constants included, gathered once into
+// sorted sample order: rows of `stride` = nr rounded up to 4 columns (the
+// spread loads a row with 16-byte loads; padding columns are zero).
 std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipStream_t s) {
     const int nr = (int)srcs.size();
+    const int stride = (nr + 3) & ~3;
+    std::vector<WSrc> all(srcs);
+    all.resize(stride, src_zero());
     void* buf = p->ws + p->lay.wsort;
-    for (int r0 = 0; r0 < nr; r0 += 2 * kMaxPairsPerSpread) {
+    for (int r0 = 0; r0 < stride; r0 += 2 * kMaxPairsPerSpread) {
         SpreadSrc chunk{};
-        const int n = std::min(2 * kMaxPairsPerSpread, nr - r0);
-        for (int q = 0; q < n; ++q) chunk.w[q] = srcs[r0 + q];
+        const int n = std::min(2 * kMaxPairsPerSpread, stride - r0);
+        for (int q = 0; q < n; ++q) chunk.w[q] = all[r0 + q];
         StageTimer t(p, FKR_STAGE_WEIGHTS, s);
-        launch_stage_weights(p->prec, chunk, n, r0, nr, p->N, at<int32_t>(p, p->lay.perm), buf, s);
+        launch_stage_weights(p->prec, chunk, n, r0, stride, p->N, at<int32_t>(p, p->lay.perm), buf, s);
     }
-    std::vector<WSrc> out(nr);
-    for (int r = 0; r < nr; ++r) {
-        if (srcs[r].kind == W_ONE || srcs[r].kind == W_ZERO) { out[r] = srcs[r]; continue; }
+    std::vector<WSrc> out(stride);
+    for (int r = 0; r < stride; ++r) {
         WSrc w{};
-        w.kind = W_SORTED; w.type = p->prec; w.ptr = buf; w.stride = nr; w.col = r;
+        w.kind = W_SORTED; w.type = p->prec; w.ptr = buf; w.stride = stride; w.col = r;
         out[r] = w;
     }
     return out;
@@ -131,9 +136,9 @@ std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipS
 
 // Spread + fold + forward FFT of every weight pair -> spec [band][npairs].
 fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_t s) {
-    const std::vector<WSrc> srcs = stage_weights(p, srcs_in, s);
+    const std::vector<WSrc> srcs = stage_weights(p, srcs_in, s);   // padded to a multiple of 4
     const Geo g = make_geo(p);
-    const int nr = (int)srcs.size();
+    const int nr = (int)srcs_in.size();
     const int npairs = (nr + 1) / 2;
     if (npairs > p->npairs_max) return FKR_E_ARG;
     const size_t csz = 2 * elem_size(p->prec);
@@ -144,7 +149,7 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
         for (int q = 0; q < gp; ++q) {
             const int r0 = 2 * (p0 + q), r1 = r0 + 1;
             src.w[2 * q] = srcs[r0];
-            src.w[2 * q + 1] = r1 < nr ? srcs[r1] : src_zero();
+            src.w[2 * q + 1] = srcs[r1];   // column nr (odd nr) is staged as zeros
         }
         {
             StageTimer t(p, FKR_STAGE_SPREAD, s);
@@ -536,7 +541,7 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         ReduceItemArgs r{};
         r.d = p->d; r.n_items = n_items; r.ny_cols = q; r.y_cplx = y_complex;
         r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
-        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.nr = nr;
+        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
         r.yfit = yfit; r.pfit = pfit;
         r.partial = partial;
         StageTimer t(p, FKR_STAGE_REDUCE, s);

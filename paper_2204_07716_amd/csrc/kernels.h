@@ -84,7 +84,7 @@ struct ReduceItemArgs {
     int x_type;                   // element type of the sorted coordinates
     const void* X;                // sorted coordinates [N][d]
     const void* wsorted;          // staged weights [N][nr] in sorted order
-    int w_type, nr;               // their element type and count (column 0 = density)
+    int w_type, wstride;          // their element type and row stride (column 0 = density)
     const double* yfit;           // [q][M] or [q][M][2]
     const double* pfit;           // [Np][M]
     int item0;                    // first item of this launch

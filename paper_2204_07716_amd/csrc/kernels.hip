@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -612,6 +613,248 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Geo g, SpreadSrc src, c
     }
 }
 
+// Lane layout of the group spread: a group of G lanes covers the W^D
+// footprint cells of one sample, R cells per lane, and 64 / G groups share a
+// wave.  In 2-D a lane owns column dx = gl % W and rows gl / W + GY r; in 3-D
+// it owns the column (gl % W, gl / W) and every plane dz = r.
+template <int D, int W> struct Foot {
+    static constexpr int R = D == 1 ? 1 : (D == 2 ? (W <= 8 ? 2 : (W <= 16 ? 4 : 12)) : W);
+    static constexpr int GY = D == 1 ? 1 : (D == 2 ? (W + R - 1) / R : W);
+    static constexpr int G = D == 1 ? W : W * GY;
+    static constexpr int NG = G <= 64 ? 64 / G : 1;
+    static constexpr bool ok = G <= 64 && G >= D * W && spread_tile_edge(D, W) > 0;
+};
+
+template <typename T, int NW>
+__device__ __forceinline__ void load_weight_row(const T* row, int nw, T (&wv)[NW]) {
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int c = 0; c < NW / 4; ++c) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (4 * c < nw) v = *reinterpret_cast<const float4*>(row + 4 * c);
+            wv[4 * c] = v.x; wv[4 * c + 1] = v.y; wv[4 * c + 2] = v.z; wv[4 * c + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NW / 2; ++c) {
+            double2 v = make_double2(0.0, 0.0);
+            if (2 * c < nw) v = *reinterpret_cast<const double2*>(row + 2 * c);
+            wv[2 * c] = v.x; wv[2 * c + 1] = v.y;
+        }
+    }
+}
+
+// Group spread of one launch (np <= 8 weight pairs, 2 np real weight columns
+// starting at col0 of the sorted weight rows).  One block per job; the job's
+// samples (sorted by first footprint cell) are cut into NGB = 4 NG segments,
+// one per lane group, interleaved so that the groups of a wave work far
+// apart.  The block walks all segments in lockstep chunks of CS samples per
+// group: the records (first cell, fractions) and weight rows of the next
+// chunk are loaded into registers while the current one, staged in LDS, is
+// being spread (double buffer, one barrier per chunk).  For every sample the
+// group's lanes evaluate the D kernel rows once (one value per lane),
+// exchange them with cross-lane permutes, and add psi * w_k for all weight
+// columns to registers that belong to the lane's footprint cells.  Registers
+// are added into the FP64 LDS tile only when the group's first footprint cell
+// changes, so consecutive samples of one cell cost no LDS atomics.  The tile
+// (pitch PE = TS + W - 1) is written out in the element type T exactly as
+// the per-pair subgrids of k_spread.
+template <int D, int W, typename T, int NWMAX_>
+struct GroupStage {
+    static constexpr int NGB = (kSpreadBlock / 64) * Foot<D, W>::NG;
+    static constexpr int STAGE = sizeof(T) == 4 ? 256 : 128;    // staged samples per chunk
+    static constexpr int CS = STAGE / NGB > 0 ? STAGE / NGB : 1;
+    static constexpr int NS = NGB * CS;
+    static constexpr int NWMAX = NWMAX_;
+    static constexpr int RECW = 4;                               // loc bits + up to 3 fractions
+    // doubles in LDS: tile [NWMAX][PSUB], then two buffers of NS records and NS rows
+    static constexpr size_t stage_bytes = 2 * (size_t)NS * (RECW + NWMAX) * sizeof(T);
+};
+
+template <int D, int W, typename T, int KER, int NWMAX>
+__global__ __launch_bounds__(kSpreadBlock) void k_spread_group(Geo g, int np, const T* wrow, int wstride,
+                                                               int col0, const uint32_t* loc, const T* frac,
+                                                               const int32_t* jobs, T* subgrid) {
+    using F = Foot<D, W>;
+    using GS = GroupStage<D, W, T, NWMAX>;
+    constexpr int TS = spread_tile_edge(D, W);
+    constexpr int PE = TS + W - 1;
+    constexpr int PSUB = D == 1 ? PE : (D == 2 ? PE * PE : PE * PE * PE);
+    constexpr int NWAVE = kSpreadBlock / 64;
+    constexpr int NGB = GS::NGB, CS = GS::CS, NS = GS::NS, RECW = GS::RECW;
+    constexpr int PPP = NWMAX / 2;
+    constexpr int R = F::R;
+    constexpr int U = 4;   // samples per group per step (CS is a multiple of U)
+    extern __shared__ double tile[];   // [NWMAX][PSUB] doubles, then the staging buffers
+    // staging in LDS (integer offsets keep the accesses in the LDS address space):
+    // records [2][NS][RECW], then weight rows [2][NS][NWMAX]
+    T* const stg = reinterpret_cast<T*>(tile + NWMAX * PSUB);
+    constexpr int WOFF = 2 * NS * RECW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = min(lane / F::G, F::NG - 1);
+    const int gl = lane - grp * F::G;
+    const bool member = lane < F::NG * F::G;
+    const int gbase = grp * F::G;
+    const int segid = grp * NWAVE + wave;
+    const int dx = gl % W;
+    const int dyb = D == 1 ? 0 : gl / W;
+    const int pj = min(gl / W, D - 1), pk = gl % W;
+    const bool psi_lane = gl < D * W;
+    const T kp = (T)g.kparam;
+    // loader role: thread -> (segment, sample within the chunk)
+    const int lseg = threadIdx.x / CS, lk = threadIdx.x - lseg * CS;
+    const bool loader = threadIdx.x < NS;
+    const int njobs = jobs[0];
+    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+        const int32_t* jd = jobs + 4 + 4 * job;
+        const int s_beg = jd[1];
+        const int n = jd[2] - jd[1];
+        const int seg = (n + NGB - 1) / NGB;
+        const int nchunk = (seg + CS - 1) / CS;
+        const int q0 = min(n, segid * seg);
+        const int len = member ? min(n, q0 + seg) - q0 : 0;
+        // the loader's segment (segments are numbered like segid)
+        const int lq0 = min(n, lseg * seg), lq1 = min(n, lq0 + seg);
+        for (int p0 = 0; p0 < np; p0 += PPP) {
+            const int nw = 2 * min(PPP, np - p0);
+            for (int c = threadIdx.x; c < nw * PSUB; c += blockDim.x) tile[c] = 0.0;
+            // register copy of the next chunk
+            T rrec[RECW], rw[NWMAX];
+            auto fetch = [&](int ch) {
+                const int q = lq0 + ch * CS + lk;
+                const bool ok = loader && q < lq1;
+                const int64_t sidx = s_beg + (ok ? q : 0);
+                rrec[0] = ok ? __builtin_bit_cast(T, (typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type)loc[sidx]) : (T)0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) rrec[1 + j] = (ok && j < D) ? frac[sidx * D + j] : (T)0;
+                if (ok) load_weight_row<T, NWMAX>(wrow + sidx * wstride + col0 + 2 * p0, nw, rw);
+            };
+            auto stash = [&](int buf) {
+                if (!loader) return;
+                const int slot = lseg * CS + lk;
+#pragma unroll
+                for (int j = 0; j < RECW; ++j) stg[(buf * NS + slot) * RECW + j] = rrec[j];
+#pragma unroll
+                for (int k = 0; k < NWMAX; k += 2) {
+                    if (k >= nw) break;
+                    stg[WOFF + (buf * NS + slot) * NWMAX + k] = rw[k];
+                    stg[WOFF + (buf * NS + slot) * NWMAX + k + 1] = rw[k + 1];
+                }
+            };
+            T acc[R][NWMAX];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < NWMAX; ++k) acc[r][k] = (T)0;
+            int cur = -1;
+            if (nchunk > 0) fetch(0);
+            for (int ch = 0; ch < nchunk; ++ch) {
+                const int buf = ch & 1;
+                stash(buf);
+                __syncthreads();
+                if (ch + 1 < nchunk) fetch(ch + 1);
+                const int rec0 = (buf * NS + segid * CS) * RECW;
+                const int wts0 = WOFF + (buf * NS + segid * CS) * NWMAX;
+                const int tmax = min(CS, len - ch * CS);   // may be <= 0 for this group
+                const int wmax = min(CS, max(0, min(seg, n - wave * seg)) - ch * CS);   // first group of the wave
+                // U samples per group per step: their LDS reads, kernel rows
+                // and permutes are independent, so their latencies overlap
+                for (int t = 0; t < wmax; t += U) {
+                    T psi[U][R];
+                    int cbu[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int tt = min(t + u, max(tmax - 1, 0));
+                        T rv[RECW];
+#pragma unroll
+                        for (int j = 0; j < RECW; ++j) rv[j] = stg[rec0 + tt * RECW + j];
+                        const uint32_t l = (uint32_t)__builtin_bit_cast(
+                            typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type, rv[0]);
+                        cbu[u] = (int)(l & 1023) + (D > 1 ? PE * (int)((l >> 10) & 1023) : 0) +
+                                 (D > 2 ? PE * PE * (int)((l >> 20) & 1023) : 0);
+                        T fj = rv[1];
+                        if (D > 1 && pj == 1) fj = rv[2];
+                        if (D > 2 && pj == 2) fj = rv[3];
+                        const T v = psi_lane ? kernel_value<T, KER>((T)pk - fj, W, kp) : (T)0;
+                        if (D == 1) {
+                            psi[u][0] = v;
+                        } else if (D == 2) {
+                            const T a = __shfl(v, gbase + dx);
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                const int dy = dyb + F::GY * r;
+                                const T b = __shfl(v, gbase + W + min(dy, W - 1));
+                                psi[u][r] = dy < W ? a * b : (T)0;
+                            }
+                        } else {
+                            const T ab = __shfl(v, gbase + dx) * __shfl(v, gbase + W + dyb);
+#pragma unroll
+                            for (int r = 0; r < R; ++r) psi[u][r] = ab * __shfl(v, gbase + 2 * W + r);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (t + u >= tmax) break;
+                        const int tt = t + u;
+                        if (cbu[u] != cur) {
+                            if (cur >= 0) {
+#pragma unroll
+                                for (int r = 0; r < R; ++r) {
+                                    const int dy = dyb + F::GY * r;
+                                    if (D == 2 && dy >= W) continue;
+                                    const int cell = cur + dx + (D == 2 ? PE * dy : (D == 3 ? PE * dyb + PE * PE * r : 0));
+#pragma unroll
+                                    for (int k = 0; k < NWMAX; k += 2) {
+                                        if (k >= nw) break;
+                                        atomicAdd(&tile[k * PSUB + cell], (double)acc[r][k]);
+                                        atomicAdd(&tile[(k + 1) * PSUB + cell], (double)acc[r][k + 1]);
+                                        acc[r][k] = acc[r][k + 1] = (T)0;
+                                    }
+                                }
+                            }
+                            cur = cbu[u];
+                        }
+#pragma unroll
+                        for (int k = 0; k < NWMAX; k += 2) {
+                            if (k >= nw) break;
+                            const T w0 = stg[wts0 + tt * NWMAX + k], w1 = stg[wts0 + tt * NWMAX + k + 1];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                acc[r][k] += psi[u][r] * w0;
+                                acc[r][k + 1] += psi[u][r] * w1;
+                            }
+                        }
+                    }
+                }
+            }
+            if (cur >= 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int dy = dyb + F::GY * r;
+                    if (D == 2 && dy >= W) continue;
+                    const int cell = cur + dx + (D == 2 ? PE * dy : (D == 3 ? PE * dyb + PE * PE * r : 0));
+#pragma unroll
+                    for (int k = 0; k < NWMAX; k += 2) {
+                        if (k >= nw) break;
+                        atomicAdd(&tile[k * PSUB + cell], (double)acc[r][k]);
+                        atomicAdd(&tile[(k + 1) * PSUB + cell], (double)acc[r][k + 1]);
+                    }
+                }
+            }
+            __syncthreads();
+            // subgrid layout [job][pair][cell][re, im]
+            for (int q = 0; 2 * q < nw; ++q) {
+                T* dst = subgrid + ((int64_t)job * np + p0 + q) * PSUB * 2;
+                for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
+                    dst[2 * c] = (T)tile[2 * q * PSUB + c];
+                    dst[2 * c + 1] = (T)tile[(2 * q + 1) * PSUB + c];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Fine cell (c_0, .., c_{d-1}) of pair p = sum over the padded tiles that
 // cover it and over the jobs of each such tile, in a fixed order
 // (deterministic).  A block handles 64 (cell, pair) items; its 4 waves take
@@ -1062,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_reduce_items(Geo g, ReduceItemArgs a) {
         for (int it = 0; it < kItemsPerGroup; ++it) {
             const int item = it0 + it;
             if (item >= a.n_items) break;
-            const int64_t row = s * a.nr;
+            const int64_t row = s * a.wstride;
             if (item < a.ny_cols) {
                 if (a.y_cplx) {
                     double fr = 0.0, fi = 0.0;
@@ -1338,12 +1581,188 @@ void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_
 #undef FKR_CSCAT
 }
 
+// 2-D spread with one sample stream per wave (footprints of at most 64
+// cells).  Lane l owns footprint cell (l % W, l / W); all lanes of the wave
+// work on the same sample, so the first-cell test, the flush and the weight
+// loads are wave-uniform (scalar loads, SGPR operands in the FMAs).  The
+// kernel rows of U = 64 / (2W) consecutive samples are evaluated in one pass
+// (lane = sample, dimension, offset) and fetched with two cross-lane permutes
+// per sample.  Each wave takes a contiguous segment of the job; registers are
+// added into the FP64 LDS tile when the first footprint cell changes.
+template <int W, int KER, int NWMAX>
+__global__ __launch_bounds__(512) void k_spread_wave(Geo g, int np, const float* __restrict__ wrow, int wstride,
+                                                     int col0, const uint32_t* __restrict__ loc,
+                                                     const float* __restrict__ frac, const int32_t* __restrict__ jobs,
+                                                     float* __restrict__ subgrid) {
+    constexpr int TS = spread_tile_edge(2, W);
+    constexpr int PE = TS + W - 1;
+    constexpr int PSUB = PE * PE;
+    constexpr int NWAVE = 512 / 64;
+    constexpr int U = 64 / (2 * W);
+    constexpr int PPP = NWMAX / 2;
+    static_assert(W * W <= 64 && U >= 1, "footprint must fit a wave");
+    extern __shared__ double tile[];   // [NWMAX][PSUB]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int dx = lane % W, dy = lane / W;
+    const bool fp_lane = lane < W * W;
+    const int pu = lane / (2 * W), pj = (lane / W) & 1, pk = lane % W;
+    const float kp = (float)g.kparam;
+    const int njobs = jobs[0];
+    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+        const int s_beg = jobs[4 + 4 * job + 1];
+        const int n = jobs[4 + 4 * job + 2] - s_beg;
+        const int seg = (n + NWAVE - 1) / NWAVE;
+        const int q0 = min(n, wave * seg), q1 = min(n, q0 + seg);
+        for (int p0 = 0; p0 < np; p0 += PPP) {
+            const int nw = 2 * min(PPP, np - p0);
+            for (int c = threadIdx.x; c < nw * PSUB; c += blockDim.x) tile[c] = 0.0;
+            __syncthreads();
+            float acc[NWMAX];
+#pragma unroll
+            for (int k = 0; k < NWMAX; ++k) acc[k] = 0.f;
+            int cur = -1;
+            const float* wbase = wrow + col0 + 2 * p0;
+            auto flush_to = [&](int cb) {
+                if (cb == cur) return;
+                if (cur >= 0 && fp_lane) {
+                    const int cell = cur + dx + PE * dy;
+#pragma unroll
+                    for (int k = 0; k < NWMAX; k += 2) {
+                        if (k >= nw) break;
+                        atomicAdd(&tile[k * PSUB + cell], (double)acc[k]);
+                        atomicAdd(&tile[(k + 1) * PSUB + cell], (double)acc[k + 1]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < NWMAX; ++k) acc[k] = 0.f;
+                cur = cb;
+            };
+            auto cell_of = [&](uint32_t l) { return (int)(l & 1023) + PE * (int)((l >> 10) & 1023); };
+            // One step = UU consecutive samples: their first cells, kernel rows
+            // and the first weight row are requested before any of them is
+            // used, and the next sample's row while the current one is spread.
+            // Columns past nw are never flushed (the rows have slack, so the
+            // loads stay in the workspace).
+            auto step = [&](const int t, auto UUc) {
+                constexpr int UU = decltype(UUc)::value;
+                const int su = s_beg + t + min(pu, UU - 1);
+                const float f = frac[(int64_t)su * 2 + pj];
+                uint32_t lu[UU];
+#pragma unroll
+                for (int u = 0; u < UU; ++u) lu[u] = loc[s_beg + t + u];
+                const float v = kernel_value<float, KER>((float)pk - f, W, kp);
+                float wn[NWMAX];
+                const float* wr0 = wbase + (int64_t)(s_beg + t) * wstride;
+#pragma unroll
+                for (int k = 0; k < NWMAX; ++k) wn[k] = wr0[k];
+#pragma unroll
+                for (int u = 0; u < UU; ++u) {
+                    float wc[NWMAX];
+#pragma unroll
+                    for (int k = 0; k < NWMAX; ++k) wc[k] = wn[k];
+                    if (u + 1 < UU) {
+                        const float* wr = wr0 + (int64_t)(u + 1) * wstride;
+#pragma unroll
+                        for (int k = 0; k < NWMAX; ++k) wn[k] = wr[k];
+                    }
+                    flush_to(cell_of(lu[u]));
+                    const float a = __shfl(v, 2 * W * u + dx);
+                    const float b = __shfl(v, 2 * W * u + W + min(dy, W - 1));
+                    const float psi = fp_lane ? a * b : 0.f;
+#pragma unroll
+                    for (int k = 0; k < NWMAX; ++k) acc[k] += psi * wc[k];
+                }
+            };
+            int t = q0;
+            for (; t + U <= q1; t += U) step(t, std::integral_constant<int, U>{});
+            for (; t < q1; ++t) step(t, std::integral_constant<int, 1>{});
+            if (cur >= 0 && fp_lane) {
+                const int cell = cur + dx + PE * dy;
+#pragma unroll
+                for (int k = 0; k < NWMAX; k += 2) {
+                    if (k >= nw) break;
+                    atomicAdd(&tile[k * PSUB + cell], (double)acc[k]);
+                    atomicAdd(&tile[(k + 1) * PSUB + cell], (double)acc[k + 1]);
+                }
+            }
+            __syncthreads();
+            // subgrid layout [job][pair][cell][re, im]
+            for (int q = 0; 2 * q < nw; ++q) {
+                float* dst = subgrid + ((int64_t)job * np + p0 + q) * PSUB * 2;
+                for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
+                    dst[2 * c] = (float)tile[2 * q * PSUB + c];
+                    dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int W, int KER, int NWMAX>
+static void spread_wave(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
+                        const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
+    constexpr int TS = spread_tile_edge(2, W);
+    constexpr int PE = TS + W - 1;
+    const size_t lds = (size_t)NWMAX * PE * PE * sizeof(double);
+    k_spread_wave<W, KER, NWMAX><<<nb, 512, lds, s>>>(g, src.npairs, static_cast<const float*>(src.w[0].ptr),
+                                                       (int)src.w[0].stride, (int)src.w[0].col, loc,
+                                                       static_cast<const float*>(frac), jobs,
+                                                       static_cast<float*>(subgrid));
+}
+
+template <int D, int W, typename T, int KER, int NWMAX>
+static void spread_group(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
+                         const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
+    if constexpr (Foot<D, W>::ok && sizeof(T) == 4) {
+        constexpr int TS = spread_tile_edge(D, W);
+        constexpr int PE = TS + W - 1;
+        constexpr int PSUB = D == 1 ? PE : (D == 2 ? PE * PE : PE * PE * PE);
+        const size_t lds = (size_t)NWMAX * PSUB * sizeof(double) + GroupStage<D, W, T, NWMAX>::stage_bytes;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_group<D, W, T, KER, NWMAX>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_spread_group<D, W, T, KER, NWMAX><<<nb, kSpreadBlock, lds, s>>>(
+            g, src.npairs, static_cast<const T*>(src.w[0].ptr), (int)src.w[0].stride, (int)src.w[0].col, loc,
+            static_cast<const T*>(frac), jobs, static_cast<T*>(subgrid));
+    }
+}
+
 template <int D, int W, typename T, int KER>
 static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
                      const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max, void* subgrid,
                      hipStream_t s) {
     if constexpr (spread_tile_edge(D, W) > 0) {
         const unsigned nb = (unsigned)std::min<int64_t>(n_jobs_max, 65535);
+        if constexpr (Foot<D, W>::ok && sizeof(T) == 4) {
+            // the group spread reads the staged rows directly: every source of
+            // the launch is a column of the sorted weight rows, in order
+            bool rows = src.w[0].kind == W_SORTED && (src.w[0].col % 4) == 0 && (src.w[0].stride % 4) == 0;
+            for (int q = 1; q < 2 * src.npairs; ++q)
+                rows = rows && src.w[q].kind == W_SORTED && src.w[q].ptr == src.w[0].ptr &&
+                       src.w[q].col == src.w[0].col + q;
+            if (rows) {
+                const int nw = 2 * src.npairs;
+                if constexpr (D == 2 && W <= 8) {
+                    // few weight columns: the lane-group kernel (3 samples per
+                    // wave step) wins; many: the one-sample-per-wave kernel
+                    if (nw <= 4) spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    else if (nw <= 8) spread_wave<W, KER, 8>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    else if (nw <= 12) spread_wave<W, KER, 12>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    else spread_wave<W, KER, 16>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    return;
+                }
+                if constexpr (D == 3) {
+                    spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
+                } else {
+                    if (nw <= 4) spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    else if (nw <= 8) spread_group<D, W, T, KER, 8>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    else spread_group<D, W, T, KER, 16>(g, src, loc, frac, jobs, nb, subgrid, s);
+                }
+                return;
+            }
+        }
         k_spread<D, W, T, KER><<<nb, kSpreadBlock, 0, s>>>(g, src, loc, static_cast<const T*>(frac),
                                                            perm, jobs, static_cast<T*>(subgrid));
     }
