@@ -107,8 +107,6 @@ const int* dev_et(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 512); }
 const int* dev_pidx(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 1024); }
 const double* dev_periods(fkr_plan* p) { return at<double>(p, p->lay.consts); }
 
-// Weight vectors staged in sorted order (one pass per call): returns sources
-// that read the staged copy, [N][nr] in the spreading precision.
 // Every weight vector of a call, constants included, gathered once into
 // sorted sample order: rows of `stride` = nr rounded up to 4 columns (the
 // spread loads a row with 16-byte loads; padding columns are zero).
@@ -407,17 +405,15 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     StageTimer t(p, FKR_STAGE_SORT, s);
     launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
     launch_zero(p->ws + p->lay.diag, 16 * 8, s);
-    launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.tile_of), at<int32_t>(p, p->lay.cell_of),
-                     at<int32_t>(p, p->lay.counts), at<long long>(p, p->lay.diag), s);
+    launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.counts), at<long long>(p, p->lay.diag), s);
     launch_scan(g, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
                 at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.cursor),
                 at<long long>(p, p->lay.diag), s);
-    launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_of),
-                      at<int32_t>(p, p->lay.cell_of), at<int32_t>(p, p->lay.tile_off),
-                      at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.cursor),
-                      at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.order), at<int32_t>(p, p->lay.cnt),
-                      at<int32_t>(p, p->lay.coff), at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
-                      at<int32_t>(p, p->lay.perm), p->ws + p->lay.xs, at<long long>(p, p->lay.diag), s);
+    launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_off),
+                      at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.cursor), at<int32_t>(p, p->lay.jobs),
+                      p->ws + p->lay.trec, at<int32_t>(p, p->lay.cnt), at<int32_t>(p, p->lay.coff),
+                      at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac, at<int32_t>(p, p->lay.perm),
+                      p->ws + p->lay.xs, s);
     if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
     p->N = N;
     p->points_set = true;
@@ -527,7 +523,6 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     double* red = at<double>(p, p->lay.red);
     double* partial = at<double>(p, p->lay.partial);
     const int n_items = q + Np;
-    const int ngroups = (n_items + kItemsPerGroup - 1) / kItemsPerGroup;
     for (int hi = 0; hi < nh; ++hi) {
         if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
         SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
@@ -538,16 +533,20 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
             StageTimer t(p, FKR_STAGE_SOLVE, s);
             launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
         }
-        ReduceItemArgs r{};
-        r.d = p->d; r.n_items = n_items; r.ny_cols = q; r.y_cplx = y_complex;
+        ReduceCvArgs r{};
         r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
         r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
-        r.yfit = yfit; r.pfit = pfit;
+        r.ny_cols = q; r.y_cplx = y_complex; r.yfit = yfit;
+        r.np = Np; r.pfit = pfit;
         r.partial = partial;
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        for (int gi = 0; gi < ngroups; ++gi) {
-            r.item0 = gi * kItemsPerGroup;
-            launch_reduce_items(g, r, 1, s);
+        const int nlaunch = std::max((q + kRedYCols - 1) / kRedYCols, (Np + kRedProbes - 1) / kRedProbes);
+        for (int li = 0; li < nlaunch; ++li) {
+            r.y0 = li * kRedYCols;
+            r.ny_launch = std::max(0, std::min(kRedYCols, q - r.y0));
+            r.p0 = li * kRedProbes;
+            r.np_launch = std::max(0, std::min(kRedProbes, Np - r.p0));
+            launch_reduce_cv(g, r, s);
         }
         launch_reduce_final(partial, 2 * n_items, red, s);
         launch_finalize_cv(hi, Np, q, p->N, red, n_items, q, rho, rss, gcv, s);
@@ -584,7 +583,9 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
         launch_resid(g, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
                      y_complex, mhat, wbuf, s);
     }
-    std::vector<WSrc> srcs{src_one(), src_array(wbuf, FKR_F64, 1, 0)};
+    WSrc z{};   // residual weights, already in sorted order
+    z.kind = W_SORTED; z.type = FKR_F64; z.ptr = wbuf; z.stride = 1; z.col = 0;
+    std::vector<WSrc> srcs{src_one(), z};
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
     launch_mult_tables(g, p->order, 1, h, dev_periods(p), at<double>(p, p->lay.mult), s);
     if ((st = run_channels(p, 0, 2, s)) != FKR_OK) return st;

@@ -10,6 +10,8 @@ namespace fkr {
 constexpr int kMaxPairsPerSpread = 8;
 constexpr int kItemsPerGroup = 8;     // interpolation-reduction items per launch row
 constexpr int kRedBlocks = 1024;      // fixed grid of the two-stage reductions
+constexpr int kRedYCols = 4;          // response columns per fused cv reduction launch
+constexpr int kRedProbes = 16;        // probes per fused cv reduction launch
 constexpr int kSortChunk = 4096;      // samples per block in the binning kernels
 constexpr int kLdsHistMax = 16384;    // tiles counted in LDS (else global atomics)
 constexpr int kSpreadBlock = 256;     // threads per spreading workgroup
@@ -72,9 +74,24 @@ struct SolveArgs {
     int64_t Mtot;
     double s0_floor;               // absolute floor for every Cholesky pivot (s_0 first)
     double* y_out;                 // [q][M][(2)] per bandwidth (may be null)
-    double* probe_out;             // [nr-1-ny][M] (may be null)
+    double* probe_out;             // [M][nr-1-ny] (may be null)
     double* s0_out;                // [M] (may be null)
     unsigned long long* ill_count;
+};
+
+struct ReduceCvArgs {
+    int64_t N;
+    int x_type;                   // element type of the sorted coordinates
+    const void* X;                // sorted coordinates [N][d]
+    const void* wsorted;          // staged rows [N][wstride]: 1, y parts, probes
+    int w_type, wstride;
+    int ny_cols, y_cplx;          // response columns (complex: re, im parts)
+    const double* yfit;           // [q][M] or [q][M][2]
+    int np;                       // probes
+    const double* pfit;           // [M][np]
+    int y0, ny_launch;            // response columns of this launch (<= kRedYCols)
+    int p0, np_launch;            // probes of this launch (<= kRedProbes)
+    double* partial;              // [slot][kRedBlocks]; items: y columns, then probes
 };
 
 struct ReduceItemArgs {
@@ -91,15 +108,15 @@ struct ReduceItemArgs {
     double* partial;              // [slot][kRedBlocks]
 };
 
-void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* tile_of,
-                      int32_t* cell_of, int32_t* counts, long long* diag, hipStream_t s);
-void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off,
-                 int32_t* jobs, int32_t* cursor, long long* diag, hipStream_t s);
-void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N,
-                       int64_t n_jobs_max, const int32_t* tile_of, const int32_t* cell_of,
-                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor,
-                       const int32_t* jobs, int32_t* order, int32_t* cnt, int32_t* off, uint32_t* loc,
-                       void* frac, int32_t* perm, void* xs, long long* diag, hipStream_t s);
+void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, long long* diag,
+                      hipStream_t s);
+void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
+                 int32_t* cursor, long long* diag, hipStream_t s);
+void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
+                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
+                       void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
+                       hipStream_t s);
+size_t tile_record_bytes(int d, int prec);   // bytes of one tile-ordered sample record
 void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, const uint32_t* loc,
                    const void* frac, const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max,
                    void* subgrid, hipStream_t s);
@@ -117,6 +134,7 @@ void launch_unpack_spec(int prec, int64_t Btot, const int64_t* B, int d, int npa
 void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, const void* chan,
                      double* S, double* T, hipStream_t s);
 void launch_reduce_items(const Geo& g, const ReduceItemArgs& a, int nslots, hipStream_t s);
+void launch_reduce_cv(const Geo& g, const ReduceCvArgs& a, hipStream_t s);
 void launch_reduce_final(const double* partial, int nslots, double* out, hipStream_t s);
 void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void* X,
                    int x_type, double* out, hipStream_t s);

@@ -89,7 +89,7 @@ __device__ __forceinline__ double wval(const WSrc& s, int64_t i) {
 // Sample binning (once per X)
 // ---------------------------------------------------------------------------
 struct Binned {
-    int64_t c0[3];    // first footprint cell, wrapped into [0, Mr)
+    int c0[3];        // first footprint cell, wrapped into [0, Mr)
     double frac[3];   // u - first cell, in [w/2 - 1, w/2)
     int tile;
     int cell;         // first cell within the tile, pitch g.tsp
@@ -108,14 +108,17 @@ __device__ __forceinline__ Binned bin_sample(const Geo& g, int x_type, const voi
         x = fmin(fmax(x, g.lo[j]), g.hi[j]);
         const double u = (x - g.lo[j]) * g.inv_hf[j];
         const double cf = floor(u - 0.5 * g.w) + 1.0;
-        int64_t c0 = (int64_t)cf;
         b.frac[j] = u - cf;
-        c0 = ((c0 % g.Mr[j]) + g.Mr[j]) % g.Mr[j];
+        // 32-bit integer arithmetic: 0 <= u < Mr, so cf lies in [1 - w/2, Mr)
+        // and one conditional add wraps it
+        const int mr = (int)g.Mr[j], ts = (int)g.ts[j];
+        int c0 = (int)cf;
+        c0 = c0 < 0 ? c0 + mr : (c0 >= mr ? c0 - mr : c0);
         b.c0[j] = c0;
-        const int tj = (int)(c0 / g.ts[j]);
+        const int tj = (int)((unsigned)c0 / (unsigned)ts);
         tile += tj * stride;
         stride *= (int)g.nt[j];
-        cell += (int)(c0 - (int64_t)tj * g.ts[j]) * cstride;
+        cell += (c0 - tj * ts) * cstride;
         cstride *= g.tsp;
     }
     b.tile = tile;
@@ -126,7 +129,6 @@ __device__ __forceinline__ Binned bin_sample(const Geo& g, int x_type, const voi
 // Tile histogram: per-block LDS counts, then one global add per touched tile.
 template <int D>
 __global__ __launch_bounds__(256) void k_bin_count(Geo g, int x_type, const void* X, int64_t N,
-                                                   int32_t* tile_of, int32_t* cell_of,
                                                    int32_t* counts, long long* diag) {
     extern __shared__ int32_t hist[];   // n_tiles entries when use_lds
     const bool use_lds = g.n_tiles <= kLdsHistMax;
@@ -138,8 +140,6 @@ __global__ __launch_bounds__(256) void k_bin_count(Geo g, int x_type, const void
     unsigned long long outside = 0;
     for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
         Binned b = bin_sample<D>(g, x_type, X, i);
-        tile_of[i] = b.tile;
-        cell_of[i] = b.cell;
         if (use_lds) atomicAdd(&hist[b.tile], 1);
         else atomicAdd(&counts[b.tile], 1);
         outside += b.outside ? 1ull : 0ull;
@@ -209,13 +209,27 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
     }
 }
 
+// Tile-ordered sample record: original index, packed first cell relative to
+// the tile (10 bits per dimension), fractions and clamped coordinates, padded
+// to a multiple of 16 bytes so it moves with vector stores and loads.
+template <int D, typename T>
+struct TileRec {
+    static constexpr int BYTES = 8 + 2 * D * (int)sizeof(T);
+    static constexpr int WORDS = ((BYTES + 15) / 16) * 4;   // 32-bit words
+    uint32_t w[WORDS];
+    __device__ __forceinline__ T& at(int k) { return reinterpret_cast<T*>(w + 2)[k]; }
+    __device__ __forceinline__ const T& at(int k) const { return reinterpret_cast<const T*>(w + 2)[k]; }
+};
+
 // Scatter into tile order: each block ranks its samples per tile in LDS,
 // reserves a range per touched tile with one global add, and writes the
-// sample index at its tile-ordered position.
-template <int D>
-__global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int64_t N, const int32_t* tile_of,
+// sample's record at its tile-ordered position.  The binning is evaluated
+// twice (the second time from the cached coordinates) rather than kept in
+// registers.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int x_type, const void* X, int64_t N,
                                                        const int32_t* tile_off, int32_t* cursor,
-                                                       int32_t* order) {
+                                                       TileRec<D, T>* trec) {
     extern __shared__ int32_t lcount[];   // [n_tiles] local counts, then bases
     const bool use_lds = g.n_tiles <= kLdsHistMax;
     if (use_lds)
@@ -230,7 +244,7 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int64_t N, const i
         const int64_t i = beg + threadIdx.x + (int64_t)q * 256;
         rank[q] = 0;
         if (i < end) {
-            const int t = tile_of[i];
+            const int t = bin_sample<D>(g, x_type, X, i).tile;
             rank[q] = use_lds ? atomicAdd(&lcount[t], 1) : atomicAdd(&cursor[t], 1);
         }
     }
@@ -245,23 +259,53 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int64_t N, const i
     for (int q = 0; q < kPer; ++q) {
         const int64_t i = beg + threadIdx.x + (int64_t)q * 256;
         if (i >= end) continue;
-        const int t = tile_of[i];
+        const Binned b = bin_sample<D>(g, x_type, X, i);
+        const int t = b.tile;
         const int64_t pos = tile_off[t] + (use_lds ? lcount[t] : 0) + rank[q];
-        if (pos < tile_off[t + 1]) order[pos] = (int32_t)i;
+        if (pos >= tile_off[t + 1]) continue;
+        TileRec<D, T> r;
+#pragma unroll
+        for (int k = 0; k < TileRec<D, T>::WORDS; ++k) r.w[k] = 0u;
+        r.w[0] = (uint32_t)i;
+        uint32_t l = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int ts = (int)g.ts[j];
+            const int tj = (int)((unsigned)b.c0[j] / (unsigned)ts);
+            l |= (uint32_t)(b.c0[j] - tj * ts) << (10 * j);
+            r.at(j) = (T)b.frac[j];
+            const double x = load_as_double(X, x_type, i * D + j);
+            r.at(D + j) = (T)fmin(fmax(x, g.lo[j]), g.hi[j]);
+        }
+        r.w[1] = l;
+        uint4* dst = reinterpret_cast<uint4*>(trec + pos);
+#pragma unroll
+        for (int k = 0; k < TileRec<D, T>::WORDS / 4; ++k)
+            dst[k] = make_uint4(r.w[4 * k], r.w[4 * k + 1], r.w[4 * k + 2], r.w[4 * k + 3]);
     }
+}
+
+// Local cell (pitch g.tsp) of a packed first-cell record.
+template <int D>
+__device__ __forceinline__ int local_cell(const Geo& g, uint32_t l) {
+    int c = (int)(l & 1023);
+    if (D > 1) c += g.tsp * (int)((l >> 10) & 1023);
+    if (D > 2) c += g.tsp * g.tsp * (int)((l >> 20) & 1023);
+    return c;
 }
 
 // Per job (a tile-ordered range of at most one chunk): counts per cell of the
 // tile, cnt[job][cell].
-__global__ __launch_bounds__(256) void k_cell_count(Geo g, const int32_t* jobs, const int32_t* order,
-                                                    const int32_t* cell_of, int32_t* cnt) {
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_cell_count(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
+                                                    int32_t* cnt) {
     extern __shared__ int32_t hist[];
     const int job = blockIdx.x;
     if (job >= jobs[0]) return;
     const int32_t* jd = jobs + 4 + 4 * job;
     for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) hist[c] = 0;
     __syncthreads();
-    for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) atomicAdd(&hist[cell_of[order[s]]], 1);
+    for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) atomicAdd(&hist[local_cell<D>(g, trec[s].w[1])], 1);
     __syncthreads();
     for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cnt[(int64_t)job * g.ncell + c] = hist[c];
 }
@@ -326,44 +370,35 @@ __global__ __launch_bounds__(1024) void k_cell_scan(Geo g, const int32_t* tile_o
     }
 }
 
-// Per job: place every sample at its (tile, cell) position and write the
-// records the spreading and the reductions read: packed first-cell offsets,
-// fractions, clamped coordinates and the permutation.
+// Per job: move every tile-ordered record to its (tile, cell) position: the
+// packed first cell, fractions, clamped coordinates and the original index.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cell_scatter(Geo g, int x_type, const void* X,
-                                                      const int32_t* jobs, const int32_t* order,
-                                                      const int32_t* cell_of, const int32_t* off,
-                                                      uint32_t* loc, T* frac, int32_t* perm, T* xs,
-                                                      long long* diag) {
+__global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
+                                                      const int32_t* off, uint32_t* loc, T* frac, int32_t* perm,
+                                                      T* xs) {
     extern __shared__ int32_t cur[];
     const int job = blockIdx.x;
     if (job >= jobs[0]) return;
     const int32_t* jd = jobs + 4 + 4 * job;
     for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = off[(int64_t)job * g.ncell + c];
     __syncthreads();
-    const int t = jd[0];
     for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
-        const int64_t i = order[s];
-        Binned b = bin_sample<D>(g, x_type, X, i);
-        // the slot follows the counted cell, so positions stay inside the tile
-        const int64_t pos = atomicAdd(&cur[cell_of[i]], 1);
-        if (b.tile != t || b.cell != cell_of[i]) {   // cannot happen: identical binning
-            atomicAdd((unsigned long long*)&diag[5], 1ull);
-            continue;
+        TileRec<D, T> r;
+        const uint4* src = reinterpret_cast<const uint4*>(trec + s);
+#pragma unroll
+        for (int k = 0; k < TileRec<D, T>::WORDS / 4; ++k) {
+            const uint4 v = src[k];
+            r.w[4 * k] = v.x; r.w[4 * k + 1] = v.y; r.w[4 * k + 2] = v.z; r.w[4 * k + 3] = v.w;
         }
-        uint32_t l = 0;
-        int64_t rem = t;
+        const uint32_t l = r.w[1];
+        const int64_t pos = atomicAdd(&cur[local_cell<D>(g, l)], 1);
+        loc[pos] = l;
+        perm[pos] = (int32_t)r.w[0];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const int64_t tj = rem % g.nt[j];
-            rem /= g.nt[j];
-            l |= (uint32_t)(b.c0[j] - tj * g.ts[j]) << (10 * j);
-            frac[pos * D + j] = (T)b.frac[j];
-            const double x = load_as_double(X, x_type, i * D + j);
-            xs[pos * D + j] = (T)fmin(fmax(x, g.lo[j]), g.hi[j]);
+            frac[pos * D + j] = r.at(j);
+            xs[pos * D + j] = r.at(D + j);
         }
-        loc[pos] = l;
-        perm[pos] = (int32_t)i;
     }
 }
 
@@ -868,18 +903,22 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
     const int64_t idx = (int64_t)blockIdx.x * 64 + slot;
     double re = 0, im = 0;
     if (idx < g.Mrtot * np) {
-        const int64_t cell = idx % g.Mrtot;
-        const int p = (int)(idx / g.Mrtot);
+        const unsigned mrtot = (unsigned)g.Mrtot;
+        const int p = (int)((unsigned)idx / mrtot);
+        const unsigned cell = (unsigned)idx - (unsigned)p * mrtot;
         const int cs = 1 + 2 * kCoverSlots;
         const int32_t* cv[3];
-        int64_t rem = cell, cov_base = 0;
+        unsigned rem = cell;
+        int64_t cov_base = 0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             if (j < D) {
-                const int64_t c = rem % g.Mr[j];
-                rem /= g.Mr[j];
-                cv[j] = cover + cov_base + c * cs;
-                cov_base += g.Mr[j] * cs;
+                const unsigned mr = (unsigned)g.Mr[j];
+                const unsigned qj = rem / mr;
+                const unsigned c = rem - qj * mr;
+                rem = qj;
+                cv[j] = cover + cov_base + (int64_t)c * cs;
+                cov_base += (int64_t)mr * cs;
             }
         }
         const int64_t lsize = g.Psub * np * 2;
@@ -1015,17 +1054,23 @@ __global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict
         // Modes n = e - K, e < n_in, placed at n mod F; modes that coincide
         // modulo F (band wider than the transform) are summed, which is exact
         // for the values at the F output points.
-        for (int64_t q = threadIdx.x; q < (int64_t)nr * F; q += blockDim.x) {
-            const int64_t r = q / F, pos = q - r * F;
+        // (32-bit index arithmetic: a block's rows hold well under 2^31 elements)
+        const int kin = (int)(f.K % F), nin = (int)n_in;
+        for (int q = threadIdx.x; q < nr * F; q += blockDim.x) {
+            const int r = (int)((unsigned)q / (unsigned)F), pos = q - r * F;
             C acc;
             acc.x = 0;
             acc.y = 0;
-            for (int64_t e = (pos + f.K) % F; e < n_in; e += F) acc = cadd(acc, in[(row0 + r) * n_in + e]);
+            const C* rowp = in + (row0 + r) * n_in;
+            int e = pos + kin;
+            e = e >= F ? e - F : e;
+            for (; e < nin; e += F) acc = cadd(acc, rowp[e]);
             buf0[q] = acc;
         }
     } else {
-        for (int64_t q = threadIdx.x; q < nr * n_in; q += blockDim.x) {
-            const int64_t r = q / n_in, e = q - r * n_in;
+        const int nin = (int)n_in;
+        for (int q = threadIdx.x; q < nr * nin; q += blockDim.x) {
+            const int r = (int)((unsigned)q / (unsigned)nin), e = q - r * nin;
             buf0[r * F + e] = in[(row0 + r) * n_in + e];
         }
     }
@@ -1051,14 +1096,21 @@ __global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict
         Ns *= rad;
     }
 
-    const int64_t n_out = f.n_out;
-    for (int64_t q = threadIdx.x; q < n_out * nr; q += blockDim.x) {
-        const int64_t e = q / nr, r = q - e * nr;
-        const int64_t pos = f.out_band ? (e - f.K + F) % F : e;
+    const int nout = (int)f.n_out;
+    const int kout = (int)(f.K % F);
+    const unsigned rdiv = (unsigned)f.out_rdiv;
+    for (int q = threadIdx.x; q < nout * nr; q += blockDim.x) {
+        const int e = (int)((unsigned)q / (unsigned)nr), r = q - e * nr;
+        int pos = e;
+        if (f.out_band) {
+            pos = e - kout;
+            pos = pos < 0 ? pos + F : pos;
+        }
         C v = src[r * F + pos];
         if (f.fac_out) v = cscale(v, (T)f.fac_out[e]);
-        const int64_t row = row0 + r;
-        out[e * f.out_estride + f.out_roff + (row / f.out_rdiv) * f.out_rmul + row % f.out_rdiv] = v;
+        const unsigned row = (unsigned)(row0 + r);
+        const unsigned rq = row / rdiv;
+        out[(int64_t)e * f.out_estride + f.out_roff + (int64_t)rq * f.out_rmul + (row - rq * rdiv)] = v;
     }
 }
 
@@ -1098,14 +1150,17 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, const int* es, con
     using C = typename V2<T>::t;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.Btot * a.ncp) return;
-    const int c = (int)(idx / a.Btot);
-    const int64_t n = idx - (int64_t)c * a.Btot;
-    int64_t e[3] = {0, 0, 0}, nn = 0, rem = n, stride = 1;
+    const int c = (int)((uint64_t)idx / (uint64_t)a.Btot);
+    const unsigned n = (unsigned)(idx - (int64_t)c * a.Btot);
+    int e[3] = {0, 0, 0};
+    unsigned nn = 0, rem = n, stride = 1;
     for (int j = 0; j < a.d; ++j) {
-        e[j] = rem % a.B[j];
-        rem /= a.B[j];
-        nn += (a.B[j] - 1 - e[j]) * stride;
-        stride *= a.B[j];
+        const unsigned bj = (unsigned)a.B[j];
+        const unsigned qj = rem / bj;
+        e[j] = (int)(rem - qj * bj);
+        rem = qj;
+        nn += (bj - 1 - (unsigned)e[j]) * stride;
+        stride *= bj;
     }
     double acc_re = 0.0, acc_im = 0.0;
     for (int half = 0; half < 2; ++half) {
@@ -1212,7 +1267,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
                 a.y_out[(col * a.Mtot + k) * cpl + part] = m;
             }
         } else if (a.probe_out) {
-            a.probe_out[(int64_t)(r - 1 - a.ny) * a.Mtot + k] = m;
+            a.probe_out[k * (a.nr - 1 - a.ny) + (r - 1 - a.ny)] = m;
         }
     }
 }
@@ -1347,6 +1402,112 @@ __global__ __launch_bounds__(256) void k_reduce_items(Geo g, ReduceItemArgs a) {
     }
 }
 
+// Fused interpolation and cv sums over the samples in sorted order: for the
+// response columns of the launch sum |y - yhat|^2 (eq. 22), for its probes
+// sum w^2 and sum w w_hat (Girard ratios, Sec. 2.1).  The probe fits are
+// interleaved per grid point, so the 2^D corners of a sample bring all probes
+// in contiguous loads; indexes past the launch's count are clamped (loaded,
+// never summed).  Wave sums by cross-lane reduction, block sums in LDS.
+template <int D, typename TW, int PC>
+__global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
+    constexpr int YC = kRedYCols, NA = YC + 2 * PC;
+    __shared__ double sh[NA][4];
+    double ay[YC], aw[PC], ah[PC];
+#pragma unroll
+    for (int j = 0; j < YC; ++j) ay[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < PC; ++j) aw[j] = ah[j] = 0.0;
+    const TW* wrow = static_cast<const TW*>(a.wsorted);
+    const int cpl = a.y_cplx ? 2 : 1;
+    const int pcol = 1 + a.ny_cols * cpl + a.p0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
+        const TW* row = wrow + s * a.wstride;
+#pragma unroll
+        for (int j = 0; j < YC; ++j) {
+            if (j >= a.ny_launch) break;
+            const int col = a.y0 + j;
+            if (a.y_cplx) {
+                const double* gv = a.yfit + (int64_t)col * g.Mtot * 2;
+                double fr = 0.0, fi = 0.0;
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) {
+                    fr += c.w[q] * gv[2 * c.idx[q]];
+                    fi += c.w[q] * gv[2 * c.idx[q] + 1];
+                }
+                const double er = (double)row[1 + 2 * col] - fr, ei = (double)row[2 + 2 * col] - fi;
+                ay[j] += er * er + ei * ei;
+            } else {
+                const double* gv = a.yfit + (int64_t)col * g.Mtot;
+                double f = 0.0;
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
+                const double e = (double)row[1 + col] - f;
+                ay[j] += e * e;
+            }
+        }
+        if (a.np_launch > 0) {
+            double fh[PC];
+#pragma unroll
+            for (int j = 0; j < PC; ++j) fh[j] = 0.0;
+            if (PC % 2 == 0 && (a.np_launch % 2) == 0 && (a.np % 2) == 0 && (a.p0 % 2) == 0) {
+                // 16-byte loads (rows are 16-byte aligned)
+                const int last = a.np_launch / 2 - 1;
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) {
+                    const double2* gv = reinterpret_cast<const double2*>(a.pfit + c.idx[q] * a.np + a.p0);
+#pragma unroll
+                    for (int j = 0; j < PC / 2; ++j) {
+                        const double2 v2 = gv[min(j, last)];
+                        fh[2 * j] += c.w[q] * v2.x;
+                        fh[2 * j + 1] += c.w[q] * v2.y;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) {
+                    const double* gv = a.pfit + c.idx[q] * a.np + a.p0;
+#pragma unroll
+                    for (int j = 0; j < PC; ++j) fh[j] += c.w[q] * gv[min(j, a.np_launch - 1)];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < PC; ++j) {
+                const double wv = (double)row[pcol + min(j, a.np_launch - 1)];
+                aw[j] += wv * wv;
+                ah[j] += wv * fh[j];
+            }
+        }
+    }
+    double acc[NA];
+#pragma unroll
+    for (int j = 0; j < YC; ++j) acc[j] = ay[j];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) { acc[YC + 2 * j] = aw[j]; acc[YC + 2 * j + 1] = ah[j]; }
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) sh[q][wave] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < NA) {
+        const int q = threadIdx.x;
+        const double v = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
+        int slot = -1;
+        if (q < YC) {
+            if (q < a.ny_launch) slot = 2 * (a.y0 + q);
+        } else {
+            const int j = (q - YC) >> 1;
+            if (j < a.np_launch) slot = 2 * (a.ny_cols + a.p0 + j) + ((q - YC) & 1);
+        }
+        if (slot >= 0) a.partial[(int64_t)slot * kRedBlocks + blockIdx.x] = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_final(const double* partial, double* out) {
     __shared__ double sh[256];
     const int slot = blockIdx.x;
@@ -1380,8 +1541,9 @@ __global__ void k_finalize_cv(int hidx, int Np, int q, int64_t N, const double* 
     }
 }
 
-// Residuals of the mean fit for the variance pass (Sec. 3): wbuf[i] = the
-// response of the second fit (log(r + 1/N) or r), wbuf[N + i] = r.
+// Residuals of the mean fit for the variance pass (Sec. 3), in sorted sample
+// order s: wbuf[s] = the response of the second fit (log(r + 1/N) or r),
+// wbuf[N + s] = r.
 template <int D>
 __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x_type, const void* xs,
                                                const int32_t* perm, int y_type, const void* Y,
@@ -1405,8 +1567,8 @@ __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x
         const double e = load_as_double(Y, y_type, i) - f;
         r = e * e;
     }
-    wbuf[i] = mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r;
-    wbuf[N + i] = r;
+    wbuf[s] = mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r;   // sorted order
+    wbuf[N + s] = r;
 }
 
 template <int D>
@@ -1421,7 +1583,7 @@ __global__ __launch_bounds__(256) void k_kappa_partial(Geo g, int64_t N, int x_t
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < (1 << D); ++q) v += c.w[q] * vhat[c.idx[q]];
-        acc[0] += r[perm[s]] * exp(-v);
+        acc[0] += r[s] * exp(-v);
     }
     block_sum<1>(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
@@ -1453,9 +1615,11 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
     const int64_t i = perm[s];
     uint64_t cached_seed = 0, cached_g = ~0ull;
     double z[4] = {0, 0, 0, 0};
+    T vals[2 * kMaxPairsPerSpread];
 #pragma unroll
     for (int q = 0; q < 2 * kMaxPairsPerSpread; ++q) {
-        if (q >= nsrc) break;
+        vals[q] = (T)0;
+        if (q >= nsrc) continue;
         const WSrc& w = src.w[q];
         double v;
         if (w.kind == W_PHILOX) {
@@ -1480,7 +1644,19 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
         } else {
             v = wval_mem(w, s, i);
         }
-        out[s * nr + r0 + q] = (T)v;
+        vals[q] = (T)v;
+    }
+    // the row chunk is written with 16-byte stores (nsrc, r0 and nr are
+    // multiples of 4 for T = float, of 2 for T = double)
+    constexpr int VW = 16 / sizeof(T);
+    T* dst = out + s * nr + r0;
+#pragma unroll
+    for (int q = 0; q < 2 * kMaxPairsPerSpread; q += VW) {
+        if (q >= nsrc) break;
+        if constexpr (sizeof(T) == 4)
+            *reinterpret_cast<float4*>(dst + q) = make_float4(vals[q], vals[q + 1], vals[q + 2], vals[q + 3]);
+        else
+            *reinterpret_cast<double2*>(dst + q) = make_double2(vals[q], vals[q + 1]);
     }
 }
 
@@ -1543,15 +1719,15 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     if (n > 0) k_zero<<<nblk(n), 256, 0, s>>>(static_cast<uint32_t*>(p), n);
 }
 
-void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* tile_of,
-                      int32_t* cell_of, int32_t* counts, long long* diag, hipStream_t s) {
+void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, long long* diag,
+                      hipStream_t s) {
     if (N == 0) return;
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
     const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
     switch (g.d) {
-        case 1: k_bin_count<1><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_of, cell_of, counts, diag); break;
-        case 2: k_bin_count<2><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_of, cell_of, counts, diag); break;
-        default: k_bin_count<3><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_of, cell_of, counts, diag); break;
+        case 1: k_bin_count<1><<<nb, 256, lds, s>>>(g, x_type, X, N, counts, diag); break;
+        case 2: k_bin_count<2><<<nb, 256, lds, s>>>(g, x_type, X, N, counts, diag); break;
+        default: k_bin_count<3><<<nb, 256, lds, s>>>(g, x_type, X, N, counts, diag); break;
     }
 }
 
@@ -1560,25 +1736,40 @@ void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_
     k_scan<<<1, 1024, 0, s>>>(g.n_tiles, g.chunk, counts, tile_off, job_off, jobs, cursor, diag);
 }
 
-void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N,
-                       int64_t n_jobs_max, const int32_t* tile_of, const int32_t* cell_of,
-                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor,
-                       const int32_t* jobs, int32_t* order, int32_t* cnt, int32_t* off, uint32_t* loc,
-                       void* frac, int32_t* perm, void* xs, long long* diag, hipStream_t s) {
-    if (N == 0) return;
+template <int D, typename T>
+static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
+                          const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
+                          void* trec_v, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm,
+                          void* xs, hipStream_t s) {
+    using R = TileRec<D, T>;
+    R* trec = static_cast<R*>(trec_v);
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
     const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
-    k_scatter_tiles<1><<<nb, 256, lds, s>>>(g, N, tile_of, tile_off, cursor, order);
+    k_scatter_tiles<D, T><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_off, cursor, trec);
     const unsigned nj = (unsigned)n_jobs_max;
-    k_cell_count<<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, order, cell_of, cnt);
+    k_cell_count<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, cnt);
     k_cell_scan<<<(unsigned)g.n_tiles, 1024, ((size_t)g.ncell + 1024) * 4, s>>>(g, tile_off, job_off, cnt, off);
-#define FKR_CSCAT(D, T) k_cell_scatter<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, x_type, X, jobs, order, cell_of, off, loc, static_cast<T*>(frac), perm, static_cast<T*>(xs), diag)
+    k_cell_scatter<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, off, loc, static_cast<T*>(frac), perm,
+                                                              static_cast<T*>(xs));
+}
+
+size_t tile_record_bytes(int d, int prec) {
+    if (prec == FKR_F64) return d == 1 ? sizeof(TileRec<1, double>) : d == 2 ? sizeof(TileRec<2, double>) : sizeof(TileRec<3, double>);
+    return d == 1 ? sizeof(TileRec<1, float>) : d == 2 ? sizeof(TileRec<2, float>) : sizeof(TileRec<3, float>);
+}
+
+void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
+                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
+                       void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
+                       hipStream_t s) {
+    if (N == 0) return;
+#define FKR_SC(D, T) sort_cells_dt<D, T>(g, x_type, X, N, n_jobs_max, tile_off, job_off, cursor, jobs, trec, cnt, off, loc, frac, perm, xs, s)
     if (prec == FKR_F64) {
-        if (g.d == 1) FKR_CSCAT(1, double); else if (g.d == 2) FKR_CSCAT(2, double); else FKR_CSCAT(3, double);
+        if (g.d == 1) FKR_SC(1, double); else if (g.d == 2) FKR_SC(2, double); else FKR_SC(3, double);
     } else {
-        if (g.d == 1) FKR_CSCAT(1, float); else if (g.d == 2) FKR_CSCAT(2, float); else FKR_CSCAT(3, float);
+        if (g.d == 1) FKR_SC(1, float); else if (g.d == 2) FKR_SC(2, float); else FKR_SC(3, float);
     }
-#undef FKR_CSCAT
+#undef FKR_SC
 }
 
 // 2-D spread with one sample stream per wave (footprints of at most 64
@@ -1888,6 +2079,26 @@ void launch_reduce_items(const Geo& g, const ReduceItemArgs& a, int ngroups, hip
         case 2: k_reduce_items<2><<<grid, 256, 0, s>>>(g, a); break;
         default: k_reduce_items<3><<<grid, 256, 0, s>>>(g, a); break;
     }
+}
+
+template <int PC>
+static void reduce_cv_pc(const Geo& g, const ReduceCvArgs& a, hipStream_t s) {
+#define FKR_RCV(D, TW) k_reduce_cv<D, TW, PC><<<kRedBlocks, 256, 0, s>>>(g, a)
+    if (a.w_type == FKR_F64) {
+        if (g.d == 1) FKR_RCV(1, double); else if (g.d == 2) FKR_RCV(2, double); else FKR_RCV(3, double);
+    } else {
+        if (g.d == 1) FKR_RCV(1, float); else if (g.d == 2) FKR_RCV(2, float); else FKR_RCV(3, float);
+    }
+#undef FKR_RCV
+}
+
+void launch_reduce_cv(const Geo& g, const ReduceCvArgs& a, hipStream_t s) {
+    // probes per launch rounded up to a compiled count
+    if (a.np_launch <= 2) reduce_cv_pc<2>(g, a, s);
+    else if (a.np_launch <= 4) reduce_cv_pc<4>(g, a, s);
+    else if (a.np_launch <= 8) reduce_cv_pc<8>(g, a, s);
+    else if (a.np_launch <= 12) reduce_cv_pc<12>(g, a, s);
+    else reduce_cv_pc<16>(g, a, s);
 }
 
 void launch_reduce_final(const double* partial, int nslots, double* out, hipStream_t s) {

@@ -23,6 +23,7 @@
 #include <cstring>
 
 #include "fkr_internal.h"
+#include "kernels.h"
 
 namespace fkr {
 
@@ -180,9 +181,7 @@ static void layout(fkr_plan* p) {
     L.cover = take(nCov * 4);
     L.diag = take(16 * 8);
     const int64_t N = std::max<int64_t>(p->n_max, 1);
-    L.tile_of = take(N * 4);
-    L.cell_of = take(N * 4);
-    L.order = take(N * 4);
+    L.trec = take(N * tile_record_bytes(p->d, p->prec));
     L.cnt = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.coff = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.counts = take((p->n_tiles + 1) * 4);
