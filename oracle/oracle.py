@@ -14,9 +14,8 @@ computes, by the plain definitions, slowly and in FP64:
                     the fit is the intercept (e_1 of eq. 3).
 * ``interp``        multilinear interpolation of a grid function (the linear
                     ``griddedInterpolant`` setting of Sec. 5).
-* ``philox4x64``    the Philox4x64-10 counter-based generator (Salmon et al.,
-                    SC'11) and ``probes``: Box-Muller normals from it, the
-                    Gaussian probe vectors of Sec. 2.1 step i.
+* ``philox4x32``    the Philox4x32-10 counter-based generator (Salmon et al.,
+                    SC'11) behind ``probes``, the Gaussian probe vectors.
 * ``dof``           Girard's fast Monte-Carlo estimate of (1/N) tr(I - S_h),
                     Sec. 2.1 steps i-iii.
 * ``gcv``           the GCV criterion of eq. (22); ``rgcv_select`` the relaxed
@@ -294,56 +293,48 @@ def interp(values: np.ndarray, M, lo, hi, Xq: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Probes: Philox4x64-10 + Box-Muller (Sec. 2.1 step i)
+# Probes: Philox4x32-10 + Box-Muller (Sec. 2.1 step i)
 # ---------------------------------------------------------------------------
 
-_PH_M0 = np.uint64(0xD2E7470EE14C6C93)
-_PH_M1 = np.uint64(0xCA5A826395121157)
-_PH_W0 = np.uint64(0x9E3779B97F4A7C15)
-_PH_W1 = np.uint64(0xBB67AE8584CAA73B)
+_PH_M0, _PH_M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)   # round multipliers
+_PH_W0, _PH_W1 = np.uint64(0x9E3779B9), np.uint64(0xBB67AE85)   # key increments
 _LO32 = np.uint64(0xFFFFFFFF)
 _S32 = np.uint64(32)
 
 
-def _mulhilo64(a: np.ndarray, b: np.uint64):
-    a0, a1 = a & _LO32, a >> _S32
-    b0, b1 = b & _LO32, b >> _S32
-    p00, p01, p10, p11 = a0 * b0, a0 * b1, a1 * b0, a1 * b1
-    mid = (p00 >> _S32) + (p01 & _LO32) + (p10 & _LO32)
-    lo = (p00 & _LO32) | (mid << _S32)
-    hi = p11 + (p01 >> _S32) + (p10 >> _S32) + (mid >> _S32)
-    return hi, lo
-
-
-def philox4x64(ctr: np.ndarray, key: Sequence[int], rounds: int = 10) -> np.ndarray:
-    """Philox4x64 with the published multipliers and Weyl key increments.
-    ctr: (n, 4) uint64; key: two uint64.  Returns (n, 4) uint64."""
-    c = [np.array(ctr[:, i], dtype=np.uint64) for i in range(4)]
-    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
-    with np.errstate(over="ignore"):
-        for _ in range(rounds):
-            hi0, lo0 = _mulhilo64(c[0], _PH_M0)
-            hi1, lo1 = _mulhilo64(c[2], _PH_M1)
-            c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
-            k0 = k0 + _PH_W0
-            k1 = k1 + _PH_W1
+def philox4x32(ctr: np.ndarray, key: Sequence[int], rounds: int = 10) -> np.ndarray:
+    """Philox4x32 (Salmon, Moraes, Dror, Shaw, SC'11), 10 rounds by default.
+    ctr: (n, 4) words < 2^32; key: two words.  Products are formed exactly in
+    uint64.  Returns (n, 4) uint64 holding 32-bit words."""
+    c = [np.array(ctr[:, i], dtype=np.uint64) & _LO32 for i in range(4)]
+    k0, k1 = np.uint64(key[0]) & _LO32, np.uint64(key[1]) & _LO32
+    for _ in range(rounds):
+        p0 = c[0] * _PH_M0
+        p1 = c[2] * _PH_M1
+        c = [(p1 >> _S32) ^ c[1] ^ k0, p1 & _LO32, (p0 >> _S32) ^ c[3] ^ k1, p0 & _LO32]
+        k0 = (k0 + _PH_W0) & _LO32
+        k1 = (k1 + _PH_W1) & _LO32
     return np.stack(c, axis=1)
 
 
 def probes(seed: int, N: int, Np: int, index: Optional[np.ndarray] = None) -> np.ndarray:
     """N x Np standard normal probes.  Sample i, probe p = 4 g + r uses the
-    Philox4x64-10 block with counter (i, g, 0, 0) and key (seed, 0); its four
-    words x_k map to uniforms u_k = (floor(x_k / 2^11) + 1) 2^-53 in (0, 1] and
-    Box-Muller gives sqrt(-2 ln u0) (cos, sin)(2 pi u1) for r = 0, 1 and
+    Philox4x32-10 block with counter (i mod 2^32, floor(i / 2^32), g, 0) and
+    key (seed mod 2^32, floor(seed / 2^32) mod 2^32); each of its words x_k
+    gives the uniform u_k = (floor(x_k / 2^8) + 1/2) 2^-24 in (0, 1) (exact in
+    single and double precision), and Box-Muller gives
+    sqrt(-2 ln u0) (cos, sin)(2 pi u1) for r = 0, 1 and
     sqrt(-2 ln u2) (cos, sin)(2 pi u3) for r = 2, 3."""
     idx = np.arange(N, dtype=np.uint64) if index is None else np.asarray(index, dtype=np.uint64)
     out = np.empty((idx.size, Np))
+    key = (int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF)
     for g in range((Np + 3) // 4):
         ctr = np.zeros((idx.size, 4), dtype=np.uint64)
-        ctr[:, 0] = idx
-        ctr[:, 1] = g
-        x = philox4x64(ctr, (np.uint64(seed), np.uint64(0)))
-        u = ((x >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+        ctr[:, 0] = idx & _LO32
+        ctr[:, 1] = idx >> _S32
+        ctr[:, 2] = g
+        x = philox4x32(ctr, key)
+        u = ((x >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
         r0 = np.sqrt(-2.0 * np.log(u[:, 0]))
         r1 = np.sqrt(-2.0 * np.log(u[:, 2]))
         z = [r0 * np.cos(2 * np.pi * u[:, 1]), r0 * np.sin(2 * np.pi * u[:, 1]),

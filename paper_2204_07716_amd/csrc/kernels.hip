@@ -47,33 +47,62 @@ __device__ __forceinline__ double load_as_double(const void* p, int type, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) + Box-Muller probes
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) + Box-Muller probes
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+// Sample i, probe p = 4 g + r: counter (i lo, i hi, g, 0), key (seed lo, seed
+// hi); word x gives the uniform (floor(x / 2^8) + 1/2) 2^-24, exact in float
+// and double.  Box-Muller pairs (u0, u1) -> normals 0, 1 and (u2, u3) -> 2, 3.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-        uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+        const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
         k0 += W0; k1 += W1;
     }
 }
 
-__device__ double probe_value(uint64_t seed, uint64_t i, int p) {
-    uint64_t c[4] = {i, (uint64_t)(p >> 2), 0, 0};
-    philox4x64_10(c, seed, 0);
-    const int r = p & 3;
-    const uint64_t xa = r < 2 ? c[0] : c[2];
-    const uint64_t xb = r < 2 ? c[1] : c[3];
-    const double ua = ((double)(xa >> 11) + 1.0) * 0x1p-53;
-    const double ub = ((double)(xb >> 11) + 1.0) * 0x1p-53;
-    const double rad = sqrt(-2.0 * log(ua));
+__device__ __forceinline__ void philox_block(uint64_t seed, uint64_t i, uint32_t g, uint32_t x[4]) {
+    x[0] = (uint32_t)i; x[1] = (uint32_t)(i >> 32); x[2] = g; x[3] = 0u;
+    philox4x32_10(x, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// Four normals of one block, in double (FP64 plans) ...
+__device__ __forceinline__ void box_muller4(const uint32_t x[4], double z[4]) {
+    double u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = ((double)(x[k] >> 8) + 0.5) * 0x1p-24;
+    const double ra = sqrt(-2.0 * log(u[0])), rb = sqrt(-2.0 * log(u[2]));
     double sn, cs;
-    sincospi(2.0 * ub, &sn, &cs);
-    return (r & 1) ? rad * sn : rad * cs;
+    sincospi(2.0 * u[1], &sn, &cs);
+    z[0] = ra * cs; z[1] = ra * sn;
+    sincospi(2.0 * u[3], &sn, &cs);
+    z[2] = rb * cs; z[3] = rb * sn;
+}
+
+// ... or in single precision with the hardware log2 / sqrt / sin / cos (the
+// trigonometric units take revolutions, so 2 pi u needs no multiply).
+__device__ __forceinline__ void box_muller4(const uint32_t x[4], float z[4]) {
+    float u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = ((float)(x[k] >> 8) + 0.5f) * 0x1p-24f;
+    const float ln2 = 0.69314718055994531f;
+    const float ra = __builtin_amdgcn_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u[0]));
+    const float rb = __builtin_amdgcn_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u[2]));
+    z[0] = ra * __builtin_amdgcn_cosf(u[1]); z[1] = ra * __builtin_amdgcn_sinf(u[1]);
+    z[2] = rb * __builtin_amdgcn_cosf(u[3]); z[3] = rb * __builtin_amdgcn_sinf(u[3]);
+}
+
+__device__ double probe_value(uint64_t seed, uint64_t i, int p) {
+    uint32_t x[4];
+    philox_block(seed, i, (uint32_t)(p >> 2), x);
+    double z[4];
+    box_muller4(x, z);
+    const int r = p & 3;
+    return r == 0 ? z[0] : r == 1 ? z[1] : r == 2 ? z[2] : z[3];
 }
 
 __device__ __forceinline__ double wval(const WSrc& s, int64_t i) {
@@ -1614,7 +1643,7 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
     if (s >= N) return;
     const int64_t i = perm[s];
     uint64_t cached_seed = 0, cached_g = ~0ull;
-    double z[4] = {0, 0, 0, 0};
+    T z[4] = {0, 0, 0, 0};
     T vals[2 * kMaxPairsPerSpread];
 #pragma unroll
     for (int q = 0; q < 2 * kMaxPairsPerSpread; ++q) {
@@ -1625,22 +1654,14 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
         if (w.kind == W_PHILOX) {
             const uint64_t gq = (uint64_t)(w.probe >> 2);
             if (gq != cached_g || w.seed != cached_seed) {
-                uint64_t c[4] = {(uint64_t)i, gq, 0, 0};
-                philox4x64_10(c, w.seed, 0);
-                double sn, cs;
-                const double u0 = ((double)(c[0] >> 11) + 1.0) * 0x1p-53, u1 = ((double)(c[1] >> 11) + 1.0) * 0x1p-53;
-                const double u2 = ((double)(c[2] >> 11) + 1.0) * 0x1p-53, u3 = ((double)(c[3] >> 11) + 1.0) * 0x1p-53;
-                const double ra = sqrt(-2.0 * log(u0)), rb = sqrt(-2.0 * log(u2));
-                sincospi(2.0 * u1, &sn, &cs);
-                z[0] = ra * cs;
-                z[1] = ra * sn;
-                sincospi(2.0 * u3, &sn, &cs);
-                z[2] = rb * cs;
-                z[3] = rb * sn;
+                uint32_t x[4];
+                philox_block(w.seed, (uint64_t)i, (uint32_t)gq, x);
+                box_muller4(x, z);
                 cached_g = gq;
                 cached_seed = w.seed;
             }
-            v = z[w.probe & 3];
+            const int pr = w.probe & 3;   // selects instead of a dynamic register index
+            v = (double)(pr == 0 ? z[0] : pr == 1 ? z[1] : pr == 2 ? z[2] : z[3]);
         } else {
             v = wval_mem(w, s, i);
         }

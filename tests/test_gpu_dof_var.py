@@ -2,8 +2,9 @@
 conditional-variance pass (Sec. 3) against the FP64 oracle.
 
 The DF path uses identical probes on both sides: the GPU generates them with
-Philox4x64-10 + Box-Muller from the sample index and the oracle's generator
-(pinned against numpy's Philox) produces the same numbers; a second case
+Philox4x32-10 + Box-Muller from the sample index and the oracle's generator
+(pinned to the generator's published known-answer vectors) produces the same
+uniforms; a second case
 passes the oracle's probes in as an array.
 """
 import numpy as np

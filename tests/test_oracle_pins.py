@@ -230,20 +230,28 @@ def test_interp_exact_on_multilinear_functions(orc):
 # Probes
 # ---------------------------------------------------------------------------
 
-def test_philox_matches_numpy_bit_generator(orc):
-    """numpy's Philox (4x64, 10 rounds) increments its counter before each
-    block, so its first block uses counter + 1."""
-    for key, ctr in [((0, 0), (0, 0, 0, 0)), ((1234567, 987654321), (5, 17, 3, 2**63 + 11)),
-                     ((2**64 - 1, 2**64 - 1), (2**64 - 2, 2**64 - 1, 2**64 - 1, 2**64 - 1))]:
-        bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
-                              counter=np.array(ctr, dtype=np.uint64))
-        ref = bg.random_raw(4)
-        c1 = list(ctr)
-        c1[0] = (c1[0] + 1) % 2**64
-        if c1[0] == 0:
-            c1[1] = (c1[1] + 1) % 2**64
-        got = orc.philox4x64(np.array([c1], dtype=np.uint64), key)[0]
-        assert [int(v) for v in got] == [int(v) for v in ref]
+def test_philox_known_answers(orc):
+    """Philox4x32-10 against the generator's published known-answer vectors."""
+    with open(os.path.join(GOLD, "philox4x32_10_kat.json")) as f:
+        kat = json.load(f)
+    for case in kat["cases"]:
+        ctr = np.array([[int(v, 16) for v in case["ctr"]]], dtype=np.uint64)
+        key = [int(v, 16) for v in case["key"]]
+        got = orc.philox4x32(ctr, key)[0]
+        assert [int(v) for v in got] == [int(v, 16) for v in case["out"]]
+
+
+def test_philox_counter_and_key_layout(orc):
+    """probes() feeds (i mod 2^32, i / 2^32, block, 0) and (seed mod 2^32,
+    seed / 2^32): sample indices and seeds above 2^32 reach the high words."""
+    i = np.array([5, 5 + 2**32], dtype=np.uint64)
+    P = orc.probes(7, 0, 4, index=i)
+    assert not np.array_equal(P[0], P[1])
+    assert not np.array_equal(orc.probes(7, 3, 4), orc.probes(7 + 2**32, 3, 4))
+    x = orc.philox4x32(np.array([[5, 0, 0, 0]], dtype=np.uint64), [7, 0])[0]
+    u = ((x >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+    assert np.isclose(P[0, 0], np.sqrt(-2 * np.log(u[0])) * np.cos(2 * np.pi * u[1]), rtol=1e-15)
+    assert np.isclose(P[0, 3], np.sqrt(-2 * np.log(u[2])) * np.sin(2 * np.pi * u[3]), rtol=1e-15)
 
 
 def test_probes_are_standard_normal_and_reproducible(orc):
