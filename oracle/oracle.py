@@ -25,8 +25,7 @@ computes, by the plain definitions, slowly and in FP64:
                     residual fit of eq. (23).
 * ``get_hlist``     the bandwidth list helper of Sec. 4.
 
-Readings taken where the paper is silent or garbled (each one is listed in
-the design notes):  the bandwidth ``h_j`` is the per-dimension kernel standard
+Readings taken where the paper is silent or garbled: the bandwidth ``h_j`` is the per-dimension kernel standard
 deviation (H = diag(h^2)); the kernel is the normalised Gaussian; the
 displacement is z = x_i - g; the design row holds every monomial of total
 degree <= l in graded order; the Girard estimate is the mean over probes of

@@ -6,8 +6,8 @@ from oracle import oracle as orc
 
 
 def rel_err(gpu, ref, mask=None) -> float:
-    """max |gpu - ref| / max |ref| over the mask (the error metric of the
-    design notes: FFT errors are relative to a channel's global magnitude)."""
+    """max |gpu - ref| / max |ref| over the mask: FFT errors are relative to a
+    channel's global magnitude, so the error is measured against it."""
     gpu = np.asarray(gpu)
     ref = np.asarray(ref)
     if mask is not None:

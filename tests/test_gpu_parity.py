@@ -1,6 +1,6 @@
 """GPU parity of the HIP path against the FP64 oracle, stage by stage.
 
-Error metric (design notes, R21): e = max |gpu - oracle| / max |oracle| over
+Error metric: e = max |gpu - oracle| / max |oracle| over
 all grid points for moment channels and spectra (FFT round-off is relative to
 a channel's global magnitude), and over the density mask
 {s_0 >= 1e-3 max s_0} for fits.  Bars: <= 10 eps in FP64 mode, <= 1e-5 in FP32
