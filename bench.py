@@ -49,6 +49,10 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--transform", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the FFTs and moment channels (spreading is FP32)")
+    ap.add_argument("--sigma", type=float, default=0.0,
+                    help="oversampling of the spreading grid (0: the plan's default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the step in a HIP graph and replay it (checked against eager steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=1024,
                     help="grid points in the oracle's timed sample")
@@ -101,7 +105,7 @@ def main() -> int:
     Xd = torch.as_tensor(w.X.astype(np.float32), device=dev)
     Yd = torch.as_tensor(w.Y.astype(np.float32), device=dev)
     plan = Plan(2, 1, M, w.lo, w.hi, h, h, w.eps, precision="fp32", n_max=N,
-                max_weights=2 + Np, max_h=1, transform_precision=args.transform)
+                max_weights=2 + Np, max_h=1, transform_precision=args.transform, sigma=args.sigma)
     g = plan.geometry
     torch.cuda.synchronize()
 
@@ -114,16 +118,56 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read()
-    torch.cuda.synchronize()
+    if args.graph:
+        # eager reference, then capture; every replay must reproduce it
+        ref = step()
+        torch.cuda.synchronize()
+        ref_vals = [ref[0]["mhat"].clone(), ref[0]["rho"].clone(), ref[0]["gcv"].clone(), ref[1].clone()]
+        s_cap = torch.cuda.Stream()
+        s_cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_cap):
+            step()                       # warm the capture stream's allocator pool
+        torch.cuda.current_stream().wait_stream(s_cap)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            res_g = step()
+        for rep in range(3):
+            graph.replay()
+            torch.cuda.synchronize()
+            got = [res_g[0]["mhat"], res_g[0]["rho"], res_g[0]["gcv"], res_g[1]]
+            for a, b in zip(got, ref_vals):
+                if not torch.allclose(a, b, rtol=1e-6, atol=0, equal_nan=True):
+                    print(json.dumps({"error": "graph replay differs from the eager step", "replay": rep}))
+                    return 1
+            step()                       # eager work between replays
+            torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = plan.profile_read()
-    plan.profile(False)
+    if args.graph:
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = res_g
+        # stage times come from an eager pass over the same steps
+        plan.profile(True)
+        plan.profile_read()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        stages = plan.profile_read()
+        plan.profile(False)
+    else:
+        plan.profile(True)
+        plan.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stages = plan.profile_read()
+        plan.profile(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     n_fits = (1 + Np) + 1
     value = N * n_fits / (ms_per_step * 1e-3)
@@ -157,7 +201,8 @@ def main() -> int:
                    "N": N, "M": list(M), "order": 1, "fits_per_step": n_fits,
                    "grid_points_per_s": round(M[0] * M[1] * n_fits / (ms_per_step * 1e-3), 1),
                    "L": [g.L[0], g.L[1]], "Mr": [g.Mr[0], g.Mr[1]], "K": [g.K[0], g.K[1]],
-                   "spread_width": g.w},
+                   "spread_width": g.w, "sigma": args.sigma or "default",
+                   "hip_graph": bool(args.graph)},
         "roofline": roofline,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "gcv": float(out["gcv"][0, 0]), "df": float(N * (1 - out["rho"][0].mean())),

@@ -405,13 +405,14 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     StageTimer t(p, FKR_STAGE_SORT, s);
     launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
     launch_zero(p->ws + p->lay.diag, 16 * 8, s);
-    launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.counts), at<long long>(p, p->lay.diag), s);
+    launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.bhist),
+                     at<long long>(p, p->lay.diag), s);
     launch_scan(g, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
                 at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.cursor),
                 at<long long>(p, p->lay.diag), s);
     launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_off),
                       at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.cursor), at<int32_t>(p, p->lay.jobs),
-                      p->ws + p->lay.trec, at<int32_t>(p, p->lay.cnt), at<int32_t>(p, p->lay.coff),
+                      at<int32_t>(p, p->lay.bhist), p->ws + p->lay.trec, at<int32_t>(p, p->lay.cnt), at<int32_t>(p, p->lay.coff),
                       at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac, at<int32_t>(p, p->lay.perm),
                       p->ws + p->lay.xs, s);
     if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;

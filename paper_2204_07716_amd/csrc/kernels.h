@@ -13,6 +13,7 @@ constexpr int kRedBlocks = 1024;      // fixed grid of the two-stage reductions
 constexpr int kRedYCols = 4;          // response columns per fused cv reduction launch
 constexpr int kRedProbes = 16;        // probes per fused cv reduction launch
 constexpr int kSortChunk = 4096;      // samples per block in the binning kernels
+constexpr int kSortThreads = 1024;    // threads per binning block
 constexpr int kLdsHistMax = 16384;    // tiles counted in LDS (else global atomics)
 constexpr int kSpreadBlock = 256;     // threads per spreading workgroup
 
@@ -108,13 +109,13 @@ struct ReduceItemArgs {
     double* partial;              // [slot][kRedBlocks]
 };
 
-void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, long long* diag,
-                      hipStream_t s);
+void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, int32_t* bhist,
+                      long long* diag, hipStream_t s);
 void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
                  int32_t* cursor, long long* diag, hipStream_t s);
 void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
                        const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
-                       void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
+                       const int32_t* bhist, void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
                        hipStream_t s);
 size_t tile_record_bytes(int d, int prec);   // bytes of one tile-ordered sample record
 void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, const uint32_t* loc,

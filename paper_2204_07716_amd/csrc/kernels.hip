@@ -157,8 +157,8 @@ __device__ __forceinline__ Binned bin_sample(const Geo& g, int x_type, const voi
 
 // Tile histogram: per-block LDS counts, then one global add per touched tile.
 template <int D>
-__global__ __launch_bounds__(256) void k_bin_count(Geo g, int x_type, const void* X, int64_t N,
-                                                   int32_t* counts, long long* diag) {
+__global__ __launch_bounds__(kSortThreads) void k_bin_count(Geo g, int x_type, const void* X, int64_t N,
+                                                   int32_t* counts, int32_t* bhist, long long* diag) {
     extern __shared__ int32_t hist[];   // n_tiles entries when use_lds
     const bool use_lds = g.n_tiles <= kLdsHistMax;
     if (use_lds)
@@ -175,9 +175,36 @@ __global__ __launch_bounds__(256) void k_bin_count(Geo g, int x_type, const void
     }
     if (outside) atomicAdd((unsigned long long*)&diag[1], outside);
     __syncthreads();
-    if (use_lds)
+    if (use_lds)   // this block's row of the block x tile count matrix (no atomics)
         for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
-            if (hist[t]) atomicAdd(&counts[t], hist[t]);
+            bhist[(int64_t)blockIdx.x * g.n_tiles + t] = hist[t];
+}
+
+// Column prefix of the block x tile count matrix: for tile t (one block per
+// tile), bhist[b][t] becomes the number of samples of t in blocks before b and
+// counts[t] the total, so each binning block owns a fixed, ordered range of
+// every tile.
+__global__ __launch_bounds__(256) void k_tile_prefix(int64_t n_tiles, int nblocks, int32_t* bhist,
+                                                     int32_t* counts) {
+    __shared__ int32_t sh[256];
+    const int64_t t = blockIdx.x;
+    int carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += 256) {
+        const int b = b0 + (int)threadIdx.x;
+        const int v = b < nblocks ? bhist[(int64_t)b * n_tiles + t] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int x = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (b < nblocks) bhist[(int64_t)b * n_tiles + t] = carry + sh[threadIdx.x] - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[t] = carry;
 }
 
 // Single-block exclusive scans of the tile counts and of the job counts;
@@ -256,9 +283,9 @@ struct TileRec {
 // twice (the second time from the cached coordinates) rather than kept in
 // registers.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int x_type, const void* X, int64_t N,
+__global__ __launch_bounds__(kSortThreads) void k_scatter_tiles(Geo g, int x_type, const void* X, int64_t N,
                                                        const int32_t* tile_off, int32_t* cursor,
-                                                       TileRec<D, T>* trec) {
+                                                       const int32_t* bhist, TileRec<D, T>* trec) {
     extern __shared__ int32_t lcount[];   // [n_tiles] local counts, then bases
     const bool use_lds = g.n_tiles <= kLdsHistMax;
     if (use_lds)
@@ -266,11 +293,11 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int x_type, const 
     __syncthreads();
     const int64_t beg = (int64_t)blockIdx.x * kSortChunk;
     const int64_t end = min<int64_t>(N, beg + kSortChunk);
-    constexpr int kPer = kSortChunk / 256;
+    constexpr int kPer = kSortChunk / kSortThreads;
     int rank[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int64_t i = beg + threadIdx.x + (int64_t)q * 256;
+        const int64_t i = beg + threadIdx.x + (int64_t)q * kSortThreads;
         rank[q] = 0;
         if (i < end) {
             const int t = bin_sample<D>(g, x_type, X, i).tile;
@@ -278,15 +305,13 @@ __global__ __launch_bounds__(256) void k_scatter_tiles(Geo g, int x_type, const 
         }
     }
     __syncthreads();
-    if (use_lds)
-        for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x) {
-            const int c = lcount[t];
-            lcount[t] = c ? atomicAdd(&cursor[t], c) : 0;
-        }
+    if (use_lds)   // this block's range of every tile, from the column prefix
+        for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
+            lcount[t] = bhist[(int64_t)blockIdx.x * g.n_tiles + t];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int64_t i = beg + threadIdx.x + (int64_t)q * 256;
+        const int64_t i = beg + threadIdx.x + (int64_t)q * kSortThreads;
         if (i >= end) continue;
         const Binned b = bin_sample<D>(g, x_type, X, i);
         const int t = b.tile;
@@ -921,80 +946,59 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_group(Geo g, int np, co
 
 // Fine cell (c_0, .., c_{d-1}) of pair p = sum over the padded tiles that
 // cover it and over the jobs of each such tile, in a fixed order
-// (deterministic).  A block handles 64 (cell, pair) items; its 4 waves take
-// the jobs of each covering tile round-robin and the 4 partial sums are added
-// in LDS.  Output layout [pair][cell].
+// (deterministic).  One thread per (cell, pair) item; consecutive threads take
+// consecutive cells of one pair, so the subgrid reads of a wave fall on rows
+// of the same tiles.  Output layout [pair][cell].
 template <int D, typename T, typename TO>
 __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cover,
                                               const int32_t* job_off, const T* subgrid, TO* fine) {
-    __shared__ double red[2][4][64];
-    const int slot = threadIdx.x & 63, phase = threadIdx.x >> 6;
-    const int64_t idx = (int64_t)blockIdx.x * 64 + slot;
-    double re = 0, im = 0;
-    if (idx < g.Mrtot * np) {
-        const unsigned mrtot = (unsigned)g.Mrtot;
-        const int p = (int)((unsigned)idx / mrtot);
-        const unsigned cell = (unsigned)idx - (unsigned)p * mrtot;
-        const int cs = 1 + 2 * kCoverSlots;
-        const int32_t* cv[3];
-        unsigned rem = cell;
-        int64_t cov_base = 0;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.Mrtot * np) return;
+    const unsigned mrtot = (unsigned)g.Mrtot;
+    const int p = (int)((unsigned)idx / mrtot);
+    const unsigned cell = (unsigned)idx - (unsigned)p * mrtot;
+    const int cs = 1 + 2 * kCoverSlots;
+    const int32_t* cv[3];
+    unsigned rem = cell;
+    int64_t cov_base = 0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            if (j < D) {
-                const unsigned mr = (unsigned)g.Mr[j];
-                const unsigned qj = rem / mr;
-                const unsigned c = rem - qj * mr;
-                rem = qj;
-                cv[j] = cover + cov_base + (int64_t)c * cs;
-                cov_base += (int64_t)mr * cs;
-            }
+    for (int j = 0; j < 3; ++j) {
+        if (j < D) {
+            const unsigned mr = (unsigned)g.Mr[j];
+            const unsigned qj = rem / mr;
+            const unsigned c = rem - qj * mr;
+            rem = qj;
+            cv[j] = cover + cov_base + (int64_t)c * cs;
+            cov_base += (int64_t)mr * cs;
         }
-        const int64_t lsize = g.Psub * np * 2;
-        const int n0 = cv[0][0];
-        const int n1 = D > 1 ? cv[1][0] : 1;
-        const int n2 = D > 2 ? cv[2][0] : 1;
-        for (int a2 = 0; a2 < n2; ++a2)
-            for (int a1 = 0; a1 < n1; ++a1)
-                for (int a0 = 0; a0 < n0; ++a0) {
-                    int64_t tile = cv[0][1 + 2 * a0];
-                    int64_t off = cv[0][2 + 2 * a0];
-                    if (D > 1) {
-                        tile += g.nt[0] * cv[1][1 + 2 * a1];
-                        off += g.pe[0] * cv[1][2 + 2 * a1];
-                    }
-                    if (D > 2) {
-                        tile += g.nt[0] * g.nt[1] * cv[2][1 + 2 * a2];
-                        off += g.pe[0] * g.pe[1] * cv[2][2 + 2 * a2];
-                    }
-                    const int64_t jb = job_off[tile] + phase, je = job_off[tile + 1];
-                    const T* sg = subgrid + jb * lsize + (p * g.Psub + off) * 2;
-                    int64_t jj = jb;
-                    double r4[4] = {0, 0, 0, 0}, i4[4] = {0, 0, 0, 0};
-                    for (; jj + 12 < je; jj += 16, sg += 16 * lsize) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            r4[u] += (double)sg[4 * u * lsize];
-                            i4[u] += (double)sg[4 * u * lsize + 1];
-                        }
-                    }
-                    for (; jj < je; jj += 4, sg += 4 * lsize) {
-                        r4[0] += (double)sg[0];
-                        i4[0] += (double)sg[1];
-                    }
-                    re += (r4[0] + r4[1]) + (r4[2] + r4[3]);
-                    im += (i4[0] + i4[1]) + (i4[2] + i4[3]);
+    }
+    const int64_t lsize = g.Psub * np * 2;
+    const int n0 = cv[0][0];
+    const int n1 = D > 1 ? cv[1][0] : 1;
+    const int n2 = D > 2 ? cv[2][0] : 1;
+    double re = 0.0, im = 0.0;
+    for (int a2 = 0; a2 < n2; ++a2)
+        for (int a1 = 0; a1 < n1; ++a1)
+            for (int a0 = 0; a0 < n0; ++a0) {
+                int64_t tile = cv[0][1 + 2 * a0];
+                int64_t off = cv[0][2 + 2 * a0];
+                if (D > 1) {
+                    tile += g.nt[0] * cv[1][1 + 2 * a1];
+                    off += g.pe[0] * cv[1][2 + 2 * a1];
                 }
-    }
-    red[0][phase][slot] = re;
-    red[1][phase][slot] = im;
-    __syncthreads();
-    if (phase == 0 && idx < g.Mrtot * np) {
-        const double sr = (red[0][0][slot] + red[0][1][slot]) + (red[0][2][slot] + red[0][3][slot]);
-        const double si = (red[1][0][slot] + red[1][1][slot]) + (red[1][2][slot] + red[1][3][slot]);
-        fine[idx * 2] = (TO)sr;
-        fine[idx * 2 + 1] = (TO)si;
-    }
+                if (D > 2) {
+                    tile += g.nt[0] * g.nt[1] * cv[2][1 + 2 * a2];
+                    off += g.pe[0] * g.pe[1] * cv[2][2 + 2 * a2];
+                }
+                const int j0 = job_off[tile], j1 = job_off[tile + 1];
+                const T* sg = subgrid + (int64_t)j0 * lsize + (p * g.Psub + off) * 2;
+                for (int jj = j0; jj < j1; ++jj, sg += lsize) {
+                    re += (double)sg[0];
+                    im += (double)sg[1];
+                }
+            }
+    fine[idx * 2] = (TO)re;
+    fine[idx * 2 + 1] = (TO)im;
 }
 
 // One radix-RAD Stockham stage (Govindaraju et al., SC'08 formulation):
@@ -1007,8 +1011,13 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
     const int sgn = INV ? 1 : -1;
     const int nb = F / RAD;
     const int tws = F / (Ns * RAD);
+    // j / Ns through a float reciprocal (exact after one correction: j < 2^24)
+    const float rns = 1.0f / (float)Ns;
     for (int j = t; j < nb; j += tpr) {
-        const int k = j % Ns;
+        int jq = (int)((float)j * rns);
+        jq -= jq * Ns > j ? 1 : 0;
+        jq += (jq + 1) * Ns <= j ? 1 : 0;
+        const int k = j - jq * Ns;
         C v[RAD];
 #pragma unroll
         for (int q = 0; q < RAD; ++q) v[q] = a[j + q * nb];
@@ -1056,7 +1065,7 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
             y[2] = cadd(r2, i2);
             y[3] = csub(r2, i2);
         }
-        const int base = (j / Ns) * Ns * RAD + k;
+        const int base = jq * Ns * RAD + k;
 #pragma unroll
         for (int q = 0; q < RAD; ++q) b[base + q * Ns] = y[q];
     }
@@ -1740,16 +1749,18 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     if (n > 0) k_zero<<<nblk(n), 256, 0, s>>>(static_cast<uint32_t*>(p), n);
 }
 
-void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, long long* diag,
-                      hipStream_t s) {
+void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, int32_t* bhist,
+                      long long* diag, hipStream_t s) {
     if (N == 0) return;
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
-    const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
+    const bool use_lds = g.n_tiles <= kLdsHistMax;
+    const size_t lds = use_lds ? (size_t)g.n_tiles * 4 : 0;
     switch (g.d) {
-        case 1: k_bin_count<1><<<nb, 256, lds, s>>>(g, x_type, X, N, counts, diag); break;
-        case 2: k_bin_count<2><<<nb, 256, lds, s>>>(g, x_type, X, N, counts, diag); break;
-        default: k_bin_count<3><<<nb, 256, lds, s>>>(g, x_type, X, N, counts, diag); break;
+        case 1: k_bin_count<1><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, diag); break;
+        case 2: k_bin_count<2><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, diag); break;
+        default: k_bin_count<3><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, diag); break;
     }
+    if (use_lds) k_tile_prefix<<<(unsigned)g.n_tiles, 256, 0, s>>>(g.n_tiles, (int)nb, bhist, counts);
 }
 
 void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
@@ -1760,13 +1771,13 @@ void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_
 template <int D, typename T>
 static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
                           const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
-                          void* trec_v, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm,
+                          const int32_t* bhist, void* trec_v, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm,
                           void* xs, hipStream_t s) {
     using R = TileRec<D, T>;
     R* trec = static_cast<R*>(trec_v);
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
     const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
-    k_scatter_tiles<D, T><<<nb, 256, lds, s>>>(g, x_type, X, N, tile_off, cursor, trec);
+    k_scatter_tiles<D, T><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, tile_off, cursor, bhist, trec);
     const unsigned nj = (unsigned)n_jobs_max;
     k_cell_count<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, cnt);
     k_cell_scan<<<(unsigned)g.n_tiles, 1024, ((size_t)g.ncell + 1024) * 4, s>>>(g, tile_off, job_off, cnt, off);
@@ -1781,10 +1792,10 @@ size_t tile_record_bytes(int d, int prec) {
 
 void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
                        const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
-                       void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
+                       const int32_t* bhist, void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
                        hipStream_t s) {
     if (N == 0) return;
-#define FKR_SC(D, T) sort_cells_dt<D, T>(g, x_type, X, N, n_jobs_max, tile_off, job_off, cursor, jobs, trec, cnt, off, loc, frac, perm, xs, s)
+#define FKR_SC(D, T) sort_cells_dt<D, T>(g, x_type, X, N, n_jobs_max, tile_off, job_off, cursor, jobs, bhist, trec, cnt, off, loc, frac, perm, xs, s)
     if (prec == FKR_F64) {
         if (g.d == 1) FKR_SC(1, double); else if (g.d == 2) FKR_SC(2, double); else FKR_SC(3, double);
     } else {
@@ -1851,9 +1862,11 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, int np, const float*
                 cur = cb;
             };
             auto cell_of = [&](uint32_t l) { return (int)(l & 1023) + PE * (int)((l >> 10) & 1023); };
-            // One step = UU consecutive samples: their first cells, kernel rows
-            // and the first weight row are requested before any of them is
-            // used, and the next sample's row while the current one is spread.
+            // One step = UU consecutive samples.  Every load of the step (first
+            // cells, fractions, weight rows) and every cross-lane permute is
+            // issued before the first FMA, so the step waits once: scalar loads
+            // return out of order and share the LDS counter, so any wait for a
+            // permute would otherwise also wait for loads issued after it.
             // Columns past nw are never flushed (the rows have slack, so the
             // loads stay in the workspace).
             auto step = [&](const int t, auto UUc) {
@@ -1861,33 +1874,34 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, int np, const float*
                 const int su = s_beg + t + min(pu, UU - 1);
                 const float f = frac[(int64_t)su * 2 + pj];
                 uint32_t lu[UU];
-#pragma unroll
-                for (int u = 0; u < UU; ++u) lu[u] = loc[s_beg + t + u];
-                const float v = kernel_value<float, KER>((float)pk - f, W, kp);
-                float wn[NWMAX];
-                const float* wr0 = wbase + (int64_t)(s_beg + t) * wstride;
-#pragma unroll
-                for (int k = 0; k < NWMAX; ++k) wn[k] = wr0[k];
+                float wv[UU][NWMAX];
 #pragma unroll
                 for (int u = 0; u < UU; ++u) {
-                    float wc[NWMAX];
+                    lu[u] = loc[s_beg + t + u];
+                    const float* wr = wbase + (int64_t)(s_beg + t + u) * wstride;
 #pragma unroll
-                    for (int k = 0; k < NWMAX; ++k) wc[k] = wn[k];
-                    if (u + 1 < UU) {
-                        const float* wr = wr0 + (int64_t)(u + 1) * wstride;
+                    for (int k = 0; k < NWMAX; ++k) wv[u][k] = wr[k];
+                }
+                const float v = kernel_value<float, KER>((float)pk - f, W, kp);
+                float psi[UU];
 #pragma unroll
-                        for (int k = 0; k < NWMAX; ++k) wn[k] = wr[k];
-                    }
-                    flush_to(cell_of(lu[u]));
+                for (int u = 0; u < UU; ++u) {
                     const float a = __shfl(v, 2 * W * u + dx);
                     const float b = __shfl(v, 2 * W * u + W + min(dy, W - 1));
-                    const float psi = fp_lane ? a * b : 0.f;
+                    psi[u] = fp_lane ? a * b : 0.f;
+                }
 #pragma unroll
-                    for (int k = 0; k < NWMAX; ++k) acc[k] += psi * wc[k];
+                for (int u = 0; u < UU; ++u) {
+                    flush_to(cell_of(lu[u]));
+#pragma unroll
+                    for (int k = 0; k < NWMAX; ++k) acc[k] += psi[u] * wv[u][k];
                 }
             };
+            // samples per step: as many as the kernel-row pass covers, fewer when
+            // the weight rows of a step would not fit the scalar registers
+            constexpr int US = NWMAX <= 8 ? U : (NWMAX <= 12 ? (U < 4 ? U : 4) : (U < 3 ? U : 3));
             int t = q0;
-            for (; t + U <= q1; t += U) step(t, std::integral_constant<int, U>{});
+            for (; t + US <= q1; t += US) step(t, std::integral_constant<int, US>{});
             for (; t < q1; ++t) step(t, std::integral_constant<int, 1>{});
             if (cur >= 0 && fp_lane) {
                 const int cell = cur + dx + PE * dy;
@@ -2010,7 +2024,7 @@ void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, con
 void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* cover,
                  const int32_t* job_off, const void* subgrid, void* fine, hipStream_t s) {
     const int64_t n = g.Mrtot * npairs;
-#define FKR_FOLD(D, T, TO) k_fold<D, T, TO><<<nblk(n, 64), 256, 0, s>>>(g, npairs, cover, job_off, static_cast<const T*>(subgrid), static_cast<TO*>(fine))
+#define FKR_FOLD(D, T, TO) k_fold<D, T, TO><<<nblk(n, 256), 256, 0, s>>>(g, npairs, cover, job_off, static_cast<const T*>(subgrid), static_cast<TO*>(fine))
 #define FKR_FOLD_D(T, TO) do { if (g.d == 1) FKR_FOLD(1, T, TO); else if (g.d == 2) FKR_FOLD(2, T, TO); else FKR_FOLD(3, T, TO); } while (0)
     if (prec == FKR_F64) FKR_FOLD_D(double, double);
     else if (tprec == FKR_F64) FKR_FOLD_D(float, double);

@@ -182,6 +182,9 @@ static void layout(fkr_plan* p) {
     L.diag = take(16 * 8);
     const int64_t N = std::max<int64_t>(p->n_max, 1);
     L.trec = take(N * tile_record_bytes(p->d, p->prec));
+    // block x tile counts of the binning pass (when the tiles fit the LDS histogram)
+    const int64_t nbins = (N + kSortChunk - 1) / kSortChunk;
+    L.bhist = take(p->n_tiles <= kLdsHistMax ? (size_t)nbins * p->n_tiles * 4 : 4);
     L.cnt = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.coff = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.counts = take((p->n_tiles + 1) * 4);

@@ -220,3 +220,55 @@ def test_repeated_calls_and_smaller_second_input(orc):
     ref, S, T, r0, ill = orc.fit(X2r, y2.astype(np.float32).astype(np.float64), h, 1, gp,
                                  return_all=True)
     assert rel_err(mh, ref[:, 0], density_mask(S[:, 0])) < 1e-5
+
+
+def test_ll2d_bench_step_sampled(orc):
+    """The benchmark's step at full size (N = 1e6 mixture, M = 256^2, order 1,
+    FP32 spreading, FP64 transforms): set_points, cv with 10 Philox probes, then
+    the log-variance pass, in the same launch configuration as bench.py.
+    Checked: the mean fit and v-hat at seeded grid points plus the corners
+    against the oracle; the probes' grid fits likewise; the Girard ratios
+    recomputed by the oracle from those grid fits (stage isolation); GCV from
+    the oracle's residual sum and the GPU's ratios; kappa from the GPU grids."""
+    w = workloads.make("ll2d")
+    h, Np, seed = w.h[0], w.n_probes, w.probe_seed
+    plan = make_plan(2, 1, w.M, h, h, w.eps, "fp32", n_max=w.N, max_weights=2 + Np, tprec="fp64")
+    Xd = to_dev(w.X, torch.float32)
+    Yd = to_dev(w.Y, torch.float32)
+    plan.set_points(Xd)
+    out = plan.cv(h, Yd, Np, seed=seed)
+    s2, vhat, kappa = plan.variance(h, Yd, out["mhat"][0, 0], mode="log")
+    mh = out["mhat"].cpu().numpy()[0, 0]
+    rho = out["rho"].cpu().numpy()[0]
+    gcv = out["gcv"].cpu().numpy()[0, 0]
+    vhat, kappa = vhat.cpu().numpy(), kappa.item()
+    X = w.X.astype(np.float32).astype(np.float64)
+    y = w.Y[:, 0].astype(np.float32).astype(np.float64)
+    P32 = orc.probes(seed, w.N, Np).astype(np.float32)
+    pf = plan.fit(h, torch.as_tensor(P32, device="cuda")).cpu().numpy()[0]     # [Np][M]
+    rng = np.random.default_rng(66)
+    flat = _sample_flat(rng, w.M, 120)
+    gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
+    fl = noise_floor(w.N, h, w.eps, "fp32", "fp64")
+    W = np.concatenate([y[:, None], P32.astype(np.float64)], axis=1)
+    ref, S, T, r0, ill = orc.fit(X, W, h, 1, gp, return_all=True, floor=fl)
+    m = density_mask(S[:, 0])
+    assert m.sum() > 100
+    nan_close(mh[flat], ref[:, 0], 1e-5, mask=m)
+    for p in range(Np):
+        nan_close(pf[p][flat], ref[:, 1 + p], 1e-5, mask=m)
+    # DF and GCV from the GPU grid fits, recomputed by the oracle
+    what = orc.interp(pf.T, w.M, w.lo, w.hi, X)
+    r_ref = orc.girard_ratios(P32.astype(np.float64), what)
+    nan_close(rho, r_ref, 1e-6, scale=1.0)
+    yhat = orc.interp(mh, w.M, w.lo, w.hi, X)
+    g_ref = orc.gcv(y, yhat, float(np.mean(rho)))[0]
+    assert abs(gcv / g_ref - 1) < 1e-6
+    # variance pass: v-hat against the oracle fit of log(r + 1/N) from the GPU mean grid
+    r = (y - yhat) ** 2
+    z = np.log(r + 1.0 / w.N)
+    v_ref = orc.fit(X, z, h, 1, gp, floor=fl)[:, 0]
+    nan_close(vhat[flat], v_ref, 1e-5, mask=m)
+    v_i = orc.interp(vhat, w.M, w.lo, w.hi, X)
+    kappa_ref = 1.0 / np.mean(r * np.exp(-v_i))
+    assert abs(kappa / kappa_ref - 1) < 1e-6
