@@ -23,7 +23,13 @@ on the launch stream; ``cpu_baseline`` times the FP64 oracle on a bounded
 sample of grid points and extrapolates to the full grid; ``accuracy`` compares
 the GPU grids with the oracle on that same sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--transform fp64|fp32]
+By default the timed steps replay a HIP graph captured from one step (the
+step's ~45 kernel launches are launch-bound on the host otherwise); before
+timing, three replays are compared with eager steps.  ``--eager`` times
+host-launched steps instead.  Stage times always come from eager steps, where
+the library brackets every launch with HIP events on the launch stream.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--transform fp64|fp32] [--eager]
 """
 from __future__ import annotations
 
@@ -51,8 +57,8 @@ def _args():
                     help="precision of the FFTs and moment channels (spreading is FP32)")
     ap.add_argument("--sigma", type=float, default=0.0,
                     help="oversampling of the spreading grid (0: the plan's default)")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture the step in a HIP graph and replay it (checked against eager steps)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every step's kernels from the host instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=1024,
                     help="grid points in the oracle's timed sample")
@@ -118,6 +124,7 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    args.graph = not args.eager
     if args.graph:
         # eager reference, then capture; every replay must reproduce it
         ref = step()
@@ -137,7 +144,12 @@ def main() -> int:
             torch.cuda.synchronize()
             got = [res_g[0]["mhat"], res_g[0]["rho"], res_g[0]["gcv"], res_g[1]]
             for a, b in zip(got, ref_vals):
-                if not torch.allclose(a, b, rtol=1e-6, atol=0, equal_nan=True):
+                # samples of one cell are ranked with LDS atomics, so the FP32
+                # summation order (and the last bits) may differ between runs
+                fin = torch.isfinite(b)
+                scale = b[fin].abs().max() if fin.any() else torch.tensor(0.0, device=b.device)
+                same_nan = torch.equal(torch.isnan(a), torch.isnan(b))
+                if not same_nan or (a[fin] - b[fin]).abs().max() > 1e-6 * scale:
                     print(json.dumps({"error": "graph replay differs from the eager step", "replay": rep}))
                     return 1
             step()                       # eager work between replays
@@ -181,7 +193,8 @@ def main() -> int:
     spread_ms, spread_n = stages["spread"]
     launches_per_step = spread_n / args.steps
     achieved = bytes_step * args.steps / (spread_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_spread", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": "spread: k_spread_wave (cv, 12 columns) + k_spread_group (variance, 2 columns)",
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": _traffic(launches_per_step),
                 "algorithmic_bytes_per_launch": bytes_step / launches_per_step,
