@@ -541,12 +541,15 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         r.np = Np; r.pfit = pfit;
         r.partial = partial;
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        const int nlaunch = std::max((q + kRedYCols - 1) / kRedYCols, (Np + kRedProbes - 1) / kRedProbes);
+        // probes per launch: at most kRedProbes, spread evenly over the launches
+        const int nlp = (Np + kRedProbes - 1) / kRedProbes;
+        const int pper = nlp > 0 ? (Np + nlp - 1) / nlp : 0;
+        const int nlaunch = std::max((q + kRedYCols - 1) / kRedYCols, nlp);
         for (int li = 0; li < nlaunch; ++li) {
             r.y0 = li * kRedYCols;
             r.ny_launch = std::max(0, std::min(kRedYCols, q - r.y0));
-            r.p0 = li * kRedProbes;
-            r.np_launch = std::max(0, std::min(kRedProbes, Np - r.p0));
+            r.p0 = li * pper;
+            r.np_launch = std::max(0, std::min(pper, Np - r.p0));
             launch_reduce_cv(g, r, s);
         }
         launch_reduce_final(partial, 2 * n_items, red, s);

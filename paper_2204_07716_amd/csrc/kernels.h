@@ -10,7 +10,7 @@ namespace fkr {
 constexpr int kMaxPairsPerSpread = 8;
 constexpr int kItemsPerGroup = 8;     // interpolation-reduction items per launch row
 constexpr int kRedBlocks = 1024;      // fixed grid of the two-stage reductions
-constexpr int kRedYCols = 4;          // response columns per fused cv reduction launch
+constexpr int kRedYCols = 1;          // response columns per fused cv reduction launch
 constexpr int kRedProbes = 16;        // probes per fused cv reduction launch
 constexpr int kSortChunk = 4096;      // samples per block in the binning kernels
 constexpr int kSortThreads = 1024;    // threads per binning block

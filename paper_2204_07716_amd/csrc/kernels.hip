@@ -2036,20 +2036,22 @@ void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* c
 void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void* out, hipStream_t s) {
     FftPass f = f0;
     const size_t csz = prec == FKR_F64 ? 16 : 8;
-    // rows per workgroup: enough workgroups to fill the chip first
+    // rows per workgroup: as many as the LDS holds, but enough workgroups to
+    // fill the chip first (256 threads share the rows)
     int R = 64;
     while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;
     while (R > 1 && f.rows < (int64_t)R * 1024) R >>= 1;
     f.rows_per_block = R;
     const size_t lds = (size_t)2 * R * f.F * csz;
     const unsigned nb = (unsigned)((f.rows + R - 1) / R);
+    const unsigned nt = 256;
     if (nb == 0) return;
     if (prec == FKR_F64) {
-        if (inverse) k_fft<double, true><<<nb, 256, lds, s>>>(static_cast<const double2*>(in), static_cast<double2*>(out), f);
-        else k_fft<double, false><<<nb, 256, lds, s>>>(static_cast<const double2*>(in), static_cast<double2*>(out), f);
+        if (inverse) k_fft<double, true><<<nb, nt, lds, s>>>(static_cast<const double2*>(in), static_cast<double2*>(out), f);
+        else k_fft<double, false><<<nb, nt, lds, s>>>(static_cast<const double2*>(in), static_cast<double2*>(out), f);
     } else {
-        if (inverse) k_fft<float, true><<<nb, 256, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
-        else k_fft<float, false><<<nb, 256, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
+        if (inverse) k_fft<float, true><<<nb, nt, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
+        else k_fft<float, false><<<nb, nt, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
     }
 }
 
@@ -2131,7 +2133,9 @@ void launch_reduce_cv(const Geo& g, const ReduceCvArgs& a, hipStream_t s) {
     // probes per launch rounded up to a compiled count
     if (a.np_launch <= 2) reduce_cv_pc<2>(g, a, s);
     else if (a.np_launch <= 4) reduce_cv_pc<4>(g, a, s);
+    else if (a.np_launch <= 6) reduce_cv_pc<6>(g, a, s);
     else if (a.np_launch <= 8) reduce_cv_pc<8>(g, a, s);
+    else if (a.np_launch <= 10) reduce_cv_pc<10>(g, a, s);
     else if (a.np_launch <= 12) reduce_cv_pc<12>(g, a, s);
     else reduce_cv_pc<16>(g, a, s);
 }
