@@ -1811,9 +1811,10 @@ void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_
 // kernel rows of U = 64 / (2W) consecutive samples are evaluated in one pass
 // (lane = sample, dimension, offset) and fetched with two cross-lane permutes
 // per sample.  Each wave takes a contiguous segment of the job; registers are
-// added into the FP64 LDS tile when the first footprint cell changes.
-template <int W, int KER, int NWMAX>
-__global__ __launch_bounds__(512) void k_spread_wave(Geo g, int np, const float* __restrict__ wrow, int wstride,
+// added into the FP64 LDS tile when the first footprint cell changes.  The
+// launch spreads exactly NW = 2 np weight columns (np <= 8 pairs).
+template <int W, int KER, int NW>
+__global__ __launch_bounds__(512) void k_spread_wave(Geo g, const float* __restrict__ wrow, int wstride,
                                                      int col0, const uint32_t* __restrict__ loc,
                                                      const float* __restrict__ frac, const int32_t* __restrict__ jobs,
                                                      float* __restrict__ subgrid) {
@@ -1822,9 +1823,9 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, int np, const float*
     constexpr int PSUB = PE * PE;
     constexpr int NWAVE = 512 / 64;
     constexpr int U = 64 / (2 * W);
-    constexpr int PPP = NWMAX / 2;
-    static_assert(W * W <= 64 && U >= 1, "footprint must fit a wave");
-    extern __shared__ double tile[];   // [NWMAX][PSUB]
+    constexpr int NP = NW / 2;
+    static_assert(W * W <= 64 && U >= 1 && NW % 2 == 0, "footprint must fit a wave");
+    extern __shared__ double tile[];   // [NW][PSUB]
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int dx = lane % W, dy = lane / W;
@@ -1837,105 +1838,98 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, int np, const float*
         const int n = jobs[4 + 4 * job + 2] - s_beg;
         const int seg = (n + NWAVE - 1) / NWAVE;
         const int q0 = min(n, wave * seg), q1 = min(n, q0 + seg);
-        for (int p0 = 0; p0 < np; p0 += PPP) {
-            const int nw = 2 * min(PPP, np - p0);
-            for (int c = threadIdx.x; c < nw * PSUB; c += blockDim.x) tile[c] = 0.0;
-            __syncthreads();
-            float acc[NWMAX];
+        for (int c = threadIdx.x; c < NW * PSUB; c += blockDim.x) tile[c] = 0.0;
+        __syncthreads();
+        float acc[NW];
 #pragma unroll
-            for (int k = 0; k < NWMAX; ++k) acc[k] = 0.f;
-            int cur = -1;
-            const float* wbase = wrow + col0 + 2 * p0;
-            auto flush_to = [&](int cb) {
-                if (cb == cur) return;
-                if (cur >= 0 && fp_lane) {
-                    const int cell = cur + dx + PE * dy;
-#pragma unroll
-                    for (int k = 0; k < NWMAX; k += 2) {
-                        if (k >= nw) break;
-                        atomicAdd(&tile[k * PSUB + cell], (double)acc[k]);
-                        atomicAdd(&tile[(k + 1) * PSUB + cell], (double)acc[k + 1]);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < NWMAX; ++k) acc[k] = 0.f;
-                cur = cb;
-            };
-            auto cell_of = [&](uint32_t l) { return (int)(l & 1023) + PE * (int)((l >> 10) & 1023); };
-            // One step = UU consecutive samples.  Every load of the step (first
-            // cells, fractions, weight rows) and every cross-lane permute is
-            // issued before the first FMA, so the step waits once: scalar loads
-            // return out of order and share the LDS counter, so any wait for a
-            // permute would otherwise also wait for loads issued after it.
-            // Columns past nw are never flushed (the rows have slack, so the
-            // loads stay in the workspace).
-            auto step = [&](const int t, auto UUc) {
-                constexpr int UU = decltype(UUc)::value;
-                const int su = s_beg + t + min(pu, UU - 1);
-                const float f = frac[(int64_t)su * 2 + pj];
-                uint32_t lu[UU];
-                float wv[UU][NWMAX];
-#pragma unroll
-                for (int u = 0; u < UU; ++u) {
-                    lu[u] = loc[s_beg + t + u];
-                    const float* wr = wbase + (int64_t)(s_beg + t + u) * wstride;
-#pragma unroll
-                    for (int k = 0; k < NWMAX; ++k) wv[u][k] = wr[k];
-                }
-                const float v = kernel_value<float, KER>((float)pk - f, W, kp);
-                float psi[UU];
-#pragma unroll
-                for (int u = 0; u < UU; ++u) {
-                    const float a = __shfl(v, 2 * W * u + dx);
-                    const float b = __shfl(v, 2 * W * u + W + min(dy, W - 1));
-                    psi[u] = fp_lane ? a * b : 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < UU; ++u) {
-                    flush_to(cell_of(lu[u]));
-#pragma unroll
-                    for (int k = 0; k < NWMAX; ++k) acc[k] += psi[u] * wv[u][k];
-                }
-            };
-            // samples per step: as many as the kernel-row pass covers, fewer when
-            // the weight rows of a step would not fit the scalar registers
-            constexpr int US = NWMAX <= 8 ? U : (NWMAX <= 12 ? (U < 4 ? U : 4) : (U < 3 ? U : 3));
-            int t = q0;
-            for (; t + US <= q1; t += US) step(t, std::integral_constant<int, US>{});
-            for (; t < q1; ++t) step(t, std::integral_constant<int, 1>{});
+        for (int k = 0; k < NW; ++k) acc[k] = 0.f;
+        int cur = -1;
+        auto flush_to = [&](int cb) {
+            if (cb == cur) return;
             if (cur >= 0 && fp_lane) {
                 const int cell = cur + dx + PE * dy;
 #pragma unroll
-                for (int k = 0; k < NWMAX; k += 2) {
-                    if (k >= nw) break;
-                    atomicAdd(&tile[k * PSUB + cell], (double)acc[k]);
-                    atomicAdd(&tile[(k + 1) * PSUB + cell], (double)acc[k + 1]);
-                }
+                for (int k = 0; k < NW; ++k) atomicAdd(&tile[k * PSUB + cell], (double)acc[k]);
             }
-            __syncthreads();
-            // subgrid layout [job][pair][cell][re, im]
-            for (int q = 0; 2 * q < nw; ++q) {
-                float* dst = subgrid + ((int64_t)job * np + p0 + q) * PSUB * 2;
-                for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
-                    dst[2 * c] = (float)tile[2 * q * PSUB + c];
-                    dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
-                }
+#pragma unroll
+            for (int k = 0; k < NW; ++k) acc[k] = 0.f;
+            cur = cb;
+        };
+        auto cell_of = [&](uint32_t l) { return (int)(l & 1023) + PE * (int)((l >> 10) & 1023); };
+        // weight rows and records of the wave's segment, advanced per step
+        const float* wp = wrow + col0 + (int64_t)(s_beg + q0) * wstride;
+        const uint32_t* lp = loc + s_beg + q0;
+        const float* fp = frac + 2 * (int64_t)(s_beg + q0);
+        // One step = UU consecutive samples.  Every load of the step (first
+        // cells, fractions, weight rows) and every cross-lane permute is
+        // issued before the first FMA, so the step waits once: scalar loads
+        // return out of order and share the LDS counter, so any wait for a
+        // permute would otherwise also wait for loads issued after it.
+        auto step = [&](auto UUc) {
+            constexpr int UU = decltype(UUc)::value;
+            const float f = fp[2 * min(pu, UU - 1) + pj];
+            uint32_t lu[UU];
+            float wv[UU][NW];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                lu[u] = lp[u];
+                const float* wr = wp + u * wstride;
+#pragma unroll
+                for (int k = 0; k < NW; ++k) wv[u][k] = wr[k];
             }
-            __syncthreads();
+            const float v = kernel_value<float, KER>((float)pk - f, W, kp);
+            float psi[UU];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const float a = __shfl(v, 2 * W * u + dx);
+                const float b = __shfl(v, 2 * W * u + W + min(dy, W - 1));
+                psi[u] = fp_lane ? a * b : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                flush_to(cell_of(lu[u]));
+#pragma unroll
+                for (int k = 0; k < NW; ++k) acc[k] += psi[u] * wv[u][k];
+            }
+            wp += UU * wstride;
+            lp += UU;
+            fp += 2 * UU;
+        };
+        // samples per step: as many as the kernel-row pass covers, fewer when
+        // the weight rows of a step would not fit the scalar registers
+        constexpr int US = NW <= 8 ? U : (NW <= 12 ? (U < 4 ? U : 4) : (U < 3 ? U : 3));
+        int t = q0;
+        for (; t + US <= q1; t += US) step(std::integral_constant<int, US>{});
+        for (; t < q1; ++t) step(std::integral_constant<int, 1>{});
+        if (cur >= 0 && fp_lane) {
+            const int cell = cur + dx + PE * dy;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) atomicAdd(&tile[k * PSUB + cell], (double)acc[k]);
         }
+        __syncthreads();
+        // subgrid layout [job][pair][cell][re, im]
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            float* dst = subgrid + ((int64_t)job * NP + q) * PSUB * 2;
+            for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
+                dst[2 * c] = (float)tile[2 * q * PSUB + c];
+                dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
+            }
+        }
+        __syncthreads();
     }
 }
 
-template <int W, int KER, int NWMAX>
+template <int W, int KER, int NW>
 static void spread_wave(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
                         const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
     constexpr int TS = spread_tile_edge(2, W);
     constexpr int PE = TS + W - 1;
-    const size_t lds = (size_t)NWMAX * PE * PE * sizeof(double);
-    k_spread_wave<W, KER, NWMAX><<<nb, 512, lds, s>>>(g, src.npairs, static_cast<const float*>(src.w[0].ptr),
-                                                       (int)src.w[0].stride, (int)src.w[0].col, loc,
-                                                       static_cast<const float*>(frac), jobs,
-                                                       static_cast<float*>(subgrid));
+    const size_t lds = (size_t)NW * PE * PE * sizeof(double);
+    k_spread_wave<W, KER, NW><<<nb, 512, lds, s>>>(g, static_cast<const float*>(src.w[0].ptr),
+                                                   (int)src.w[0].stride, (int)src.w[0].col, loc,
+                                                   static_cast<const float*>(frac), jobs,
+                                                   static_cast<float*>(subgrid));
 }
 
 template <int D, int W, typename T, int KER, int NWMAX>
@@ -1973,10 +1967,15 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
                 if constexpr (D == 2 && W <= 8) {
                     // few weight columns: the lane-group kernel (3 samples per
                     // wave step) wins; many: the one-sample-per-wave kernel
-                    if (nw <= 4) spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
-                    else if (nw <= 8) spread_wave<W, KER, 8>(g, src, loc, frac, jobs, nb, subgrid, s);
-                    else if (nw <= 12) spread_wave<W, KER, 12>(g, src, loc, frac, jobs, nb, subgrid, s);
-                    else spread_wave<W, KER, 16>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    switch (nw) {
+                        case 2: case 4: spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 6: spread_wave<W, KER, 6>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 8: spread_wave<W, KER, 8>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 10: spread_wave<W, KER, 10>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 12: spread_wave<W, KER, 12>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 14: spread_wave<W, KER, 14>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        default: spread_wave<W, KER, 16>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                    }
                     return;
                 }
                 if constexpr (D == 3) {
