@@ -17,9 +17,9 @@ synthetic.  One step is one pass of the whole path:
 The headline value is samples/s = N x fits / step time, where a fit is one
 weight vector through spread + FFT + solve (1 response + 10 probes + 1
 variance pass = 12 per step).  The ``roofline`` object reports the spreading
-kernel (the largest single kernel of the step) against HBM bandwidth with its
-algorithmic bytes per launch, timed with HIP events that the library records
-on the launch stream; ``cpu_baseline`` times the FP64 oracle on a bounded
+kernel (the largest single kernel of the step) against FP32 FMA issue with its
+algorithmic flops per launch, and against HBM bandwidth with its algorithmic
+bytes, timed with HIP events that the library records on the launch stream; ``cpu_baseline`` times the FP64 oracle on a bounded
 sample of grid points and extrapolates to the full grid; ``accuracy`` compares
 the GPU grids with the oracle on that same sample.
 
@@ -44,6 +44,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA issue: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (no packed FP32)
+FP32_FMA_PEAK_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "k_spread_ll2d_counters.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_07716_amd", "csrc", "kernels.hip")
 
@@ -60,7 +62,7 @@ def _args():
     ap.add_argument("--eager", action="store_true",
                     help="launch every step's kernels from the host instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=1024,
+    ap.add_argument("--cpu-points", type=int, default=4096,
                     help="grid points in the oracle's timed sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (counter calibration)")
@@ -184,22 +186,31 @@ def main() -> int:
     n_fits = (1 + Np) + 1
     value = N * n_fits / (ms_per_step * 1e-3)
 
-    # Roofline of the spreading kernel: algorithmic bytes (positions and
-    # weights read once, the oversampled grid written once per weight pair).
+    # Roofline of the spreading kernel.  Its arithmetic is 2 W^d n_w flops per
+    # sample (one FMA per footprint cell and weight column) against N (d b_x +
+    # n_w b_w) + n_pair Mr^d b_c algorithmic bytes: about 13 flop/B for the
+    # step's two launches, above the 9.8 flop/B ridge of FP32 FMA issue
+    # (78.6 TFLOP/s) over HBM (8 TB/s), so the bound is the ALU.
     Mr2 = g.Mr[0] * g.Mr[1]
     bx, bw, bc = 4, 4, 8
     nw_launch = [2 + Np, 2]              # cv (density, y, probes), variance (density, z)
     bytes_step = sum(N * (2 * bx + nw * bw) + ((nw + 1) // 2) * Mr2 * bc for nw in nw_launch)
+    flops_step = sum(2.0 * N * g.w ** 2 * nw for nw in nw_launch)
     spread_ms, spread_n = stages["spread"]
     launches_per_step = spread_n / args.steps
-    achieved = bytes_step * args.steps / (spread_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "spread: k_spread_wave (cv, 12 columns) + k_spread_group (variance, 2 columns)",
-                "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    spread_s = spread_ms * 1e-3 / args.steps
+    achieved = flops_step / spread_s / 1e12
+    hbm_achieved = bytes_step / spread_s / 1e9
+    roofline = {"bound": "alu", "kernel": "spread: k_spread_wave (cv, 12 columns) + k_spread_group (variance, 2 columns)",
+                "achieved": round(achieved, 2), "peak": FP32_FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_FMA_PEAK_TFLOPS, 4),
                 "traffic": _traffic(launches_per_step),
+                "algorithmic_flops_per_launch": flops_step / launches_per_step,
                 "algorithmic_bytes_per_launch": bytes_step / launches_per_step,
                 "avg_launch_us": round(spread_ms * 1e3 / max(spread_n, 1), 2),
-                "launches_per_step": launches_per_step}
+                "launches_per_step": launches_per_step,
+                "hbm": {"achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}}
 
     out, s2, vhat, kappa = res
     line = {
