@@ -249,7 +249,7 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
         diag[4] = smax[1023];
     }
     __syncthreads();
-    // job table entries: (tile, start, end, 0) at jobs[4 + 4 * job]
+    // job table entries: (tile, start, end, order) at jobs[4 + 4 * job]
     for (int64_t k = t; k < n_tiles; k += 1024) {
         const int64_t c = counts[k];
         const int64_t nj = (c + chunk - 1) / chunk;
@@ -259,10 +259,30 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
             e[0] = (int32_t)k;
             e[1] = (int32_t)(s0 + q * chunk);
             e[2] = (int32_t)min<int64_t>(s0 + (q + 1) * chunk, s0 + c);
-            e[3] = 0;
         }
         cursor[k] = 0;
     }
+    // Processing order (field 3 of entry b = the job that workgroup b of a
+    // spread takes): jobs bucketed by size, largest first, so the workgroups
+    // that the dispatcher hands out last are the short ones.  The order
+    // within a bucket is arbitrary; every job writes its own subgrid.
+    __shared__ int32_t bcnt[8];
+    if (t < 8) bcnt[t] = 0;
+    __syncthreads();
+    const int nj_all = (int)sb[1023];
+    auto bucket = [&](int j) {
+        const int32_t* e = jobs + 4 + 4 * j;
+        const int sz = e[2] - e[1];
+        return min(7, (int)(((int64_t)(chunk - sz) * 8) / chunk));
+    };
+    for (int j = t; j < nj_all; j += 1024) atomicAdd(&bcnt[bucket(j)], 1);
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int b = 0; b < 8; ++b) { const int c = bcnt[b]; bcnt[b] = run; run += c; }
+    }
+    __syncthreads();
+    for (int j = t; j < nj_all; j += 1024) jobs[4 + 4 * atomicAdd(&bcnt[bucket(j)], 1) + 3] = j;
 }
 
 // Tile-ordered sample record: original index, packed first cell relative to
@@ -522,7 +542,8 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Geo g, SpreadSrc src, c
     const T kp = (T)g.kparam;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int segid = lane * NWAVE + wave;
-    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+    for (int b = blockIdx.x; b < njobs; b += gridDim.x) {
+        const int job = jobs[4 + 4 * b + 3];
         const int32_t* jd = jobs + 4 + 4 * job;
         const int s_beg = jd[1];
         const int n = jd[2] - jd[1];
@@ -794,7 +815,8 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_group(Geo g, int np, co
     const int lseg = threadIdx.x / CS, lk = threadIdx.x - lseg * CS;
     const bool loader = threadIdx.x < NS;
     const int njobs = jobs[0];
-    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+    for (int b = blockIdx.x; b < njobs; b += gridDim.x) {
+        const int job = jobs[4 + 4 * b + 3];
         const int32_t* jd = jobs + 4 + 4 * job;
         const int s_beg = jd[1];
         const int n = jd[2] - jd[1];
@@ -1833,7 +1855,8 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, const float* __restr
     const int pu = lane / (2 * W), pj = (lane / W) & 1, pk = lane % W;
     const float kp = (float)g.kparam;
     const int njobs = jobs[0];
-    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+    for (int b = blockIdx.x; b < njobs; b += gridDim.x) {
+        const int job = jobs[4 + 4 * b + 3];
         const int s_beg = jobs[4 + 4 * job + 1];
         const int n = jobs[4 + 4 * job + 2] - s_beg;
         const int seg = (n + NWAVE - 1) / NWAVE;
