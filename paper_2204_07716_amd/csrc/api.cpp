@@ -520,7 +520,11 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
     const int nr = (int)srcs.size();
     double* internal = at<double>(p, p->lay.mhat);
-    double* pfit = internal + (int64_t)ny * p->Mtot;
+    // probe fits [M][pstride] in the spreading precision (they only feed the
+    // DF reduction), 16-byte aligned rows for FP32
+    const bool pf32 = p->prec == FKR_F32;
+    const int pstride = pf32 ? (Np + 3) & ~3 : Np;
+    void* pfit = p->ws + p->lay.mhat + (((size_t)ny * p->Mtot * 8 + 15) & ~(size_t)15);
     double* red = at<double>(p, p->lay.red);
     double* partial = at<double>(p, p->lay.partial);
     const int n_items = q + Np;
@@ -530,6 +534,8 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
         a.y_out = yfit;
         a.probe_out = pfit;
+        a.probe_f32 = pf32 ? 1 : 0;
+        a.probe_stride = pstride;
         {
             StageTimer t(p, FKR_STAGE_SOLVE, s);
             launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
@@ -538,7 +544,7 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
         r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
         r.ny_cols = q; r.y_cplx = y_complex; r.yfit = yfit;
-        r.np = Np; r.pfit = pfit;
+        r.np = Np; r.pfit = pfit; r.pstride = pstride;
         r.partial = partial;
         StageTimer t(p, FKR_STAGE_REDUCE, s);
         // probes per launch: at most kRedProbes, spread evenly over the launches

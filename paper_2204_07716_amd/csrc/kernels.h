@@ -8,7 +8,6 @@
 namespace fkr {
 
 constexpr int kMaxPairsPerSpread = 8;
-constexpr int kItemsPerGroup = 8;     // interpolation-reduction items per launch row
 constexpr int kRedBlocks = 1024;      // fixed grid of the two-stage reductions
 constexpr int kRedYCols = 1;          // response columns per fused cv reduction launch
 constexpr int kRedProbes = 16;        // probes per fused cv reduction launch
@@ -75,7 +74,8 @@ struct SolveArgs {
     int64_t Mtot;
     double s0_floor;               // absolute floor for every Cholesky pivot (s_0 first)
     double* y_out;                 // [q][M][(2)] per bandwidth (may be null)
-    double* probe_out;             // [M][nr-1-ny] (may be null)
+    void* probe_out;               // [M][probe_stride], FP32 or FP64 (may be null)
+    int probe_f32, probe_stride;
     double* s0_out;                // [M] (may be null)
     unsigned long long* ill_count;
 };
@@ -89,24 +89,11 @@ struct ReduceCvArgs {
     int ny_cols, y_cplx;          // response columns (complex: re, im parts)
     const double* yfit;           // [q][M] or [q][M][2]
     int np;                       // probes
-    const double* pfit;           // [M][np]
+    const void* pfit;             // [M][pstride], element type w_type
+    int pstride;
     int y0, ny_launch;            // response columns of this launch (<= kRedYCols)
     int p0, np_launch;            // probes of this launch (<= kRedProbes)
     double* partial;              // [slot][kRedBlocks]; items: y columns, then probes
-};
-
-struct ReduceItemArgs {
-    int d;
-    int n_items, ny_cols, y_cplx; // items: y columns first, then probes
-    int64_t N;
-    int x_type;                   // element type of the sorted coordinates
-    const void* X;                // sorted coordinates [N][d]
-    const void* wsorted;          // staged weights [N][nr] in sorted order
-    int w_type, wstride;          // their element type and row stride (column 0 = density)
-    const double* yfit;           // [q][M] or [q][M][2]
-    const double* pfit;           // [Np][M]
-    int item0;                    // first item of this launch
-    double* partial;              // [slot][kRedBlocks]
 };
 
 void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, int32_t* bhist,
@@ -134,7 +121,6 @@ void launch_unpack_spec(int prec, int64_t Btot, const int64_t* B, int d, int npa
                         const void* spec, double* out, hipStream_t s);
 void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, const void* chan,
                      double* S, double* T, hipStream_t s);
-void launch_reduce_items(const Geo& g, const ReduceItemArgs& a, int nslots, hipStream_t s);
 void launch_reduce_cv(const Geo& g, const ReduceCvArgs& a, hipStream_t s);
 void launch_reduce_final(const double* partial, int nslots, double* out, hipStream_t s);
 void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void* X,

@@ -1327,7 +1327,9 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
                 a.y_out[(col * a.Mtot + k) * cpl + part] = m;
             }
         } else if (a.probe_out) {
-            a.probe_out[k * (a.nr - 1 - a.ny) + (r - 1 - a.ny)] = m;
+            const int64_t o = k * a.probe_stride + (r - 1 - a.ny);
+            if (a.probe_f32) static_cast<float*>(a.probe_out)[o] = (float)m;
+            else static_cast<double*>(a.probe_out)[o] = m;
         }
     }
 }
@@ -1404,63 +1406,6 @@ __device__ __forceinline__ void block_sum(double (&acc)[NA], double* sh) {
     for (int q = 0; q < NA; ++q) acc[q] = sh[q * 256];
 }
 
-// Items: y columns (slot 2 it: sum |y - yhat|^2) and probes
-// (slots 2 it, 2 it + 1: sum w^2, sum w * w_hat).
-template <int D>
-__global__ __launch_bounds__(256) void k_reduce_items(Geo g, ReduceItemArgs a) {
-    __shared__ double sh[2 * kItemsPerGroup * 256];
-    double acc[2 * kItemsPerGroup];
-#pragma unroll
-    for (int q = 0; q < 2 * kItemsPerGroup; ++q) acc[q] = 0.0;
-    const int it0 = a.item0 + blockIdx.y * kItemsPerGroup;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
-#pragma unroll
-        for (int it = 0; it < kItemsPerGroup; ++it) {
-            const int item = it0 + it;
-            if (item >= a.n_items) break;
-            const int64_t row = s * a.wstride;
-            if (item < a.ny_cols) {
-                if (a.y_cplx) {
-                    double fr = 0.0, fi = 0.0;
-                    const double* gv = a.yfit + (int64_t)item * g.Mtot * 2;
-#pragma unroll
-                    for (int q = 0; q < (1 << D); ++q) { fr += c.w[q] * gv[2 * c.idx[q]]; fi += c.w[q] * gv[2 * c.idx[q] + 1]; }
-                    const double yr = load_as_double(a.wsorted, a.w_type, row + 1 + 2 * item);
-                    const double yi = load_as_double(a.wsorted, a.w_type, row + 2 + 2 * item);
-                    acc[2 * it] += (yr - fr) * (yr - fr) + (yi - fi) * (yi - fi);
-                } else {
-                    double f = 0.0;
-                    const double* gv = a.yfit + (int64_t)item * g.Mtot;
-#pragma unroll
-                    for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
-                    const double y = load_as_double(a.wsorted, a.w_type, row + 1 + item);
-                    acc[2 * it] += (y - f) * (y - f);
-                }
-            } else {
-                const int ycols = a.ny_cols * (a.y_cplx ? 2 : 1);
-                const double wv = load_as_double(a.wsorted, a.w_type, row + 1 + ycols + (item - a.ny_cols));
-                const double* gv = a.pfit + (int64_t)(item - a.ny_cols) * g.Mtot;
-                double f = 0.0;
-#pragma unroll
-                for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
-                acc[2 * it] += wv * wv;
-                acc[2 * it + 1] += wv * f;
-            }
-        }
-    }
-    block_sum<2 * kItemsPerGroup>(acc, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int it = 0; it < kItemsPerGroup; ++it) {
-            const int item = it0 + it;
-            if (item >= a.n_items) break;
-            a.partial[(int64_t)(2 * item) * kRedBlocks + blockIdx.x] = acc[2 * it];
-            a.partial[(int64_t)(2 * item + 1) * kRedBlocks + blockIdx.x] = acc[2 * it + 1];
-        }
-    }
-}
 
 // Fused interpolation and cv sums over the samples in sorted order: for the
 // response columns of the launch sum |y - yhat|^2 (eq. 22), for its probes
@@ -1511,12 +1456,31 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
             double fh[PC];
 #pragma unroll
             for (int j = 0; j < PC; ++j) fh[j] = 0.0;
-            if (PC % 2 == 0 && (a.np_launch % 2) == 0 && (a.np % 2) == 0 && (a.p0 % 2) == 0) {
-                // 16-byte loads (rows are 16-byte aligned)
+            const TW* pf = static_cast<const TW*>(a.pfit);
+            // fits of the probes beyond np_launch (row padding included) land
+            // in fh[j >= np_launch], which is never written out
+            if (sizeof(TW) == 4 && (a.pstride % 4) == 0 && (a.p0 % 4) == 0) {
+                // FP32 rows padded to 16 bytes: float4 loads
+                const int last = (a.np_launch + 3) / 4 - 1;
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) {
+                    const float4* gv = reinterpret_cast<const float4*>(pf + c.idx[q] * a.pstride + a.p0);
+#pragma unroll
+                    for (int j = 0; j < (PC + 3) / 4; ++j) {
+                        const float4 v4 = gv[min(j, last)];
+                        const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (4 * j + e < PC) fh[4 * j + e] += c.w[q] * (double)vv[e];
+                    }
+                }
+            } else if (sizeof(TW) == 8 && PC % 2 == 0 && (a.np_launch % 2) == 0 && (a.pstride % 2) == 0 &&
+                       (a.p0 % 2) == 0) {
+                // FP64 rows: 16-byte loads
                 const int last = a.np_launch / 2 - 1;
 #pragma unroll
                 for (int q = 0; q < (1 << D); ++q) {
-                    const double2* gv = reinterpret_cast<const double2*>(a.pfit + c.idx[q] * a.np + a.p0);
+                    const double2* gv = reinterpret_cast<const double2*>(pf + c.idx[q] * a.pstride + a.p0);
 #pragma unroll
                     for (int j = 0; j < PC / 2; ++j) {
                         const double2 v2 = gv[min(j, last)];
@@ -1527,9 +1491,9 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
             } else {
 #pragma unroll
                 for (int q = 0; q < (1 << D); ++q) {
-                    const double* gv = a.pfit + c.idx[q] * a.np + a.p0;
+                    const TW* gv = pf + c.idx[q] * a.pstride + a.p0;
 #pragma unroll
-                    for (int j = 0; j < PC; ++j) fh[j] += c.w[q] * gv[min(j, a.np_launch - 1)];
+                    for (int j = 0; j < PC; ++j) fh[j] += c.w[q] * (double)gv[min(j, a.np_launch - 1)];
                 }
             }
 #pragma unroll
@@ -2129,15 +2093,6 @@ void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, 
         k_chan_out<double><<<nblk(n), 256, 0, s>>>(Mtot, ncp, n_s, n_t, nw, static_cast<const double*>(chan), S, T);
     else
         k_chan_out<float><<<nblk(n), 256, 0, s>>>(Mtot, ncp, n_s, n_t, nw, static_cast<const float*>(chan), S, T);
-}
-
-void launch_reduce_items(const Geo& g, const ReduceItemArgs& a, int ngroups, hipStream_t s) {
-    dim3 grid(kRedBlocks, (unsigned)ngroups);
-    switch (g.d) {
-        case 1: k_reduce_items<1><<<grid, 256, 0, s>>>(g, a); break;
-        case 2: k_reduce_items<2><<<grid, 256, 0, s>>>(g, a); break;
-        default: k_reduce_items<3><<<grid, 256, 0, s>>>(g, a); break;
-    }
 }
 
 template <int PC>
