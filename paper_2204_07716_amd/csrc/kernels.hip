@@ -2022,11 +2022,15 @@ void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* c
 void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void* out, hipStream_t s) {
     FftPass f = f0;
     const size_t csz = prec == FKR_F64 ? 16 : 8;
-    // rows per workgroup: as many as the LDS holds, but enough workgroups to
-    // fill the chip first (256 threads share the rows)
-    int R = 64;
+    // rows per workgroup (256 threads share them).  More rows lengthen the
+    // runs of the transposed stores but cost occupancy (two LDS buffers per
+    // row).  Measured: up to 8192 rows (2-D grids) at most two rows per
+    // workgroup, with 512 workgroups first; beyond (3-D grids) as many rows
+    // as the LDS holds, with 1024 workgroups first.
+    const bool many = f.rows > 8192;
+    int R = many ? 64 : 2;
     while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;
-    while (R > 1 && f.rows < (int64_t)R * 1024) R >>= 1;
+    while (R > 1 && f.rows < (int64_t)R * (many ? 1024 : 512)) R >>= 1;
     f.rows_per_block = R;
     const size_t lds = (size_t)2 * R * f.F * csz;
     const unsigned nb = (unsigned)((f.rows + R - 1) / R);
