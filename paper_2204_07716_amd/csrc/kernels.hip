@@ -999,6 +999,66 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
     const int n1 = D > 1 ? cv[1][0] : 1;
     const int n2 = D > 2 ? cv[2][0] : 1;
     double re = 0.0, im = 0.0;
+    if (n0 <= 2 && n1 <= 2 && n2 <= 2) {
+        // Common case, at most two covering tiles per dimension: every job
+        // offset, then every first-job subgrid value, is loaded before any is
+        // used, so the chain is cover -> job offsets -> subgrids (a dense
+        // tile's further jobs follow).  Same summation order as below.
+        constexpr int NT = 1 << D;
+        int64_t tl[NT], of[NT];
+        bool ok[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const int a0 = k & 1, a1 = (k >> 1) & 1, a2 = (k >> 2) & 1;
+            ok[k] = a0 < n0 && (D < 2 || a1 < n1) && (D < 3 || a2 < n2);
+            int64_t tile = 0, off = 0;
+            if (ok[k]) {
+                tile = cv[0][1 + 2 * a0];
+                off = cv[0][2 + 2 * a0];
+                if (D > 1) {
+                    tile += g.nt[0] * cv[1][1 + 2 * a1];
+                    off += g.pe[0] * cv[1][2 + 2 * a1];
+                }
+                if (D > 2) {
+                    tile += g.nt[0] * g.nt[1] * cv[2][1 + 2 * a2];
+                    off += g.pe[0] * g.pe[1] * cv[2][2 + 2 * a2];
+                }
+            }
+            tl[k] = tile;
+            of[k] = off;
+        }
+        int j0[NT], j1[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            j0[k] = ok[k] ? job_off[tl[k]] : 0;
+            j1[k] = ok[k] ? job_off[tl[k] + 1] : 0;
+        }
+        T fr[NT], fi[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            fr[k] = fi[k] = (T)0;
+            if (j0[k] < j1[k]) {
+                const T* sg = subgrid + (int64_t)j0[k] * lsize + (p * g.Psub + of[k]) * 2;
+                fr[k] = sg[0];
+                fi[k] = sg[1];
+            }
+        }
+        // loop order a2 > a1 > a0, as below
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (j0[k] >= j1[k]) continue;
+            re += (double)fr[k];
+            im += (double)fi[k];
+            const T* sg = subgrid + (int64_t)(j0[k] + 1) * lsize + (p * g.Psub + of[k]) * 2;
+            for (int jj = j0[k] + 1; jj < j1[k]; ++jj, sg += lsize) {
+                re += (double)sg[0];
+                im += (double)sg[1];
+            }
+        }
+        fine[idx * 2] = (TO)re;
+        fine[idx * 2 + 1] = (TO)im;
+        return;
+    }
     for (int a2 = 0; a2 < n2; ++a2)
         for (int a1 = 0; a1 < n1; ++a1)
             for (int a0 = 0; a0 < n0; ++a0) {
