@@ -403,13 +403,14 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
     StageTimer t(p, FKR_STAGE_SORT, s);
-    launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
-    launch_zero(p->ws + p->lay.diag, 16 * 8, s);
+    // the tile counts need clearing only where the binning adds to them with
+    // global atomics (more tiles than the LDS histogram holds) or does not run
+    if (p->n_tiles > kLdsHistMax || N == 0) launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
     launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.bhist),
-                     at<long long>(p, p->lay.diag), s);
-    launch_scan(g, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
+                     at<int32_t>(p, p->lay.obuf), s);
+    launch_scan(g, N, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
                 at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.cursor),
-                at<long long>(p, p->lay.diag), s);
+                at<long long>(p, p->lay.diag), at<int32_t>(p, p->lay.obuf), s);
     launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_off),
                       at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.cursor), at<int32_t>(p, p->lay.jobs),
                       at<int32_t>(p, p->lay.bhist), p->ws + p->lay.trec, at<int32_t>(p, p->lay.cnt), at<int32_t>(p, p->lay.coff),
@@ -447,7 +448,7 @@ fkr_status fkr_moments(fkr_plan* p, int nh, const double* h, int nw, const void*
     for (int r = 0; r < nw; ++r) srcs.push_back(src_array(W, w_type, nw, r));
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
     const Geo g = make_geo(p);
-    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), nullptr, s);
     const int nr = 1 + nw;
     const int ncp = (p->n_s + p->n_t * nw + 1) / 2;
     for (int hi = 0; hi < nh; ++hi) {
@@ -470,10 +471,10 @@ fkr_status fkr_fit(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
     const hipStream_t s = S(stream);
     std::vector<WSrc> srcs{src_one()};
     add_response_sources(&srcs, q, y_complex, Y, y_type);
-    launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
     const Geo g = make_geo(p);
-    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult),
+                       at<unsigned long long>(p, p->lay.diag + 2 * 8), s);
     const int nr = (int)srcs.size();
     for (int hi = 0; hi < nh; ++hi) {
         if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
@@ -514,10 +515,10 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     std::vector<WSrc> srcs{src_one()};
     add_response_sources(&srcs, q, y_complex, Y, y_type);
     add_probe_sources(&srcs, Np, seed, probes, ptype);
-    launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
     const Geo g = make_geo(p);
-    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult),
+                       at<unsigned long long>(p, p->lay.diag + 2 * 8), s);
     const int nr = (int)srcs.size();
     double* internal = at<double>(p, p->lay.mhat);
     // probe fits [M][pstride] in the spreading precision (they only feed the
@@ -587,7 +588,6 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
     double* wbuf = at<double>(p, p->lay.wbuf);
-    launch_zero(p->ws + p->lay.diag + 2 * 8, 8, s);
     {
         StageTimer t(p, FKR_STAGE_REDUCE, s);
         launch_resid(g, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
@@ -597,7 +597,8 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     z.kind = W_SORTED; z.type = FKR_F64; z.ptr = wbuf; z.stride = 1; z.col = 0;
     std::vector<WSrc> srcs{src_one(), z};
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
-    launch_mult_tables(g, p->order, 1, h, dev_periods(p), at<double>(p, p->lay.mult), s);
+    launch_mult_tables(g, p->order, 1, h, dev_periods(p), at<double>(p, p->lay.mult),
+                       at<unsigned long long>(p, p->lay.diag + 2 * 8), s);
     if ((st = run_channels(p, 0, 2, s)) != FKR_OK) return st;
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
@@ -609,9 +610,9 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     if (mode == FKR_VAR_LOG) {
         StageTimer t(p, FKR_STAGE_REDUCE, s);
         double* partial = at<double>(p, p->lay.partial);
-        double* red = at<double>(p, p->lay.red);
         launch_kappa_partial(g, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), v,
                              wbuf + p->N, partial, s);
+        double* red = at<double>(p, p->lay.red);
         launch_reduce_final(partial, 1, red, s);
         launch_sigma2(p->Mtot, p->N, v, red, sigma2, kappa, s);
     }

@@ -97,9 +97,9 @@ struct ReduceCvArgs {
 };
 
 void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, int32_t* bhist,
-                      long long* diag, hipStream_t s);
-void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
-                 int32_t* cursor, long long* diag, hipStream_t s);
+                      int32_t* obuf, hipStream_t s);
+void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
+                 int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s);
 void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
                        const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
                        const int32_t* bhist, void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
@@ -112,8 +112,9 @@ void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* c
                  const void* subgrid, void* fine, hipStream_t s);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
+// also clears *ill_clear (when given): the ill-posed counter of the call's solves
 void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, const double* T,
-                        double* mult, hipStream_t s);
+                        double* mult, unsigned long long* ill_clear, hipStream_t s);
 void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
                     void* out, hipStream_t s);
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);

@@ -158,7 +158,7 @@ __device__ __forceinline__ Binned bin_sample(const Geo& g, int x_type, const voi
 // Tile histogram: per-block LDS counts, then one global add per touched tile.
 template <int D>
 __global__ __launch_bounds__(kSortThreads) void k_bin_count(Geo g, int x_type, const void* X, int64_t N,
-                                                   int32_t* counts, int32_t* bhist, long long* diag) {
+                                                   int32_t* counts, int32_t* bhist, int32_t* obuf) {
     extern __shared__ int32_t hist[];   // n_tiles entries when use_lds
     const bool use_lds = g.n_tiles <= kLdsHistMax;
     if (use_lds)
@@ -166,15 +166,19 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(Geo g, int x_type, c
     __syncthreads();
     const int64_t beg = (int64_t)blockIdx.x * kSortChunk;
     const int64_t end = min<int64_t>(N, beg + kSortChunk);
-    unsigned long long outside = 0;
+    __shared__ int32_t n_out;
+    if (threadIdx.x == 0) n_out = 0;
+    __syncthreads();
+    int outside = 0;
     for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
         Binned b = bin_sample<D>(g, x_type, X, i);
         if (use_lds) atomicAdd(&hist[b.tile], 1);
         else atomicAdd(&counts[b.tile], 1);
-        outside += b.outside ? 1ull : 0ull;
+        outside += b.outside ? 1 : 0;
     }
-    if (outside) atomicAdd((unsigned long long*)&diag[1], outside);
+    if (outside) atomicAdd(&n_out, outside);
     __syncthreads();
+    if (threadIdx.x == 0) obuf[blockIdx.x] = n_out;   // summed by k_scan (no clearing needed)
     if (use_lds)   // this block's row of the block x tile count matrix (no atomics)
         for (int64_t t = threadIdx.x; t < g.n_tiles; t += blockDim.x)
             bhist[(int64_t)blockIdx.x * g.n_tiles + t] = hist[t];
@@ -211,7 +215,8 @@ __global__ __launch_bounds__(256) void k_tile_prefix(int64_t n_tiles, int nblock
 // writes tile_off, job_off, the job table and resets the scatter cursors.
 __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32_t* counts,
                                                int32_t* tile_off, int32_t* job_off, int32_t* jobs,
-                                               int32_t* cursor, long long* diag) {
+                                               int32_t* cursor, long long* diag, const int32_t* obuf,
+                                               int nbins) {
     __shared__ int64_t sa[1024], sb[1024];
     __shared__ int64_t smax[1024];
     const int t = threadIdx.x;
@@ -240,6 +245,16 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
         job_off[k] = (int32_t)rb;
         ra += c;
         rb += (c + chunk - 1) / chunk;
+    }
+    {   // samples outside [lo, hi]: sum of the binning pass's per-block counts
+        __shared__ unsigned long long n_out;
+        if (t == 0) n_out = 0;
+        __syncthreads();
+        unsigned long long o = 0;
+        for (int b = t; b < nbins; b += 1024) o += (unsigned long long)obuf[b];
+        if (o) atomicAdd(&n_out, o);
+        __syncthreads();
+        if (t == 0) diag[1] = (long long)n_out;
     }
     if (t == 1023) {
         tile_off[n_tiles] = (int32_t)sa[1023];
@@ -1243,8 +1258,9 @@ __global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict
 struct HList { double h[FKR_MAX_H * 3]; };
 
 __global__ void k_mult_tables(Geo g, int na, int nh, HList hl, const double* T, double* mult,
-                              int64_t per_h) {
+                              int64_t per_h, unsigned long long* ill_clear) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0 && ill_clear) *ill_clear = 0ull;   // the call's solves count from here
     if (idx >= per_h * nh) return;
     const int hi = (int)(idx / per_h);
     int64_t r = idx - hi * per_h;
@@ -1796,22 +1812,23 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, int32_t* bhist,
-                      long long* diag, hipStream_t s) {
+                      int32_t* obuf, hipStream_t s) {
     if (N == 0) return;
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
     const bool use_lds = g.n_tiles <= kLdsHistMax;
     const size_t lds = use_lds ? (size_t)g.n_tiles * 4 : 0;
     switch (g.d) {
-        case 1: k_bin_count<1><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, diag); break;
-        case 2: k_bin_count<2><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, diag); break;
-        default: k_bin_count<3><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, diag); break;
+        case 1: k_bin_count<1><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, obuf); break;
+        case 2: k_bin_count<2><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, obuf); break;
+        default: k_bin_count<3><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, obuf); break;
     }
     if (use_lds) k_tile_prefix<<<(unsigned)g.n_tiles, 256, 0, s>>>(g.n_tiles, (int)nb, bhist, counts);
 }
 
-void launch_scan(const Geo& g, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
-                 int32_t* cursor, long long* diag, hipStream_t s) {
-    k_scan<<<1, 1024, 0, s>>>(g.n_tiles, g.chunk, counts, tile_off, job_off, jobs, cursor, diag);
+void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
+                 int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s) {
+    const int nbins = (int)((N + kSortChunk - 1) / kSortChunk);
+    k_scan<<<1, 1024, 0, s>>>(g.n_tiles, g.chunk, counts, tile_off, job_off, jobs, cursor, diag, obuf, nbins);
 }
 
 template <int D, typename T>
@@ -2106,7 +2123,7 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
 }
 
 void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, const double* T,
-                        double* mult, hipStream_t s) {
+                        double* mult, unsigned long long* ill_clear, hipStream_t s) {
     HList hl;
     for (int q = 0; q < FKR_MAX_H * 3; ++q) hl.h[q] = 0.0;
     for (int q = 0; q < nh; ++q)
@@ -2115,7 +2132,7 @@ void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, c
     int64_t per_h = 0;
     for (int j = 0; j < g.d; ++j) per_h += na * g.B[j];
     const int64_t n = per_h * nh;
-    k_mult_tables<<<nblk(n), 256, 0, s>>>(g, na, nh, hl, T, mult, per_h);
+    k_mult_tables<<<nblk(n), 256, 0, s>>>(g, na, nh, hl, T, mult, per_h, ill_clear);
 }
 
 

@@ -185,6 +185,7 @@ static void layout(fkr_plan* p) {
     // block x tile counts of the binning pass (when the tiles fit the LDS histogram)
     const int64_t nbins = (N + kSortChunk - 1) / kSortChunk;
     L.bhist = take(p->n_tiles <= kLdsHistMax ? (size_t)nbins * p->n_tiles * 4 : 4);
+    L.obuf = take((size_t)nbins * 4);   // per-block counts of samples outside [lo, hi]
     L.cnt = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.coff = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.counts = take((p->n_tiles + 1) * 4);
