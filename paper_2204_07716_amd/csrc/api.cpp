@@ -105,7 +105,7 @@ WSrc src_philox(uint64_t seed, int probe) { WSrc w{}; w.kind = W_PHILOX; w.seed 
 const int* dev_es(fkr_plan* p) { return at<int>(p, p->lay.consts + 64); }
 const int* dev_et(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 512); }
 const int* dev_pidx(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 1024); }
-const double* dev_periods(fkr_plan* p) { return at<double>(p, p->lay.consts); }
+unsigned long long* ill_ctr(fkr_plan* p) { return at<unsigned long long>(p, p->lay.diag + 2 * 8); }
 
 // Every weight vector of a call, constants included, gathered once into
 // sorted sample order: rows of `stride` = nr rounded up to 4 columns (the
@@ -204,18 +204,17 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
 }
 
 // Channels of bandwidth index hi: expand + inverse FFT -> chan [M][ncp].
-fkr_status run_channels(fkr_plan* p, int hidx, int nr, hipStream_t s) {
+fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
     if (ncp > p->ncp_max) return FKR_E_ARG;
     ExpandArgs a{};
     a.d = p->d; a.n_s = p->n_s; a.n_t = p->n_t; a.nreal = nreal; a.ncp = ncp;
     a.npairs = (nr + 1) / 2;
-    int64_t per_h = 0;
     for (int j = 0; j < 3; ++j) { a.B[j] = p->B[j]; a.K[j] = p->K[j]; }
-    for (int j = 0; j < p->d; ++j) { a.mult_off[j] = per_h; per_h += (2 * p->order + 1) * p->B[j]; }
+    for (int j = 0; j < p->d; ++j) { a.h[j] = h[j]; a.T[j] = p->T[j]; }
     a.Btot = p->Btot;
-    a.mult = at<double>(p, p->lay.mult) + (int64_t)hidx * per_h;
+    a.ill_clear = ill_clear;
     {
         StageTimer t(p, FKR_STAGE_EXPAND, s);
         launch_expand2(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftA, s);
@@ -447,12 +446,10 @@ fkr_status fkr_moments(fkr_plan* p, int nh, const double* h, int nw, const void*
     std::vector<WSrc> srcs{src_one()};
     for (int r = 0; r < nw; ++r) srcs.push_back(src_array(W, w_type, nw, r));
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
-    const Geo g = make_geo(p);
-    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult), nullptr, s);
     const int nr = 1 + nw;
     const int ncp = (p->n_s + p->n_t * nw + 1) / 2;
     for (int hi = 0; hi < nh; ++hi) {
-        if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
+        if ((st = run_channels(p, h + hi * p->d, nr, nullptr, s)) != FKR_OK) return st;
         launch_chan_out(p->tprec, p->Mtot, ncp, p->n_s, p->n_t, nw, p->ws + p->lay.chan,
                         Sout ? Sout + (int64_t)hi * p->n_s * p->Mtot : nullptr,
                         Tout ? Tout + (int64_t)hi * nw * p->n_t * p->Mtot : nullptr, s);
@@ -472,12 +469,9 @@ fkr_status fkr_fit(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
     std::vector<WSrc> srcs{src_one()};
     add_response_sources(&srcs, q, y_complex, Y, y_type);
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
-    const Geo g = make_geo(p);
-    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult),
-                       at<unsigned long long>(p, p->lay.diag + 2 * 8), s);
     const int nr = (int)srcs.size();
     for (int hi = 0; hi < nh; ++hi) {
-        if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
+        if ((st = run_channels(p, h + hi * p->d, nr, hi == 0 ? ill_ctr(p) : nullptr, s)) != FKR_OK) return st;
         SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
         a.y_out = mhat + (int64_t)hi * ny * p->Mtot;
         a.s0_out = s0 ? s0 + (int64_t)hi * p->Mtot : nullptr;
@@ -517,8 +511,6 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     add_probe_sources(&srcs, Np, seed, probes, ptype);
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
     const Geo g = make_geo(p);
-    launch_mult_tables(g, p->order, nh, h, dev_periods(p), at<double>(p, p->lay.mult),
-                       at<unsigned long long>(p, p->lay.diag + 2 * 8), s);
     const int nr = (int)srcs.size();
     double* internal = at<double>(p, p->lay.mhat);
     // probe fits [M][pstride] in the spreading precision (they only feed the
@@ -530,7 +522,7 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     double* partial = at<double>(p, p->lay.partial);
     const int n_items = q + Np;
     for (int hi = 0; hi < nh; ++hi) {
-        if ((st = run_channels(p, hi, nr, s)) != FKR_OK) return st;
+        if ((st = run_channels(p, h + hi * p->d, nr, hi == 0 ? ill_ctr(p) : nullptr, s)) != FKR_OK) return st;
         SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
         double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
         a.y_out = yfit;
@@ -597,9 +589,7 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     z.kind = W_SORTED; z.type = FKR_F64; z.ptr = wbuf; z.stride = 1; z.col = 0;
     std::vector<WSrc> srcs{src_one(), z};
     if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
-    launch_mult_tables(g, p->order, 1, h, dev_periods(p), at<double>(p, p->lay.mult),
-                       at<unsigned long long>(p, p->lay.diag + 2 * 8), s);
-    if ((st = run_channels(p, 0, 2, s)) != FKR_OK) return st;
+    if ((st = run_channels(p, h, 2, ill_ctr(p), s)) != FKR_OK) return st;
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
     a.y_out = v;

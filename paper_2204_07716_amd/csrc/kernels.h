@@ -64,8 +64,8 @@ struct FftPass {
 struct ExpandArgs {
     int d, n_s, n_t, nreal, ncp, npairs;
     int64_t B[3], K[3], Btot;
-    const double* mult;      // [dim][a][e] tables for this bandwidth
-    int64_t mult_off[3];     // offset of dim j's tables (a-major, B_j each)
+    double h[3], T[3];       // bandwidth and period per dimension
+    unsigned long long* ill_clear;   // cleared by the launch when given
 };
 
 struct SolveArgs {
@@ -112,9 +112,6 @@ void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* c
                  const void* subgrid, void* fine, hipStream_t s);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
-// also clears *ill_clear (when given): the ill-posed counter of the call's solves
-void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, const double* T,
-                        double* mult, unsigned long long* ill_clear, hipStream_t s);
 void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
                     void* out, hipStream_t s);
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);

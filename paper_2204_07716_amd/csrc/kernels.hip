@@ -1251,30 +1251,20 @@ __global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict
 
 // ---------------------------------------------------------------------------
 // Kernel-moment spectra (Hermite form of the Gaussian's moment transforms):
-// mult[h][dim j][a][e] = He_a(h_j w) exp(-(h_j w)^2/2) / T_j, w = 2 pi (e-K_j)/T_j.
-// The phase i^a is applied in k_expand; the division by h^a (equilibration)
-// is implicit in using He_a(h w) without the h^a factor.
+// per dimension j, He_a(h_j w) exp(-(h_j w)^2/2) / T_j, w = 2 pi (e-K_j)/T_j,
+// evaluated where k_expand needs it.  The phase i^a is applied in k_expand;
+// the division by h^a (equilibration) is implicit in using He_a(h w) without
+// the h^a factor.
 // ---------------------------------------------------------------------------
-struct HList { double h[FKR_MAX_H * 3]; };
-
-__global__ void k_mult_tables(Geo g, int na, int nh, HList hl, const double* T, double* mult,
-                              int64_t per_h, unsigned long long* ill_clear) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0 && ill_clear) *ill_clear = 0ull;   // the call's solves count from here
-    if (idx >= per_h * nh) return;
-    const int hi = (int)(idx / per_h);
-    int64_t r = idx - hi * per_h;
-    int j = 0;
-    while (j < g.d - 1 && r >= na * g.B[j]) { r -= na * g.B[j]; ++j; }
-    const int a = (int)(r / g.B[j]);
-    const int64_t e = r - a * g.B[j];
-    const double Tj = T[j];
-    const double om = 2.0 * M_PI * (double)(e - g.K[j]) / Tj;
-    const double u = hl.h[hi * 3 + j] * om;
+// Multiplier of moment degree a at band index e of dimension j (Hermite form
+// of the Gaussian moment kernel's transform, over the period T_j).
+__device__ __forceinline__ double moment_mult(double hj, double Tj, int64_t Kj, int a, int64_t e) {
+    const double om = 2.0 * M_PI * (double)(e - Kj) / Tj;
+    const double u = hj * om;
     double hm = 1.0, he = u;
     if (a == 0) he = 1.0;
     for (int k = 1; k < a; ++k) { const double hn = u * he - k * hm; hm = he; he = hn; }
-    mult[idx] = he * exp(-0.5 * u * u) / Tj;
+    return he * exp(-0.5 * u * u) / Tj;
 }
 
 // Y_c(n) = X_{2c}(n) + i X_{2c+1}(n), X_ch = C_r(n) i^{|a|} prod_j mult_j[a_j](n_j),
@@ -1285,6 +1275,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, const int* es, con
                                                 typename V2<T>::t* out) {
     using C = typename V2<T>::t;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0 && a.ill_clear) *a.ill_clear = 0ull;   // the call's solves count from here
     if (idx >= a.Btot * a.ncp) return;
     const int c = (int)((uint64_t)idx / (uint64_t)a.Btot);
     const unsigned n = (unsigned)(idx - (int64_t)c * a.Btot);
@@ -1315,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, const int* es, con
         double m = 1.0;
         int deg = 0;
         for (int j = 0; j < a.d; ++j) {
-            m *= a.mult[a.mult_off[j] + ex[j] * a.B[j] + e[j]];
+            m *= moment_mult(a.h[j], a.T[j], a.K[j], ex[j], e[j]);
             deg += ex[j];
         }
         double xr = cr * m, xi = ci * m;
@@ -2121,20 +2112,6 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
         else k_fft<float, false><<<nb, nt, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
     }
 }
-
-void launch_mult_tables(const Geo& g, int order, int nh, const double* h_host, const double* T,
-                        double* mult, unsigned long long* ill_clear, hipStream_t s) {
-    HList hl;
-    for (int q = 0; q < FKR_MAX_H * 3; ++q) hl.h[q] = 0.0;
-    for (int q = 0; q < nh; ++q)
-        for (int j = 0; j < g.d; ++j) hl.h[q * 3 + j] = h_host[q * g.d + j];
-    const int na = 2 * order + 1;
-    int64_t per_h = 0;
-    for (int j = 0; j < g.d; ++j) per_h += na * g.B[j];
-    const int64_t n = per_h * nh;
-    k_mult_tables<<<nblk(n), 256, 0, s>>>(g, na, nh, hl, T, mult, per_h, ill_clear);
-}
-
 
 void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
                     void* out, hipStream_t s) {

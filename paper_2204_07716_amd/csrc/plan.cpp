@@ -224,7 +224,6 @@ static void layout(fkr_plan* p) {
     L.fftB = take(cap * tcsz);
     L.cap_spec = p->Btot * p->npairs_max;
     L.spec = take(L.cap_spec * tcsz);
-    L.mult = take((size_t)p->max_h * (2 * p->order + 1) * nB * 8);
     L.cap_chan = p->Mtot * p->ncp_max;
     L.chan = take(L.cap_chan * tcsz);
     L.cap_mhat = p->Mtot * (int64_t)p->max_weights;
