@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void k_cell_count(Geo g, const int32_t* jobs, 
 // final (tile, cell) order.
 __global__ __launch_bounds__(1024) void k_cell_scan(Geo g, const int32_t* tile_off, const int32_t* job_off,
                                                     const int32_t* cnt, int32_t* off) {
-    extern __shared__ uint32_t sh[];   // [ncell] totals, then [256] scan scratch
+    extern __shared__ uint32_t sh[];   // [ncell] totals, then [blockDim] scan scratch
     const int t = blockIdx.x;
     const int j0 = job_off[t], j1 = job_off[t + 1];
     if (j0 == j1) return;
@@ -1834,7 +1834,9 @@ static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, in
     k_scatter_tiles<D, T><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, tile_off, cursor, bhist, trec);
     const unsigned nj = (unsigned)n_jobs_max;
     k_cell_count<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, cnt);
-    k_cell_scan<<<(unsigned)g.n_tiles, 1024, ((size_t)g.ncell + 1024) * 4, s>>>(g, tile_off, job_off, cnt, off);
+    // one thread per cell of a tile (64 in 2-D), at most 1024
+    const unsigned nts = (unsigned)std::min(1024, std::max(64, (g.ncell + 63) / 64 * 64));
+    k_cell_scan<<<(unsigned)g.n_tiles, nts, ((size_t)g.ncell + nts) * 4, s>>>(g, tile_off, job_off, cnt, off);
     k_cell_scatter<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, off, loc, static_cast<T*>(frac), perm,
                                                               static_cast<T*>(xs));
 }
