@@ -62,6 +62,8 @@ def _args():
     ap.add_argument("--eager", action="store_true",
                     help="launch every step's kernels from the host instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the warm-path timing (profiling runs count only the cold steps)")
     ap.add_argument("--cpu-points", type=int, default=4096,
                     help="grid points in the oracle's timed sample")
     ap.add_argument("--copy-probe", action="store_true",
@@ -220,10 +222,13 @@ def main() -> int:
         s2, vhat, kappa = plan.variance(h, Yd, out["mhat"][0, 0], mode="log")
         return out, s2, vhat, kappa
 
-    plan.set_points(Xd)
-    warm_step()
-    torch.cuda.synchronize()
-    if args.graph:
+    warm_ms = None
+    if args.no_warm:
+        pass
+    elif args.graph:
+        plan.set_points(Xd)
+        warm_step()
+        torch.cuda.synchronize()
         s_cap = torch.cuda.Stream()
         s_cap.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s_cap):
@@ -247,12 +252,16 @@ def main() -> int:
         torch.cuda.synchronize()
         tw1 = time.perf_counter()
     else:
+        plan.set_points(Xd)
+        warm_step()
+        torch.cuda.synchronize()
         tw0 = time.perf_counter()
         for _ in range(args.steps):
             warm_step()
         torch.cuda.synchronize()
         tw1 = time.perf_counter()
-    warm_ms = (tw1 - tw0) * 1e3 / args.steps
+    if not args.no_warm:
+        warm_ms = (tw1 - tw0) * 1e3 / args.steps
     value = N * n_fits / (ms_per_step * 1e-3)
 
     # Roofline of the spreading kernel.  Its arithmetic is 2 W^d n_w flops per
@@ -297,7 +306,8 @@ def main() -> int:
                    "spread_width": g.w, "sigma": args.sigma or "default",
                    "hip_graph": bool(args.graph)},
         "roofline": roofline,
-        "warm": {"ms_per_step": round(warm_ms, 4), "value": round(N * n_fits / (warm_ms * 1e-3), 1),
+        "warm": None if warm_ms is None else
+                {"ms_per_step": round(warm_ms, 4), "value": round(N * n_fits / (warm_ms * 1e-3), 1),
                  "unit": "samples/s", "note": "X already sorted: set_points outside the timed region"},
         "hbm_model": _hbm_model(g, N, M, Np, stages, args.steps, ms_per_step),
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
