@@ -133,8 +133,9 @@ std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipS
 }
 
 // Spread + fold + forward FFT of every weight pair -> spec [band][npairs].
-fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_t s) {
-    const std::vector<WSrc> srcs = stage_weights(p, srcs_in, s);   // padded to a multiple of 4
+// With staged = true the sources already are columns of the staged rows.
+fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_t s, bool staged) {
+    const std::vector<WSrc> srcs = staged ? srcs_in : stage_weights(p, srcs_in, s);   // padded to a multiple of 4
     const Geo g = make_geo(p);
     const int nr = (int)srcs_in.size();
     const int npairs = (nr + 1) / 2;
@@ -431,7 +432,7 @@ fkr_status fkr_spectrum(fkr_plan* p, int nw, const void* W, int w_type, double* 
     std::vector<WSrc> srcs;
     for (int r = 0; r < nw; ++r) srcs.push_back(W ? src_array(W, w_type, nw, r) : src_one());
     const hipStream_t s = S(stream);
-    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
     launch_unpack_spec(p->tprec, p->Btot, p->B, p->d, (nw + 1) / 2, nw, p->ws + p->lay.spec, out, s);
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
@@ -445,7 +446,7 @@ fkr_status fkr_moments(fkr_plan* p, int nh, const double* h, int nw, const void*
     const hipStream_t s = S(stream);
     std::vector<WSrc> srcs{src_one()};
     for (int r = 0; r < nw; ++r) srcs.push_back(src_array(W, w_type, nw, r));
-    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
     const int nr = 1 + nw;
     const int ncp = (p->n_s + p->n_t * nw + 1) / 2;
     for (int hi = 0; hi < nh; ++hi) {
@@ -468,7 +469,7 @@ fkr_status fkr_fit(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
     const hipStream_t s = S(stream);
     std::vector<WSrc> srcs{src_one()};
     add_response_sources(&srcs, q, y_complex, Y, y_type);
-    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
     const int nr = (int)srcs.size();
     for (int hi = 0; hi < nh; ++hi) {
         if ((st = run_channels(p, h + hi * p->d, nr, hi == 0 ? ill_ctr(p) : nullptr, s)) != FKR_OK) return st;
@@ -509,7 +510,7 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     std::vector<WSrc> srcs{src_one()};
     add_response_sources(&srcs, q, y_complex, Y, y_type);
     add_probe_sources(&srcs, Np, seed, probes, ptype);
-    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
     const Geo g = make_geo(p);
     const int nr = (int)srcs.size();
     double* internal = at<double>(p, p->lay.mhat);
@@ -581,14 +582,17 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     const Geo g = make_geo(p);
     double* wbuf = at<double>(p, p->lay.wbuf);
     {
+        // residuals, and the staged rows (1, z) of the second fit, in sorted order
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        launch_resid(g, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
-                     y_complex, mhat, wbuf, s);
+        launch_resid(g, p->prec, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
+                     y_complex, mhat, wbuf + p->N, p->ws + p->lay.wsort, s);
     }
-    WSrc z{};   // residual weights, already in sorted order
-    z.kind = W_SORTED; z.type = FKR_F64; z.ptr = wbuf; z.stride = 1; z.col = 0;
-    std::vector<WSrc> srcs{src_one(), z};
-    if ((st = run_spectra(p, srcs, s)) != FKR_OK) return st;
+    std::vector<WSrc> srcs(2);
+    for (int r = 0; r < 2; ++r) {
+        srcs[r].kind = W_SORTED; srcs[r].type = p->prec; srcs[r].ptr = p->ws + p->lay.wsort;
+        srcs[r].stride = 4; srcs[r].col = r;
+    }
+    if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
     if ((st = run_channels(p, h, 2, ill_ctr(p), s)) != FKR_OK) return st;
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));

@@ -1633,12 +1633,13 @@ __global__ void k_finalize_cv(int hidx, int Np, int q, int64_t N, const double* 
 }
 
 // Residuals of the mean fit for the variance pass (Sec. 3), in sorted sample
-// order s: wbuf[s] = the response of the second fit (log(r + 1/N) or r),
-// wbuf[N + s] = r.
-template <int D>
+// order s: rows[s] = (1, z, 0, 0), the staged weight row of the second fit's
+// spread (z = log(r + 1/N) or r, in the spreading precision TW), and
+// r_out[s] = r.
+template <int D, typename TW>
 __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x_type, const void* xs,
                                                const int32_t* perm, int y_type, const void* Y,
-                                               int y_cplx, const double* mhat, double* wbuf) {
+                                               int y_cplx, const double* mhat, double* r_out, TW* rows) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const Corners<D> c = corners<D>(g, x_type, xs, s);
@@ -1658,8 +1659,14 @@ __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x
         const double e = load_as_double(Y, y_type, i) - f;
         r = e * e;
     }
-    wbuf[s] = mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r;   // sorted order
-    wbuf[N + s] = r;
+    const TW z = (TW)(mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r);
+    if constexpr (sizeof(TW) == 4) {
+        reinterpret_cast<float4*>(rows)[s] = make_float4(1.f, z, 0.f, 0.f);
+    } else {
+        reinterpret_cast<double2*>(rows)[2 * s] = make_double2(1.0, z);
+        reinterpret_cast<double2*>(rows)[2 * s + 1] = make_double2(0.0, 0.0);
+    }
+    r_out[s] = r;
 }
 
 template <int D>
@@ -2198,15 +2205,18 @@ void launch_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, i
     k_finalize_cv<<<1, 64, 0, s>>>(hidx, Np, q, N, red, ny_cols, rho_out, rss_out, gcv_out);
 }
 
-void launch_resid(const Geo& g, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
-                  int y_type, const void* Y, int y_cplx, const double* mhat, double* wbuf,
+void launch_resid(const Geo& g, int prec, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
+                  int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out, void* rows,
                   hipStream_t s) {
     if (N == 0) return;
-    switch (g.d) {
-        case 1: k_resid<1><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, mhat, wbuf); break;
-        case 2: k_resid<2><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, mhat, wbuf); break;
-        default: k_resid<3><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, mhat, wbuf); break;
+#define FKR_RES(D, TW) k_resid<D, TW><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, \
+                                                              mhat, r_out, static_cast<TW*>(rows))
+    if (prec == FKR_F64) {
+        if (g.d == 1) FKR_RES(1, double); else if (g.d == 2) FKR_RES(2, double); else FKR_RES(3, double);
+    } else {
+        if (g.d == 1) FKR_RES(1, float); else if (g.d == 2) FKR_RES(2, float); else FKR_RES(3, float);
     }
+#undef FKR_RES
 }
 
 void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, const int32_t* perm,
