@@ -192,9 +192,13 @@ fkr_status fkr_interp(fkr_plan* plan, int nv, const double* G_dev, int64_t Nq,
  * through the grid smoother (moments -> solve -> interpolation to the
  * samples).  rho_dev: [nh][Np] doubles, rho_p = w_p^T (w_p - w_hat_p) /
  * (w_p^T w_p); their mean estimates (1/N) tr(I - S_h).  Probes come from
- * probes_dev (N x Np, type w_type) or, when it is NULL, from the Philox4x64-10
- * generator: sample i, probe 4g + r uses the block with counter (i, g, 0, 0)
- * and key (seed, 0), uniforms (floor(x/2^11) + 1) 2^-53 and Box-Muller. */
+ * probes_dev (N x Np, type w_type) or, when it is NULL, from the Philox4x32-10
+ * generator: sample i, probe 4g + r uses word r of the Box-Muller transform of
+ * the block with counter (i mod 2^32, floor(i / 2^32), g, 0) and key
+ * (seed mod 2^32, floor(seed / 2^32)); uniforms u = (floor(x / 2^8) + 1/2)
+ * 2^-24; normals sqrt(-2 ln u_0) (cos, sin)(2 pi u_1) from words (0, 1) and
+ * likewise from (2, 3), in FP64 for FP64 plans and with the hardware
+ * log / sqrt / sin / cos for FP32 plans. */
 fkr_status fkr_dof(fkr_plan* plan, int nh, const double* h, int Np, uint64_t seed,
                    const void* probes_dev, int w_type, double* rho_dev, void* stream);
 
