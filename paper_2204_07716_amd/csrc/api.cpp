@@ -238,10 +238,13 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         for (int q = 0; q < p->fL[j].nfac; ++q) f.fac[q] = p->fL[j].fac[q];
         f.tw = at<double>(p, p->fL[j].tw_off);
         f.fac_out = nullptr;
-        f.out_estride = f.rows;
+        // row = (pair, m over the done dimensions, e over the rest) with the
+        // pair outermost; the output keeps the pair outermost, so the last
+        // pass writes the channels pair-major, [pair][M^d][re, im]
+        f.out_estride = done_M * rest;
         f.out_roff = 0;
-        f.out_rdiv = f.rows;
-        f.out_rmul = 0;
+        f.out_rdiv = done_M * rest;
+        f.out_rmul = done_M * p->M[j] * rest;
         void* out;
         if (j == p->d - 1) out = p->ws + p->lay.chan;
         else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);

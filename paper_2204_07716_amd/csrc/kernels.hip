@@ -1332,13 +1332,15 @@ template <int P, typename T>
 __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, const T* chan) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.Mtot) return;
-    const T* ch = chan + k * 2 * a.ncp;
+    // channels are stored pair-major, [pair][M][re, im]: real channel r of
+    // point k is chan[((r / 2) M + k) 2 + r % 2] (coalesced over k)
+    auto ch = [&](int r) { return chan[(((int64_t)(r >> 1)) * a.Mtot + k) * 2 + (r & 1)]; };
     double A[P][P];
 #pragma unroll
     for (int b = 0; b < P; ++b)
 #pragma unroll
-        for (int c = 0; c <= b; ++c) A[b][c] = (double)ch[pidx[b * kMaxP + c]];
-    const double s0 = (double)ch[0];
+        for (int c = 0; c <= b; ++c) A[b][c] = (double)ch(pidx[b * kMaxP + c]);
+    const double s0 = (double)ch(0);
     // s_0 is the first pivot; every pivot must clear the plan's noise floor.
     bool ill = !isfinite(s0);
     // Cholesky A = L L^T (lower triangle in place).
@@ -1382,10 +1384,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
     if (a.s0_out) a.s0_out[k] = s0;
     if (ill && a.ill_count) atomicAdd(a.ill_count, 1ull);
     for (int r = 1; r < a.nr; ++r) {
-        const T* t = ch + a.n_s + (r - 1) * a.n_t;
+        const int t0 = a.n_s + (r - 1) * a.n_t;
         double m = 0.0;
 #pragma unroll
-        for (int b = 0; b < P; ++b) m += r0[b] * (double)t[b];
+        for (int b = 0; b < P; ++b) m += r0[b] * (double)ch(t0 + b);
         if (ill) m = nan;
         if (r <= a.ny) {
             if (a.y_out) {
@@ -1785,7 +1787,7 @@ __global__ void k_chan_out(int64_t Mtot, int ncp, int n_s, int n_t, int nw, cons
     if (idx >= Mtot * nreal) return;
     const int ch = (int)(idx / Mtot);
     const int64_t k = idx - (int64_t)ch * Mtot;
-    const double v = (double)chan[k * 2 * ncp + ch];
+    const double v = (double)chan[((int64_t)(ch >> 1) * Mtot + k) * 2 + (ch & 1)];   // [pair][M][re, im]
     if (ch < n_s) { if (S) S[(int64_t)ch * Mtot + k] = v; }
     else if (Tt) Tt[(int64_t)(ch - n_s) * Mtot + k] = v;
 }
