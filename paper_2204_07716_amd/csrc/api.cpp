@@ -520,7 +520,10 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
     // probe fits [M][pstride] in the spreading precision (they only feed the
     // DF reduction), 16-byte aligned rows for FP32
     const bool pf32 = p->prec == FKR_F32;
-    const int pstride = pf32 ? (Np + 3) & ~3 : Np;
+    // one real response and all probes in one reduction launch: the y fit
+    // rides in column 0 of the FP32 rows, so the reduction gathers one row
+    const bool yrow = pf32 && q == 1 && !y_complex && Np >= 1 && Np <= kRedProbes;
+    const int pstride = pf32 ? ((yrow ? 1 : 0) + Np + 3) & ~3 : Np;
     void* pfit = p->ws + p->lay.mhat + (((size_t)ny * p->Mtot * 8 + 15) & ~(size_t)15);
     double* red = at<double>(p, p->lay.red);
     double* partial = at<double>(p, p->lay.partial);
@@ -533,6 +536,7 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         a.probe_out = pfit;
         a.probe_f32 = pf32 ? 1 : 0;
         a.probe_stride = pstride;
+        a.rows_with_y = yrow ? 1 : 0;
         {
             StageTimer t(p, FKR_STAGE_SOLVE, s);
             launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
@@ -541,7 +545,7 @@ fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, co
         r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
         r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
         r.ny_cols = q; r.y_cplx = y_complex; r.yfit = yfit;
-        r.np = Np; r.pfit = pfit; r.pstride = pstride;
+        r.np = Np; r.pfit = pfit; r.pstride = pstride; r.yrow = yrow ? 1 : 0;
         r.partial = partial;
         StageTimer t(p, FKR_STAGE_REDUCE, s);
         // probes per launch: at most kRedProbes, spread evenly over the launches

@@ -76,6 +76,7 @@ struct SolveArgs {
     double* y_out;                 // [q][M][(2)] per bandwidth (may be null)
     void* probe_out;               // [M][probe_stride], FP32 or FP64 (may be null)
     int probe_f32, probe_stride;
+    int rows_with_y;               // the y fits go to the rows too: column r - 1 for weight r
     double* s0_out;                // [M] (may be null)
     unsigned long long* ill_count;
 };
@@ -91,6 +92,7 @@ struct ReduceCvArgs {
     int np;                       // probes
     const void* pfit;             // [M][pstride], element type w_type
     int pstride;
+    int yrow;                     // one real response whose fit is column 0 of the rows (FP32)
     int y0, ny_launch;            // response columns of this launch (<= kRedYCols)
     int p0, np_launch;            // probes of this launch (<= kRedProbes)
     double* partial;              // [slot][kRedBlocks]; items: y columns, then probes

@@ -1395,8 +1395,9 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
                 const int col = (r - 1) / cpl, part = (r - 1) % cpl;
                 a.y_out[(col * a.Mtot + k) * cpl + part] = m;
             }
+            if (a.rows_with_y && a.probe_out) static_cast<float*>(a.probe_out)[k * a.probe_stride + (r - 1)] = (float)m;
         } else if (a.probe_out) {
-            const int64_t o = k * a.probe_stride + (r - 1 - a.ny);
+            const int64_t o = k * a.probe_stride + (r - 1 - (a.rows_with_y ? 0 : a.ny));
             if (a.probe_f32) static_cast<float*>(a.probe_out)[o] = (float)m;
             else static_cast<double*>(a.probe_out)[o] = m;
         }
@@ -1482,7 +1483,7 @@ __device__ __forceinline__ void block_sum(double (&acc)[NA], double* sh) {
 // interleaved per grid point, so the 2^D corners of a sample bring all probes
 // in contiguous loads; indexes past the launch's count are clamped (loaded,
 // never summed).  Wave sums by cross-lane reduction, block sums in LDS.
-template <int D, typename TW, int PC>
+template <int D, typename TW, int PC, bool YR>
 __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
     constexpr int YC = kRedYCols, NA = YC + 2 * PC;
     __shared__ double sh[NA][4];
@@ -1498,6 +1499,37 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
          s += (int64_t)gridDim.x * blockDim.x) {
         const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
         const TW* row = wrow + s * a.wstride;
+        if constexpr (YR) {
+            // FP32 rows [y | probes | pad] of 16-byte loads: the fit of the one
+            // real response comes with the probe fits (all probes in this launch)
+            constexpr int NV = 1 + PC, NC = (NV + 3) / 4;
+            double fa[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) fa[j] = 0.0;
+            const float* pf = static_cast<const float*>(a.pfit);
+            const int last = (1 + a.np_launch + 3) / 4 - 1;
+#pragma unroll
+            for (int q = 0; q < (1 << D); ++q) {
+                const float4* gv = reinterpret_cast<const float4*>(pf + c.idx[q] * a.pstride);
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    const float4 v4 = gv[min(j, last)];
+                    const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (4 * j + e < NV) fa[4 * j + e] += c.w[q] * (double)vv[e];
+                }
+            }
+            const double e0 = (double)row[1] - fa[0];
+            ay[0] += e0 * e0;
+#pragma unroll
+            for (int j = 0; j < PC; ++j) {
+                const double wv = (double)row[pcol + min(j, a.np_launch - 1)];
+                aw[j] += wv * wv;
+                ah[j] += wv * fa[1 + j];
+            }
+            continue;
+        }
 #pragma unroll
         for (int j = 0; j < YC; ++j) {
             if (j >= a.ny_launch) break;
@@ -2166,11 +2198,13 @@ void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, 
 
 template <int PC>
 static void reduce_cv_pc(const Geo& g, const ReduceCvArgs& a, hipStream_t s) {
-#define FKR_RCV(D, TW) k_reduce_cv<D, TW, PC><<<kRedBlocks, 256, 0, s>>>(g, a)
+#define FKR_RCV(D, TW, YR) k_reduce_cv<D, TW, PC, YR><<<kRedBlocks, 256, 0, s>>>(g, a)
     if (a.w_type == FKR_F64) {
-        if (g.d == 1) FKR_RCV(1, double); else if (g.d == 2) FKR_RCV(2, double); else FKR_RCV(3, double);
+        if (g.d == 1) FKR_RCV(1, double, false); else if (g.d == 2) FKR_RCV(2, double, false); else FKR_RCV(3, double, false);
+    } else if (a.yrow) {
+        if (g.d == 1) FKR_RCV(1, float, true); else if (g.d == 2) FKR_RCV(2, float, true); else FKR_RCV(3, float, true);
     } else {
-        if (g.d == 1) FKR_RCV(1, float); else if (g.d == 2) FKR_RCV(2, float); else FKR_RCV(3, float);
+        if (g.d == 1) FKR_RCV(1, float, false); else if (g.d == 2) FKR_RCV(2, float, false); else FKR_RCV(3, float, false);
     }
 #undef FKR_RCV
 }
