@@ -228,7 +228,7 @@ static void layout(fkr_plan* p) {
     L.chan = take(L.cap_chan * tcsz);
     L.cap_mhat = p->Mtot * (int64_t)p->max_weights;
     L.mhat = take(L.cap_mhat * 8 + 64);   // + alignment and row padding of the FP32 probe fits
-    L.cap_partial = 1024 * (int64_t)(2 * p->max_weights + 2);
+    L.cap_partial = kRedBlocks * (int64_t)(2 * p->max_weights + 2);
     L.partial = take(L.cap_partial * 8);
     L.cap_wbuf = 2 * N;
     L.wbuf = take(L.cap_wbuf * 8);
