@@ -248,7 +248,7 @@ typedef enum {
     FKR_STAGE_SORT = 0,      /* set_points: bin, scan, two-level scatter    */
     FKR_STAGE_WEIGHTS = 1,   /* weights gathered into sorted order          */
     FKR_STAGE_SPREAD = 2,    /* spreading onto tile subgrids (eq. 16-17)    */
-    FKR_STAGE_FOLD = 3,      /* subgrids summed into the fine grid          */
+    FKR_STAGE_FOLD = 3,      /* kept for numbering: the subgrids are summed into the fine grid by the first forward FFT pass (FKR_STAGE_FFT_FWD) */
     FKR_STAGE_FFT_FWD = 4,   /* forward FFT passes + deconvolution (eq. 19-20) */
     FKR_STAGE_EXPAND = 5,    /* moment multipliers per channel (eq. 12-13)  */
     FKR_STAGE_FFT_INV = 6,   /* inverse FFT passes + crop (eq. 21)          */

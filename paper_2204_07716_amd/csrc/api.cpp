@@ -156,13 +156,9 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
                           at<int32_t>(p, p->lay.perm), at<int32_t>(p, p->lay.jobs), p->n_jobs_max,
                           p->ws + p->lay.subgrid, s);
         }
-        {
-            StageTimer t(p, FKR_STAGE_FOLD, s);
-            launch_fold(g, p->prec, p->tprec, gp, at<int32_t>(p, p->lay.cover),
-                        at<int32_t>(p, p->lay.job_off), p->ws + p->lay.subgrid, p->ws + p->lay.fine, s);
-        }
+        // the first forward pass folds its rows from the subgrids itself
         StageTimer tf(p, FKR_STAGE_FFT_FWD, s);
-        const void* in = p->ws + p->lay.fine;
+        const void* in = nullptr;
         int64_t done_B = 1;
         for (int j = 0; j < p->d; ++j) {
             FftPass f{};
@@ -175,6 +171,13 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
             f.K = p->K[j];
             f.in_band = 0;
             f.out_band = 1;
+            if (j == 0) {
+                f.fold_d = p->d;
+                f.fold_f64 = p->prec == FKR_F64 ? 1 : 0;
+                f.fold_rest = rest;
+                f.fold = fold_args(g, gp, at<int32_t>(p, p->lay.cover), at<int32_t>(p, p->lay.job_off),
+                                   p->ws + p->lay.subgrid);
+            }
             f.nfac = p->fMr[j].nfac;
             for (int q = 0; q < p->fMr[j].nfac; ++q) f.fac[q] = p->fMr[j].fac[q];
             f.tw = at<double>(p, p->fMr[j].tw_off);

@@ -51,7 +51,7 @@ struct Layout {                      // byte offsets into the workspace
     size_t trec = 0, bhist = 0, obuf = 0, cnt = 0, coff = 0;   // tile-ordered records, block x tile counts, per-job cell counts and offsets
     size_t counts = 0, tile_off = 0, cursor = 0, job_off = 0, jobs = 0;
     size_t loc = 0, frac = 0, perm = 0, xs = 0;
-    size_t subgrid = 0, fine = 0, fftA = 0, fftB = 0, spec = 0;
+    size_t subgrid = 0, fftA = 0, fftB = 0, spec = 0;
     size_t chan = 0, mhat = 0, partial = 0, wbuf = 0, red = 0, wsort = 0;
     size_t total = 0;
     // element capacities (for checks)

@@ -44,6 +44,18 @@ struct SpreadSrc {
     WSrc w[2 * kMaxPairsPerSpread];
 };
 
+// What a fold needs: the fine cell (c_0, .., c_{d-1}) of pair p is the sum
+// over the padded tiles that cover it and the jobs of each such tile.
+struct FoldArgs {
+    const int32_t* cover;    // per dim: Mr_j entries of (1 + 2 kCoverSlots) int32
+    const int32_t* job_off;  // [n_tiles + 1]
+    const void* subgrid;     // [job][pair][Psub][re, im], spreading precision
+    int64_t Psub;
+    int np;                  // pairs of the launch
+    int64_t nt0, nt1, pe0, pe1;
+    int64_t Mr[3];
+};
+
 struct FftPass {
     int64_t rows;      // number of rows
     int64_t n_in;      // input row length
@@ -59,6 +71,12 @@ struct FftPass {
     const double* tw;  // exp(-2 pi i k / F), FP64 pairs
     const double* fac_out;  // optional real factor per output element
     int rows_per_block;
+    // forward first pass only: the input rows are folded from the subgrids
+    // (row = pair * rest + (c_1 + Mr_1 c_2), element = c_0) instead of read
+    int fold_d;                   // 0: read `in`; else the dimension count
+    int fold_f64;                 // subgrid element type
+    int64_t fold_rest;            // Mr_1 Mr_2
+    FoldArgs fold;
 };
 
 struct ExpandArgs {
@@ -110,8 +128,7 @@ size_t tile_record_bytes(int d, int prec);   // bytes of one tile-ordered sample
 void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, const uint32_t* loc,
                    const void* frac, const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max,
                    void* subgrid, hipStream_t s);
-void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* cover, const int32_t* job_off,
-                 const void* subgrid, void* fine, hipStream_t s);
+FoldArgs fold_args(const Geo& g, int npairs, const int32_t* cover, const int32_t* job_off, const void* subgrid);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
 void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,

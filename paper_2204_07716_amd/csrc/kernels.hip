@@ -986,14 +986,9 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_group(Geo g, int np, co
 // (deterministic).  One thread per (cell, pair) item; consecutive threads take
 // consecutive cells of one pair, so the subgrid reads of a wave fall on rows
 // of the same tiles.  Output layout [pair][cell].
-template <int D, typename T, typename TO>
-__global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cover,
-                                              const int32_t* job_off, const T* subgrid, TO* fine) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.Mrtot * np) return;
-    const unsigned mrtot = (unsigned)g.Mrtot;
-    const int p = (int)((unsigned)idx / mrtot);
-    const unsigned cell = (unsigned)idx - (unsigned)p * mrtot;
+template <int D, typename T>
+__device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned cell) {
+    const T* subgrid = static_cast<const T*>(fa.subgrid);
     const int cs = 1 + 2 * kCoverSlots;
     const int32_t* cv[3];
     unsigned rem = cell;
@@ -1001,15 +996,15 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         if (j < D) {
-            const unsigned mr = (unsigned)g.Mr[j];
+            const unsigned mr = (unsigned)fa.Mr[j];
             const unsigned qj = rem / mr;
             const unsigned c = rem - qj * mr;
             rem = qj;
-            cv[j] = cover + cov_base + (int64_t)c * cs;
+            cv[j] = fa.cover + cov_base + (int64_t)c * cs;
             cov_base += (int64_t)mr * cs;
         }
     }
-    const int64_t lsize = g.Psub * np * 2;
+    const int64_t lsize = fa.Psub * fa.np * 2;
     const int n0 = cv[0][0];
     const int n1 = D > 1 ? cv[1][0] : 1;
     const int n2 = D > 2 ? cv[2][0] : 1;
@@ -1031,12 +1026,12 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
                 tile = cv[0][1 + 2 * a0];
                 off = cv[0][2 + 2 * a0];
                 if (D > 1) {
-                    tile += g.nt[0] * cv[1][1 + 2 * a1];
-                    off += g.pe[0] * cv[1][2 + 2 * a1];
+                    tile += fa.nt0 * cv[1][1 + 2 * a1];
+                    off += fa.pe0 * cv[1][2 + 2 * a1];
                 }
                 if (D > 2) {
-                    tile += g.nt[0] * g.nt[1] * cv[2][1 + 2 * a2];
-                    off += g.pe[0] * g.pe[1] * cv[2][2 + 2 * a2];
+                    tile += fa.nt0 * fa.nt1 * cv[2][1 + 2 * a2];
+                    off += fa.pe0 * fa.pe1 * cv[2][2 + 2 * a2];
                 }
             }
             tl[k] = tile;
@@ -1045,15 +1040,15 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
         int j0[NT], j1[NT];
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
-            j0[k] = ok[k] ? job_off[tl[k]] : 0;
-            j1[k] = ok[k] ? job_off[tl[k] + 1] : 0;
+            j0[k] = ok[k] ? fa.job_off[tl[k]] : 0;
+            j1[k] = ok[k] ? fa.job_off[tl[k] + 1] : 0;
         }
         T fr[NT], fi[NT];
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             fr[k] = fi[k] = (T)0;
             if (j0[k] < j1[k]) {
-                const T* sg = subgrid + (int64_t)j0[k] * lsize + (p * g.Psub + of[k]) * 2;
+                const T* sg = subgrid + (int64_t)j0[k] * lsize + (p * fa.Psub + of[k]) * 2;
                 fr[k] = sg[0];
                 fi[k] = sg[1];
             }
@@ -1064,15 +1059,13 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
             if (j0[k] >= j1[k]) continue;
             re += (double)fr[k];
             im += (double)fi[k];
-            const T* sg = subgrid + (int64_t)(j0[k] + 1) * lsize + (p * g.Psub + of[k]) * 2;
+            const T* sg = subgrid + (int64_t)(j0[k] + 1) * lsize + (p * fa.Psub + of[k]) * 2;
             for (int jj = j0[k] + 1; jj < j1[k]; ++jj, sg += lsize) {
                 re += (double)sg[0];
                 im += (double)sg[1];
             }
         }
-        fine[idx * 2] = (TO)re;
-        fine[idx * 2 + 1] = (TO)im;
-        return;
+        return make_double2(re, im);
     }
     for (int a2 = 0; a2 < n2; ++a2)
         for (int a1 = 0; a1 < n1; ++a1)
@@ -1080,22 +1073,21 @@ __global__ __launch_bounds__(256) void k_fold(Geo g, int np, const int32_t* cove
                 int64_t tile = cv[0][1 + 2 * a0];
                 int64_t off = cv[0][2 + 2 * a0];
                 if (D > 1) {
-                    tile += g.nt[0] * cv[1][1 + 2 * a1];
-                    off += g.pe[0] * cv[1][2 + 2 * a1];
+                    tile += fa.nt0 * cv[1][1 + 2 * a1];
+                    off += fa.pe0 * cv[1][2 + 2 * a1];
                 }
                 if (D > 2) {
-                    tile += g.nt[0] * g.nt[1] * cv[2][1 + 2 * a2];
-                    off += g.pe[0] * g.pe[1] * cv[2][2 + 2 * a2];
+                    tile += fa.nt0 * fa.nt1 * cv[2][1 + 2 * a2];
+                    off += fa.pe0 * fa.pe1 * cv[2][2 + 2 * a2];
                 }
-                const int j0 = job_off[tile], j1 = job_off[tile + 1];
-                const T* sg = subgrid + (int64_t)j0 * lsize + (p * g.Psub + off) * 2;
+                const int j0 = fa.job_off[tile], j1 = fa.job_off[tile + 1];
+                const T* sg = subgrid + (int64_t)j0 * lsize + (p * fa.Psub + off) * 2;
                 for (int jj = j0; jj < j1; ++jj, sg += lsize) {
                     re += (double)sg[0];
                     im += (double)sg[1];
                 }
             }
-    fine[idx * 2] = (TO)re;
-    fine[idx * 2 + 1] = (TO)im;
+    return make_double2(re, im);
 }
 
 // One radix-RAD Stockham stage (Govindaraju et al., SC'08 formulation):
@@ -1171,9 +1163,9 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
 // ---------------------------------------------------------------------------
 // Stockham FFT along the contiguous axis of `rows` rows, in LDS.
 // ---------------------------------------------------------------------------
-template <typename T, bool INV>
-__global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict__ in,
-                                             typename V2<T>::t* __restrict__ out, FftPass f) {
+template <typename T, bool INV, int FD = 0, typename TS = float>
+__global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restrict__ in,
+                                              typename V2<T>::t* __restrict__ out, FftPass f) {
     using C = typename V2<T>::t;
     extern __shared__ unsigned char smem_raw[];
     const int R = f.rows_per_block;
@@ -1201,6 +1193,21 @@ __global__ __launch_bounds__(256) void k_fft(const typename V2<T>::t* __restrict
             e = e >= F ? e - F : e;
             for (; e < nin; e += F) acc = cadd(acc, rowp[e]);
             buf0[q] = acc;
+        }
+    } else if constexpr (FD > 0) {
+        // fold the row from the subgrids (forward first pass, nin = F = Mr_0)
+        const int nin = (int)n_in;
+        const unsigned rest = (unsigned)f.fold_rest;
+        for (int q = threadIdx.x; q < nr * nin; q += blockDim.x) {
+            const int r = (int)((unsigned)q / (unsigned)nin), e = q - r * nin;
+            const unsigned row = (unsigned)(row0 + r);
+            const int p = (int)(row / rest);
+            const unsigned cell = (row - (unsigned)p * rest) * (unsigned)nin + (unsigned)e;
+            const double2 v = fold_at<FD, TS>(f.fold, p, cell);
+            C c;
+            c.x = (T)v.x;
+            c.y = (T)v.y;
+            buf0[r * F + e] = c;
         }
     } else {
         const int nin = (int)n_in;
@@ -2118,16 +2125,17 @@ void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, con
 #undef FKR_SPREAD
 }
 
-void launch_fold(const Geo& g, int prec, int tprec, int npairs, const int32_t* cover,
-                 const int32_t* job_off, const void* subgrid, void* fine, hipStream_t s) {
-    const int64_t n = g.Mrtot * npairs;
-#define FKR_FOLD(D, T, TO) k_fold<D, T, TO><<<nblk(n, 256), 256, 0, s>>>(g, npairs, cover, job_off, static_cast<const T*>(subgrid), static_cast<TO*>(fine))
-#define FKR_FOLD_D(T, TO) do { if (g.d == 1) FKR_FOLD(1, T, TO); else if (g.d == 2) FKR_FOLD(2, T, TO); else FKR_FOLD(3, T, TO); } while (0)
-    if (prec == FKR_F64) FKR_FOLD_D(double, double);
-    else if (tprec == FKR_F64) FKR_FOLD_D(float, double);
-    else FKR_FOLD_D(float, float);
-#undef FKR_FOLD_D
-#undef FKR_FOLD
+FoldArgs fold_args(const Geo& g, int npairs, const int32_t* cover, const int32_t* job_off, const void* subgrid) {
+    FoldArgs fa{};
+    fa.cover = cover;
+    fa.job_off = job_off;
+    fa.subgrid = subgrid;
+    fa.Psub = g.Psub;
+    fa.np = npairs;
+    fa.nt0 = g.nt[0]; fa.nt1 = g.nt[1];
+    fa.pe0 = g.pe[0]; fa.pe1 = g.pe[1];
+    for (int j = 0; j < 3; ++j) fa.Mr[j] = g.Mr[j];
+    return fa;
 }
 
 void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void* out, hipStream_t s) {
@@ -2138,6 +2146,27 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
     // row).  Measured: up to 8192 rows (2-D grids) at most two rows per
     // workgroup, with 512 workgroups first; beyond (3-D grids) as many rows
     // as the LDS holds, with 1024 workgroups first.
+    if (f.fold_d > 0 && !inverse) {
+        // rows folded from the subgrids: one element per thread, so each
+        // thread runs one fold chain; two rows per workgroup where they fit
+        int Rf = 2;
+        while (Rf > 1 && (Rf * f.F > 1024 || (size_t)2 * Rf * f.F * csz > 65536 || f.rows < (int64_t)Rf * 512)) Rf >>= 1;
+        f.rows_per_block = Rf;
+        const unsigned ntf = (unsigned)std::min<int64_t>(1024, (Rf * f.F + 63) / 64 * 64);
+        const size_t ldsf = (size_t)2 * Rf * f.F * csz;
+        const unsigned nbf = (unsigned)((f.rows + Rf - 1) / Rf);
+        if (nbf == 0) return;
+#define FKR_FFTF(T, D, TS) k_fft<T, false, D, TS><<<nbf, ntf, ldsf, s>>>(nullptr, static_cast<typename V2<T>::t*>(out), f)
+#define FKR_FFTF_D(T, TS) do { if (f.fold_d == 1) FKR_FFTF(T, 1, TS); else if (f.fold_d == 2) FKR_FFTF(T, 2, TS); else FKR_FFTF(T, 3, TS); } while (0)
+        if (prec == FKR_F64) {
+            if (f.fold_f64) FKR_FFTF_D(double, double); else FKR_FFTF_D(double, float);
+        } else {
+            FKR_FFTF_D(float, float);
+        }
+#undef FKR_FFTF_D
+#undef FKR_FFTF
+        return;
+    }
     const bool many = f.rows > 8192;
     int R = many ? 64 : 2;
     while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;

@@ -199,7 +199,6 @@ static void layout(fkr_plan* p) {
     L.perm = take(N * 4);
     L.xs = take(N * p->d * sz);
     L.subgrid = take((size_t)p->n_jobs_max * p->Psub * p->pairs_per_spread * csz);
-    L.fine = take((size_t)p->pairs_per_spread * p->Mrtot * tcsz);
     // FFT intermediates (complex elements)
     int64_t cap = 0;
     {
