@@ -250,7 +250,7 @@ typedef enum {
     FKR_STAGE_SPREAD = 2,    /* spreading onto tile subgrids (eq. 16-17)    */
     FKR_STAGE_FOLD = 3,      /* kept for numbering: the subgrids are summed into the fine grid by the first forward FFT pass (FKR_STAGE_FFT_FWD) */
     FKR_STAGE_FFT_FWD = 4,   /* forward FFT passes + deconvolution (eq. 19-20) */
-    FKR_STAGE_EXPAND = 5,    /* moment multipliers per channel (eq. 12-13)  */
+    FKR_STAGE_EXPAND = 5,    /* kept for numbering: the channel spectra are expanded by the first inverse FFT pass (FKR_STAGE_FFT_INV) */
     FKR_STAGE_FFT_INV = 6,   /* inverse FFT passes + crop (eq. 21)          */
     FKR_STAGE_SOLVE = 7,     /* per-grid-point solves (eq. 3 / 11)          */
     FKR_STAGE_REDUCE = 8,    /* interpolation + DF/RSS/variance reductions  */

@@ -219,12 +219,9 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     for (int j = 0; j < p->d; ++j) { a.h[j] = h[j]; a.T[j] = p->T[j]; }
     a.Btot = p->Btot;
     a.ill_clear = ill_clear;
-    {
-        StageTimer t(p, FKR_STAGE_EXPAND, s);
-        launch_expand2(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftA, s);
-    }
+    // the first inverse pass expands its rows from the pair spectra itself
     StageTimer tf(p, FKR_STAGE_FFT_INV, s);
-    const void* in = p->ws + p->lay.fftA;
+    const void* in = nullptr;
     int64_t done_M = 1;
     for (int j = 0; j < p->d; ++j) {
         FftPass f{};
@@ -241,6 +238,14 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         for (int q = 0; q < p->fL[j].nfac; ++q) f.fac[q] = p->fL[j].fac[q];
         f.tw = at<double>(p, p->fL[j].tw_off);
         f.fac_out = nullptr;
+        if (j == 0) {
+            f.exp_mode = 1;
+            f.exp_rest = rest;
+            f.ex = a;
+            f.exp_es = dev_es(p);
+            f.exp_et = dev_et(p);
+            f.exp_spec = p->ws + p->lay.spec;
+        }
         // row = (pair, m over the done dimensions, e over the rest) with the
         // pair outermost; the output keeps the pair outermost, so the last
         // pass writes the channels pair-major, [pair][M^d][re, im]
@@ -250,7 +255,7 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         f.out_rmul = done_M * p->M[j] * rest;
         void* out;
         if (j == p->d - 1) out = p->ws + p->lay.chan;
-        else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);
+        else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);   // fftA first
         launch_fft(p->tprec, true, f, in, out, s);
         in = out;
         done_M *= p->M[j];

@@ -44,6 +44,13 @@ struct SpreadSrc {
     WSrc w[2 * kMaxPairsPerSpread];
 };
 
+struct ExpandArgs {
+    int d, n_s, n_t, nreal, ncp, npairs;
+    int64_t B[3], K[3], Btot;
+    double h[3], T[3];       // bandwidth and period per dimension
+    unsigned long long* ill_clear;   // cleared by the launch when given
+};
+
 // What a fold needs: the fine cell (c_0, .., c_{d-1}) of pair p is the sum
 // over the padded tiles that cover it and the jobs of each such tile.
 struct FoldArgs {
@@ -77,14 +84,17 @@ struct FftPass {
     int fold_f64;                 // subgrid element type
     int64_t fold_rest;            // Mr_1 Mr_2
     FoldArgs fold;
+    // inverse first pass only: the input rows are expanded from the pair
+    // spectra (row = channel pair * rest + band index of dims 1.., element =
+    // band index of dim 0) instead of read
+    int exp_mode;
+    int64_t exp_rest;             // B_1 B_2
+    ExpandArgs ex;
+    const int* exp_es;
+    const int* exp_et;
+    const void* exp_spec;
 };
 
-struct ExpandArgs {
-    int d, n_s, n_t, nreal, ncp, npairs;
-    int64_t B[3], K[3], Btot;
-    double h[3], T[3];       // bandwidth and period per dimension
-    unsigned long long* ill_clear;   // cleared by the launch when given
-};
 
 struct SolveArgs {
     int P, n_s, n_t, ncp, nr;      // nr real weights incl. density
@@ -131,8 +141,6 @@ void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, con
 FoldArgs fold_args(const Geo& g, int npairs, const int32_t* cover, const int32_t* job_off, const void* subgrid);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
-void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
-                    void* out, hipStream_t s);
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);
 void launch_unpack_spec(int prec, int64_t Btot, const int64_t* B, int d, int npairs, int nw,
                         const void* spec, double* out, hipStream_t s);

@@ -5,15 +5,17 @@
 //   spread                 gridding of eq. (16)-(17): every sample adds its
 //                          kernel footprint into an LDS copy of its padded tile
 //                          (no global atomics)
-//   fold                   sums the padded tiles into the periodic fine grid
 //   fft pass               mixed-radix Stockham FFT along one axis in LDS,
 //                          forward (eq. 19, keeping the retained band and
 //                          dividing by the gridding kernel's transform, eq. 20)
-//                          or inverse (eq. 21, zero-padded band -> grid rows)
-//   expand                 kernel-moment spectra x data spectrum (eq. 12-13 in
-//                          the frequency domain), two real channels per complex
+//                          or inverse (eq. 21, zero-padded band -> grid rows).
+//                          The first forward pass folds its rows (the padded
+//                          tiles summed into the periodic fine grid); the
+//                          first inverse pass expands its rows (kernel-moment
+//                          spectra x data spectrum, eq. 12-13 in the frequency
+//                          domain, two real channels per complex)
 //   solve                  per-grid-point FP64 normal equations (eq. 3 / 11)
-//   reduce items           interpolation to the samples with the Girard and
+//   reduce                 interpolation to the samples with the Girard and
 //                          residual dot products (Sec. 2.1, eq. 22)
 #include <hip/hip_runtime.h>
 
@@ -1163,7 +1165,7 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
 // ---------------------------------------------------------------------------
 // Stockham FFT along the contiguous axis of `rows` rows, in LDS.
 // ---------------------------------------------------------------------------
-template <typename T, bool INV, int FD = 0, typename TS = float>
+template <typename T, bool INV, int FD = 0, typename TS = float, bool EXP = false>
 __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restrict__ in,
                                               typename V2<T>::t* __restrict__ out, FftPass f) {
     using C = typename V2<T>::t;
@@ -1183,15 +1185,26 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
         // for the values at the F output points.
         // (32-bit index arithmetic: a block's rows hold well under 2^31 elements)
         const int kin = (int)(f.K % F), nin = (int)n_in;
+        if (EXP && blockIdx.x == 0 && threadIdx.x == 0 && f.ex.ill_clear) *f.ex.ill_clear = 0ull;
         for (int q = threadIdx.x; q < nr * F; q += blockDim.x) {
             const int r = (int)((unsigned)q / (unsigned)F), pos = q - r * F;
             C acc;
             acc.x = 0;
             acc.y = 0;
-            const C* rowp = in + (row0 + r) * n_in;
             int e = pos + kin;
             e = e >= F ? e - F : e;
-            for (; e < nin; e += F) acc = cadd(acc, rowp[e]);
+            if constexpr (EXP) {
+                // the channel spectra of the row are expanded here from the
+                // pair spectra: row = pair c * rest + band index of the rest
+                const unsigned row = (unsigned)(row0 + r), rest = (unsigned)f.exp_rest;
+                const int c = (int)(row / rest);
+                const unsigned nb0 = (row - (unsigned)c * rest) * (unsigned)nin;
+                const C* sp = static_cast<const C*>(f.exp_spec);
+                for (; e < nin; e += F) acc = cadd(acc, expand_at<T>(f.ex, f.exp_es, f.exp_et, sp, c, nb0 + (unsigned)e));
+            } else {
+                const C* rowp = in + (row0 + r) * n_in;
+                for (; e < nin; e += F) acc = cadd(acc, rowp[e]);
+            }
             buf0[q] = acc;
         }
     } else if constexpr (FD > 0) {
@@ -1259,7 +1272,7 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
 // ---------------------------------------------------------------------------
 // Kernel-moment spectra (Hermite form of the Gaussian's moment transforms):
 // per dimension j, He_a(h_j w) exp(-(h_j w)^2/2) / T_j, w = 2 pi (e-K_j)/T_j,
-// evaluated where k_expand needs it.  The phase i^a is applied in k_expand;
+// evaluated where expand_at needs it.  The phase i^a is applied in expand_at;
 // the division by h^a (equilibration) is implicit in using He_a(h w) without
 // the h^a factor.
 // ---------------------------------------------------------------------------
@@ -1277,15 +1290,9 @@ __device__ __forceinline__ double moment_mult(double hj, double Tj, int64_t Kj, 
 // Y_c(n) = X_{2c}(n) + i X_{2c+1}(n), X_ch = C_r(n) i^{|a|} prod_j mult_j[a_j](n_j),
 // with C_r unpacked from the pair spectra Z_p = C_{2p} + i C_{2p+1}.
 template <typename T>
-__global__ __launch_bounds__(256) void k_expand(ExpandArgs a, const int* es, const int* et,
-                                                const typename V2<T>::t* spec,
-                                                typename V2<T>::t* out) {
+__device__ __forceinline__ typename V2<T>::t expand_at(const ExpandArgs& a, const int* es, const int* et,
+                                                       const typename V2<T>::t* spec, int c, unsigned n) {
     using C = typename V2<T>::t;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0 && a.ill_clear) *a.ill_clear = 0ull;   // the call's solves count from here
-    if (idx >= a.Btot * a.ncp) return;
-    const int c = (int)((uint64_t)idx / (uint64_t)a.Btot);
-    const unsigned n = (unsigned)(idx - (int64_t)c * a.Btot);
     int e[3] = {0, 0, 0};
     unsigned nn = 0, rem = n, stride = 1;
     for (int j = 0; j < a.d; ++j) {
@@ -1329,7 +1336,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, const int* es, con
     C o;
     o.x = (T)acc_re;
     o.y = (T)acc_im;
-    out[idx] = o;
+    return o;
 }
 
 // ---------------------------------------------------------------------------
@@ -2167,6 +2174,21 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
 #undef FKR_FFTF
         return;
     }
+    if (f.exp_mode && inverse) {
+        // first inverse pass with the expansion in its loader: same rows
+        // per workgroup rule as below
+        int R = 2;
+        while (R > 1 && ((size_t)2 * R * f.F * csz > 65536 || f.rows < (int64_t)R * 512)) R >>= 1;
+        f.rows_per_block = R;
+        const size_t ldse = (size_t)2 * R * f.F * csz;
+        const unsigned nbe = (unsigned)((f.rows + R - 1) / R);
+        if (nbe == 0) return;
+        if (prec == FKR_F64)
+            k_fft<double, true, 0, float, true><<<nbe, 256, ldse, s>>>(nullptr, static_cast<double2*>(out), f);
+        else
+            k_fft<float, true, 0, float, true><<<nbe, 256, ldse, s>>>(nullptr, static_cast<float2*>(out), f);
+        return;
+    }
     const bool many = f.rows > 8192;
     int R = many ? 64 : 2;
     while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;
@@ -2183,15 +2205,6 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
         if (inverse) k_fft<float, true><<<nb, nt, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
         else k_fft<float, false><<<nb, nt, lds, s>>>(static_cast<const float2*>(in), static_cast<float2*>(out), f);
     }
-}
-
-void launch_expand2(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec,
-                    void* out, hipStream_t s) {
-    const int64_t n = a.Btot * a.ncp;
-    if (prec == FKR_F64)
-        k_expand<double><<<nblk(n), 256, 0, s>>>(a, es, et, static_cast<const double2*>(spec), static_cast<double2*>(out));
-    else
-        k_expand<float><<<nblk(n), 256, 0, s>>>(a, es, et, static_cast<const float2*>(spec), static_cast<float2*>(out));
 }
 
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s) {
