@@ -2077,10 +2077,12 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
             if (rows) {
                 const int nw = 2 * src.npairs;
                 if constexpr (D == 2 && W <= 8) {
-                    // few weight columns: the lane-group kernel (3 samples per
-                    // wave step) wins; many: the one-sample-per-wave kernel
+                    // four weight columns: the lane-group kernel (3 samples per
+                    // wave step) wins; two or more than four: the
+                    // one-sample-per-wave kernel (measured)
                     switch (nw) {
-                        case 2: case 4: spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 2: spread_wave<W, KER, 2>(g, src, loc, frac, jobs, nb, subgrid, s); break;
+                        case 4: spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s); break;
                         case 6: spread_wave<W, KER, 6>(g, src, loc, frac, jobs, nb, subgrid, s); break;
                         case 8: spread_wave<W, KER, 8>(g, src, loc, frac, jobs, nb, subgrid, s); break;
                         case 10: spread_wave<W, KER, 10>(g, src, loc, frac, jobs, nb, subgrid, s); break;
