@@ -279,7 +279,7 @@ def main() -> int:
     spread_s = spread_ms * 1e-3 / args.steps
     achieved = flops_step / spread_s / 1e12
     hbm_achieved = bytes_step / spread_s / 1e9
-    roofline = {"bound": "alu", "kernel": "spread: k_spread_wave (cv, 12 columns) + k_spread_group (variance, 2 columns)",
+    roofline = {"bound": "alu", "kernel": "spread: k_spread_wave (cv, 12 columns; variance, 2 columns)",
                 "achieved": round(achieved, 2), "peak": FP32_FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_FMA_PEAK_TFLOPS, 4),
                 "traffic": _traffic(launches_per_step),
