@@ -207,7 +207,7 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-// Channels of bandwidth index hi: expand + inverse FFT -> chan [M][ncp].
+// Channels at one bandwidth h: expansion + inverse FFT -> chan [pair][M][re, im].
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
