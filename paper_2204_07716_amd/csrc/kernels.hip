@@ -1756,16 +1756,20 @@ __global__ void k_zero(uint32_t* p, int64_t n) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, int r0, int nr,
                                                        int64_t N, const int32_t* perm, T* out) {
+    // one sample per thread; when the launch writes whole rows (nsrc == nr)
+    // the rows of each wave go out through LDS as one contiguous block
+    __shared__ __align__(16) T stg[256 * 2 * kMaxPairsPerSpread];
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    const int64_t i = perm[s];
+    const bool whole = nsrc == nr;
+    if (s >= N && !whole) return;
+    const int64_t i = s < N ? perm[s] : 0;
     uint64_t cached_seed = 0, cached_g = ~0ull;
     T z[4] = {0, 0, 0, 0};
     T vals[2 * kMaxPairsPerSpread];
 #pragma unroll
     for (int q = 0; q < 2 * kMaxPairsPerSpread; ++q) {
         vals[q] = (T)0;
-        if (q >= nsrc) continue;
+        if (q >= nsrc || s >= N) continue;
         const WSrc& w = src.w[q];
         double v;
         if (w.kind == W_PHILOX) {
@@ -1784,9 +1788,30 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
         }
         vals[q] = (T)v;
     }
-    // the row chunk is written with 16-byte stores (nsrc, r0 and nr are
-    // multiples of 4 for T = float, of 2 for T = double)
+    // 16-byte stores (nsrc, r0 and nr are multiples of 4 for T = float, of 2
+    // for T = double)
     constexpr int VW = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    if (whole) {
+        // the wave's rows [s0, s0 + 64) are contiguous in `out`: stage them in
+        // LDS and store 16-byte chunks with consecutive lanes on consecutive
+        // chunks
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        T* w = stg + wv * 64 * 2 * kMaxPairsPerSpread;
+#pragma unroll
+        for (int q = 0; q < 2 * kMaxPairsPerSpread; ++q)
+            if (q < nsrc) w[lane * nsrc + q] = vals[q];
+        __syncthreads();
+        const int64_t s0 = s - lane;
+        const int64_t nrows = min<int64_t>(64, N - s0);
+        if (nrows > 0) {
+            const int nv = (int)(nrows * nr / VW);
+            V* dst = reinterpret_cast<V*>(out + s0 * nr);
+            const V* src4 = reinterpret_cast<const V*>(w);
+            for (int k = lane; k < nv; k += 64) dst[k] = src4[k];
+        }
+        return;
+    }
     T* dst = out + s * nr + r0;
 #pragma unroll
     for (int q = 0; q < 2 * kMaxPairsPerSpread; q += VW) {
