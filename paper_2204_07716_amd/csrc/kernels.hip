@@ -465,12 +465,23 @@ __global__ __launch_bounds__(1024) void k_cell_scan(Geo g, const int32_t* tile_o
 // packed first cell, fractions, clamped coordinates and the original index.
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
-                                                      const int32_t* off, uint32_t* loc, T* frac, int32_t* perm,
-                                                      T* xs) {
-    extern __shared__ int32_t cur[];
+                                                      const int32_t* off, const int32_t* tile_off,
+                                                      const int32_t* job_off, int stage, uint32_t* loc, T* frac,
+                                                      int32_t* perm, T* xs) {
+    extern __shared__ int32_t cur[];   // [ncell] cursors, then the staged output (stage != 0)
     const int job = blockIdx.x;
     if (job >= jobs[0]) return;
     const int32_t* jd = jobs + 4 + 4 * job;
+    const int tile = jd[0];
+    // a tile with one job owns the output range [tile_off, tile_off + n):
+    // the records are placed in LDS and leave as contiguous runs
+    const bool single = stage && job_off[tile + 1] - job_off[tile] == 1;
+    const int64_t base = tile_off[tile];
+    const int n = jd[2] - jd[1];
+    uint32_t* sl_loc = reinterpret_cast<uint32_t*>(cur + g.ncell);
+    int32_t* sl_perm = reinterpret_cast<int32_t*>(sl_loc + g.chunk);
+    T* sl_frac = reinterpret_cast<T*>(sl_perm + g.chunk);
+    T* sl_xs = sl_frac + (int64_t)g.chunk * D;
     for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = off[(int64_t)job * g.ncell + c];
     __syncthreads();
     for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
@@ -483,12 +494,34 @@ __global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs
         }
         const uint32_t l = r.w[1];
         const int64_t pos = atomicAdd(&cur[local_cell<D>(g, l)], 1);
-        loc[pos] = l;
-        perm[pos] = (int32_t)r.w[0];
+        if (single) {
+            const int k = (int)(pos - base);
+            sl_loc[k] = l;
+            sl_perm[k] = (int32_t)r.w[0];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            frac[pos * D + j] = r.at(j);
-            xs[pos * D + j] = r.at(D + j);
+            for (int j = 0; j < D; ++j) {
+                sl_frac[k * D + j] = r.at(j);
+                sl_xs[k * D + j] = r.at(D + j);
+            }
+        } else {
+            loc[pos] = l;
+            perm[pos] = (int32_t)r.w[0];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                frac[pos * D + j] = r.at(j);
+                xs[pos * D + j] = r.at(D + j);
+            }
+        }
+    }
+    if (single) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            loc[base + k] = sl_loc[k];
+            perm[base + k] = sl_perm[k];
+        }
+        for (int k = threadIdx.x; k < n * D; k += blockDim.x) {
+            frac[base * D + k] = sl_frac[k];
+            xs[base * D + k] = sl_xs[k];
         }
     }
 }
@@ -1917,8 +1950,12 @@ static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, in
     // one thread per cell of a tile (64 in 2-D), at most 1024
     const unsigned nts = (unsigned)std::min(1024, std::max(64, (g.ncell + 63) / 64 * 64));
     k_cell_scan<<<(unsigned)g.n_tiles, nts, ((size_t)g.ncell + nts) * 4, s>>>(g, tile_off, job_off, cnt, off);
-    k_cell_scatter<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, off, loc, static_cast<T*>(frac), perm,
-                                                              static_cast<T*>(xs));
+    // staging of single-job tiles when the job's records fit the LDS budget
+    const size_t stage_bytes = (size_t)g.chunk * (8 + 2 * D * sizeof(T));
+    const int stage = (size_t)g.ncell * 4 + stage_bytes <= 65536 ? 1 : 0;
+    const size_t lds_cs = (size_t)g.ncell * 4 + (stage ? stage_bytes : 0);
+    k_cell_scatter<D, T><<<nj, 256, lds_cs, s>>>(g, jobs, trec, off, tile_off, job_off, stage, loc,
+                                                 static_cast<T*>(frac), perm, static_cast<T*>(xs));
 }
 
 size_t tile_record_bytes(int d, int prec) {
