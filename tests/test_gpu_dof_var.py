@@ -122,3 +122,33 @@ def test_complex_response_cv(orc):
     yhat = orc.interp(ref[:, 0], M, (0, 0), (1, 1), X)
     rss_ref = np.sum(np.abs(y32 - yhat) ** 2)
     assert abs(out["rss"].cpu().numpy()[0, 0] / rss_ref - 1) < 1e-5
+
+
+def test_cv_many_probes_two_responses(orc):
+    """More weight vectors than one spreading launch or one reduction launch
+    holds (2 responses + 20 probes: the rows are staged in two column chunks,
+    the spread runs in two launches of at most 8 pairs, the reduction in two
+    probe launches, the fit rows without the response column): DF, RSS and
+    GCV against the oracle with identical probes."""
+    N, Np, seed = 2500, 20, 9
+    X, y = _data(430, N, 2)
+    y2 = np.cos(2 * X[:, 0]) + 0.1 * np.random.default_rng(431).standard_normal(N)
+    Y = np.stack([y, y2], axis=1)
+    M, h = (36, 32), (0.09, 0.1)
+    plan = make_plan(2, 1, M, h, h, 1e-6, "fp32", n_max=N, max_weights=1 + 2 + Np, tprec="fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    out = plan.cv(h, to_dev(Y, torch.float32), Np, seed=seed)
+    rho = out["rho"].cpu().numpy()[0]
+    rss = out["rss"].cpu().numpy()[0]
+    gcv = out["gcv"].cpu().numpy()[0]
+    probes = orc.probes(seed, N, Np)
+    r_ref, mean, _ = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+    assert np.abs(rho - r_ref).max() < 1e-6
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    for c in range(2):
+        mh = orc.fit(X, Y[:, c], h, 1, gp)
+        yhat = orc.interp(mh[:, 0], M, (0, 0), (1, 1), X)
+        rss_ref = np.sum((Y[:, c] - yhat) ** 2)
+        assert abs(rss[c] / rss_ref - 1) < 1e-5
+        g_ref = orc.gcv(Y[:, c], yhat, mean)[0]
+        assert abs(gcv[c] / g_ref - 1) < 1e-5
