@@ -19,17 +19,21 @@ weight vector through spread + FFT + solve (1 response + 10 probes + 1
 variance pass = 12 per step).  The ``roofline`` object reports the spreading
 kernel (the largest single kernel of the step) against FP32 FMA issue with its
 algorithmic flops per launch, and against HBM bandwidth with its algorithmic
-bytes, timed with HIP events that the library records on the launch stream; ``cpu_baseline`` times the FP64 oracle on a bounded
-sample of grid points and extrapolates to the full grid; ``accuracy`` compares
-the GPU grids with the oracle on that same sample.
+bytes, timed with HIP events that the library records on the launch stream;
+``warm`` times the same step without set_points (X already sorted);
+``hbm_model`` sets the step's algorithmic bytes against HBM bandwidth;
+``cpu_baseline`` times the FP64 oracle on a bounded sample of grid points and
+extrapolates to the full grid; ``accuracy`` compares the GPU grids with the
+oracle on that same sample.
 
 By default the timed steps replay a HIP graph captured from one step (the
-step's ~45 kernel launches are launch-bound on the host otherwise); before
+step's ~30 kernel launches are launch-bound on the host otherwise); before
 timing, three replays are compared with eager steps.  ``--eager`` times
 host-launched steps instead.  Stage times always come from eager steps, where
 the library brackets every launch with HIP events on the launch stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--transform fp64|fp32] [--eager]
+                       [--no-warm] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
