@@ -221,7 +221,15 @@ fkr_status fkr_cv(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
  *       [mean_i r_i exp(-v(x_i))]^-1; sigma^2(g) = exp(v(g)) / kappa;
  *   FKR_VAR_DIRECT (eq. 23): sigma^2(g) = fit of r_i.
  * The fit uses the plan's order.  sigma2_dev: [M^d] doubles; vhat_dev
- * (optional, FKR_VAR_LOG) [M^d]; kappa_dev (optional) 1 double. */
+ * (optional, FKR_VAR_LOG) [M^d]; kappa_dev (optional) 1 double.
+ * The density moments s_alpha of the second fit equal those of the first
+ * (same points, same h): when the plan's last fkr_fit, fkr_cv, fkr_moments
+ * or fkr_variance call ran at a bandwidth bitwise equal to h, on the points
+ * of the last fkr_set_points, and C(d+2l, 2l) is even, the call keeps them
+ * from the plan's channel buffer and transforms only the moments t_alpha of
+ * the new weights.  This choice is made on the host when the call is
+ * enqueued; a graph that captured the call must replay it after the same
+ * preceding call. */
 fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const void* Y_dev,
                         int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
                         double* vhat_dev, double* kappa_dev, void* stream);

@@ -208,12 +208,30 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
 }
 
 // Channels at one bandwidth h: expansion + inverse FFT -> chan [pair][M][re, im].
-fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s) {
+// True when the channel buffer holds the density moments of the current
+// points at bandwidth h (bitwise equal h), left there by the last fit, cv,
+// moments or variance call.
+bool reuse_density_channels(const fkr_plan* p, const double* h) {
+    if (!p->schan_valid || p->n_s % 2 != 0) return false;
+    for (int j = 0; j < p->d; ++j)
+        if (p->schan_h[j] != h[j]) return false;
+    return true;
+}
+
+// Channel pairs c0 .. ncp - 1 of bandwidth h into the channel buffer (pair
+// c at pair offset c).  Weight 0 of the spectra is the density in every
+// caller, so afterwards the first n_s / 2 pairs hold its moments s_alpha at h.
+fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
+                        int c0 = 0) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
-    if (ncp > p->ncp_max) return FKR_E_ARG;
+    if (ncp > p->ncp_max || c0 < 0 || c0 >= ncp) return FKR_E_ARG;
+    if (c0 > 0 && !reuse_density_channels(p, h)) return FKR_E_ARG;
+    p->schan_valid = false;
+    const int nout = ncp - c0;
     ExpandArgs a{};
     a.d = p->d; a.n_s = p->n_s; a.n_t = p->n_t; a.nreal = nreal; a.ncp = ncp;
+    a.c0 = c0;
     a.npairs = (nr + 1) / 2;
     for (int j = 0; j < 3; ++j) { a.B[j] = p->B[j]; a.K[j] = p->K[j]; }
     for (int j = 0; j < p->d; ++j) { a.h[j] = h[j]; a.T[j] = p->T[j]; }
@@ -227,7 +245,7 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         FftPass f{};
         int64_t rest = 1;
         for (int i = j + 1; i < p->d; ++i) rest *= p->B[i];
-        f.rows = done_M * ncp * rest;
+        f.rows = done_M * nout * rest;
         f.n_in = p->B[j];
         f.F = p->L[j];
         f.n_out = p->M[j];
@@ -254,13 +272,18 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         f.out_rdiv = done_M * rest;
         f.out_rmul = done_M * p->M[j] * rest;
         void* out;
-        if (j == p->d - 1) out = p->ws + p->lay.chan;
+        if (j == p->d - 1) out = p->ws + p->lay.chan + (size_t)c0 * p->Mtot * 2 * (p->tprec == FKR_F64 ? 8 : 4);
         else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);   // fftA first
         launch_fft(p->tprec, true, f, in, out, s);
         in = out;
         done_M *= p->M[j];
     }
-    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+    if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
+    if (p->n_s % 2 == 0) {
+        p->schan_valid = true;
+        for (int j = 0; j < 3; ++j) p->schan_h[j] = j < p->d ? h[j] : 0.0;
+    }
+    return FKR_OK;
 }
 
 double s0_floor(const fkr_plan* p, const double* h) {
@@ -376,6 +399,7 @@ fkr_status fkr_set_workspace(fkr_plan* p, void* ws, size_t bytes) {
     p->ws_bytes = bytes;
     p->ws_ready = false;
     p->points_set = false;
+    p->schan_valid = false;
     std::vector<unsigned char> consts(4096, 0);
     double* per = reinterpret_cast<double*>(consts.data());
     for (int j = 0; j < p->d; ++j) per[j] = p->T[j];
@@ -411,6 +435,7 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     if (!p) return FKR_E_ARG;
     if (!p->ws_ready) return FKR_E_WORKSPACE;
     if (N < 0 || N > p->n_max || (N > 0 && !X) || !valid_type(x_type)) return FKR_E_ARG;
+    p->schan_valid = false;
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
     StageTimer t(p, FKR_STAGE_SORT, s);
@@ -608,7 +633,11 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
         srcs[r].stride = 4; srcs[r].col = r;
     }
     if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
-    if ((st = run_channels(p, h, 2, ill_ctr(p), s)) != FKR_OK) return st;
+    // The density moments s_alpha depend on the points and h only: when the
+    // plan's last fit (or cv, moments, variance) at this h left them in the
+    // channel buffer, only the pairs of the moments t_alpha of z are made.
+    const int c0 = reuse_density_channels(p, h) ? p->n_s / 2 : 0;
+    if ((st = run_channels(p, h, 2, ill_ctr(p), s, c0)) != FKR_OK) return st;
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
     a.y_out = v;

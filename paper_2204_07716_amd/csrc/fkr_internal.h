@@ -102,6 +102,10 @@ struct fkr_plan {
     bool ws_ready = false;
     bool points_set = false;
     int64_t N = 0;
+    // The channel buffer's first n_s / 2 pairs hold the density moments
+    // s_alpha at bandwidth schan_h of the current points (n_s even only).
+    bool schan_valid = false;
+    double schan_h[3] = {0.0, 0.0, 0.0};
     void* last_stream = nullptr;
     // stage timing (fkr_profile_enable / fkr_profile_read)
     bool prof_on = false;

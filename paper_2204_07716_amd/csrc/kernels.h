@@ -46,6 +46,7 @@ struct SpreadSrc {
 
 struct ExpandArgs {
     int d, n_s, n_t, nreal, ncp, npairs;
+    int c0;                  // first channel pair expanded (row pair c is channel pair c0 + c)
     int64_t B[3], K[3], Btot;
     double h[3], T[3];       // bandwidth and period per dimension
     unsigned long long* ill_clear;   // cleared by the launch when given

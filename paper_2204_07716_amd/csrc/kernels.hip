@@ -1230,8 +1230,8 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
                 // the channel spectra of the row are expanded here from the
                 // pair spectra: row = pair c * rest + band index of the rest
                 const unsigned row = (unsigned)(row0 + r), rest = (unsigned)f.exp_rest;
-                const int c = (int)(row / rest);
-                const unsigned nb0 = (row - (unsigned)c * rest) * (unsigned)nin;
+                const int cr = (int)(row / rest), c = f.ex.c0 + cr;
+                const unsigned nb0 = (row - (unsigned)cr * rest) * (unsigned)nin;
                 const C* sp = static_cast<const C*>(f.exp_spec);
                 for (; e < nin; e += F) acc = cadd(acc, expand_at<T>(f.ex, f.exp_es, f.exp_et, sp, c, nb0 + (unsigned)e));
             } else {
