@@ -463,26 +463,73 @@ __global__ __launch_bounds__(1024) void k_cell_scan(Geo g, const int32_t* tile_o
 
 // Per job: move every tile-ordered record to its (tile, cell) position: the
 // packed first cell, fractions, clamped coordinates and the original index.
+// When the job's records fit the LDS budget they are first placed in the
+// job's own cell order in LDS (job-local offsets from an exclusive scan of
+// its cell counts) and leave as runs: a cell's samples of one job are
+// contiguous in the output, from off[job][cell] on.
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
-                                                      const int32_t* off, const int32_t* tile_off,
-                                                      const int32_t* job_off, int stage, uint32_t* loc, T* frac,
+                                                      const int32_t* cnt, const int32_t* off,
+                                                      const int32_t* tile_off, int stage, uint32_t* loc, T* frac,
                                                       int32_t* perm, T* xs) {
-    extern __shared__ int32_t cur[];   // [ncell] cursors, then the staged output (stage != 0)
+    // [ncell] cursors; staged: then [ncell] output bases, [256] scan scratch
+    // and the staged records
+    extern __shared__ int32_t cur[];
     const int job = blockIdx.x;
     if (job >= jobs[0]) return;
     const int32_t* jd = jobs + 4 + 4 * job;
-    const int tile = jd[0];
-    // a tile with one job owns the output range [tile_off, tile_off + n):
-    // the records are placed in LDS and leave as contiguous runs
-    const bool single = stage && job_off[tile + 1] - job_off[tile] == 1;
-    const int64_t base = tile_off[tile];
     const int n = jd[2] - jd[1];
-    uint32_t* sl_loc = reinterpret_cast<uint32_t*>(cur + g.ncell);
+    const int32_t* joff = off + (int64_t)job * g.ncell;
+    if (!stage) {
+        for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = joff[c];
+        __syncthreads();
+        for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
+            TileRec<D, T> r;
+            const uint4* src = reinterpret_cast<const uint4*>(trec + s);
+#pragma unroll
+            for (int k = 0; k < TileRec<D, T>::WORDS / 4; ++k) {
+                const uint4 v = src[k];
+                r.w[4 * k] = v.x; r.w[4 * k + 1] = v.y; r.w[4 * k + 2] = v.z; r.w[4 * k + 3] = v.w;
+            }
+            const uint32_t l = r.w[1];
+            const int64_t pos = atomicAdd(&cur[local_cell<D>(g, l)], 1);
+            loc[pos] = l;
+            perm[pos] = (int32_t)r.w[0];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                frac[pos * D + j] = r.at(j);
+                xs[pos * D + j] = r.at(D + j);
+            }
+        }
+        return;
+    }
+    int32_t* gb = cur + g.ncell;
+    int32_t* scan = gb + g.ncell;
+    uint32_t* sl_loc = reinterpret_cast<uint32_t*>(scan + 256);
     int32_t* sl_perm = reinterpret_cast<int32_t*>(sl_loc + g.chunk);
     T* sl_frac = reinterpret_cast<T*>(sl_perm + g.chunk);
     T* sl_xs = sl_frac + (int64_t)g.chunk * D;
-    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = off[(int64_t)job * g.ncell + c];
+    // exclusive scan of the job's cell counts: thread t owns cells
+    // [t per, (t + 1) per), block scan of the thread sums
+    const int32_t* jcnt = cnt + (int64_t)job * g.ncell;
+    const int per = (g.ncell + 255) / 256;
+    const int c_beg = min(g.ncell, (int)threadIdx.x * per), c_end = min(g.ncell, c_beg + per);
+    int sum = 0;
+    for (int c = c_beg; c < c_end; ++c) sum += jcnt[c];
+    scan[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int v = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = scan[threadIdx.x] - sum;
+    for (int c = c_beg; c < c_end; ++c) {
+        cur[c] = run;
+        gb[c] = joff[c] - run;
+        run += jcnt[c];
+    }
     __syncthreads();
     for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
         TileRec<D, T> r;
@@ -493,35 +540,29 @@ __global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs
             r.w[4 * k] = v.x; r.w[4 * k + 1] = v.y; r.w[4 * k + 2] = v.z; r.w[4 * k + 3] = v.w;
         }
         const uint32_t l = r.w[1];
-        const int64_t pos = atomicAdd(&cur[local_cell<D>(g, l)], 1);
-        if (single) {
-            const int k = (int)(pos - base);
-            sl_loc[k] = l;
-            sl_perm[k] = (int32_t)r.w[0];
+        const int k = atomicAdd(&cur[local_cell<D>(g, l)], 1);
+        if (k >= n) continue;   // counts inconsistent with the records: never taken
+        sl_loc[k] = l;
+        sl_perm[k] = (int32_t)r.w[0];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                sl_frac[k * D + j] = r.at(j);
-                sl_xs[k * D + j] = r.at(D + j);
-            }
-        } else {
-            loc[pos] = l;
-            perm[pos] = (int32_t)r.w[0];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                frac[pos * D + j] = r.at(j);
-                xs[pos * D + j] = r.at(D + j);
-            }
+        for (int j = 0; j < D; ++j) {
+            sl_frac[k * D + j] = r.at(j);
+            sl_xs[k * D + j] = r.at(D + j);
         }
     }
-    if (single) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            loc[base + k] = sl_loc[k];
-            perm[base + k] = sl_perm[k];
-        }
-        for (int k = threadIdx.x; k < n * D; k += blockDim.x) {
-            frac[base * D + k] = sl_frac[k];
-            xs[base * D + k] = sl_xs[k];
+    __syncthreads();
+    const int tile = jd[0];
+    const int64_t tlo = tile_off[tile], thi = tile_off[tile + 1];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const uint32_t l = sl_loc[k];
+        const int64_t pos = (int64_t)gb[local_cell<D>(g, l)] + k;
+        if (pos < tlo || pos >= thi) continue;
+        loc[pos] = l;
+        perm[pos] = sl_perm[k];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            frac[pos * D + j] = sl_frac[k * D + j];
+            xs[pos * D + j] = sl_xs[k * D + j];
         }
     }
 }
@@ -1194,6 +1235,11 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
         for (int q = 0; q < RAD; ++q) b[base + q * Ns] = y[q];
     }
 }
+
+// Channel spectrum pair c at band index n (defined with the moment multipliers below).
+template <typename T>
+__device__ __forceinline__ typename V2<T>::t expand_at(const ExpandArgs& a, const int* es, const int* et,
+                                                       const typename V2<T>::t* spec, int c, unsigned n);
 
 // ---------------------------------------------------------------------------
 // Stockham FFT along the contiguous axis of `rows` rows, in LDS.
@@ -1950,11 +1996,11 @@ static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, in
     // one thread per cell of a tile (64 in 2-D), at most 1024
     const unsigned nts = (unsigned)std::min(1024, std::max(64, (g.ncell + 63) / 64 * 64));
     k_cell_scan<<<(unsigned)g.n_tiles, nts, ((size_t)g.ncell + nts) * 4, s>>>(g, tile_off, job_off, cnt, off);
-    // staging of single-job tiles when the job's records fit the LDS budget
-    const size_t stage_bytes = (size_t)g.chunk * (8 + 2 * D * sizeof(T));
-    const int stage = (size_t)g.ncell * 4 + stage_bytes <= 65536 ? 1 : 0;
-    const size_t lds_cs = (size_t)g.ncell * 4 + (stage ? stage_bytes : 0);
-    k_cell_scatter<D, T><<<nj, 256, lds_cs, s>>>(g, jobs, trec, off, tile_off, job_off, stage, loc,
+    // records staged in LDS (job-local cell order) when they fit the budget
+    const size_t stage_bytes = (size_t)g.ncell * 8 + 256 * 4 + (size_t)g.chunk * (8 + 2 * D * sizeof(T));
+    const int stage = stage_bytes <= 65536 ? 1 : 0;
+    const size_t lds_cs = stage ? stage_bytes : (size_t)g.ncell * 4;
+    k_cell_scatter<D, T><<<nj, 256, lds_cs, s>>>(g, jobs, trec, cnt, off, tile_off, stage, loc,
                                                  static_cast<T*>(frac), perm, static_cast<T*>(xs));
 }
 
