@@ -186,31 +186,39 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(Geo g, int x_type, c
             bhist[(int64_t)blockIdx.x * g.n_tiles + t] = hist[t];
 }
 
-// Column prefix of the block x tile count matrix: for tile t (one block per
-// tile), bhist[b][t] becomes the number of samples of t in blocks before b and
-// counts[t] the total, so each binning block owns a fixed, ordered range of
-// every tile.
-__global__ __launch_bounds__(256) void k_tile_prefix(int64_t n_tiles, int nblocks, int32_t* bhist,
-                                                     int32_t* counts) {
-    __shared__ int32_t sh[256];
-    const int64_t t = blockIdx.x;
-    int carry = 0;
-    for (int b0 = 0; b0 < nblocks; b0 += 256) {
-        const int b = b0 + (int)threadIdx.x;
-        const int v = b < nblocks ? bhist[(int64_t)b * n_tiles + t] : 0;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const int x = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += x;
-            __syncthreads();
-        }
-        if (b < nblocks) bhist[(int64_t)b * n_tiles + t] = carry + sh[threadIdx.x] - v;
-        carry += sh[255];
-        __syncthreads();
+// Column prefix of the block x tile count matrix: for tile t, bhist[b][t]
+// becomes the number of samples of t in blocks before b and counts[t] the
+// total, so each binning block owns a fixed, ordered range of every tile.
+// A workgroup takes 64 consecutive tiles, one per lane, so every row of the
+// matrix is read and written as one contiguous run; its 16 waves take
+// consecutive ranges of rows and start from the totals of the ranges before.
+__global__ __launch_bounds__(1024) void k_tile_prefix(int64_t n_tiles, int nblocks, int32_t* bhist,
+                                                      int32_t* counts) {
+    __shared__ int32_t part[16][64];
+    const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = t < n_tiles;
+    const int per = (nblocks + 15) / 16;
+    const int b0 = min(nblocks, seg * per), b1 = min(nblocks, b0 + per);
+    int sum = 0;
+    if (ok) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) sum += bhist[(int64_t)b * n_tiles + t];
     }
-    if (threadIdx.x == 0) counts[t] = carry;
+    part[seg][lane] = sum;
+    __syncthreads();
+    int run = 0;
+    for (int q = 0; q < seg; ++q) run += part[q][lane];
+    if (ok) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) {
+            const int64_t at = (int64_t)b * n_tiles + t;
+            const int v = bhist[at];
+            bhist[at] = run;
+            run += v;
+        }
+        if (seg == 15) counts[t] = run;
+    }
 }
 
 // Single-block exclusive scans of the tile counts and of the job counts;
@@ -1972,7 +1980,7 @@ void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_
         case 2: k_bin_count<2><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, obuf); break;
         default: k_bin_count<3><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, counts, bhist, obuf); break;
     }
-    if (use_lds) k_tile_prefix<<<(unsigned)g.n_tiles, 256, 0, s>>>(g.n_tiles, (int)nb, bhist, counts);
+    if (use_lds) k_tile_prefix<<<(unsigned)((g.n_tiles + 63) / 64), 1024, 0, s>>>(g.n_tiles, (int)nb, bhist, counts);
 }
 
 void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
