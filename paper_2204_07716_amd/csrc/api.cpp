@@ -448,10 +448,9 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
                 at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.cursor),
                 at<long long>(p, p->lay.diag), at<int32_t>(p, p->lay.obuf), s);
     launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_off),
-                      at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.cursor), at<int32_t>(p, p->lay.jobs),
-                      at<int32_t>(p, p->lay.bhist), p->ws + p->lay.trec, at<int32_t>(p, p->lay.cnt), at<int32_t>(p, p->lay.coff),
-                      at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac, at<int32_t>(p, p->lay.perm),
-                      p->ws + p->lay.xs, s);
+                      at<int32_t>(p, p->lay.cursor), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.bhist),
+                      p->ws + p->lay.trec, at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
+                      at<int32_t>(p, p->lay.perm), p->ws + p->lay.xs, s);
     if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
     p->N = N;
     p->points_set = true;

@@ -48,7 +48,7 @@ struct Layout {                      // byte offsets into the workspace
     size_t deconv = 0;               // per dim: B_j doubles (1 / psi_hat)
     size_t cover = 0;                // per dim: Mr_j * (1 + 2*kCoverSlots) int32
     size_t diag = 0;                 // int64 counters
-    size_t trec = 0, bhist = 0, obuf = 0, cnt = 0, coff = 0;   // tile-ordered records, block x tile counts, per-job cell counts and offsets
+    size_t trec = 0, bhist = 0, obuf = 0;   // tile-ordered records, block x tile counts, outside counts per binning block
     size_t counts = 0, tile_off = 0, cursor = 0, job_off = 0, jobs = 0;
     size_t loc = 0, frac = 0, perm = 0, xs = 0;
     size_t subgrid = 0, fftA = 0, fftB = 0, spec = 0;

@@ -132,9 +132,8 @@ void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_
 void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
                  int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s);
 void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
-                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
-                       const int32_t* bhist, void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
-                       hipStream_t s);
+                       const int32_t* tile_off, int32_t* cursor, const int32_t* jobs, const int32_t* bhist,
+                       void* trec, uint32_t* loc, void* frac, int32_t* perm, void* xs, hipStream_t s);
 size_t tile_record_bytes(int d, int prec);   // bytes of one tile-ordered sample record
 void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, const uint32_t* loc,
                    const void* frac, const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max,

@@ -393,137 +393,38 @@ __device__ __forceinline__ int local_cell(const Geo& g, uint32_t l) {
     return c;
 }
 
-// Per job (a tile-ordered range of at most one chunk): counts per cell of the
-// tile, cnt[job][cell].
+// Per job (a tile-ordered range of at most one chunk): order the job's
+// records by first cell within the job's own range, writing the packed first
+// cell, fractions, clamped coordinates and original index.  Counts per cell
+// in LDS, an exclusive scan over the cells, then LDS-atomic ranks.  The jobs
+// keep the ranges the tile scatter gave them, so a tile's samples end up in
+// (job, cell) order and no job needs another job's counts.  When the records
+// fit the LDS budget they are placed there first and leave as one contiguous
+// run.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cell_count(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
-                                                    int32_t* cnt) {
-    extern __shared__ int32_t hist[];
-    const int job = blockIdx.x;
-    if (job >= jobs[0]) return;
-    const int32_t* jd = jobs + 4 + 4 * job;
-    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) hist[c] = 0;
-    __syncthreads();
-    for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) atomicAdd(&hist[local_cell<D>(g, trec[s].w[1])], 1);
-    __syncthreads();
-    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cnt[(int64_t)job * g.ncell + c] = hist[c];
-}
-
-// Per tile: cell-major, job-minor exclusive offsets off[job][cell] of the
-// final (tile, cell) order.
-__global__ __launch_bounds__(1024) void k_cell_scan(Geo g, const int32_t* tile_off, const int32_t* job_off,
-                                                    const int32_t* cnt, int32_t* off) {
-    extern __shared__ uint32_t sh[];   // [ncell] totals, then [blockDim] scan scratch
-    const int t = blockIdx.x;
-    const int j0 = job_off[t], j1 = job_off[t + 1];
-    if (j0 == j1) return;
-    uint32_t* tot = sh;
-    uint32_t* tmp = sh + g.ncell;
-    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
-        uint32_t s = 0;
-        int j = j0;
-        for (; j + 8 <= j1; j += 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = cnt[(int64_t)(j + u) * g.ncell + c];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
-        }
-        for (; j < j1; ++j) s += cnt[(int64_t)j * g.ncell + c];
-        tot[c] = s;
-    }
-    __syncthreads();
-    // inclusive scan of tot (ncell <= 4 * blockDim)
-    const int per = (g.ncell + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int beg = threadIdx.x * per, end = min(g.ncell, beg + per);
-    uint32_t run = 0;
-    for (int c = beg; c < end; ++c) { run += tot[c]; tot[c] = run; }
-    tmp[threadIdx.x] = run;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const uint32_t v = (int)threadIdx.x >= o ? tmp[threadIdx.x - o] : 0u;
-        __syncthreads();
-        tmp[threadIdx.x] += v;
-        __syncthreads();
-    }
-    const uint32_t before = threadIdx.x ? tmp[threadIdx.x - 1] : 0u;
-    for (int c = beg; c < end; ++c) tot[c] += before;
-    __syncthreads();
-    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) {
-        int64_t run2 = tile_off[t] + (c ? tot[c - 1] : 0u);
-        int j = j0;
-        for (; j + 8 <= j1; j += 8) {
-            int32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = cnt[(int64_t)(j + u) * g.ncell + c];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                off[(int64_t)(j + u) * g.ncell + c] = (int32_t)run2;
-                run2 += v[u];
-            }
-        }
-        for (; j < j1; ++j) {
-            off[(int64_t)j * g.ncell + c] = (int32_t)run2;
-            run2 += cnt[(int64_t)j * g.ncell + c];
-        }
-    }
-}
-
-// Per job: move every tile-ordered record to its (tile, cell) position: the
-// packed first cell, fractions, clamped coordinates and the original index.
-// When the job's records fit the LDS budget they are first placed in the
-// job's own cell order in LDS (job-local offsets from an exclusive scan of
-// its cell counts) and leave as runs: a cell's samples of one job are
-// contiguous in the output, from off[job][cell] on.
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
-                                                      const int32_t* cnt, const int32_t* off,
-                                                      const int32_t* tile_off, int stage, uint32_t* loc, T* frac,
-                                                      int32_t* perm, T* xs) {
-    // [ncell] cursors; staged: then [ncell] output bases, [256] scan scratch
-    // and the staged records
+__global__ __launch_bounds__(256) void k_cell_sort(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
+                                                   int stage, uint32_t* loc, T* frac, int32_t* perm, T* xs) {
+    // [ncell] counts, then cursors; [256] scan scratch; staged records
     extern __shared__ int32_t cur[];
     const int job = blockIdx.x;
     if (job >= jobs[0]) return;
     const int32_t* jd = jobs + 4 + 4 * job;
-    const int n = jd[2] - jd[1];
-    const int32_t* joff = off + (int64_t)job * g.ncell;
-    if (!stage) {
-        for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = joff[c];
-        __syncthreads();
-        for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
-            TileRec<D, T> r;
-            const uint4* src = reinterpret_cast<const uint4*>(trec + s);
-#pragma unroll
-            for (int k = 0; k < TileRec<D, T>::WORDS / 4; ++k) {
-                const uint4 v = src[k];
-                r.w[4 * k] = v.x; r.w[4 * k + 1] = v.y; r.w[4 * k + 2] = v.z; r.w[4 * k + 3] = v.w;
-            }
-            const uint32_t l = r.w[1];
-            const int64_t pos = atomicAdd(&cur[local_cell<D>(g, l)], 1);
-            loc[pos] = l;
-            perm[pos] = (int32_t)r.w[0];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                frac[pos * D + j] = r.at(j);
-                xs[pos * D + j] = r.at(D + j);
-            }
-        }
-        return;
-    }
-    int32_t* gb = cur + g.ncell;
-    int32_t* scan = gb + g.ncell;
+    const int s0 = jd[1], s1 = jd[2], n = s1 - s0;
+    int32_t* scan = cur + g.ncell;
     uint32_t* sl_loc = reinterpret_cast<uint32_t*>(scan + 256);
     int32_t* sl_perm = reinterpret_cast<int32_t*>(sl_loc + g.chunk);
     T* sl_frac = reinterpret_cast<T*>(sl_perm + g.chunk);
     T* sl_xs = sl_frac + (int64_t)g.chunk * D;
-    // exclusive scan of the job's cell counts: thread t owns cells
-    // [t per, (t + 1) per), block scan of the thread sums
-    const int32_t* jcnt = cnt + (int64_t)job * g.ncell;
+    for (int c = threadIdx.x; c < g.ncell; c += blockDim.x) cur[c] = 0;
+    __syncthreads();
+    for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) atomicAdd(&cur[local_cell<D>(g, trec[s].w[1])], 1);
+    __syncthreads();
+    // exclusive scan of the counts: thread t owns cells [t per, (t + 1) per),
+    // block scan of the thread sums
     const int per = (g.ncell + 255) / 256;
     const int c_beg = min(g.ncell, (int)threadIdx.x * per), c_end = min(g.ncell, c_beg + per);
     int sum = 0;
-    for (int c = c_beg; c < c_end; ++c) sum += jcnt[c];
+    for (int c = c_beg; c < c_end; ++c) sum += cur[c];
     scan[threadIdx.x] = sum;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
@@ -534,12 +435,12 @@ __global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs
     }
     int run = scan[threadIdx.x] - sum;
     for (int c = c_beg; c < c_end; ++c) {
+        const int v = cur[c];
         cur[c] = run;
-        gb[c] = joff[c] - run;
-        run += jcnt[c];
+        run += v;
     }
     __syncthreads();
-    for (int s = jd[1] + threadIdx.x; s < jd[2]; s += blockDim.x) {
+    for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
         TileRec<D, T> r;
         const uint4* src = reinterpret_cast<const uint4*>(trec + s);
 #pragma unroll
@@ -549,29 +450,35 @@ __global__ __launch_bounds__(256) void k_cell_scatter(Geo g, const int32_t* jobs
         }
         const uint32_t l = r.w[1];
         const int k = atomicAdd(&cur[local_cell<D>(g, l)], 1);
-        if (k >= n) continue;   // counts inconsistent with the records: never taken
-        sl_loc[k] = l;
-        sl_perm[k] = (int32_t)r.w[0];
+        if (k >= n) continue;   // never taken: the ranks are a permutation of 0 .. n-1
+        if (stage) {
+            sl_loc[k] = l;
+            sl_perm[k] = (int32_t)r.w[0];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            sl_frac[k * D + j] = r.at(j);
-            sl_xs[k * D + j] = r.at(D + j);
+            for (int j = 0; j < D; ++j) {
+                sl_frac[k * D + j] = r.at(j);
+                sl_xs[k * D + j] = r.at(D + j);
+            }
+        } else {
+            const int64_t pos = (int64_t)s0 + k;
+            loc[pos] = l;
+            perm[pos] = (int32_t)r.w[0];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                frac[pos * D + j] = r.at(j);
+                xs[pos * D + j] = r.at(D + j);
+            }
         }
     }
+    if (!stage) return;
     __syncthreads();
-    const int tile = jd[0];
-    const int64_t tlo = tile_off[tile], thi = tile_off[tile + 1];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const uint32_t l = sl_loc[k];
-        const int64_t pos = (int64_t)gb[local_cell<D>(g, l)] + k;
-        if (pos < tlo || pos >= thi) continue;
-        loc[pos] = l;
-        perm[pos] = sl_perm[k];
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            frac[pos * D + j] = sl_frac[k * D + j];
-            xs[pos * D + j] = sl_xs[k * D + j];
-        }
+        loc[s0 + k] = sl_loc[k];
+        perm[s0 + k] = sl_perm[k];
+    }
+    for (int k = threadIdx.x; k < n * D; k += blockDim.x) {
+        frac[(int64_t)s0 * D + k] = sl_frac[k];
+        xs[(int64_t)s0 * D + k] = sl_xs[k];
     }
 }
 
@@ -1991,25 +1898,19 @@ void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, in
 
 template <int D, typename T>
 static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
-                          const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
-                          const int32_t* bhist, void* trec_v, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm,
-                          void* xs, hipStream_t s) {
+                          const int32_t* tile_off, int32_t* cursor, const int32_t* jobs, const int32_t* bhist,
+                          void* trec_v, uint32_t* loc, void* frac, int32_t* perm, void* xs, hipStream_t s) {
     using R = TileRec<D, T>;
     R* trec = static_cast<R*>(trec_v);
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
     const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
     k_scatter_tiles<D, T><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, tile_off, cursor, bhist, trec);
-    const unsigned nj = (unsigned)n_jobs_max;
-    k_cell_count<D, T><<<nj, 256, (size_t)g.ncell * 4, s>>>(g, jobs, trec, cnt);
-    // one thread per cell of a tile (64 in 2-D), at most 1024
-    const unsigned nts = (unsigned)std::min(1024, std::max(64, (g.ncell + 63) / 64 * 64));
-    k_cell_scan<<<(unsigned)g.n_tiles, nts, ((size_t)g.ncell + nts) * 4, s>>>(g, tile_off, job_off, cnt, off);
-    // records staged in LDS (job-local cell order) when they fit the budget
-    const size_t stage_bytes = (size_t)g.ncell * 8 + 256 * 4 + (size_t)g.chunk * (8 + 2 * D * sizeof(T));
+    // records staged in LDS when they fit the budget
+    const size_t base_bytes = (size_t)g.ncell * 4 + 256 * 4;
+    const size_t stage_bytes = base_bytes + (size_t)g.chunk * (8 + 2 * D * sizeof(T));
     const int stage = stage_bytes <= 65536 ? 1 : 0;
-    const size_t lds_cs = stage ? stage_bytes : (size_t)g.ncell * 4;
-    k_cell_scatter<D, T><<<nj, 256, lds_cs, s>>>(g, jobs, trec, cnt, off, tile_off, stage, loc,
-                                                 static_cast<T*>(frac), perm, static_cast<T*>(xs));
+    k_cell_sort<D, T><<<(unsigned)n_jobs_max, 256, stage ? stage_bytes : base_bytes, s>>>(
+        g, jobs, trec, stage, loc, static_cast<T*>(frac), perm, static_cast<T*>(xs));
 }
 
 size_t tile_record_bytes(int d, int prec) {
@@ -2018,11 +1919,10 @@ size_t tile_record_bytes(int d, int prec) {
 }
 
 void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
-                       const int32_t* tile_off, const int32_t* job_off, int32_t* cursor, const int32_t* jobs,
-                       const int32_t* bhist, void* trec, int32_t* cnt, int32_t* off, uint32_t* loc, void* frac, int32_t* perm, void* xs,
-                       hipStream_t s) {
+                       const int32_t* tile_off, int32_t* cursor, const int32_t* jobs, const int32_t* bhist,
+                       void* trec, uint32_t* loc, void* frac, int32_t* perm, void* xs, hipStream_t s) {
     if (N == 0) return;
-#define FKR_SC(D, T) sort_cells_dt<D, T>(g, x_type, X, N, n_jobs_max, tile_off, job_off, cursor, jobs, bhist, trec, cnt, off, loc, frac, perm, xs, s)
+#define FKR_SC(D, T) sort_cells_dt<D, T>(g, x_type, X, N, n_jobs_max, tile_off, cursor, jobs, bhist, trec, loc, frac, perm, xs, s)
     if (prec == FKR_F64) {
         if (g.d == 1) FKR_SC(1, double); else if (g.d == 2) FKR_SC(2, double); else FKR_SC(3, double);
     } else {

@@ -186,8 +186,6 @@ static void layout(fkr_plan* p) {
     const int64_t nbins = (N + kSortChunk - 1) / kSortChunk;
     L.bhist = take(p->n_tiles <= kLdsHistMax ? (size_t)nbins * p->n_tiles * 4 : 4);
     L.obuf = take((size_t)nbins * 4);   // per-block counts of samples outside [lo, hi]
-    L.cnt = take((size_t)p->n_jobs_max * p->ncell * 4);
-    L.coff = take((size_t)p->n_jobs_max * p->ncell * 4);
     L.counts = take((p->n_tiles + 1) * 4);
     L.tile_off = take((p->n_tiles + 1) * 4);
     L.cursor = take(p->n_tiles * 4);
