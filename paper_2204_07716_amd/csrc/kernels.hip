@@ -274,19 +274,7 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
         diag[4] = smax[1023];
     }
     __syncthreads();
-    // job table entries: (tile, start, end, order) at jobs[4 + 4 * job]
-    for (int64_t k = t; k < n_tiles; k += 1024) {
-        const int64_t c = counts[k];
-        const int64_t nj = (c + chunk - 1) / chunk;
-        const int64_t j0 = job_off[k], s0 = tile_off[k];
-        for (int64_t q = 0; q < nj; ++q) {
-            int32_t* e = jobs + 4 + 4 * (j0 + q);
-            e[0] = (int32_t)k;
-            e[1] = (int32_t)(s0 + q * chunk);
-            e[2] = (int32_t)min<int64_t>(s0 + (q + 1) * chunk, s0 + c);
-        }
-        cursor[k] = 0;
-    }
+    // job table entries: (tile, start, end, order) at jobs[4 + 4 * job].
     // Processing order (field 3 of entry b = the job that workgroup b of a
     // spread takes): jobs bucketed by size, largest first, so the workgroups
     // that the dispatcher hands out last are the short ones.  The order
@@ -294,20 +282,36 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
     __shared__ int32_t bcnt[8];
     if (t < 8) bcnt[t] = 0;
     __syncthreads();
-    const int nj_all = (int)sb[1023];
-    auto bucket = [&](int j) {
-        const int32_t* e = jobs + 4 + 4 * j;
-        const int sz = e[2] - e[1];
-        return min(7, (int)(((int64_t)(chunk - sz) * 8) / chunk));
-    };
-    for (int j = t; j < nj_all; j += 1024) atomicAdd(&bcnt[bucket(j)], 1);
+    auto bucket = [&](int64_t sz) { return min(7, (int)(((int64_t)chunk - sz) * 8 / chunk)); };
+    for (int64_t k = t; k < n_tiles; k += 1024) {
+        const int64_t c = counts[k];
+        const int64_t nj = (c + chunk - 1) / chunk;
+        const int64_t j0 = job_off[k], s0 = tile_off[k];
+        for (int64_t q = 0; q < nj; ++q) {
+            int32_t* e = jobs + 4 + 4 * (j0 + q);
+            const int64_t a0 = s0 + q * chunk, a1 = min<int64_t>(a0 + chunk, s0 + c);
+            e[0] = (int32_t)k;
+            e[1] = (int32_t)a0;
+            e[2] = (int32_t)a1;
+            atomicAdd(&bcnt[bucket(a1 - a0)], 1);
+        }
+        cursor[k] = 0;
+    }
     __syncthreads();
     if (t == 0) {
         int run = 0;
         for (int b = 0; b < 8; ++b) { const int c = bcnt[b]; bcnt[b] = run; run += c; }
     }
     __syncthreads();
-    for (int j = t; j < nj_all; j += 1024) jobs[4 + 4 * atomicAdd(&bcnt[bucket(j)], 1) + 3] = j;
+    for (int64_t k = t; k < n_tiles; k += 1024) {
+        const int64_t c = counts[k];
+        const int64_t nj = (c + chunk - 1) / chunk;
+        const int64_t j0 = job_off[k];
+        for (int64_t q = 0; q < nj; ++q) {
+            const int64_t sz = min<int64_t>(chunk, c - q * chunk);
+            jobs[4 + 4 * atomicAdd(&bcnt[bucket(sz)], 1) + 3] = (int32_t)(j0 + q);
+        }
+    }
 }
 
 // Tile-ordered sample record: original index, packed first cell relative to
