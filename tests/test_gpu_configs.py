@@ -272,3 +272,57 @@ def test_ll2d_bench_step_sampled(orc):
     v_i = orc.interp(vhat, w.M, w.lo, w.hi, X)
     kappa_ref = 1.0 / np.mean(r * np.exp(-v_i))
     assert abs(kappa / kappa_ref - 1) < 1e-6
+
+
+def test_graph_replay_matches_eager(orc):
+    """set_points, cv and the variance pass captured into one HIP graph: three
+    replays, each after eager calls on other data that overwrite the plan's
+    workspace, reproduce the eager results (to the last-bit spread of the
+    LDS-atomic summation order), and the first matches the oracle."""
+    rng = np.random.default_rng(70)
+    N, Np, M, h = 20000, 4, (40, 36), (0.08, 0.09)
+    X = rng.random((N, 2))
+    y = np.sin(4 * X[:, 0]) * np.cos(3 * X[:, 1]) + 0.2 * rng.standard_normal(N)
+    X2, y2 = rng.random((N // 2, 2)), rng.standard_normal(N // 2)
+    plan = make_plan(2, 1, M, h, (0.12, 0.12), 1e-6, "fp32", n_max=N, max_weights=2 + Np, tprec="fp64")
+    Xd, Yd = to_dev(X, torch.float32), to_dev(y[:, None], torch.float32)
+    X2d, Y2d = to_dev(X2, torch.float32), to_dev(y2[:, None], torch.float32)
+
+    def step():
+        plan.set_points(Xd)
+        out = plan.cv(h, Yd, Np, seed=21)
+        s2 = plan.variance(h, Yd, out["mhat"][0, 0], mode="log")[0]
+        return [out["mhat"], out["rho"], out["gcv"], s2]
+
+    def other():
+        plan.set_points(X2d)
+        plan.fit((0.12, 0.12), Y2d)
+        plan.variance(h, Y2d, plan.fit(h, Y2d)[0, 0], mode="log")
+
+    ref = [t.clone() for t in step()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        res = step()
+    for rep in range(3):
+        other()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(res, ref):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            fin = np.isfinite(b)
+            assert np.array_equal(np.isnan(a), np.isnan(b)), rep
+            assert np.abs(a[fin] - b[fin]).max() <= 1e-6 * np.abs(b[fin]).max(), rep
+    mh = res[0].cpu().numpy()[0, 0]
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    X32 = X.astype(np.float32).astype(np.float64)
+    ref_fit, S, T, r0, ill = orc.fit(X32, y.astype(np.float32).astype(np.float64), h, 1, gp,
+                                     return_all=True)
+    assert rel_err(mh, ref_fit[:, 0], density_mask(S[:, 0])) < 1e-5
