@@ -84,6 +84,7 @@ struct FftPass {
     int fold_d;                   // 0: read `in`; else the dimension count
     int fold_f64;                 // subgrid element type
     int64_t fold_rest;            // Mr_1 Mr_2
+    int fold_split;               // two threads per element (set by the launcher)
     FoldArgs fold;
     // inverse first pass only: the input rows are expanded from the pair
     // spectra (row = channel pair * rest + band index of dims 1.., element =

@@ -980,9 +980,11 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread_group(Geo g, int np, co
 // cover it and over the jobs of each such tile, in a fixed order
 // (deterministic).  One thread per (cell, pair) item; consecutive threads take
 // consecutive cells of one pair, so the subgrid reads of a wave fall on rows
-// of the same tiles.  Output layout [pair][cell].
+// of the same tiles.  With a0_step = 2 only the covering tiles a0 = a0_first,
+// a0_first + 2, .. of dimension 0 are summed (two threads share a cell).
 template <int D, typename T>
-__device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned cell) {
+__device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned cell, int a0_first = 0,
+                                           int a0_step = 1) {
     const T* subgrid = static_cast<const T*>(fa.subgrid);
     const int cs = 1 + 2 * kCoverSlots;
     const int32_t* cv[3];
@@ -1015,7 +1017,8 @@ __device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned c
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             const int a0 = k & 1, a1 = (k >> 1) & 1, a2 = (k >> 2) & 1;
-            ok[k] = a0 < n0 && (D < 2 || a1 < n1) && (D < 3 || a2 < n2);
+            ok[k] = a0 < n0 && (D < 2 || a1 < n1) && (D < 3 || a2 < n2) &&
+                    (a0_step == 1 || a0 == a0_first);
             int64_t tile = 0, off = 0;
             if (ok[k]) {
                 tile = cv[0][1 + 2 * a0];
@@ -1064,7 +1067,7 @@ __device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned c
     }
     for (int a2 = 0; a2 < n2; ++a2)
         for (int a1 = 0; a1 < n1; ++a1)
-            for (int a0 = 0; a0 < n0; ++a0) {
+            for (int a0 = a0_first; a0 < n0; a0 += a0_step) {
                 int64_t tile = cv[0][1 + 2 * a0];
                 int64_t off = cv[0][2 + 2 * a0];
                 if (D > 1) {
@@ -1206,19 +1209,31 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
             buf0[q] = acc;
         }
     } else if constexpr (FD > 0) {
-        // fold the row from the subgrids (forward first pass, nin = F = Mr_0)
+        // fold the row from the subgrids (forward first pass, nin = F = Mr_0);
+        // split: two threads per element, one per parity of the covering
+        // tile index of dimension 0, the odd half added through buf1
         const int nin = (int)n_in;
         const unsigned rest = (unsigned)f.fold_rest;
-        for (int q = threadIdx.x; q < nr * nin; q += blockDim.x) {
-            const int r = (int)((unsigned)q / (unsigned)nin), e = q - r * nin;
+        const int halves = f.fold_split ? 2 : 1;
+        for (int q = threadIdx.x; q < halves * nr * nin; q += blockDim.x) {
+            const int h = q >= nr * nin ? 1 : 0;
+            const int qq = q - h * nr * nin;
+            const int r = (int)((unsigned)qq / (unsigned)nin), e = qq - r * nin;
             const unsigned row = (unsigned)(row0 + r);
             const int p = (int)(row / rest);
             const unsigned cell = (row - (unsigned)p * rest) * (unsigned)nin + (unsigned)e;
-            const double2 v = fold_at<FD, TS>(f.fold, p, cell);
+            const double2 v = fold_at<FD, TS>(f.fold, p, cell, h, halves);
             C c;
             c.x = (T)v.x;
             c.y = (T)v.y;
-            buf0[r * F + e] = c;
+            (h ? buf1 : buf0)[r * F + e] = c;
+        }
+        if (halves == 2) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < nr * nin; q += blockDim.x) {
+                const int r = (int)((unsigned)q / (unsigned)nin), e = q - r * nin;
+                buf0[r * F + e] = cadd(buf0[r * F + e], buf1[r * F + e]);
+            }
         }
     } else {
         const int nin = (int)n_in;
@@ -2181,7 +2196,9 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
         int Rf = 2;
         while (Rf > 1 && (Rf * f.F > 1024 || (size_t)2 * Rf * f.F * csz > 65536 || f.rows < (int64_t)Rf * 512)) Rf >>= 1;
         f.rows_per_block = Rf;
-        const unsigned ntf = (unsigned)std::min<int64_t>(1024, (Rf * f.F + 63) / 64 * 64);
+        // few rows (one pair): two threads per element halve each fold chain
+        f.fold_split = (Rf == 1 && f.rows < 512 && 2 * f.F <= 1024) ? 1 : 0;
+        const unsigned ntf = (unsigned)std::min<int64_t>(1024, ((1 + f.fold_split) * Rf * f.F + 63) / 64 * 64);
         const size_t ldsf = (size_t)2 * Rf * f.F * csz;
         const unsigned nbf = (unsigned)((f.rows + Rf - 1) / Rf);
         if (nbf == 0) return;
