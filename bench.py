@@ -24,7 +24,9 @@ bytes, timed with HIP events that the library records on the launch stream;
 ``hbm_model`` sets the step's algorithmic bytes against HBM bandwidth;
 ``cpu_baseline`` times the FP64 oracle on a bounded sample of grid points and
 extrapolates to the full grid; ``accuracy`` compares the GPU grids with the
-oracle on that same sample.
+oracle on that same sample; ``fp64_single`` times the plain FP64 form (FP64
+spreading, transforms and solves) of one regression on the same samples, for
+comparison with the batched FP32-spreading step.
 
 By default the timed steps replay a HIP graph captured from one step (the
 step's ~30 kernel launches are launch-bound on the host otherwise); before
@@ -33,7 +35,7 @@ host-launched steps instead.  Stage times always come from eager steps, where
 the library brackets every launch with HIP events on the launch stream.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--transform fp64|fp32] [--eager]
-                       [--no-warm] [--no-cpu-baseline]
+                       [--no-warm] [--no-cpu-baseline] [--no-fp64-single]
 """
 from __future__ import annotations
 
@@ -66,6 +68,8 @@ def _args():
     ap.add_argument("--eager", action="store_true",
                     help="launch every step's kernels from the host instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-single", action="store_true",
+                    help="skip timing the plain FP64 single-regression form")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-path timing (profiling runs count only the cold steps)")
     ap.add_argument("--cpu-points", type=int, default=4096,
@@ -326,10 +330,43 @@ def main() -> int:
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = a.numel() * 4
 
+    if not args.no_fp64_single:
+        line["fp64_single"] = _fp64_single(w, Xd, Yd, args.steps, args.warmup, value)
     if not args.no_cpu_baseline:
         line.update(_cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, value))
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _fp64_single(w, Xd, Yd, steps, warmup, batched_value):
+    """The plain FP64 form of one regression on the same samples and grid:
+    FP64 spreading, transforms and solves, at the same requested accuracy;
+    one step is set_points and one fit (density and y, 2 weight vectors),
+    launched eagerly.  samples/s counts N per weight vector, as `value` does."""
+    import torch
+    from paper_2204_07716_amd import Plan
+    h = w.h[0]
+    p64 = Plan(2, 1, w.M, w.lo, w.hi, h, h, w.eps, precision="fp64", n_max=w.N, max_weights=2,
+               max_h=1, transform_precision="fp64")
+    X64, Y64 = Xd.double(), Yd.double()
+
+    def st():
+        p64.set_points(X64)
+        return p64.fit(h, Y64)
+
+    for _ in range(max(1, warmup)):
+        st()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    v = w.N * 2 / (ms * 1e-3)
+    del p64
+    return {"ms_per_step": round(ms, 4), "value": round(v, 1), "unit": "samples/s",
+            "fits_per_step": 2, "batched_fp32_over_fp64": round(batched_value / v, 2),
+            "note": "FP64 plan, one response, eager launches"}
 
 
 def _cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, gpu_value):
