@@ -107,6 +107,7 @@ struct SolveArgs {
     void* probe_out;               // [M][probe_stride], FP32 or FP64 (may be null)
     int probe_f32, probe_stride;
     int rows_with_y;               // the y fits go to the rows too: column r - 1 for weight r
+    int wpg;                       // weights per thread (set by the launcher)
     double* s0_out;                // [M] (may be null)
     unsigned long long* ill_count;
 };

@@ -1355,10 +1355,15 @@ __device__ __forceinline__ typename V2<T>::t expand_at(const ExpandArgs& a, cons
 // ---------------------------------------------------------------------------
 // Per-grid-point solve (eq. 3 / 11) in FP64.
 // ---------------------------------------------------------------------------
+// Workgroup row blockIdx.y takes the weights 1 + y wpg .. of every point
+// (each row factors the point's matrix itself), so a call with many weight
+// vectors runs several threads per grid point.
 template <int P, typename T>
 __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, const T* chan) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.Mtot) return;
+    const int grp = blockIdx.y;
+    const int r_beg = 1 + grp * a.wpg, r_end = min(a.nr, r_beg + a.wpg);
     // channels are stored pair-major, [pair][M][re, im]: real channel r of
     // point k is chan[((r / 2) M + k) 2 + r % 2] (coalesced over k)
     auto ch = [&](int r) { return chan[(((int64_t)(r >> 1)) * a.Mtot + k) * 2 + (r & 1)]; };
@@ -1408,9 +1413,11 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
         r0[b] = v / A[b][b];
     }
     const double nan = __builtin_nan("");
-    if (a.s0_out) a.s0_out[k] = s0;
-    if (ill && a.ill_count) atomicAdd(a.ill_count, 1ull);
-    for (int r = 1; r < a.nr; ++r) {
+    if (grp == 0) {
+        if (a.s0_out) a.s0_out[k] = s0;
+        if (ill && a.ill_count) atomicAdd(a.ill_count, 1ull);
+    }
+    for (int r = r_beg; r < r_end; ++r) {
         const int t0 = a.n_s + (r - 1) * a.n_t;
         double m = 0.0;
 #pragma unroll
@@ -2246,8 +2253,13 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
     }
 }
 
-void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s) {
-    const unsigned nb = nblk(a.Mtot);
+void launch_solve2(int prec, const SolveArgs& a0, const int* pidx, const void* chan, hipStream_t s) {
+    // three weight vectors per thread: more threads per grid point for
+    // calls with many weights (the grid alone gives few waves per CU)
+    SolveArgs a = a0;
+    a.wpg = 3;
+    const unsigned ng = (unsigned)std::max(1, (a.nr - 1 + a.wpg - 1) / a.wpg);
+    const dim3 nb(nblk(a.Mtot), ng);
 #define FKR_SOLVE(P, T) k_solve<P, T><<<nb, 256, 0, s>>>(a, pidx, static_cast<const T*>(chan))
 #define FKR_SOLVE_P(T) do { switch (a.P) { case 1: FKR_SOLVE(1, T); break; case 2: FKR_SOLVE(2, T); break; \
     case 3: FKR_SOLVE(3, T); break; case 4: FKR_SOLVE(4, T); break; case 6: FKR_SOLVE(6, T); break; \
