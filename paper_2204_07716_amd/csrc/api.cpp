@@ -239,13 +239,10 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     a.ill_clear = ill_clear;
     // the first inverse pass expands its rows from the pair spectra itself
     StageTimer tf(p, FKR_STAGE_FFT_INV, s);
-    const void* in = nullptr;
-    int64_t done_M = 1;
-    for (int j = 0; j < p->d; ++j) {
+    const size_t tcsz = p->tprec == FKR_F64 ? 16 : 8;
+    void* chan_out = p->ws + p->lay.chan + (size_t)c0 * p->Mtot * tcsz;
+    auto pass = [&](int j) {
         FftPass f{};
-        int64_t rest = 1;
-        for (int i = j + 1; i < p->d; ++i) rest *= p->B[i];
-        f.rows = done_M * nout * rest;
         f.n_in = p->B[j];
         f.F = p->L[j];
         f.n_out = p->M[j];
@@ -256,27 +253,62 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         for (int q = 0; q < p->fL[j].nfac; ++q) f.fac[q] = p->fL[j].fac[q];
         f.tw = at<double>(p, p->fL[j].tw_off);
         f.fac_out = nullptr;
-        if (j == 0) {
-            f.exp_mode = 1;
-            f.exp_rest = rest;
-            f.ex = a;
-            f.exp_es = dev_es(p);
-            f.exp_et = dev_et(p);
-            f.exp_spec = p->ws + p->lay.spec;
+        return f;
+    };
+    auto expand = [&](FftPass& f, int64_t rest, int64_t rmul, int64_t emul) {
+        f.exp_mode = 1;
+        f.exp_rest = rest;
+        f.exp_rmul = rmul;
+        f.exp_emul = emul;
+        f.ex = a;
+        f.exp_es = dev_es(p);
+        f.exp_et = dev_et(p);
+        f.exp_spec = p->ws + p->lay.spec;
+    };
+    if (p->d == 2) {
+        // dimension 1 first, so the last pass runs along dimension 0 and
+        // writes every row of the pair-major channels [pair][M^d] as one
+        // contiguous run.  Pass 1: row = (pair, e_0), element e_1, output
+        // [pair][m_1][e_0].  Pass 2: row = (pair, m_1), element e_0.
+        FftPass f1 = pass(1);
+        f1.rows = nout * p->B[0];
+        expand(f1, p->B[0], 1, p->B[0]);
+        f1.out_estride = p->B[0];
+        f1.out_roff = 0;
+        f1.out_rdiv = p->B[0];
+        f1.out_rmul = p->M[1] * p->B[0];
+        void* mid = p->ws + p->lay.fftA;
+        launch_fft(p->tprec, true, f1, nullptr, mid, s);
+        FftPass f0 = pass(0);
+        f0.rows = nout * p->M[1];
+        f0.out_estride = 1;
+        f0.out_roff = 0;
+        f0.out_rdiv = 1;
+        f0.out_rmul = p->M[0];
+        launch_fft(p->tprec, true, f0, mid, chan_out, s);
+    } else {
+        const void* in = nullptr;
+        int64_t done_M = 1;
+        for (int j = 0; j < p->d; ++j) {
+            FftPass f = pass(j);
+            int64_t rest = 1;
+            for (int i = j + 1; i < p->d; ++i) rest *= p->B[i];
+            f.rows = done_M * nout * rest;
+            if (j == 0) expand(f, rest, p->B[0], 1);
+            // row = (pair, m over the done dimensions, e over the rest) with
+            // the pair outermost; the output keeps the pair outermost, so the
+            // last pass writes the channels pair-major, [pair][M^d][re, im]
+            f.out_estride = done_M * rest;
+            f.out_roff = 0;
+            f.out_rdiv = done_M * rest;
+            f.out_rmul = done_M * p->M[j] * rest;
+            void* out;
+            if (j == p->d - 1) out = chan_out;
+            else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);   // fftA first
+            launch_fft(p->tprec, true, f, in, out, s);
+            in = out;
+            done_M *= p->M[j];
         }
-        // row = (pair, m over the done dimensions, e over the rest) with the
-        // pair outermost; the output keeps the pair outermost, so the last
-        // pass writes the channels pair-major, [pair][M^d][re, im]
-        f.out_estride = done_M * rest;
-        f.out_roff = 0;
-        f.out_rdiv = done_M * rest;
-        f.out_rmul = done_M * p->M[j] * rest;
-        void* out;
-        if (j == p->d - 1) out = p->ws + p->lay.chan + (size_t)c0 * p->Mtot * 2 * (p->tprec == FKR_F64 ? 8 : 4);
-        else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);   // fftA first
-        launch_fft(p->tprec, true, f, in, out, s);
-        in = out;
-        done_M *= p->M[j];
     }
     if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
     if (p->n_s % 2 == 0) {

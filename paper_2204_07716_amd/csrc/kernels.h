@@ -90,7 +90,8 @@ struct FftPass {
     // spectra (row = channel pair * rest + band index of dims 1.., element =
     // band index of dim 0) instead of read
     int exp_mode;
-    int64_t exp_rest;             // B_1 B_2
+    int64_t exp_rest;             // rows per channel pair
+    int64_t exp_rmul, exp_emul;   // band index = (row % exp_rest) exp_rmul + element exp_emul
     ExpandArgs ex;
     const int* exp_es;
     const int* exp_et;

@@ -1196,12 +1196,14 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
             e = e >= F ? e - F : e;
             if constexpr (EXP) {
                 // the channel spectra of the row are expanded here from the
-                // pair spectra: row = pair c * rest + band index of the rest
+                // pair spectra: row = pair c * rest + the band indices of the
+                // other dimensions
                 const unsigned row = (unsigned)(row0 + r), rest = (unsigned)f.exp_rest;
                 const int cr = (int)(row / rest), c = f.ex.c0 + cr;
-                const unsigned nb0 = (row - (unsigned)cr * rest) * (unsigned)nin;
+                const unsigned nb0 = (row - (unsigned)cr * rest) * (unsigned)f.exp_rmul;
+                const unsigned em = (unsigned)f.exp_emul;
                 const C* sp = static_cast<const C*>(f.exp_spec);
-                for (; e < nin; e += F) acc = cadd(acc, expand_at<T>(f.ex, f.exp_es, f.exp_et, sp, c, nb0 + (unsigned)e));
+                for (; e < nin; e += F) acc = cadd(acc, expand_at<T>(f.ex, f.exp_es, f.exp_et, sp, c, nb0 + (unsigned)e * em));
             } else {
                 const C* rowp = in + (row0 + r) * n_in;
                 for (; e < nin; e += F) acc = cadd(acc, rowp[e]);

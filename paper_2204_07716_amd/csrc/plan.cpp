@@ -215,6 +215,8 @@ static void layout(fkr_plan* p) {
             for (int i = j + 1; i < p->d; ++i) e *= p->B[i];
             cap = std::max(cap, e);
         }
+        // 2-D inverse transforms run dimension 1 first: [pair][M_1][B_0]
+        if (p->d == 2) cap = std::max(cap, c * p->B[0] * p->M[1]);
     }
     L.cap_fft = cap;
     L.fftA = take(cap * tcsz);
