@@ -207,7 +207,6 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-// Channels at one bandwidth h: expansion + inverse FFT -> chan [pair][M][re, im].
 // True when the channel buffer holds the density moments of the current
 // points at bandwidth h (bitwise equal h), left there by the last fit, cv,
 // moments or variance call.
@@ -218,9 +217,10 @@ bool reuse_density_channels(const fkr_plan* p, const double* h) {
     return true;
 }
 
-// Channel pairs c0 .. ncp - 1 of bandwidth h into the channel buffer (pair
-// c at pair offset c).  Weight 0 of the spectra is the density in every
-// caller, so afterwards the first n_s / 2 pairs hold its moments s_alpha at h.
+// Channels at one bandwidth h: expansion + inverse FFT -> chan [pair][M][re, im],
+// channel pairs c0 .. ncp - 1 (pair c at pair offset c).  Weight 0 of the
+// spectra is the density in every caller, so afterwards the first n_s / 2
+// pairs hold its moments s_alpha at h.
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
                         int c0 = 0) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
