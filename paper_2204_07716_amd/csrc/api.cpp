@@ -661,7 +661,7 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     std::vector<WSrc> srcs(2);
     for (int r = 0; r < 2; ++r) {
         srcs[r].kind = W_SORTED; srcs[r].type = p->prec; srcs[r].ptr = p->ws + p->lay.wsort;
-        srcs[r].stride = 4; srcs[r].col = r;
+        srcs[r].stride = resid_row_stride(g, p->prec); srcs[r].col = r;
     }
     if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
     // The density moments s_alpha depend on the points and h only: when the

@@ -156,7 +156,9 @@ void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void
 void launch_finalize_cv(int nh_index, int Np, int q, int64_t N, const double* red, int n_items,
                         int ny_cols, double* rho_out, double* rss_out, double* gcv_out,
                         hipStream_t s);
-// residuals r_out[s] and the staged rows (1, z, 0, 0) of the variance pass
+// residuals r_out[s] and the staged rows (1, z) of the variance pass, of
+// resid_row_stride elements each (2 or 4; unused elements zero)
+int resid_row_stride(const Geo& g, int prec);
 void launch_resid(const Geo& g, int prec, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
                   int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out, void* rows,
                   hipStream_t s);

@@ -1709,7 +1709,8 @@ __global__ void k_finalize_cv(int hidx, int Np, int q, int64_t N, const double* 
 template <int D, typename TW>
 __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x_type, const void* xs,
                                                const int32_t* perm, int y_type, const void* Y,
-                                               int y_cplx, const double* mhat, double* r_out, TW* rows) {
+                                               int y_cplx, const double* mhat, double* r_out, TW* rows,
+                                               int rstride) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const Corners<D> c = corners<D>(g, x_type, xs, s);
@@ -1731,7 +1732,8 @@ __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x
     }
     const TW z = (TW)(mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r);
     if constexpr (sizeof(TW) == 4) {
-        reinterpret_cast<float4*>(rows)[s] = make_float4(1.f, z, 0.f, 0.f);
+        if (rstride == 2) reinterpret_cast<float2*>(rows)[s] = make_float2(1.f, z);
+        else reinterpret_cast<float4*>(rows)[s] = make_float4(1.f, z, 0.f, 0.f);
     } else {
         reinterpret_cast<double2*>(rows)[2 * s] = make_double2(1.0, z);
         reinterpret_cast<double2*>(rows)[2 * s + 1] = make_double2(0.0, 0.0);
@@ -2114,7 +2116,11 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
         if constexpr (Foot<D, W>::ok && sizeof(T) == 4) {
             // the group spread reads the staged rows directly: every source of
             // the launch is a column of the sorted weight rows, in order
-            bool rows = src.w[0].kind == W_SORTED && (src.w[0].col % 4) == 0 && (src.w[0].stride % 4) == 0;
+            // (the one-sample-per-wave kernel reads them with scalar loads, so
+            // two columns need only 8-byte rows; the lane-group kernels need
+            // 16-byte aligned rows)
+            const int al = (D == 2 && W <= 8 && src.npairs == 1) ? 2 : 4;
+            bool rows = src.w[0].kind == W_SORTED && (src.w[0].col % al) == 0 && (src.w[0].stride % al) == 0;
             for (int q = 1; q < 2 * src.npairs; ++q)
                 rows = rows && src.w[q].kind == W_SORTED && src.w[q].ptr == src.w[0].ptr &&
                        src.w[q].col == src.w[0].col + q;
@@ -2336,12 +2342,19 @@ void launch_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, i
     k_finalize_cv<<<1, 64, 0, s>>>(hidx, Np, q, N, red, ny_cols, rho_out, rss_out, gcv_out);
 }
 
+int resid_row_stride(const Geo& g, int prec) {
+    // (1, z) rows of 8 bytes where the two-column spread is the
+    // one-sample-per-wave kernel (2-D, FP32, w <= 8), else 16-byte rows
+    return prec == FKR_F32 && g.d == 2 && g.w <= 8 ? 2 : 4;
+}
+
 void launch_resid(const Geo& g, int prec, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
                   int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out, void* rows,
                   hipStream_t s) {
     if (N == 0) return;
+    const int rstride = resid_row_stride(g, prec);
 #define FKR_RES(D, TW) k_resid<D, TW><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, \
-                                                              mhat, r_out, static_cast<TW*>(rows))
+                                                              mhat, r_out, static_cast<TW*>(rows), rstride)
     if (prec == FKR_F64) {
         if (g.d == 1) FKR_RES(1, double); else if (g.d == 2) FKR_RES(2, double); else FKR_RES(3, double);
     } else {
