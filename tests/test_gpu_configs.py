@@ -326,3 +326,32 @@ def test_graph_replay_matches_eager(orc):
     ref_fit, S, T, r0, ill = orc.fit(X32, y.astype(np.float32).astype(np.float64), h, 1, gp,
                                      return_all=True)
     assert rel_err(mh, ref_fit[:, 0], density_mask(S[:, 0])) < 1e-5
+
+
+def test_coarse_grid_wide_band(orc):
+    """A bandwidth much narrower than the grid spacing: the kept band of the
+    transforms (2K + 1 modes) is wider than the output grid, so the 2-D
+    inverse pass that runs first writes an intermediate larger than M^d.
+    Fit and log-variance pass against the oracle."""
+    rng = np.random.default_rng(72)
+    N = 30000
+    X = rng.random((N, 2))
+    y = np.sin(5 * X[:, 0]) + X[:, 1] ** 2 + 0.1 * rng.standard_normal(N)
+    M, h = (9, 7), (0.03, 0.035)
+    plan = make_plan(2, 1, M, h, h, 1e-6, "fp32", n_max=N, max_weights=3, tprec="fp64")
+    g = plan.geometry
+    assert 2 * g.K[0] + 1 > M[0] and 2 * g.K[1] + 1 > M[1]
+    plan.set_points(to_dev(X, torch.float32))
+    Yd = to_dev(y[:, None], torch.float32)
+    mh_d = plan.fit(h, Yd)[0, 0]
+    mh = mh_d.cpu().numpy()
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    X32 = X.astype(np.float32).astype(np.float64)
+    y32 = y.astype(np.float32).astype(np.float64)
+    ref, S, T, r0, ill = orc.fit(X32, y32, h, 1, gp, return_all=True)
+    mask = density_mask(S[:, 0])
+    assert rel_err(mh, ref[:, 0], mask) < 1e-5
+    s2 = plan.variance(h, Yd, mh_d, mode="log")[0].cpu().numpy()
+    yhat = orc.interp(mh, M, (0, 0), (1, 1), X32)
+    vref, _ = orc.variance(X32, y32, yhat, h, 1, M, (0, 0), (1, 1), mode="log")
+    assert rel_err(s2, vref, mask) < 1e-5
