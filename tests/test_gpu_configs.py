@@ -355,3 +355,31 @@ def test_coarse_grid_wide_band(orc):
     yhat = orc.interp(mh, M, (0, 0), (1, 1), X32)
     vref, _ = orc.variance(X32, y32, yhat, h, 1, M, (0, 0), (1, 1), mode="log")
     assert rel_err(s2, vref, mask) < 1e-5
+
+
+def test_anisotropic_band_and_grid(orc):
+    """A narrow bandwidth along dimension 0 on a coarse axis and a wide one
+    along dimension 1 on a fine axis, three responses: the 2-D inverse
+    intermediate [pair][M_1][2 K_0 + 1] is the largest transform buffer of
+    the plan.  Fits against the oracle."""
+    rng = np.random.default_rng(74)
+    N = 20000
+    X = rng.random((N, 2))
+    y = np.sin(6 * X[:, 0]) * (1 + X[:, 1]) + 0.1 * rng.standard_normal(N)
+    Y = np.stack([y, X[:, 1] ** 2, np.cos(3 * X[:, 0])], axis=1)
+    M, h = (9, 120), (0.03, 0.3)
+    plan = make_plan(2, 1, M, h, h, 1e-6, "fp32", n_max=N, max_weights=4, tprec="fp64")
+    g = plan.geometry
+    B0 = 2 * g.K[0] + 1
+    # eight channel pairs: the intermediate 8 B0 M_1 outgrows the forward
+    # buffers 8 B0 Mr_1 because M_1 > Mr_1
+    assert B0 > M[0] and M[1] > g.Mr[1]
+    plan.set_points(to_dev(X, torch.float32))
+    mh = plan.fit(h, to_dev(Y, torch.float32))[0].cpu().numpy()
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    X32 = X.astype(np.float32).astype(np.float64)
+    ref, S, T, r0, ill = orc.fit(X32, Y.astype(np.float32).astype(np.float64), h, 1, gp,
+                                 return_all=True)
+    mask = density_mask(S[:, 0])
+    for c in range(3):
+        assert rel_err(mh[c], ref[:, c], mask) < 1e-5
