@@ -23,14 +23,17 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    objs, procs = [], []
+    for src in SOURCES:   # the translation units compile in parallel
         obj = os.path.join(BUILD, src + ".o")
         cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd, stderr=None if verbose else subprocess.STDOUT)
+        procs.append((cmd, subprocess.Popen(cmd, stderr=None if verbose else subprocess.STDOUT)))
         objs.append(obj)
+    for cmd, pr in procs:
+        if pr.wait() != 0:
+            raise subprocess.CalledProcessError(pr.returncode, cmd)
     tmp = OUT + ".tmp"
     subprocess.check_call(["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, OUT)

@@ -289,7 +289,8 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
         const int64_t j0 = job_off[k], s0 = tile_off[k];
         for (int64_t q = 0; q < nj; ++q) {
             int32_t* e = jobs + 4 + 4 * (j0 + q);
-            const int64_t a0 = s0 + q * chunk, a1 = min<int64_t>(a0 + chunk, s0 + c);
+            // nj near-equal pieces of at most one chunk each
+            const int64_t a0 = s0 + q * c / nj, a1 = s0 + (q + 1) * c / nj;
             e[0] = (int32_t)k;
             e[1] = (int32_t)a0;
             e[2] = (int32_t)a1;
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
         const int64_t nj = (c + chunk - 1) / chunk;
         const int64_t j0 = job_off[k];
         for (int64_t q = 0; q < nj; ++q) {
-            const int64_t sz = min<int64_t>(chunk, c - q * chunk);
+            const int64_t sz = (q + 1) * c / nj - q * c / nj;   // the piece sizes of the loop above
             jobs[4 + 4 * atomicAdd(&bcnt[bucket(sz)], 1) + 3] = (int32_t)(j0 + q);
         }
     }
@@ -388,13 +389,18 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter_tiles(Geo g, int x_typ
     }
 }
 
-// Local cell (pitch g.tsp) of a packed first-cell record.
+// Local cell (pitch g.tsp) of a packed first-cell record: the sort key of
+// the samples within a job.  In 3-D the key is (x, y) major and z minor, so
+// the samples of one (x, y) column of first cells are contiguous with z
+// ascending (the 3-D column spread keeps such a run in registers).
 template <int D>
 __device__ __forceinline__ int local_cell(const Geo& g, uint32_t l) {
-    int c = (int)(l & 1023);
-    if (D > 1) c += g.tsp * (int)((l >> 10) & 1023);
-    if (D > 2) c += g.tsp * g.tsp * (int)((l >> 20) & 1023);
-    return c;
+    const int x = (int)(l & 1023);
+    if (D == 1) return x;
+    const int y = (int)((l >> 10) & 1023);
+    if (D == 2) return x + g.tsp * y;
+    const int z = (int)((l >> 20) & 1023);
+    return z + g.tsp * (x + g.tsp * y);
 }
 
 // Per job (a tile-ordered range of at most one chunk): order the job's
@@ -2078,6 +2084,217 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, const float* __restr
     }
 }
 
+// 3-D spread with one sample stream per wave, W = 8.  Lane l owns the (x, y)
+// footprint column (l % 8, l / 8) and keeps, for NC weight columns, the whole
+// z extent of the padded tile (PE = 15 planes) in registers.  Within a job the
+// samples are sorted by first cell with (x, y) major and z minor, so a wave
+// sees long runs (about a hundred samples) of one (x, y) column; a sample adds
+// its eight z planes at register offset z0 (a wave-uniform branch picks the
+// unrolled case per run of equal first cells), and the registers go to the
+// FP64 LDS tile only when the (x, y) column changes.  Per sample and column
+// that is eight FMAs per lane on all 64 lanes.
+//
+// A wave takes its samples in batches of kCol3Batch: one lane pair per sample
+// loads the record and weights with vector loads (the next batch is fetched
+// while the current one is spread), evaluates the sample's 24 kernel values
+// (12 per lane) and writes them with the weights to a per-wave LDS row; the
+// spreading loop then reads psi_x(dx) and psi_y(dy) per lane and psi_z and
+// the weights as broadcasts.  A launch spreads np pairs in passes of NC / 2
+// pairs (the LDS tile holds NC columns).
+constexpr int kCol3Batch = 32;
+constexpr int kCol3Row = 28;   // floats per staged sample: psi_x[8], psi_y[8], psi_z[8], w[4]
+
+template <int NC>
+__device__ __forceinline__ void col3_flush(float (&acc)[15][NC], double* tile, int cur, int dx, int dy) {
+    constexpr int PE = 15, PSUB = PE * PE * PE;
+    if (cur < 0) return;
+    double* t = tile + (cur & 1023) + dx + PE * (((cur >> 10) & 1023) + dy);
+#pragma unroll
+    for (int z = 0; z < PE; ++z)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            // columns past the pass's count hold zeros and land in tile
+            // columns that are never written out
+            atomicAdd(t + c * PSUB + PE * PE * z, (double)acc[z][c]);
+            acc[z][c] = 0.f;
+        }
+}
+
+// Staged samples i .. i + U - 1 of the batch (one first cell, plane Z0).
+template <int NC, int Z0, int U>
+__device__ __forceinline__ void col3_samples(float (&acc)[15][NC], const float* stage, int i, int dx, int dy) {
+    float px[U], py[U];
+    float4 z0[U], z1[U], wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float* row = stage + (i + u) * kCol3Row;
+        px[u] = row[dx];
+        py[u] = row[8 + dy];
+        z0[u] = *reinterpret_cast<const float4*>(row + 16);
+        z1[u] = *reinterpret_cast<const float4*>(row + 20);
+        wv[u] = *reinterpret_cast<const float4*>(row + 24);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const float pxy = px[u] * py[u];
+        const float wa[4] = {wv[u].x, wv[u].y, wv[u].z, wv[u].w};
+        const float pz[8] = {z0[u].x, z0[u].y, z0[u].z, z0[u].w, z1[u].x, z1[u].y, z1[u].z, z1[u].w};
+        float tc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) tc[c] = pxy * wa[c];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[Z0 + k][c] += tc[c] * pz[k];
+    }
+}
+
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// The run of staged samples from i (of nb) that share the packed first cell
+// `key` (plane Z0), in pairs while the next sample continues it.  Returns
+// the first sample after the run or the batch.
+template <int NC, int Z0>
+__device__ __forceinline__ int col3_run(float (&acc)[15][NC], uint32_t key, int i, int nb, const float* stage,
+                                        uint32_t keys, int dx, int dy) {
+    for (;;) {
+        if (i + 1 < nb && lane_value(keys, i + 1) == key) {
+            col3_samples<NC, Z0, 2>(acc, stage, i, dx, dy);
+            i += 2;
+            if (i >= nb || lane_value(keys, i) != key) return i;
+        } else {
+            col3_samples<NC, Z0, 1>(acc, stage, i, dx, dy);
+            return i + 1;
+        }
+    }
+}
+
+template <int KER, int NC, int NT>
+__global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* __restrict__ wrow, int wstride,
+                                                    int col0, const uint32_t* __restrict__ loc,
+                                                    const float* __restrict__ frac,
+                                                    const int32_t* __restrict__ jobs,
+                                                    float* __restrict__ subgrid) {
+    constexpr int W = 8, PE = 15, PSUB = PE * PE * PE;
+    constexpr int NWAVE = NT / 64;
+    constexpr int PPP = NC / 2;
+    constexpr int B = kCol3Batch;
+    static_assert(NC == 2 || NC == 4, "columns per pass");
+    // LDS: the tile [NC][PSUB] (cell = x + PE (y + PE z)), then one staging
+    // area of B rows per wave
+    extern __shared__ double tile[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float* const stage = reinterpret_cast<float*>(tile + NC * PSUB) + wave * B * kCol3Row;
+    const int dx = lane & 7, dy = lane >> 3;
+    // staging role: sample sl of the batch; the low half of the wave takes
+    // kernel values 0..11 of the row, the high half 12..23 and the weights
+    const int sl = lane & (B - 1);
+    const int hi = lane >> 5;
+    const float kp = (float)g.kparam;
+    const int njobs = jobs[0];
+    for (int b = blockIdx.x; b < njobs; b += gridDim.x) {
+        const int job = jobs[4 + 4 * b + 3];
+        const int s_beg = jobs[4 + 4 * job + 1];
+        const int n = jobs[4 + 4 * job + 2] - s_beg;
+        const int seg = (n + NWAVE - 1) / NWAVE;
+        const int q0 = min(n, wave * seg), q1 = min(n, q0 + seg);
+        for (int p0 = 0; p0 < np; p0 += PPP) {
+            const int nw = 2 * min(PPP, np - p0);   // columns of this pass
+            for (int c = threadIdx.x; c < NC * PSUB; c += blockDim.x) tile[c] = 0.0;
+            __syncthreads();
+            float acc[PE][NC];
+#pragma unroll
+            for (int z = 0; z < PE; ++z)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[z][c] = 0.f;
+            int cur = -1;   // packed (x, y) first cell held in the registers
+            const float* wp = wrow + col0 + 2 * p0 + (int64_t)s_beg * wstride;
+            // the batch in registers: sample q0 + bt + sl
+            uint32_t rkey = 0;
+            float rf[3] = {0.f, 0.f, 0.f}, rw[4] = {0.f, 0.f, 0.f, 0.f};
+            auto fetch = [&](int bt) {
+                const int q = bt + sl;
+                if (q < q1) {
+                    const int64_t si = (int64_t)s_beg + q;
+                    rkey = loc[si];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) rf[j] = frac[3 * si + j];
+                    if (hi)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) rw[c] = c < nw ? wp[(int64_t)q * wstride + c] : 0.f;
+                }
+            };
+            fetch(q0);
+            for (int bt = q0; bt < q1; bt += B) {
+                const int nb = min(B, q1 - bt);
+                // kernel values of the staged row: index j = 12 hi + k
+                // (dimension j / 8, offset j % 8), then the weights
+                {
+                    float* row = stage + sl * kCol3Row + 12 * hi;
+                    float kv[12];
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) {
+                        const int j = 12 * hi + k;
+                        const float f = j < 8 ? rf[0] : (j < 16 ? rf[1] : rf[2]);
+                        kv[k] = kernel_value<float, KER>((float)(j & 7) - f, W, kp);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 12; k += 4)
+                        *reinterpret_cast<float4*>(row + k) = make_float4(kv[k], kv[k + 1], kv[k + 2], kv[k + 3]);
+                    if (hi) *reinterpret_cast<float4*>(row + 12) = make_float4(rw[0], rw[1], rw[2], rw[3]);
+                }
+                const uint32_t keys = rkey;
+                if (bt + B < q1) fetch(bt + B);   // next batch, in flight while this one is spread
+                int i = 0;
+                while (i < nb) {
+                    const uint32_t key = lane_value(keys, i);
+                    const int xy = (int)(key & 0xFFFFFu);
+                    if (xy != cur) {
+                        col3_flush<NC>(acc, tile, cur, dx, dy);
+                        cur = xy;
+                    }
+                    switch ((int)((key >> 20) & 1023u)) {
+#define FKR_COL3_CASE(Z) case Z: i = col3_run<NC, Z>(acc, key, i, nb, stage, keys, dx, dy); break;
+                        FKR_COL3_CASE(0) FKR_COL3_CASE(1) FKR_COL3_CASE(2) FKR_COL3_CASE(3)
+                        FKR_COL3_CASE(4) FKR_COL3_CASE(5) FKR_COL3_CASE(6)
+                        default: i = col3_run<NC, 7>(acc, key, i, nb, stage, keys, dx, dy); break;
+#undef FKR_COL3_CASE
+                    }
+                }
+            }
+            col3_flush<NC>(acc, tile, cur, dx, dy);
+            __syncthreads();
+            // subgrid layout [job][pair][cell][re, im]
+            for (int q = 0; 2 * q < nw; ++q) {
+                float* dst = subgrid + ((int64_t)job * np + p0 + q) * PSUB * 2;
+                for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
+                    dst[2 * c] = (float)tile[2 * q * PSUB + c];
+                    dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int KER, int NC>
+static void spread_col3(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
+                        const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
+    constexpr int PSUB = 15 * 15 * 15;
+    constexpr int NT = NC == 2 ? 1024 : 768;
+    const size_t lds = (size_t)NC * PSUB * sizeof(double) + (size_t)(NT / 64) * kCol3Batch * kCol3Row * sizeof(float);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_col3<KER, NC, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_spread_col3<KER, NC, NT><<<nb, NT, lds, s>>>(g, src.npairs, static_cast<const float*>(src.w[0].ptr),
+                                                   (int)src.w[0].stride, (int)src.w[0].col, loc,
+                                                   static_cast<const float*>(frac), jobs,
+                                                   static_cast<float*>(subgrid));
+}
+
 template <int W, int KER, int NW>
 static void spread_wave(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
                         const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
@@ -2119,7 +2336,7 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
             // (the one-sample-per-wave kernel reads them with scalar loads, so
             // two columns need only 8-byte rows; the lane-group kernels need
             // 16-byte aligned rows)
-            const int al = (D == 2 && W <= 8 && src.npairs == 1) ? 2 : 4;
+            const int al = ((D == 2 || D == 3) && W == 8 && src.npairs == 1) || (D == 2 && W < 8 && src.npairs == 1) ? 2 : 4;
             bool rows = src.w[0].kind == W_SORTED && (src.w[0].col % al) == 0 && (src.w[0].stride % al) == 0;
             for (int q = 1; q < 2 * src.npairs; ++q)
                 rows = rows && src.w[q].kind == W_SORTED && src.w[q].ptr == src.w[0].ptr &&
@@ -2142,7 +2359,12 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
                     }
                     return;
                 }
-                if constexpr (D == 3) {
+                if constexpr (D == 3 && W == 8) {
+                    // columns per pass: four (a 108 KB FP64 tile), or two for
+                    // one pair (two workgroups per CU)
+                    if (src.npairs == 1) spread_col3<KER, 2>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    else spread_col3<KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
+                } else if constexpr (D == 3) {
                     spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
                 } else {
                     if (nw <= 4) spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
@@ -2343,9 +2565,10 @@ void launch_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, i
 }
 
 int resid_row_stride(const Geo& g, int prec) {
-    // (1, z) rows of 8 bytes where the two-column spread is the
-    // one-sample-per-wave kernel (2-D, FP32, w <= 8), else 16-byte rows
-    return prec == FKR_F32 && g.d == 2 && g.w <= 8 ? 2 : 4;
+    // (1, z) rows of 8 bytes where the two-column spread is a
+    // one-sample-per-wave kernel (FP32: 2-D with w <= 8, 3-D with w = 8),
+    // else 16-byte rows
+    return prec == FKR_F32 && ((g.d == 2 && g.w <= 8) || (g.d == 3 && g.w == 8)) ? 2 : 4;
 }
 
 void launch_resid(const Geo& g, int prec, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,

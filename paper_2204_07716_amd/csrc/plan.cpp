@@ -391,10 +391,12 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
         }
     }
 
-    // Spreading jobs: a tile's samples, cut into pieces so that dense tiles do
-    // not serialise on one workgroup.  Every piece costs one subgrid of
-    // (TS + W - 1)^d cells that the fold reads back, which weighs more in 3-D.
-    p->chunk = p->d <= 2 ? 1024 : 2048;
+    // Spreading jobs: a tile's samples, cut into near-equal pieces of at most
+    // one chunk so that dense tiles do not serialise on one workgroup.  Every
+    // piece costs one subgrid of (TS + W - 1)^d cells that the fold reads
+    // back, which weighs more in 3-D; there the pieces are large (the column
+    // spread keeps a whole (x, y) run of first cells in registers).
+    p->chunk = p->d <= 2 ? 1024 : 8192;
     p->n_jobs_max = p->n_tiles + (p->n_max + p->chunk - 1) / p->chunk + 1;
     p->npairs_max = (p->max_weights + 1) / 2;
     const int nreal = p->n_s + p->n_t * (p->max_weights - 1);
