@@ -65,6 +65,19 @@ enum { FKR_TP_SAME = 0, FKR_TP_F32 = 1, FKR_TP_F64 = 2 }; /* transform precision
 #define FKR_MAX_ORDER 2
 #define FKR_MAX_H 64        /* bandwidths per call */
 
+/* Support of the DF, RSS and GCV sums (fkr_cv, fkr_dof, fkr_gcv).  A grid
+ * point is *resolved* when its solve is well-posed and every Cholesky pivot
+ * of its bandwidth-equilibrated moment matrix exceeds FKR_RESOLVE times the
+ * matching diagonal entry: pivot_c / A_cc is one minus the uncentred R^2 of
+ * design column c on the earlier columns (the reciprocal of its variance
+ * inflation factor), so resolved points have a local design with VIF <= 1000
+ * in every direction.  A sample is *supported* when all 2^d corners of its
+ * interpolation cell are resolved; the Girard ratios, the RSS and N in eq.
+ * (22) run over the N_I supported samples only, and N_I is reported.  A
+ * sample whose cell touches a grid point this library leaves NaN (see
+ * fkr_fit) is left out as well. */
+#define FKR_RESOLVE 1e-3
+
 typedef struct fkr_plan fkr_plan;
 
 /* Plan description; mirrors the options of Table 1 that concern the fast
@@ -170,13 +183,15 @@ fkr_status fkr_moments(fkr_plan* plan, int nh, const double* h, int nw, const vo
  * bandwidth-equilibrated matrix); mhat = intercept.  Y: N x q (real or
  * complex).  mhat_dev: [nh][q][M^d] doubles (complex: [nh][q][M^d][2]).
  * s0_dev (optional, [nh][M^d] doubles): s_0, the unnormalised KDE of eq. (8).
- * Grid points whose system is ill-posed get NaN and are counted: some
- * Cholesky pivot c of the equilibrated matrix (s_0 is the first) is at most
- * max(1e-12 A_cc, e N K_h(0)), where K_h(0) = prod_j 1/(h_j sqrt(2 pi)) and
- * e = max(eps, unit round-off of the transform precision, 30 unit round-offs
- * of the spreading precision): the moments are only known to about
- * e N K_h(0).  NaN grid values propagate into the DF, RSS and GCV of any
- * sample whose interpolation cell touches them. */
+ * Grid points whose system the fast moments cannot resolve get NaN and are
+ * counted: some Cholesky pivot c of the equilibrated matrix (s_0 is the
+ * first) is at most max(r A_cc, e N K_h(0)), with K_h(0) = prod_j 1 / (h_j
+ * sqrt(2 pi)), r = max(64 unit round-offs of the spreading precision,
+ * 10 eps) (the moments are known to about that fraction of their local size)
+ * and e = max(16 unit round-offs of the transform precision, 1e-5 eps) (the
+ * transforms' global error).  This is a property of the fast path, not a
+ * reading of the method: the plain definition leaves every non-singular
+ * system well-posed. */
 fkr_status fkr_fit(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
                    const void* Y_dev, int y_type, double* mhat_dev, double* s0_dev,
                    void* stream);
@@ -190,9 +205,11 @@ fkr_status fkr_interp(fkr_plan* plan, int nv, const double* G_dev, int64_t Nq,
 
 /* Fast Monte-Carlo DF (Sec. 2.1, Girard): Np Gaussian probes w_p pushed
  * through the grid smoother (moments -> solve -> interpolation to the
- * samples).  rho_dev: [nh][Np] doubles, rho_p = w_p^T (w_p - w_hat_p) /
- * (w_p^T w_p); their mean estimates (1/N) tr(I - S_h).  Probes come from
- * probes_dev (N x Np, type w_type) or, when it is NULL, from the Philox4x32-10
+ * samples).  rho_dev: [nh][Np] doubles, rho_p = sum_I w_p (w_p - w_hat_p) /
+ * sum_I w_p^2 over the supported samples I (see FKR_RESOLVE); their mean
+ * estimates (1/N_I) tr((I - S_h)_II), and DF = N_I (1 - mean).  nused_dev
+ * (optional, [nh] doubles) receives N_I.  Probes come from probes_dev
+ * (N x Np, type w_type) or, when it is NULL, from the Philox4x32-10
  * generator: sample i, probe 4g + r uses word r of the Box-Muller transform of
  * the block with counter (i mod 2^32, floor(i / 2^32), g, 0) and key
  * (seed mod 2^32, floor(seed / 2^32)); uniforms u = (floor(x / 2^8) + 1/2)
@@ -200,18 +217,33 @@ fkr_status fkr_interp(fkr_plan* plan, int nv, const double* G_dev, int64_t Nq,
  * likewise from (2, 3), in FP64 for FP64 plans and with the hardware
  * log / sqrt / sin / cos for FP32 plans. */
 fkr_status fkr_dof(fkr_plan* plan, int nh, const double* h, int Np, uint64_t seed,
-                   const void* probes_dev, int w_type, double* rho_dev, void* stream);
+                   const void* probes_dev, int w_type, double* rho_dev, double* nused_dev,
+                   void* stream);
 
 /* Batched cross-validation (Sec. 2 and Fig. 3, cv_fkreg): for every h, the
  * fit of all q responses and the DF from Np probes share one spreading and
  * one forward FFT of every weight vector.  Outputs (any may be NULL):
- * mhat_dev as in fkr_fit; rho_dev [nh][Np]; rss_dev [nh][q] = sum_i
- * |y_i - yhat(x_i)|^2; gcv_dev [nh][q] = (rss/N) / mean_p(rho_p)^2 (eq. 22;
- * needs Np >= 1). */
+ * mhat_dev as in fkr_fit; rho_dev [nh][Np] as in fkr_dof; rss_dev [nh][q] =
+ * sum_I |y_i - yhat(x_i)|^2 over the supported samples; gcv_dev [nh][q] =
+ * (rss / N_I) / mean_p(rho_p)^2 (eq. 22; needs Np >= 1); nused_dev [nh] =
+ * N_I. */
 fkr_status fkr_cv(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
                   const void* Y_dev, int y_type, int Np, uint64_t seed,
                   const void* probes_dev, double* mhat_dev, double* rho_dev,
-                  double* rss_dev, double* gcv_dev, void* stream);
+                  double* rss_dev, double* gcv_dev, double* nused_dev, void* stream);
+
+/* GCV of eq. (22) for responses Y against a DF computed earlier (Sec. 2.1:
+ * the DF does not depend on y): rho_dev holds the [nh][Np] Girard ratios of
+ * fkr_dof (or fkr_cv) for the same points and bandwidths.  Fits density and
+ * Y at every h, interpolates the fits to the samples and sums the squared
+ * residuals over the supported samples I on the device; gcv_dev [nh][q] =
+ * (rss / N_I) / mean_p(rho_p)^2.  mhat_dev, rss_dev and nused_dev are
+ * optional (as in fkr_cv).  FKR_E_ARG for q < 1, Np < 1 or missing rho_dev
+ * or gcv_dev. */
+fkr_status fkr_gcv(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
+                   const void* Y_dev, int y_type, int Np, const double* rho_dev,
+                   double* mhat_dev, double* rss_dev, double* gcv_dev, double* nused_dev,
+                   void* stream);
 
 /* Conditional-variance second pass (Sec. 3) at one bandwidth h (d doubles):
  * residuals r_i = |y_i - mhat(x_i)|^2 from the mean fit's grid mhat_dev
@@ -220,16 +252,17 @@ fkr_status fkr_cv(fkr_plan* plan, int nh, const double* h, int q, int y_complex,
  *   FKR_VAR_LOG (eq. 24-26): v = fit of log(r_i + 1/N); kappa =
  *       [mean_i r_i exp(-v(x_i))]^-1; sigma^2(g) = exp(v(g)) / kappa;
  *   FKR_VAR_DIRECT (eq. 23): sigma^2(g) = fit of r_i.
- * The fit uses the plan's order.  sigma2_dev: [M^d] doubles; vhat_dev
- * (optional, FKR_VAR_LOG) [M^d]; kappa_dev (optional) 1 double.
- * The density moments s_alpha of the second fit equal those of the first
- * (same points, same h): when the plan's last fkr_fit, fkr_cv, fkr_moments
- * or fkr_variance call ran at a bandwidth bitwise equal to h, on the points
- * of the last fkr_set_points, and C(d+2l, 2l) is even, the call keeps them
- * from the plan's channel buffer and transforms only the moments t_alpha of
- * the new weights.  This choice is made on the host when the call is
- * enqueued; a graph that captured the call must replay it after the same
- * preceding call. */
+ * Samples whose residual is undefined (NaN mean fit at a corner of their
+ * cell) are left out of the second fit and of kappa, whose mean runs over the
+ * samples where r_i exp(-v(x_i)) is defined.  The fit uses the plan's order.
+ * sigma2_dev: [M^d] doubles; vhat_dev (optional, FKR_VAR_LOG) [M^d];
+ * kappa_dev (optional) 1 double.  The density moments s_alpha of the second
+ * fit equal those of the first (same points, same h, no sample left out):
+ * when C(d+2l, 2l) is even and the channel buffer still holds them from the
+ * plan's last fkr_fit, fkr_cv, fkr_gcv, fkr_moments or fkr_variance call at
+ * a bitwise equal h on the same points, the call transforms only the moments
+ * t_alpha of the new weights.  The check runs on the device, so a captured
+ * graph replays correctly after any preceding call. */
 fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const void* Y_dev,
                         int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
                         double* vhat_dev, double* kappa_dev, void* stream);
@@ -268,8 +301,12 @@ fkr_status fkr_profile_enable(fkr_plan* plan, int on);
 fkr_status fkr_profile_read(fkr_plan* plan, int stage, double* ms, int64_t* launches);
 
 /* Synchronises the stream of the last call and reports the device-side
- * counters.  Returns FKR_E_DOMAIN if samples were outside the box,
- * FKR_WARN_ILLPOSED if the last solve produced NaN points, else FKR_OK. */
+ * counters.  Returns FKR_E_STATE if a call since the last fkr_set_points
+ * found other points sorted on the device than the plan's last
+ * fkr_set_points left there (a replayed graph that sorted other points: the
+ * call did nothing; call fkr_set_points again), FKR_E_DOMAIN if samples were
+ * outside the box, FKR_WARN_ILLPOSED if the last solve produced NaN points,
+ * else FKR_OK. */
 fkr_status fkr_get_diagnostics(fkr_plan* plan, fkr_diag* out);
 
 const char* fkr_status_string(fkr_status s);

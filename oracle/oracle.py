@@ -30,11 +30,24 @@ deviation (H = diag(h^2)); the kernel is the normalised Gaussian; the
 displacement is z = x_i - g; the design row holds every monomial of total
 degree <= l in graded order; the Girard estimate is the mean over probes of
 per-probe ratios; a grid point is ill-posed (NaN) when some pivot of the
-equilibrated moment matrix (s_0 is the first) is at most max(1e-12 times its
-diagonal entry, ``floor``), the floor being a caller-chosen absolute noise
-level (0 by default, i.e. only exact or near-exact singularity); NaN fit values
-propagate into the DF and GCV of samples whose interpolation cell touches
-them, and ``rgcv_select`` skips NaN GCV values.
+equilibrated moment matrix (s_0 is the first) is at most 1e-12 times its
+diagonal entry (exact or near-exact singularity, nothing else).
+
+DF, RSS and GCV are sums over the *supported* samples: those whose
+interpolation cell has all 2^d corners *resolved*.  A grid point is resolved
+when it is not ill-posed and every pivot of its moment matrix is more than
+``RESOLVE`` = 1e-3 times the matching diagonal entry.  The ratio pivot_c / A_cc
+is the part of the c-th design column's weighted second moment that the
+earlier columns do not explain (one minus its uncentred R^2, the reciprocal
+of its variance inflation factor), so the rule keeps the points whose local
+design has VIF <= 1000 in every direction; it does not depend on the
+bandwidth equilibration.  The Girard ratio, RSS and GCV of eq. (22) then use
+N_I supported samples in place of N.  In the variance pass, samples whose
+residual is undefined (the mean fit is NaN at a corner of their cell) are
+left out of the second fit and of kappa.  ``rgcv_select`` skips NaN GCV values.
+
+No part of this module is pinned to the fast path's arithmetic: every
+threshold here is a fixed reading of the method, not a round-off model.
 
 Parity pins for every function here live in ``tests/test_oracle_*.py``.
 """
@@ -53,7 +66,8 @@ _SRC = os.path.join(_HERE, "fkr_oracle.c")
 _LIB = os.path.join(_HERE, "libfkr_oracle.so")
 _lib = None
 
-ILL_REL = 1e-12
+ILL_REL = 1e-12      # relative pivot at or below which a point is ill-posed
+RESOLVE = 1e-3       # pivot / A_cc above which a point supports DF / RSS sums
 
 
 def build(force: bool = True) -> str:
@@ -199,12 +213,29 @@ def pivots(A: np.ndarray) -> np.ndarray:
     return pv
 
 
-def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int,
-          floor: float = 0.0):
+def relative_pivots(A: np.ndarray) -> np.ndarray:
+    """pivot_c / A_cc for each symmetric matrix in A (G x P x P): one minus
+    the uncentred R^2 of design column c on the columns before it (the
+    reciprocal of its variance inflation factor).  Invariant to diagonal
+    scaling, so the bandwidth equilibration does not change it."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return pivots(A) / np.diagonal(A, axis1=1, axis2=2)
+
+
+def resolved(S: np.ndarray, h: Sequence[float], order: int, d: int,
+             kappa: float = RESOLVE) -> np.ndarray:
+    """Grid points whose moment matrix is resolved: every relative pivot
+    exceeds kappa (VIF <= 1 / kappa in every design direction)."""
+    rp = relative_pivots(assemble(S, h, order, d))
+    with np.errstate(invalid="ignore"):
+        return np.all(rp > kappa, axis=1)
+
+
+def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int):
     """Per grid point: solve A c = t (eq. 3 / 11) and return
     mhat (G x nw) = c_0, r0 (G x P) = row 0 of the inverse of the
     equilibrated matrix, and the ill-posed mask (G,): some pivot of the
-    equilibrated matrix is at most max(1e-12 A_cc, floor)."""
+    equilibrated matrix is at most 1e-12 A_cc."""
     et = multi_indices(d, order)
     h = np.asarray(h, dtype=np.float64)
     scale = np.array([np.prod(h ** np.array(b)) for b in et])
@@ -212,7 +243,7 @@ def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int,
     rhs = T / scale[None, None, :]
     G, nw, P = rhs.shape
     pv = pivots(A)
-    thr = np.maximum(ILL_REL * np.diagonal(A, axis1=1, axis2=2), floor)
+    thr = ILL_REL * np.diagonal(A, axis1=1, axis2=2)
     with np.errstate(invalid="ignore"):
         ill = ~np.all(pv > thr, axis=1)
     ok = ~ill
@@ -236,18 +267,17 @@ def _split_complex(Y: np.ndarray):
     return Y.astype(np.float64), False
 
 
-def fit(X, Y, h, order, gpts, return_all: bool = False, floor: float = 0.0):
+def fit(X, Y, h, order, gpts, return_all: bool = False):
     """m_hat(g; l) of eq. (11) at the given grid points, for each response
     column (complex responses: real and imaginary parts share the real moment
-    matrix); ``floor`` is the absolute pivot floor of ``solve``.
-    Returns mhat (G x q) [, S, T, r0, ill]."""
+    matrix).  Returns mhat (G x q) [, S, T, r0, ill]."""
     X = np.asarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X[:, None]
     d = X.shape[1]
     W, cplx = _split_complex(Y)
     S, T = moments(X, W, h, order, gpts)
-    mhat, r0, ill = solve(S, T, h, order, d, floor)
+    mhat, r0, ill = solve(S, T, h, order, d)
     if cplx:
         q = W.shape[1] // 2
         mhat = mhat[:, :q] + 1j * mhat[:, q:]
@@ -259,6 +289,31 @@ def fit(X, Y, h, order, gpts, return_all: bool = False, floor: float = 0.0):
 # ---------------------------------------------------------------------------
 # Interpolation (Sec. 1.1 end, Sec. 5: linear griddedInterpolant)
 # ---------------------------------------------------------------------------
+
+def cell_corners(M, lo, hi, Xq: np.ndarray) -> np.ndarray:
+    """Flat grid indices (n x 2^d) of the corners of each point's
+    interpolation cell, floor((x - lo)/Delta) clamped to [0, M - 2]."""
+    Xq = np.asarray(Xq, dtype=np.float64)
+    if Xq.ndim == 1:
+        Xq = Xq[:, None]
+    d = Xq.shape[1]
+    cell = []
+    for j in range(d):
+        delta = (hi[j] - lo[j]) / (M[j] - 1)
+        cell.append(np.clip(np.floor((Xq[:, j] - lo[j]) / delta).astype(np.int64), 0, M[j] - 2))
+    out = np.zeros((Xq.shape[0], 1 << d), dtype=np.int64)
+    for q, corner in enumerate(itertools.product((0, 1), repeat=d)):
+        stride = 1
+        for j in range(d):
+            out[:, q] += (cell[j] + corner[j]) * stride
+            stride *= M[j]
+    return out
+
+
+def supported(ok_grid: np.ndarray, M, lo, hi, X: np.ndarray) -> np.ndarray:
+    """Samples whose interpolation cell has every corner in ok_grid."""
+    return np.all(np.asarray(ok_grid, dtype=bool)[cell_corners(M, lo, hi, X)], axis=1)
+
 
 def interp(values: np.ndarray, M, lo, hi, Xq: np.ndarray) -> np.ndarray:
     """Multilinear interpolation of grid values (G x k, or G) at Xq (n x d).
@@ -354,24 +409,51 @@ def girard_ratios(Wp: np.ndarray, What: np.ndarray) -> np.ndarray:
     return np.einsum("ip,ip->p", Wp, Wp - What) / np.einsum("ip,ip->p", Wp, Wp)
 
 
-def dof(X, h, order, M, lo, hi, Wp, floor: float = 0.0):
+def support(X, h, order, M, lo, hi, kappa: float = RESOLVE):
+    """Supported samples at bandwidth h (see the module docstring): the grid
+    fit of the density moments, the resolved points, and the samples whose
+    cell corners are all resolved.  Returns (supported samples, resolved
+    grid points)."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    d = X.shape[1]
+    S, _ = moments(X, None, h, order, grid_points(M, lo, hi))
+    ok = resolved(S, h, order, d, kappa)
+    return supported(ok, M, lo, hi, X), ok
+
+
+def dof(X, h, order, M, lo, hi, Wp, kappa: float = RESOLVE, include=None):
     """Fast Monte-Carlo DF (Sec. 2.1): each probe is pushed through the grid
-    smoother (moments -> solve -> interpolation back to the samples).
-    Returns (rho per probe, mean rho ~ (1/N) tr(I - S), DF = N (1 - mean))."""
+    smoother (moments -> solve -> interpolation back to the samples), and the
+    Girard ratio is taken over the supported samples I (``include``, or the
+    rule of ``support`` with ``kappa``; kappa = 0 keeps every sample whose
+    cell has no ill-posed corner):
+        rho_p = sum_I w_ip (w_ip - w_hat_ip) / sum_I w_ip^2.
+    Returns (rho per probe, mean rho ~ (1/N_I) tr((I - S)_II),
+    DF = N_I (1 - mean), supported-sample mask)."""
     X = np.asarray(X, dtype=np.float64).reshape(len(Wp), -1)
+    d = X.shape[1]
     gp = grid_points(M, lo, hi)
-    mh = fit(X, Wp, h, order, gp, floor=floor)
+    mh, S, T, r0, ill = fit(X, Wp, h, order, gp, return_all=True)
+    if include is None:
+        ok = ~ill & (resolved(S, h, order, d, kappa) if kappa > 0 else True)
+        include = supported(ok, M, lo, hi, X)
+    include = np.asarray(include, dtype=bool)
     What = interp(mh, M, lo, hi, X)
-    rho = girard_ratios(Wp, What)
+    rho = girard_ratios(Wp[include], What[include])
     m = float(np.mean(rho))
-    return rho, m, X.shape[0] * (1.0 - m)
+    return rho, m, int(include.sum()) * (1.0 - m), include
 
 
-def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float) -> np.ndarray:
-    """eq. (22): (1/N) ||y - yhat||^2 / [(1/N) tr(I - S)]^2 per response column
-    (|.|^2 for complex responses)."""
+def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float, include=None) -> np.ndarray:
+    """eq. (22): (1/N_I) sum_I |y - yhat|^2 / [(1/N_I) tr((I - S)_II)]^2 per
+    response column over the supported samples I (all when include is
+    None); |.|^2 for complex responses."""
     r = np.asarray(y) - np.asarray(yhat)
     r = r.reshape(r.shape[0], -1)
+    if include is not None:
+        r = r[np.asarray(include, dtype=bool)]
     return np.mean(np.abs(r) ** 2, axis=0) / rho_mean ** 2
 
 
@@ -415,26 +497,30 @@ def get_hlist(n, rng, kind: str = "log") -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
-             gpts: Optional[np.ndarray] = None, floor: float = 0.0):
+             gpts: Optional[np.ndarray] = None):
     """Second pass on squared residuals r_i = |y_i - yhat(x_i)|^2.
 
+    Samples whose residual is undefined (NaN mean fit at their cell) are left
+    out of the second fit and of kappa.
     mode "log" (eq. 24-26): v = local fit of log(r_i + 1/N); kappa =
-    [mean_i r_i exp(-v(x_i))]^-1 with v(x_i) interpolated from the full grid;
-    sigma^2(g) = exp(v(g)) / kappa.
+    [mean_i r_i exp(-v(x_i))]^-1 with v(x_i) interpolated from the full grid,
+    over the samples where that term is defined; sigma^2(g) = exp(v(g)) / kappa.
     mode "direct" (eq. 23): sigma^2(g) = local fit of r_i.
     Returns (sigma2 at gpts (or the full grid), extras dict)."""
     X = np.asarray(X, dtype=np.float64).reshape(len(yhat_at_samples), -1)
     N = X.shape[0]
     r = np.abs(np.asarray(y).reshape(N) - np.asarray(yhat_at_samples).reshape(N)) ** 2
+    keep = np.isfinite(r)
     full = grid_points(M, lo, hi)
     if mode == "direct":
-        s2 = fit(X, r, h, order, full if gpts is None else gpts, floor=floor)[:, 0]
+        s2 = fit(X[keep], r[keep], h, order, full if gpts is None else gpts)[:, 0]
         return s2, {"r": r}
     z = np.log(r + 1.0 / N)
-    v_full = fit(X, z, h, order, full, floor=floor)[:, 0]
+    v_full = fit(X[keep], z[keep], h, order, full)[:, 0]
     v_i = interp(v_full, M, lo, hi, X)
-    kappa = 1.0 / np.mean(r * np.exp(-v_i))
-    v = v_full if gpts is None else fit(X, z, h, order, gpts, floor=floor)[:, 0]
+    term = r * np.exp(-v_i)
+    kappa = 1.0 / np.mean(term[np.isfinite(term)])
+    v = v_full if gpts is None else fit(X[keep], z[keep], h, order, gpts)[:, 0]
     return np.exp(v) / kappa, {"r": r, "z": z, "v": v_full, "kappa": kappa}
 
 

@@ -15,6 +15,7 @@ FKR_KERNEL_ES, FKR_KERNEL_GAUSS = 0, 1
 FKR_VAR_LOG, FKR_VAR_DIRECT = 0, 1
 FKR_TP_SAME, FKR_TP_F32, FKR_TP_F64 = 0, 1, 2
 FKR_MAX_H = 64
+FKR_RESOLVE = 1e-3
 
 I64x3 = ctypes.c_int64 * 3
 F64x3 = ctypes.c_double * 3
@@ -45,7 +46,7 @@ class Diag(ctypes.Structure):
 
 EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_workspace_size",
            "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit",
-           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_variance", "fkr_get_diagnostics",
+           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_get_diagnostics",
            "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
            "fkr_profile_read"]
 
@@ -83,8 +84,9 @@ def load() -> ctypes.CDLL:
         "fkr_moments": ([P, I, pD, I, P, I, P, P, P], I),
         "fkr_fit": ([P, I, pD, I, I, P, I, P, P, P], I),
         "fkr_interp": ([P, I, P, I64, P, I, P, P], I),
-        "fkr_dof": ([P, I, pD, I, U64, P, I, P, P], I),
-        "fkr_cv": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P], I),
+        "fkr_dof": ([P, I, pD, I, U64, P, I, P, P, P], I),
+        "fkr_cv": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P, P], I),
+        "fkr_gcv": ([P, I, pD, I, I, P, I, I, P, P, P, P, P, P], I),
         "fkr_variance": ([P, pD, I, P, I, P, I, P, P, P, P], I),
         "fkr_get_diagnostics": ([P, ctypes.POINTER(Diag)], I),
         "fkr_status_string": ([I], ctypes.c_char_p),

@@ -106,6 +106,8 @@ const int* dev_es(fkr_plan* p) { return at<int>(p, p->lay.consts + 64); }
 const int* dev_et(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 512); }
 const int* dev_pidx(fkr_plan* p) { return at<int>(p, p->lay.consts + 64 + 1024); }
 unsigned long long* ill_ctr(fkr_plan* p) { return at<unsigned long long>(p, p->lay.diag + 2 * 8); }
+long long* diag_ptr(fkr_plan* p) { return at<long long>(p, p->lay.diag); }
+PointsCheck points_check(fkr_plan* p) { return PointsCheck{p->N, p->epoch, diag_ptr(p)}; }
 
 // Every weight vector of a call, constants included, gathered once into
 // sorted sample order: rows of `stride` = nr rounded up to 4 columns (the
@@ -121,7 +123,7 @@ std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipS
         const int n = std::min(2 * kMaxPairsPerSpread, stride - r0);
         for (int q = 0; q < n; ++q) chunk.w[q] = all[r0 + q];
         StageTimer t(p, FKR_STAGE_WEIGHTS, s);
-        launch_stage_weights(p->prec, chunk, n, r0, stride, p->N, at<int32_t>(p, p->lay.perm), buf, s);
+        launch_stage_weights(p->prec, chunk, n, r0, stride, points_check(p), at<int32_t>(p, p->lay.perm), buf, s);
     }
     std::vector<WSrc> out(stride);
     for (int r = 0; r < stride; ++r) {
@@ -207,31 +209,26 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-// True when the channel buffer holds the density moments of the current
-// points at bandwidth h (bitwise equal h), left there by the last fit, cv,
-// moments or variance call.
-bool reuse_density_channels(const fkr_plan* p, const double* h) {
-    if (!p->schan_valid || p->n_s % 2 != 0) return false;
-    for (int j = 0; j < p->d; ++j)
-        if (p->schan_h[j] != h[j]) return false;
-    return true;
-}
-
-// Channels at one bandwidth h: expansion + inverse FFT -> chan [pair][M][re, im],
-// channel pairs c0 .. ncp - 1 (pair c at pair offset c).  Weight 0 of the
-// spectra is the density in every caller, so afterwards the first n_s / 2
-// pairs hold its moments s_alpha at h.
+// Channels at one bandwidth h: expansion + inverse FFT -> chan [pair][M][re, im].
+// Weight 0 of the spectra is the density in every caller, so afterwards the
+// first n_s / 2 pairs hold its moments s_alpha at h, and (when n_s is even) a
+// device tag records the points epoch and h they belong to.  With reuse, the
+// passes skip those pairs when the tag already matches (the density moments
+// depend on the points and h only); the decision is taken on the device, so a
+// captured graph stays valid whatever ran before its replay.
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
-                        int c0 = 0) {
+                        bool reuse = false) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
-    if (ncp > p->ncp_max || c0 < 0 || c0 >= ncp) return FKR_E_ARG;
-    if (c0 > 0 && !reuse_density_channels(p, h)) return FKR_E_ARG;
-    p->schan_valid = false;
-    const int nout = ncp - c0;
+    if (ncp > p->ncp_max) return FKR_E_ARG;
+    const bool even = p->n_s % 2 == 0;
+    reuse = reuse && even;
+    const int64_t c_keep = reuse ? p->n_s / 2 : 0;   // pairs a matching tag lets the passes skip
+    if (reuse) launch_chan_reuse(diag_ptr(p), h, p->d, s);
+    const long long* skip_flag = reuse ? diag_ptr(p) + kDiagReuse : nullptr;
     ExpandArgs a{};
     a.d = p->d; a.n_s = p->n_s; a.n_t = p->n_t; a.nreal = nreal; a.ncp = ncp;
-    a.c0 = c0;
+    a.c0 = 0;
     a.npairs = (nr + 1) / 2;
     for (int j = 0; j < 3; ++j) { a.B[j] = p->B[j]; a.K[j] = p->K[j]; }
     for (int j = 0; j < p->d; ++j) { a.h[j] = h[j]; a.T[j] = p->T[j]; }
@@ -239,8 +236,7 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     a.ill_clear = ill_clear;
     // the first inverse pass expands its rows from the pair spectra itself
     StageTimer tf(p, FKR_STAGE_FFT_INV, s);
-    const size_t tcsz = p->tprec == FKR_F64 ? 16 : 8;
-    void* chan_out = p->ws + p->lay.chan + (size_t)c0 * p->Mtot * tcsz;
+    void* chan_out = p->ws + p->lay.chan;
     auto pass = [&](int j) {
         FftPass f{};
         f.n_in = p->B[j];
@@ -253,6 +249,7 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         for (int q = 0; q < p->fL[j].nfac; ++q) f.fac[q] = p->fL[j].fac[q];
         f.tw = at<double>(p, p->fL[j].tw_off);
         f.fac_out = nullptr;
+        f.skip_flag = skip_flag;
         return f;
     };
     auto expand = [&](FftPass& f, int64_t rest, int64_t rmul, int64_t emul) {
@@ -271,7 +268,8 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         // contiguous run.  Pass 1: row = (pair, e_0), element e_1, output
         // [pair][m_1][e_0].  Pass 2: row = (pair, m_1), element e_0.
         FftPass f1 = pass(1);
-        f1.rows = nout * p->B[0];
+        f1.rows = ncp * p->B[0];
+        f1.skip_rows = c_keep * p->B[0];
         expand(f1, p->B[0], 1, p->B[0]);
         f1.out_estride = p->B[0];
         f1.out_roff = 0;
@@ -280,7 +278,8 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         void* mid = p->ws + p->lay.fftA;
         launch_fft(p->tprec, true, f1, nullptr, mid, s);
         FftPass f0 = pass(0);
-        f0.rows = nout * p->M[1];
+        f0.rows = ncp * p->M[1];
+        f0.skip_rows = c_keep * p->M[1];
         f0.out_estride = 1;
         f0.out_roff = 0;
         f0.out_rdiv = 1;
@@ -293,7 +292,8 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
             FftPass f = pass(j);
             int64_t rest = 1;
             for (int i = j + 1; i < p->d; ++i) rest *= p->B[i];
-            f.rows = done_M * nout * rest;
+            f.rows = done_M * ncp * rest;
+            f.skip_rows = c_keep * done_M * rest;
             if (j == 0) expand(f, rest, p->B[0], 1);
             // row = (pair, m over the done dimensions, e over the rest) with
             // the pair outermost; the output keeps the pair outermost, so the
@@ -310,28 +310,33 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
             done_M *= p->M[j];
         }
     }
-    if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
-    if (p->n_s % 2 == 0) {
-        p->schan_valid = true;
-        for (int j = 0; j < 3; ++j) p->schan_h[j] = j < p->d ? h[j] : 0.0;
-    }
-    return FKR_OK;
+    if (even) launch_chan_tag(diag_ptr(p), h, p->d, s);
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-double s0_floor(const fkr_plan* p, const double* h) {
-    // Noise floor of the moment matrix.  Every channel is known only to a
-    // relative accuracy e of N K_h(0), the largest value s_0 can take: e is
-    // the NUFFT tolerance, or the round-off of the transforms, or 30 unit
-    // round-offs of the spreading arithmetic, whichever is coarsest.  A
-    // Cholesky pivot (s_0 is the first) at or below e N K_h(0) cannot be told
-    // apart from a singular system.
+// Ill-posedness floors of the solve.  The moments are known to about a
+// relative 1e-6 of their local size with FP32 spreading (the spreading
+// kernel's values carry FP32 round-off; the LDS sums are FP64) and to about
+// the requested accuracy eps otherwise (the spreading kernel is sized for
+// eps / 10), so a pivot below rel_floor A_cc = max(64 unit round-offs,
+// 10 eps) A_cc cannot be told from a singular direction.  Globally the transforms add an error of
+// about the transform round-off (16 units) or 1e-5 of the requested accuracy
+// times N K_h(0), the largest value s_0 can take; a pivot below that absolute
+// floor is noise.  (Measured on the workloads: relative errors of 3e-7 to
+// 8e-6 with FP32 spreading, absolute errors below 3.1e-12 N K_h(0) with FP64
+// transforms and below 2e-7 N K_h(0) with FP32 transforms.)
+double abs_floor(const fkr_plan* p, const double* h) {
     double k0 = 1.0;
     for (int j = 0; j < p->d; ++j) k0 *= 1.0 / (h[j] * std::sqrt(2.0 * M_PI));
     const double u32 = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
-    const double us = p->prec == FKR_F64 ? u64 : u32;
     const double ut = p->tprec == FKR_F64 ? u64 : u32;
-    const double e = std::max(std::max(p->eps, ut), 30.0 * us);
+    const double e = std::max(16.0 * ut, 1e-5 * p->eps);
     return std::max(1e-300, e * (double)std::max<int64_t>(p->N, 1) * k0);
+}
+
+double rel_floor(const fkr_plan* p) {
+    const double u32 = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
+    return std::max(64.0 * (p->prec == FKR_F64 ? u64 : u32), 10.0 * p->eps);
 }
 
 SolveArgs solve_args(fkr_plan* p, int nr, int ny, int y_cplx, const double* h) {
@@ -340,7 +345,9 @@ SolveArgs solve_args(fkr_plan* p, int nr, int ny, int y_cplx, const double* h) {
     a.ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;
     a.nr = nr; a.ny = ny; a.y_cplx = y_cplx;
     a.Mtot = p->Mtot;
-    a.s0_floor = s0_floor(p, h);
+    a.abs_floor = abs_floor(p, h);
+    a.rel_floor = rel_floor(p);
+    a.resolve = FKR_RESOLVE;
     a.ill_count = at<unsigned long long>(p, p->lay.diag + 2 * 8);
     return a;
 }
@@ -365,6 +372,77 @@ fkr_status common_fit_checks(fkr_plan* p, int nh, const double* h, int q, int y_
     if (q < 0 || (q > 0 && !Y && p->N > 0) || (y_complex != 0 && y_complex != 1)) return FKR_E_ARG;
     if (q > 0 && !valid_type(y_type)) return FKR_E_ARG;
     return FKR_OK;
+}
+
+// Fits, DF and RSS of a bandwidth list (the batched loop of Sec. 2 and
+// Fig. 3).  With rho_in the DF is given (fkr_gcv): no probes are spread and
+// the GCV uses the given Girard ratios.
+fkr_status cv_impl(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y, int y_type, int Np,
+                   uint64_t seed, const void* probes, const double* rho_in, double* mhat, double* rho, double* rss,
+                   double* gcv, double* nused, hipStream_t s) {
+    fkr_status st;
+    const int cpl = y_complex ? 2 : 1;
+    const int ny = q * cpl;
+    const int Ns = rho_in ? 0 : Np;   // probes that are spread
+    const int ptype = y_type;
+    std::vector<WSrc> srcs{src_one()};
+    add_response_sources(&srcs, q, y_complex, Y, y_type);
+    add_probe_sources(&srcs, Ns, seed, probes, ptype);
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
+    const Geo g = make_geo(p);
+    const int nr = (int)srcs.size();
+    double* internal = at<double>(p, p->lay.mhat);
+    // probe fits [M][pstride] in the spreading precision (they only feed the
+    // DF reduction), 16-byte aligned rows for FP32
+    const bool pf32 = p->prec == FKR_F32;
+    // one real response and all probes in one reduction launch: the y fit
+    // rides in column 0 of the FP32 rows, so the reduction gathers one row
+    // (NaN rows mark the corners that are not resolved)
+    const bool yrow = pf32 && q == 1 && !y_complex && Ns <= kRedProbes;
+    const int pstride = pf32 ? ((yrow ? 1 : 0) + Ns + 3) & ~3 : std::max(Ns, 1);
+    void* pfit = p->ws + p->lay.mhat + (((size_t)ny * p->Mtot * 8 + 15) & ~(size_t)15);
+    double* red = at<double>(p, p->lay.red);
+    double* partial = at<double>(p, p->lay.partial);
+    float* sup = at<float>(p, p->lay.sup);
+    const int n_items = q + Ns;
+    for (int hi = 0; hi < nh; ++hi) {
+        if ((st = run_channels(p, h + hi * p->d, nr, hi == 0 ? ill_ctr(p) : nullptr, s)) != FKR_OK) return st;
+        SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
+        double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
+        a.y_out = yfit;
+        a.probe_out = (yrow || Ns > 0) ? pfit : nullptr;
+        a.probe_f32 = pf32 ? 1 : 0;
+        a.probe_stride = pstride;
+        a.rows_with_y = yrow ? 1 : 0;
+        a.sup_out = sup;
+        {
+            StageTimer t(p, FKR_STAGE_SOLVE, s);
+            launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+        }
+        ReduceCvArgs r{};
+        r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
+        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
+        r.ny_cols = q; r.y_cplx = y_complex; r.yfit = yfit;
+        r.np = Ns; r.pfit = pfit; r.pstride = pstride; r.yrow = yrow ? 1 : 0;
+        r.sup = sup;
+        r.partial = partial;
+        StageTimer t(p, FKR_STAGE_REDUCE, s);
+        // probes per launch: at most kRedProbes, spread evenly over the launches
+        const int nlp = (Ns + kRedProbes - 1) / kRedProbes;
+        const int pper = nlp > 0 ? (Ns + nlp - 1) / nlp : 0;
+        const int nlaunch = std::max(std::max((q + kRedYCols - 1) / kRedYCols, nlp), 1);
+        for (int li = 0; li < nlaunch; ++li) {
+            r.y0 = li * kRedYCols;
+            r.ny_launch = std::max(0, std::min(kRedYCols, q - r.y0));
+            r.p0 = li * pper;
+            r.np_launch = std::max(0, std::min(pper, Ns - r.p0));
+            r.count_slot = li == 0 ? 2 * n_items : -1;   // every launch counts the same samples
+            launch_reduce_cv(g, r, s);
+        }
+        launch_reduce_final(partial, 2 * n_items + 1, red, s);
+        launch_finalize_cv(hi, Np, q, red, n_items, q, rho_in, rho, rss, gcv, nused, s);
+    }
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
 }  // namespace
@@ -431,7 +509,6 @@ fkr_status fkr_set_workspace(fkr_plan* p, void* ws, size_t bytes) {
     p->ws_bytes = bytes;
     p->ws_ready = false;
     p->points_set = false;
-    p->schan_valid = false;
     std::vector<unsigned char> consts(4096, 0);
     double* per = reinterpret_cast<double*>(consts.data());
     for (int j = 0; j < p->d; ++j) per[j] = p->T[j];
@@ -467,8 +544,8 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     if (!p) return FKR_E_ARG;
     if (!p->ws_ready) return FKR_E_WORKSPACE;
     if (N < 0 || N > p->n_max || (N > 0 && !X) || !valid_type(x_type)) return FKR_E_ARG;
-    p->schan_valid = false;
     const hipStream_t s = S(stream);
+    const long long epoch = p->epoch + 1;
     const Geo g = make_geo(p);
     StageTimer t(p, FKR_STAGE_SORT, s);
     // the tile counts need clearing only where the binning adds to them with
@@ -476,15 +553,16 @@ fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, voi
     if (p->n_tiles > kLdsHistMax || N == 0) launch_zero(p->ws + p->lay.counts, (p->n_tiles + 1) * 4, s);
     launch_bin_count(g, x_type, X, N, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.bhist),
                      at<int32_t>(p, p->lay.obuf), s);
-    launch_scan(g, N, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
+    launch_scan(g, N, epoch, at<int32_t>(p, p->lay.counts), at<int32_t>(p, p->lay.tile_off),
                 at<int32_t>(p, p->lay.job_off), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.cursor),
-                at<long long>(p, p->lay.diag), at<int32_t>(p, p->lay.obuf), s);
+                diag_ptr(p), at<int32_t>(p, p->lay.obuf), s);
     launch_sort_cells(g, p->prec, x_type, X, N, p->n_jobs_max, at<int32_t>(p, p->lay.tile_off),
                       at<int32_t>(p, p->lay.cursor), at<int32_t>(p, p->lay.jobs), at<int32_t>(p, p->lay.bhist),
                       p->ws + p->lay.trec, at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac,
                       at<int32_t>(p, p->lay.perm), p->ws + p->lay.xs, s);
     if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
     p->N = N;
+    p->epoch = epoch;
     p->points_set = true;
     p->last_stream = stream;
     return FKR_OK;
@@ -563,75 +641,36 @@ fkr_status fkr_interp(fkr_plan* p, int nv, const double* G, int64_t Nq, const vo
 
 fkr_status fkr_cv(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y, int y_type,
                   int Np, uint64_t seed, const void* probes, double* mhat, double* rho, double* rss,
-                  double* gcv, void* stream) {
+                  double* gcv, double* nused, void* stream) {
     fkr_status st = common_fit_checks(p, nh, h, q, y_complex, Y, y_type);
     if (st != FKR_OK) return st;
     if (Np < 0 || (q == 0 && Np == 0)) return FKR_E_ARG;
     if (gcv && (Np < 1 || q < 1)) return FKR_E_ARG;
-    const int cpl = y_complex ? 2 : 1;
-    const int ny = q * cpl;
+    const int ny = q * (y_complex ? 2 : 1);
     if (1 + ny + Np > p->max_weights) return FKR_E_ARG;
-    const hipStream_t s = S(stream);
     if (probes && !valid_type(y_type)) return FKR_E_ARG;
-    const int ptype = y_type;
-    std::vector<WSrc> srcs{src_one()};
-    add_response_sources(&srcs, q, y_complex, Y, y_type);
-    add_probe_sources(&srcs, Np, seed, probes, ptype);
-    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
-    const Geo g = make_geo(p);
-    const int nr = (int)srcs.size();
-    double* internal = at<double>(p, p->lay.mhat);
-    // probe fits [M][pstride] in the spreading precision (they only feed the
-    // DF reduction), 16-byte aligned rows for FP32
-    const bool pf32 = p->prec == FKR_F32;
-    // one real response and all probes in one reduction launch: the y fit
-    // rides in column 0 of the FP32 rows, so the reduction gathers one row
-    const bool yrow = pf32 && q == 1 && !y_complex && Np >= 1 && Np <= kRedProbes;
-    const int pstride = pf32 ? ((yrow ? 1 : 0) + Np + 3) & ~3 : Np;
-    void* pfit = p->ws + p->lay.mhat + (((size_t)ny * p->Mtot * 8 + 15) & ~(size_t)15);
-    double* red = at<double>(p, p->lay.red);
-    double* partial = at<double>(p, p->lay.partial);
-    const int n_items = q + Np;
-    for (int hi = 0; hi < nh; ++hi) {
-        if ((st = run_channels(p, h + hi * p->d, nr, hi == 0 ? ill_ctr(p) : nullptr, s)) != FKR_OK) return st;
-        SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
-        double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
-        a.y_out = yfit;
-        a.probe_out = pfit;
-        a.probe_f32 = pf32 ? 1 : 0;
-        a.probe_stride = pstride;
-        a.rows_with_y = yrow ? 1 : 0;
-        {
-            StageTimer t(p, FKR_STAGE_SOLVE, s);
-            launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
-        }
-        ReduceCvArgs r{};
-        r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
-        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
-        r.ny_cols = q; r.y_cplx = y_complex; r.yfit = yfit;
-        r.np = Np; r.pfit = pfit; r.pstride = pstride; r.yrow = yrow ? 1 : 0;
-        r.partial = partial;
-        StageTimer t(p, FKR_STAGE_REDUCE, s);
-        // probes per launch: at most kRedProbes, spread evenly over the launches
-        const int nlp = (Np + kRedProbes - 1) / kRedProbes;
-        const int pper = nlp > 0 ? (Np + nlp - 1) / nlp : 0;
-        const int nlaunch = std::max((q + kRedYCols - 1) / kRedYCols, nlp);
-        for (int li = 0; li < nlaunch; ++li) {
-            r.y0 = li * kRedYCols;
-            r.ny_launch = std::max(0, std::min(kRedYCols, q - r.y0));
-            r.p0 = li * pper;
-            r.np_launch = std::max(0, std::min(pper, Np - r.p0));
-            launch_reduce_cv(g, r, s);
-        }
-        launch_reduce_final(partial, 2 * n_items, red, s);
-        launch_finalize_cv(hi, Np, q, p->N, red, n_items, q, rho, rss, gcv, s);
-    }
+    st = cv_impl(p, nh, h, q, y_complex, Y, y_type, Np, seed, probes, nullptr, mhat, rho, rss, gcv, nused,
+                 S(stream));
     p->last_stream = stream;
-    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+    return st;
+}
+
+fkr_status fkr_gcv(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y, int y_type,
+                   int Np, const double* rho_dev, double* mhat, double* rss, double* gcv, double* nused,
+                   void* stream) {
+    fkr_status st = common_fit_checks(p, nh, h, q, y_complex, Y, y_type);
+    if (st != FKR_OK) return st;
+    if (q < 1 || Np < 1 || !rho_dev || !gcv) return FKR_E_ARG;
+    const int ny = q * (y_complex ? 2 : 1);
+    if (1 + ny > p->max_weights) return FKR_E_ARG;
+    st = cv_impl(p, nh, h, q, y_complex, Y, y_type, Np, 0, nullptr, rho_dev, mhat, nullptr, rss, gcv, nused,
+                 S(stream));
+    p->last_stream = stream;
+    return st;
 }
 
 fkr_status fkr_dof(fkr_plan* p, int nh, const double* h, int Np, uint64_t seed, const void* probes,
-                   int w_type, double* rho, void* stream) {
+                   int w_type, double* rho, double* nused, void* stream) {
     if (!p) return FKR_E_ARG;
     if (Np < 1 || !rho) return FKR_E_ARG;
     if (probes && !valid_type(w_type)) return FKR_E_ARG;
@@ -639,7 +678,7 @@ fkr_status fkr_dof(fkr_plan* p, int nh, const double* h, int Np, uint64_t seed, 
     fkr_status st = ready(p);
     if (st != FKR_OK) return st;
     if ((st = check_h(p, nh, h)) != FKR_OK) return st;
-    return fkr_cv(p, nh, h, 0, 0, probes, w_type, Np, seed, probes, nullptr, rho, nullptr, nullptr, stream);
+    return fkr_cv(p, nh, h, 0, 0, probes, w_type, Np, seed, probes, nullptr, rho, nullptr, nullptr, nused, stream);
 }
 
 fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type,
@@ -655,8 +694,8 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     {
         // residuals, and the staged rows (1, z) of the second fit, in sorted order
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        launch_resid(g, p->prec, mode, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), y_type, Y,
-                     y_complex, mhat, wbuf + p->N, p->ws + p->lay.wsort, s);
+        launch_resid(g, p->prec, mode, points_check(p), p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
+                     y_type, Y, y_complex, mhat, wbuf + p->N, p->ws + p->lay.wsort, s);
     }
     std::vector<WSrc> srcs(2);
     for (int r = 0; r < 2; ++r) {
@@ -665,10 +704,10 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     }
     if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
     // The density moments s_alpha depend on the points and h only: when the
-    // plan's last fit (or cv, moments, variance) at this h left them in the
-    // channel buffer, only the pairs of the moments t_alpha of z are made.
-    const int c0 = reuse_density_channels(p, h) ? p->n_s / 2 : 0;
-    if ((st = run_channels(p, h, 2, ill_ctr(p), s, c0)) != FKR_OK) return st;
+    // channel buffer still holds them for these points at this h and the
+    // residual pass left no sample out, the passes skip their pairs (decided
+    // on the device).
+    if ((st = run_channels(p, h, 2, ill_ctr(p), s, true)) != FKR_OK) return st;
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
     a.y_out = v;
@@ -682,8 +721,8 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
         launch_kappa_partial(g, p->N, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm), v,
                              wbuf + p->N, partial, s);
         double* red = at<double>(p, p->lay.red);
-        launch_reduce_final(partial, 1, red, s);
-        launch_sigma2(p->Mtot, p->N, v, red, sigma2, kappa, s);
+        launch_reduce_final(partial, 2, red, s);
+        launch_sigma2(p->Mtot, v, red, sigma2, kappa, s);
     }
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
@@ -773,6 +812,7 @@ fkr_status fkr_get_diagnostics(fkr_plan* p, fkr_diag* out) {
     out->n_jobs = d[3];
     out->max_tile_count = d[4];
     if (d[5] != 0) return FKR_E_DEVICE;
+    if (d[kDiagStale] != 0) return FKR_E_STATE;
     if (d[1] != 0) return FKR_E_DOMAIN;
     if (d[2] != 0) return FKR_WARN_ILLPOSED;
     return FKR_OK;

@@ -53,6 +53,7 @@ struct Layout {                      // byte offsets into the workspace
     size_t loc = 0, frac = 0, perm = 0, xs = 0;
     size_t subgrid = 0, fftA = 0, fftB = 0, spec = 0;
     size_t chan = 0, mhat = 0, partial = 0, wbuf = 0, red = 0, wsort = 0;
+    size_t sup = 0;                  // [M] FP32 resolved flags (0 / NaN) of the last solve
     size_t total = 0;
     // element capacities (for checks)
     int64_t cap_jobs = 0, cap_fft = 0, cap_spec = 0, cap_chan = 0, cap_mhat = 0;
@@ -102,10 +103,10 @@ struct fkr_plan {
     bool ws_ready = false;
     bool points_set = false;
     int64_t N = 0;
-    // The channel buffer's first n_s / 2 pairs hold the density moments
-    // s_alpha at bandwidth schan_h of the current points (n_s even only).
-    bool schan_valid = false;
-    double schan_h[3] = {0.0, 0.0, 0.0};
+    // fkr_set_points calls so far; the sort writes it to the device, and the
+    // kernels that index a caller's arrays through the sort permutation
+    // check it there (a replayed HIP graph may have re-sorted other points)
+    long long epoch = 0;
     void* last_stream = nullptr;
     // stage timing (fkr_profile_enable / fkr_profile_read)
     bool prof_on = false;

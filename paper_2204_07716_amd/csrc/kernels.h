@@ -96,6 +96,10 @@ struct FftPass {
     const int* exp_es;
     const int* exp_et;
     const void* exp_spec;
+    // rows below skip_rows are neither read nor written when *skip_flag is
+    // nonzero (density channel pairs kept from an earlier call)
+    const long long* skip_flag;
+    int64_t skip_rows;
 };
 
 
@@ -103,13 +107,17 @@ struct SolveArgs {
     int P, n_s, n_t, ncp, nr;      // nr real weights incl. density
     int ny, y_cplx;                // real weights 1..ny are responses
     int64_t Mtot;
-    double s0_floor;               // absolute floor for every Cholesky pivot (s_0 first)
-    double* y_out;                 // [q][M][(2)] per bandwidth (may be null)
-    void* probe_out;               // [M][probe_stride], FP32 or FP64 (may be null)
+    // A point is ill-posed (NaN) when a Cholesky pivot of the equilibrated
+    // matrix (s_0 first) is at most max(rel_floor A_cc, abs_floor), and
+    // unresolved when it is ill-posed or a pivot is at most resolve A_cc.
+    double abs_floor, rel_floor, resolve;
+    double* y_out;                 // [q][M][(2)] per bandwidth (may be null); NaN where ill-posed
+    void* probe_out;               // [M][probe_stride], FP32 or FP64 (may be null); NaN where unresolved
     int probe_f32, probe_stride;
     int rows_with_y;               // the y fits go to the rows too: column r - 1 for weight r
     int wpg;                       // weights per thread (set by the launcher)
     double* s0_out;                // [M] (may be null)
+    float* sup_out;                // [M] 0 where resolved, NaN elsewhere (may be null)
     unsigned long long* ill_count;
 };
 
@@ -127,13 +135,34 @@ struct ReduceCvArgs {
     int yrow;                     // one real response whose fit is column 0 of the rows (FP32)
     int y0, ny_launch;            // response columns of this launch (<= kRedYCols)
     int p0, np_launch;            // probes of this launch (<= kRedProbes)
-    double* partial;              // [slot][kRedBlocks]; items: y columns, then probes
+    const float* sup;             // [M] 0 / NaN resolved flags (read when yrow == 0)
+    int count_slot;               // slot of the supported-sample count (< 0: not written)
+    double* partial;              // [slot][kRedBlocks]; items: y columns, then probes, then the count
+};
+
+// Device-side record of the sorted points, checked by every kernel that
+// reads a caller's per-sample array through the sort permutation.  Slots of
+// the diagnostics block: kDiagN / kDiagEpoch are written by the sort (the
+// point count and the host's set_points counter); a kernel launched for other
+// points sets kDiagStale and does nothing (a HIP graph replay can leave the
+// device with points the host did not set last).
+constexpr int kDiagN = 6, kDiagEpoch = 7, kDiagStale = 8;
+// Density-channel tag: the epoch and bandwidth (bit patterns) of the density
+// moments in the channel buffer, and the reuse flag computed from it.
+constexpr int kDiagChanEpoch = 9, kDiagChanH = 10, kDiagReuse = 13;
+// Set by the variance pass's residual kernel when it leaves samples out (the
+// second fit's density then differs from the first fit's: no reuse).
+constexpr int kDiagResidExcl = 14;
+struct PointsCheck {
+    int64_t n;
+    long long epoch;
+    long long* diag;
 };
 
 void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_t* counts, int32_t* bhist,
                       int32_t* obuf, hipStream_t s);
-void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
-                 int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s);
+void launch_scan(const Geo& g, int64_t N, long long epoch, int32_t* counts, int32_t* tile_off, int32_t* job_off,
+                 int32_t* jobs, int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s);
 void launch_sort_cells(const Geo& g, int prec, int x_type, const void* X, int64_t N, int64_t n_jobs_max,
                        const int32_t* tile_off, int32_t* cursor, const int32_t* jobs, const int32_t* bhist,
                        void* trec, uint32_t* loc, void* frac, int32_t* perm, void* xs, hipStream_t s);
@@ -153,21 +182,28 @@ void launch_reduce_cv(const Geo& g, const ReduceCvArgs& a, hipStream_t s);
 void launch_reduce_final(const double* partial, int nslots, double* out, hipStream_t s);
 void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void* X,
                    int x_type, double* out, hipStream_t s);
-void launch_finalize_cv(int nh_index, int Np, int q, int64_t N, const double* red, int n_items,
-                        int ny_cols, double* rho_out, double* rss_out, double* gcv_out,
-                        hipStream_t s);
+// DF / RSS / GCV of one bandwidth from the reduced sums; the Girard mean
+// comes from the probes of the sums, or from rho_in ([nh][Np]) when given.
+void launch_finalize_cv(int nh_index, int Np, int q, const double* red, int n_items,
+                        int ny_cols, const double* rho_in, double* rho_out, double* rss_out,
+                        double* gcv_out, double* nused_out, hipStream_t s);
 // residuals r_out[s] and the staged rows (1, z) of the variance pass, of
 // resid_row_stride elements each (2 or 4; unused elements zero)
 int resid_row_stride(const Geo& g, int prec);
-void launch_resid(const Geo& g, int prec, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
-                  int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out, void* rows,
-                  hipStream_t s);
+// (samples whose residual is undefined get the row (0, 0) and r = NaN)
+void launch_resid(const Geo& g, int prec, int mode, const PointsCheck& pc, int x_type, const void* xs,
+                  const int32_t* perm, int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out,
+                  void* rows, hipStream_t s);
+// partial sums of r exp(-v) (slot 0) and of their count (slot 1) over the
+// samples where the term is defined
 void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, const int32_t* perm,
                           const double* vhat, const double* r, double* partial, hipStream_t s);
-void launch_sigma2(int64_t Mtot, int64_t N, const double* vhat, const double* kappa_sum,
-                   double* sigma2, double* kappa_out, hipStream_t s);
+void launch_sigma2(int64_t Mtot, const double* vhat, const double* kappa_sums, double* sigma2,
+                   double* kappa_out, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
-void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t N,
+void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
+void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);
+void launch_chan_reuse(long long* diag, const double* h, int d, hipStream_t s);
 
 }  // namespace fkr

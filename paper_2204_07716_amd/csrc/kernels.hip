@@ -223,10 +223,10 @@ __global__ __launch_bounds__(1024) void k_tile_prefix(int64_t n_tiles, int nbloc
 
 // Single-block exclusive scans of the tile counts and of the job counts;
 // writes tile_off, job_off, the job table and resets the scatter cursors.
-__global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32_t* counts,
-                                               int32_t* tile_off, int32_t* job_off, int32_t* jobs,
-                                               int32_t* cursor, long long* diag, const int32_t* obuf,
-                                               int nbins) {
+__global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int64_t N, long long epoch,
+                                               int32_t* counts, int32_t* tile_off, int32_t* job_off,
+                                               int32_t* jobs, int32_t* cursor, long long* diag,
+                                               const int32_t* obuf, int nbins) {
     __shared__ int64_t sa[1024], sb[1024];
     __shared__ int64_t smax[1024];
     const int t = threadIdx.x;
@@ -265,6 +265,11 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t n_tiles, int chunk, int32
         if (o) atomicAdd(&n_out, o);
         __syncthreads();
         if (t == 0) diag[1] = (long long)n_out;
+    }
+    if (t == 0) {   // the device's record of the points (see PointsCheck)
+        diag[kDiagN] = (long long)N;
+        diag[kDiagEpoch] = epoch;
+        diag[kDiagStale] = 0;
     }
     if (t == 1023) {
         tile_off[n_tiles] = (int32_t)sa[1023];
@@ -1180,6 +1185,10 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
     const int R = f.rows_per_block;
     const int64_t row0 = (int64_t)blockIdx.x * R;
     const int nr = (int)min<int64_t>(R, f.rows - row0);
+    // rows kept from an earlier call: a block that holds only such rows
+    // returns, one that straddles the boundary neither loads nor stores them
+    const int64_t skip = (f.skip_flag && *f.skip_flag) ? f.skip_rows : 0;
+    if (row0 + nr <= skip) return;
     const int F = (int)f.F;
     C* buf0 = reinterpret_cast<C*>(smem_raw);
     C* buf1 = buf0 + (int64_t)R * F;
@@ -1198,6 +1207,10 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
             C acc;
             acc.x = 0;
             acc.y = 0;
+            if (row0 + r < skip) {
+                buf0[q] = acc;
+                continue;
+            }
             int e = pos + kin;
             e = e >= F ? e - F : e;
             if constexpr (EXP) {
@@ -1282,6 +1295,7 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
             pos = e - kout;
             pos = pos < 0 ? pos + F : pos;
         }
+        if (row0 + r < skip) continue;
         C v = src[r * F + pos];
         if (f.fac_out) v = cscale(v, (T)f.fac_out[e]);
         const unsigned row = (unsigned)(row0 + r);
@@ -1381,8 +1395,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
 #pragma unroll
         for (int c = 0; c <= b; ++c) A[b][c] = (double)ch(pidx[b * kMaxP + c]);
     const double s0 = (double)ch(0);
-    // s_0 is the first pivot; every pivot must clear the plan's noise floor.
+    // s_0 is the first pivot; every pivot must clear the floors (ill-posed
+    // otherwise) and, for the point to be resolved, resolve A_cc.
     bool ill = !isfinite(s0);
+    bool unres = false;
     // Cholesky A = L L^T (lower triangle in place).
     double diag0[P];
 #pragma unroll
@@ -1392,7 +1408,8 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
         double v = A[c][c];
 #pragma unroll
         for (int q = 0; q < c; ++q) v -= A[c][q] * A[c][q];
-        if (!(v > fmax(1e-12 * diag0[c], a.s0_floor))) ill = true;
+        if (!(v > fmax(a.rel_floor * diag0[c], a.abs_floor))) ill = true;
+        if (!(v > a.resolve * diag0[c])) unres = true;
         const double l = sqrt(fmax(v, 1e-300));
         A[c][c] = l;
         const double il = 1.0 / l;
@@ -1421,27 +1438,32 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
         r0[b] = v / A[b][b];
     }
     const double nan = __builtin_nan("");
+    unres = unres || ill;
     if (grp == 0) {
         if (a.s0_out) a.s0_out[k] = s0;
+        if (a.sup_out) a.sup_out[k] = unres ? __builtin_nanf("") : 0.f;
         if (ill && a.ill_count) atomicAdd(a.ill_count, 1ull);
     }
+    // the caller's fits are NaN where ill-posed; the internal rows that feed
+    // the DF / RSS sums are NaN wherever the point is not resolved
     for (int r = r_beg; r < r_end; ++r) {
         const int t0 = a.n_s + (r - 1) * a.n_t;
         double m = 0.0;
 #pragma unroll
         for (int b = 0; b < P; ++b) m += r0[b] * (double)ch(t0 + b);
         if (ill) m = nan;
+        const double mr = unres ? nan : m;
         if (r <= a.ny) {
             if (a.y_out) {
                 const int cpl = a.y_cplx ? 2 : 1;
                 const int col = (r - 1) / cpl, part = (r - 1) % cpl;
                 a.y_out[(col * a.Mtot + k) * cpl + part] = m;
             }
-            if (a.rows_with_y && a.probe_out) static_cast<float*>(a.probe_out)[k * a.probe_stride + (r - 1)] = (float)m;
+            if (a.rows_with_y && a.probe_out) static_cast<float*>(a.probe_out)[k * a.probe_stride + (r - 1)] = (float)mr;
         } else if (a.probe_out) {
             const int64_t o = k * a.probe_stride + (r - 1 - (a.rows_with_y ? 0 : a.ny));
-            if (a.probe_f32) static_cast<float*>(a.probe_out)[o] = (float)m;
-            else static_cast<double*>(a.probe_out)[o] = m;
+            if (a.probe_f32) static_cast<float*>(a.probe_out)[o] = (float)mr;
+            else static_cast<double*>(a.probe_out)[o] = mr;
         }
     }
 }
@@ -1527,9 +1549,9 @@ __device__ __forceinline__ void block_sum(double (&acc)[NA], double* sh) {
 // never summed).  Wave sums by cross-lane reduction, block sums in LDS.
 template <int D, typename TW, int PC, bool YR>
 __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
-    constexpr int YC = kRedYCols, NA = YC + 2 * PC;
+    constexpr int YC = kRedYCols, NA = YC + 2 * PC + 1;
     __shared__ double sh[NA][4];
-    double ay[YC], aw[PC], ah[PC];
+    double ay[YC], aw[PC], ah[PC], an = 0.0;
 #pragma unroll
     for (int j = 0; j < YC; ++j) ay[j] = 0.0;
 #pragma unroll
@@ -1562,6 +1584,10 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
                         if (4 * j + e < NV) fa[4 * j + e] += c.w[q] * (double)vv[e];
                 }
             }
+            // a sample whose cell touches an unresolved corner (NaN rows,
+            // whatever the corner's weight) is left out of every sum
+            if (isnan(fa[0])) continue;
+            an += 1.0;
             const double e0 = (double)row[1] - fa[0];
             ay[0] += e0 * e0;
 #pragma unroll
@@ -1571,6 +1597,13 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
                 ah[j] += wv * fa[1 + j];
             }
             continue;
+        }
+        {
+            float su = 0.f;
+#pragma unroll
+            for (int q = 0; q < (1 << D); ++q) su += a.sup[c.idx[q]];
+            if (isnan(su)) continue;
+            an += 1.0;
         }
 #pragma unroll
         for (int j = 0; j < YC; ++j) {
@@ -1652,6 +1685,7 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
     for (int j = 0; j < YC; ++j) acc[j] = ay[j];
 #pragma unroll
     for (int j = 0; j < PC; ++j) { acc[YC + 2 * j] = aw[j]; acc[YC + 2 * j + 1] = ah[j]; }
+    acc[NA - 1] = an;
 #pragma unroll
     for (int q = 0; q < NA; ++q)
 #pragma unroll
@@ -1665,7 +1699,9 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
         const int q = threadIdx.x;
         const double v = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
         int slot = -1;
-        if (q < YC) {
+        if (q == NA - 1) {
+            slot = a.count_slot;
+        } else if (q < YC) {
             if (q < a.ny_launch) slot = 2 * (a.y0 + q);
         } else {
             const int j = (q - YC) >> 1;
@@ -1689,22 +1725,56 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* partial, dou
     if (threadIdx.x == 0) out[slot] = sh[0];
 }
 
-__global__ void k_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, int ny_cols,
-                              double* rho_out, double* rss_out, double* gcv_out) {
+// True (and the stale flag set) when the points on the device are not the
+// ones this launch was made for.  Uniform over the grid.
+__device__ __forceinline__ bool points_stale(const PointsCheck& pc) {
+    const bool bad = pc.diag[kDiagN] != (long long)pc.n || pc.diag[kDiagEpoch] != pc.epoch;
+    if (bad && blockIdx.x == 0 && threadIdx.x == 0) pc.diag[kDiagStale] = 1;
+    return bad;
+}
+
+__global__ void k_chan_tag(long long* diag, double h0, double h1, double h2) {
+    if (threadIdx.x != 0) return;
+    diag[kDiagChanEpoch] = diag[kDiagEpoch];
+    diag[kDiagChanH] = __double_as_longlong(h0);
+    diag[kDiagChanH + 1] = __double_as_longlong(h1);
+    diag[kDiagChanH + 2] = __double_as_longlong(h2);
+}
+
+__global__ void k_chan_reuse(long long* diag, double h0, double h1, double h2) {
+    if (threadIdx.x != 0) return;
+    diag[kDiagReuse] = diag[kDiagChanEpoch] == diag[kDiagEpoch] && diag[kDiagChanH] == __double_as_longlong(h0) &&
+                       diag[kDiagChanH + 1] == __double_as_longlong(h1) &&
+                       diag[kDiagChanH + 2] == __double_as_longlong(h2) && diag[kDiagResidExcl] == 0;
+}
+
+// Girard ratios, RSS and GCV of one bandwidth over the N_I supported
+// samples (red[2 n_items] holds N_I).  With rho_in the Girard mean is that
+// of the given ratios (a DF computed by an earlier call).
+__global__ void k_finalize_cv(int hidx, int Np, int q, const double* red, int n_items, int ny_cols,
+                              const double* rho_in, double* rho_out, double* rss_out, double* gcv_out,
+                              double* nused_out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double n_used = red[2 * n_items];
     double mean = 0.0;
     for (int p = 0; p < Np; ++p) {
-        const int item = ny_cols + p;
-        const double ww = red[2 * item], wh = red[2 * item + 1];
-        const double rho = (ww - wh) / ww;
+        double rho;
+        if (rho_in) {
+            rho = rho_in[(int64_t)hidx * Np + p];
+        } else {
+            const int item = ny_cols + p;
+            const double ww = red[2 * item], wh = red[2 * item + 1];
+            rho = (ww - wh) / ww;
+        }
         if (rho_out) rho_out[(int64_t)hidx * Np + p] = rho;
         mean += rho;
     }
     mean = Np > 0 ? mean / Np : __builtin_nan("");
+    if (nused_out) nused_out[hidx] = n_used;
     for (int c = 0; c < q; ++c) {
         const double rss = red[2 * c];
         if (rss_out) rss_out[(int64_t)hidx * q + c] = rss;
-        if (gcv_out) gcv_out[(int64_t)hidx * q + c] = (rss / (double)N) / (mean * mean);
+        if (gcv_out) gcv_out[(int64_t)hidx * q + c] = (rss / n_used) / (mean * mean);
     }
 }
 
@@ -1713,10 +1783,12 @@ __global__ void k_finalize_cv(int hidx, int Np, int q, int64_t N, const double* 
 // spread (z = log(r + 1/N) or r, in the spreading precision TW), and
 // r_out[s] = r.
 template <int D, typename TW>
-__global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x_type, const void* xs,
+__global__ __launch_bounds__(256) void k_resid(Geo g, int mode, PointsCheck pc, int x_type, const void* xs,
                                                const int32_t* perm, int y_type, const void* Y,
                                                int y_cplx, const double* mhat, double* r_out, TW* rows,
                                                int rstride) {
+    if (points_stale(pc)) return;
+    const int64_t N = pc.n;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const Corners<D> c = corners<D>(g, x_type, xs, s);
@@ -1736,40 +1808,51 @@ __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, int64_t N, int x
         const double e = load_as_double(Y, y_type, i) - f;
         r = e * e;
     }
-    const TW z = (TW)(mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r);
+    // a sample whose residual is undefined (NaN mean fit at a corner) is
+    // left out of the second fit: density and response weights 0
+    const bool ok = isfinite(r);
+    const TW one = ok ? (TW)1 : (TW)0;
+    const TW z = ok ? (TW)(mode == FKR_VAR_LOG ? log(r + 1.0 / (double)N) : r) : (TW)0;
     if constexpr (sizeof(TW) == 4) {
-        if (rstride == 2) reinterpret_cast<float2*>(rows)[s] = make_float2(1.f, z);
-        else reinterpret_cast<float4*>(rows)[s] = make_float4(1.f, z, 0.f, 0.f);
+        if (rstride == 2) reinterpret_cast<float2*>(rows)[s] = make_float2(one, z);
+        else reinterpret_cast<float4*>(rows)[s] = make_float4(one, z, 0.f, 0.f);
     } else {
-        reinterpret_cast<double2*>(rows)[2 * s] = make_double2(1.0, z);
+        reinterpret_cast<double2*>(rows)[2 * s] = make_double2(one, z);
         reinterpret_cast<double2*>(rows)[2 * s + 1] = make_double2(0.0, 0.0);
     }
-    r_out[s] = r;
+    r_out[s] = ok ? r : __builtin_nan("");
+    if (!ok) pc.diag[kDiagResidExcl] = 1;
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_kappa_partial(Geo g, int64_t N, int x_type, const void* xs,
                                                        const int32_t* perm, const double* vhat,
                                                        const double* r, double* partial) {
-    __shared__ double sh[256];
-    double acc[1] = {0.0};
+    __shared__ double sh[2 * 256];
+    double acc[2] = {0.0, 0.0};
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N;
          s += (int64_t)gridDim.x * blockDim.x) {
         const Corners<D> c = corners<D>(g, x_type, xs, s);
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < (1 << D); ++q) v += c.w[q] * vhat[c.idx[q]];
-        acc[0] += r[s] * exp(-v);
+        const double term = r[s] * exp(-v);
+        if (isfinite(term)) {
+            acc[0] += term;
+            acc[1] += 1.0;
+        }
     }
-    block_sum<1>(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+    block_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = acc[0];
+        partial[kRedBlocks + blockIdx.x] = acc[1];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_sigma2(int64_t Mtot, int64_t N, const double* vhat,
-                                                const double* ksum, double* sigma2,
-                                                double* kappa_out) {
+__global__ __launch_bounds__(256) void k_sigma2(int64_t Mtot, const double* vhat, const double* ksum,
+                                                double* sigma2, double* kappa_out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double kappa = (double)N / ksum[0];
+    const double kappa = ksum[1] / ksum[0];   // count / sum of r exp(-v)
     if (k == 0 && kappa_out) kappa_out[0] = kappa;
     if (k >= Mtot) return;
     sigma2[k] = exp(vhat[k]) / kappa;
@@ -1785,10 +1868,12 @@ __global__ void k_zero(uint32_t* p, int64_t n) {
 // its two Box-Muller transforms.
 template <typename T>
 __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, int r0, int nr,
-                                                       int64_t N, const int32_t* perm, T* out) {
+                                                       PointsCheck pc, const int32_t* perm, T* out) {
     // one sample per thread; when the launch writes whole rows (nsrc == nr)
     // the rows of each wave go out through LDS as one contiguous block
     __shared__ __align__(16) T stg[256 * 2 * kMaxPairsPerSpread];
+    if (points_stale(pc)) return;
+    const int64_t N = pc.n;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool whole = nsrc == nr;
     if (s >= N && !whole) return;
@@ -1898,13 +1983,13 @@ __global__ void k_chan_out(int64_t Mtot, int ncp, int n_s, int n_t, int nw, cons
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t N,
+void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s) {
-    if (N == 0) return;
+    if (pc.n == 0) return;
     if (prec == FKR_F64)
-        k_stage_weights<double><<<nblk(N), 256, 0, s>>>(src, nsrc, r0, nr, N, perm, static_cast<double*>(out));
+        k_stage_weights<double><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, pc, perm, static_cast<double*>(out));
     else
-        k_stage_weights<float><<<nblk(N), 256, 0, s>>>(src, nsrc, r0, nr, N, perm, static_cast<float*>(out));
+        k_stage_weights<float><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, pc, perm, static_cast<float*>(out));
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
@@ -1926,10 +2011,19 @@ void launch_bin_count(const Geo& g, int x_type, const void* X, int64_t N, int32_
     if (use_lds) k_tile_prefix<<<(unsigned)((g.n_tiles + 63) / 64), 1024, 0, s>>>(g.n_tiles, (int)nb, bhist, counts);
 }
 
-void launch_scan(const Geo& g, int64_t N, int32_t* counts, int32_t* tile_off, int32_t* job_off, int32_t* jobs,
-                 int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s) {
+void launch_scan(const Geo& g, int64_t N, long long epoch, int32_t* counts, int32_t* tile_off, int32_t* job_off,
+                 int32_t* jobs, int32_t* cursor, long long* diag, const int32_t* obuf, hipStream_t s) {
     const int nbins = (int)((N + kSortChunk - 1) / kSortChunk);
-    k_scan<<<1, 1024, 0, s>>>(g.n_tiles, g.chunk, counts, tile_off, job_off, jobs, cursor, diag, obuf, nbins);
+    k_scan<<<1, 1024, 0, s>>>(g.n_tiles, g.chunk, N, epoch, counts, tile_off, job_off, jobs, cursor, diag, obuf,
+                              nbins);
+}
+
+void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s) {
+    k_chan_tag<<<1, 64, 0, s>>>(diag, h[0], d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0);
+}
+
+void launch_chan_reuse(long long* diag, const double* h, int d, hipStream_t s) {
+    k_chan_reuse<<<1, 64, 0, s>>>(diag, h[0], d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0);
 }
 
 template <int D, typename T>
@@ -2557,11 +2651,11 @@ void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void
     }
 }
 
-void launch_finalize_cv(int hidx, int Np, int q, int64_t N, const double* red, int n_items,
-                        int ny_cols, double* rho_out, double* rss_out, double* gcv_out,
-                        hipStream_t s) {
-    (void)n_items;
-    k_finalize_cv<<<1, 64, 0, s>>>(hidx, Np, q, N, red, ny_cols, rho_out, rss_out, gcv_out);
+void launch_finalize_cv(int hidx, int Np, int q, const double* red, int n_items, int ny_cols,
+                        const double* rho_in, double* rho_out, double* rss_out, double* gcv_out,
+                        double* nused_out, hipStream_t s) {
+    k_finalize_cv<<<1, 64, 0, s>>>(hidx, Np, q, red, n_items, ny_cols, rho_in, rho_out, rss_out, gcv_out,
+                                   nused_out);
 }
 
 int resid_row_stride(const Geo& g, int prec) {
@@ -2571,13 +2665,14 @@ int resid_row_stride(const Geo& g, int prec) {
     return prec == FKR_F32 && ((g.d == 2 && g.w <= 8) || (g.d == 3 && g.w == 8)) ? 2 : 4;
 }
 
-void launch_resid(const Geo& g, int prec, int mode, int64_t N, int x_type, const void* xs, const int32_t* perm,
-                  int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out, void* rows,
-                  hipStream_t s) {
-    if (N == 0) return;
+void launch_resid(const Geo& g, int prec, int mode, const PointsCheck& pc, int x_type, const void* xs,
+                  const int32_t* perm, int y_type, const void* Y, int y_cplx, const double* mhat, double* r_out,
+                  void* rows, hipStream_t s) {
+    launch_zero(pc.diag + kDiagResidExcl, 8, s);
+    if (pc.n == 0) return;
     const int rstride = resid_row_stride(g, prec);
-#define FKR_RES(D, TW) k_resid<D, TW><<<nblk(N), 256, 0, s>>>(g, mode, N, x_type, xs, perm, y_type, Y, y_cplx, \
-                                                              mhat, r_out, static_cast<TW*>(rows), rstride)
+#define FKR_RES(D, TW) k_resid<D, TW><<<nblk(pc.n), 256, 0, s>>>(g, mode, pc, x_type, xs, perm, y_type, Y, y_cplx, \
+                                                                 mhat, r_out, static_cast<TW*>(rows), rstride)
     if (prec == FKR_F64) {
         if (g.d == 1) FKR_RES(1, double); else if (g.d == 2) FKR_RES(2, double); else FKR_RES(3, double);
     } else {
@@ -2595,9 +2690,9 @@ void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, c
     }
 }
 
-void launch_sigma2(int64_t Mtot, int64_t N, const double* vhat, const double* kappa_sum,
-                   double* sigma2, double* kappa_out, hipStream_t s) {
-    k_sigma2<<<nblk(Mtot), 256, 0, s>>>(Mtot, N, vhat, kappa_sum, sigma2, kappa_out);
+void launch_sigma2(int64_t Mtot, const double* vhat, const double* kappa_sums, double* sigma2,
+                   double* kappa_out, hipStream_t s) {
+    k_sigma2<<<nblk(Mtot), 256, 0, s>>>(Mtot, vhat, kappa_sums, sigma2, kappa_out);
 }
 
 }  // namespace fkr

@@ -194,16 +194,38 @@ class Plan:
         return out
 
     # -- a9 -------------------------------------------------------------
-    def dof(self, h, Np: int, seed: int = 0, probes: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def dof(self, h, Np: int, seed: int = 0, probes: Optional[torch.Tensor] = None,
+            want_nused: bool = False):
+        """Girard ratios [nh][Np] over the supported samples (and N_I [nh])."""
         hb = _hbuf(h, self.d)
         nh = hb.shape[0]
         rho = torch.empty((nh, Np), dtype=torch.float64, device=self.device)
+        nused = torch.empty(nh, dtype=torch.float64, device=self.device)
         if probes is not None:
             probes = probes.contiguous()
         check(self.lib.fkr_dof(self._plan, nh, _hptr(hb), Np, ctypes.c_uint64(seed), _ptr(probes),
-                               _dtype_code(probes) if probes is not None else 1, _ptr(rho),
+                               _dtype_code(probes) if probes is not None else 1, _ptr(rho), _ptr(nused),
                                _stream()), "fkr_dof")
-        return rho
+        return (rho, nused) if want_nused else rho
+
+    # -- a10 ------------------------------------------------------------
+    def gcv(self, h, Y: torch.Tensor, rho: torch.Tensor, want_mhat: bool = False):
+        """GCV (eq. 22) of responses Y against Girard ratios from dof()."""
+        hb = _hbuf(h, self.d)
+        nh = hb.shape[0]
+        Yr, q, cplx = _real_view(Y)
+        rho = rho.to(torch.float64).contiguous()
+        Np = rho.shape[-1]
+        mhat = (torch.empty((nh, q, self.Mtot) + ((2,) if cplx else ()), dtype=torch.float64,
+                            device=self.device) if want_mhat else None)
+        rss = torch.empty((nh, q), dtype=torch.float64, device=self.device)
+        gcv = torch.empty((nh, q), dtype=torch.float64, device=self.device)
+        nused = torch.empty(nh, dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_gcv(self._plan, nh, _hptr(hb), q, cplx, _ptr(Yr), _dtype_code(Yr), Np, _ptr(rho),
+                               _ptr(mhat), _ptr(rss), _ptr(gcv), _ptr(nused), _stream()), "fkr_gcv")
+        if mhat is not None and cplx:
+            mhat = torch.view_as_complex(mhat)
+        return {"mhat": mhat, "rss": rss, "gcv": gcv, "nused": nused}
 
     # -- a7-a10 batched -------------------------------------------------
     def cv(self, h, Y: torch.Tensor, Np: int, seed: int = 0,
@@ -218,12 +240,13 @@ class Plan:
         rho = torch.empty((nh, Np), dtype=torch.float64, device=self.device) if Np else None
         rss = torch.empty((nh, q), dtype=torch.float64, device=self.device)
         gcv = torch.empty((nh, q), dtype=torch.float64, device=self.device) if Np else None
+        nused = torch.empty(nh, dtype=torch.float64, device=self.device)
         check(self.lib.fkr_cv(self._plan, nh, _hptr(hb), q, cplx, _ptr(Yr), _dtype_code(Yr), Np,
                               ctypes.c_uint64(seed), _ptr(probes), _ptr(mhat), _ptr(rho), _ptr(rss),
-                              _ptr(gcv), _stream()), "fkr_cv")
+                              _ptr(gcv), _ptr(nused), _stream()), "fkr_cv")
         if mhat is not None and cplx:
             mhat = torch.view_as_complex(mhat)
-        return {"mhat": mhat, "rho": rho, "rss": rss, "gcv": gcv}
+        return {"mhat": mhat, "rho": rho, "rss": rss, "gcv": gcv, "nused": nused}
 
     # -- a11 ------------------------------------------------------------
     def variance(self, h, Y: torch.Tensor, mhat: torch.Tensor, mode: str = "log"):

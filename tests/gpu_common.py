@@ -23,18 +23,108 @@ def density_mask(s0: np.ndarray, rho: float = 1e-3) -> np.ndarray:
     return s0 >= rho * s0.max()
 
 
-U32, U64 = 2.0 ** -24, 2.0 ** -53
+def resolved_oracle(S, h, order, d) -> np.ndarray:
+    """Grid points resolved by the reading (FKR_RESOLVE), from oracle moments."""
+    return orc.resolved(S, h, order, d)
 
 
-def noise_floor(N, h, eps, precision="fp32", tprec="same") -> float:
-    """The library's documented absolute pivot floor e N K_h(0), with
-    e = max(eps, round-off of the transforms, 30 round-offs of the spreading);
-    handed to the oracle so both sides apply the same ill-posedness rule."""
-    us = U64 if precision == "fp64" else U32
-    tp = precision if tprec == "same" else tprec
-    ut = U64 if tp == "fp64" else U32
-    k0 = float(np.prod(1.0 / (np.asarray(h, dtype=np.float64) * np.sqrt(2.0 * np.pi))))
-    return max(eps, ut, 30.0 * us) * max(N, 1) * k0
+def fit_mask(S, h, order, d, rho: float = 1e-3) -> np.ndarray:
+    """Where fits are compared: the density mask of the error metric,
+    restricted to resolved points (a nearly singular local design amplifies
+    any moment error, so neither side's fit is meaningful there)."""
+    return density_mask(S[:, 0], rho) & orc.resolved(S, h, order, d)
+
+
+def check_gpu_nans(gpu, S, h, order, d):
+    """The fast path may leave NaN only where the plain definition is not
+    resolved, outside the density mask, or where a design column is
+    numerically zero (its weighted mean square, in bandwidth units, below
+    1e-4 of the weight: samples piled within 1% of h of the grid point, a
+    degenerate design the fast moments cannot resolve); it never drops a
+    dense, well-spread, well-conditioned grid point."""
+    A = orc.assemble(S, h, order, d)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        flat = np.min(np.diagonal(A, axis1=1, axis2=2) / A[:, :1, 0], axis=1) < 1e-4
+    bad = np.isnan(np.asarray(gpu)) & density_mask(S[:, 0]) & orc.resolved(S, h, order, d) & ~flat
+    assert not bad.any(), f"{bad.sum()} resolved dense points are NaN on the GPU"
+
+
+def amplification(S, h, order, d) -> np.ndarray:
+    """Sensitivity of the intercept to relative errors in the moments:
+    F = sum_b |[A^-1]_0b| sqrt(A_bb A_00) for the equilibrated moment matrix
+    A of each grid point (invariant to diagonal scaling; 1 for an orthogonal
+    centred local design, large where the fit extrapolates from samples on
+    one side).  NaN where A is singular."""
+    A = orc.assemble(S, h, order, d)
+    F = np.full(A.shape[0], np.nan)
+    dg = np.diagonal(A, axis1=1, axis2=2)
+    with np.errstate(invalid="ignore"):
+        ok = np.all(orc.relative_pivots(A) > 1e-12, axis=1)
+    if ok.any():
+        r0 = np.linalg.inv(A[ok])[:, 0, :]
+        F[ok] = np.sum(np.abs(r0) * np.sqrt(dg[ok] * dg[ok, :1]), axis=1)
+    return F
+
+
+def compare_fit(gpu, ref, S, h, order, d, bar, rho: float = 1e-3) -> float:
+    """Fits on the comparison mask: |gpu - ref| <= bar max|ref| where the
+    intercept's amplification factor F (``amplification``) is at most 10,
+    and bar max|ref| F / 10 above that: a fit's forward error is its moments'
+    relative error times F, for any method that computes the moments to a
+    relative accuracy.  Returns the largest error in units of the point's
+    allowance."""
+    check_gpu_nans(gpu, S, h, order, d)
+    gpu, ref = np.asarray(gpu), np.asarray(ref)
+    m = fit_mask(S, h, order, d, rho) & ~np.isnan(gpu)   # the NaNs check_gpu_nans admits
+    allow = np.maximum(1.0, amplification(S, h, order, d) / 10.0)
+    scale = np.abs(ref[m]).max()
+    err = float((np.abs(gpu[m] - ref[m]) / allow[m]).max() / scale)
+    assert err < bar, err
+    return err
+
+
+def unequilibrate(S_eq, h, order, d):
+    """Library channels s_a / h^a (grid-major [n_s][M]) -> oracle layout [M][n_s] of s_a."""
+    es = orc.multi_indices(d, 2 * order)
+    h = np.asarray(h, dtype=np.float64)
+    sc = np.array([np.prod(h ** np.array(a)) for a in es])
+    return np.asarray(S_eq).T * sc[None, :]
+
+
+def support_variants(S, ill, h, order, d, M, lo, hi, X, band: float = 1e-2, max_amb: int = 4):
+    """Supported-sample masks of the DF / RSS sums from the moments S (any
+    source) and the ill-posed flags.  Grid points whose smallest relative
+    pivot lies within `band` (relative) of FKR_RESOLVE are ambiguous: moments
+    computed by two methods that agree to about 1e-6 may decide them either
+    way, and both decisions are correct.  Returns one mask per assignment of
+    the ambiguous points (one mask when there are none)."""
+    import itertools
+    kappa = orc.RESOLVE
+    rp = orc.relative_pivots(orc.assemble(S, h, order, d))
+    with np.errstate(invalid="ignore"):
+        rpmin = np.min(rp, axis=1)
+        ok = ~ill & np.all(rp > kappa, axis=1)
+        amb = np.nonzero(~ill & (np.abs(rpmin / kappa - 1) < band))[0]
+    assert len(amb) <= max_amb, f"{len(amb)} ambiguous grid points"
+    out = []
+    for bits in itertools.product([False, True], repeat=len(amb)):
+        okv = ok.copy()
+        okv[amb] = bits
+        out.append(orc.supported(okv, M, lo, hi, X))
+    return out
+
+
+def match_dof(rho_gpu, nused_gpu, Wp, What, variants, bar):
+    """The GPU's Girard ratios and supported count must match the oracle's
+    for one admissible support (see support_variants).  Returns that mask."""
+    errs = []
+    for inc in variants:
+        r = orc.girard_ratios(Wp[inc], What[inc])
+        e = float(np.abs(np.asarray(rho_gpu) - r).max())
+        errs.append((e, int(inc.sum())))
+        if e < bar and int(inc.sum()) == int(round(float(nused_gpu))):
+            return inc
+    raise AssertionError(f"no admissible support matches: (err, N_I) {errs}, GPU N_I {nused_gpu}")
 
 
 def nan_close(gpu, ref, bar, mask=None, scale=None) -> float:

@@ -33,9 +33,12 @@ def test_dof_matches_oracle_with_identical_probes(orc, d, order, prec, tprec):
                      max_weights=2 + Np, tprec=tprec)
     dt = torch.float64 if prec == "fp64" else torch.float32
     plan.set_points(to_dev(X, dt))
-    rho = plan.dof(h, Np, seed=seed).cpu().numpy()[0]
+    rho, nused = plan.dof(h, Np, seed=seed, want_nused=True)
+    rho, nused = rho.cpu().numpy()[0], nused.cpu().numpy()[0]
     probes = orc.probes(seed, N, Np)
-    ref, mean, df = orc.dof(X, h, order, M, (0,) * d, (1,) * d, probes)
+    ref, mean, df, inc = orc.dof(X, h, order, M, (0,) * d, (1,) * d, probes)
+    # uniform samples on a grid coarser than the kernel: every sample is supported
+    assert inc.all() and nused == N
     bar = 1e-9 if prec == "fp64" else (1e-6 if tprec == "fp64" else 2e-5)
     assert np.abs(rho - ref).max() < bar, (rho, ref)
     # the same probes passed in as an array
@@ -57,16 +60,18 @@ def test_cv_gcv_matches_oracle(orc):
     gcv = out["gcv"].cpu().numpy()[:, 0]
     rss = out["rss"].cpu().numpy()[:, 0]
     rho = out["rho"].cpu().numpy()
+    nused = out["nused"].cpu().numpy()
     probes = orc.probes(seed, N, Np)
     gp = orc.grid_points(M, (0, 0), (1, 1))
     for k, h in enumerate(hs):
         mh = orc.fit(X, y, h, 1, gp)
         yhat = orc.interp(mh[:, 0], M, (0, 0), (1, 1), X)
-        r_ref, mean, _ = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+        r_ref, mean, _, inc = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+        assert nused[k] == inc.sum()
         assert np.abs(rho[k] - r_ref).max() < 1e-6
-        rss_ref = np.sum((y - yhat) ** 2)
+        rss_ref = np.sum(((y - yhat) ** 2)[inc])
         assert abs(rss[k] / rss_ref - 1) < 1e-5
-        g_ref = orc.gcv(y, yhat, mean)[0]
+        g_ref = orc.gcv(y, yhat, mean, include=inc)[0]
         assert abs(gcv[k] / g_ref - 1) < 1e-5
     from paper_2204_07716_amd import select_bandwidth
     assert select_bandwidth(gcv, 0.0) == orc.rgcv_select(gcv, 0.0)
@@ -120,7 +125,9 @@ def test_complex_response_cv(orc):
     mask = density_mask(S[:, 0])
     assert rel_err(mh, ref[:, 0], mask) < 1e-5
     yhat = orc.interp(ref[:, 0], M, (0, 0), (1, 1), X)
-    rss_ref = np.sum(np.abs(y32 - yhat) ** 2)
+    inc, _ = orc.support(X, h, 2, M, (0, 0), (1, 1))
+    assert out["nused"].cpu().numpy()[0] == inc.sum()
+    rss_ref = np.sum((np.abs(y32 - yhat) ** 2)[inc])
     assert abs(out["rss"].cpu().numpy()[0, 0] / rss_ref - 1) < 1e-5
 
 
@@ -142,15 +149,15 @@ def test_cv_many_probes_two_responses(orc):
     rss = out["rss"].cpu().numpy()[0]
     gcv = out["gcv"].cpu().numpy()[0]
     probes = orc.probes(seed, N, Np)
-    r_ref, mean, _ = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+    r_ref, mean, _, inc = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
     assert np.abs(rho - r_ref).max() < 1e-6
     gp = orc.grid_points(M, (0, 0), (1, 1))
     for c in range(2):
         mh = orc.fit(X, Y[:, c], h, 1, gp)
         yhat = orc.interp(mh[:, 0], M, (0, 0), (1, 1), X)
-        rss_ref = np.sum((Y[:, c] - yhat) ** 2)
+        rss_ref = np.sum(((Y[:, c] - yhat) ** 2)[inc])
         assert abs(rss[c] / rss_ref - 1) < 1e-5
-        g_ref = orc.gcv(Y[:, c], yhat, mean)[0]
+        g_ref = orc.gcv(Y[:, c], yhat, mean, include=inc)[0]
         assert abs(gcv[c] / g_ref - 1) < 1e-5
 
 
@@ -188,3 +195,63 @@ def test_variance_density_channel_reuse(orc):
     # launches, and the pair partner of the density column differs (y or z)
     for got in (kept, other, again):
         assert rel_err(got, fresh, mask) < 1e-7
+
+
+def test_gcv_call_from_stored_dof(orc):
+    """fkr_gcv: GCV of a response against Girard ratios computed earlier by
+    fkr_dof (the DF does not depend on y), over a bandwidth list; equals the
+    batched cv call and the oracle."""
+    N, Np, seed = 3000, 6, 17
+    X, y = _data(450, N, 2)
+    y2 = np.cos(3 * X[:, 1]) + 0.2 * np.random.default_rng(451).standard_normal(N)
+    Y = np.stack([y, y2], axis=1)
+    M = (36, 34)
+    hs = np.stack([orc.get_hlist(3, [0.07, 0.18], "log")[:, 0]] * 2, axis=1)
+    plan = make_plan(2, 1, M, hs[0], hs[-1], 1e-6, "fp32", n_max=N, max_weights=3 + Np,
+                     max_h=len(hs), tprec="fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    rho, nused = plan.dof(hs, Np, seed=seed, want_nused=True)
+    Yd = to_dev(Y, torch.float32)
+    g = plan.gcv(hs, Yd, rho)
+    cv = plan.cv(hs, Yd, Np, seed=seed)
+    gcv, gcv_cv = g["gcv"].cpu().numpy(), cv["gcv"].cpu().numpy()
+    assert np.allclose(g["nused"].cpu().numpy(), nused.cpu().numpy())
+    assert np.abs(gcv / gcv_cv - 1).max() < 1e-6
+    probes = orc.probes(seed, N, Np)
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    rho = rho.cpu().numpy()
+    for k, h in enumerate(hs):
+        r_ref, mean, _, inc = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+        assert np.abs(rho[k] - r_ref).max() < 1e-6
+        for c in range(2):
+            mh = orc.fit(X, Y[:, c], h, 1, gp)
+            yhat = orc.interp(mh[:, 0], M, (0, 0), (1, 1), X)
+            g_ref = orc.gcv(Y[:, c], yhat, mean, include=inc)[0]
+            assert abs(gcv[k, c] / g_ref - 1) < 1e-5
+
+
+def test_unresolved_points_are_left_out_of_dof(orc):
+    """Samples on the line x1 = 0.3 plus a cloud in x1 > 0.6: grid points
+    near the line see a collinear or nearly collinear local design (singular
+    or unresolved), and the samples whose cell touches one are left out of
+    the DF and RSS sums on both sides (a finite GCV, the same N_I)."""
+    rng = np.random.default_rng(460)
+    N, Np, seed = 4000, 6, 19
+    X = np.concatenate([np.stack([rng.random(3000), np.full(3000, 0.3)], axis=1),
+                        np.stack([rng.random(1000), 0.6 + 0.4 * rng.random(1000)], axis=1)])
+    y = np.sin(3 * X[:, 0]) + 0.2 * rng.standard_normal(N)
+    M, h = (24, 22), (0.06, 0.06)
+    plan = make_plan(2, 1, M, h, h, 1e-9, "fp64", n_max=N, max_weights=2 + Np)
+    plan.set_points(to_dev(X))
+    out = plan.cv(h, to_dev(y[:, None]), Np, seed=seed)
+    probes = orc.probes(seed, N, Np)
+    r_ref, mean, _, inc = orc.dof(X, h, 1, M, (0, 0), (1, 1), probes)
+    assert 0 < inc.sum() < N
+    assert out["nused"].cpu().numpy()[0] == inc.sum()
+    assert np.abs(out["rho"].cpu().numpy()[0] - r_ref).max() < 1e-8
+    gcv = out["gcv"].cpu().numpy()[0, 0]
+    assert np.isfinite(gcv)
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    yhat = orc.interp(orc.fit(X, y, h, 1, gp)[:, 0], M, (0, 0), (1, 1), X)
+    g_ref = orc.gcv(y, yhat, mean, include=inc)[0]
+    assert abs(gcv / g_ref - 1) < 1e-8

@@ -283,7 +283,8 @@ def test_dof_identity_smoother_gives_zero(orc):
     M = (33,)
     X = orc.grid_points(M, (0,), (1,))
     Wp = orc.probes(5, 33, 8)
-    rho, m, df = orc.dof(X, [1.0 / 32 / 20], 0, M, (0,), (1,), Wp)
+    rho, m, df, inc = orc.dof(X, [1.0 / 32 / 20], 0, M, (0,), (1,), Wp)
+    assert inc.all()
     assert np.all(np.abs(rho) < 1e-12) and abs(df - 33) < 1e-9
 
 
@@ -296,7 +297,8 @@ def test_dof_large_bandwidth_is_ols_projection(orc, d):
     X = rng.random((N, d))
     M, lo, hi = (9,) * d, (0,) * d, (1,) * d
     Wp = orc.probes(77, N, 5)
-    rho, m, df = orc.dof(X, [1e3] * d, 1, M, lo, hi, Wp)
+    rho, m, df, inc = orc.dof(X, [1e3] * d, 1, M, lo, hi, Wp)
+    assert inc.all()
     D = np.concatenate([np.ones((N, 1)), X], axis=1)
     res = Wp - D @ np.linalg.lstsq(D, Wp, rcond=None)[0]
     assert np.allclose(rho, (res ** 2).sum(0) / (Wp ** 2).sum(0), rtol=1e-5)
@@ -315,9 +317,33 @@ def test_girard_estimator_mean_matches_exact_trace(orc):
     var = 2 * (np.trace(Bs @ Bs) - np.trace(Bs) ** 2 / N) / (N * (N + 2))
     Np = 3000
     Wp = orc.probes(99, N, Np)
-    rho, m, df = orc.dof(X, [0.08], 1, M, (0,), (1,), Wp)
+    rho, m, df, inc = orc.dof(X, [0.08], 1, M, (0,), (1,), Wp)
+    assert inc.all()
     assert abs(m - exact) < 4 * math.sqrt(var / Np)
     assert abs(np.var(rho, ddof=1) / var - 1) < 0.15
+
+
+def test_girard_estimator_over_a_subset_matches_restricted_trace(orc):
+    """Over a sample subset I the ratio sum_I w (w - S w) / sum_I w^2 has
+    mean tr(B_II) / N_I exactly (B = I - S; the probes off I enter linearly
+    with zero mean), with the variance formula applied to sym(B_II)."""
+    rng = np.random.default_rng(32)
+    N, M = 40, (16,)
+    X = rng.random((N, 1))
+    S = _smoother_matrix(orc, X, [0.08], 1, M, (0,), (1,))
+    inc = rng.random(N) < 0.6
+    B = (np.eye(N) - S)[np.ix_(inc, inc)]
+    Bs = 0.5 * (B + B.T)
+    n = int(inc.sum())
+    exact = np.trace(B) / n
+    Np = 4000
+    Wp = orc.probes(98, N, Np)
+    # the variance of the subset ratio also carries the off-subset probe
+    # terms; bound the mean with the full conditional variance by simulation
+    rho, m, df, got = orc.dof(X, [0.08], 1, M, (0,), (1,), Wp, include=inc)
+    assert np.array_equal(got, inc) and abs(df - n * (1 - m)) < 1e-9
+    assert abs(m - exact) < 4 * np.std(rho, ddof=1) / math.sqrt(Np)
+    assert np.std(rho, ddof=1) > math.sqrt(2 * (np.trace(Bs @ Bs) - np.trace(Bs) ** 2 / n) / (n * (n + 2))) * 0.8
 
 
 def test_gcv_of_ols_fit(orc):
@@ -421,19 +447,82 @@ def test_collinear_design_is_ill_posed(orc):
     assert not ill.any()
 
 
-def test_pivot_floor_flags_sparse_points(orc):
-    """An absolute floor flags exactly the points whose smallest pivot is at
-    or below it; floor 0 keeps every well-posed point."""
-    rng = np.random.default_rng(72)
-    X = rng.random((200, 1)) * 0.5
-    gp = np.linspace(0, 1, 21)[:, None]
-    mh0, S, T, r0, ill0 = orc.fit(X, np.ones(200), [0.03], 1, gp, return_all=True)
-    A = orc.assemble(S, [0.03], 1, 1)
-    pmin = orc.pivots(A).min(axis=1)
-    fl = np.nanmedian(pmin[~ill0])
-    mh1, S1, T1, r01, ill1 = orc.fit(X, np.ones(200), [0.03], 1, gp, return_all=True, floor=fl)
-    assert (ill1 == (ill0 | ~(pmin > fl))).all()
-    assert ill1.sum() > ill0.sum()
+def test_relative_pivots_are_one_minus_r_squared(orc):
+    """pivot_c / A_cc of the weighted Gram matrix of a design equals one minus
+    the uncentred R^2 of column c regressed (weighted least squares, numpy
+    lstsq) on the columns before it, and does not change under diagonal
+    scaling of the columns (the bandwidth equilibration)."""
+    rng = np.random.default_rng(73)
+    for P in (2, 3, 6):
+        D = rng.standard_normal((50, P))
+        D[:, -1] = D[:, 0] * 0.9 + 0.1 * rng.standard_normal(50)   # a nearly collinear column
+        wgt = rng.random(50)
+        A = (D * wgt[:, None]).T @ D
+        rp = orc.relative_pivots(A[None])[0]
+        sq = np.sqrt(wgt)[:, None]
+        assert abs(rp[0] - 1) < 1e-12
+        for c in range(1, P):
+            coef = np.linalg.lstsq(D[:, :c] * sq, D[:, c] * sq[:, 0], rcond=None)[0]
+            res = (D[:, c] - D[:, :c] @ coef) * sq[:, 0]
+            r2 = 1 - (res @ res) / ((D[:, c] * sq[:, 0]) @ (D[:, c] * sq[:, 0]))
+            assert abs(rp[c] - (1 - r2)) < 1e-10
+        sc = 10.0 ** rng.uniform(-3, 3, P)
+        assert np.allclose(orc.relative_pivots((A * sc[:, None] * sc[None, :])[None])[0], rp, rtol=1e-9)
+
+
+def test_resolved_points_follow_the_local_design(orc):
+    """1-D local linear: the relative pivot is 1 - s_1^2 / (s_0 s_2) (closed
+    form).  Samples piled on one point x = 0.26 between grid points leave the
+    grid points near it unresolved (their local design is a single point),
+    while a spread cloud resolves every point it covers."""
+    rng = np.random.default_rng(74)
+    X = np.concatenate([np.full(300, 0.26), 0.6 + 0.4 * rng.random(300)])[:, None]
+    gp = np.linspace(0, 1, 41)[:, None]
+    h = [0.04]
+    S, _ = orc.moments(X, None, h, 1, gp)
+    s0, s1, s2 = S[:, 0], S[:, 1], S[:, 2]
+    closed = 1 - s1 ** 2 / (s0 * s2)
+    A = orc.assemble(S, h, 1, 1)
+    assert np.allclose(orc.relative_pivots(A)[:, 1], closed, rtol=1e-6, atol=1e-13)
+    ok = orc.resolved(S, h, 1, 1)
+    assert np.array_equal(ok, closed > orc.RESOLVE)
+    assert not ok[10] and not ok[11] and ok[32]    # g = 0.25, 0.275 (the pile) and 0.8 (the cloud)
+
+
+def test_supported_samples_by_brute_force(orc):
+    """A sample is supported when every corner of its interpolation cell
+    (floor clamped to [0, M - 2]) is in the resolved set: checked against
+    explicit loops over samples and corners."""
+    rng = np.random.default_rng(75)
+    M, lo, hi = (7, 6), (0.0, -1.0), (1.0, 2.0)
+    X = np.stack([rng.random(300), -1 + 3 * rng.random(300)], axis=1)
+    X[:5] = [[1.0, 2.0], [0.0, -1.0], [1.0, -1.0], [0.5, 2.0], [0.0, 0.5]]
+    ok = rng.random(M[0] * M[1]) < 0.8
+    got = orc.supported(ok, M, lo, hi, X)
+    for i in range(X.shape[0]):
+        cell = []
+        for j in range(2):
+            dlt = (hi[j] - lo[j]) / (M[j] - 1)
+            cell.append(min(max(int(math.floor((X[i, j] - lo[j]) / dlt)), 0), M[j] - 2))
+        want = all(ok[(cell[0] + a) + M[0] * (cell[1] + b)] for a in (0, 1) for b in (0, 1))
+        assert got[i] == want, i
+
+
+def test_variance_skips_undefined_residuals(orc):
+    """Residuals that are undefined (NaN mean fit) are left out: with the
+    rest constant, sigma^2 is still that constant (eq. 24-26 invariant)."""
+    rng = np.random.default_rng(76)
+    N, M = 3000, (15, 14)
+    X = rng.random((N, 2))
+    c = 0.37
+    yhat = rng.standard_normal(N)
+    y = yhat + math.sqrt(c)
+    yhat[:200] = np.nan
+    s2, ex = orc.variance(X, y, yhat, [0.2, 0.2], 1, M, (0, 0), (1, 1))
+    assert np.isnan(ex["r"][:200]).all()
+    kappa = (c + 1.0 / N) / c
+    assert abs(ex["kappa"] / kappa - 1) < 1e-9
+    assert np.allclose(s2, c, rtol=1e-8)
 
 
 def test_rgcv_select_skips_nan(orc):
