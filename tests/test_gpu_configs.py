@@ -405,3 +405,45 @@ def test_anisotropic_band_and_grid(orc):
     mask = density_mask(S[:, 0])
     for c in range(3):
         assert rel_err(mh[c], ref[:, c], mask) < 1e-5
+
+
+def test_eager_call_after_replaying_other_points_is_reported(orc):
+    """A graph that captured set_points on other points, replayed after an
+    eager set_points, leaves the device sorted differently from what the host
+    last set: the next eager call touches no caller array through the stale
+    permutation and is reported as FKR_E_STATE; an eager set_points makes the
+    plan usable again."""
+    rng = np.random.default_rng(80)
+    M, h = (30, 28), (0.1, 0.1)
+    Na, Nb = 8000, 3000
+    Xa, Xb = rng.random((Na, 2)), rng.random((Nb, 2))
+    ya, yb = rng.standard_normal(Na), np.cos(3 * Xb[:, 0]) + 0.1 * rng.standard_normal(Nb)
+    plan = make_plan(2, 1, M, h, h, 1e-6, "fp32", n_max=Na, max_weights=2, tprec="fp64")
+    Xad, Yad = to_dev(Xa, torch.float32), to_dev(ya[:, None], torch.float32)
+    Xbd, Ybd = to_dev(Xb, torch.float32), to_dev(yb[:, None], torch.float32)
+    plan.set_points(Xad)
+    plan.fit(h, Yad)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.set_points(Xad)
+        plan.fit(h, Yad)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.set_points(Xad)
+        plan.fit(h, Yad)
+    plan.set_points(Xbd)
+    graph.replay()
+    plan.fit(h, Ybd)
+    torch.cuda.synchronize()
+    assert plan.diagnostics()["status"] == -6
+    plan.set_points(Xbd)
+    mh = plan.fit(h, Ybd).cpu().numpy()[0, 0]
+    assert plan.diagnostics()["status"] == 0
+    gp = orc.grid_points(M, (0, 0), (1, 1))
+    X32 = Xb.astype(np.float32).astype(np.float64)
+    ref, S, T, r0, ill = orc.fit(X32, yb.astype(np.float32).astype(np.float64), h, 1, gp, return_all=True)
+    compare_fit(mh, ref[:, 0], S, h, 1, 2, 1e-5)
