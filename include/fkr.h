@@ -196,6 +196,24 @@ fkr_status fkr_fit(fkr_plan* plan, int nh, const double* h, int q, int y_complex
                    const void* Y_dev, int y_type, double* mhat_dev, double* s0_dev,
                    void* stream);
 
+/* fkr_set_points followed by fkr_fit, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): the
+ * workspace is an array the library holds on each device for the life of the
+ * process, FKR_STATIC_WORKSPACE_BYTES long, instead of a caller buffer bound
+ * with fkr_set_workspace.  Calls no hipMalloc / hipFree.  The plan must need
+ * at most that much (fkr_workspace_size), else FKR_E_WORKSPACE and nothing
+ * is enqueued; arguments as in fkr_set_points and fkr_fit (N <= n_max).  The
+ * plan stays bound to the array, so later calls on it use the array too.
+ * Every call on a device shares that device's array and keeps the last
+ * call's contents: the plan's tables are uploaded and the counters cleared,
+ * ordered on `stream`, at the start of each call.  Calls on one device that
+ * can overlap (other streams, other host threads, other plans) race on the
+ * array; serialise them. */
+#define FKR_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+fkr_status fkr_fit_noalloc(fkr_plan* plan, int64_t N, const void* X_dev, int x_type, int nh,
+                           const double* h, int q, int y_complex, const void* Y_dev, int y_type,
+                           double* mhat_dev, double* s0_dev, void* stream);
+
 /* Multilinear interpolation (the linear griddedInterpolant of Sec. 1.1/5) of
  * nv grid functions G_dev ([nv][M^d] doubles) at Nq query points Xq_dev
  * (Nq x d, type x_type) -> out_dev ([nv][Nq] doubles).  The cell of a point

@@ -16,6 +16,7 @@ FKR_VAR_LOG, FKR_VAR_DIRECT = 0, 1
 FKR_TP_SAME, FKR_TP_F32, FKR_TP_F64 = 0, 1, 2
 FKR_MAX_H = 64
 FKR_RESOLVE = 1e-3
+FKR_STATIC_WORKSPACE_BYTES = 64 << 20
 
 I64x3 = ctypes.c_int64 * 3
 F64x3 = ctypes.c_double * 3
@@ -45,7 +46,7 @@ class Diag(ctypes.Structure):
 
 
 EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_workspace_size",
-           "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit",
+           "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit", "fkr_fit_noalloc",
            "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_get_diagnostics",
            "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
            "fkr_profile_read"]
@@ -83,6 +84,7 @@ def load() -> ctypes.CDLL:
         "fkr_spectrum": ([P, I, P, I, P, P], I),
         "fkr_moments": ([P, I, pD, I, P, I, P, P, P], I),
         "fkr_fit": ([P, I, pD, I, I, P, I, P, P, P], I),
+        "fkr_fit_noalloc": ([P, I64, P, I, I, pD, I, I, P, I, P, P, P], I),
         "fkr_interp": ([P, I, P, I64, P, I, P, P], I),
         "fkr_dof": ([P, I, pD, I, U64, P, I, P, P, P], I),
         "fkr_cv": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P, P], I),

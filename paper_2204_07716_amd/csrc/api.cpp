@@ -445,6 +445,52 @@ fkr_status cv_impl(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
+// The plan's constant tables (periods, channel exponents, pair index,
+// deconvolution factors, twiddles, tile cover lists) as (workspace offset,
+// bytes) blobs.
+std::vector<std::pair<size_t, std::vector<unsigned char>>> constant_tables(const fkr_plan* p) {
+    std::vector<std::pair<size_t, std::vector<unsigned char>>> out;
+    auto add = [&](size_t off, const void* data, size_t n) {
+        const unsigned char* c = static_cast<const unsigned char*>(data);
+        out.emplace_back(off, std::vector<unsigned char>(c, c + n));
+    };
+    std::vector<unsigned char> consts(4096, 0);
+    double* per = reinterpret_cast<double*>(consts.data());
+    for (int j = 0; j < p->d; ++j) per[j] = p->T[j];
+    int* es = reinterpret_cast<int*>(consts.data() + 64);
+    int* et = reinterpret_cast<int*>(consts.data() + 64 + 512);
+    int* pi = reinterpret_cast<int*>(consts.data() + 64 + 1024);
+    for (int c = 0; c < p->n_s; ++c) for (int j = 0; j < 3; ++j) es[3 * c + j] = p->es[c][j];
+    for (int c = 0; c < p->n_t; ++c) for (int j = 0; j < 3; ++j) et[3 * c + j] = p->et[c][j];
+    for (int b = 0; b < kMaxP; ++b) for (int c = 0; c < kMaxP; ++c) pi[b * kMaxP + c] = p->pair_index[b][c];
+    add(p->lay.consts, consts.data(), consts.size());
+    size_t off = p->lay.deconv;
+    for (int j = 0; j < p->d; ++j) {
+        add(off, p->deconv[j].data(), p->deconv[j].size() * 8);
+        off += p->deconv[j].size() * 8;
+        std::vector<double> tw;
+        twiddle_table(p->Mr[j], &tw);
+        add(p->fMr[j].tw_off, tw.data(), tw.size() * 8);
+        twiddle_table(p->L[j], &tw);
+        add(p->fL[j].tw_off, tw.data(), tw.size() * 8);
+    }
+    off = p->lay.cover;
+    for (int j = 0; j < p->d; ++j) {
+        add(off, p->cover[j].data(), p->cover[j].size() * 4);
+        off += p->cover[j].size() * 4;
+    }
+    return out;
+}
+
+// The argument checks of fkr_fit that do not need points on the device.
+fkr_status st_check_fit(const fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y,
+                        int y_type, const double* mhat) {
+    if (check_h(p, nh, h) != FKR_OK) return FKR_E_ARG;
+    if (q < 1 || !mhat || !Y || (y_complex != 0 && y_complex != 1) || !valid_type(y_type)) return FKR_E_ARG;
+    if (1 + q * (y_complex ? 2 : 1) > p->max_weights) return FKR_E_ARG;
+    return FKR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -509,35 +555,39 @@ fkr_status fkr_set_workspace(fkr_plan* p, void* ws, size_t bytes) {
     p->ws_bytes = bytes;
     p->ws_ready = false;
     p->points_set = false;
-    std::vector<unsigned char> consts(4096, 0);
-    double* per = reinterpret_cast<double*>(consts.data());
-    for (int j = 0; j < p->d; ++j) per[j] = p->T[j];
-    int* es = reinterpret_cast<int*>(consts.data() + 64);
-    int* et = reinterpret_cast<int*>(consts.data() + 64 + 512);
-    int* pi = reinterpret_cast<int*>(consts.data() + 64 + 1024);
-    for (int c = 0; c < p->n_s; ++c) for (int j = 0; j < 3; ++j) es[3 * c + j] = p->es[c][j];
-    for (int c = 0; c < p->n_t; ++c) for (int j = 0; j < 3; ++j) et[3 * c + j] = p->et[c][j];
-    for (int b = 0; b < kMaxP; ++b) for (int c = 0; c < kMaxP; ++c) pi[b * kMaxP + c] = p->pair_index[b][c];
-    FKR_HIP(hipMemcpy(p->ws + p->lay.consts, consts.data(), consts.size(), hipMemcpyHostToDevice));
-    size_t off = p->lay.deconv;
-    for (int j = 0; j < p->d; ++j) {
-        FKR_HIP(hipMemcpy(p->ws + off, p->deconv[j].data(), p->deconv[j].size() * 8, hipMemcpyHostToDevice));
-        off += p->deconv[j].size() * 8;
-        std::vector<double> tw;
-        twiddle_table(p->Mr[j], &tw);
-        FKR_HIP(hipMemcpy(p->ws + p->fMr[j].tw_off, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
-        twiddle_table(p->L[j], &tw);
-        FKR_HIP(hipMemcpy(p->ws + p->fL[j].tw_off, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
-    }
-    off = p->lay.cover;
-    for (int j = 0; j < p->d; ++j) {
-        FKR_HIP(hipMemcpy(p->ws + off, p->cover[j].data(), p->cover[j].size() * 4, hipMemcpyHostToDevice));
-        off += p->cover[j].size() * 4;
-    }
+    for (const auto& blob : constant_tables(p))
+        FKR_HIP(hipMemcpy(p->ws + blob.first, blob.second.data(), blob.second.size(), hipMemcpyHostToDevice));
     FKR_HIP(hipMemset(p->ws + p->lay.diag, 0, 16 * 8));
     FKR_HIP(hipDeviceSynchronize());
     p->ws_ready = true;
     return FKR_OK;
+}
+
+fkr_status fkr_fit_noalloc(fkr_plan* p, int64_t N, const void* X, int x_type, int nh, const double* h, int q,
+                           int y_complex, const void* Y, int y_type, double* mhat, double* s0, void* stream) {
+    if (!p) return FKR_E_ARG;
+    if (p->lay.total > kStaticScratchBytes) return FKR_E_WORKSPACE;   // the plan needs more than the array holds
+    if (N < 0 || N > p->n_max || (N > 0 && !X) || !valid_type(x_type)) return FKR_E_ARG;
+    if ((st_check_fit(p, nh, h, q, y_complex, Y, y_type, mhat)) != FKR_OK) return FKR_E_ARG;
+    void* ws = nullptr;
+    if (static_scratch(&ws) != hipSuccess) return FKR_E_DEVICE;
+    const hipStream_t s = S(stream);
+    // Bind the plan to the device's array.  Its contents are whatever the
+    // last call on this device left: the plan's tables are uploaded again
+    // (ordered on the stream, after any earlier call queued there) and the
+    // counters are cleared.
+    p->ws = static_cast<unsigned char*>(ws);
+    p->ws_bytes = kStaticScratchBytes;
+    p->points_set = false;
+    if (p->const_blobs.empty()) p->const_blobs = constant_tables(p);
+    for (const auto& blob : p->const_blobs)
+        FKR_HIP(hipMemcpyAsync(p->ws + blob.first, blob.second.data(), blob.second.size(), hipMemcpyHostToDevice, s));
+    launch_zero(p->ws + p->lay.diag, 16 * 8, s);
+    if (hipGetLastError() != hipSuccess) return FKR_E_DEVICE;
+    p->ws_ready = true;
+    fkr_status st = fkr_set_points(p, N, X, x_type, stream);
+    if (st != FKR_OK) return st;
+    return fkr_fit(p, nh, h, q, y_complex, Y, y_type, mhat, s0, stream);
 }
 
 fkr_status fkr_set_points(fkr_plan* p, int64_t N, const void* X, int x_type, void* stream) {

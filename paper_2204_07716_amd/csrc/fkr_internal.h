@@ -108,6 +108,10 @@ struct fkr_plan {
     // check it there (a replayed HIP graph may have re-sorted other points)
     long long epoch = 0;
     void* last_stream = nullptr;
+    // constant tables as (workspace offset, bytes), kept for the
+    // asynchronous uploads of fkr_fit_noalloc (their source must outlive the
+    // copies queued on the stream)
+    std::vector<std::pair<size_t, std::vector<unsigned char>>> const_blobs;
     // stage timing (fkr_profile_enable / fkr_profile_read)
     bool prof_on = false;
     std::vector<hipEvent_t> ev_free;

@@ -201,6 +201,11 @@ void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, c
 void launch_sigma2(int64_t Mtot, const double* vhat, const double* kappa_sums, double* sigma2,
                    double* kappa_out, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// The library-held workspace of the current device (fkr_fit_noalloc):
+// kStaticScratchBytes, 256-byte aligned.
+constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(void** ptr);
 void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);

@@ -19,6 +19,8 @@
 //                          residual dot products (Sec. 2.1, eq. 22)
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -1990,6 +1992,35 @@ void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int 
         k_stage_weights<double><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, pc, perm, static_cast<double*>(out));
     else
         k_stage_weights<float><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, pc, perm, static_cast<float*>(out));
+}
+
+// ---------------------------------------------------------------------------
+// Workspace held by the library for the entry point that allocates nothing
+// (fkr_fit_noalloc): one array per device, for the life of the process.  In
+// host code the array's name only stands in for it; its device address comes
+// from hipGetSymbolAddress, taken once per device and cached.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
