@@ -1,41 +1,45 @@
 #!/usr/bin/env python3
 """Throughput of the fast kernel-regression hot path on one MI355X.
 
-Workload: the 2-D local-linear mixture regression (N = 1e6 samples from a
-4-component Gaussian mixture clipped to the unit square, y = sin(4 x1)
-cos(3 x2) + 0.2 e, h = (0.03, 0.05), M = 256^2 grid, order 1, eps = 1e-6,
-FP32 spreading, FP64 transforms by default, FP64 3x3 solves), seeded and
-synthetic.  One step is one pass of the whole path:
+Headline workload (``--workload ll3d``, the default): 3-D local linear
+regression with the heteroscedastic-variance second pass, N = 1e7 samples
+x ~ U[0,1]^3, y = |x|^2 + (0.1 + 0.5 x1) e, h = 0.05 in every dimension,
+M = 128^3 grid, eps = 1e-6, FP32 spreading, FP64 transforms and FP64 4x4
+solves, seeded and synthetic.  One step is one pass of the whole path:
 
   set_points   bin and sort the samples (once per X)
   cv           spread of density, y and 10 Philox probes -> forward FFTs ->
                moment channels -> FP64 solves -> interpolation -> Girard DF,
-               RSS and GCV (Sec. 2.1, eq. 22)
+               RSS and GCV over the supported samples (Sec. 2.1, eq. 22)
   variance     log-residual second pass (eq. 24-26): residuals, spread,
                FFTs, solves, kappa, sigma^2 on the grid
 
+``--workload ll2d`` runs the 2-D mixture configuration (N = 1e6, M = 256^2,
+h = (0.03, 0.05)) the same way; its working set (about 217 MB) fits the
+256 MB Infinity Cache, so its HBM fractions are labelled cache-resident.
+
 The headline value is samples/s = N x fits / step time, where a fit is one
 weight vector through spread + FFT + solve (1 response + 10 probes + 1
-variance pass = 12 per step).  The ``roofline`` object reports the spreading
-kernel (the largest single kernel of the step) against FP32 FMA issue with its
-algorithmic flops per launch, and against HBM bandwidth with its algorithmic
-bytes, timed with HIP events that the library records on the launch stream;
-``warm`` times the same step without set_points (X already sorted);
-``hbm_model`` sets the step's algorithmic bytes against HBM bandwidth;
-``cpu_baseline`` times the FP64 oracle on a bounded sample of grid points and
-extrapolates to the full grid; ``accuracy`` compares the GPU grids with the
-oracle on that same sample; ``fp64_single`` times the plain FP64 form (FP64
-spreading, transforms and solves) of one regression on the same samples, for
-comparison with the batched FP32-spreading step.
+variance pass = 12 per step).  ``roofline`` reports the dominant kernel, the
+cv call's spreading launch, against FP32 FMA issue with its algorithmic flops
+(2 w^d flops per sample and weight column) and against HBM with its
+algorithmic bytes, timed with the HIP events the library records on the
+launch stream; ``hbm_model`` sets the step's algorithmic bytes against HBM
+bandwidth; ``cpu_baseline`` times the FP64 oracle on a bounded sample of grid
+points and extrapolates to the full grid; ``accuracy`` compares the GPU grids
+with the oracle on that sample; ``fp64_single`` times the plain FP64 form
+(FP64 spreading, transforms and solves) of one regression on the same
+samples, replayed as a HIP graph like the batched step, with its own error.
 
-By default the timed steps replay a HIP graph captured from one step (the
-step's ~30 kernel launches are launch-bound on the host otherwise); before
-timing, three replays are compared with eager steps.  ``--eager`` times
-host-launched steps instead.  Stage times always come from eager steps, where
-the library brackets every launch with HIP events on the launch stream.
+The timed steps replay a HIP graph captured from one step (the step's
+launches are launch-bound on the host otherwise); before timing, replays are
+compared with eager steps.  ``--eager`` times host-launched steps instead.
+Stage times always come from eager steps, where the library brackets every
+launch with HIP events on the launch stream.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--transform fp64|fp32] [--eager]
-                       [--no-warm] [--no-cpu-baseline] [--no-fp64-single]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ll3d|ll2d]
+                       [--transform fp64|fp32] [--eager] [--no-warm]
+                       [--no-cpu-baseline] [--no-fp64-single] [--cpu-points G]
 """
 from __future__ import annotations
 
@@ -43,6 +47,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -50,10 +55,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 FMA issue: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (no packed FP32)
+# FP32 FMA issue: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (packed
+# FP32 off); the published 157.3 TFLOP/s counts two FMAs per lane per cycle.
 FP32_FMA_PEAK_TFLOPS = 78.6
-COUNTERS = os.path.join(ROOT, "profiles", "k_spread_ll2d_counters.json")
+FP32_PUBLISHED_TFLOPS = 157.3
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_07716_amd", "csrc", "kernels.hip")
+COUNTERS = {"ll3d": os.path.join(ROOT, "profiles", "k_spread_col3_ll3d_counters.json"),
+            "ll2d": os.path.join(ROOT, "profiles", "k_spread_ll2d_counters.json")}
+LABEL = {
+    "ll3d": "3-D local linear + log-variance pass, N=1e7 uniform, h=0.05, M=128^3, eps=1e-6, "
+            "10 Philox probes",
+    "ll2d": "2-D local linear + log-variance pass, N=1e6 mixture, h=(0.03,0.05), M=256x256, "
+            "eps=1e-6, 10 Philox probes (cache-resident: working set < 256 MB Infinity Cache)",
+}
 
 
 def _args():
@@ -61,6 +75,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["ll3d", "ll2d"], default="ll3d")
     ap.add_argument("--transform", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the FFTs and moment channels (spreading is FP32)")
     ap.add_argument("--sigma", type=float, default=0.0,
@@ -72,8 +87,8 @@ def _args():
                     help="skip timing the plain FP64 single-regression form")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-path timing (profiling runs count only the cold steps)")
-    ap.add_argument("--cpu-points", type=int, default=4096,
-                    help="grid points in the oracle's timed sample")
+    ap.add_argument("--cpu-points", type=int, default=0,
+                    help="grid points per pass in the oracle's timed sample (0: 512 in 3-D, 2048 in 2-D)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (counter calibration)")
     return ap.parse_args()
@@ -84,48 +99,94 @@ def _kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _traffic(launches_per_step: int):
-    """HBM bytes per spread launch from the committed counter run, or None when
-    the kernel source has changed since the counters were taken."""
+def _traffic(workload: str):
+    """HBM bytes per launch of the cv spread from the committed counter run,
+    or None when the kernel source has changed since the counters were taken."""
     try:
-        with open(COUNTERS) as f:
+        with open(COUNTERS[workload]) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
     if c.get("kernel_source_sha256") != _kernel_hash():
         return None
-    per_step = (c["fetch_kib_per_step"] * 1024 * c["copy_fetch_scale"]
-                + c["write_kib_per_step"] * 1024 * c["copy_write_scale"])
-    return per_step / launches_per_step
+    return (c["fetch_kib_per_launch"] * 1024 * c["copy_fetch_scale"]
+            + c["write_kib_per_launch"] * 1024 * c["copy_write_scale"])
 
 
-def _hbm_model(g, N, M, Np, stages, steps, ms_per_step):
-    """Algorithmic bytes of the step (sort, spread, forward FFT, inverse FFT,
-    solve; FP32 spreading, FP64 complex transforms) against HBM bandwidth, for
-    spread + FFT and for the whole step."""
-    d = 2
-    Mr = g.Mr[0] * g.Mr[1]
-    L = g.L[0] * g.L[1]
-    Mg = M[0] * M[1]
-    bx, bw, bc_s, bc_t = 4, 4, 8, 16
-    n_s, n_t = 6, 3
-    calls = [dict(nw=2 + Np, q=1, np_=Np), dict(nw=2, q=1, np_=0)]   # cv, variance
-    b_sort = N * (d * bx + 24)
+import numpy as np  # noqa: E402  (host arithmetic of the byte model)
+
+
+def _pass_bytes(npair, n_in, n_out, rows_in, b):
+    """Bytes one transform pass moves: rows_in x n_in read, rows_in x n_out written."""
+    return npair * rows_in * (n_in + n_out) * b
+
+
+def _hbm_model(g, d, N, M, n_s, n_t, Np, n_jobs, stages, steps, ms_per_step, cache_resident):
+    """Algorithmic bytes of the step for the plan actually run (sort, spread
+    with its tile subgrids, forward passes with the fold, inverse passes from
+    the band to the grid, solve), FP32 spreading and FP64 complex transforms,
+    against HBM bandwidth: for spread + forward FFT and for the whole step."""
+    Mr = [g.Mr[j] for j in range(d)]
+    B = [2 * g.K[j] + 1 for j in range(d)]
+    Mg = list(M)
+    psub = (g.tile[0] + g.w - 1) ** d
+    bx, bw, bs, bt = 4, 4, 8, 16
+    b_sort = N * (d * bx + 4 * 8 + 32)                      # read X, write + read the tile record, write the sorted record
+    calls = [dict(nw=2 + Np, ncp=(n_s + n_t * (1 + Np) + 1) // 2, keep=0, nsol=n_s + n_t * (1 + Np) + 1 + Np),
+             dict(nw=2, ncp=(n_s + n_t + 1) // 2, keep=n_s // 2, nsol=n_s + n_t + 1)]   # cv, variance
     b_spread = b_fft = b_inv = b_solve = 0
     for c in calls:
         npair = (c["nw"] + 1) // 2
-        n_ch = n_s + n_t * (c["nw"] - 1)
-        b_spread += N * (d * bx + c["nw"] * bw) + npair * Mr * bc_s
-        b_fft += d * 2 * npair * Mr * bc_t
-        b_inv += ((n_ch + 1) // 2) * L * bc_t * (1 + 2 * d)
-        b_solve += (n_ch + c["q"] + c["np_"]) * Mg * 8
+        b_spread += N * (d * bx + c["nw"] * bw) + n_jobs * npair * psub * bs    # samples in, subgrids out
+        # forward: pass j reads its rows (the fold reads the subgrids) and keeps the band
+        shape = list(Mr)
+        fwd = n_jobs * npair * psub * bs
+        for j in range(d):
+            rows = 1
+            for i in range(d):
+                if i != j:
+                    rows *= shape[i]
+            fwd += _pass_bytes(npair, 0 if j == 0 else shape[j], B[j], rows, bt)
+            shape[j] = B[j]
+        b_fft += fwd
+        # inverse: expand from the pair band, then band -> grid per dimension
+        ncp = c["ncp"] - c["keep"]
+        shape = list(B)
+        inv = npair * int(np.prod(B)) * bt
+        for j in (range(d) if d != 2 else (1, 0)):
+            rows = 1
+            for i in range(d):
+                if i != j:
+                    rows *= shape[i]
+            inv += _pass_bytes(ncp, 0 if shape == list(B) else shape[j], Mg[j], rows, bt)
+            shape[j] = Mg[j]
+        b_inv += inv
+        b_solve += c["nsol"] * int(np.prod(Mg)) * 8
     t_sf = sum(stages[k][0] for k in ("spread", "fold", "fft_fwd")) * 1e-3 / steps
     b_all = b_sort + b_spread + b_fft + b_inv + b_solve
-    return {"spread_fft": {"bytes": b_spread + b_fft, "ms": round(t_sf * 1e3, 4),
-                           "frac": round((b_spread + b_fft) / t_sf / 8e12, 4)},
-            "whole_step": {"bytes": b_all, "ms": round(ms_per_step, 4),
-                           "frac": round(b_all / (ms_per_step * 1e-3) / 8e12, 4)},
-            "peak_GBs": 8000.0}
+    out = {"spread_fft": {"bytes": b_spread + b_fft, "ms": round(t_sf * 1e3, 4),
+                          "frac": round((b_spread + b_fft) / t_sf / 8e12, 4)},
+           "whole_step": {"bytes": b_all, "ms": round(ms_per_step, 4),
+                          "frac": round(b_all / (ms_per_step * 1e-3) / 8e12, 4)},
+           "stage_bytes": {"sort": b_sort, "spread": b_spread, "fft_fwd": b_fft, "fft_inv": b_inv,
+                           "solve": b_solve},
+           "peak_GBs": HBM_PEAK_GBS}
+    if cache_resident:
+        out["cache_resident"] = True
+    return out
+
+
+def _cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
 def main() -> int:
@@ -146,12 +207,12 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}))
         return 1
     dev = torch.device("cuda:0")
-    w = workloads.make("ll2d")
-    N, M, h = w.N, w.M, w.h[0]
+    w = workloads.make(args.workload)
+    d, N, M, h = w.d, w.N, w.M, w.h[0]
     Np, seed = w.n_probes, w.probe_seed
     Xd = torch.as_tensor(w.X.astype(np.float32), device=dev)
     Yd = torch.as_tensor(w.Y.astype(np.float32), device=dev)
-    plan = Plan(2, 1, M, w.lo, w.hi, h, h, w.eps, precision="fp32", n_max=N,
+    plan = Plan(d, 1, M, w.lo, w.hi, h, h, w.eps, precision="fp32", n_max=N,
                 max_weights=2 + Np, max_h=1, transform_precision=args.transform, sigma=args.sigma)
     g = plan.geometry
     torch.cuda.synchronize()
@@ -162,67 +223,78 @@ def main() -> int:
         s2, vhat, kappa = plan.variance(h, Yd, out["mhat"][0, 0], mode="log")
         return out, s2, vhat, kappa
 
+    def graph_of(fn):
+        s_cap = torch.cuda.Stream()
+        s_cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_cap):
+            fn()                         # warm the capture stream's allocator pool
+        torch.cuda.current_stream().wait_stream(s_cap)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            res = fn()
+        return gr, res
+
+    def same(a, b, rel=1e-6):
+        # samples of one cell are ranked with LDS atomics, so the FP32
+        # summation order (and the last bits) may differ between runs
+        fin = torch.isfinite(b)
+        scale = b[fin].abs().max() if fin.any() else torch.tensor(0.0, device=b.device)
+        return torch.equal(torch.isnan(a), torch.isnan(b)) and \
+            bool((a[fin] - b[fin]).abs().max() <= rel * scale) if fin.any() else True
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     args.graph = not args.eager
     if args.graph:
-        # eager reference, then capture; every replay must reproduce it
         ref = step()
         torch.cuda.synchronize()
         ref_vals = [ref[0]["mhat"].clone(), ref[0]["rho"].clone(), ref[0]["gcv"].clone(), ref[1].clone()]
-        s_cap = torch.cuda.Stream()
-        s_cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s_cap):
-            step()                       # warm the capture stream's allocator pool
-        torch.cuda.current_stream().wait_stream(s_cap)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            res_g = step()
-        for rep in range(3):
+        graph, res_g = graph_of(step)
+        for rep in range(2):
             graph.replay()
             torch.cuda.synchronize()
             got = [res_g[0]["mhat"], res_g[0]["rho"], res_g[0]["gcv"], res_g[1]]
-            for a, b in zip(got, ref_vals):
-                # samples of one cell are ranked with LDS atomics, so the FP32
-                # summation order (and the last bits) may differ between runs
-                fin = torch.isfinite(b)
-                scale = b[fin].abs().max() if fin.any() else torch.tensor(0.0, device=b.device)
-                same_nan = torch.equal(torch.isnan(a), torch.isnan(b))
-                if not same_nan or (a[fin] - b[fin]).abs().max() > 1e-6 * scale:
-                    print(json.dumps({"error": "graph replay differs from the eager step", "replay": rep}))
-                    return 1
+            if not all(same(a, b) for a, b in zip(got, ref_vals)):
+                print(json.dumps({"error": "graph replay differs from the eager step", "replay": rep}))
+                return 1
             step()                       # eager work between replays
             torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if args.graph:
+        t0 = time.perf_counter()
         for _ in range(args.steps):
             graph.replay()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         res = res_g
-        # stage times come from an eager pass over the same steps
-        plan.profile(True)
-        plan.profile_read()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        stages = plan.profile_read()
-        plan.profile(False)
     else:
-        plan.profile(True)
-        plan.profile_read()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             res = step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        stages = plan.profile_read()
-        plan.profile(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     n_fits = (1 + Np) + 1
+
+    # Stage times and the cv spread launch alone, from eager profiled steps
+    # (HIP events the library records on the launch stream).
+    plan.profile(True)
+    plan.profile_read()
+    stages = {k: [0.0, 0] for k in plan.profile_read()}
+    cv_spread_ms, cv_spread_n = 0.0, 0
+    for _ in range(args.steps):
+        plan.set_points(Xd)
+        out_p = plan.cv(h, Yd, Np, seed=seed)
+        a = plan.profile_read()
+        cv_spread_ms += a["spread"][0]
+        cv_spread_n += a["spread"][1]
+        plan.variance(h, Yd, out_p["mhat"][0, 0], mode="log")
+        b = plan.profile_read()
+        for k in stages:
+            stages[k][0] += a[k][0] + b[k][0]
+            stages[k][1] += a[k][1] + b[k][1]
+    plan.profile(False)
 
     # Warm path: X already sorted, set_points outside the timed region.
     def warm_step():
@@ -231,95 +303,77 @@ def main() -> int:
         return out, s2, vhat, kappa
 
     warm_ms = None
-    if args.no_warm:
-        pass
-    elif args.graph:
+    if not args.no_warm:
         plan.set_points(Xd)
         warm_step()
         torch.cuda.synchronize()
-        s_cap = torch.cuda.Stream()
-        s_cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s_cap):
-            warm_step()
-        torch.cuda.current_stream().wait_stream(s_cap)
-        torch.cuda.synchronize()
-        wgraph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(wgraph):
-            wres = warm_step()
-        wgraph.replay()
-        torch.cuda.synchronize()
-        for a, b in zip([wres[0]["mhat"], wres[1]], [res[0]["mhat"], res[1]]):
-            fin = torch.isfinite(b)
-            if not torch.equal(torch.isnan(a), torch.isnan(b)) or \
-                    (a[fin] - b[fin]).abs().max() > 1e-6 * b[fin].abs().max():
+        if args.graph:
+            wgraph, wres = graph_of(warm_step)
+            wgraph.replay()
+            torch.cuda.synchronize()
+            if not (same(wres[0]["mhat"], res[0]["mhat"]) and same(wres[1], res[1])):
                 print(json.dumps({"error": "warm graph replay differs from the timed steps"}))
                 return 1
-        tw0 = time.perf_counter()
-        for _ in range(args.steps):
-            wgraph.replay()
-        torch.cuda.synchronize()
-        tw1 = time.perf_counter()
-    else:
-        plan.set_points(Xd)
-        warm_step()
-        torch.cuda.synchronize()
-        tw0 = time.perf_counter()
-        for _ in range(args.steps):
-            warm_step()
-        torch.cuda.synchronize()
-        tw1 = time.perf_counter()
-    if not args.no_warm:
-        warm_ms = (tw1 - tw0) * 1e3 / args.steps
+            tw0 = time.perf_counter()
+            for _ in range(args.steps):
+                wgraph.replay()
+            torch.cuda.synchronize()
+        else:
+            tw0 = time.perf_counter()
+            for _ in range(args.steps):
+                warm_step()
+            torch.cuda.synchronize()
+        warm_ms = (time.perf_counter() - tw0) * 1e3 / args.steps
     value = N * n_fits / (ms_per_step * 1e-3)
 
-    # Roofline of the spreading kernel.  Its arithmetic is 2 W^d n_w flops per
-    # sample (one FMA per footprint cell and weight column) against N (d b_x +
-    # n_w b_w) + n_pair Mr^d b_c algorithmic bytes: about 13 flop/B for the
-    # step's two launches, above the 9.8 flop/B ridge of FP32 FMA issue
-    # (78.6 TFLOP/s) over HBM (8 TB/s), so the bound is the ALU.
-    Mr2 = g.Mr[0] * g.Mr[1]
-    bx, bw, bc = 4, 4, 8
-    nw_launch = [2 + Np, 2]              # cv (density, y, probes), variance (density, z)
-    bytes_step = sum(N * (2 * bx + nw * bw) + ((nw + 1) // 2) * Mr2 * bc for nw in nw_launch)
-    flops_step = sum(2.0 * N * g.w ** 2 * nw for nw in nw_launch)
-    spread_ms, spread_n = stages["spread"]
-    launches_per_step = spread_n / args.steps
-    spread_s = spread_ms * 1e-3 / args.steps
-    achieved = flops_step / spread_s / 1e12
-    hbm_achieved = bytes_step / spread_s / 1e9
-    roofline = {"bound": "alu", "kernel": "spread: k_spread_wave (cv, 12 columns; variance, 2 columns)",
+    # Roofline of the cv spread (the step's largest kernel): 2 w^d flops per
+    # sample and weight column, FP32 FMA issue; HBM view with its algorithmic
+    # bytes N (d b_x + n_w b_w) + n_pair Mr^d b_c.
+    Mr = 1
+    for j in range(d):
+        Mr *= g.Mr[j]
+    nw = 2 + Np
+    flops = 2.0 * N * g.w ** d * nw
+    bytes_ = N * (d * 4 + nw * 4) + ((nw + 1) // 2) * Mr * 8
+    launch_s = cv_spread_ms * 1e-3 / max(cv_spread_n, 1)
+    achieved = flops / launch_s / 1e12
+    kname = "k_spread_col3 (cv: 12 columns, 3 passes of 4)" if d == 3 else "k_spread_wave (cv: 12 columns)"
+    roofline = {"bound": "alu", "kernel": kname,
                 "achieved": round(achieved, 2), "peak": FP32_FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_FMA_PEAK_TFLOPS, 4),
-                "traffic": _traffic(launches_per_step),
-                "algorithmic_flops_per_launch": flops_step / launches_per_step,
-                "algorithmic_bytes_per_launch": bytes_step / launches_per_step,
-                "avg_launch_us": round(spread_ms * 1e3 / max(spread_n, 1), 2),
-                "launches_per_step": launches_per_step,
-                "hbm": {"achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}}
+                "traffic": _traffic(args.workload),
+                "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": bytes_,
+                "avg_launch_us": round(launch_s * 1e6, 2),
+                "launches_measured": cv_spread_n,
+                "frac_of_published_fp32_157": round(achieved / FP32_PUBLISHED_TFLOPS, 4),
+                "hbm": {"achieved": round(bytes_ / launch_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(bytes_ / launch_s / 1e9 / HBM_PEAK_GBS, 4)}}
 
     out, s2, vhat, kappa = res
+    cache_resident = args.workload == "ll2d"
     line = {
         "metric": "samples/s (spread+FFT+solve) at stated rel err vs FP64 oracle; % of HBM BW",
         "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 spread, %s transforms, f64 solves" % ("f64" if args.transform == "fp64" else "f32"),
-        "data": "synthetic (seeded 4-component Gaussian mixture, N=1e6)",
-        "config": {"workload": "2-D local linear, N=1e6 mixture, h=(0.03,0.05), M=256x256, "
-                               "eps=1e-6, 10 Philox probes, log-variance pass",
+        "data": "synthetic (seeded, %s)" % ("x ~ U[0,1]^3, N=1e7" if d == 3 else "4-component Gaussian mixture, N=1e6"),
+        "config": {"workload": LABEL[args.workload],
                    "N": N, "M": list(M), "order": 1, "fits_per_step": n_fits,
-                   "grid_points_per_s": round(M[0] * M[1] * n_fits / (ms_per_step * 1e-3), 1),
-                   "L": [g.L[0], g.L[1]], "Mr": [g.Mr[0], g.Mr[1]], "K": [g.K[0], g.K[1]],
-                   "spread_width": g.w, "sigma": args.sigma or "default",
-                   "hip_graph": bool(args.graph)},
+                   "grid_points_per_s": round(float(np.prod(M)) * n_fits / (ms_per_step * 1e-3), 1),
+                   "L": [g.L[j] for j in range(d)], "Mr": [g.Mr[j] for j in range(d)],
+                   "K": [g.K[j] for j in range(d)], "spread_width": g.w,
+                   "sigma": args.sigma or "default", "hip_graph": bool(args.graph)},
         "roofline": roofline,
         "warm": None if warm_ms is None else
                 {"ms_per_step": round(warm_ms, 4), "value": round(N * n_fits / (warm_ms * 1e-3), 1),
                  "unit": "samples/s", "note": "X already sorted: set_points outside the timed region"},
-        "hbm_model": _hbm_model(g, N, M, Np, stages, args.steps, ms_per_step),
+        "hbm_model": _hbm_model(g, d, N, M, plan.n_s, plan.n_t, Np, plan.diagnostics()["n_jobs"], stages,
+                                args.steps, ms_per_step, cache_resident),
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
-        "gcv": float(out["gcv"][0, 0]), "df": float(N * (1 - out["rho"][0].mean())),
+        "gcv": float(out["gcv"][0, 0]), "n_supported": float(out["nused"][0]),
+        "df": float(out["nused"][0] * (1 - out["rho"][0].mean())),
     }
 
     if args.copy_probe:
@@ -330,23 +384,37 @@ def main() -> int:
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = a.numel() * 4
 
+    sample = None
+    if not args.no_cpu_baseline or not args.no_fp64_single:
+        rng = np.random.default_rng(2024)
+        Mtot = int(np.prod(M))
+        G = args.cpu_points or (512 if d == 3 else 2048)
+        flat = rng.choice(Mtot, size=G, replace=False)
+        flat[:2] = [0, Mtot - 1]
+        sample = flat
+    fp64 = None
     if not args.no_fp64_single:
-        line["fp64_single"] = _fp64_single(w, Xd, Yd, args.steps, args.warmup, value)
+        fp64 = _fp64_single(w, Xd, Yd, args.steps, args.warmup, value, args.graph)
+        line["fp64_single"] = fp64
     if not args.no_cpu_baseline:
-        line.update(_cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, value))
+        line.update(_cpu_baseline(w, out, vhat, kappa, n_fits, value, sample, fp64))
+    if fp64 is not None:
+        fp64.pop("_mhat", None)
+    del plan
     print(json.dumps(line), flush=True)
     return 0
 
 
-def _fp64_single(w, Xd, Yd, steps, warmup, batched_value):
+def _fp64_single(w, Xd, Yd, steps, warmup, batched_value, use_graph):
     """The plain FP64 form of one regression on the same samples and grid:
-    FP64 spreading, transforms and solves, at the same requested accuracy;
-    one step is set_points and one fit (density and y, 2 weight vectors),
-    launched eagerly.  samples/s counts N per weight vector, as `value` does."""
+    FP64 spreading, transforms and solves at the same requested accuracy; one
+    step is set_points and one fit (density and y), replayed as a HIP graph
+    when the batched step is.  samples/s counts the response only (1 fit per
+    step), as `value` counts the 12 responses, probes and variance fits."""
     import torch
     from paper_2204_07716_amd import Plan
     h = w.h[0]
-    p64 = Plan(2, 1, w.M, w.lo, w.hi, h, h, w.eps, precision="fp64", n_max=w.N, max_weights=2,
+    p64 = Plan(w.d, 1, w.M, w.lo, w.hi, h, h, w.eps, precision="fp64", n_max=w.N, max_weights=2,
                max_h=1, transform_precision="fp64")
     X64, Y64 = Xd.double(), Yd.double()
 
@@ -357,32 +425,50 @@ def _fp64_single(w, Xd, Yd, steps, warmup, batched_value):
     for _ in range(max(1, warmup)):
         st()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        st()
-    torch.cuda.synchronize()
+    if use_graph:
+        s_cap = torch.cuda.Stream()
+        s_cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_cap):
+            st()
+        torch.cuda.current_stream().wait_stream(s_cap)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            mh = st()
+        gr.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gr.replay()
+        torch.cuda.synchronize()
+    else:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            mh = st()
+        torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    v = w.N * 2 / (ms * 1e-3)
+    v = w.N * 1 / (ms * 1e-3)
+    res = {"ms_per_step": round(ms, 4), "value": round(v, 1), "unit": "samples/s",
+           "fits_per_step": 1, "batched_fp32_over_fp64": round(batched_value / v, 2),
+           "hip_graph": bool(use_graph),
+           "note": "FP64 plan (spreading, transforms, solves), one response, set_points + fit per step",
+           "_mhat": mh[0, 0].cpu().numpy()}
     del p64
-    return {"ms_per_step": round(ms, 4), "value": round(v, 1), "unit": "samples/s",
-            "fits_per_step": 2, "batched_fp32_over_fp64": round(batched_value / v, 2),
-            "note": "FP64 plan, one response, eager launches"}
+    return res
 
 
-def _cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, gpu_value):
-    """The oracle on G seeded grid points (plus the corners): the fits of y and
-    the 10 probes and the log-variance fit, timed on the host cores and
+def _cpu_baseline(w, out, vhat, kappa, n_fits, gpu_value, flat, fp64):
+    """The oracle on G seeded grid points per pass: the fits of y and the 10
+    probes, then the log-variance fit, timed on the host cores and
     extrapolated to the full grid; its values at those points check the GPU
-    grids (density mask s_0 >= 1e-3 max s_0 over the sample)."""
+    grids (mask: s_0 >= 1e-3 max s_0 over the sample, resolved points)."""
     import numpy as np
 
     from oracle import oracle as orc
 
-    N, M, h = w.N, w.M, w.h[0]
-    G = max(16, int(args.cpu_points))
-    rng = np.random.default_rng(2024)
-    flat = rng.choice(M[0] * M[1], size=G, replace=False)
-    flat[:4] = [0, M[0] - 1, M[0] * (M[1] - 1), M[0] * M[1] - 1]
+    N, M, h, d = w.N, w.M, w.h[0], w.d
+    Mtot = int(np.prod(M))
+    G = len(flat)
     gp = orc.grid_points(M, w.lo, w.hi)[flat]
     X = w.X.astype(np.float32).astype(np.float64)
     y = w.Y[:, 0].astype(np.float32).astype(np.float64)
@@ -390,32 +476,37 @@ def _cpu_baseline(args, w, plan, out, vhat, kappa, n_fits, gpu_value):
     mh_gpu = out["mhat"][0, 0].cpu().numpy()
     # the variance pass's input: residuals against the GPU mean grid
     r = (y - orc.interp(mh_gpu, M, w.lo, w.hi, X)) ** 2
+    keep = np.isfinite(r)
     z = np.log(r + 1.0 / N)
     Wfit = np.concatenate([y[:, None], probes], axis=1)
     orc.fit(X[:1000], Wfit[:1000], h, 1, gp[:2])          # load / warm the library
     t0 = time.perf_counter()
     ref, S, T, r0, ill = orc.fit(X, Wfit, h, 1, gp, return_all=True)
-    v_ref = orc.fit(X, z, h, 1, gp)[:, 0]
+    v_ref = orc.fit(X[keep], z[keep], h, 1, gp)[:, 0]
     t_sample = time.perf_counter() - t0
-    t_full = t_sample * (M[0] * M[1]) / G
+    t_full = t_sample * Mtot / G
     cpu_value = N * n_fits / t_full
-    mask = S[:, 0] >= 1e-3 * S[:, 0].max()
+    mask = (S[:, 0] >= 1e-3 * S[:, 0].max()) & orc.resolved(S, h, 1, d)
 
     def rel(a, b):
         a, b = a[mask], b[mask]
         return float(np.abs(a - b).max() / np.abs(b).max())
 
+    model, nproc = _cpu_info()
+    acc = {"mhat_rel_err": rel(mh_gpu[flat], ref[:, 0]),
+           "vhat_rel_err": rel(vhat.cpu().numpy()[flat], v_ref),
+           "mask": "s0 >= 1e-3 max s0, resolved", "points": int(mask.sum()), "bar": 1e-5}
+    if fp64 is not None:
+        acc["fp64_single_mhat_rel_err"] = rel(fp64.pop("_mhat")[flat], ref[:, 0])
     return {
         "cpu_baseline": {
             "value": round(cpu_value, 2), "unit": "samples/s", "cores": orc.threads(),
             "kind": "oracle",
-            "sample": f"FP64 direct sums of the 12 fits at {G} of {M[0] * M[1]} grid points "
-                      f"(N={N}), {t_sample:.2f} s, extrapolated x{M[0] * M[1] / G:.0f} to the grid",
+            "sample": f"FP64 direct sums of the {n_fits} fits at {G} of {Mtot} grid points per pass "
+                      f"(N={N}), {t_sample:.2f} s, extrapolated x{Mtot / G:.0f} to the grid",
+            "nproc": nproc, "omp_threads": orc.threads(), "cpu_model": model,
             "gpu_over_cpu": round(gpu_value / cpu_value, 1)},
-        "accuracy": {"mhat_rel_err": rel(mh_gpu[flat], ref[:, 0]),
-                     "vhat_rel_err": rel(vhat.cpu().numpy()[flat], v_ref),
-                     "mask": "s0 >= 1e-3 max s0", "points": int(mask.sum()),
-                     "bar": 1e-5},
+        "accuracy": acc,
     }
 
 
