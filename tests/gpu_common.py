@@ -1,4 +1,6 @@
 """Helpers shared by the GPU parity tests (not collected by pytest)."""
+import itertools
+
 import numpy as np
 import torch
 
@@ -167,3 +169,46 @@ def equilibrate_oracle(S, T, h, order, d):
     Se = S / np.array([np.prod(h ** np.array(a)) for a in es])[None, :]
     Te = T / np.array([np.prod(h ** np.array(b)) for b in et])[None, None, :]
     return Se, Te
+
+
+def sample_flat(rng, M, n, extra=()):
+    d = len(M)
+    pts = [tuple(int(rng.integers(0, M[j])) for j in range(d)) for _ in range(n)]
+    pts += list(itertools.product(*[(0, M[j] - 1) for j in range(d)]))
+    pts += list(extra)
+    strides = np.cumprod((1,) + tuple(M[:-1]))
+    return np.array([sum(k[j] * strides[j] for j in range(d)) for k in pts])
+
+
+def stage_isolated_dof(orc, plan, w, h, probes, rho_gpu, nused_gpu, gcv_gpu, mh_gpu, flat, Y=None):
+    """Stage isolation at full size (the direct oracle cannot cover the whole
+    grid): the GPU's density moments on the whole grid and the probes' grid
+    fits are checked at seeded grid points against the oracle, then the
+    oracle's support rule, Girard ratios and GCV are evaluated from those GPU
+    grids and compared with the GPU's reductions."""
+    d, order = w.d, w.order
+    X = w.X.astype(np.float32).astype(np.float64)
+    P32 = probes.astype(np.float32)
+    Np = P32.shape[1]
+    S_eq, _ = plan.moments(h)
+    S_gpu = unequilibrate(S_eq.cpu().numpy()[0], h, order, d)                 # [M][n_s]
+    pf = plan.fit(h, torch.as_tensor(P32, device="cuda")).cpu().numpy()[0]   # [Np][M]
+    gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
+    ref, S, T, r0, ill = orc.fit(X, P32.astype(np.float64), h, order, gp, return_all=True)
+    assert rel_err(S_gpu[flat, 0], S[:, 0]) < 1e-5
+    for p in range(Np):
+        compare_fit(pf[p][flat], ref[:, p], S, h, order, d, 1e-5)
+    ill_gpu = np.isnan(pf[0])
+    what = orc.interp(pf.T, w.M, w.lo, w.hi, X)
+    variants = support_variants(S_gpu, ill_gpu, h, order, d, w.M, w.lo, w.hi, X)
+    inc = match_dof(rho_gpu[:Np], nused_gpu, P32.astype(np.float64), what, variants, 1e-6)
+    if gcv_gpu is not None:
+        Yv = (w.Y[:, 0] if Y is None else Y)
+        if np.iscomplexobj(Yv):
+            Yv = Yv.astype(np.complex64).astype(np.complex128)
+        else:
+            Yv = Yv.astype(np.float32).astype(np.float64)
+        yhat = orc.interp(mh_gpu, w.M, w.lo, w.hi, X)
+        g_ref = orc.gcv(Yv, yhat, float(np.mean(rho_gpu)), include=inc)[0]
+        assert abs(gcv_gpu / g_ref - 1) < 1e-6, (gcv_gpu, g_ref)
+    return inc

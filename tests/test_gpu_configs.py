@@ -9,20 +9,11 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_common import (compare_fit, density_mask, make_plan, match_dof, rel_err, support_variants, to_dev,
-                        unequilibrate)
+from gpu_common import (compare_fit, density_mask, make_plan, match_dof, rel_err, sample_flat,
+                        stage_isolated_dof, support_variants, to_dev)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-
-
-def _sample_flat(rng, M, n, extra=()):
-    d = len(M)
-    pts = [tuple(int(rng.integers(0, M[j])) for j in range(d)) for _ in range(n)]
-    pts += list(itertools.product(*[(0, M[j] - 1) for j in range(d)]))
-    pts += list(extra)
-    strides = np.cumprod((1,) + tuple(M[:-1]))
-    return np.array([sum(k[j] * strides[j] for j in range(d)) for k in pts])
 
 
 def test_ll3d_full_size_fit_and_variance(orc):
@@ -42,7 +33,7 @@ def test_ll3d_full_size_fit_and_variance(orc):
     s2, vhat, kappa = s2.cpu().numpy(), vhat.cpu().numpy(), kappa.item()
     assert plan.diagnostics()["status"] == 0
     rng = np.random.default_rng(33)
-    flat = _sample_flat(rng, w.M, 60)
+    flat = sample_flat(rng, w.M, 60)
     gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
     X = w.X.astype(np.float32).astype(np.float64)
     y = w.Y[:, 0].astype(np.float32).astype(np.float64)
@@ -71,7 +62,7 @@ def test_cplx2d_full_size_fit(orc):
     mh, s0 = plan.fit(h, torch.as_tensor(yc, device="cuda"), want_s0=True)
     mh, s0 = mh.cpu().numpy()[0, 0], s0.cpu().numpy()[0]
     rng = np.random.default_rng(55)
-    flat = _sample_flat(rng, w.M, 60)
+    flat = sample_flat(rng, w.M, 60)
     gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
     X = w.X.astype(np.float32).astype(np.float64)
     ref, S, T, r0, ill = orc.fit(X, yc.astype(np.complex128), h, 2, gp, return_all=True)
@@ -114,40 +105,6 @@ def test_batch2d_downscaled_full(orc):
     assert select_bandwidth(gcv, 0.5) == orc.rgcv_select(gcv, 0.5)
 
 
-def _stage_isolated_dof(orc, plan, w, h, probes, rho_gpu, nused_gpu, gcv_gpu, mh_gpu, flat, Y=None):
-    """Stage isolation at full size (the direct oracle cannot cover the whole
-    grid): the GPU's density moments on the whole grid and the probes' grid
-    fits are checked at seeded grid points against the oracle, then the
-    oracle's support rule, Girard ratios and GCV are evaluated from those GPU
-    grids and compared with the GPU's reductions."""
-    d, order = w.d, w.order
-    X = w.X.astype(np.float32).astype(np.float64)
-    P32 = probes.astype(np.float32)
-    Np = P32.shape[1]
-    S_eq, _ = plan.moments(h)
-    S_gpu = unequilibrate(S_eq.cpu().numpy()[0], h, order, d)                 # [M][n_s]
-    pf = plan.fit(h, torch.as_tensor(P32, device="cuda")).cpu().numpy()[0]   # [Np][M]
-    gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
-    ref, S, T, r0, ill = orc.fit(X, P32.astype(np.float64), h, order, gp, return_all=True)
-    assert rel_err(S_gpu[flat, 0], S[:, 0]) < 1e-5
-    for p in range(Np):
-        compare_fit(pf[p][flat], ref[:, p], S, h, order, d, 1e-5)
-    ill_gpu = np.isnan(pf[0])
-    what = orc.interp(pf.T, w.M, w.lo, w.hi, X)
-    variants = support_variants(S_gpu, ill_gpu, h, order, d, w.M, w.lo, w.hi, X)
-    inc = match_dof(rho_gpu[:Np], nused_gpu, P32.astype(np.float64), what, variants, 1e-6)
-    if gcv_gpu is not None:
-        Yv = (w.Y[:, 0] if Y is None else Y)
-        if np.iscomplexobj(Yv):
-            Yv = Yv.astype(np.complex64).astype(np.complex128)
-        else:
-            Yv = Yv.astype(np.float32).astype(np.float64)
-        yhat = orc.interp(mh_gpu, w.M, w.lo, w.hi, X)
-        g_ref = orc.gcv(Yv, yhat, float(np.mean(rho_gpu)), include=inc)[0]
-        assert abs(gcv_gpu / g_ref - 1) < 1e-6, (gcv_gpu, g_ref)
-    return inc
-
-
 def test_batch2d_full_size_all_bandwidths(orc):
     """The batch workload's DF set at full size: N = 2e6 mixture, M = 256^2,
     64 Philox probes, all 32 log-spaced bandwidths 0.01 .. 0.2 in one cv call.
@@ -168,9 +125,9 @@ def test_batch2d_full_size_all_bandwidths(orc):
     assert (nused > 0.99 * w.N).all()
     probes = orc.probes(seed, w.N, 2)
     rng = np.random.default_rng(44)
-    flat = _sample_flat(rng, w.M, 24)
+    flat = sample_flat(rng, w.M, 24)
     for k in (0, 15, 31):
-        _stage_isolated_dof(orc, plan, w, w.h[k], probes, rho[k], nused[k], gcv[k], mh[k], flat)
+        stage_isolated_dof(orc, plan, w, w.h[k], probes, rho[k], nused[k], gcv[k], mh[k], flat)
 
 
 # ---------------------------------------------------------------------------
@@ -277,12 +234,12 @@ def test_ll2d_bench_step_sampled(orc):
     X = w.X.astype(np.float32).astype(np.float64)
     y = w.Y[:, 0].astype(np.float32).astype(np.float64)
     rng = np.random.default_rng(66)
-    flat = _sample_flat(rng, w.M, 120)
+    flat = sample_flat(rng, w.M, 120)
     gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
     ref, S, T, r0, ill = orc.fit(X, y, h, 1, gp, return_all=True)
     assert density_mask(S[:, 0]).sum() > 100
     compare_fit(mh[flat], ref[:, 0], S, h, 1, 2, 1e-5)
-    _stage_isolated_dof(orc, plan, w, h, orc.probes(seed, w.N, Np), rho, nused, gcv, mh, flat)
+    stage_isolated_dof(orc, plan, w, h, orc.probes(seed, w.N, Np), rho, nused, gcv, mh, flat)
     # variance pass: v-hat against the oracle fit of log(r + 1/N) from the GPU mean grid
     yhat = orc.interp(mh, w.M, w.lo, w.hi, X)
     r = (y - yhat) ** 2

@@ -122,16 +122,22 @@ def _sample_points(rng, M, n, extra):
     return idx
 
 
-@pytest.mark.parametrize("tprec,rho,bar", [("fp64", 1e-3, 1e-5), ("fp32", 1e-1, 1e-5)])
+@pytest.mark.parametrize("tprec,rho,bar", [
+    ("fp64", 1e-3, 1e-5),
+    ("fp32", 1e-1, 1e-5),
+    pytest.param("fp32", 1e-3, 1e-5, marks=pytest.mark.xfail(
+        reason="FP32 transforms miss the 1e-5 bar on the rho = 1e-3 mask (measured 3-5e-5): the FFT "
+               "round-off, global and uncorrelated between the s and t channels, is amplified by about "
+               "1/rho in low-density solves; the library's default for FP32 spreading is FP64 "
+               "transforms", strict=False)),
+])
 def test_fit_ll2d_full_config_sampled(orc, tprec, rho, bar):
     """The 2-D local-linear mixture workload at full size (N = 1e6, M = 256^2,
     FP32 spreading, FP64 3x3 solves) on seeded grid points plus the corners,
     the mixture centres and the edges.  With FP64 transforms the bar 1e-5
-    holds on the density mask rho = 1e-3; with FP32 transforms the FFT
-    round-off (uncorrelated between the s and t channels) is amplified by
-    1/rho in the solve: measured errors are ~1e-6 at rho = 0.1, ~1e-5 at
-    rho = 1e-2 and ~4e-5 at rho = 1e-3, so that mode is held to the bar on
-    rho = 0.1 and its other errors are printed."""
+    holds on the density mask rho = 1e-3.  With FP32 transforms it holds on
+    rho = 0.1 only (errors ~1e-6 at rho = 0.1, ~1e-5 at rho = 1e-2, ~4e-5 at
+    rho = 1e-3); the rho = 1e-3 case is an expected failure."""
     import workloads
     w = workloads.make("ll2d")
     h = w.h[0]
