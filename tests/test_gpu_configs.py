@@ -3,7 +3,6 @@ isolation, where the direct oracle cannot cover the whole grid) and edge
 cases: empty input, ragged grids, samples on the box faces, samples outside
 the box, degenerate designs.
 """
-import itertools
 
 import numpy as np
 import pytest
