@@ -418,17 +418,17 @@ __device__ __forceinline__ int local_cell(const Geo& g, uint32_t l) {
 // (job, cell) order and no job needs another job's counts.  When the records
 // fit the LDS budget they are placed there first and leave as one contiguous
 // run.
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_cell_sort(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
-                                                   int stage, uint32_t* loc, T* frac, int32_t* perm, T* xs) {
-    // [ncell] counts, then cursors; [256] scan scratch; staged records
+template <int D, typename T, int NT>
+__global__ __launch_bounds__(NT) void k_cell_sort(Geo g, const int32_t* jobs, const TileRec<D, T>* trec,
+                                                  int stage, uint32_t* loc, T* frac, int32_t* perm, T* xs) {
+    // [ncell] counts, then cursors; [NT] scan scratch; staged records
     extern __shared__ int32_t cur[];
     const int job = blockIdx.x;
     if (job >= jobs[0]) return;
     const int32_t* jd = jobs + 4 + 4 * job;
     const int s0 = jd[1], s1 = jd[2], n = s1 - s0;
     int32_t* scan = cur + g.ncell;
-    uint32_t* sl_loc = reinterpret_cast<uint32_t*>(scan + 256);
+    uint32_t* sl_loc = reinterpret_cast<uint32_t*>(scan + NT);
     int32_t* sl_perm = reinterpret_cast<int32_t*>(sl_loc + g.chunk);
     T* sl_frac = reinterpret_cast<T*>(sl_perm + g.chunk);
     T* sl_xs = sl_frac + (int64_t)g.chunk * D;
@@ -438,13 +438,13 @@ __global__ __launch_bounds__(256) void k_cell_sort(Geo g, const int32_t* jobs, c
     __syncthreads();
     // exclusive scan of the counts: thread t owns cells [t per, (t + 1) per),
     // block scan of the thread sums
-    const int per = (g.ncell + 255) / 256;
+    const int per = (g.ncell + NT - 1) / NT;
     const int c_beg = min(g.ncell, (int)threadIdx.x * per), c_end = min(g.ncell, c_beg + per);
     int sum = 0;
     for (int c = c_beg; c < c_end; ++c) sum += cur[c];
     scan[threadIdx.x] = sum;
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
+    for (int o = 1; o < NT; o <<= 1) {
         const int v = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
         __syncthreads();
         scan[threadIdx.x] += v;
@@ -2066,12 +2066,19 @@ static void sort_cells_dt(const Geo& g, int x_type, const void* X, int64_t N, in
     const unsigned nb = (unsigned)((N + kSortChunk - 1) / kSortChunk);
     const size_t lds = g.n_tiles <= kLdsHistMax ? (size_t)g.n_tiles * 4 : 0;
     k_scatter_tiles<D, T><<<nb, kSortThreads, lds, s>>>(g, x_type, X, N, tile_off, cursor, bhist, trec);
-    // records staged in LDS when they fit the budget
-    const size_t base_bytes = (size_t)g.ncell * 4 + 256 * 4;
+    // records staged in LDS when they fit the budget (up to the 160 KB a
+    // gfx950 workgroup may hold; 3-D jobs are sized for it); 3-D jobs are
+    // large and sorted by 1024 threads
+    constexpr int NT = D == 3 ? 1024 : 256;
+    const size_t base_bytes = (size_t)g.ncell * 4 + NT * 4;
     const size_t stage_bytes = base_bytes + (size_t)g.chunk * (8 + 2 * D * sizeof(T));
-    const int stage = stage_bytes <= 65536 ? 1 : 0;
-    k_cell_sort<D, T><<<(unsigned)n_jobs_max, 256, stage ? stage_bytes : base_bytes, s>>>(
-        g, jobs, trec, stage, loc, static_cast<T*>(frac), perm, static_cast<T*>(xs));
+    const int stage = stage_bytes <= 160 * 1024 ? 1 : 0;
+    const size_t sort_lds = stage ? stage_bytes : base_bytes;
+    if (sort_lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cell_sort<D, T, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_lds);
+    k_cell_sort<D, T, NT><<<(unsigned)n_jobs_max, NT, sort_lds, s>>>(g, jobs, trec, stage, loc, static_cast<T*>(frac),
+                                                                perm, static_cast<T*>(xs));
 }
 
 size_t tile_record_bytes(int d, int prec) {
@@ -2209,91 +2216,106 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, const float* __restr
     }
 }
 
-// 3-D spread with one sample stream per wave, W = 8.  Lane l owns the (x, y)
-// footprint column (l % 8, l / 8) and keeps, for NC weight columns, the whole
-// z extent of the padded tile (PE = 15 planes) in registers.  Within a job the
-// samples are sorted by first cell with (x, y) major and z minor, so a wave
-// sees long runs (about a hundred samples) of one (x, y) column; a sample adds
-// its eight z planes at register offset z0 (a wave-uniform branch picks the
-// unrolled case per run of equal first cells), and the registers go to the
-// FP64 LDS tile only when the (x, y) column changes.  Per sample and column
-// that is eight FMAs per lane on all 64 lanes.
+// 3-D spread on the matrix cores, W = 8.  Within a job the samples are sorted
+// by first cell with (x, y) major and z minor, so a wave sees long runs (about
+// a hundred samples) of one (x, y) column of first cells, made of runs (about
+// sixteen) of one first cell.  For one column the spread is a contraction over
+// its samples s:
+//
+//   S[(dx, dy), (z, c)] += sum_s psi_x(s, dx) psi_y(s, dy) * psi_z(s, z - z0(s)) w(s, c)
+//
+// a [64 x S] by [S x (15 planes x NC columns)] product with the 64 footprint
+// columns as rows.  It runs as FP32 MFMA 16x16x4 blocks: four row blocks of
+// 16 (dx, dy) and NC column blocks of 16 (16 / NC planes x NC weight
+// columns).  One block step takes up to four samples of one first cell, so
+// the plane offset z0 is uniform over the step: with z0 = ZPB a + b the
+// window z0 .. z0 + 7 meets column blocks a .. a + 8 / ZPB (the last only
+// when b > 0), and the B operand of block a + t is psi_z at offset
+// ZPB t + (plane in block) - b, read from psi_z staged with zeros on both
+// sides.  The accumulators stay in the matrix unit for the whole column and
+// go to the FP64 LDS tile when the (x, y) column changes.
 //
 // A wave takes its samples in batches of kCol3Batch: one lane pair per sample
 // loads the record and weights with vector loads (the next batch is fetched
 // while the current one is spread), evaluates the sample's 24 kernel values
-// (12 per lane) and writes them with the weights to a per-wave LDS row; the
-// spreading loop then reads psi_x(dx) and psi_y(dy) per lane and psi_z and
-// the weights as broadcasts.  A launch spreads np pairs in passes of NC / 2
-// pairs (the LDS tile holds NC columns).
+// (12 per lane) and writes them with the weights to a per-wave LDS row, from
+// which the block operands are read.  A run of one first cell that a batch
+// cuts leaves its last (length mod 4) samples to the next batch, so no step
+// is cut short.  A launch spreads np pairs in passes of NC / 2 pairs (the LDS
+// tile holds NC columns).
 constexpr int kCol3Batch = 32;
-constexpr int kCol3Row = 28;   // floats per staged sample: psi_x[8], psi_y[8], psi_z[8], w[4]
-
+// Staged sample row (floats): psi_x[8], psi_y[8] (permuted), 16 / NC zeros,
+// psi_z[8], 16 / NC zeros, w[4]
 template <int NC>
-__device__ __forceinline__ void col3_flush(float (&acc)[15][NC], double* tile, int cur, int dx, int dy) {
-    constexpr int PE = 15, PSUB = PE * PE * PE;
-    if (cur < 0) return;
-    double* t = tile + (cur & 1023) + dx + PE * (((cur >> 10) & 1023) + dy);
-#pragma unroll
-    for (int z = 0; z < PE; ++z)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            // columns past the pass's count hold zeros and land in tile
-            // columns that are never written out
-            atomicAdd(t + c * PSUB + PE * PE * z, (double)acc[z][c]);
-            acc[z][c] = 0.f;
-        }
-}
+struct Col3Row {
+    static constexpr int PAD = 16 / NC;
+    static constexpr int Z = 16 + PAD;     // psi_z[0]
+    static constexpr int W = Z + 8 + PAD;  // w[0]
+    static constexpr int N = W + 4;
+};
 
-// Staged samples i .. i + U - 1 of the batch (one first cell, plane Z0).
-template <int NC, int Z0, int U>
-__device__ __forceinline__ void col3_samples(float (&acc)[15][NC], const float* stage, int i, int dx, int dy) {
-    float px[U], py[U];
-    float4 z0[U], z1[U], wv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const float* row = stage + (i + u) * kCol3Row;
-        px[u] = row[dx];
-        py[u] = row[8 + dy];
-        z0[u] = *reinterpret_cast<const float4*>(row + 16);
-        z1[u] = *reinterpret_cast<const float4*>(row + 20);
-        wv[u] = *reinterpret_cast<const float4*>(row + 24);
+typedef float col3_v4 __attribute__((ext_vector_type(4)));
+
+// Row offset of kernel value slot s (0..23): psi_x(s) for s < 8; psi_y for
+// s < 16, stored as [dy % 2][dy / 2] so that a lane reads its four row
+// blocks' values with one 16-byte load; psi_z(s - 16) after the zeros.
+__device__ __forceinline__ int col3_slot_offset(int s) {
+    if (s < 8) return s;
+    if (s < 16) {
+        const int t = s - 8;
+        return 2 * (t & 3) + (t >> 2);
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const float pxy = px[u] * py[u];
-        const float wa[4] = {wv[u].x, wv[u].y, wv[u].z, wv[u].w};
-        const float pz[8] = {z0[u].x, z0[u].y, z0[u].z, z0[u].w, z1[u].x, z1[u].y, z1[u].z, z1[u].w};
-        float tc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) tc[c] = pxy * wa[c];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[Z0 + k][c] += tc[c] * pz[k];
-    }
+    return s - 16;
 }
 
 __device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// The run of staged samples from i (of nb) that share the packed first cell
-// `key` (plane Z0), in pairs while the next sample continues it.  Returns
-// the first sample after the run or the batch.
-template <int NC, int Z0>
-__device__ __forceinline__ int col3_run(float (&acc)[15][NC], uint32_t key, int i, int nb, const float* stage,
-                                        uint32_t keys, int dx, int dy) {
-    for (;;) {
-        if (i + 1 < nb && lane_value(keys, i + 1) == key) {
-            col3_samples<NC, Z0, 2>(acc, stage, i, dx, dy);
-            i += 2;
-            if (i >= nb || lane_value(keys, i) != key) return i;
-        } else {
-            col3_samples<NC, Z0, 1>(acc, stage, i, dx, dy);
-            return i + 1;
+// Column blocks a step touches: its window of eight planes starts in block
+// a = z0 / ZPB and reaches block a + 8 / ZPB.
+template <int NC>
+constexpr int col3_blocks() { return 8 / (16 / NC) + 1; }
+
+// Accumulator blocks t = 0 .. NF - 1 of one (x, y) column to the LDS tile:
+// block t holds planes ZPB (base + t) .. ZPB (base + t) + ZPB - 1; in it
+// row block rb, lane l, register r is footprint row 4 (l / 16) + r of the
+// row block, column l % 16 (plane offset (l % 16) / NC, weight (l % 16) % NC).
+template <int NC, int NF>
+__device__ __forceinline__ void col3_flush(col3_v4 (&acc)[col3_blocks<NC>()][4], double* tile, int cur, int base,
+                                           int lane) {
+    constexpr int PE = 15, PSUB = PE * PE * PE, ZPB = 16 / NC;
+    const int q = lane >> 4, j = lane & 15;
+    const int zc = j / NC, c = j % NC;
+    double* t = tile + c * PSUB + (cur & 1023) + 4 * (q & 1) + PE * (((cur >> 10) & 1023) + (q >> 1));
+#pragma unroll
+    for (int tb = 0; tb < NF; ++tb) {
+        const int z = ZPB * (base + tb) + zc;   // planes past 14 only ever hold zeros
+        if (z < PE) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    // columns past the pass's count hold zeros and land in
+                    // tile columns that are never written out
+                    atomicAdd(t + r + PE * (2 * rb) + PE * PE * z, (double)acc[tb][rb][r]);
         }
     }
+}
+
+// Block base to the tile, the others move down one block (a zero block
+// comes in at the top).
+template <int NC>
+__device__ __forceinline__ void col3_flush_first(col3_v4 (&acc)[col3_blocks<NC>()][4], double* tile, int cur,
+                                                 int base, int lane) {
+    constexpr int NB = col3_blocks<NC>();
+    col3_flush<NC, 1>(acc, tile, cur, base, lane);
+#pragma unroll
+    for (int tb = 0; tb + 1 < NB; ++tb)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[tb][rb] = acc[tb + 1][rb];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[NB - 1][rb] = col3_v4{0.f, 0.f, 0.f, 0.f};
 }
 
 template <int KER, int NC, int NT>
@@ -2306,19 +2328,34 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
     constexpr int NWAVE = NT / 64;
     constexpr int PPP = NC / 2;
     constexpr int B = kCol3Batch;
+    constexpr int ZPB = 16 / NC;   // planes per column block
+    constexpr int NB = col3_blocks<NC>();
     static_assert(NC == 2 || NC == 4, "columns per pass");
     // LDS: the tile [NC][PSUB] (cell = x + PE (y + PE z)), then one staging
     // area of B rows per wave
     extern __shared__ double tile[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    float* const stage = reinterpret_cast<float*>(tile + NC * PSUB) + wave * B * kCol3Row;
-    const int dx = lane & 7, dy = lane >> 3;
+    using RW = Col3Row<NC>;
+    float* const stage = reinterpret_cast<float*>(tile + NC * PSUB) + wave * B * RW::N;
+    // block-operand roles: sample k of the step; row i (A) and column j (B)
+    const int k = lane >> 4, ij = lane & 15;
+    const int ax = ij & 7, ah = ij >> 3;      // A row i = (dx, dy) = (i % 8, 2 rb + i / 8)
+    const int bz = ij / NC, bc = ij % NC;     // B column j = (plane ZPB cb + j / NC, weight j % NC)
     // staging role: sample sl of the batch; the low half of the wave takes
-    // kernel values 0..11 of the row, the high half 12..23 and the weights
+    // kernel slots 0..11 of the row, the high half 12..23 and the weights
     const int sl = lane & (B - 1);
     const int hi = lane >> 5;
     const float kp = (float)g.kparam;
+    // the zeros around psi_z are never overwritten
+    for (int r = lane; r < B; r += 64) {
+        float* row = stage + r * RW::N;
+#pragma unroll
+        for (int u = 0; u < RW::PAD; u += 4) {
+            *reinterpret_cast<float4*>(row + RW::Z - RW::PAD + u) = make_float4(0.f, 0.f, 0.f, 0.f);
+            *reinterpret_cast<float4*>(row + RW::Z + 8 + u) = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
     const int njobs = jobs[0];
     for (int b = blockIdx.x; b < njobs; b += gridDim.x) {
         const int job = jobs[4 + 4 * b + 3];
@@ -2330,15 +2367,20 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
             const int nw = 2 * min(PPP, np - p0);   // columns of this pass
             for (int c = threadIdx.x; c < NC * PSUB; c += blockDim.x) tile[c] = 0.0;
             __syncthreads();
-            float acc[PE][NC];
+            // the column's accumulators, blocks base .. base + NB - 1; planes
+            // ascend within a column, so base moves at most once (0 to 1,
+            // after block 0 has gone to the tile)
+            col3_v4 acc[NB][4];
 #pragma unroll
-            for (int z = 0; z < PE; ++z)
+            for (int tb = 0; tb < NB; ++tb)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[z][c] = 0.f;
-            int cur = -1;   // packed (x, y) first cell held in the registers
+                for (int rb = 0; rb < 4; ++rb) acc[tb][rb] = col3_v4{0.f, 0.f, 0.f, 0.f};
+            int cur = -1;   // packed (x, y) first cell held in the accumulators
+            int base = 0;
             const float* wp = wrow + col0 + 2 * p0 + (int64_t)s_beg * wstride;
-            // the batch in registers: sample q0 + bt + sl
-            uint32_t rkey = 0;
+            // the batch in registers: sample q0 + bt + sl; lane 63 also
+            // holds the key of the sample after the batch (or ~0)
+            uint32_t rkey = 0, rnext = ~0u;
             float rf[3] = {0.f, 0.f, 0.f}, rw[4] = {0.f, 0.f, 0.f, 0.f};
             auto fetch = [&](int bt) {
                 const int q = bt + sl;
@@ -2351,46 +2393,94 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
 #pragma unroll
                         for (int c = 0; c < 4; ++c) rw[c] = c < nw ? wp[(int64_t)q * wstride + c] : 0.f;
                 }
+                if (lane == 63) rnext = q + 1 < q1 ? loc[(int64_t)s_beg + q + 1] : ~0u;
             };
             fetch(q0);
-            for (int bt = q0; bt < q1; bt += B) {
+            int ne = 0;
+            for (int bt = q0; bt < q1; bt += ne) {
                 const int nb = min(B, q1 - bt);
-                // kernel values of the staged row: index j = 12 hi + k
-                // (dimension j / 8, offset j % 8), then the weights
+                // kernel values of the staged row (slots 12 hi .. 12 hi + 11),
+                // then the weights
                 {
-                    float* row = stage + sl * kCol3Row + 12 * hi;
+                    float* row = stage + sl * RW::N;
                     float kv[12];
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) {
-                        const int j = 12 * hi + k;
-                        const float f = j < 8 ? rf[0] : (j < 16 ? rf[1] : rf[2]);
-                        kv[k] = kernel_value<float, KER>((float)(j & 7) - f, W, kp);
+                    for (int u = 0; u < 12; ++u) {
+                        const int s = 12 * hi + u;
+                        const float f = s < 8 ? rf[0] : (s < 16 ? rf[1] : rf[2]);
+                        kv[u] = kernel_value<float, KER>((float)col3_slot_offset(s) - f, W, kp);
                     }
+                    if (!hi) {
 #pragma unroll
-                    for (int k = 0; k < 12; k += 4)
-                        *reinterpret_cast<float4*>(row + k) = make_float4(kv[k], kv[k + 1], kv[k + 2], kv[k + 3]);
-                    if (hi) *reinterpret_cast<float4*>(row + 12) = make_float4(rw[0], rw[1], rw[2], rw[3]);
+                        for (int u = 0; u < 12; u += 4)
+                            *reinterpret_cast<float4*>(row + u) = make_float4(kv[u], kv[u + 1], kv[u + 2], kv[u + 3]);
+                    } else {
+                        *reinterpret_cast<float4*>(row + 12) = make_float4(kv[0], kv[1], kv[2], kv[3]);
+                        *reinterpret_cast<float4*>(row + RW::Z) = make_float4(kv[4], kv[5], kv[6], kv[7]);
+                        *reinterpret_cast<float4*>(row + RW::Z + 4) = make_float4(kv[8], kv[9], kv[10], kv[11]);
+                        *reinterpret_cast<float4*>(row + RW::W) = make_float4(rw[0], rw[1], rw[2], rw[3]);
+                    }
                 }
                 const uint32_t keys = rkey;
-                if (bt + B < q1) fetch(bt + B);   // next batch, in flight while this one is spread
-                int i = 0;
-                while (i < nb) {
-                    const uint32_t key = lane_value(keys, i);
-                    const int xy = (int)(key & 0xFFFFFu);
-                    if (xy != cur) {
-                        col3_flush<NC>(acc, tile, cur, dx, dy);
+                // runs of one first cell in the batch: bit l set where sample
+                // l starts one
+                const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute(4 * max(lane - 1, 0), (int)keys);
+                const uint64_t starts = __builtin_amdgcn_ballot_w64(lane < nb && (lane == 0 || keys != prev));
+                // a run that goes on past the batch leaves its last len % 4
+                // samples to the next batch
+                int defer = 0;
+                if (nb == B && lane_value(rnext, 63) == lane_value(keys, B - 1))
+                    defer = (nb - (63 - __builtin_clzll(starts))) & 3;
+                ne = nb - defer;
+                if (bt + ne < q1) fetch(bt + ne);   // next batch, in flight while this one is spread
+                for (int i = 0; i < ne;) {
+                    // one block step: up to four samples of one first cell
+                    const uint32_t key0 = lane_value(keys, i);
+                    const int xy = (int)(key0 & 0xFFFFFu);
+                    const int z0 = (int)(key0 >> 20);
+                    const int za = z0 / ZPB, zb = z0 % ZPB;
+                    if (xy != cur || za != base) {
+                        if (xy != cur) {
+                            if (cur >= 0) col3_flush<NC, NB>(acc, tile, cur, base, lane);
+#pragma unroll
+                            for (int tb = 0; tb < NB; ++tb)
+#pragma unroll
+                                for (int rb = 0; rb < 4; ++rb) acc[tb][rb] = col3_v4{0.f, 0.f, 0.f, 0.f};
+                        } else {
+                            // the column moves on to planes past block base:
+                            // that block is complete
+                            col3_flush_first<NC>(acc, tile, cur, base, lane);
+                        }
                         cur = xy;
+                        base = za;
                     }
-                    switch ((int)((key >> 20) & 1023u)) {
-#define FKR_COL3_CASE(Z) case Z: i = col3_run<NC, Z>(acc, key, i, nb, stage, keys, dx, dy); break;
-                        FKR_COL3_CASE(0) FKR_COL3_CASE(1) FKR_COL3_CASE(2) FKR_COL3_CASE(3)
-                        FKR_COL3_CASE(4) FKR_COL3_CASE(5) FKR_COL3_CASE(6)
-                        default: i = col3_run<NC, 7>(acc, key, i, nb, stage, keys, dx, dy); break;
-#undef FKR_COL3_CASE
+                    const uint64_t later = starts >> (i + 1);   // i < 32
+                    const int run_end = later ? i + 1 + (int)__builtin_ctzll(later) : ne;
+                    const int gsz = min(4, min(ne, run_end) - i);
+                    // lanes past the step's samples read sample i's row (finite)
+                    // and contribute zero A rows
+                    const bool kin = k < gsz;
+                    const float* row = stage + (i + (kin ? k : 0)) * RW::N;
+                    const float px = row[ax];
+                    const float4 py = *reinterpret_cast<const float4*>(row + 8 + 4 * ah);
+                    const float wc = row[RW::W + bc];
+                    const float* pz = row + RW::Z + bz - zb;
+                    const float am = kin ? px : 0.f;
+                    const float a[4] = {am * py.x, am * py.y, am * py.z, am * py.w};
+                    // block base + t: plane offsets ZPB t + plane - zb (zero
+                    // outside the window; zero for the last block when the
+                    // window is block aligned)
+#pragma unroll
+                    for (int tb = 0; tb < NB; ++tb) {
+                        const float bv = pz[ZPB * tb] * wc;
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb)
+                            acc[tb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], bv, acc[tb][rb], 0, 0, 0);
                     }
+                    i += gsz;
                 }
             }
-            col3_flush<NC>(acc, tile, cur, dx, dy);
+            if (cur >= 0) col3_flush<NC, NB>(acc, tile, cur, base, lane);
             __syncthreads();
             // subgrid layout [job][pair][cell][re, im]
             for (int q = 0; 2 * q < nw; ++q) {
@@ -2410,7 +2500,9 @@ static void spread_col3(const Geo& g, const SpreadSrc& src, const uint32_t* loc,
                         const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
     constexpr int PSUB = 15 * 15 * 15;
     constexpr int NT = NC == 2 ? 1024 : 768;
-    const size_t lds = (size_t)NC * PSUB * sizeof(double) + (size_t)(NT / 64) * kCol3Batch * kCol3Row * sizeof(float);
+    constexpr size_t lds =
+        (size_t)NC * PSUB * sizeof(double) + (size_t)(NT / 64) * kCol3Batch * Col3Row<NC>::N * sizeof(float);
+    static_assert(lds <= 160 * 1024, "tile and staging rows exceed the LDS of a workgroup");
     if (lds > 65536)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_col3<KER, NC, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
