@@ -59,6 +59,8 @@ HBM_PEAK_GBS = 8000.0
 # FP32 off); the published 157.3 TFLOP/s counts two FMAs per lane per cycle.
 FP32_FMA_PEAK_TFLOPS = 78.6
 FP32_PUBLISHED_TFLOPS = 157.3
+# dense FP32 MFMA: 256 CUs x 4 SIMDs x 64 flops x 2.4 GHz
+FP32_MFMA_PEAK_TFLOPS = 157.3
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_07716_amd", "csrc", "kernels.hip")
 COUNTERS = {"ll3d": os.path.join(ROOT, "profiles", "k_spread_col3_ll3d_counters.json"),
             "ll2d": os.path.join(ROOT, "profiles", "k_spread_ll2d_counters.json")}
@@ -149,16 +151,17 @@ def _hbm_model(g, d, N, M, n_s, n_t, Np, n_jobs, stages, steps, ms_per_step, cac
             fwd += _pass_bytes(npair, 0 if j == 0 else shape[j], B[j], rows, bt)
             shape[j] = B[j]
         b_fft += fwd
-        # inverse: expand from the pair band, then band -> grid per dimension
+        # inverse: channel spectra from the pair spectra (pair band in,
+        # channel band out), then band -> grid along dimensions d-1 .. 0
         ncp = c["ncp"] - c["keep"]
         shape = list(B)
-        inv = npair * int(np.prod(B)) * bt
-        for j in (range(d) if d != 2 else (1, 0)):
+        inv = (npair + ncp) * int(np.prod(B)) * bt
+        for j in reversed(range(d)):
             rows = 1
             for i in range(d):
                 if i != j:
                     rows *= shape[i]
-            inv += _pass_bytes(ncp, 0 if shape == list(B) else shape[j], Mg[j], rows, bt)
+            inv += _pass_bytes(ncp, shape[j], Mg[j], rows, bt)
             shape[j] = Mg[j]
         b_inv += inv
         b_solve += c["nsol"] * int(np.prod(Mg)) * 8
@@ -327,8 +330,10 @@ def main() -> int:
     value = N * n_fits / (ms_per_step * 1e-3)
 
     # Roofline of the cv spread (the step's largest kernel): 2 w^d flops per
-    # sample and weight column, FP32 FMA issue; HBM view with its algorithmic
-    # bytes N (d b_x + n_w b_w) + n_pair Mr^d b_c.
+    # sample and weight column; the 3-D spread runs on FP32 MFMA (dense peak
+    # 157.3 TFLOP/s), the 2-D one on FP32 FMA issue without packed math
+    # (78.6 TFLOP/s).  HBM view with its algorithmic bytes
+    # N (d b_x + n_w b_w) + n_pair Mr^d b_c.
     Mr = 1
     for j in range(d):
         Mr *= g.Mr[j]
@@ -337,18 +342,23 @@ def main() -> int:
     bytes_ = N * (d * 4 + nw * 4) + ((nw + 1) // 2) * Mr * 8
     launch_s = cv_spread_ms * 1e-3 / max(cv_spread_n, 1)
     achieved = flops / launch_s / 1e12
-    kname = "k_spread_col3 (cv: 12 columns, 3 passes of 4)" if d == 3 else "k_spread_wave (cv: 12 columns)"
-    roofline = {"bound": "alu", "kernel": kname,
-                "achieved": round(achieved, 2), "peak": FP32_FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_FMA_PEAK_TFLOPS, 4),
+    if d == 3:
+        kname, bound, peak = "k_spread_col3 (cv: 12 columns, 3 passes of 4; FP32 MFMA 16x16x4)", "mfma", \
+            FP32_MFMA_PEAK_TFLOPS
+    else:
+        kname, bound, peak = "k_spread_wave (cv: 12 columns; FP32 FMA)", "alu", FP32_FMA_PEAK_TFLOPS
+    roofline = {"bound": bound, "kernel": kname,
+                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
                 "traffic": _traffic(args.workload),
                 "algorithmic_flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": bytes_,
                 "avg_launch_us": round(launch_s * 1e6, 2),
                 "launches_measured": cv_spread_n,
-                "frac_of_published_fp32_157": round(achieved / FP32_PUBLISHED_TFLOPS, 4),
                 "hbm": {"achieved": round(bytes_ / launch_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(bytes_ / launch_s / 1e9 / HBM_PEAK_GBS, 4)}}
+    if d != 3:
+        roofline["frac_of_published_fp32_157"] = round(achieved / FP32_PUBLISHED_TFLOPS, 4)
 
     out, s2, vhat, kappa = res
     cache_resident = args.workload == "ll2d"

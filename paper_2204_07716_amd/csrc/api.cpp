@@ -252,63 +252,35 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         f.skip_flag = skip_flag;
         return f;
     };
-    auto expand = [&](FftPass& f, int64_t rest, int64_t rmul, int64_t emul) {
-        f.exp_mode = 1;
-        f.exp_rest = rest;
-        f.exp_rmul = rmul;
-        f.exp_emul = emul;
-        f.ex = a;
-        f.exp_es = dev_es(p);
-        f.exp_et = dev_et(p);
-        f.exp_spec = p->ws + p->lay.spec;
-    };
-    if (p->d == 2) {
-        // dimension 1 first, so the last pass runs along dimension 0 and
-        // writes every row of the pair-major channels [pair][M^d] as one
-        // contiguous run.  Pass 1: row = (pair, e_0), element e_1, output
-        // [pair][m_1][e_0].  Pass 2: row = (pair, m_1), element e_0.
-        FftPass f1 = pass(1);
-        f1.rows = ncp * p->B[0];
-        f1.skip_rows = c_keep * p->B[0];
-        expand(f1, p->B[0], 1, p->B[0]);
-        f1.out_estride = p->B[0];
-        f1.out_roff = 0;
-        f1.out_rdiv = p->B[0];
-        f1.out_rmul = p->M[1] * p->B[0];
-        void* mid = p->ws + p->lay.fftA;
-        launch_fft(p->tprec, true, f1, nullptr, mid, s);
-        FftPass f0 = pass(0);
-        f0.rows = ncp * p->M[1];
-        f0.skip_rows = c_keep * p->M[1];
-        f0.out_estride = 1;
-        f0.out_roff = 0;
-        f0.out_rdiv = 1;
-        f0.out_rmul = p->M[0];
-        launch_fft(p->tprec, true, f0, mid, chan_out, s);
-    } else {
-        const void* in = nullptr;
-        int64_t done_M = 1;
-        for (int j = 0; j < p->d; ++j) {
-            FftPass f = pass(j);
-            int64_t rest = 1;
-            for (int i = j + 1; i < p->d; ++i) rest *= p->B[i];
-            f.rows = done_M * ncp * rest;
-            f.skip_rows = c_keep * done_M * rest;
-            if (j == 0) expand(f, rest, p->B[0], 1);
-            // row = (pair, m over the done dimensions, e over the rest) with
-            // the pair outermost; the output keeps the pair outermost, so the
-            // last pass writes the channels pair-major, [pair][M^d][re, im]
-            f.out_estride = done_M * rest;
-            f.out_roff = 0;
-            f.out_rdiv = done_M * rest;
-            f.out_rmul = done_M * p->M[j] * rest;
-            void* out;
-            if (j == p->d - 1) out = chan_out;
-            else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);   // fftA first
-            launch_fft(p->tprec, true, f, in, out, s);
-            in = out;
-            done_M *= p->M[j];
-        }
+    // The channel spectra [pair][band index e_0 + B_0 e_1 + ..] first, then
+    // dimensions d-1 .. 0.  Before the pass along dimension j the rows are
+    // (pair, e_{j-1} .. e_0, m_{d-1} .. m_{j+1}) with the pair outermost and
+    // e_0 fastest among the band indices, m_{j+1} fastest among the grid
+    // ones; the pass reads element e_j at row stride R (the other indices'
+    // extent) and writes each row's M_j outputs contiguously, so every pass
+    // stores whole rows and the last one leaves the channels pair-major,
+    // [pair][M^d][re, im] with m_0 fastest.
+    launch_expand(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftB, skip_flag, c_keep, s);
+    const void* in = p->ws + p->lay.fftB;
+    for (int j = p->d - 1; j >= 0; --j) {
+        FftPass f = pass(j);
+        int64_t R = 1;
+        for (int i = 0; i < j; ++i) R *= p->B[i];
+        for (int i = j + 1; i < p->d; ++i) R *= p->M[i];
+        f.rows = ncp * R;
+        f.skip_rows = c_keep * R;
+        f.in_rdiv = R;
+        f.in_rmul = p->B[j] * R;
+        f.in_estride = R;
+        f.out_estride = 1;
+        f.out_roff = 0;
+        f.out_rdiv = 1;
+        f.out_rmul = p->M[j];
+        void* out;
+        if (j == 0) out = chan_out;
+        else out = p->ws + (in == p->ws + p->lay.fftA ? p->lay.fftB : p->lay.fftA);   // fftA first
+        launch_fft(p->tprec, true, f, in, out, s);
+        in = out;
     }
     if (even) launch_chan_tag(diag_ptr(p), h, p->d, s);
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;

@@ -72,6 +72,9 @@ struct FftPass {
     int64_t K;         // band half-width (band input/output modes)
     int64_t out_estride, out_roff;
     int64_t out_rdiv, out_rmul;   // output row map: (r / rdiv) * rmul + r % rdiv
+    // input element e of row r at (r / in_rdiv) in_rmul + r % in_rdiv +
+    // e in_estride (in_rdiv = 0: contiguous rows of n_in)
+    int64_t in_estride, in_rdiv, in_rmul;
     int in_band;       // input row holds modes -K..K (zero-padded to F)
     int out_band;      // output = modes -K..K (else indices 0..n_out-1)
     int nfac;
@@ -86,16 +89,6 @@ struct FftPass {
     int64_t fold_rest;            // Mr_1 Mr_2
     int fold_split;               // two threads per element (set by the launcher)
     FoldArgs fold;
-    // inverse first pass only: the input rows are expanded from the pair
-    // spectra (row = channel pair * rest + band index of dims 1.., element =
-    // band index of dim 0) instead of read
-    int exp_mode;
-    int64_t exp_rest;             // rows per channel pair
-    int64_t exp_rmul, exp_emul;   // band index = (row % exp_rest) exp_rmul + element exp_emul
-    ExpandArgs ex;
-    const int* exp_es;
-    const int* exp_et;
-    const void* exp_spec;
     // rows below skip_rows are neither read nor written when *skip_flag is
     // nonzero (density channel pairs kept from an earlier call)
     const long long* skip_flag;
@@ -171,6 +164,10 @@ void launch_spread(const Geo& g, int prec, int kernel, const SpreadSrc& src, con
                    const void* frac, const int32_t* perm, const int32_t* jobs, int64_t n_jobs_max,
                    void* subgrid, hipStream_t s);
 FoldArgs fold_args(const Geo& g, int npairs, const int32_t* cover, const int32_t* job_off, const void* subgrid);
+// Channel spectra [pair][band index] (pairs c_keep .. when *skip_flag is set,
+// else all ncp) from the pair spectra `spec` (the forward transforms' output).
+void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,
+                   const long long* skip_flag, int64_t c_keep, hipStream_t s);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);

@@ -1106,7 +1106,7 @@ __device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned c
 // k = j mod Ns, and writes b[(j/Ns) Ns RAD + k + q Ns].
 template <typename T, bool INV, int RAD>
 __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typename V2<T>::t* b,
-                                               int F, int Ns, int t, int tpr, const double* tw) {
+                                               int F, int Ns, int t, int tpr, const double2* tw) {
     using C = typename V2<T>::t;
     const int sgn = INV ? 1 : -1;
     const int nb = F / RAD;
@@ -1124,7 +1124,7 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
         if (Ns > 1) {
 #pragma unroll
             for (int q = 1; q < RAD; ++q) {
-                const double2 w = reinterpret_cast<const double2*>(tw)[q * k * tws];
+                const double2 w = tw[q * k * tws];
                 C c;
                 c.x = (T)w.x;
                 c.y = (T)(INV ? -w.y : w.y);
@@ -1171,15 +1171,19 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
     }
 }
 
-// Channel spectrum pair c at band index n (defined with the moment multipliers below).
-template <typename T>
-__device__ __forceinline__ typename V2<T>::t expand_at(const ExpandArgs& a, const int* es, const int* et,
-                                                       const typename V2<T>::t* spec, int c, unsigned n);
+// LDS of a transform workgroup: two buffers of R rows of F elements, then
+// the F twiddles (FP64 pairs, 16-byte aligned).
+__host__ __device__ constexpr size_t fft_twiddle_offset(int R, int F, size_t csz) {
+    return ((size_t)2 * R * F * csz + 15) & ~(size_t)15;
+}
+__host__ __device__ constexpr size_t fft_lds_bytes(int R, int F, size_t csz) {
+    return fft_twiddle_offset(R, F, csz) + (size_t)F * 16;
+}
 
 // ---------------------------------------------------------------------------
 // Stockham FFT along the contiguous axis of `rows` rows, in LDS.
 // ---------------------------------------------------------------------------
-template <typename T, bool INV, int FD = 0, typename TS = float, bool EXP = false>
+template <typename T, bool INV, int FD = 0, typename TS = float>
 __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restrict__ in,
                                               typename V2<T>::t* __restrict__ out, FftPass f) {
     using C = typename V2<T>::t;
@@ -1194,42 +1198,51 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
     const int F = (int)f.F;
     C* buf0 = reinterpret_cast<C*>(smem_raw);
     C* buf1 = buf0 + (int64_t)R * F;
+    // the F twiddles after the two row buffers (read by every stage)
+    double2* twl = reinterpret_cast<double2*>(smem_raw + fft_twiddle_offset(R, F, sizeof(C)));
+    for (int q = threadIdx.x; q < F; q += blockDim.x) twl[q] = reinterpret_cast<const double2*>(f.tw)[q];
     const int tpr = blockDim.x / R;
     const int rl = threadIdx.x / tpr, t = threadIdx.x % tpr;
     const int64_t n_in = f.n_in;
     if (f.in_band) {
         // Modes n = e - K, e < n_in, placed at n mod F; modes that coincide
         // modulo F (band wider than the transform) are summed, which is exact
-        // for the values at the F output points.
+        // for the values at the F output points.  The positions no mode
+        // reaches are zero.
         // (32-bit index arithmetic: a block's rows hold well under 2^31 elements)
         const int kin = (int)(f.K % F), nin = (int)n_in;
-        if (EXP && blockIdx.x == 0 && threadIdx.x == 0 && f.ex.ill_clear) *f.ex.ill_clear = 0ull;
-        for (int q = threadIdx.x; q < nr * F; q += blockDim.x) {
-            const int r = (int)((unsigned)q / (unsigned)F), pos = q - r * F;
+        const int ns = min(nin, F);   // band slots; slot s takes modes s, s + F, ..
+        if (ns < F) {
+            for (int q = threadIdx.x; q < nr * F; q += blockDim.x) {
+                buf0[q].x = 0;
+                buf0[q].y = 0;
+            }
+            __syncthreads();
+        }
+        // strided rows: consecutive threads take consecutive rows (the
+        // loads of one element of neighbouring rows are adjacent)
+        const bool rfast = f.in_rdiv > 0 && f.in_estride != 1;
+        for (int q = threadIdx.x; q < nr * ns; q += blockDim.x) {
+            int r, sl;
+            if (rfast) {
+                sl = (int)((unsigned)q / (unsigned)nr);
+                r = q - sl * nr;
+            } else {
+                r = (int)((unsigned)q / (unsigned)ns);
+                sl = q - r * ns;
+            }
+            int pos = sl - kin;
+            pos = pos < 0 ? pos + F : pos;
             C acc;
             acc.x = 0;
             acc.y = 0;
-            if (row0 + r < skip) {
-                buf0[q] = acc;
-                continue;
+            if (row0 + r >= skip) {
+                const int64_t row = row0 + r;
+                const int64_t rq = row / f.in_rdiv;
+                const C* rowp = in + rq * f.in_rmul + (row - rq * f.in_rdiv);
+                for (int e = sl; e < nin; e += F) acc = cadd(acc, rowp[(int64_t)e * f.in_estride]);
             }
-            int e = pos + kin;
-            e = e >= F ? e - F : e;
-            if constexpr (EXP) {
-                // the channel spectra of the row are expanded here from the
-                // pair spectra: row = pair c * rest + the band indices of the
-                // other dimensions
-                const unsigned row = (unsigned)(row0 + r), rest = (unsigned)f.exp_rest;
-                const int cr = (int)(row / rest), c = f.ex.c0 + cr;
-                const unsigned nb0 = (row - (unsigned)cr * rest) * (unsigned)f.exp_rmul;
-                const unsigned em = (unsigned)f.exp_emul;
-                const C* sp = static_cast<const C*>(f.exp_spec);
-                for (; e < nin; e += F) acc = cadd(acc, expand_at<T>(f.ex, f.exp_es, f.exp_et, sp, c, nb0 + (unsigned)e * em));
-            } else {
-                const C* rowp = in + (row0 + r) * n_in;
-                for (; e < nin; e += F) acc = cadd(acc, rowp[e]);
-            }
-            buf0[q] = acc;
+            buf0[r * F + pos] = acc;
         }
     } else if constexpr (FD > 0) {
         // fold the row from the subgrids (forward first pass, nin = F = Mr_0);
@@ -1260,9 +1273,19 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
         }
     } else {
         const int nin = (int)n_in;
+        const bool rfast = f.in_estride != 1;
         for (int q = threadIdx.x; q < nr * nin; q += blockDim.x) {
-            const int r = (int)((unsigned)q / (unsigned)nin), e = q - r * nin;
-            buf0[r * F + e] = in[(row0 + r) * n_in + e];
+            int r, e;
+            if (rfast) {
+                e = (int)((unsigned)q / (unsigned)nr);
+                r = q - e * nr;
+            } else {
+                r = (int)((unsigned)q / (unsigned)nin);
+                e = q - r * nin;
+            }
+            const int64_t row = row0 + r;
+            const int64_t rq = row / f.in_rdiv;
+            buf0[r * F + e] = in[rq * f.in_rmul + (row - rq * f.in_rdiv) + (int64_t)e * f.in_estride];
         }
     }
     __syncthreads();
@@ -1276,10 +1299,10 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
             const C* a = src + (int64_t)rl * F;
             C* b = dst + (int64_t)rl * F;
             switch (rad) {
-                case 4: stockham_stage<T, INV, 4>(a, b, F, Ns, t, tpr, f.tw); break;
-                case 2: stockham_stage<T, INV, 2>(a, b, F, Ns, t, tpr, f.tw); break;
-                case 3: stockham_stage<T, INV, 3>(a, b, F, Ns, t, tpr, f.tw); break;
-                default: stockham_stage<T, INV, 5>(a, b, F, Ns, t, tpr, f.tw); break;
+                case 4: stockham_stage<T, INV, 4>(a, b, F, Ns, t, tpr, twl); break;
+                case 2: stockham_stage<T, INV, 2>(a, b, F, Ns, t, tpr, twl); break;
+                case 3: stockham_stage<T, INV, 3>(a, b, F, Ns, t, tpr, twl); break;
+                default: stockham_stage<T, INV, 5>(a, b, F, Ns, t, tpr, twl); break;
             }
         }
         __syncthreads();
@@ -1290,8 +1313,18 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
     const int nout = (int)f.n_out;
     const int kout = (int)(f.K % F);
     const unsigned rdiv = (unsigned)f.out_rdiv;
+    // contiguous output rows: consecutive threads take consecutive elements
+    // of a row; strided rows: consecutive rows of one element
+    const bool efast = f.out_estride == 1;
     for (int q = threadIdx.x; q < nout * nr; q += blockDim.x) {
-        const int e = (int)((unsigned)q / (unsigned)nr), r = q - e * nr;
+        int e, r;
+        if (efast) {
+            r = (int)((unsigned)q / (unsigned)nout);
+            e = q - r * nout;
+        } else {
+            e = (int)((unsigned)q / (unsigned)nr);
+            r = q - e * nr;
+        }
         int pos = e;
         if (f.out_band) {
             pos = e - kout;
@@ -1307,74 +1340,121 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Kernel-moment spectra (Hermite form of the Gaussian's moment transforms):
-// per dimension j, He_a(h_j w) exp(-(h_j w)^2/2) / T_j, w = 2 pi (e-K_j)/T_j,
-// evaluated where expand_at needs it.  The phase i^a is applied in expand_at;
-// the division by h^a (equilibration) is implicit in using He_a(h w) without
-// the h^a factor.
+// Channel spectra from the pair spectra (Hermite form of the Gaussian's
+// moment transforms): channel (r, a) at band index n is
+// C_r(n) i^{|a|} prod_j He_{a_j}(u_j) exp(-u_j^2 / 2) / T_j with
+// u_j = h_j 2 pi (e_j - K_j) / T_j; the division by h^a (equilibration) is
+// implicit in using He_a(u) without the h^a factor.  C_r is unpacked from the
+// pair spectra Z_p = C_{2p} + i C_{2p+1}, and channel pair c is
+// X_{2c} + i X_{2c+1}.
 // ---------------------------------------------------------------------------
-// Multiplier of moment degree a at band index e of dimension j (Hermite form
-// of the Gaussian moment kernel's transform, over the period T_j).
-__device__ __forceinline__ double moment_mult(double hj, double Tj, int64_t Kj, int a, int64_t e) {
-    const double om = 2.0 * M_PI * (double)(e - Kj) / Tj;
-    const double u = hj * om;
-    double hm = 1.0, he = u;
-    if (a == 0) he = 1.0;
-    for (int k = 1; k < a; ++k) { const double hn = u * he - k * hm; hm = he; he = hn; }
-    return he * exp(-0.5 * u * u) / Tj;
-}
-
-// Y_c(n) = X_{2c}(n) + i X_{2c+1}(n), X_ch = C_r(n) i^{|a|} prod_j mult_j[a_j](n_j),
-// with C_r unpacked from the pair spectra Z_p = C_{2p} + i C_{2p+1}.
+// One thread per band index n: workgroup row blockIdx.y forms channel pairs
+// blockIdx.y, blockIdx.y + gridDim.y, ..  The thread reads the pair spectra
+// at n and at its mirror once (the pairs of one band index are adjacent) and
+// keeps the unpacked real-weight spectra C_r(n) and its moment multipliers
+// (one exponential per dimension, the degrees by the Hermite recurrence) in
+// LDS (the first kExpandCols real weights; later ones are unpacked from the
+// pair spectra where a channel needs them).
+constexpr int kExpandThreads = 128;
+constexpr int kExpandCols = 16;
+constexpr int kExpandDeg = 5;   // moment degrees per dimension (<= 2 l = 4)
 template <typename T>
-__device__ __forceinline__ typename V2<T>::t expand_at(const ExpandArgs& a, const int* es, const int* et,
-                                                       const typename V2<T>::t* spec, int c, unsigned n) {
-    using C = typename V2<T>::t;
-    int e[3] = {0, 0, 0};
-    unsigned nn = 0, rem = n, stride = 1;
+__global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const int* es, const int* et,
+                                                             const typename V2<T>::t* spec,
+                                                             typename V2<T>::t* out, const long long* skip_flag,
+                                                             int64_t c_keep) {
+    __shared__ double2 cw[kExpandCols][kExpandThreads];
+    __shared__ double mloc[3][kExpandDeg][kExpandThreads];
+    const int tid = threadIdx.x;
+    const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && a.ill_clear) *a.ill_clear = 0ull;
+    if (n >= a.Btot) return;
+    unsigned nn = 0, rem = (unsigned)n, stride = 1;
     for (int j = 0; j < a.d; ++j) {
         const unsigned bj = (unsigned)a.B[j];
         const unsigned qj = rem / bj;
-        e[j] = (int)(rem - qj * bj);
+        const int ej = (int)(rem - qj * bj);
         rem = qj;
-        nn += (bj - 1 - (unsigned)e[j]) * stride;
+        nn += (bj - 1 - (unsigned)ej) * stride;
         stride *= bj;
-    }
-    double acc_re = 0.0, acc_im = 0.0;
-    for (int half = 0; half < 2; ++half) {
-        const int ch = 2 * c + half;
-        if (ch >= a.nreal) break;
-        int r;
-        const int* ex;
-        if (ch < a.n_s) { r = 0; ex = es + 3 * ch; }
-        else { r = 1 + (ch - a.n_s) / a.n_t; ex = et + 3 * ((ch - a.n_s) % a.n_t); }
-        const int p = r >> 1;
-        const C zn = spec[n * a.npairs + p];
-        const C zm = spec[nn * a.npairs + p];
-        double cr, ci;
-        if ((r & 1) == 0) { cr = 0.5 * ((double)zn.x + (double)zm.x); ci = 0.5 * ((double)zn.y - (double)zm.y); }
-        else { cr = 0.5 * ((double)zn.y + (double)zm.y); ci = -0.5 * ((double)zn.x - (double)zm.x); }
-        double m = 1.0;
-        int deg = 0;
-        for (int j = 0; j < a.d; ++j) {
-            m *= moment_mult(a.h[j], a.T[j], a.K[j], ex[j], e[j]);
-            deg += ex[j];
+        // multiplier of degree k: He_k(u) exp(-u^2 / 2) / T_j, u = h_j 2 pi (e_j - K_j) / T_j
+        const double u = a.h[j] * (2.0 * M_PI * (double)(ej - a.K[j]) / a.T[j]);
+        const double gj = exp(-0.5 * u * u) / a.T[j];
+        double hm = 1.0, he = u;
+        mloc[j][0][tid] = gj;
+        mloc[j][1][tid] = u * gj;
+#pragma unroll
+        for (int k = 1; k + 1 < kExpandDeg; ++k) {
+            const double hn = u * he - k * hm;
+            hm = he;
+            he = hn;
+            mloc[j][k + 1][tid] = he * gj;
         }
-        double xr = cr * m, xi = ci * m;
-        switch (deg & 3) {   // multiply by i^deg
-            case 1: { const double t0 = xr; xr = -xi; xi = t0; break; }
-            case 2: xr = -xr; xi = -xi; break;
-            case 3: { const double t0 = xr; xr = xi; xi = -t0; break; }
-            default: break;
-        }
-        if (half == 0) { acc_re += xr; acc_im += xi; }
-        else { acc_re -= xi; acc_im += xr; }   // + i * X
     }
-    C o;
-    o.x = (T)acc_re;
-    o.y = (T)acc_im;
-    return o;
+    // real weight spectra C_r(n), r = 2 p + half, from Z_p(n) and Z_p(-n)
+    const int np_lds = min(a.npairs, kExpandCols / 2);
+    for (int p = 0; p < np_lds; ++p) {
+        const typename V2<T>::t zn = spec[n * a.npairs + p];
+        const typename V2<T>::t zm = spec[(int64_t)nn * a.npairs + p];
+        cw[2 * p][tid] = make_double2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
+        cw[2 * p + 1][tid] = make_double2(0.5 * ((double)zn.y + (double)zm.y), -0.5 * ((double)zn.x - (double)zm.x));
+    }
+    const int c_first = (skip_flag && *skip_flag) ? (int)c_keep : 0;
+    for (int c = (int)blockIdx.y; c < a.ncp; c += (int)gridDim.y) {
+        if (c < c_first) continue;
+        double acc_re = 0.0, acc_im = 0.0;
+        for (int half = 0; half < 2; ++half) {
+            const int ch = 2 * c + half;
+            if (ch >= a.nreal) break;
+            int r;
+            const int* ex;
+            if (ch < a.n_s) { r = 0; ex = es + 3 * ch; }
+            else { r = 1 + (ch - a.n_s) / a.n_t; ex = et + 3 * ((ch - a.n_s) % a.n_t); }
+            double m = 1.0;
+            int deg = 0;
+            for (int j = 0; j < a.d; ++j) {
+                m *= mloc[j][ex[j]][tid];
+                deg += ex[j];
+            }
+            double2 cr;
+            if (r < kExpandCols) {
+                cr = cw[r][tid];
+            } else {
+                const typename V2<T>::t zn = spec[n * a.npairs + (r >> 1)];
+                const typename V2<T>::t zm = spec[(int64_t)nn * a.npairs + (r >> 1)];
+                if ((r & 1) == 0) cr = make_double2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
+                else cr = make_double2(0.5 * ((double)zn.y + (double)zm.y), -0.5 * ((double)zn.x - (double)zm.x));
+            }
+            double xr = cr.x * m, xi = cr.y * m;
+            switch (deg & 3) {   // multiply by i^deg
+                case 1: { const double t0 = xr; xr = -xi; xi = t0; break; }
+                case 2: xr = -xr; xi = -xi; break;
+                case 3: { const double t0 = xr; xr = xi; xi = -t0; break; }
+                default: break;
+            }
+            if (half == 0) { acc_re += xr; acc_im += xi; }
+            else { acc_re -= xi; acc_im += xr; }   // + i * X
+        }
+        typename V2<T>::t o;
+        o.x = (T)acc_re;
+        o.y = (T)acc_im;
+        out[(int64_t)c * a.Btot + n] = o;
+    }
 }
+
+void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,
+                   const long long* skip_flag, int64_t c_keep, hipStream_t s) {
+    // up to four workgroup rows of channel pairs (more waves for few band indices)
+    const dim3 nbn((unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads),
+                   (unsigned)std::min(4, std::max(1, a.ncp)));
+    if (prec == FKR_F64)
+        k_expand_n<double><<<nbn, kExpandThreads, 0, s>>>(a, es, et, static_cast<const double2*>(spec),
+                                                          static_cast<double2*>(out), skip_flag, c_keep);
+    else
+        k_expand_n<float><<<nbn, kExpandThreads, 0, s>>>(a, es, et, static_cast<const float2*>(spec),
+                                                         static_cast<float2*>(out), skip_flag, c_keep);
+}
+
 
 // ---------------------------------------------------------------------------
 // Per-grid-point solve (eq. 3 / 11) in FP64.
@@ -2638,22 +2718,28 @@ FoldArgs fold_args(const Geo& g, int npairs, const int32_t* cover, const int32_t
 
 void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void* out, hipStream_t s) {
     FftPass f = f0;
+    if (f.in_rdiv == 0) {   // contiguous input rows
+        f.in_rdiv = 1;
+        f.in_rmul = f.n_in;
+        f.in_estride = 1;
+    }
     const size_t csz = prec == FKR_F64 ? 16 : 8;
     // rows per workgroup (256 threads share them).  More rows lengthen the
-    // runs of the transposed stores but cost occupancy (two LDS buffers per
+    // runs of the strided loads but cost occupancy (two LDS buffers per
     // row).  Measured: up to 8192 rows (2-D grids) at most two rows per
     // workgroup, with 512 workgroups first; beyond (3-D grids) as many rows
-    // as the LDS holds, with 1024 workgroups first.
+    // as 32 KB of LDS holds (four FP64 rows of 180: 64-byte load runs), with
+    // 1024 workgroups first.
     if (f.fold_d > 0 && !inverse) {
         // rows folded from the subgrids: one element per thread, so each
         // thread runs one fold chain; two rows per workgroup where they fit
         int Rf = 2;
-        while (Rf > 1 && (Rf * f.F > 1024 || (size_t)2 * Rf * f.F * csz > 65536 || f.rows < (int64_t)Rf * 512)) Rf >>= 1;
+        while (Rf > 1 && (Rf * f.F > 1024 || fft_lds_bytes(Rf, (int)f.F, csz) > 65536 || f.rows < (int64_t)Rf * 512)) Rf >>= 1;
         f.rows_per_block = Rf;
         // few rows (one pair): two threads per element halve each fold chain
         f.fold_split = (Rf == 1 && f.rows < 512 && 2 * f.F <= 1024) ? 1 : 0;
         const unsigned ntf = (unsigned)std::min<int64_t>(1024, ((1 + f.fold_split) * Rf * f.F + 63) / 64 * 64);
-        const size_t ldsf = (size_t)2 * Rf * f.F * csz;
+        const size_t ldsf = fft_lds_bytes(Rf, (int)f.F, csz);
         const unsigned nbf = (unsigned)((f.rows + Rf - 1) / Rf);
         if (nbf == 0) return;
 #define FKR_FFTF(T, D, TS) k_fft<T, false, D, TS><<<nbf, ntf, ldsf, s>>>(nullptr, static_cast<typename V2<T>::t*>(out), f)
@@ -2667,27 +2753,12 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
 #undef FKR_FFTF
         return;
     }
-    if (f.exp_mode && inverse) {
-        // first inverse pass with the expansion in its loader: same rows
-        // per workgroup rule as below
-        int R = 2;
-        while (R > 1 && ((size_t)2 * R * f.F * csz > 65536 || f.rows < (int64_t)R * 512)) R >>= 1;
-        f.rows_per_block = R;
-        const size_t ldse = (size_t)2 * R * f.F * csz;
-        const unsigned nbe = (unsigned)((f.rows + R - 1) / R);
-        if (nbe == 0) return;
-        if (prec == FKR_F64)
-            k_fft<double, true, 0, float, true><<<nbe, 256, ldse, s>>>(nullptr, static_cast<double2*>(out), f);
-        else
-            k_fft<float, true, 0, float, true><<<nbe, 256, ldse, s>>>(nullptr, static_cast<float2*>(out), f);
-        return;
-    }
     const bool many = f.rows > 8192;
     int R = many ? 64 : 2;
-    while (R > 1 && (size_t)2 * R * f.F * csz > 65536) R >>= 1;
+    while (R > 1 && fft_lds_bytes(R, (int)f.F, csz) > 32768) R >>= 1;
     while (R > 1 && f.rows < (int64_t)R * (many ? 1024 : 512)) R >>= 1;
     f.rows_per_block = R;
-    const size_t lds = (size_t)2 * R * f.F * csz;
+    const size_t lds = fft_lds_bytes(R, (int)f.F, csz);
     const unsigned nb = (unsigned)((f.rows + R - 1) / R);
     const unsigned nt = 256;
     if (nb == 0) return;

@@ -209,14 +209,14 @@ static void layout(fkr_plan* p) {
         }
         int64_t c = p->ncp_max;
         cap = std::max(cap, c * p->Btot);
-        for (int j = 0; j < p->d; ++j) {
+        // inverse transforms run dimensions d-1 .. 0: after the pass along
+        // dimension j, [pair][B_{j-1} .. B_0][M_{d-1} .. M_j]
+        for (int j = p->d - 1; j >= 0; --j) {
             int64_t e = c;
-            for (int i = 0; i <= j; ++i) e *= p->M[i];
-            for (int i = j + 1; i < p->d; ++i) e *= p->B[i];
+            for (int i = 0; i < j; ++i) e *= p->B[i];
+            for (int i = j; i < p->d; ++i) e *= p->M[i];
             cap = std::max(cap, e);
         }
-        // 2-D inverse transforms run dimension 1 first: [pair][M_1][B_0]
-        if (p->d == 2) cap = std::max(cap, c * p->B[0] * p->M[1]);
     }
     L.cap_fft = cap;
     L.fftA = take(cap * tcsz);
