@@ -96,9 +96,19 @@ def _args():
     return ap.parse_args()
 
 
-def _kernel_hash() -> str:
+# Source region of the cv spread kernel of each workload (its launcher
+# included): the committed counters stay valid while that text is unchanged.
+KERNEL_REGION = {"ll3d": ("// 3-D spread on the matrix cores", "static void spread_wave("),
+                 "ll2d": ("// 2-D spread with one sample stream per wave", "// 3-D spread on the matrix cores")}
+
+
+def _kernel_hash(workload: str) -> str:
     with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        src = f.read().decode()
+    a, b = KERNEL_REGION[workload]
+    i = src.index(a)
+    j = src.index(b, i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
 
 
 def _traffic(workload: str):
@@ -109,10 +119,13 @@ def _traffic(workload: str):
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("kernel_source_sha256") != _kernel_hash():
+    if c.get("kernel_source_sha256") != _kernel_hash(workload):
         return None
-    return (c["fetch_kib_per_launch"] * 1024 * c["copy_fetch_scale"]
-            + c["write_kib_per_launch"] * 1024 * c["copy_write_scale"])
+    try:
+        return (c["fetch_kib_per_launch"] * 1024 * c["copy_fetch_scale"]
+                + c["write_kib_per_launch"] * 1024 * c["copy_write_scale"])
+    except (KeyError, TypeError):
+        return None
 
 
 import numpy as np  # noqa: E402  (host arithmetic of the byte model)
