@@ -307,7 +307,7 @@ typedef enum {
     FKR_STAGE_SORT = 0,      /* set_points: bin, scan, two-level scatter    */
     FKR_STAGE_WEIGHTS = 1,   /* weights gathered into sorted order          */
     FKR_STAGE_SPREAD = 2,    /* spreading onto tile subgrids (eq. 16-17)    */
-    FKR_STAGE_FOLD = 3,      /* kept for numbering: the subgrids are summed into the fine grid by the first forward FFT pass (FKR_STAGE_FFT_FWD) */
+    FKR_STAGE_FOLD = 3,      /* 3-D: the subgrids summed into the fine grid; 1-D and 2-D do this inside the first forward FFT pass (FKR_STAGE_FFT_FWD) */
     FKR_STAGE_FFT_FWD = 4,   /* forward FFT passes + deconvolution (eq. 19-20) */
     FKR_STAGE_EXPAND = 5,    /* kept for numbering: the channel spectra are expanded by the first inverse FFT pass (FKR_STAGE_FFT_INV) */
     FKR_STAGE_FFT_INV = 6,   /* inverse FFT passes + crop (eq. 21)          */

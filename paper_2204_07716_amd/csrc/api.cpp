@@ -158,9 +158,20 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
                           at<int32_t>(p, p->lay.perm), at<int32_t>(p, p->lay.jobs), p->n_jobs_max,
                           p->ws + p->lay.subgrid, s);
         }
-        // the first forward pass folds its rows from the subgrids itself
-        StageTimer tf(p, FKR_STAGE_FFT_FWD, s);
+        // In 1-D and 2-D the first forward pass folds its rows from the
+        // subgrids itself; in 3-D the fold writes the fine grid first, one
+        // workgroup per tile (the subgrids are read once, in runs).
         const void* in = nullptr;
+        const bool grid_fold = p->d == 3;
+        if (grid_fold) {
+            StageTimer tg(p, FKR_STAGE_FOLD, s);
+            launch_fold_grid(p->prec, p->tprec, g,
+                             fold_args(g, gp, at<int32_t>(p, p->lay.cover), at<int32_t>(p, p->lay.job_off),
+                                       p->ws + p->lay.subgrid),
+                             gp, p->ws + p->lay.fftB, s);
+            in = p->ws + p->lay.fftB;
+        }
+        StageTimer tf(p, FKR_STAGE_FFT_FWD, s);
         int64_t done_B = 1;
         for (int j = 0; j < p->d; ++j) {
             FftPass f{};
@@ -173,7 +184,7 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
             f.K = p->K[j];
             f.in_band = 0;
             f.out_band = 1;
-            if (j == 0) {
+            if (j == 0 && !grid_fold) {
                 f.fold_d = p->d;
                 f.fold_f64 = p->prec == FKR_F64 ? 1 : 0;
                 f.fold_rest = rest;

@@ -168,6 +168,9 @@ FoldArgs fold_args(const Geo& g, int npairs, const int32_t* cover, const int32_t
 // else all ncp) from the pair spectra `spec` (the forward transforms' output).
 void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,
                    const long long* skip_flag, int64_t c_keep, hipStream_t s);
+// 3-D: the fine grid [pair][Mr^d] (transform precision) of the launch's
+// pairs folded from the subgrids; the first forward pass then reads its rows.
+void launch_fold_grid(int prec, int tprec, const Geo& g, const FoldArgs& fa, int npairs, void* grid, hipStream_t s);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);

@@ -1101,6 +1101,44 @@ __device__ __forceinline__ double2 fold_at(const FoldArgs& fa, int p, unsigned c
     return make_double2(re, im);
 }
 
+// The fine grid [pair][Mr^d] of the launch's pairs, one workgroup per
+// (spreading tile, pair): thread = fine cell of the tile's interior (x
+// fastest), its value the fold of the covering padded tiles' subgrids (the
+// same sum as fold_at, in the same order).  The workgroup's cells share
+// their covering tiles, so the cover and job lookups hit the caches and the
+// subgrid reads of a wave are runs of consecutive cells.
+template <int D, typename TS, typename T>
+__global__ __launch_bounds__(512) void k_fold_grid(FoldArgs fa, int64_t nt0, int64_t nt1, int64_t ts0, int64_t ts1,
+                                                   int64_t ts2, int64_t Mrtot, typename V2<T>::t* grid) {
+    const int64_t b = blockIdx.x;
+    const int p = blockIdx.y;
+    const int64_t b0 = b % nt0, b1 = (b / nt0) % nt1, b2 = b / (nt0 * nt1);
+    const int tid = threadIdx.x;
+    const int lx = (int)(tid % ts0), ly = (int)((tid / ts0) % ts1), lz = (int)(tid / (ts0 * ts1));
+    if (lz >= ts2) return;
+    const int64_t c0 = b0 * ts0 + lx, c1 = b1 * ts1 + ly, c2 = b2 * ts2 + lz;
+    if (c0 >= fa.Mr[0] || c1 >= fa.Mr[1] || c2 >= fa.Mr[2]) return;
+    const int64_t cell = c0 + fa.Mr[0] * (c1 + fa.Mr[1] * c2);
+    const double2 v = fold_at<D, TS>(fa, p, (unsigned)cell);
+    typename V2<T>::t o;
+    o.x = (T)v.x;
+    o.y = (T)v.y;
+    grid[(int64_t)p * Mrtot + cell] = o;
+}
+
+void launch_fold_grid(int prec, int tprec, const Geo& g, const FoldArgs& fa, int npairs, void* grid, hipStream_t s) {
+    const dim3 nb((unsigned)g.n_tiles, (unsigned)npairs);
+    const unsigned nt = (unsigned)(g.ts[0] * g.ts[1] * g.ts[2]);
+#define FKR_FOLDG(TS, T) k_fold_grid<3, TS, T><<<nb, nt, 0, s>>>(fa, g.nt[0], g.nt[1], g.ts[0], g.ts[1], g.ts[2], \
+                                                                 g.Mrtot, static_cast<typename V2<T>::t*>(grid))
+    if (tprec == FKR_F64) {
+        if (prec == FKR_F64) FKR_FOLDG(double, double); else FKR_FOLDG(float, double);
+    } else {
+        FKR_FOLDG(float, float);
+    }
+#undef FKR_FOLDG
+}
+
 // One radix-RAD Stockham stage (Govindaraju et al., SC'08 formulation):
 // butterfly j reads a[j + q F/RAD], twiddles by W_F^(q k F/(Ns RAD)) with
 // k = j mod Ns, and writes b[(j/Ns) Ns RAD + k + q Ns].
@@ -1168,6 +1206,72 @@ __device__ __forceinline__ void stockham_stage(const typename V2<T>::t* a, typen
         const int base = jq * Ns * RAD + k;
 #pragma unroll
         for (int q = 0; q < RAD; ++q) b[base + q * Ns] = y[q];
+    }
+}
+
+// The Stockham stages of a workgroup's nr rows (R rows of F elements in
+// buf0, the other buffer as scratch); returns the buffer holding the result.
+template <typename T, bool INV>
+__device__ __forceinline__ const typename V2<T>::t* fft_stages(typename V2<T>::t* buf0, typename V2<T>::t* buf1,
+                                                               const FftPass& f, int nr, int tpr, int rl, int t,
+                                                               const double2* twl) {
+    using C = typename V2<T>::t;
+    const int F = (int)f.F;
+    C* src = buf0;
+    C* dst = buf1;
+    int Ns = 1;
+    for (int s = 0; s < f.nfac; ++s) {
+        const int rad = f.fac[s];
+        if (rl < nr) {
+            const C* a = src + (int64_t)rl * F;
+            C* b = dst + (int64_t)rl * F;
+            switch (rad) {
+                case 4: stockham_stage<T, INV, 4>(a, b, F, Ns, t, tpr, twl); break;
+                case 2: stockham_stage<T, INV, 2>(a, b, F, Ns, t, tpr, twl); break;
+                case 3: stockham_stage<T, INV, 3>(a, b, F, Ns, t, tpr, twl); break;
+                default: stockham_stage<T, INV, 5>(a, b, F, Ns, t, tpr, twl); break;
+            }
+        }
+        __syncthreads();
+        C* tmp = src; src = dst; dst = tmp;
+        Ns *= rad;
+    }
+    return src;
+}
+
+// Store the transformed rows row0 .. row0 + nr - 1 (outputs 0 .. n_out - 1,
+// or the band modes) through the output row map; rows below `skip` are kept.
+template <typename T>
+__device__ __forceinline__ void fft_store(const typename V2<T>::t* src, typename V2<T>::t* out, const FftPass& f,
+                                          int64_t row0, int nr, int64_t skip) {
+    using C = typename V2<T>::t;
+    const int F = (int)f.F;
+    const int nout = (int)f.n_out;
+    const int kout = (int)(f.K % F);
+    const unsigned rdiv = (unsigned)f.out_rdiv;
+    // contiguous output rows: consecutive threads take consecutive elements
+    // of a row; strided rows: consecutive rows of one element
+    const bool efast = f.out_estride == 1;
+    for (int q = threadIdx.x; q < nout * nr; q += blockDim.x) {
+        int e, r;
+        if (efast) {
+            r = (int)((unsigned)q / (unsigned)nout);
+            e = q - r * nout;
+        } else {
+            e = (int)((unsigned)q / (unsigned)nr);
+            r = q - e * nr;
+        }
+        int pos = e;
+        if (f.out_band) {
+            pos = e - kout;
+            pos = pos < 0 ? pos + F : pos;
+        }
+        if (row0 + r < skip) continue;
+        C v = src[r * F + pos];
+        if (f.fac_out) v = cscale(v, (T)f.fac_out[e]);
+        const unsigned row = (unsigned)(row0 + r);
+        const unsigned rq = row / rdiv;
+        out[(int64_t)e * f.out_estride + f.out_roff + (int64_t)rq * f.out_rmul + (row - rq * rdiv)] = v;
     }
 }
 
@@ -1290,53 +1394,8 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
     }
     __syncthreads();
 
-    C* src = buf0;
-    C* dst = buf1;
-    int Ns = 1;
-    for (int s = 0; s < f.nfac; ++s) {
-        const int rad = f.fac[s];
-        if (rl < nr) {
-            const C* a = src + (int64_t)rl * F;
-            C* b = dst + (int64_t)rl * F;
-            switch (rad) {
-                case 4: stockham_stage<T, INV, 4>(a, b, F, Ns, t, tpr, twl); break;
-                case 2: stockham_stage<T, INV, 2>(a, b, F, Ns, t, tpr, twl); break;
-                case 3: stockham_stage<T, INV, 3>(a, b, F, Ns, t, tpr, twl); break;
-                default: stockham_stage<T, INV, 5>(a, b, F, Ns, t, tpr, twl); break;
-            }
-        }
-        __syncthreads();
-        C* tmp = src; src = dst; dst = tmp;
-        Ns *= rad;
-    }
-
-    const int nout = (int)f.n_out;
-    const int kout = (int)(f.K % F);
-    const unsigned rdiv = (unsigned)f.out_rdiv;
-    // contiguous output rows: consecutive threads take consecutive elements
-    // of a row; strided rows: consecutive rows of one element
-    const bool efast = f.out_estride == 1;
-    for (int q = threadIdx.x; q < nout * nr; q += blockDim.x) {
-        int e, r;
-        if (efast) {
-            r = (int)((unsigned)q / (unsigned)nout);
-            e = q - r * nout;
-        } else {
-            e = (int)((unsigned)q / (unsigned)nr);
-            r = q - e * nr;
-        }
-        int pos = e;
-        if (f.out_band) {
-            pos = e - kout;
-            pos = pos < 0 ? pos + F : pos;
-        }
-        if (row0 + r < skip) continue;
-        C v = src[r * F + pos];
-        if (f.fac_out) v = cscale(v, (T)f.fac_out[e]);
-        const unsigned row = (unsigned)(row0 + r);
-        const unsigned rq = row / rdiv;
-        out[(int64_t)e * f.out_estride + f.out_roff + (int64_t)rq * f.out_rmul + (row - rq * rdiv)] = v;
-    }
+    const C* src = fft_stages<T, INV>(buf0, buf1, f, nr, tpr, rl, t, twl);
+    fft_store<T>(src, out, f, row0, nr, skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -2772,10 +2831,14 @@ void launch_fft(int prec, bool inverse, const FftPass& f0, const void* in, void*
 }
 
 void launch_solve2(int prec, const SolveArgs& a0, const int* pidx, const void* chan, hipStream_t s) {
-    // three weight vectors per thread: more threads per grid point for
-    // calls with many weights (the grid alone gives few waves per CU)
+    // Weight vectors per thread.  Small grids (2-D): three, so a call with
+    // many weights runs several threads per grid point (the grid alone gives
+    // few waves per CU).  Grids of a million points or more (3-D) have the
+    // waves: up to 16 per thread, each factoring its point's matrix and
+    // reading the density channels once for all of them (measured at
+    // M = 128^3 with 11 weights: 0.51 ms with three, 0.34 ms with all).
     SolveArgs a = a0;
-    a.wpg = 3;
+    a.wpg = a.Mtot >= (int64_t)1 << 20 ? std::min(16, std::max(1, a.nr - 1)) : 3;
     const unsigned ng = (unsigned)std::max(1, (a.nr - 1 + a.wpg - 1) / a.wpg);
     const dim3 nb(nblk(a.Mtot), ng);
 #define FKR_SOLVE(P, T) k_solve<P, T><<<nb, 256, 0, s>>>(a, pidx, static_cast<const T*>(chan))

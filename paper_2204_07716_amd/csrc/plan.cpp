@@ -201,6 +201,7 @@ static void layout(fkr_plan* p) {
     int64_t cap = 0;
     {
         int64_t g = p->pairs_per_spread;
+        if (p->d == 3) cap = std::max(cap, g * p->Mr[0] * p->Mr[1] * p->Mr[2]);   // the folded fine grid
         for (int j = 0; j < p->d; ++j) {
             int64_t e = g;
             for (int i = 0; i <= j; ++i) e *= p->B[i];
