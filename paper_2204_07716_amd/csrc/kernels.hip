@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <vector>
 
 #include <algorithm>
 #include <cmath>
@@ -1700,6 +1701,9 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
     const TW* wrow = static_cast<const TW*>(a.wsorted);
     const int cpl = a.y_cplx ? 2 : 1;
     const int pcol = 1 + a.ny_cols * cpl + a.p0;
+    // FP32 rows [1, y, probes of this launch ..] that 16-byte loads can take whole
+    constexpr int NQ = (2 + PC + 3) / 4;
+    const bool vec_row = YR && sizeof(TW) == 4 && pcol == 2 && (a.wstride % 4) == 0 && a.wstride >= 4 * NQ;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N;
          s += (int64_t)gridDim.x * blockDim.x) {
         const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
@@ -1729,6 +1733,25 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
             // whatever the corner's weight) is left out of every sum
             if (isnan(fa[0])) continue;
             an += 1.0;
+            if (vec_row) {
+                // the staged row [1, y, probes ..] in 16-byte loads (probe
+                // slots past the launch's count feed sums never written out)
+                float rv[4 * NQ];
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) {
+                    const float4 v4 = reinterpret_cast<const float4*>(row)[k];
+                    rv[4 * k] = v4.x; rv[4 * k + 1] = v4.y; rv[4 * k + 2] = v4.z; rv[4 * k + 3] = v4.w;
+                }
+                const double e0 = (double)rv[1] - fa[0];
+                ay[0] += e0 * e0;
+#pragma unroll
+                for (int j = 0; j < PC; ++j) {
+                    const double wv = (double)rv[2 + j];
+                    aw[j] += wv * wv;
+                    ah[j] += wv * fa[1 + j];
+                }
+                continue;
+            }
             const double e0 = (double)row[1] - fa[0];
             ay[0] += e0 * e0;
 #pragma unroll
@@ -1848,7 +1871,13 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
             const int j = (q - YC) >> 1;
             if (j < a.np_launch) slot = 2 * (a.ny_cols + a.p0 + j) + ((q - YC) & 1);
         }
-        if (slot >= 0) a.partial[(int64_t)slot * kRedBlocks + blockIdx.x] = v;
+        if (slot >= 0) {
+            a.partial[(int64_t)slot * kRedBlocks + blockIdx.x] = v;
+            // a launch of fewer than kRedBlocks workgroups: the slots no
+            // workgroup owns hold zeros
+            for (int b = blockIdx.x + gridDim.x; b < kRedBlocks; b += gridDim.x)
+                a.partial[(int64_t)slot * kRedBlocks + b] = 0.0;
+        }
     }
 }
 
@@ -2383,6 +2412,11 @@ __global__ __launch_bounds__(512) void k_spread_wave(Geo g, const float* __restr
 // is cut short.  A launch spreads np pairs in passes of NC / 2 pairs (the LDS
 // tile holds NC columns).
 constexpr int kCol3Batch = 32;
+// Doubles per weight column of the LDS tile: the 15^3 cells and 9 of padding,
+// which puts the columns 8 bank pairs apart (3384 = 24 mod 32) so that the
+// FP64 atomic adds of a flush spread over the banks (3375: 3.91 ms for the
+// step's two 3-D spread launches; 3384: 3.53 ms; 3392: 3.97 ms).
+constexpr int kCol3TileStride = 15 * 15 * 15 + 9;
 // Staged sample row (floats): psi_x[8], psi_y[8] (permuted), 16 / NC zeros,
 // psi_z[8], 16 / NC zeros, w[4]
 template <int NC>
@@ -2423,7 +2457,7 @@ constexpr int col3_blocks() { return 8 / (16 / NC) + 1; }
 template <int NC, int NF>
 __device__ __forceinline__ void col3_flush(col3_v4 (&acc)[col3_blocks<NC>()][4], double* tile, int cur, int base,
                                            int lane) {
-    constexpr int PE = 15, PSUB = PE * PE * PE, ZPB = 16 / NC;
+    constexpr int PE = 15, PSUB = kCol3TileStride, ZPB = 16 / NC;
     const int q = lane >> 4, j = lane & 15;
     const int zc = j / NC, c = j % NC;
     double* t = tile + c * PSUB + (cur & 1023) + 4 * (q & 1) + PE * (((cur >> 10) & 1023) + (q >> 1));
@@ -2463,7 +2497,7 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
                                                     const float* __restrict__ frac,
                                                     const int32_t* __restrict__ jobs,
                                                     float* __restrict__ subgrid) {
-    constexpr int W = 8, PE = 15, PSUB = PE * PE * PE;
+    constexpr int W = 8, PE = 15, PSUB = kCol3TileStride, NCELL = PE * PE * PE;
     constexpr int NWAVE = NT / 64;
     constexpr int PPP = NC / 2;
     constexpr int B = kCol3Batch;
@@ -2623,8 +2657,8 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
             __syncthreads();
             // subgrid layout [job][pair][cell][re, im]
             for (int q = 0; 2 * q < nw; ++q) {
-                float* dst = subgrid + ((int64_t)job * np + p0 + q) * PSUB * 2;
-                for (int c = threadIdx.x; c < PSUB; c += blockDim.x) {
+                float* dst = subgrid + ((int64_t)job * np + p0 + q) * NCELL * 2;
+                for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
                     dst[2 * c] = (float)tile[2 * q * PSUB + c];
                     dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
                 }
@@ -2637,7 +2671,7 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
 template <int KER, int NC>
 static void spread_col3(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
                         const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
-    constexpr int PSUB = 15 * 15 * 15;
+    constexpr int PSUB = kCol3TileStride;
     constexpr int NT = NC == 2 ? 1024 : 768;
     constexpr size_t lds =
         (size_t)NC * PSUB * sizeof(double) + (size_t)(NT / 64) * kCol3Batch * Col3Row<NC>::N * sizeof(float);
@@ -2870,9 +2904,29 @@ void launch_chan_out(int prec, int64_t Mtot, int ncp, int n_s, int n_t, int nw, 
         k_chan_out<float><<<nblk(n), 256, 0, s>>>(Mtot, ncp, n_s, n_t, nw, static_cast<const float*>(chan), S, T);
 }
 
+// Workgroups of a reduction launch: at most kRedBlocks, and no more than the
+// device holds at once (a second, partly filled round of a register-heavy
+// reduction would leave most CUs idle).
+template <typename K>
+static unsigned red_blocks(K kernel) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, unsigned>> cache;   // per kernel (devices of one kind)
+    std::lock_guard<std::mutex> lock(mu);
+    const void* key = reinterpret_cast<const void*>(kernel);
+    for (const auto& e : cache)
+        if (e.first == key) return e.second;
+    int per_cu = 0, dev = 0, ncu = 0;
+    unsigned nb = kRedBlocks;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, key, 256, 0) == hipSuccess && per_cu > 0 && ncu > 0)
+        nb = (unsigned)std::min<int64_t>(kRedBlocks, (int64_t)per_cu * ncu);
+    cache.emplace_back(key, nb);
+    return nb;
+}
+
 template <int PC>
 static void reduce_cv_pc(const Geo& g, const ReduceCvArgs& a, hipStream_t s) {
-#define FKR_RCV(D, TW, YR) k_reduce_cv<D, TW, PC, YR><<<kRedBlocks, 256, 0, s>>>(g, a)
+#define FKR_RCV(D, TW, YR) k_reduce_cv<D, TW, PC, YR><<<red_blocks(&k_reduce_cv<D, TW, PC, YR>), 256, 0, s>>>(g, a)
     if (a.w_type == FKR_F64) {
         if (g.d == 1) FKR_RCV(1, double, false); else if (g.d == 2) FKR_RCV(2, double, false); else FKR_RCV(3, double, false);
     } else if (a.yrow) {
