@@ -109,12 +109,18 @@ unsigned long long* ill_ctr(fkr_plan* p) { return at<unsigned long long>(p, p->l
 long long* diag_ptr(fkr_plan* p) { return at<long long>(p, p->lay.diag); }
 PointsCheck points_check(fkr_plan* p) { return PointsCheck{p->N, p->epoch, diag_ptr(p)}; }
 
+// The staged weights are grouped by four columns, [group][N][4], where the
+// 3-D FP32 w = 8 spread reads them: each of its passes takes one group, so it
+// streams exactly the 16 bytes per sample it uses.  Elsewhere they are rows.
+bool grouped_weights(const fkr_plan* p) { return p->d == 3 && p->prec == FKR_F32 && p->w == 8; }
+
 // Every weight vector of a call, constants included, gathered once into
-// sorted sample order: rows of `stride` = nr rounded up to 4 columns (the
-// spread loads a row with 16-byte loads; padding columns are zero).
+// sorted sample order: `stride` = nr rounded up to 4 columns (16-byte loads;
+// padding columns are zero), as rows [N][stride] or as column groups.
 std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipStream_t s) {
     const int nr = (int)srcs.size();
     const int stride = (nr + 3) & ~3;
+    const int64_t gstride = grouped_weights(p) ? 4 * p->N : 0;
     std::vector<WSrc> all(srcs);
     all.resize(stride, src_zero());
     void* buf = p->ws + p->lay.wsort;
@@ -123,12 +129,14 @@ std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipS
         const int n = std::min(2 * kMaxPairsPerSpread, stride - r0);
         for (int q = 0; q < n; ++q) chunk.w[q] = all[r0 + q];
         StageTimer t(p, FKR_STAGE_WEIGHTS, s);
-        launch_stage_weights(p->prec, chunk, n, r0, stride, points_check(p), at<int32_t>(p, p->lay.perm), buf, s);
+        launch_stage_weights(p->prec, chunk, n, r0, stride, gstride, points_check(p), at<int32_t>(p, p->lay.perm),
+                             buf, s);
     }
     std::vector<WSrc> out(stride);
     for (int r = 0; r < stride; ++r) {
         WSrc w{};
-        w.kind = W_SORTED; w.type = p->prec; w.ptr = buf; w.stride = stride; w.col = r;
+        w.kind = W_SORTED; w.type = p->prec; w.ptr = buf; w.stride = gstride ? 4 : stride; w.col = r;
+        w.gstride = gstride;
         out[r] = w;
     }
     return out;
@@ -404,7 +412,9 @@ fkr_status cv_impl(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
         }
         ReduceCvArgs r{};
         r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
-        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec; r.wstride = (nr + 3) & ~3;
+        r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec;
+        r.wgstride = grouped_weights(p) ? 4 * p->N : 0;
+        r.wstride = r.wgstride ? 4 : (nr + 3) & ~3;
         r.ny_cols = q; r.y_cplx = y_complex; r.yfit = yfit;
         r.np = Ns; r.pfit = pfit; r.pstride = pstride; r.yrow = yrow ? 1 : 0;
         r.sup = sup;

@@ -37,6 +37,9 @@ struct WSrc {
     int64_t col;       // element offset of this vector
     uint64_t seed;
     int probe;         // probe index (Philox)
+    // W_SORTED: 0 for rows (column c of sample s at s stride + c); else the
+    // columns in groups of four, [group][sample][4]: (c / 4) gstride + s stride + c % 4
+    int64_t gstride;
 };
 
 struct SpreadSrc {
@@ -118,8 +121,9 @@ struct ReduceCvArgs {
     int64_t N;
     int x_type;                   // element type of the sorted coordinates
     const void* X;                // sorted coordinates [N][d]
-    const void* wsorted;          // staged rows [N][wstride]: 1, y parts, probes
+    const void* wsorted;          // staged weights: 1, y parts, probes (layout of WSrc W_SORTED)
     int w_type, wstride;
+    int64_t wgstride;             // 0: rows [N][wstride]; else [group of 4][N][4], groups wgstride apart
     int ny_cols, y_cplx;          // response columns (complex: re, im parts)
     const double* yfit;           // [q][M] or [q][M][2]
     int np;                       // probes
@@ -206,7 +210,9 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;
 constexpr int kMaxDevices = 64;
 hipError_t static_scratch(void** ptr);
-void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, const PointsCheck& pc,
+// gstride 0: rows [N][nr]; else columns in groups of four, [group][N][4] with
+// groups gstride elements apart (FP32 only).
+void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t gstride, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);
 void launch_chan_reuse(long long* diag, const double* h, int d, hipStream_t s);

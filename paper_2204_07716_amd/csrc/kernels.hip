@@ -527,7 +527,10 @@ __device__ __forceinline__ double wval_mem(const WSrc& s, int64_t sp, int64_t i)
     switch (s.kind) {
         case W_ONE: return 1.0;
         case W_ARRAY: return load_as_double(s.ptr, s.type, i * s.stride + s.col);
-        case W_SORTED: return load_as_double(s.ptr, s.type, sp * s.stride + s.col);
+        case W_SORTED:
+            return load_as_double(s.ptr, s.type,
+                                  s.gstride ? (s.col >> 2) * s.gstride + sp * s.stride + (s.col & 3)
+                                            : sp * s.stride + s.col);
         default: return 0.0;
     }
 }
@@ -1703,11 +1706,16 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
     const int pcol = 1 + a.ny_cols * cpl + a.p0;
     // FP32 rows [1, y, probes of this launch ..] that 16-byte loads can take whole
     constexpr int NQ = (2 + PC + 3) / 4;
-    const bool vec_row = YR && sizeof(TW) == 4 && pcol == 2 && (a.wstride % 4) == 0 && a.wstride >= 4 * NQ;
+    const bool vec_row = YR && sizeof(TW) == 4 && pcol == 2 &&
+                         (a.wgstride ? true : ((a.wstride % 4) == 0 && a.wstride >= 4 * NQ));
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N;
          s += (int64_t)gridDim.x * blockDim.x) {
         const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
         const TW* row = wrow + s * a.wstride;
+        // column k of the sample's staged weights (rows or column groups)
+        auto wcol = [&](int k) -> double {
+            return (double)(a.wgstride ? wrow[(k >> 2) * a.wgstride + s * 4 + (k & 3)] : row[k]);
+        };
         if constexpr (YR) {
             // FP32 rows [y | probes | pad] of 16-byte loads: the fit of the one
             // real response comes with the probe fits (all probes in this launch)
@@ -1739,7 +1747,8 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
                 float rv[4 * NQ];
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) {
-                    const float4 v4 = reinterpret_cast<const float4*>(row)[k];
+                    const float4 v4 = *reinterpret_cast<const float4*>(a.wgstride ? wrow + k * a.wgstride + s * 4
+                                                                                  : row + 4 * k);
                     rv[4 * k] = v4.x; rv[4 * k + 1] = v4.y; rv[4 * k + 2] = v4.z; rv[4 * k + 3] = v4.w;
                 }
                 const double e0 = (double)rv[1] - fa[0];
@@ -1752,11 +1761,11 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
                 }
                 continue;
             }
-            const double e0 = (double)row[1] - fa[0];
+            const double e0 = wcol(1) - fa[0];
             ay[0] += e0 * e0;
 #pragma unroll
             for (int j = 0; j < PC; ++j) {
-                const double wv = (double)row[pcol + min(j, a.np_launch - 1)];
+                const double wv = wcol(pcol + min(j, a.np_launch - 1));
                 aw[j] += wv * wv;
                 ah[j] += wv * fa[1 + j];
             }
@@ -1781,14 +1790,14 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
                     fr += c.w[q] * gv[2 * c.idx[q]];
                     fi += c.w[q] * gv[2 * c.idx[q] + 1];
                 }
-                const double er = (double)row[1 + 2 * col] - fr, ei = (double)row[2 + 2 * col] - fi;
+                const double er = wcol(1 + 2 * col) - fr, ei = wcol(2 + 2 * col) - fi;
                 ay[j] += er * er + ei * ei;
             } else {
                 const double* gv = a.yfit + (int64_t)col * g.Mtot;
                 double f = 0.0;
 #pragma unroll
                 for (int q = 0; q < (1 << D); ++q) f += c.w[q] * gv[c.idx[q]];
-                const double e = (double)row[1 + col] - f;
+                const double e = wcol(1 + col) - f;
                 ay[j] += e * e;
             }
         }
@@ -1838,7 +1847,7 @@ __global__ __launch_bounds__(256) void k_reduce_cv(Geo g, ReduceCvArgs a) {
             }
 #pragma unroll
             for (int j = 0; j < PC; ++j) {
-                const double wv = (double)row[pcol + min(j, a.np_launch - 1)];
+                const double wv = wcol(pcol + min(j, a.np_launch - 1));
                 aw[j] += wv * wv;
                 ah[j] += wv * fh[j];
             }
@@ -2037,7 +2046,7 @@ __global__ void k_zero(uint32_t* p, int64_t n) {
 // perm[s].  Probes of one Philox block (indices 4g .. 4g+3) share the block and
 // its two Box-Muller transforms.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, int r0, int nr,
+__global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, int r0, int nr, int64_t gstride,
                                                        PointsCheck pc, const int32_t* perm, T* out) {
     // one sample per thread; when the launch writes whole rows (nsrc == nr)
     // the rows of each wave go out through LDS as one contiguous block
@@ -2045,7 +2054,7 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
     if (points_stale(pc)) return;
     const int64_t N = pc.n;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool whole = nsrc == nr;
+    const bool whole = nsrc == nr && gstride == 0;
     if (s >= N && !whole) return;
     const int64_t i = s < N ? perm[s] : 0;
     uint64_t cached_seed = 0, cached_g = ~0ull;
@@ -2094,6 +2103,22 @@ __global__ __launch_bounds__(256) void k_stage_weights(SpreadSrc src, int nsrc, 
             V* dst = reinterpret_cast<V*>(out + s0 * nr);
             const V* src4 = reinterpret_cast<const V*>(w);
             for (int k = lane; k < nv; k += 64) dst[k] = src4[k];
+        }
+        return;
+    }
+    if (gstride) {
+        // column groups of four: consecutive samples' 16-byte chunks are
+        // adjacent (r0 and nsrc are multiples of 4)
+#pragma unroll
+        for (int q = 0; q < 2 * kMaxPairsPerSpread; q += 4) {
+            if (q >= nsrc) break;
+            T* dg = out + ((r0 + q) >> 2) * gstride + s * 4;
+            if constexpr (sizeof(T) == 4) {
+                *reinterpret_cast<float4*>(dg) = make_float4(vals[q], vals[q + 1], vals[q + 2], vals[q + 3]);
+            } else {
+                *reinterpret_cast<double2*>(dg) = make_double2(vals[q], vals[q + 1]);
+                *reinterpret_cast<double2*>(dg + 2) = make_double2(vals[q + 2], vals[q + 3]);
+            }
         }
         return;
     }
@@ -2153,13 +2178,15 @@ __global__ void k_chan_out(int64_t Mtot, int ncp, int n_s, int n_t, int nw, cons
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, const PointsCheck& pc,
-                          const int32_t* perm, void* out, hipStream_t s) {
+void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t gstride,
+                          const PointsCheck& pc, const int32_t* perm, void* out, hipStream_t s) {
     if (pc.n == 0) return;
     if (prec == FKR_F64)
-        k_stage_weights<double><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, pc, perm, static_cast<double*>(out));
+        k_stage_weights<double><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, gstride, pc, perm,
+                                                           static_cast<double*>(out));
     else
-        k_stage_weights<float><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, pc, perm, static_cast<float*>(out));
+        k_stage_weights<float><<<nblk(pc.n), 256, 0, s>>>(src, nsrc, r0, nr, gstride, pc, perm,
+                                                          static_cast<float*>(out));
 }
 
 // ---------------------------------------------------------------------------
@@ -2493,7 +2520,7 @@ __device__ __forceinline__ void col3_flush_first(col3_v4 (&acc)[col3_blocks<NC>(
 
 template <int KER, int NC, int NT>
 __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* __restrict__ wrow, int wstride,
-                                                    int col0, const uint32_t* __restrict__ loc,
+                                                    int64_t gstride, int col0, const uint32_t* __restrict__ loc,
                                                     const float* __restrict__ frac,
                                                     const int32_t* __restrict__ jobs,
                                                     float* __restrict__ subgrid) {
@@ -2550,7 +2577,10 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
                 for (int rb = 0; rb < 4; ++rb) acc[tb][rb] = col3_v4{0.f, 0.f, 0.f, 0.f};
             int cur = -1;   // packed (x, y) first cell held in the accumulators
             int base = 0;
-            const float* wp = wrow + col0 + 2 * p0 + (int64_t)s_beg * wstride;
+            // the pass's four columns: a group of the grouped layout, or
+            // four columns of the rows
+            const int cb = col0 + 2 * p0;
+            const float* wp = wrow + (gstride ? (cb >> 2) * gstride + (cb & 3) : (int64_t)cb) + (int64_t)s_beg * wstride;
             // the batch in registers: sample q0 + bt + sl; lane 63 also
             // holds the key of the sample after the batch (or ~0)
             uint32_t rkey = 0, rnext = ~0u;
@@ -2680,7 +2710,7 @@ static void spread_col3(const Geo& g, const SpreadSrc& src, const uint32_t* loc,
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_col3<KER, NC, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_spread_col3<KER, NC, NT><<<nb, NT, lds, s>>>(g, src.npairs, static_cast<const float*>(src.w[0].ptr),
-                                                   (int)src.w[0].stride, (int)src.w[0].col, loc,
+                                                   (int)src.w[0].stride, src.w[0].gstride, (int)src.w[0].col, loc,
                                                    static_cast<const float*>(frac), jobs,
                                                    static_cast<float*>(subgrid));
 }
