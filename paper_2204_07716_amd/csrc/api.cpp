@@ -114,6 +114,16 @@ PointsCheck points_check(fkr_plan* p) { return PointsCheck{p->N, p->epoch, diag_
 // streams exactly the 16 bytes per sample it uses.  Elsewhere they are rows.
 bool grouped_weights(const fkr_plan* p) { return p->d == 3 && p->prec == FKR_F32 && p->w == 8; }
 
+// Every fine cell is covered by its own padded tile and at most the previous
+// one in each dimension (no padded tile wider than the period, so none covers
+// a cell twice): the fold's workgroups then share their covering tiles.
+bool fold_two_covers(const fkr_plan* p) {
+    if (p->max_cover > 2) return false;
+    for (int j = 0; j < p->d; ++j)
+        if (p->pe[j] > p->Mr[j]) return false;
+    return true;
+}
+
 // Every weight vector of a call, constants included, gathered once into
 // sorted sample order: `stride` = nr rounded up to 4 columns (16-byte loads;
 // padding columns are zero), as rows [N][stride] or as column groups.
@@ -176,7 +186,7 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
             launch_fold_grid(p->prec, p->tprec, g,
                              fold_args(g, gp, at<int32_t>(p, p->lay.cover), at<int32_t>(p, p->lay.job_off),
                                        p->ws + p->lay.subgrid),
-                             gp, p->ws + p->lay.fftB, s);
+                             gp, fold_two_covers(p), p->ws + p->lay.fftB, s);
             in = p->ws + p->lay.fftB;
         }
         StageTimer tf(p, FKR_STAGE_FFT_FWD, s);

@@ -96,6 +96,7 @@ struct fkr_plan {
     fkr::FftLen fMr[fkr::kMaxD], fL[fkr::kMaxD];
     std::vector<double> deconv[fkr::kMaxD];
     std::vector<int32_t> cover[fkr::kMaxD];
+    int max_cover = 0;                     // most padded tiles covering one fine cell in one dimension
     fkr::Layout lay;
     // state
     unsigned char* ws = nullptr;

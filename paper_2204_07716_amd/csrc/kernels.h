@@ -174,7 +174,9 @@ void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, 
                    const long long* skip_flag, int64_t c_keep, hipStream_t s);
 // 3-D: the fine grid [pair][Mr^d] (transform precision) of the launch's
 // pairs folded from the subgrids; the first forward pass then reads its rows.
-void launch_fold_grid(int prec, int tprec, const Geo& g, const FoldArgs& fa, int npairs, void* grid, hipStream_t s);
+// two_covers: no fine cell is covered by more than two padded tiles in any dimension.
+void launch_fold_grid(int prec, int tprec, const Geo& g, const FoldArgs& fa, int npairs, bool two_covers,
+                      void* grid, hipStream_t s);
 void launch_fft(int prec, bool inverse, const FftPass& f, const void* in, void* out,
                 hipStream_t s);
 void launch_solve2(int prec, const SolveArgs& a, const int* pidx, const void* chan, hipStream_t s);

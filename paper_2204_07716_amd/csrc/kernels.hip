@@ -1130,9 +1130,76 @@ __global__ __launch_bounds__(512) void k_fold_grid(FoldArgs fa, int64_t nt0, int
     grid[(int64_t)p * Mrtot + cell] = o;
 }
 
-void launch_fold_grid(int prec, int tprec, const Geo& g, const FoldArgs& fa, int npairs, void* grid, hipStream_t s) {
+// The same when no fine cell is covered by more than two padded tiles in any
+// dimension and no padded tile is wider than the period: the cell's covering
+// tiles are its own tile and, per dimension, the previous one (periodically)
+// where the cell lies in that tile's halo.
+// The eight (neighbour, job range) pairs are the workgroup's, so the loop
+// over them is uniform and each step is one coalesced subgrid load per lane.
+// (Summation order: own tile first, then the neighbours, jobs ascending.)
+template <typename TS, typename T>
+__global__ __launch_bounds__(512) void k_fold_tiles(FoldArgs fa, int w, int64_t nt0, int64_t nt1, int64_t nt2,
+                                                    int64_t ts0, int64_t ts1, int64_t ts2, int64_t Mrtot,
+                                                    typename V2<T>::t* grid) {
+    const int64_t b = blockIdx.x;
+    const int p = blockIdx.y;
+    const int64_t bt[3] = {b % nt0, (b / nt0) % nt1, b / (nt0 * nt1)};
+    const int64_t nt[3] = {nt0, nt1, nt2}, ts[3] = {ts0, ts1, ts2};
+    const int tid = threadIdx.x;
+    const int64_t l[3] = {tid % ts0, (tid / ts0) % ts1, tid / (ts0 * ts1)};
+    if (l[2] >= ts2) return;
+    int64_t c[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c[j] = bt[j] * ts[j] + l[j];
+    if (c[0] >= fa.Mr[0] || c[1] >= fa.Mr[1] || c[2] >= fa.Mr[2]) return;
+    const TS* sub = static_cast<const TS*>(fa.subgrid);
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        int64_t t[3], off[3];
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int oj = (o >> j) & 1;
+            if (oj && nt[j] == 1) ok = false;   // the only tile: no other cover
+            t[j] = bt[j] - oj;
+            if (t[j] < 0) t[j] += nt[j];
+            off[j] = c[j] - t[j] * ts[j];
+            if (off[j] < 0) off[j] += fa.Mr[j];
+            const int64_t interior = min(ts[j], fa.Mr[j] - t[j] * ts[j]);
+            ok = ok && off[j] < interior + w - 1;
+        }
+        const int64_t tile = t[0] + nt0 * (t[1] + nt1 * t[2]);
+        const int j0 = fa.job_off[tile], j1 = fa.job_off[tile + 1];
+        if (!ok) continue;
+        const int64_t cell = off[0] + fa.pe0 * (off[1] + fa.pe1 * off[2]);
+        for (int job = j0; job < j1; ++job) {
+            const TS* v = sub + (((int64_t)job * fa.np + p) * fa.Psub + cell) * 2;
+            re += (double)v[0];
+            im += (double)v[1];
+        }
+    }
+    typename V2<T>::t out;
+    out.x = (T)re;
+    out.y = (T)im;
+    grid[(int64_t)p * Mrtot + c[0] + fa.Mr[0] * (c[1] + fa.Mr[1] * c[2])] = out;
+}
+
+void launch_fold_grid(int prec, int tprec, const Geo& g, const FoldArgs& fa, int npairs, bool two_covers,
+                      void* grid, hipStream_t s) {
     const dim3 nb((unsigned)g.n_tiles, (unsigned)npairs);
     const unsigned nt = (unsigned)(g.ts[0] * g.ts[1] * g.ts[2]);
+    if (two_covers) {
+#define FKR_FOLDT(TS, T) k_fold_tiles<TS, T><<<nb, nt, 0, s>>>(fa, g.w, g.nt[0], g.nt[1], g.nt[2], g.ts[0], g.ts[1], \
+                                                               g.ts[2], g.Mrtot, static_cast<typename V2<T>::t*>(grid))
+        if (tprec == FKR_F64) {
+            if (prec == FKR_F64) FKR_FOLDT(double, double); else FKR_FOLDT(float, double);
+        } else {
+            FKR_FOLDT(float, float);
+        }
+#undef FKR_FOLDT
+        return;
+    }
 #define FKR_FOLDG(TS, T) k_fold_grid<3, TS, T><<<nb, nt, 0, s>>>(fa, g.nt[0], g.nt[1], g.ts[0], g.ts[1], g.ts[2], \
                                                                  g.Mrtot, static_cast<typename V2<T>::t*>(grid))
     if (tprec == FKR_F64) {

@@ -389,6 +389,7 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
                 e[1 + 2 * e[0]] = (int32_t)b;
                 e[2 + 2 * e[0]] = (int32_t)o;
                 e[0]++;
+                p->max_cover = std::max(p->max_cover, (int)e[0]);
             }
         }
     }
