@@ -24,6 +24,13 @@ computes, by the plain definitions, slowly and in FP64:
                     log-residual fit of eq. (24)-(26) (default) or the direct
                     residual fit of eq. (23).
 * ``get_hlist``     the bandwidth list helper of Sec. 4.
+* ``spline_predict`` tensor-product not-a-knot cubic spline interpolation of a
+                    grid function with linear extrapolation (Sec. 4
+                    fkreg_predict; Table 1 y_grid_opt), one dimension at a
+                    time from the dense spline system.
+* ``fit_variance``  the variance of the fit, Sigma(g) = sum_i S_gi^2 sigma_i^2
+                    (eq. 27), from the smoother weights of eq. (3); with
+                    ``interval`` the confidence band of eq. (28).
 
 Readings taken where the paper is silent or garbled: the bandwidth ``h_j`` is the per-dimension kernel standard
 deviation (H = diag(h^2)); the kernel is the normalised Gaussian; the
@@ -550,3 +557,134 @@ def nudft(X, W, lo, period, K) -> np.ndarray:
         raise ValueError("orc_nudft failed")
     c = out[..., 0] + 1j * out[..., 1]
     return c.reshape(tuple((2 * K + 1)[::-1]) + (nw,))
+
+
+# ---------------------------------------------------------------------------
+# Prediction and pointwise inference (Sec. 4 fkreg_predict and
+# fkreg_interval, Table 1 y_grid_opt; Sec. 4.2 eq. 27-28)
+# ---------------------------------------------------------------------------
+
+def spline_second_derivatives(f: np.ndarray) -> np.ndarray:
+    """Second derivatives (in index units, spacing 1) of the not-a-knot cubic
+    interpolating spline through f[0], ..., f[n-1] at consecutive integer
+    nodes, along axis 0 (any trailing shape: one spline per column).
+
+    The spline is C^2 at every interior node, which gives
+    m_{k-1} + 4 m_k + m_{k+1} = 6 (f_{k-1} - 2 f_k + f_{k+1}) for k = 1..n-2,
+    and its third derivative is continuous at nodes 1 and n-2 (the
+    not-a-knot ends): m_0 - 2 m_1 + m_2 = 0 and m_{n-3} - 2 m_{n-2} + m_{n-1}
+    = 0.  Three nodes: the interpolating parabola (constant m); two: the
+    line (m = 0).  Solved as one dense linear system."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    rest = f.shape[1:]
+    F = f.reshape(n, -1)
+    if n <= 2:
+        return np.zeros_like(f)
+    A = np.zeros((n, n))
+    R = np.zeros((n, F.shape[1]))
+    for k in range(1, n - 1):
+        A[k, k - 1:k + 2] = (1.0, 4.0, 1.0)
+        R[k] = 6.0 * (F[k - 1] - 2.0 * F[k] + F[k + 1])
+    if n == 3:
+        A[0, :] = (1.0, -1.0, 0.0)
+        A[2, :] = (0.0, 1.0, -1.0)
+    else:
+        A[0, 0:3] = (1.0, -2.0, 1.0)
+        A[n - 1, n - 3:n] = (1.0, -2.0, 1.0)
+    return np.linalg.solve(A, R).reshape((n,) + rest)
+
+
+def spline_eval_1d(f: np.ndarray, t: float) -> np.ndarray:
+    """Value at index coordinate t of the not-a-knot spline through f along
+    axis 0 (node k at t = k).  Inside [0, n-1] the cubic piece of t's
+    interval; outside, the tangent line at the nearer end (linear
+    extrapolation).  Returns an array of f's trailing shape."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    m = spline_second_derivatives(f)
+
+    def piece(k, u):   # cubic on [k, k+1] at k + u
+        a, b = 1.0 - u, u
+        return a * f[k] + b * f[k + 1] + ((a ** 3 - a) * m[k] + (b ** 3 - b) * m[k + 1]) / 6.0
+
+    def slope(k, u):   # its derivative
+        return f[k + 1] - f[k] + ((1.0 - 3.0 * (1.0 - u) ** 2) * m[k] + (3.0 * u ** 2 - 1.0) * m[k + 1]) / 6.0
+
+    if t < 0.0:
+        return piece(0, 0.0) + t * slope(0, 0.0)
+    if t > n - 1:
+        return piece(n - 2, 1.0) + (t - (n - 1)) * slope(n - 2, 1.0)
+    k = min(int(np.floor(t)), n - 2)
+    return piece(k, t - k)
+
+
+def spline_predict(values: np.ndarray, M, lo, hi, Xq: np.ndarray) -> np.ndarray:
+    """Tensor-product not-a-knot cubic spline interpolation of a grid function
+    (the 'spline' method of griddedInterpolant named by Table 1 y_grid_opt,
+    with its 'linear' extrapolation) at the query points Xq (n x d):
+    interpolate along one dimension at a time, every grid line of the
+    remaining dimensions, down to one value.  values: flat grid, dimension 0
+    fastest, optionally with a leading axis of several grid functions."""
+    M = [int(m) for m in M]
+    d = len(M)
+    Xq = np.asarray(Xq, dtype=np.float64).reshape(-1, d)
+    V = np.asarray(values, dtype=np.float64).reshape((-1,) + tuple(M[::-1]))   # [nv][M_{d-1}]..[M_0]
+    nv = V.shape[0]
+    delta = [(hi[j] - lo[j]) / (M[j] - 1) for j in range(d)]
+    out = np.empty((nv, Xq.shape[0]))
+    for i, x in enumerate(Xq):
+        for v in range(nv):
+            A = V[v]
+            for j in range(d):                      # axis -1 is dimension j now
+                t = (x[j] - lo[j]) / delta[j]
+                A = spline_eval_1d(np.moveaxis(A, -1, 0), t)
+            out[v, i] = float(A)
+    return out
+
+
+def fit_variance(X, sigma2_i, h, order, gpts) -> np.ndarray:
+    """Variance of the linear fit m_hat(g) = sum_i S_gi y_i for independent
+    errors of variance sigma2_i (the Sigma of eq. 27):
+    Sigma(g) = sum_i S_gi^2 sigma2_i, with the smoother weights of eq. (3),
+    S_gi = e_1^T A(g)^{-1} K_h(x_i - g) d(x_i - g), d the monomial row of
+    eq. (4)/(14).  Computed from its definition: row 0 of the inverse of the
+    (equilibrated) moment matrix, then every weight S_gi.  NaN where the fit
+    is ill-posed; samples with undefined sigma2_i are left out."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    N, d = X.shape
+    gpts = np.asarray(gpts, dtype=np.float64).reshape(-1, d)
+    h = np.asarray(h, dtype=np.float64)
+    s2 = np.broadcast_to(np.asarray(sigma2_i, dtype=np.float64), (N,))
+    keep = np.isfinite(s2)
+    S, _ = moments(X, None, h, order, gpts)
+    _, r0, ill = solve(S, np.zeros((len(gpts), 0, len(multi_indices(d, order)))), h, order, d)
+    et = np.array(multi_indices(d, order))
+    norm = 1.0 / np.prod(h * np.sqrt(2.0 * np.pi))
+    out = np.full(len(gpts), np.nan)
+    Xk, sk = X[keep], s2[keep]
+    for g in range(len(gpts)):
+        if ill[g]:
+            continue
+        u = (Xk - gpts[g]) / h                                   # (x_i - g) / h per dimension
+        K = norm * np.exp(-0.5 * np.sum(u * u, axis=1))
+        D = np.prod(u[:, None, :] ** et[None, :, :], axis=2)    # equilibrated monomials
+        w = (D @ r0[g]) * K
+        out[g] = np.sum(w * w * sk)
+    return out
+
+
+def normal_quantile(p: float) -> float:
+    """z with Phi(z) = p (the quantile of eq. 28), SciPy's ndtri."""
+    from scipy.special import ndtri
+    return float(ndtri(p))
+
+
+def interval(mhat: np.ndarray, Sigma: np.ndarray, alpha: float = 0.05):
+    """Pointwise confidence interval of eq. (28): m_hat -/+ z_{1-alpha/2}
+    sqrt(Sigma)."""
+    z = normal_quantile(1.0 - alpha / 2.0)
+    half = z * np.sqrt(np.maximum(Sigma, 0.0))
+    return mhat - half, mhat + half

@@ -531,3 +531,131 @@ def test_rgcv_select_skips_nan(orc):
     f = g[np.isfinite(g)]
     thr = f.min() + 0.1 * np.std(f, ddof=1)
     assert orc.rgcv_select(g, 0.1) == max(k for k in range(6) if np.isfinite(g[k]) and g[k] <= thr)
+
+
+# ---------------------------------------------------------------------------
+# Prediction (Sec. 4 fkreg_predict; Table 1 y_grid_opt: 'spline', extrapolation
+# 'linear') and the variance of the fit with its interval (Sec. 4.2, eq. 27-28)
+# ---------------------------------------------------------------------------
+
+def test_spline_1d_matches_scipy_not_a_knot(orc):
+    """Inside: SciPy's CubicSpline with not-a-knot ends.  Outside: the
+    tangent line at the nearer end, from CubicSpline's own derivative."""
+    from scipy.interpolate import CubicSpline
+    rng = np.random.default_rng(5)
+    for n in (4, 5, 6, 11, 40):
+        f = rng.standard_normal(n)
+        cs = CubicSpline(np.arange(n, dtype=float), f, bc_type="not-a-knot")
+        for t in np.concatenate([rng.uniform(0, n - 1, 20), [0.0, n - 1.0, 1.0, n - 2.0]]):
+            assert orc.spline_eval_1d(f, t) == pytest.approx(cs(t), abs=1e-13)
+        for t in (-2.5, -0.01):
+            assert orc.spline_eval_1d(f, t) == pytest.approx(cs(0.0) + t * cs(0.0, 1), abs=1e-12)
+        for t in (n - 1 + 0.01, n + 3.0):
+            assert orc.spline_eval_1d(f, t) == pytest.approx(cs(n - 1.0) + (t - n + 1) * cs(n - 1.0, 1),
+                                                             abs=1e-12)
+
+
+def test_spline_few_nodes_parabola_and_line(orc):
+    """Three nodes: the interpolating parabola (np.polyfit, exact); two: the
+    line through them, also beyond the ends."""
+    f3 = np.array([0.3, -1.2, 2.0])
+    par = np.polyfit([0.0, 1.0, 2.0], f3, 2)
+    for t in (0.0, 0.4, 1.7, 2.0):
+        assert orc.spline_eval_1d(f3, t) == pytest.approx(np.polyval(par, t), abs=1e-14)
+    f2 = np.array([1.5, -0.5])
+    for t in (-1.0, 0.25, 1.0, 3.0):
+        assert orc.spline_eval_1d(f2, t) == pytest.approx(1.5 - 2.0 * t, abs=1e-14)
+
+
+def test_spline_tensor_product_matches_scipy_grid_cubic(orc):
+    """Interior points: SciPy's RegularGridInterpolator 'cubic' (tensor
+    product of not-a-knot B-splines) with an exact sparse solve."""
+    from scipy.interpolate import RegularGridInterpolator
+    from scipy.sparse.linalg import spsolve
+    rng = np.random.default_rng(6)
+    for M, lo, hi in (([7, 9, 6], [0.0, -1.0, 2.0], [1.0, 1.0, 3.0]), ([5, 4], [0.0, 0.0], [1.0, 2.0])):
+        d = len(M)
+        G = rng.standard_normal(int(np.prod(M)))
+        Xq = np.stack([rng.uniform(lo[j], hi[j], 40) for j in range(d)], 1)
+        V = G.reshape(M[::-1]).transpose(tuple(range(d - 1, -1, -1)))   # axis j = dimension j
+        ref = RegularGridInterpolator(orc.grid_axes(M, lo, hi), V, method="cubic", solver=spsolve)(Xq)
+        np.testing.assert_allclose(orc.spline_predict(G, M, lo, hi, Xq)[0], ref, atol=1e-12)
+
+
+def test_spline_reproduces_separable_cubics_and_extends_linearly(orc):
+    """A product of cubics is its own tensor spline (grid values in, the
+    function out, at any interior point); beyond the box in one dimension the
+    value is the function at the face plus its normal derivative times the
+    distance; beyond a corner, the product of the per-dimension tangent
+    lines."""
+    cub = [np.poly1d([0.5, -1.0, 0.3, 2.0]), np.poly1d([-0.2, 0.7, 1.1, -0.4]), np.poly1d([1.3, 0.0, -0.6, 0.9])]
+    M, lo, hi = [6, 5, 7], [0.0, -1.0, 0.5], [2.0, 1.0, 1.5]
+    ax = orc.grid_axes(M, lo, hi)
+    G = np.einsum("k,j,i->kji", cub[2](ax[2]), cub[1](ax[1]), cub[0](ax[0])).ravel()
+    rng = np.random.default_rng(7)
+    Xq = np.stack([rng.uniform(lo[j], hi[j], 30) for j in range(3)], 1)
+    exact = cub[0](Xq[:, 0]) * cub[1](Xq[:, 1]) * cub[2](Xq[:, 2])
+    np.testing.assert_allclose(orc.spline_predict(G, M, lo, hi, Xq)[0], exact, rtol=1e-11, atol=1e-11)
+
+    def ext(p, x, a, b):
+        if x < a:
+            return p(a) + (x - a) * p.deriv()(a)
+        if x > b:
+            return p(b) + (x - b) * p.deriv()(b)
+        return p(x)
+
+    for x in ([-0.7, 0.2, 1.0], [1.0, 1.6, 0.9], [2.5, -1.4, 1.7]):
+        want = np.prod([ext(cub[j], x[j], lo[j], hi[j]) for j in range(3)])
+        got = orc.spline_predict(G, M, lo, hi, np.array([x]))[0, 0]
+        assert got == pytest.approx(want, rel=1e-11, abs=1e-11)
+
+
+def test_fit_variance_equals_explicit_smoother_rows(orc):
+    """Sigma(g) = sum_i S_gi^2 sigma_i^2 with the rows S_g. of the smoother
+    built column by column: the fit of each unit response e_i (eq. 3)."""
+    rng = np.random.default_rng(8)
+    for d, order, h in ((1, 0, [0.08]), (1, 2, [0.12]), (2, 1, [0.15, 0.2]), (3, 1, [0.25, 0.3, 0.2])):
+        N = 150
+        X = rng.uniform(0, 1, (N, d))
+        M = [6, 5, 4][:d]
+        gp = orc.grid_points(M, [0.0] * d, [1.0] * d)
+        s2 = 0.1 + X[:, 0] ** 2
+        rows = orc.fit(X, np.eye(N), h, order, gp)
+        np.testing.assert_allclose(orc.fit_variance(X, s2, h, order, gp), (rows ** 2 * s2).sum(1), rtol=1e-10)
+
+
+def test_fit_variance_is_the_variance_of_the_fit(orc):
+    """eq. (27): Sigma is var[m_hat(g)].  Simulated responses y = m + sigma eps
+    (8000 replicas): the sample variance of the fits agrees within five
+    standard errors, sqrt(2 / R) relative."""
+    rng = np.random.default_rng(9)
+    N, R = 200, 8000
+    X = rng.uniform(0, 1, (N, 2))
+    h, order = [0.15, 0.2], 1
+    gp = orc.grid_points([5, 4], [0.0, 0.0], [1.0, 1.0])
+    s2 = 0.1 + X[:, 0] ** 2
+    Y = np.sin(3 * X[:, 0])[:, None] + np.sqrt(s2)[:, None] * rng.standard_normal((N, R))
+    emp = orc.fit(X, Y, h, order, gp).var(axis=1, ddof=1)
+    np.testing.assert_allclose(emp, orc.fit_variance(X, s2, h, order, gp), rtol=5 * np.sqrt(2.0 / R))
+
+
+def test_fit_variance_nadaraya_watson_constant_noise(orc):
+    """l = 0, constant sigma^2: Sigma = sigma^2 sum K^2 / (sum K)^2, the
+    variance of a weighted mean (direct sums here)."""
+    rng = np.random.default_rng(10)
+    X = rng.uniform(0, 1, (120, 1))
+    g = np.array([[0.0], [0.37], [1.0]])
+    h = 0.07
+    K = np.exp(-0.5 * ((X[:, 0][None, :] - g) / h) ** 2)
+    want = 0.3 * (K ** 2).sum(1) / K.sum(1) ** 2
+    np.testing.assert_allclose(orc.fit_variance(X, 0.3, [h], 0, g), want, rtol=1e-12)
+
+
+def test_interval_quantile(orc):
+    """z_{0.975} = 1.959963984540054 (the two-sided 95% point); the band is
+    symmetric about m_hat with half-width z sqrt(Sigma)."""
+    assert orc.normal_quantile(0.975) == pytest.approx(1.959963984540054, rel=1e-15)
+    assert orc.normal_quantile(0.5) == 0.0
+    lo, hi = orc.interval(np.array([1.0, -2.0]), np.array([4.0, 0.25]), alpha=0.05)
+    np.testing.assert_allclose(hi - lo, 2 * 1.959963984540054 * np.array([2.0, 0.5]), rtol=1e-15)
+    np.testing.assert_allclose((hi + lo) / 2, [1.0, -2.0], rtol=1e-15)
