@@ -91,6 +91,8 @@ def _args():
                     help="skip the warm-path timing (profiling runs count only the cold steps)")
     ap.add_argument("--cpu-points", type=int, default=0,
                     help="grid points per pass in the oracle's timed sample (0: 512 in 3-D, 2048 in 2-D)")
+    ap.add_argument("--no-inference", action="store_true",
+                    help="skip the variance-of-fit / band / spline-prediction timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (counter calibration)")
     return ap.parse_args()
@@ -407,6 +409,9 @@ def main() -> int:
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = a.numel() * 4
 
+    if not args.no_inference:
+        line["inference"] = _inference(w, Xd, Yd, args.transform, args.sigma, args.steps)
+
     sample = None
     if not args.no_cpu_baseline or not args.no_fp64_single:
         rng = np.random.default_rng(2024)
@@ -426,6 +431,52 @@ def main() -> int:
     del plan
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _inference(w, Xd, Yd, transform, sigma, steps, n_query=1_000_000):
+    """Prediction and inference on the same samples (Sec. 4 fkreg_interval and
+    fkreg_predict; eq. 27-28): the variance of the fit and its 95% band for
+    the log-variance pass's sigma^2 grid (one call: density moments at h and
+    sigma^2-weighted moments of the squared kernel at h / sqrt 2, which the
+    plan's band must cover), then the spline coefficients of the fit and its
+    values at n_query points drawn over the box widened by 10% per side.
+    Eager calls, timed with device synchronisation around each loop."""
+    import numpy as np
+    import torch
+    from paper_2204_07716_amd import Plan
+    h = w.h[0]
+    h2 = tuple(v / np.sqrt(2.0) for v in h)
+    plan = Plan(w.d, 1, w.M, w.lo, w.hi, h2, h, w.eps, precision="fp32", n_max=w.N, max_weights=2,
+                max_h=1, transform_precision=transform, sigma=sigma)
+    plan.set_points(Xd)
+    mh = plan.fit(h, Yd)[0, 0]
+    s2 = plan.variance(h, Yd, mh, mode="log")[0]
+    rng = np.random.default_rng(7)
+    span = np.asarray(w.hi) - np.asarray(w.lo)
+    Q = rng.uniform(np.asarray(w.lo) - 0.1 * span, np.asarray(w.hi) + 0.1 * span, (n_query, w.d))
+    Qd = torch.as_tensor(Q.astype(np.float32), device=Xd.device)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, r
+
+    t_int, iv = timed(lambda: plan.interval(h, s2, mhat=mh, alpha=0.05))
+    t_spl, coef = timed(lambda: plan.spline(mh[None]))
+    t_pred, _ = timed(lambda: plan.predict(coef, Qd))
+    Mtot = int(np.prod(w.M))
+    fin = torch.isfinite(iv["Sigma"])
+    out = {"interval_ms": round(t_int, 4), "interval_grid_points_per_s": round(Mtot / (t_int * 1e-3), 1),
+           "spline_ms": round(t_spl, 4), "predict_ms": round(t_pred, 4), "predict_points": n_query,
+           "predict_points_per_s": round(n_query / (t_pred * 1e-3), 1),
+           "band_halfwidth_median": float(torch.median(iv["upper"][fin] - iv["lower"][fin]).item() / 2),
+           "plan": "FP32 spreading, %s transforms, h_min = h / sqrt 2" % transform}
+    del plan
+    return out
 
 
 def _fp64_single(w, Xd, Yd, steps, warmup, batched_value, use_graph):

@@ -60,6 +60,7 @@ enum { FKR_F32 = 0, FKR_F64 = 1 };             /* element types */
 enum { FKR_KERNEL_ES = 0, FKR_KERNEL_GAUSS = 1 }; /* spreading (gridding) kernel */
 enum { FKR_VAR_LOG = 0, FKR_VAR_DIRECT = 1 };   /* variance estimator */
 enum { FKR_TP_SAME = 0, FKR_TP_F32 = 1, FKR_TP_F64 = 2 }; /* transform precision */
+enum { FKR_SIG_SCALAR = 0, FKR_SIG_GRID = 1 };   /* error variance of fkr_interval */
 
 #define FKR_MAX_D 3
 #define FKR_MAX_ORDER 2
@@ -285,6 +286,48 @@ fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const vo
                         int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
                         double* vhat_dev, double* kappa_dev, void* stream);
 
+/* Variance of the fit and pointwise confidence band (Sec. 4.2, eq. 27-28;
+ * Sec. 4 fkreg_interval) at one bandwidth h (d doubles).  The fit of eq. (3)
+ * is linear in y, m_hat(g) = sum_i S_gi y_i, so for independent errors of
+ * variance sigma_i^2 its variance is Sigma(g) = sum_i S_gi^2 sigma_i^2 =
+ * r^T Q r, with r = A(g)^{-1} e_1 and Q_bc = sum_i K_h(x_i - g)^2 (x_i -
+ * g)^{b+c} sigma_i^2.  The squared Gaussian kernel is K_{h/sqrt2} times
+ * prod_j 1 / (2 sqrt(pi) h_j), so Q comes from one more pass of the moment
+ * path at h / sqrt 2, which must lie within the plan's bandwidth range
+ * (create the plan with h_min <= h / sqrt 2), else FKR_E_ARG.
+ *   sig_kind FKR_SIG_SCALAR: sigma_i^2 = sigma2 (homoscedastic model);
+ *   FKR_SIG_GRID: sigma_i^2 = multilinear interpolation at x_i of the grid
+ *   sigma2_dev ([M^d] doubles, e.g. fkr_variance's output); samples where it
+ *   is undefined (NaN at a corner of their cell) are left out of the sum.
+ * Sigma_dev [M^d] doubles receives Sigma (NaN where the fit is ill-posed, as
+ * in fkr_fit).  lower_dev / upper_dev (optional, [M^d]) receive
+ * mhat -/+ z_{1-alpha/2} sqrt(max(Sigma, 0)) for the real fit mhat_dev ([M^d]
+ * doubles) and 0 < alpha < 1; z is found on the host from the C library's
+ * erfc.  The call spreads and transforms the density (and, for
+ * FKR_SIG_GRID, the interpolated sigma^2); it needs points set. */
+fkr_status fkr_interval(fkr_plan* plan, const double* h, int sig_kind, double sigma2,
+                        const double* sigma2_dev, const double* mhat_dev, double alpha,
+                        double* Sigma_dev, double* lower_dev, double* upper_dev, void* stream);
+
+/* Prediction at new points by tensor-product cubic spline interpolation of
+ * grid functions (Sec. 4 fkreg_compact / fkreg_predict; Table 1 y_grid_opt:
+ * Method 'spline', ExtrapolationMethod 'linear').  Along each dimension the
+ * spline is the not-a-knot cubic interpolant of the M_j grid values (the
+ * parabola for M_j = 3, the line for M_j = 2); beyond the box it continues
+ * along the tangent at the nearer end, dimension by dimension.  NaN grid
+ * values make the spline NaN along every grid line through them.
+ *   fkr_spline: coef_dev ([nv][2^d][M^d] doubles, caller-owned, must not
+ *   overlap G_dev) receives, per grid function of G_dev ([nv][M^d]), the
+ *   function itself and its mixed second derivatives d^2|S| f /
+ *   prod_{j in S} dk_j^2 in grid-index units, for every nonempty subset S of
+ *   the dimensions (array index = bit mask of S).
+ *   fkr_predict: the spline value at Nq points Xq_dev (Nq x d, type x_type)
+ *   -> out_dev [nv][Nq] doubles; NaN for non-finite coordinates.
+ * Neither call needs points or the workspace, only the plan's grid. */
+fkr_status fkr_spline(fkr_plan* plan, int nv, const double* G_dev, double* coef_dev, void* stream);
+fkr_status fkr_predict(fkr_plan* plan, int nv, const double* coef_dev, int64_t Nq, const void* Xq_dev,
+                       int x_type, double* out_dev, void* stream);
+
 /* Bandwidth candidates (Sec. 4, get_hList), host only: n values from a to b
  * inclusive, log-spaced (kind 0, a > 0) or linearly spaced (kind 1). */
 fkr_status fkr_hlist(int n, double a, double b, int kind, double* out);
@@ -309,9 +352,9 @@ typedef enum {
     FKR_STAGE_SPREAD = 2,    /* spreading onto tile subgrids (eq. 16-17)    */
     FKR_STAGE_FOLD = 3,      /* 3-D: the subgrids summed into the fine grid; 1-D and 2-D do this inside the first forward FFT pass (FKR_STAGE_FFT_FWD) */
     FKR_STAGE_FFT_FWD = 4,   /* forward FFT passes + deconvolution (eq. 19-20) */
-    FKR_STAGE_EXPAND = 5,    /* kept for numbering: the channel spectra are expanded by the first inverse FFT pass (FKR_STAGE_FFT_INV) */
+    FKR_STAGE_EXPAND = 5,    /* kept for numbering: the channel spectra kernel is timed with the inverse passes (FKR_STAGE_FFT_INV) */
     FKR_STAGE_FFT_INV = 6,   /* inverse FFT passes + crop (eq. 21)          */
-    FKR_STAGE_SOLVE = 7,     /* per-grid-point solves (eq. 3 / 11)          */
+    FKR_STAGE_SOLVE = 7,     /* per-grid-point solves (eq. 3 / 11), and fkr_interval's variance of the fit */
     FKR_STAGE_REDUCE = 8,    /* interpolation + DF/RSS/variance reductions  */
     FKR_N_STAGES = 9
 } fkr_stage;

@@ -665,14 +665,27 @@ def fit_variance(X, sigma2_i, h, order, gpts) -> np.ndarray:
     norm = 1.0 / np.prod(h * np.sqrt(2.0 * np.pi))
     out = np.full(len(gpts), np.nan)
     Xk, sk = X[keep], s2[keep]
+    chunk = 1 << 20
     for g in range(len(gpts)):
         if ill[g]:
             continue
-        u = (Xk - gpts[g]) / h                                   # (x_i - g) / h per dimension
-        K = norm * np.exp(-0.5 * np.sum(u * u, axis=1))
-        D = np.prod(u[:, None, :] ** et[None, :, :], axis=2)    # equilibrated monomials
-        w = (D @ r0[g]) * K
-        out[g] = np.sum(w * w * sk)
+        acc = 0.0
+        for c0 in range(0, len(Xk), chunk):                     # the sum over samples, in pieces
+            u = (Xk[c0:c0 + chunk] - gpts[g]) / h               # (x_i - g) / h per dimension
+            K = norm * np.exp(-0.5 * np.sum(u * u, axis=1))
+            pw = [[np.ones(len(u))] for _ in range(d)]          # powers u_j^a, a <= order
+            for j in range(d):
+                for a in range(order):
+                    pw[j].append(pw[j][-1] * u[:, j])
+            row = np.zeros(len(u))
+            for b, e in enumerate(et):                          # e_1^T A~^{-1} d~(x_i - g)
+                mono = pw[0][e[0]]
+                for j in range(1, d):
+                    mono = mono * pw[j][e[j]]
+                row += r0[g, b] * mono
+            w = row * K
+            acc += float(np.sum(w * w * sk[c0:c0 + chunk]))
+        out[g] = acc
     return out
 
 

@@ -14,6 +14,7 @@ FKR_F32, FKR_F64 = 0, 1
 FKR_KERNEL_ES, FKR_KERNEL_GAUSS = 0, 1
 FKR_VAR_LOG, FKR_VAR_DIRECT = 0, 1
 FKR_TP_SAME, FKR_TP_F32, FKR_TP_F64 = 0, 1, 2
+FKR_SIG_SCALAR, FKR_SIG_GRID = 0, 1
 FKR_MAX_H = 64
 FKR_RESOLVE = 1e-3
 FKR_STATIC_WORKSPACE_BYTES = 64 << 20
@@ -47,7 +48,8 @@ class Diag(ctypes.Structure):
 
 EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_workspace_size",
            "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit", "fkr_fit_noalloc",
-           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_get_diagnostics",
+           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_interval", "fkr_spline",
+           "fkr_predict", "fkr_get_diagnostics",
            "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
            "fkr_profile_read"]
 
@@ -90,6 +92,9 @@ def load() -> ctypes.CDLL:
         "fkr_cv": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P, P], I),
         "fkr_gcv": ([P, I, pD, I, I, P, I, I, P, P, P, P, P, P], I),
         "fkr_variance": ([P, pD, I, P, I, P, I, P, P, P, P], I),
+        "fkr_interval": ([P, pD, I, D, P, P, D, P, P, P, P], I),
+        "fkr_spline": ([P, I, P, P, P], I),
+        "fkr_predict": ([P, I, P, I64, P, I, P, P], I),
         "fkr_get_diagnostics": ([P, ctypes.POINTER(Diag)], I),
         "fkr_status_string": ([I], ctypes.c_char_p),
         "fkr_hlist": ([I, D, D, I, pD], I),

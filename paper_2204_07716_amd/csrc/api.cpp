@@ -246,7 +246,7 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
 // depend on the points and h only); the decision is taken on the device, so a
 // captured graph stays valid whatever ran before its replay.
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
-                        bool reuse = false) {
+                        bool reuse = false, bool density = true) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
     if (ncp > p->ncp_max) return FKR_E_ARG;
@@ -311,7 +311,10 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         launch_fft(p->tprec, true, f, in, out, s);
         in = out;
     }
-    if (even) launch_chan_tag(diag_ptr(p), h, p->d, s);
+    // (density = false: weight 0 is not the unit density, so the buffer no
+    // longer holds density moments at any h)
+    if (!density) launch_chan_untag(diag_ptr(p), s);
+    else if (even) launch_chan_tag(diag_ptr(p), h, p->d, s);
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
@@ -483,6 +486,21 @@ std::vector<std::pair<size_t, std::vector<unsigned char>>> constant_tables(const
         off += p->cover[j].size() * 4;
     }
     return out;
+}
+
+// z with Phi(z) = 1 - alpha / 2 (the quantile of eq. 28): bisection on the
+// decreasing upper tail Q(z) = erfc(z / sqrt 2) / 2 until the bracket stops
+// shrinking, so z is as accurate as the library's erfc.
+double upper_quantile(double alpha) {
+    double lo = 0.0, hi = 40.0;
+    const double target = 0.5 * alpha;
+    for (int it = 0; it < 256; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (0.5 * std::erfc(mid / std::sqrt(2.0)) > target) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
 }
 
 // The argument checks of fkr_fit that do not need points on the device.
@@ -777,6 +795,103 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
         launch_reduce_final(partial, 2, red, s);
         launch_sigma2(p->Mtot, v, red, sigma2, kappa, s);
     }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma2, const double* sigma2_dev,
+                        const double* mhat, double alpha, double* Sigma, double* lower, double* upper,
+                        void* stream) {
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if ((st = check_h(p, 1, h)) != FKR_OK) return st;
+    if (!Sigma) return FKR_E_ARG;
+    if (sig_kind == FKR_SIG_SCALAR) {
+        if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return FKR_E_ARG;
+    } else if (sig_kind != FKR_SIG_GRID || !sigma2_dev) {
+        return FKR_E_ARG;
+    }
+    if ((lower || upper) && (!mhat || !(alpha > 0.0 && alpha < 1.0))) return FKR_E_ARG;
+    // the squared Gaussian kernel is a Gaussian of bandwidth h / sqrt 2
+    double h2[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < p->d; ++j) h2[j] = h[j] / std::sqrt(2.0);
+    if (check_h(p, 1, h2) != FKR_OK) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    const Geo g = make_geo(p);
+    // 1. density moments at h -> row 0 of the equilibrated inverse per point
+    std::vector<WSrc> dens{src_one()};
+    if ((st = run_spectra(p, dens, s, false)) != FKR_OK) return st;
+    if ((st = run_channels(p, h, 1, ill_ctr(p), s)) != FKR_OK) return st;
+    SolveArgs a = solve_args(p, 1, 0, 0, h);
+    a.r0_out = at<double>(p, p->lay.r0);
+    {
+        StageTimer t(p, FKR_STAGE_SOLVE, s);
+        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    }
+    // 2. moments of the weights sigma_i^2 under the squared kernel (the
+    // Gaussian at h / sqrt 2): the same density spectra for a constant
+    // sigma^2, else the interpolated grid staged as the weights of a spread
+    IntervalArgs iv{};
+    double scale = 1.0;
+    for (int j = 0; j < p->d; ++j) scale *= 1.0 / (2.0 * std::sqrt(M_PI) * h[j]);
+    if (sig_kind == FKR_SIG_SCALAR) {
+        if ((st = run_channels(p, h2, 1, nullptr, s)) != FKR_OK) return st;
+        scale *= sigma2;
+    } else {
+        {
+            StageTimer t(p, FKR_STAGE_WEIGHTS, s);
+            launch_stage_grid(g, p->prec, points_check(p), p->ws + p->lay.xs, sigma2_dev, p->ws + p->lay.wsort, s);
+        }
+        std::vector<WSrc> srcs(2);
+        for (int r = 0; r < 2; ++r) {
+            srcs[r].kind = W_SORTED; srcs[r].type = p->prec; srcs[r].ptr = p->ws + p->lay.wsort;
+            srcs[r].stride = resid_row_stride(g, p->prec); srcs[r].col = r;
+        }
+        if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
+        if ((st = run_channels(p, h2, 1, nullptr, s, false, false)) != FKR_OK) return st;
+    }
+    // 3. Sigma = scale r0^T Q r0, with Q re-equilibrated from h / sqrt 2 to h
+    iv.P = p->n_t;
+    iv.Mtot = p->Mtot;
+    iv.r0 = at<double>(p, p->lay.r0);
+    for (int b = 0; b < p->n_t; ++b)
+        for (int c = 0; c < p->n_t; ++c) {
+            int deg = 0;
+            for (int j = 0; j < p->d; ++j) deg += p->et[b][j] + p->et[c][j];
+            iv.sidx[b * kMaxP + c] = p->pair_index[b][c];
+            iv.fac[b * kMaxP + c] = std::pow(2.0, -0.5 * deg);
+        }
+    iv.scale = scale;
+    iv.mhat = mhat;
+    iv.z = (lower || upper) ? upper_quantile(alpha) : 0.0;
+    iv.sigma = Sigma;
+    iv.lower = lower;
+    iv.upper = upper;
+    {
+        StageTimer t(p, FKR_STAGE_SOLVE, s);
+        launch_interval(p->tprec, iv, p->ws + p->lay.chan, s);
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_spline(fkr_plan* p, int nv, const double* G, double* coef, void* stream) {
+    if (!p) return FKR_E_ARG;
+    if (nv < 1 || !G || !coef) return FKR_E_ARG;
+    const size_t blk = (size_t)p->Mtot << p->d;
+    const char* gb = reinterpret_cast<const char*>(G);
+    const char* cb = reinterpret_cast<const char*>(coef);
+    if (gb < cb + blk * nv * 8 && cb < gb + (size_t)p->Mtot * nv * 8) return FKR_E_ARG;   // overlap
+    launch_spline(make_geo(p), nv, G, coef, S(stream));
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_predict(fkr_plan* p, int nv, const double* coef, int64_t Nq, const void* Xq, int x_type,
+                       double* out, void* stream) {
+    if (!p) return FKR_E_ARG;
+    if (nv < 1 || !coef || Nq < 0 || (Nq > 0 && (!Xq || !out)) || !valid_type(x_type)) return FKR_E_ARG;
+    launch_spline_eval(make_geo(p), nv, coef, Nq, Xq, x_type, out, S(stream));
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }

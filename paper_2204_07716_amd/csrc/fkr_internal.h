@@ -54,6 +54,7 @@ struct Layout {                      // byte offsets into the workspace
     size_t subgrid = 0, fftA = 0, fftB = 0, spec = 0;
     size_t chan = 0, mhat = 0, partial = 0, wbuf = 0, red = 0, wsort = 0;
     size_t sup = 0;                  // [M] FP32 resolved flags (0 / NaN) of the last solve
+    size_t r0 = 0;                   // [P][M] FP64 row 0 of the equilibrated inverse (variance of the fit)
     size_t total = 0;
     // element capacities (for checks)
     int64_t cap_jobs = 0, cap_fft = 0, cap_spec = 0, cap_chan = 0, cap_mhat = 0;

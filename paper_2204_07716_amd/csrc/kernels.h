@@ -113,8 +113,27 @@ struct SolveArgs {
     int rows_with_y;               // the y fits go to the rows too: column r - 1 for weight r
     int wpg;                       // weights per thread (set by the launcher)
     double* s0_out;                // [M] (may be null)
+    double* r0_out;                // [P][M] row 0 of the equilibrated inverse (may be null); NaN where ill-posed
     float* sup_out;                // [M] 0 where resolved, NaN elsewhere (may be null)
     unsigned long long* ill_count;
+};
+
+// Variance of the fit (eq. 27) per grid point from row 0 of the
+// equilibrated inverse at h and the s-channels of the weights sigma_i^2 at
+// h / sqrt 2 (the squared Gaussian kernel): Sigma = scale sum_bc r0_b r0_c
+// fac_bc s_{b+c}, fac_bc = 2^(-|b+c|/2) re-equilibrates the channels to h.
+struct IntervalArgs {
+    int P;
+    int64_t Mtot;
+    const double* r0;              // [P][M]
+    int sidx[kMaxP * kMaxP];       // s-channel of b + c
+    double fac[kMaxP * kMaxP];
+    double scale;                  // prod_j 1 / (2 sqrt(pi) h_j), times sigma^2 when it is a constant
+    const double* mhat;            // [M] (needed for the band)
+    double z;                      // z_{1 - alpha / 2}
+    double* sigma;                 // [M]
+    double* lower;                 // [M] (may be null)
+    double* upper;                 // [M] (may be null)
 };
 
 struct ReduceCvArgs {
@@ -217,6 +236,13 @@ hipError_t static_scratch(void** ptr);
 void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t gstride, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);
+void launch_chan_untag(long long* diag, hipStream_t s);
+void launch_stage_grid(const Geo& g, int prec, const PointsCheck& pc, const void* xs, const double* G, void* rows,
+                       hipStream_t s);
+void launch_interval(int prec, const IntervalArgs& a, const void* chan, hipStream_t s);
+void launch_spline(const Geo& g, int nv, const double* G, double* coef, hipStream_t s);
+void launch_spline_eval(const Geo& g, int nv, const double* coef, int64_t Nq, const void* X, int x_type,
+                        double* out, hipStream_t s);
 void launch_chan_reuse(long long* diag, const double* h, int d, hipStream_t s);
 
 }  // namespace fkr

@@ -1653,6 +1653,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
     unres = unres || ill;
     if (grp == 0) {
         if (a.s0_out) a.s0_out[k] = s0;
+        if (a.r0_out) {
+#pragma unroll
+            for (int b = 0; b < P; ++b) a.r0_out[b * a.Mtot + k] = ill ? nan : r0[b];
+        }
         if (a.sup_out) a.sup_out[k] = unres ? __builtin_nanf("") : 0.f;
         if (ill && a.ill_count) atomicAdd(a.ill_count, 1ull);
     }
@@ -1677,6 +1681,36 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
             if (a.probe_f32) static_cast<float*>(a.probe_out)[o] = (float)mr;
             else static_cast<double*>(a.probe_out)[o] = mr;
         }
+    }
+}
+
+// Variance of the fit and its confidence band (eq. 27-28), one grid point per
+// thread: Sigma = scale r0^T Q r0 with Q_bc the s-channel of b + c of the
+// sigma^2-weighted samples under the squared kernel, brought to the
+// equilibration of r0; the band is m_hat -/+ z sqrt(max(Sigma, 0)).
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_interval(IntervalArgs a, const T* chan) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.Mtot) return;
+    auto ch = [&](int r) { return (double)chan[(((int64_t)(r >> 1)) * a.Mtot + k) * 2 + (r & 1)]; };
+    double r0[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) r0[b] = a.r0[b * a.Mtot + k];
+    double v = 0.0;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+        double row = 0.0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) row += a.fac[b * kMaxP + c] * ch(a.sidx[b * kMaxP + c]) * r0[c];
+        v += r0[b] * row;
+    }
+    const double sig = a.scale * v;
+    a.sigma[k] = sig;
+    if (a.lower || a.upper) {
+        const double m = a.mhat[k];
+        const double half = a.z * sqrt(fmax(sig, 0.0));
+        if (a.lower) a.lower[k] = m - half;
+        if (a.upper) a.upper[k] = m + half;
     }
 }
 
@@ -1732,6 +1766,146 @@ __global__ __launch_bounds__(256) void k_interp(Geo g, int nv, const double* G, 
 #pragma unroll
         for (int q = 0; q < (1 << D); ++q) s += c.w[q] * gv[c.idx[q]];
         out[(int64_t)v * Nq + i] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Prediction by tensor-product cubic spline (the 'spline' interpolation with
+// 'linear' extrapolation of Table 1's y_grid_opt).  Along one dimension the
+// not-a-knot spline through f_0 .. f_{n-1} (unit node spacing) is fixed by
+// its second derivatives m_k: C^2 continuity gives
+// m_{k-1} + 4 m_k + m_{k+1} = r_k = 6 (f_{k-1} - 2 f_k + f_{k+1}), and the
+// not-a-knot ends (third derivative continuous at nodes 1 and n-2) turn the
+// equations at k = 1 and k = n-2 into 6 m_1 = r_1 and 6 m_{n-2} = r_{n-2};
+// the rest is a (1, 4, 1) tridiagonal system for m_2 .. m_{n-3}, and
+// m_0 = 2 m_1 - m_2, m_{n-1} = 2 m_{n-2} - m_{n-3}.  Three nodes give the
+// parabola (m constant), two the line (m = 0).  In d dimensions the spline
+// value on a cell needs, at its 2^d corners, every mixed derivative
+// d^2|S| / prod_{j in S} dx_j^2 for S a subset of the dimensions: array S of
+// the coefficient block is array S minus dimension j differentiated along j.
+// ---------------------------------------------------------------------------
+constexpr int kSplineCp = 32;   // forward-sweep factors kept; later ones equal the limit 2 - sqrt 3 in FP64
+
+__global__ __launch_bounds__(256) void k_copy_f64(const double* in, double* out, int64_t n, int64_t in_stride,
+                                                  int64_t out_stride, int nv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nv) return;
+    const int64_t v = i / n, k = i - v * n;
+    out[v * out_stride + k] = in[v * in_stride + k];
+}
+
+// One thread per grid line along dimension j: lines of array S (S without
+// bit j) of every grid function go to array S | (1 << j).
+__global__ __launch_bounds__(256) void k_spline_line(double* coef, int64_t Mtot, int d, int j, int64_t n,
+                                                     int64_t st, int64_t nlines, int nv) {
+    __shared__ double cp[kSplineCp];
+    if (threadIdx.x < kSplineCp) {
+        // Thomas factors of the (1, 4, 1) system: c_0 = 1/4, c_u = 1 / (4 - c_{u-1})
+        double c = 0.25;
+        for (int u = 1; u <= (int)threadIdx.x; ++u) c = 1.0 / (4.0 - c);
+        cp[threadIdx.x] = c;
+    }
+    __syncthreads();
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nsub = (int64_t)1 << j;
+    if (id >= nlines * nsub * nv) return;
+    const int64_t a = id / nlines, l = id - a * nlines;
+    const int64_t v = a >> j, S = a & (nsub - 1);
+    const int64_t o = l / st, r = l - o * st;
+    const int64_t base = o * n * st + r;
+    const double* f = coef + ((v << d) + S) * Mtot + base;
+    double* m = coef + ((v << d) + (S | nsub)) * Mtot + base;
+    if (n <= 2) {
+        for (int64_t k = 0; k < n; ++k) m[k * st] = 0.0;
+        return;
+    }
+    if (n == 3) {
+        const double c = f[0] - 2.0 * f[st] + f[2 * st];
+        m[0] = c; m[st] = c; m[2 * st] = c;
+        return;
+    }
+    const double m1 = f[0] - 2.0 * f[st] + f[2 * st];
+    const double mL = f[(n - 3) * st] - 2.0 * f[(n - 2) * st] + f[(n - 1) * st];
+    const int64_t nu = n - 4;   // unknowns m_2 .. m_{n-3}
+    double fa = f[st], fb = f[2 * st], dp = 0.0;
+    for (int64_t u = 0; u < nu; ++u) {
+        const int64_t k = u + 2;
+        const double fc = f[(k + 1) * st];
+        double rhs = 6.0 * (fa - 2.0 * fb + fc);
+        if (k == 2) rhs -= m1;
+        if (k == n - 3) rhs -= mL;
+        dp = (rhs - dp) * cp[u < kSplineCp ? u : kSplineCp - 1];
+        m[k * st] = dp;
+        fa = fb; fb = fc;
+    }
+    double nx = 0.0;
+    for (int64_t u = nu - 1; u >= 0; --u) {
+        const int64_t k = u + 2;
+        const double x = m[k * st] - (u == nu - 1 ? 0.0 : cp[u < kSplineCp ? u : kSplineCp - 1] * nx);
+        m[k * st] = x;
+        nx = x;
+    }
+    const double m2 = n >= 5 ? m[2 * st] : mL;
+    const double mN3 = n >= 5 ? m[(n - 3) * st] : m1;
+    m[st] = m1;
+    m[(n - 2) * st] = mL;
+    m[0] = 2.0 * m1 - m2;
+    m[(n - 1) * st] = 2.0 * mL - mN3;
+}
+
+// Spline value at each query point: per dimension the cell k (clamped to
+// [0, M - 2]) and offset u; weights (1 - u, u) on the corner values and, on
+// the second derivatives, ((1-u)^3 - (1-u)) / 6, (u^3 - u) / 6 inside the box,
+// or the end tangent's (-u/3, -u/6) below it and (v/6, v/3), v = u - 1, above.
+template <int D>
+__global__ __launch_bounds__(256) void k_spline_eval(Geo g, int nv, const double* coef, int64_t Nq, const void* X,
+                                                     int x_type, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nq) return;
+    double aw[D][2], cw[D][2];
+    int64_t base = 0, off[D], stride = 1;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double t = (load_as_double(X, x_type, i * D + j) - g.lo[j]) * g.inv_delta[j];
+        bad |= !isfinite(t);
+        const double top = (double)(g.M[j] - 2);
+        const double kf = isfinite(t) ? fmin(fmax(floor(t), 0.0), top) : 0.0;
+        const double u = isfinite(t) ? t - kf : 0.0;
+        aw[j][0] = 1.0 - u;
+        aw[j][1] = u;
+        if (t < 0.0) {
+            cw[j][0] = -u / 3.0; cw[j][1] = -u / 6.0;
+        } else if (t > top + 1.0) {
+            const double w = u - 1.0;
+            cw[j][0] = w / 6.0; cw[j][1] = w / 3.0;
+        } else {
+            const double b = 1.0 - u;
+            cw[j][0] = (b * b * b - b) / 6.0; cw[j][1] = (u * u * u - u) / 6.0;
+        }
+        base += (int64_t)kf * stride;
+        off[j] = stride;
+        stride *= g.M[j];
+    }
+    for (int v = 0; v < nv; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int S = 0; S < (1 << D); ++S) {
+            const double* c = coef + (((int64_t)v << D) + S) * g.Mtot + base;
+#pragma unroll
+            for (int q = 0; q < (1 << D); ++q) {
+                double w = 1.0;
+                int64_t o = 0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const int e = (q >> j) & 1;
+                    w *= ((S >> j) & 1) ? cw[j][e] : aw[j][e];
+                    o += e ? off[j] : 0;
+                }
+                acc += w * c[o];
+            }
+        }
+        out[(int64_t)v * Nq + i] = bad ? __builtin_nan("") : acc;
     }
 }
 
@@ -2070,6 +2244,29 @@ __global__ __launch_bounds__(256) void k_resid(Geo g, int mode, PointsCheck pc, 
     if (!ok) pc.diag[kDiagResidExcl] = 1;
 }
 
+// A grid function (a variance estimate) at every sorted sample by multilinear
+// interpolation, staged as the two-column rows (G(x_s), 0) of a spread;
+// samples where it is undefined get weight 0 (they are left out).
+template <int D, typename TW>
+__global__ __launch_bounds__(256) void k_stage_grid(Geo g, PointsCheck pc, int x_type, const void* xs,
+                                                    const double* G, TW* rows, int rstride) {
+    if (points_stale(pc)) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= pc.n) return;
+    const Corners<D> c = corners<D>(g, x_type, xs, s);
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) v += c.w[q] * G[c.idx[q]];
+    const TW w = isfinite(v) ? (TW)v : (TW)0;
+    if constexpr (sizeof(TW) == 4) {
+        if (rstride == 2) reinterpret_cast<float2*>(rows)[s] = make_float2(w, 0.f);
+        else reinterpret_cast<float4*>(rows)[s] = make_float4(w, 0.f, 0.f, 0.f);
+    } else {
+        reinterpret_cast<double2*>(rows)[2 * s] = make_double2(w, 0.0);
+        reinterpret_cast<double2*>(rows)[2 * s + 1] = make_double2(0.0, 0.0);
+    }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_kappa_partial(Geo g, int64_t N, int x_type, const void* xs,
                                                        const int32_t* perm, const double* vhat,
@@ -2314,6 +2511,12 @@ void launch_scan(const Geo& g, int64_t N, long long epoch, int32_t* counts, int3
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s) {
     k_chan_tag<<<1, 64, 0, s>>>(diag, h[0], d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0);
 }
+
+__global__ void k_chan_untag(long long* diag) {
+    if (threadIdx.x == 0) diag[kDiagChanEpoch] = -1;
+}
+
+void launch_chan_untag(long long* diag, hipStream_t s) { k_chan_untag<<<1, 64, 0, s>>>(diag); }
 
 void launch_chan_reuse(long long* diag, const double* h, int d, hipStream_t s) {
     k_chan_reuse<<<1, 64, 0, s>>>(diag, h[0], d > 1 ? h[1] : 0.0, d > 2 ? h[2] : 0.0);
@@ -3056,6 +3259,53 @@ void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void
         case 1: k_interp<1><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
         case 2: k_interp<2><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
         default: k_interp<3><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
+    }
+}
+
+void launch_stage_grid(const Geo& g, int prec, const PointsCheck& pc, const void* xs, const double* G, void* rows,
+                       hipStream_t s) {
+    if (pc.n == 0) return;
+    const int rstride = resid_row_stride(g, prec);
+#define FKR_SG(D, TW) k_stage_grid<D, TW><<<nblk(pc.n), 256, 0, s>>>(g, pc, prec, xs, G, static_cast<TW*>(rows), rstride)
+    if (prec == FKR_F64) {
+        if (g.d == 1) FKR_SG(1, double); else if (g.d == 2) FKR_SG(2, double); else FKR_SG(3, double);
+    } else {
+        if (g.d == 1) FKR_SG(1, float); else if (g.d == 2) FKR_SG(2, float); else FKR_SG(3, float);
+    }
+#undef FKR_SG
+}
+
+void launch_interval(int prec, const IntervalArgs& a, const void* chan, hipStream_t s) {
+#define FKR_IV(P, T) k_interval<P, T><<<nblk(a.Mtot), 256, 0, s>>>(a, static_cast<const T*>(chan))
+#define FKR_IV_P(T) do { switch (a.P) { case 1: FKR_IV(1, T); break; case 2: FKR_IV(2, T); break; \
+    case 3: FKR_IV(3, T); break; case 4: FKR_IV(4, T); break; case 6: FKR_IV(6, T); break; \
+    default: FKR_IV(10, T); break; } } while (0)
+    if (prec == FKR_F64) FKR_IV_P(double); else FKR_IV_P(float);
+#undef FKR_IV_P
+#undef FKR_IV
+}
+
+void launch_spline(const Geo& g, int nv, const double* G, double* coef, hipStream_t s) {
+    const int64_t M = g.Mtot;
+    // array 0 of each block is the grid function itself
+    k_copy_f64<<<nblk(M * nv), 256, 0, s>>>(G, coef, M, M, M << g.d, nv);
+    int64_t st = 1;
+    for (int j = 0; j < g.d; ++j) {
+        const int64_t n = g.M[j];
+        const int64_t nlines = M / n;
+        const int64_t nthr = nlines * ((int64_t)1 << j) * nv;
+        k_spline_line<<<nblk(nthr), 256, 0, s>>>(coef, M, g.d, j, n, st, nlines, nv);
+        st *= n;
+    }
+}
+
+void launch_spline_eval(const Geo& g, int nv, const double* coef, int64_t Nq, const void* X, int x_type,
+                        double* out, hipStream_t s) {
+    if (Nq == 0) return;
+    switch (g.d) {
+        case 1: k_spline_eval<1><<<nblk(Nq), 256, 0, s>>>(g, nv, coef, Nq, X, x_type, out); break;
+        case 2: k_spline_eval<2><<<nblk(Nq), 256, 0, s>>>(g, nv, coef, Nq, X, x_type, out); break;
+        default: k_spline_eval<3><<<nblk(Nq), 256, 0, s>>>(g, nv, coef, Nq, X, x_type, out); break;
     }
 }
 

@@ -235,6 +235,7 @@ static void layout(fkr_plan* p) {
     L.wsort = take((size_t)N * ((p->max_weights + 3) & ~3) * sz + 256);   // slack: row loads may read 16 past the last row
     L.red = take((size_t)p->max_h * (2 * p->max_weights + 4) * 8);
     L.sup = take((size_t)p->Mtot * 4);
+    L.r0 = take((size_t)p->Mtot * p->n_t * 8);
     L.total = off;
 }
 

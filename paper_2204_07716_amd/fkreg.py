@@ -263,6 +263,44 @@ class Plan:
               "fkr_variance")
         return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
 
+    # -- prediction and inference ---------------------------------------
+    def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05):
+        """Variance of the fit Sigma [M] (eq. 27) for error variance sigma2 (a
+        number, or a grid [M] interpolated to the samples), and with mhat the
+        band mhat -/+ z_{1-alpha/2} sqrt(Sigma) (eq. 28)."""
+        hb = _hbuf(h, self.d)
+        Sigma = torch.empty(self.Mtot, dtype=torch.float64, device=self.device)
+        band = mhat is not None
+        lower = torch.empty_like(Sigma) if band else None
+        upper = torch.empty_like(Sigma) if band else None
+        m = mhat.reshape(self.Mtot).to(torch.float64).contiguous() if band else None
+        if isinstance(sigma2, torch.Tensor):
+            g = sigma2.reshape(self.Mtot).to(torch.float64).contiguous()
+            kind, val = _lib.FKR_SIG_GRID, 0.0
+        else:
+            g, kind, val = None, _lib.FKR_SIG_SCALAR, float(sigma2)
+        check(self.lib.fkr_interval(self._plan, _hptr(hb), kind, val, _ptr(g), _ptr(m), float(alpha),
+                                    _ptr(Sigma), _ptr(lower), _ptr(upper), _stream()), "fkr_interval")
+        return {"Sigma": Sigma, "lower": lower, "upper": upper}
+
+    def spline(self, G: torch.Tensor) -> torch.Tensor:
+        """Spline coefficient blocks [nv][2^d][M] of grid functions G ([nv][M])."""
+        G = G.reshape(-1, self.Mtot).to(torch.float64).contiguous()
+        coef = torch.empty((G.shape[0], 1 << self.d, self.Mtot), dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_spline(self._plan, G.shape[0], _ptr(G), _ptr(coef), _stream()), "fkr_spline")
+        return coef
+
+    def predict(self, coef: torch.Tensor, Xq: torch.Tensor) -> torch.Tensor:
+        """Spline values [nv][Nq] at the points Xq from fkr_spline's coefficients."""
+        Xq = Xq.contiguous()
+        if Xq.dim() == 1:
+            Xq = Xq[:, None]
+        nv = coef.shape[0]
+        out = torch.empty((nv, Xq.shape[0]), dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_predict(self._plan, nv, _ptr(coef), Xq.shape[0], _ptr(Xq), _dtype_code(Xq),
+                                   _ptr(out), _stream()), "fkr_predict")
+        return out
+
     # -- stage timing ---------------------------------------------------
     def profile(self, on: bool = True) -> None:
         check(self.lib.fkr_profile_enable(self._plan, 1 if on else 0), "fkr_profile_enable")
