@@ -91,6 +91,8 @@ def _args():
                     help="skip the warm-path timing (profiling runs count only the cold steps)")
     ap.add_argument("--cpu-points", type=int, default=0,
                     help="grid points per pass in the oracle's timed sample (0: 512 in 3-D, 2048 in 2-D)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch workload (256 independent regressions; 64-probe x 32-bandwidth DF sweep)")
     ap.add_argument("--no-inference", action="store_true",
                     help="skip the variance-of-fit / band / spline-prediction timing")
     ap.add_argument("--copy-probe", action="store_true",
@@ -411,6 +413,8 @@ def main() -> int:
 
     if not args.no_inference:
         line["inference"] = _inference(w, Xd, Yd, args.transform, args.sigma, args.steps)
+    if not args.no_batch:
+        line["batch"] = _batch_workload(min(args.steps, 5))
 
     sample = None
     if not args.no_cpu_baseline or not args.no_fp64_single:
@@ -475,6 +479,82 @@ def _inference(w, Xd, Yd, transform, sigma, steps, n_query=1_000_000):
            "predict_points_per_s": round(n_query / (t_pred * 1e-3), 1),
            "band_halfwidth_median": float(torch.median(iv["upper"][fin] - iv["lower"][fin]).item() / 2),
            "plan": "FP32 spreading, %s transforms, h_min = h / sqrt 2" % transform}
+    del plan
+    return out
+
+
+def _batch_workload(reps):
+    """The batch workload on one GPU (Sec. 2.1, Fig. 3, Sec. 4.3), both parts
+    replayed as HIP graphs:
+    * its 256 independent regressions (N log-uniform in [1e3, 1e6], x ~
+      U[0,1]^2, M = 256^2, h = 0.05, 4 Philox probes each, fit + DF + GCV) in
+      one fkr_batch_cv call, with the lane count and job size the autotuner
+      picks, against the same batch on one lane (the regressions one after
+      another on one stream);
+    * the shared-grid DF sweep: N = 2e6 mixture samples, 64 probes x 32
+      log-spaced bandwidths in [0.01, 0.2], one fkr_cv call (one spread and
+      forward FFT of all 66 weight vectors, then channels, solves and
+      reductions per bandwidth)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2204_07716_amd import Batch, Plan
+    w = workloads.make("batch2d")
+    sizes = w.extra["regression_sizes"]
+    Xs, Ys = zip(*(workloads.independent_regression(w, k) for k in range(len(sizes))))
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(np.concatenate(Xs).astype(np.float32), device=dev)
+    Y = torch.as_tensor(np.concatenate(Ys).astype(np.float32), device=dev)
+    h = (w.extra["regression_h"],) * 2
+    Np = 4
+    b = Batch(2, 1, w.M, w.lo, w.hi, h, h, w.eps, precision="fp32", n_max=int(sizes.max()),
+              max_weights=2 + Np, n_lanes=8, transform_precision="fp64")
+
+    def replay_ms(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            res = fn()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, res
+
+    run = lambda: b.cv(off, X, h, Y, Np, seed=4100, want_mhat=False)   # noqa: E731
+    b.config(1)
+    t_loop, _ = replay_ms(run)
+    tuned = b.tune(off, X, h, Y, Np, seed=4100, reps=2)
+    t_batch, res = replay_ms(run)
+    n_tot = int(off[-1])
+    gcv = res["gcv"][:, 0, 0]
+    out = {"regressions": len(sizes), "samples": n_tot, "ms_batched": round(t_batch, 3),
+           "ms_one_lane": round(t_loop, 3), "samples_per_s": round(n_tot / (t_batch * 1e-3), 1),
+           "speedup_over_one_lane": round(t_loop / t_batch, 3), "tuned": tuned,
+           "finite_gcv": int(torch.isfinite(gcv).sum().item())}
+    del b
+    # the DF sweep
+    hs = w.h
+    Npd = w.n_probes
+    plan = Plan(2, 1, w.M, w.lo, w.hi, hs[0], hs[-1], w.eps, precision="fp32", n_max=w.N,
+                max_weights=2 + Npd, max_h=len(hs), transform_precision="fp64")
+    Xd = torch.as_tensor(w.X.astype(np.float32), device=dev)
+    Yd = torch.as_tensor(w.Y.astype(np.float32), device=dev)
+    plan.set_points(Xd)
+    t_df, r = replay_ms(lambda: plan.cv(hs, Yd, Npd, seed=w.probe_seed, want_mhat=False))
+    g2 = r["gcv"][:, 0]
+    out["df_sweep"] = {"N": w.N, "probes": Npd, "bandwidths": len(hs), "ms": round(t_df, 3),
+                       "probe_fits_per_s": round(w.N * Npd * len(hs) / (t_df * 1e-3), 1),
+                       "finite_gcv": int(torch.isfinite(g2).sum().item()),
+                       "note": "set_points outside the timed graph; one fkr_cv call per sweep"}
     del plan
     return out
 

@@ -328,6 +328,57 @@ fkr_status fkr_spline(fkr_plan* plan, int nv, const double* G_dev, double* coef_
 fkr_status fkr_predict(fkr_plan* plan, int nv, const double* coef_dev, int64_t Nq, const void* Xq_dev,
                        int x_type, double* out_dev, void* stream);
 
+/* Batches of independent regressions (Sec. 2.1 and Fig. 3: the cross-
+ * validation loop of one regression; Sec. 4.3: many responses): R
+ * regressions of uneven size on one plan geometry (the same grid, order,
+ * bandwidth range and precision), each run as fkr_set_points + fkr_cv.  A
+ * batch owns n_lanes plans, each with a HIP stream of its own (default
+ * priority, created by fkr_batch_create) and a slice of one caller-owned
+ * workspace.  fkr_batch_cv records an event on `stream`, lets the lanes wait
+ * on it, runs the regressions on the lanes, largest first, each to the lane
+ * with the least estimated work so far (N + 4 M^d sample equivalents per
+ * regression), and makes `stream` wait for every lane, so the whole batch is
+ * ordered on `stream` and can be captured into one HIP graph by capturing
+ * `stream`.
+ *   offsets: host array of R + 1 sample offsets (offsets[0] = 0,
+ *   nondecreasing, each regression at most desc.n_max samples); regression
+ *   r owns rows offsets[r] .. offsets[r+1] - 1 of X_dev (x_type) and Y_dev
+ *   (y_type, q columns, complex interleaved when y_complex) -- the layouts of
+ *   fkr_set_points and fkr_cv.  Its probes are those of fkr_cv with seed
+ *   `seed + r` (generated; Np >= 1).
+ *   Outputs (each optional), regression-major: mhat_dev [R][nh][q][M^d]
+ *   (complex: [..][2]), rho_dev [R][nh][Np], rss_dev and gcv_dev [R][nh][q],
+ *   nused_dev [R][nh].  A regression without samples gets NaN fits, ratios
+ *   and GCV and zero RSS and N_I.
+ * Errors: FKR_E_ARG for a bad offset list, sizes beyond the plan's maxima or
+ * bandwidths outside its range, all found before anything is enqueued. */
+typedef struct fkr_batch fkr_batch;
+fkr_status fkr_batch_create(const fkr_plan_desc* desc, int n_lanes, fkr_batch** out);
+void fkr_batch_destroy(fkr_batch* batch);
+fkr_status fkr_batch_workspace_size(const fkr_batch* batch, size_t* bytes);
+fkr_status fkr_batch_set_workspace(fkr_batch* batch, void* ws_dev, size_t bytes);
+fkr_status fkr_batch_cv(fkr_batch* batch, int R, const int64_t* offsets, const void* X_dev, int x_type,
+                        int nh, const double* h, int q, int y_complex, const void* Y_dev, int y_type,
+                        int Np, uint64_t seed, double* mhat_dev, double* rho_dev, double* rss_dev,
+                        double* gcv_dev, double* nused_dev, void* stream);
+
+/* Autotuner for a batch: runs the given batch (as fkr_batch_cv, outputs
+ * discarded) once to warm up and `reps` times timed with HIP events, for
+ * every lane count 1, 2, 4, .., n_lanes and, in 1-D and 2-D, for spreading
+ * jobs of 1, 2 and 4 times the plan's chunk of samples per tile piece; keeps
+ * the fastest configuration in the batch for later calls and reports it
+ * (lanes, chunk, ms per batch; each output may be NULL).  Synchronises
+ * `stream`; FKR_E_STATE when `stream` is being captured.  The outputs of
+ * fkr_batch_cv do not depend on the configuration beyond the order of
+ * floating-point sums.  fkr_batch_config sets a configuration directly
+ * (chunk 0 keeps the current one; chunks below the plan's own, or any chunk
+ * change in 3-D, are FKR_E_ARG). */
+fkr_status fkr_batch_tune(fkr_batch* batch, int R, const int64_t* offsets, const void* X_dev, int x_type,
+                          int nh, const double* h, int q, int y_complex, const void* Y_dev, int y_type,
+                          int Np, uint64_t seed, int reps, int* lanes, int64_t* chunk, double* ms,
+                          void* stream);
+fkr_status fkr_batch_config(fkr_batch* batch, int lanes, int64_t chunk);
+
 /* Bandwidth candidates (Sec. 4, get_hList), host only: n values from a to b
  * inclusive, log-spaced (kind 0, a > 0) or linearly spaced (kind 1). */
 fkr_status fkr_hlist(int n, double a, double b, int kind, double* out);

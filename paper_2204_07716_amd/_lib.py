@@ -51,7 +51,8 @@ EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_work
            "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_interval", "fkr_spline",
            "fkr_predict", "fkr_get_diagnostics",
            "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
-           "fkr_profile_read"]
+           "fkr_profile_read", "fkr_batch_create", "fkr_batch_destroy", "fkr_batch_workspace_size",
+           "fkr_batch_set_workspace", "fkr_batch_cv", "fkr_batch_tune", "fkr_batch_config"]
 
 STAGES = ["sort", "weights", "spread", "fold", "fft_fwd", "expand", "fft_inv", "solve", "reduce"]
 
@@ -101,6 +102,14 @@ def load() -> ctypes.CDLL:
         "fkr_select_bandwidth": ([I, pD, D, ctypes.POINTER(I)], I),
         "fkr_profile_enable": ([P, I], I),
         "fkr_profile_read": ([P, I, pD, ctypes.POINTER(I64)], I),
+        "fkr_batch_create": ([ctypes.POINTER(PlanDesc), I, ctypes.POINTER(P)], I),
+        "fkr_batch_destroy": ([P], None),
+        "fkr_batch_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
+        "fkr_batch_set_workspace": ([P, P, ctypes.c_size_t], I),
+        "fkr_batch_cv": ([P, I, P, P, I, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P], I),
+        "fkr_batch_tune": ([P, I, P, P, I, I, pD, I, I, P, I, I, U64, I, ctypes.POINTER(I),
+                            ctypes.POINTER(I64), pD, P], I),
+        "fkr_batch_config": ([P, I, I64], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfkr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "batch.cpp", "kernels.hip"]
 ARCH = os.environ.get("FKR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

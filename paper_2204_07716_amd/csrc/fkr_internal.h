@@ -16,6 +16,7 @@ constexpr int kMaxD = FKR_MAX_D;
 constexpr int kMaxFactors = 20;      // radix stages of one FFT length
 constexpr int kMaxChannels = 36;     // s-channels C(d+2l, 2l) <= 35 for d <= 3, l <= 2
 constexpr int kMaxP = 10;            // P = C(d+l, l) <= 10
+constexpr int kMaxBatchLanes = 16;   // plans (and streams) of one batch
 constexpr int kCoverSlots = 5;       // spreading tiles covering one fine cell (per dimension)
 constexpr int kMaxW = 24;            // widest spreading kernel (fine cells)
 
@@ -91,6 +92,7 @@ struct fkr_plan {
     int64_t n_max = 0;
     int max_weights = 1, max_h = 1, npairs_max = 1, ncp_max = 1;
     int64_t n_jobs_max = 1;
+    int64_t chunk_min = 1;   // the chunk the job table was sized for; a batch may lengthen jobs beyond it
     int es[fkr::kMaxChannels][fkr::kMaxD] = {};   // s-channel exponents
     int et[fkr::kMaxChannels][fkr::kMaxD] = {};   // t-channel exponents
     int pair_index[fkr::kMaxP][fkr::kMaxP] = {};  // s-channel of et[b] + et[c]

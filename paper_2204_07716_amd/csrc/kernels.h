@@ -226,6 +226,7 @@ void launch_kappa_partial(const Geo& g, int64_t N, int x_type, const void* xs, c
 void launch_sigma2(int64_t Mtot, const double* vhat, const double* kappa_sums, double* sigma2,
                    double* kappa_out, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 // The library-held workspace of the current device (fkr_fit_noalloc):
 // kStaticScratchBytes, 256-byte aligned.
 constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;

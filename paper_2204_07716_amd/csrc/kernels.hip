@@ -2301,6 +2301,11 @@ __global__ __launch_bounds__(256) void k_sigma2(int64_t Mtot, const double* vhat
     sigma2[k] = exp(vhat[k]) / kappa;
 }
 
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_zero(uint32_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -3260,6 +3265,10 @@ void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void
         case 2: k_interp<2><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
         default: k_interp<3><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
     }
+}
+
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+    if (n > 0) k_fill_f64<<<nblk(n), 256, 0, s>>>(p, n, v);
 }
 
 void launch_stage_grid(const Geo& g, int prec, const PointsCheck& pc, const void* xs, const double* G, void* rows,

@@ -404,6 +404,7 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
     // LDS the per-job cell sort stages them in; a dense 8^3-cell tile of
     // ~8000 samples is two jobs)
     p->chunk = p->d <= 2 ? 1024 : (p->prec == FKR_F32 ? 4800 : 2400);
+    p->chunk_min = p->chunk;
     p->n_jobs_max = p->n_tiles + (p->n_max + p->chunk - 1) / p->chunk + 1;
     p->npairs_max = (p->max_weights + 1) / 2;
     const int nreal = p->n_s + p->n_t * (p->max_weights - 1);

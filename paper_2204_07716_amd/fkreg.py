@@ -76,6 +76,100 @@ def select_bandwidth(gcv: Sequence[float], dstd: float = 0.0) -> int:
     return idx.value
 
 
+def _plan_desc(d, order, M, lo, hi, h_min, h_max, eps, precision, kernel, sigma, n_max, max_weights,
+               max_h, transform_precision):
+    desc = _lib.PlanDesc()
+    desc.d, desc.order = d, order
+    for j in range(d):
+        desc.M[j] = int(M[j])
+        desc.lo[j], desc.hi[j] = float(lo[j]), float(hi[j])
+        desc.h_min[j], desc.h_max[j] = float(h_min[j]), float(h_max[j])
+    desc.eps = float(eps)
+    desc.precision = _lib.FKR_F64 if precision == "fp64" else _lib.FKR_F32
+    desc.spread_kernel = _lib.FKR_KERNEL_ES if kernel == "es" else _lib.FKR_KERNEL_GAUSS
+    desc.sigma = float(sigma)
+    desc.n_max = int(n_max)
+    desc.max_weights = int(max_weights)
+    desc.max_h = int(max_h)
+    desc.transform_precision = {"same": _lib.FKR_TP_SAME, "fp32": _lib.FKR_TP_F32,
+                                "fp64": _lib.FKR_TP_F64}[transform_precision]
+    return desc
+
+
+class Batch:
+    """Independent regressions of uneven size on one plan geometry, run over
+    n_lanes plans and streams (fkr_batch_*)."""
+
+    def __init__(self, d: int, order: int, M: Sequence[int], lo: Sequence[float],
+                 hi: Sequence[float], h_min: Sequence[float], h_max: Sequence[float],
+                 eps: float, precision: str = "fp32", kernel: str = "es", sigma: float = 0.0,
+                 n_max: int = 0, max_weights: int = 2, max_h: int = 1, n_lanes: int = 4,
+                 device="cuda", transform_precision: str = "same"):
+        self.lib = _lib.load()
+        self.desc = _plan_desc(d, order, M, lo, hi, h_min, h_max, eps, precision, kernel, sigma, n_max,
+                               max_weights, max_h, transform_precision)
+        self.d = d
+        self.Mtot = int(np.prod([int(m) for m in M]))
+        self._b = ctypes.c_void_p()
+        check(self.lib.fkr_batch_create(ctypes.byref(self.desc), int(n_lanes), ctypes.byref(self._b)),
+              "fkr_batch_create")
+        size = ctypes.c_size_t()
+        check(self.lib.fkr_batch_workspace_size(self._b, ctypes.byref(size)), "fkr_batch_workspace_size")
+        self.workspace = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        check(self.lib.fkr_batch_set_workspace(self._b, ctypes.c_void_p(base + (-base) % 256), size),
+              "fkr_batch_set_workspace")
+        self.device = self.workspace.device
+
+    def __del__(self):
+        try:
+            if getattr(self, "_b", None) and self._b.value:
+                torch.cuda.synchronize(self.device)   # the lanes' streams may still run
+                self.lib.fkr_batch_destroy(self._b)
+                self._b = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def _args(self, offsets, X, h, Y):
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        X = X.contiguous()
+        Yr, q, cplx = _real_view(Y)
+        hb = _hbuf(h, self.d)
+        self._keep = (off, X, Yr, hb)
+        return off, X, Yr, q, cplx, hb
+
+    def cv(self, offsets, X: torch.Tensor, h, Y: torch.Tensor, Np: int, seed: int = 0,
+           want_mhat: bool = True) -> dict:
+        off, X, Yr, q, cplx, hb = self._args(offsets, X, h, Y)
+        R, nh = len(off) - 1, hb.shape[0]
+        dev = self.device
+        mhat = (torch.empty((R, nh, q, self.Mtot) + ((2,) if cplx else ()), dtype=torch.float64, device=dev)
+                if want_mhat else None)
+        rho = torch.empty((R, nh, Np), dtype=torch.float64, device=dev)
+        rss = torch.empty((R, nh, q), dtype=torch.float64, device=dev)
+        gcv = torch.empty((R, nh, q), dtype=torch.float64, device=dev)
+        nused = torch.empty((R, nh), dtype=torch.float64, device=dev)
+        check(self.lib.fkr_batch_cv(self._b, R, off.ctypes.data_as(ctypes.c_void_p), _ptr(X), _dtype_code(X), nh,
+                                    _hptr(hb), q, cplx, _ptr(Yr), _dtype_code(Yr), Np, ctypes.c_uint64(seed),
+                                    _ptr(mhat), _ptr(rho), _ptr(rss), _ptr(gcv), _ptr(nused), _stream()),
+              "fkr_batch_cv")
+        if mhat is not None and cplx:
+            mhat = torch.view_as_complex(mhat)
+        return {"mhat": mhat, "rho": rho, "rss": rss, "gcv": gcv, "nused": nused}
+
+    def tune(self, offsets, X: torch.Tensor, h, Y: torch.Tensor, Np: int, seed: int = 0, reps: int = 2) -> dict:
+        off, X, Yr, q, cplx, hb = self._args(offsets, X, h, Y)
+        lanes, chunk, ms = ctypes.c_int(), ctypes.c_int64(), ctypes.c_double()
+        check(self.lib.fkr_batch_tune(self._b, len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), _ptr(X),
+                                      _dtype_code(X), hb.shape[0], _hptr(hb), q, cplx, _ptr(Yr), _dtype_code(Yr),
+                                      Np, ctypes.c_uint64(seed), int(reps), ctypes.byref(lanes),
+                                      ctypes.byref(chunk), ctypes.byref(ms), _stream()), "fkr_batch_tune")
+        return {"lanes": lanes.value, "chunk": chunk.value, "ms": ms.value}
+
+    def config(self, lanes: int, chunk: int = 0) -> None:
+        check(self.lib.fkr_batch_config(self._b, int(lanes), ctypes.c_int64(chunk)), "fkr_batch_config")
+
+
 class Plan:
     """A plan bound to one device workspace (fkr_plan_create + fkr_set_workspace)."""
 

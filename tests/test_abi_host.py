@@ -233,3 +233,18 @@ def test_select_bandwidth_matches_oracle(lib):
             continue
         for dstd in (0.0, 0.1, 0.5, 1.0):
             assert select_bandwidth(g, dstd) == orc.rgcv_select(g, dstd), (g, dstd)
+
+
+def test_batch_create_rejects_lane_counts():
+    """fkr_batch_create checks its lane count before touching the device."""
+    from paper_2204_07716_amd import _lib
+    lib = _lib.load()
+    desc = _lib.PlanDesc()
+    desc.d, desc.order = 2, 1
+    for j in range(2):
+        desc.M[j], desc.lo[j], desc.hi[j], desc.h_min[j], desc.h_max[j] = 32, 0.0, 1.0, 0.1, 0.1
+    desc.eps, desc.precision, desc.n_max, desc.max_weights, desc.max_h = 1e-6, _lib.FKR_F32, 1000, 4, 1
+    out = ctypes.c_void_p()
+    for n in (0, -1, 17):
+        assert lib.fkr_batch_create(ctypes.byref(desc), n, ctypes.byref(out)) == _lib.FKR_E_ARG
+        assert not out.value
