@@ -286,6 +286,27 @@ fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const vo
                         int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
                         double* vhat_dev, double* kappa_dev, void* stream);
 
+/* Gradient of the GCV criterion of eq. (22) with respect to log h (Sec. 2.1:
+ * bandwidth selection minimises GCV over h) for one real response Y (N x 1,
+ * type y_type) and Np Philox probes (as fkr_cv with that seed).  The fits
+ * are m_hat = e_0^T A^{-1} t with the bandwidth-equilibrated moments A, t of
+ * eq. (11); their derivative in theta_j = log h_j is
+ * e_0^T A^{-1} (dt - dA A^{-1} t), where dA, dt come from the same type-1
+ * spectra multiplied by the derivative of the Gaussian moment multipliers,
+ * d/dtheta_j [He_a(u) exp(-u^2/2)] = -u He_{a+1}(u) exp(-u^2/2), u = h_j w_j.
+ * With the supported set I held fixed, dRSS = -2 sum_I r_i d yhat_i and
+ * d rho_p = -sum_I w_pi d what_pi / sum_I w_pi^2, so
+ * d GCV / d theta_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar).
+ * gcv_dev (optional, 1 double): GCV at h; dlogh_dev [d] doubles: the
+ * gradient; dfit_dev [d][1 + Np][M^d] doubles (caller-owned): d m_hat /
+ * d log h_j of y and of each probe fit, NaN where the fit is not resolved.
+ * The plan's channel buffer holds the channels at h and their derivatives
+ * side by side: FKR_E_ARG unless 2 ceil((n_s + n_t (1 + Np)) / 2) <=
+ * ceil((n_s + n_t (max_weights - 1)) / 2) (max_weights >= 2 (2 + Np) +
+ * n_s / n_t suffices). */
+fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, const void* Y_dev, int y_type, int Np, uint64_t seed,
+                        double* gcv_dev, double* dlogh_dev, double* dfit_dev, void* stream);
+
 /* Variance of the fit and pointwise confidence band (Sec. 4.2, eq. 27-28;
  * Sec. 4 fkreg_interval) at one bandwidth h (d doubles).  The fit of eq. (3)
  * is linear in y, m_hat(g) = sum_i S_gi y_i, so for independent errors of

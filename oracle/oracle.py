@@ -19,7 +19,9 @@ computes, by the plain definitions, slowly and in FP64:
 * ``dof``           Girard's fast Monte-Carlo estimate of (1/N) tr(I - S_h),
                     Sec. 2.1 steps i-iii.
 * ``gcv``           the GCV criterion of eq. (22); ``rgcv_select`` the relaxed
-                    selection rule of Table 1 (``dstd``).
+                    selection rule of Table 1 (``dstd``); ``gcv_criterion`` GCV
+                    as a function of h and ``gcv_log_h_gradient`` its gradient
+                    in log h by central differences.
 * ``variance``      the conditional-variance second pass of Sec. 3: the
                     log-residual fit of eq. (24)-(26) (default) or the direct
                     residual fit of eq. (23).
@@ -462,6 +464,40 @@ def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float, include=None) -> np.nd
     if include is not None:
         r = r[np.asarray(include, dtype=bool)]
     return np.mean(np.abs(r) ** 2, axis=0) / rho_mean ** 2
+
+
+def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None) -> float:
+    """GCV of eq. (22) at bandwidth h for one real response y, with the DF
+    from the probes Wp (``dof``), over the supported samples I (``include``,
+    else the support rule at h)."""
+    X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
+    W = np.concatenate([np.asarray(y, dtype=np.float64).reshape(-1, 1), Wp], axis=1)
+    gp = grid_points(M, lo, hi)
+    mh, S, T, r0, ill = fit(X, W, h, order, gp, return_all=True)
+    d = X.shape[1]
+    if include is None:
+        include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
+    include = np.asarray(include, dtype=bool)
+    F = interp(mh, M, lo, hi, X)
+    rho = girard_ratios(Wp[include], F[include, 1:])
+    return float(gcv(y, F[:, 0], float(np.mean(rho)), include=include)[0])
+
+
+def gcv_log_h_gradient(X, y, h, order, M, lo, hi, Wp, include=None, step: float = 1e-4) -> np.ndarray:
+    """d GCV / d log h_j by central differences of ``gcv_criterion`` (step
+    in log h), with the supported set held at that of h."""
+    h = np.asarray(h, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
+    if include is None:
+        include = support(X, h, order, M, lo, hi)[0]
+    out = np.empty(len(h))
+    for j in range(len(h)):
+        e = np.zeros(len(h))
+        e[j] = step
+        gp_ = gcv_criterion(X, y, h * np.exp(e), order, M, lo, hi, Wp, include)
+        gm_ = gcv_criterion(X, y, h * np.exp(-e), order, M, lo, hi, Wp, include)
+        out[j] = (gp_ - gm_) / (2.0 * step)
+    return out
 
 
 def rgcv_select(gcv_values: Sequence[float], dstd: float = 0.0) -> int:

@@ -245,11 +245,17 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
 // passes skip those pairs when the tag already matches (the density moments
 // depend on the points and h only); the decision is taken on the device, so a
 // captured graph stays valid whatever ran before its replay.
+// tag: 1 records the density tag (weight 0 is the unit density), 0 clears
+// it (weight 0 is not the density), 2 leaves it (the call writes only pairs
+// above the density moments).  deriv_dim >= 0 expands the derivatives of the
+// channels in log h of that dimension; pair_off places the channels that
+// many pairs up in the channel buffer.
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
-                        bool reuse = false, bool density = true) {
+                        bool reuse = false, int tag = 1, int deriv_dim = -1, int64_t pair_off = 0) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
-    if (ncp > p->ncp_max) return FKR_E_ARG;
+    if (ncp + pair_off > p->ncp_max) return FKR_E_ARG;
+    if (pair_off > 0 && reuse) return FKR_E_ARG;
     const bool even = p->n_s % 2 == 0;
     reuse = reuse && even;
     const int64_t c_keep = reuse ? p->n_s / 2 : 0;   // pairs a matching tag lets the passes skip
@@ -263,9 +269,10 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     for (int j = 0; j < p->d; ++j) { a.h[j] = h[j]; a.T[j] = p->T[j]; }
     a.Btot = p->Btot;
     a.ill_clear = ill_clear;
+    a.deriv_dim = deriv_dim;
     // the first inverse pass expands its rows from the pair spectra itself
     StageTimer tf(p, FKR_STAGE_FFT_INV, s);
-    void* chan_out = p->ws + p->lay.chan;
+    void* chan_out = p->ws + p->lay.chan + (size_t)pair_off * p->Mtot * 2 * elem_size(p->tprec);
     auto pass = [&](int j) {
         FftPass f{};
         f.n_in = p->B[j];
@@ -311,10 +318,8 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         launch_fft(p->tprec, true, f, in, out, s);
         in = out;
     }
-    // (density = false: weight 0 is not the unit density, so the buffer no
-    // longer holds density moments at any h)
-    if (!density) launch_chan_untag(diag_ptr(p), s);
-    else if (even) launch_chan_tag(diag_ptr(p), h, p->d, s);
+    if (tag == 0) launch_chan_untag(diag_ptr(p), s);
+    else if (tag == 1 && even) launch_chan_tag(diag_ptr(p), h, p->d, s);
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
@@ -848,7 +853,7 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
             srcs[r].stride = resid_row_stride(g, p->prec); srcs[r].col = r;
         }
         if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
-        if ((st = run_channels(p, h2, 1, nullptr, s, false, false)) != FKR_OK) return st;
+        if ((st = run_channels(p, h2, 1, nullptr, s, false, 0)) != FKR_OK) return st;
     }
     // 3. Sigma = scale r0^T Q r0, with Q re-equilibrated from h / sqrt 2 to h
     iv.P = p->n_t;
@@ -871,6 +876,66 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
         StageTimer t(p, FKR_STAGE_SOLVE, s);
         launch_interval(p->tprec, iv, p->ws + p->lay.chan, s);
     }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, const void* Y, int y_type, int Np, uint64_t seed,
+                        double* gcv, double* dlogh, double* dfit, void* stream) {
+    fkr_status st = common_fit_checks(p, 1, h, 1, 0, Y, y_type);
+    if (st != FKR_OK) return st;
+    if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
+    const int nr = 2 + Np;
+    const int ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;
+    const int n_items = 1 + Np;
+    const int nslot = p->d * n_items;
+    // the channels at h and their derivatives side by side; the gradient sums
+    // after the base sums
+    if (nr > p->max_weights || 2 * ncp > p->ncp_max) return FKR_E_ARG;
+    if ((int64_t)nslot * kRedBlocks > p->lay.cap_partial) return FKR_E_ARG;
+    if (2 * n_items + 1 + nslot > (int64_t)p->max_h * (2 * p->max_weights + 4)) return FKR_E_ARG;
+    const hipStream_t s = S(stream);
+    // base pass: fit, DF and GCV at h (spectra, channels in pairs [0, ncp),
+    // support flags, the fit of y, the sums)
+    if ((st = cv_impl(p, 1, h, 1, 0, Y, y_type, Np, seed, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, s)) != FKR_OK)
+        return st;
+    const Geo g = make_geo(p);
+    double* red = at<double>(p, p->lay.red);
+    double* gred = red + 2 * n_items + 1;
+    double* partial = at<double>(p, p->lay.partial);
+    const float* sup = at<float>(p, p->lay.sup);
+    const size_t pair_bytes = (size_t)p->Mtot * 2 * elem_size(p->tprec);
+    for (int j = 0; j < p->d; ++j) {
+        if ((st = run_channels(p, h, nr, nullptr, s, false, 2, j, ncp)) != FKR_OK) return st;
+        DSolveArgs a{};
+        a.P = p->n_t; a.n_s = p->n_s; a.n_t = p->n_t; a.ncp = ncp; a.nr = nr;
+        a.Mtot = p->Mtot;
+        a.sup = sup;
+        a.out = dfit + (int64_t)j * (nr - 1) * p->Mtot;
+        {
+            StageTimer t(p, FKR_STAGE_SOLVE, s);
+            launch_dsolve(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, p->ws + p->lay.chan + ncp * pair_bytes, s);
+        }
+        StageTimer t(p, FKR_STAGE_REDUCE, s);
+        for (int c0 = 0; c0 < n_items; c0 += 8) {
+            GradSumArgs r{};
+            r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
+            r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec;
+            r.wgstride = grouped_weights(p) ? 4 * p->N : 0;
+            r.wstride = r.wgstride ? 4 : (nr + 3) & ~3;
+            r.yfit = at<double>(p, p->lay.mhat);
+            r.dfit = a.out;
+            r.sup = sup;
+            r.ncol = std::min(8, n_items - c0);
+            r.col0 = c0;
+            r.slot0 = j * n_items + c0;
+            r.partial = partial;
+            launch_grad_sums(g, r, s);
+        }
+    }
+    launch_reduce_final(partial, nslot, gred, s);
+    launch_finalize_grad(p->d, Np, red, gred, gcv, dlogh, s);
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }

@@ -53,6 +53,35 @@ struct ExpandArgs {
     int64_t B[3], K[3], Btot;
     double h[3], T[3];       // bandwidth and period per dimension
     unsigned long long* ill_clear;   // cleared by the launch when given
+    int deriv_dim;           // >= 0: the multipliers' derivative in log h of this dimension
+};
+
+// Derivative of the fits in log h_j (one dimension per launch), per grid
+// point from the equilibrated channels at h (A, t) and their derivatives
+// (dA, dt): d m_hat = e_0^T A^{-1} (dt - dA A^{-1} t).
+struct DSolveArgs {
+    int P, n_s, n_t, ncp, nr;      // nr real weights incl. the density
+    int64_t Mtot;
+    const float* sup;              // [M] 0 where resolved (the base solve), NaN elsewhere
+    double* out;                   // [nr - 1][M]; NaN where not resolved
+};
+
+// Sums over the supported samples for the log-h gradient of GCV: column 0
+// sum r_i d yhat_i (r = y - yhat), column 1 + p sum w_pi d what_pi, for the
+// derivative grids of one dimension.
+struct GradSumArgs {
+    int64_t N;
+    int x_type;
+    const void* X;                 // sorted coordinates
+    const void* wsorted;           // staged weights: 1, y, probes
+    int w_type, wstride;
+    int64_t wgstride;
+    const double* yfit;            // [M] the base fit of y
+    const double* dfit;            // [1 + Np][M] derivative grids of this dimension
+    const float* sup;              // [M]
+    int ncol, col0;                // columns of this launch (<= 8), first column
+    int slot0;                     // first partial slot
+    double* partial;               // [slot][kRedBlocks]
 };
 
 // What a fold needs: the fine cell (c_0, .., c_{d-1}) of pair p is the sum
@@ -227,6 +256,11 @@ void launch_sigma2(int64_t Mtot, const double* vhat, const double* kappa_sums, d
                    double* kappa_out, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+void launch_dsolve(int prec, const DSolveArgs& a, const int* pidx, const void* chan_base, const void* chan_der,
+                   hipStream_t s);
+void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s);
+void launch_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
+                          hipStream_t s);
 // The library-held workspace of the current device (fkr_fit_noalloc):
 // kStaticScratchBytes, 256-byte aligned.
 constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;

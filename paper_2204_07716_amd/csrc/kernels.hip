@@ -1507,19 +1507,18 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
         rem = qj;
         nn += (bj - 1 - (unsigned)ej) * stride;
         stride *= bj;
-        // multiplier of degree k: He_k(u) exp(-u^2 / 2) / T_j, u = h_j 2 pi (e_j - K_j) / T_j
+        // multiplier of degree k: He_k(u) exp(-u^2 / 2) / T_j, u = h_j 2 pi (e_j - K_j) / T_j;
+        // its derivative in log h_j is u d/du of it, -u He_{k+1}(u) exp(-u^2 / 2) / T_j
         const double u = a.h[j] * (2.0 * M_PI * (double)(ej - a.K[j]) / a.T[j]);
         const double gj = exp(-0.5 * u * u) / a.T[j];
-        double hm = 1.0, he = u;
-        mloc[j][0][tid] = gj;
-        mloc[j][1][tid] = u * gj;
+        double he[kExpandDeg + 1];
+        he[0] = 1.0;
+        he[1] = u;
 #pragma unroll
-        for (int k = 1; k + 1 < kExpandDeg; ++k) {
-            const double hn = u * he - k * hm;
-            hm = he;
-            he = hn;
-            mloc[j][k + 1][tid] = he * gj;
-        }
+        for (int k = 1; k < kExpandDeg; ++k) he[k + 1] = u * he[k] - k * he[k - 1];
+        const bool dj = j == a.deriv_dim;
+#pragma unroll
+        for (int k = 0; k < kExpandDeg; ++k) mloc[j][k][tid] = (dj ? -u * he[k + 1] : he[k]) * gj;
     }
     // real weight spectra C_r(n), r = 2 p + half, from Z_p(n) and Z_p(-n)
     const int np_lds = min(a.npairs, kExpandCols / 2);
@@ -1681,6 +1680,82 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a, const int* pidx, con
             if (a.probe_f32) static_cast<float*>(a.probe_out)[o] = (float)mr;
             else static_cast<double*>(a.probe_out)[o] = mr;
         }
+    }
+}
+
+// Derivatives of the fits in log h_j, one grid point per thread (resolved
+// points only): the Cholesky factor of the equilibrated matrix A at h, then
+// for every weight m = A^{-1} t and d m_hat = e_0^T A^{-1} (dt - dA m), the
+// channels dA, dt being those of the derivative multipliers.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_dsolve(DSolveArgs a, const int* pidx, const T* cb, const T* cd) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.Mtot) return;
+    const double nan = __builtin_nan("");
+    if (!(a.sup[k] == 0.f)) {
+        for (int r = 1; r < a.nr; ++r) a.out[(r - 1) * a.Mtot + k] = nan;
+        return;
+    }
+    auto chb = [&](int r) { return (double)cb[(((int64_t)(r >> 1)) * a.Mtot + k) * 2 + (r & 1)]; };
+    auto chd = [&](int r) { return (double)cd[(((int64_t)(r >> 1)) * a.Mtot + k) * 2 + (r & 1)]; };
+    double L[P][P], dA[P][P];
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+#pragma unroll
+        for (int c = 0; c <= b; ++c) {
+            const int sidx = pidx[b * kMaxP + c];
+            L[b][c] = chb(sidx);
+            dA[b][c] = chd(sidx);
+            dA[c][b] = dA[b][c];
+        }
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        double v = L[c][c];
+#pragma unroll
+        for (int q = 0; q < c; ++q) v -= L[c][q] * L[c][q];
+        L[c][c] = sqrt(fmax(v, 1e-300));
+#pragma unroll
+        for (int b = c + 1; b < P; ++b) {
+            double u = L[b][c];
+#pragma unroll
+            for (int q = 0; q < c; ++q) u -= L[b][q] * L[c][q];
+            L[b][c] = u / L[c][c];
+        }
+    }
+    // x = A^{-1} v by the two triangular solves
+    auto solve = [&](double (&v)[P]) {
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+#pragma unroll
+            for (int q = 0; q < b; ++q) v[b] -= L[b][q] * v[q];
+            v[b] /= L[b][b];
+        }
+#pragma unroll
+        for (int b = P - 1; b >= 0; --b) {
+#pragma unroll
+            for (int q = b + 1; q < P; ++q) v[b] -= L[q][b] * v[q];
+            v[b] /= L[b][b];
+        }
+    };
+    double c0[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) c0[b] = b == 0 ? 1.0 : 0.0;
+    solve(c0);
+    for (int r = 1; r < a.nr; ++r) {
+        const int t0 = a.n_s + (r - 1) * a.n_t;
+        double m[P];
+#pragma unroll
+        for (int b = 0; b < P; ++b) m[b] = chb(t0 + b);
+        solve(m);
+        double dm = 0.0;
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            double v = chd(t0 + b);
+#pragma unroll
+            for (int c = 0; c < P; ++c) v -= dA[b][c] * m[c];
+            dm += c0[b] * v;
+        }
+        a.out[(r - 1) * a.Mtot + k] = dm;
     }
 }
 
@@ -2195,6 +2270,77 @@ __global__ void k_finalize_cv(int hidx, int Np, int q, const double* red, int n_
         const double rss = red[2 * c];
         if (rss_out) rss_out[(int64_t)hidx * q + c] = rss;
         if (gcv_out) gcv_out[(int64_t)hidx * q + c] = (rss / n_used) / (mean * mean);
+    }
+}
+
+// Gradient sums over the supported samples (all 2^d corners of the cell
+// resolved), in sorted order: column 0 sum r d yhat with r = y - yhat,
+// columns 1 + p sum w_p d w_hat_p, for up to eight columns per launch.
+template <int D, typename TW>
+__global__ __launch_bounds__(256) void k_grad_sums(Geo g, GradSumArgs a) {
+    constexpr int NA = 8;
+    __shared__ double sh[NA * 256];
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    const TW* W = static_cast<const TW*>(a.wsorted);
+    auto wcol = [&](int64_t s, int col) {
+        return (double)(a.wgstride ? W[(col >> 2) * a.wgstride + s * 4 + (col & 3)] : W[s * a.wstride + col]);
+    };
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.N; s += (int64_t)gridDim.x * blockDim.x) {
+        const Corners<D> c = corners<D>(g, a.x_type, a.X, s);
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < (1 << D); ++q) ok &= a.sup[c.idx[q]] == 0.f;
+        if (!ok) continue;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            if (q >= a.ncol) break;
+            const int col = a.col0 + q;
+            const double* gd = a.dfit + (int64_t)col * g.Mtot;
+            double dv = 0.0;
+#pragma unroll
+            for (int e = 0; e < (1 << D); ++e) dv += c.w[e] * gd[c.idx[e]];
+            double coef;
+            if (col == 0) {
+                double yh = 0.0;
+#pragma unroll
+                for (int e = 0; e < (1 << D); ++e) yh += c.w[e] * a.yfit[c.idx[e]];
+                coef = wcol(s, 1) - yh;
+            } else {
+                coef = wcol(s, 1 + col);
+            }
+            acc[q] += coef * dv;
+        }
+    }
+    block_sum<NA>(acc, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < a.ncol; ++q) a.partial[(int64_t)(a.slot0 + q) * kRedBlocks + blockIdx.x] = acc[q];
+}
+
+// d GCV / d log h_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar), dRSS = -2 sum r
+// d yhat, d rho_p = -sum w_p d w_hat_p / sum w_p^2 (the supported set fixed).
+__global__ void k_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv_out,
+                                double* dlogh) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int n_items = 1 + Np;
+    const double n_used = red[2 * n_items];
+    const double rss = red[0];
+    double mean = 0.0;
+    for (int p = 0; p < Np; ++p) {
+        const double ww = red[2 * (1 + p)], wh = red[2 * (1 + p) + 1];
+        mean += (ww - wh) / ww;
+    }
+    mean /= Np;
+    const double gcv = (rss / n_used) / (mean * mean);
+    if (gcv_out) *gcv_out = gcv;
+    for (int j = 0; j < d; ++j) {
+        const double* gj = gred + (int64_t)j * n_items;
+        const double drss = -2.0 * gj[0];
+        double dmean = 0.0;
+        for (int p = 0; p < Np; ++p) dmean += -gj[1 + p] / red[2 * (1 + p)];
+        dmean /= Np;
+        dlogh[j] = gcv * (drss / rss - 2.0 * dmean / mean);
     }
 }
 
@@ -3265,6 +3411,33 @@ void launch_interp(const Geo& g, int nv, const double* G, int64_t Nq, const void
         case 2: k_interp<2><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
         default: k_interp<3><<<nblk(Nq), 256, 0, s>>>(g, nv, G, Nq, X, x_type, out); break;
     }
+}
+
+void launch_dsolve(int prec, const DSolveArgs& a, const int* pidx, const void* chan_base, const void* chan_der,
+                   hipStream_t s) {
+#define FKR_DS(P, T) k_dsolve<P, T><<<nblk(a.Mtot), 256, 0, s>>>(a, pidx, static_cast<const T*>(chan_base), \
+                                                                 static_cast<const T*>(chan_der))
+#define FKR_DS_P(T) do { switch (a.P) { case 1: FKR_DS(1, T); break; case 2: FKR_DS(2, T); break; \
+    case 3: FKR_DS(3, T); break; case 4: FKR_DS(4, T); break; case 6: FKR_DS(6, T); break; \
+    default: FKR_DS(10, T); break; } } while (0)
+    if (prec == FKR_F64) FKR_DS_P(double); else FKR_DS_P(float);
+#undef FKR_DS_P
+#undef FKR_DS
+}
+
+void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s) {
+#define FKR_GS(D, TW) k_grad_sums<D, TW><<<kRedBlocks, 256, 0, s>>>(g, a)
+    if (a.w_type == FKR_F64) {
+        if (g.d == 1) FKR_GS(1, double); else if (g.d == 2) FKR_GS(2, double); else FKR_GS(3, double);
+    } else {
+        if (g.d == 1) FKR_GS(1, float); else if (g.d == 2) FKR_GS(2, float); else FKR_GS(3, float);
+    }
+#undef FKR_GS
+}
+
+void launch_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
+                          hipStream_t s) {
+    k_finalize_grad<<<1, 64, 0, s>>>(d, Np, red, gred, gcv, dlogh);
 }
 
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {

@@ -76,6 +76,24 @@ def select_bandwidth(gcv: Sequence[float], dstd: float = 0.0) -> int:
     return idx.value
 
 
+class GCVLogH(torch.autograd.Function):
+    """GCV (eq. 22) of one real response as a function of log h, with the
+    library's hand-written gradient as its backward: ``GCVLogH.apply(log_h,
+    plan, Y, Np, seed)`` with log_h a tensor of d entries."""
+
+    @staticmethod
+    def forward(ctx, log_h, plan, Y, Np, seed):
+        h = torch.exp(log_h.detach().to(torch.float64)).cpu().numpy()
+        out = plan.gcv_grad(h, Y, Np, seed)
+        ctx.save_for_backward(out["dlogh"].to(log_h.device, log_h.dtype))
+        return out["gcv"][0].to(log_h.device, log_h.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (dl,) = ctx.saved_tensors
+        return grad_out * dl, None, None, None, None
+
+
 def _plan_desc(d, order, M, lo, hi, h_min, h_max, eps, precision, kernel, sigma, n_max, max_weights,
                max_h, transform_precision):
     desc = _lib.PlanDesc()
@@ -356,6 +374,20 @@ class Plan:
                                     md, _ptr(sigma2), _ptr(vhat), _ptr(kappa), _stream()),
               "fkr_variance")
         return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
+
+    # -- differentiation ------------------------------------------------
+    def gcv_grad(self, h, Y: torch.Tensor, Np: int, seed: int = 0) -> dict:
+        """GCV at h for one real response with Np Philox probes, its gradient
+        in log h [d], and d m_hat / d log h_j of y and the probes [d][1+Np][M]."""
+        hb = _hbuf(h, self.d)
+        assert hb.shape[0] == 1, "one bandwidth"
+        Yr = Y.reshape(-1, 1).contiguous()
+        gcv = torch.empty(1, dtype=torch.float64, device=self.device)
+        dlogh = torch.empty(self.d, dtype=torch.float64, device=self.device)
+        dfit = torch.empty((self.d, 1 + Np, self.Mtot), dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_gcv_grad(self._plan, _hptr(hb), _ptr(Yr), _dtype_code(Yr), Np, ctypes.c_uint64(seed),
+                                    _ptr(gcv), _ptr(dlogh), _ptr(dfit), _stream()), "fkr_gcv_grad")
+        return {"gcv": gcv, "dlogh": dlogh, "dfit": dfit}
 
     # -- prediction and inference ---------------------------------------
     def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05):

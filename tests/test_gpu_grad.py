@@ -1,0 +1,101 @@
+"""GPU parity of the GCV gradient in log h (eq. 22, Sec. 2.1): the library's
+hand-written derivative (derivative moment multipliers, the derivative of
+the normal-equation solve, sums over the supported samples) against central
+differences of the GPU's own GCV and fits, against the oracle's gradient, and
+through torch.autograd."""
+import numpy as np
+import pytest
+
+from gpu_common import make_plan, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _setup(d, N, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.random((N, d))
+    y = np.sin(3 * X).sum(axis=1) + 0.3 * rng.standard_normal(N)
+    M, h = {1: ((60,), (0.06,)), 2: ((30, 26), (0.1, 0.12)), 3: ((12, 11, 10), (0.17, 0.16, 0.18))}[d]
+    return X, y, M, np.array(h)
+
+
+def _plan(d, M, h, N, Np, prec, tprec, order=1):
+    n_s = {1: 3, 2: 6, 3: 10}[d] if order == 1 else None
+    n_t = d + 1
+    mw = 2 * (2 + Np) + n_s // n_t + 2
+    return make_plan(d, order, M, tuple(0.9 * h), tuple(1.1 * h), 1e-10 if prec == "fp64" else 1e-6, prec,
+                     n_max=N, max_weights=mw, max_h=1, tprec=tprec)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_gcv_grad_matches_finite_differences(d):
+    """FP64 path: the gradient and the derivative grids d m_hat / d log h_j
+    against central differences (step 1e-4 in log h) of the GPU's own GCV
+    and fits; the supported set does not change across the steps."""
+    N, Np, seed = 3000, 6, 21
+    X, y, M, h = _setup(d, N, 500 + d)
+    plan = _plan(d, M, h, N, Np, "fp64", "same")
+    plan.set_points(to_dev(X))
+    Y = to_dev(y[:, None])
+    out = plan.gcv_grad(h, Y, Np, seed)
+    g = out["dlogh"].cpu().numpy()
+    dfit = out["dfit"].cpu().numpy()
+    base = plan.cv(h, Y, Np, seed=seed)
+    assert out["gcv"].item() == pytest.approx(base["gcv"].item(), rel=1e-12)
+    st = 1e-4
+    for j in range(d):
+        e = np.zeros(d)
+        e[j] = st
+        up = plan.cv(h * np.exp(e), Y, Np, seed=seed)
+        dn = plan.cv(h * np.exp(-e), Y, Np, seed=seed)
+        assert up["nused"].item() == dn["nused"].item() == base["nused"].item()
+        fd = (up["gcv"].item() - dn["gcv"].item()) / (2 * st)
+        print(f"d={d} j={j}: grad {g[j]:.8e} fd {fd:.8e}")
+        assert g[j] == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(base["gcv"].item()))
+        fdm = (up["mhat"].cpu().numpy()[0, 0] - dn["mhat"].cpu().numpy()[0, 0]) / (2 * st)
+        fin = np.isfinite(dfit[j, 0])
+        scale = np.abs(fdm[fin]).max()
+        assert np.abs(dfit[j, 0][fin] - fdm[fin]).max() < 1e-6 * scale
+
+
+@pytest.mark.parametrize("d,prec,tprec", [(1, "fp64", "same"), (2, "fp32", "fp64"), (3, "fp32", "fp64")])
+def test_gcv_grad_matches_oracle(orc, d, prec, tprec):
+    """Against the oracle's gradient (central differences of the plain GCV
+    with the same Philox probes and the supported set of h)."""
+    N, Np, seed = 2500, 6, 33
+    X, y, M, h = _setup(d, N, 600 + d)
+    plan = _plan(d, M, h, N, Np, prec, tprec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    plan.set_points(to_dev(X, dt))
+    out = plan.gcv_grad(h, to_dev(y[:, None], dt), Np, seed)
+    g = out["dlogh"].cpu().numpy()
+    Xr = X.astype(np.float32).astype(np.float64) if prec == "fp32" else X
+    yr = y.astype(np.float32).astype(np.float64) if prec == "fp32" else y
+    Wp = orc.probes(seed, N, Np)
+    if prec == "fp32":
+        Wp = Wp.astype(np.float32).astype(np.float64)
+    lo, hi = (0.0,) * d, (1.0,) * d
+    inc = orc.support(Xr, h, 1, M, lo, hi)[0]
+    assert inc.all()
+    ref_g = orc.gcv_criterion(Xr, yr, h, 1, M, lo, hi, Wp, inc)
+    ref = orc.gcv_log_h_gradient(Xr, yr, h, 1, M, lo, hi, Wp, include=inc, step=1e-4)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print(f"d={d} {prec}: gcv {out['gcv'].item():.10e} / {ref_g:.10e}; grad {g} / {ref}; rel err {err:.2e}")
+    assert out["gcv"].item() == pytest.approx(ref_g, rel=1e-9 if prec == "fp64" else 1e-5)
+    assert err < (1e-6 if prec == "fp64" else 1e-5)   # FP64: the oracle's central differences (step 1e-4)
+
+
+def test_gcv_autograd_backward():
+    from paper_2204_07716_amd import GCVLogH
+    N, Np, seed, d = 2000, 4, 5, 2
+    X, y, M, h = _setup(d, N, 700)
+    plan = _plan(d, M, h, N, Np, "fp32", "fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    Y = to_dev(y[:, None], torch.float32)
+    log_h = torch.tensor(np.log(h), dtype=torch.float64, requires_grad=True)
+    gcv = GCVLogH.apply(log_h, plan, Y, Np, seed)
+    gcv.backward()
+    ref = plan.gcv_grad(h, Y, Np, seed)
+    assert gcv.item() == pytest.approx(ref["gcv"].item(), rel=1e-12)
+    np.testing.assert_allclose(log_h.grad.numpy(), ref["dlogh"].cpu().numpy(), rtol=1e-12)

@@ -659,3 +659,46 @@ def test_interval_quantile(orc):
     lo, hi = orc.interval(np.array([1.0, -2.0]), np.array([4.0, 0.25]), alpha=0.05)
     np.testing.assert_allclose(hi - lo, 2 * 1.959963984540054 * np.array([2.0, 0.5]), rtol=1e-15)
     np.testing.assert_allclose((hi + lo) / 2, [1.0, -2.0], rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# The GCV criterion as a function of log h and its gradient (eq. 22, Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def test_gcv_gradient_step_independent_and_vanishes_in_ols_limit(orc):
+    """The central-difference gradient agrees for two steps (an O(step^2)
+    scheme: a dropped or mis-scaled term would not); at bandwidths far above
+    the data span the local fit is the global OLS fit, independent of h, so
+    the gradient vanishes."""
+    rng = np.random.default_rng(12)
+    N = 400
+    X = rng.random((N, 2))
+    y = np.sin(3 * X[:, 0]) + X[:, 1] + 0.3 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 4))
+    M, lo, hi = (12, 10), (0.0, 0.0), (1.0, 1.0)
+    h = np.array([0.15, 0.2])
+    g1 = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, step=1e-3)
+    g2 = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, step=5e-4)
+    np.testing.assert_allclose(g1, g2, rtol=2e-5)
+    # the approach to the OLS limit is O((span / h)^2): the gradient falls
+    # about a hundredfold from h = 300 to h = 3000
+    g300 = orc.gcv_log_h_gradient(X, y, np.array([300.0, 300.0]), 1, M, lo, hi, Wp, step=1e-3)
+    g3000 = orc.gcv_log_h_gradient(X, y, np.array([3000.0, 3000.0]), 1, M, lo, hi, Wp, step=1e-3)
+    G = orc.gcv_criterion(X, y, np.array([3000.0, 3000.0]), 1, M, lo, hi, Wp)
+    assert np.abs(g3000).max() < 1e-7 * G
+    assert 50 < abs(g300[0] / g3000[0]) < 200
+
+
+def test_gcv_gradient_symmetric_design(orc):
+    """A design and response symmetric under swapping the two coordinates
+    (each sample also present with x_1 and x_2 exchanged) has equal partial
+    derivatives at equal bandwidths."""
+    rng = np.random.default_rng(13)
+    X0 = rng.random((150, 2))
+    X = np.concatenate([X0, X0[:, ::-1]])
+    y = np.cos(2 * X[:, 0]) + np.cos(2 * X[:, 1])
+    y = y + 0.2 * np.concatenate([e := rng.standard_normal(150), e])
+    Wp0 = rng.standard_normal((150, 3))
+    Wp = np.concatenate([Wp0, Wp0])
+    g = orc.gcv_log_h_gradient(X, y, np.array([0.2, 0.2]), 1, (9, 9), (0.0, 0.0), (1.0, 1.0), Wp)
+    assert g[0] == pytest.approx(g[1], rel=1e-8)
