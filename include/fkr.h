@@ -297,15 +297,25 @@ fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const vo
  * With the supported set I held fixed, dRSS = -2 sum_I r_i d yhat_i and
  * d rho_p = -sum_I w_pi d what_pi / sum_I w_pi^2, so
  * d GCV / d theta_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar).
+ * The gradient in y (the DF does not depend on y) is
+ * d GCV / dy = 2 / (N_I rho_bar^2) (r - S^T r), r_i = y_i - yhat_i on the
+ * supported samples and 0 elsewhere, with the adjoint of the smoother
+ * (S^T r)_l = sum_g sum_b u(g) c_b(g) k_b(x_l - g): u the residuals scattered
+ * to the grid by the interpolation weights, c = A^{-1} e_0 and k_b the
+ * equilibrated moment kernels; the sum over g runs as a type-2 transform
+ * (the adjoint of the spread: forward FFT of the zero-padded grid functions,
+ * conjugate moment multipliers, inverse FFT to the fine grid, the spreading
+ * kernel at each sample).
  * gcv_dev (optional, 1 double): GCV at h; dlogh_dev [d] doubles: the
- * gradient; dfit_dev [d][1 + Np][M^d] doubles (caller-owned): d m_hat /
+ * gradient in log h; dy_dev (optional, [N] doubles, the order of Y): the
+ * gradient in y; dfit_dev [d][1 + Np][M^d] doubles (caller-owned): d m_hat /
  * d log h_j of y and of each probe fit, NaN where the fit is not resolved.
  * The plan's channel buffer holds the channels at h and their derivatives
  * side by side: FKR_E_ARG unless 2 ceil((n_s + n_t (1 + Np)) / 2) <=
  * ceil((n_s + n_t (max_weights - 1)) / 2) (max_weights >= 2 (2 + Np) +
  * n_s / n_t suffices). */
 fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, const void* Y_dev, int y_type, int Np, uint64_t seed,
-                        double* gcv_dev, double* dlogh_dev, double* dfit_dev, void* stream);
+                        double* gcv_dev, double* dlogh_dev, double* dy_dev, double* dfit_dev, void* stream);
 
 /* Variance of the fit and pointwise confidence band (Sec. 4.2, eq. 27-28;
  * Sec. 4 fkreg_interval) at one bandwidth h (d doubles).  The fit of eq. (3)

@@ -21,7 +21,8 @@ computes, by the plain definitions, slowly and in FP64:
 * ``gcv``           the GCV criterion of eq. (22); ``rgcv_select`` the relaxed
                     selection rule of Table 1 (``dstd``); ``gcv_criterion`` GCV
                     as a function of h and ``gcv_log_h_gradient`` its gradient
-                    in log h by central differences.
+                    in log h by central differences; ``gcv_y_gradient`` its
+                    gradient in y from the explicit smoother.
 * ``variance``      the conditional-variance second pass of Sec. 3: the
                     log-residual fit of eq. (24)-(26) (default) or the direct
                     residual fit of eq. (23).
@@ -498,6 +499,32 @@ def gcv_log_h_gradient(X, y, h, order, M, lo, hi, Wp, include=None, step: float 
         gm_ = gcv_criterion(X, y, h * np.exp(-e), order, M, lo, hi, Wp, include)
         out[j] = (gp_ - gm_) / (2.0 * step)
     return out
+
+
+def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None) -> np.ndarray:
+    """d GCV / dy of ``gcv_criterion`` from its definition: the fitted
+    values are yhat = S y with the smoother S (samples to samples through the
+    grid fit and the interpolation) built column by column from the fits of
+    the unit responses; the Girard ratios do not depend on y, so with
+    r = (y - S y) on the supported samples I,
+    d GCV / dy = 2 / (N_I rho_bar^2) (r - S_I^T r_I)."""
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    N = len(y)
+    X = np.asarray(X, dtype=np.float64).reshape(N, -1)
+    d = X.shape[1]
+    gp = grid_points(M, lo, hi)
+    mh, S, T, r0, ill = fit(X, np.concatenate([np.eye(N), Wp], axis=1), h, order, gp, return_all=True)
+    if include is None:
+        include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
+    include = np.asarray(include, dtype=bool)
+    F = interp(mh, M, lo, hi, X)
+    Smat = F[include, :N]                       # rows of the supported samples
+    rho = girard_ratios(Wp[include], F[include, N:])
+    m = float(np.mean(rho))
+    r = y[include] - Smat @ y
+    g = np.zeros(N)
+    g[include] = r
+    return 2.0 / (include.sum() * m * m) * (g - Smat.T @ r)
 
 
 def rgcv_select(gcv_values: Sequence[float], dstd: float = 0.0) -> int:

@@ -880,8 +880,100 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
+// Gradient of GCV in y after the base pass at h (channels at h in the first
+// pairs, support flags, the fit of y, the sums): c = A^{-1} e_0, u = P^T r,
+// the type-2 path of v_b = u c_b to the fine grid, the gather at the samples.
+// u uses `scratch` ([M] doubles).
+fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, double* scratch, double* dy, hipStream_t s) {
+    const Geo g = make_geo(p);
+    const int P = p->n_t;
+    const int npv = (P + 1) / 2;
+    SolveArgs a = solve_args(p, 1, 0, 0, h);
+    a.r0_out = at<double>(p, p->lay.r0);
+    a.ill_count = nullptr;   // counted by the base solve
+    launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    const int64_t wgstride = grouped_weights(p) ? 4 * p->N : 0;
+    const int wstride = wgstride ? 4 : (nr + 3) & ~3;
+    const double* yfit = at<double>(p, p->lay.mhat);
+    const float* sup = at<float>(p, p->lay.sup);
+    launch_fill_f64(scratch, p->Mtot, 0.0, s);
+    launch_adj_scatter(g, p->N, p->prec, p->ws + p->lay.xs, p->ws + p->lay.wsort, wstride, wgstride, yfit, sup,
+                       scratch, s);
+    void* bufs[2] = {p->ws + p->lay.fftA, p->ws + p->lay.fftB};
+    int cur = 0;
+    launch_adj_pack(p->tprec, P, p->Mtot, scratch, at<double>(p, p->lay.r0), bufs[cur], s);
+    // grid (zero-padded to the period L) -> band, each pass moving its axis
+    // to the end as the forward passes of the spread do: [band index][pair]
+    int64_t done_B = 1;
+    for (int j = 0; j < p->d; ++j) {
+        FftPass f{};
+        int64_t rest = 1;
+        for (int i = j + 1; i < p->d; ++i) rest *= p->M[i];
+        f.rows = done_B * npv * rest;
+        f.n_in = p->M[j];
+        f.F = p->L[j];
+        f.n_out = p->B[j];
+        f.K = p->K[j];
+        f.in_band = 0;
+        f.out_band = 1;
+        f.nfac = p->fL[j].nfac;
+        for (int q = 0; q < p->fL[j].nfac; ++q) f.fac[q] = p->fL[j].fac[q];
+        f.tw = at<double>(p, p->fL[j].tw_off);
+        if (j == p->d - 1) {
+            f.out_estride = done_B * npv;
+            f.out_rdiv = npv;
+            f.out_rmul = npv;
+        } else {
+            f.out_estride = f.rows;
+            f.out_rdiv = f.rows;
+            f.out_rmul = 0;
+        }
+        launch_fft(p->tprec, false, f, bufs[cur], bufs[1 - cur], s);
+        cur = 1 - cur;
+        done_B *= p->B[j];
+    }
+    ExpandArgs ea{};
+    ea.d = p->d;
+    for (int j = 0; j < 3; ++j) { ea.B[j] = p->B[j]; ea.K[j] = p->K[j]; }
+    for (int j = 0; j < p->d; ++j) { ea.h[j] = h[j]; ea.T[j] = p->T[j]; }
+    ea.Btot = p->Btot;
+    ea.deriv_dim = -1;
+    launch_adj_combine(p->tprec, ea, P, dev_et(p), at<double>(p, p->lay.deconv), bufs[cur], bufs[1 - cur], s);
+    cur = 1 - cur;
+    // band -> fine grid along dimensions d-1 .. 0 (the inverse passes of the
+    // channels with the fine grid's length and no crop)
+    for (int j = p->d - 1; j >= 0; --j) {
+        FftPass f{};
+        int64_t R = 1;
+        for (int i = 0; i < j; ++i) R *= p->B[i];
+        for (int i = j + 1; i < p->d; ++i) R *= p->Mr[i];
+        f.rows = R;
+        f.n_in = p->B[j];
+        f.F = p->Mr[j];
+        f.n_out = p->Mr[j];
+        f.K = p->K[j];
+        f.in_band = 1;
+        f.out_band = 0;
+        f.nfac = p->fMr[j].nfac;
+        for (int q = 0; q < p->fMr[j].nfac; ++q) f.fac[q] = p->fMr[j].fac[q];
+        f.tw = at<double>(p, p->fMr[j].tw_off);
+        f.in_rdiv = R;
+        f.in_rmul = p->B[j] * R;
+        f.in_estride = R;
+        f.out_estride = 1;
+        f.out_rdiv = 1;
+        f.out_rmul = p->Mr[j];
+        launch_fft(p->tprec, true, f, bufs[cur], bufs[1 - cur], s);
+        cur = 1 - cur;
+    }
+    launch_adj_gather(g, p->tprec, p->kernel, p->N, Np, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
+                      bufs[cur], yfit, sup, p->ws + p->lay.wsort, p->prec, wstride, wgstride,
+                      at<double>(p, p->lay.red), dy, s);
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
 fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, const void* Y, int y_type, int Np, uint64_t seed,
-                        double* gcv, double* dlogh, double* dfit, void* stream) {
+                        double* gcv, double* dlogh, double* dy, double* dfit, void* stream) {
     fkr_status st = common_fit_checks(p, 1, h, 1, 0, Y, y_type);
     if (st != FKR_OK) return st;
     if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
@@ -900,6 +992,10 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, const void* Y, int y_type,
     if ((st = cv_impl(p, 1, h, 1, 0, Y, y_type, Np, seed, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                       nullptr, s)) != FKR_OK)
         return st;
+    if (dy) {
+        StageTimer t(p, FKR_STAGE_REDUCE, s);
+        if ((st = grad_y(p, h, Np, nr, dfit, dy, s)) != FKR_OK) return st;
+    }
     const Geo g = make_geo(p);
     double* red = at<double>(p, p->lay.red);
     double* gred = red + 2 * n_items + 1;

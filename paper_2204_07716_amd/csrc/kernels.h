@@ -261,6 +261,14 @@ void launch_dsolve(int prec, const DSolveArgs& a, const int* pidx, const void* c
 void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s);
 void launch_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
                           hipStream_t s);
+void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
+                        int64_t wgstride, const double* yfit, const float* sup, double* u, hipStream_t s);
+void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s);
+void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
+                        void* out, hipStream_t s);
+void launch_adj_gather(const Geo& g, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
+                       const int32_t* perm, const void* fgrid, const double* yfit, const float* sup, const void* W,
+                       int w_type, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s);
 // The library-held workspace of the current device (fkr_fit_noalloc):
 // kStaticScratchBytes, 256-byte aligned.
 constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;

@@ -1333,9 +1333,9 @@ __device__ __forceinline__ void fft_store(const typename V2<T>::t* src, typename
             r = q - e * nr;
         }
         int pos = e;
-        if (f.out_band) {
+        if (f.out_band) {   // mode e - K at (e - K) mod F (a band wider than F wraps)
             pos = e - kout;
-            pos = pos < 0 ? pos + F : pos;
+            pos = pos < 0 ? pos + F : (pos >= F ? pos % F : pos);
         }
         if (row0 + r < skip) continue;
         C v = src[r * F + pos];
@@ -1461,6 +1461,14 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
             const int64_t row = row0 + r;
             const int64_t rq = row / f.in_rdiv;
             buf0[r * F + e] = in[rq * f.in_rmul + (row - rq * f.in_rdiv) + (int64_t)e * f.in_estride];
+        }
+        // rows shorter than the transform are zero-padded
+        for (int q = threadIdx.x; q < nr * (F - nin); q += blockDim.x) {
+            const int r = (int)((unsigned)q / (unsigned)(F - nin));
+            C z;
+            z.x = 0;
+            z.y = 0;
+            buf0[r * F + nin + (q - r * (F - nin))] = z;
         }
     }
     __syncthreads();
@@ -2342,6 +2350,198 @@ __global__ void k_finalize_grad(int d, int Np, const double* red, const double* 
         dmean /= Np;
         dlogh[j] = gcv * (drss / rss - 2.0 * dmean / mean);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of GCV in y: d GCV / dy = 2 / (N_I rho_bar^2) (r - S^T r), with r
+// the residuals on the supported samples and S^T the adjoint of the smoother
+// (interpolation, solve, moments): (S^T r)_l = sum_g sum_b v_b(g) k_b(x_l - g)
+// with u = P^T r (the interpolation weights of the supported samples scattered
+// to the grid), v_b = u c_b and c = A^{-1} e_0.  The sum over g is a type-2
+// transform: the v_b on the zero-padded grid to the band (forward FFT), times
+// the conjugate moment multipliers and the deconvolution, summed over b, back
+// to the fine grid (inverse FFT), then the spreading kernel at each sample.
+// ---------------------------------------------------------------------------
+template <int D, typename TW>
+__global__ __launch_bounds__(256) void k_adj_scatter(Geo g, int64_t N, int x_type, const void* X, const TW* W,
+                                                     int wstride, int64_t wgstride, const double* yfit,
+                                                     const float* sup, double* u) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const Corners<D> c = corners<D>(g, x_type, X, s);
+    bool ok = true;
+    double yh = 0.0;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) {
+        ok &= sup[c.idx[q]] == 0.f;
+        yh += c.w[q] * yfit[c.idx[q]];
+    }
+    if (!ok) return;
+    const double y = (double)(wgstride ? W[s * 4 + 1] : W[s * wstride + 1]);
+    const double r = y - yh;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) atomicAdd(&u[c.idx[q]], c.w[q] * r);
+}
+
+// v_b = u c_b packed two per complex grid function, [ceil(P/2)][M]; zero
+// where no supported sample reaches the grid point (c may be NaN there).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_pack(int P, int64_t Mtot, const double* u, const double* c,
+                                                  typename V2<T>::t* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mtot) return;
+    const double uk = u[k];
+    for (int q = 0; q < (P + 1) / 2; ++q) {
+        const int b0 = 2 * q, b1 = 2 * q + 1;
+        typename V2<T>::t v;
+        v.x = (T)(uk == 0.0 ? 0.0 : uk * c[b0 * Mtot + k]);
+        v.y = (T)(b1 < P && uk != 0.0 ? uk * c[b1 * Mtot + k] : 0.0);
+        out[q * Mtot + k] = v;
+    }
+}
+
+// Band spectrum of the adjoint: G(n) = prod_j fac_j(e_j) sum_b (-i)^{|b|}
+// prod_j He_{b_j}(u_j) exp(-u_j^2/2) / T_j V_b(n), V_b unpacked from the pair
+// spectra Z_q = V_{2q} + i V_{2q+1} ([band index][pairs]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, const int* et, const double* fac,
+                                                     const typename V2<T>::t* spec, typename V2<T>::t* out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.Btot) return;
+    const int npv = (P + 1) / 2;
+    double mloc[3][kExpandDeg];
+    unsigned nn = 0, rem = (unsigned)n, stride = 1;
+    double dec = 1.0;
+    int64_t foff = 0;
+    for (int j = 0; j < a.d; ++j) {
+        const unsigned bj = (unsigned)a.B[j];
+        const unsigned qj = rem / bj;
+        const int ej = (int)(rem - qj * bj);
+        rem = qj;
+        nn += (bj - 1 - (unsigned)ej) * stride;
+        stride *= bj;
+        dec *= fac[foff + ej];
+        foff += a.B[j];
+        const double u = a.h[j] * (2.0 * M_PI * (double)(ej - a.K[j]) / a.T[j]);
+        const double gj = exp(-0.5 * u * u) / a.T[j];
+        double hm = 1.0, he = u;
+        mloc[j][0] = gj;
+        mloc[j][1] = u * gj;
+        for (int k = 1; k + 1 < kExpandDeg; ++k) {
+            const double hn = u * he - k * hm;
+            hm = he;
+            he = hn;
+            mloc[j][k + 1] = he * gj;
+        }
+    }
+    double gr = 0.0, gi = 0.0;
+    for (int b = 0; b < P; ++b) {
+        const typename V2<T>::t zn = spec[n * npv + (b >> 1)];
+        const typename V2<T>::t zm = spec[(int64_t)nn * npv + (b >> 1)];
+        double vr, vi;
+        if ((b & 1) == 0) { vr = 0.5 * ((double)zn.x + (double)zm.x); vi = 0.5 * ((double)zn.y - (double)zm.y); }
+        else { vr = 0.5 * ((double)zn.y + (double)zm.y); vi = -0.5 * ((double)zn.x - (double)zm.x); }
+        double m = 1.0;
+        int deg = 0;
+        for (int j = 0; j < a.d; ++j) {
+            m *= mloc[j][et[3 * b + j]];
+            deg += et[3 * b + j];
+        }
+        double xr = vr * m, xi = vi * m;
+        switch (deg & 3) {   // multiply by (-i)^deg
+            case 1: { const double t0 = xr; xr = xi; xi = -t0; break; }
+            case 2: xr = -xr; xi = -xi; break;
+            case 3: { const double t0 = xr; xr = -xi; xi = t0; break; }
+            default: break;
+        }
+        gr += xr;
+        gi += xi;
+    }
+    typename V2<T>::t o;
+    o.x = (T)(gr * dec);
+    o.y = (T)(gi * dec);
+    out[n] = o;
+}
+
+// (S^T r) at each sample from the fine grid f (the spreading kernel over the
+// sample's footprint, the real part), and the gradient in original order.
+template <int D, typename T, int KER>
+__global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, int x_type, const void* X,
+                                                    const int32_t* perm, const typename V2<T>::t* fgrid,
+                                                    const double* yfit, const float* sup, const void* Wv,
+                                                    int w_type, int wstride, int64_t wgstride,
+                                                    const double* red, double* grad) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    double kv[D][kMaxW];
+    int c0[D];
+    const int w = g.w;
+    for (int j = 0; j < D; ++j) {
+        const double x = load_as_double(X, x_type, s * D + j);
+        const double uu = (x - g.lo[j]) * g.inv_hf[j];
+        const double cf = floor(uu - 0.5 * w) + 1.0;
+        const double fr = uu - cf;
+        int c = (int)cf;
+        const int mr = (int)g.Mr[j];
+        c0[j] = c < 0 ? c + mr : (c >= mr ? c - mr : c);
+        for (int k = 0; k < w; ++k) kv[j][k] = (double)kernel_value<double, KER>((double)k - fr, w, g.kparam);
+    }
+    double acc = 0.0;
+    if (D == 1) {
+        for (int k0 = 0; k0 < w; ++k0) {
+            int m0 = c0[0] + k0; m0 -= m0 >= g.Mr[0] ? (int)g.Mr[0] : 0;
+            acc += kv[0][k0] * (double)fgrid[m0].x;
+        }
+    } else if (D == 2) {
+        for (int k1 = 0; k1 < w; ++k1) {
+            int m1 = c0[D > 1 ? 1 : 0] + k1; m1 -= m1 >= g.Mr[1] ? (int)g.Mr[1] : 0;
+            double a1 = 0.0;
+            for (int k0 = 0; k0 < w; ++k0) {
+                int m0 = c0[0] + k0; m0 -= m0 >= g.Mr[0] ? (int)g.Mr[0] : 0;
+                a1 += kv[0][k0] * (double)fgrid[(int64_t)m1 * g.Mr[0] + m0].x;
+            }
+            acc += kv[D > 1 ? 1 : 0][k1] * a1;
+        }
+    } else {
+        for (int k2 = 0; k2 < w; ++k2) {
+            int m2 = c0[D > 2 ? 2 : 0] + k2; m2 -= m2 >= g.Mr[2] ? (int)g.Mr[2] : 0;
+            double a2 = 0.0;
+            for (int k1 = 0; k1 < w; ++k1) {
+                int m1 = c0[D > 1 ? 1 : 0] + k1; m1 -= m1 >= g.Mr[1] ? (int)g.Mr[1] : 0;
+                double a1 = 0.0;
+                for (int k0 = 0; k0 < w; ++k0) {
+                    int m0 = c0[0] + k0; m0 -= m0 >= g.Mr[0] ? (int)g.Mr[0] : 0;
+                    a1 += kv[0][k0] * (double)fgrid[((int64_t)m2 * g.Mr[1] + m1) * g.Mr[0] + m0].x;
+                }
+                a2 += kv[D > 1 ? 1 : 0][k1] * a1;
+            }
+            acc += kv[D > 2 ? 2 : 0][k2] * a2;
+        }
+    }
+    // the sample's own residual when it is supported
+    const Corners<D> c = corners<D>(g, x_type, X, s);
+    bool ok = true;
+    double yh = 0.0;
+#pragma unroll
+    for (int q = 0; q < (1 << D); ++q) {
+        ok &= sup[c.idx[q]] == 0.f;
+        yh += c.w[q] * yfit[c.idx[q]];
+    }
+    double y;
+    if (w_type == FKR_F64) {
+        const double* W = static_cast<const double*>(Wv);
+        y = wgstride ? W[s * 4 + 1] : W[s * wstride + 1];
+    } else {
+        const float* W = static_cast<const float*>(Wv);
+        y = (double)(wgstride ? W[s * 4 + 1] : W[s * wstride + 1]);
+    }
+    const double r = ok ? y - yh : 0.0;
+    const int n_items = 1 + Np;
+    double mean = 0.0;
+    for (int p = 0; p < Np; ++p) mean += (red[2 * (1 + p)] - red[2 * (1 + p) + 1]) / red[2 * (1 + p)];
+    mean /= Np;
+    const double scale = 2.0 / (red[2 * n_items] * mean * mean);
+    grad[perm[s]] = scale * (r - acc);
 }
 
 // Residuals of the mean fit for the variance pass (Sec. 3), in sorted sample
@@ -3438,6 +3638,49 @@ void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s) {
 void launch_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
                           hipStream_t s) {
     k_finalize_grad<<<1, 64, 0, s>>>(d, Np, red, gred, gcv, dlogh);
+}
+
+void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
+                        int64_t wgstride, const double* yfit, const float* sup, double* u, hipStream_t s) {
+    if (N == 0) return;
+    // sorted coordinates and staged weights are both in the spreading precision
+#define FKR_AS(D, TW) k_adj_scatter<D, TW><<<nblk(N), 256, 0, s>>>(g, N, prec, X, static_cast<const TW*>(W), \
+                                                                  wstride, wgstride, yfit, sup, u)
+    if (prec == FKR_F64) {
+        if (g.d == 1) FKR_AS(1, double); else if (g.d == 2) FKR_AS(2, double); else FKR_AS(3, double);
+    } else {
+        if (g.d == 1) FKR_AS(1, float); else if (g.d == 2) FKR_AS(2, float); else FKR_AS(3, float);
+    }
+#undef FKR_AS
+}
+
+void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s) {
+    if (prec == FKR_F64) k_adj_pack<double><<<nblk(Mtot), 256, 0, s>>>(P, Mtot, u, c, static_cast<double2*>(out));
+    else k_adj_pack<float><<<nblk(Mtot), 256, 0, s>>>(P, Mtot, u, c, static_cast<float2*>(out));
+}
+
+void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
+                        void* out, hipStream_t s) {
+    if (prec == FKR_F64)
+        k_adj_combine<double><<<nblk(a.Btot), 256, 0, s>>>(a, P, et, fac, static_cast<const double2*>(spec),
+                                                           static_cast<double2*>(out));
+    else
+        k_adj_combine<float><<<nblk(a.Btot), 256, 0, s>>>(a, P, et, fac, static_cast<const float2*>(spec),
+                                                          static_cast<float2*>(out));
+}
+
+void launch_adj_gather(const Geo& g, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
+                       const int32_t* perm, const void* fgrid, const double* yfit, const float* sup, const void* W,
+                       int w_type, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s) {
+    if (N == 0) return;
+#define FKR_AG(D, T, K) k_adj_gather<D, T, K><<<nblk(N), 256, 0, s>>>(g, N, Np, x_type, X, perm, \
+        static_cast<const typename V2<T>::t*>(fgrid), yfit, sup, W, w_type, wstride, wgstride, red, grad)
+#define FKR_AG_K(D, T) do { if (kernel == FKR_KERNEL_ES) FKR_AG(D, T, FKR_KERNEL_ES); else FKR_AG(D, T, FKR_KERNEL_GAUSS); } while (0)
+#define FKR_AG_D(T) do { if (g.d == 1) FKR_AG_K(1, T); else if (g.d == 2) FKR_AG_K(2, T); else FKR_AG_K(3, T); } while (0)
+    if (tprec == FKR_F64) FKR_AG_D(double); else FKR_AG_D(float);
+#undef FKR_AG_D
+#undef FKR_AG_K
+#undef FKR_AG
 }
 
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {

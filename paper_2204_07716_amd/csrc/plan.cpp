@@ -202,6 +202,14 @@ static void layout(fkr_plan* p) {
     {
         int64_t g = p->pairs_per_spread;
         if (p->d == 3) cap = std::max(cap, g * p->Mr[0] * p->Mr[1] * p->Mr[2]);   // the folded fine grid
+        // one complex fine grid and the band-to-fine-grid intermediates of the
+        // gradient in y (the adjoint of the moment path)
+        for (int j = 0; j < p->d; ++j) {
+            int64_t e = 1;
+            for (int i = 0; i < j; ++i) e *= p->B[i];
+            for (int i = j; i < p->d; ++i) e *= p->Mr[i];
+            cap = std::max(cap, e);
+        }
         for (int j = 0; j < p->d; ++j) {
             int64_t e = g;
             for (int i = 0; i <= j; ++i) e *= p->B[i];

@@ -77,21 +77,24 @@ def select_bandwidth(gcv: Sequence[float], dstd: float = 0.0) -> int:
 
 
 class GCVLogH(torch.autograd.Function):
-    """GCV (eq. 22) of one real response as a function of log h, with the
-    library's hand-written gradient as its backward: ``GCVLogH.apply(log_h,
-    plan, Y, Np, seed)`` with log_h a tensor of d entries."""
+    """GCV (eq. 22) of one real response as a function of log h and of the
+    response y, with the library's hand-written gradients as its backward:
+    ``GCVLogH.apply(log_h, Y, plan, Np, seed)`` with log_h a tensor of d
+    entries and Y of N (either may require grad)."""
 
     @staticmethod
-    def forward(ctx, log_h, plan, Y, Np, seed):
+    def forward(ctx, log_h, Y, plan, Np, seed):
         h = torch.exp(log_h.detach().to(torch.float64)).cpu().numpy()
-        out = plan.gcv_grad(h, Y, Np, seed)
-        ctx.save_for_backward(out["dlogh"].to(log_h.device, log_h.dtype))
+        out = plan.gcv_grad(h, Y.detach(), Np, seed, want_dy=Y.requires_grad)
+        dy = out["dy"].to(Y.dtype).reshape(Y.shape) if out["dy"] is not None else None
+        ctx.save_for_backward(out["dlogh"].to(log_h.device, log_h.dtype), dy)
         return out["gcv"][0].to(log_h.device, log_h.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):
-        (dl,) = ctx.saved_tensors
-        return grad_out * dl, None, None, None, None
+        dl, dy = ctx.saved_tensors
+        g_y = grad_out.to(dy.device, dy.dtype) * dy if dy is not None else None
+        return grad_out * dl, g_y, None, None, None
 
 
 def _plan_desc(d, order, M, lo, hi, h_min, h_max, eps, precision, kernel, sigma, n_max, max_weights,
@@ -376,18 +379,20 @@ class Plan:
         return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
 
     # -- differentiation ------------------------------------------------
-    def gcv_grad(self, h, Y: torch.Tensor, Np: int, seed: int = 0) -> dict:
-        """GCV at h for one real response with Np Philox probes, its gradient
-        in log h [d], and d m_hat / d log h_j of y and the probes [d][1+Np][M]."""
+    def gcv_grad(self, h, Y: torch.Tensor, Np: int, seed: int = 0, want_dy: bool = True) -> dict:
+        """GCV at h for one real response with Np Philox probes, its gradients
+        in log h [d] and in y [N], and d m_hat / d log h_j of y and the probes
+        [d][1+Np][M]."""
         hb = _hbuf(h, self.d)
         assert hb.shape[0] == 1, "one bandwidth"
         Yr = Y.reshape(-1, 1).contiguous()
         gcv = torch.empty(1, dtype=torch.float64, device=self.device)
         dlogh = torch.empty(self.d, dtype=torch.float64, device=self.device)
         dfit = torch.empty((self.d, 1 + Np, self.Mtot), dtype=torch.float64, device=self.device)
+        dy = torch.empty(Yr.shape[0], dtype=torch.float64, device=self.device) if want_dy else None
         check(self.lib.fkr_gcv_grad(self._plan, _hptr(hb), _ptr(Yr), _dtype_code(Yr), Np, ctypes.c_uint64(seed),
-                                    _ptr(gcv), _ptr(dlogh), _ptr(dfit), _stream()), "fkr_gcv_grad")
-        return {"gcv": gcv, "dlogh": dlogh, "dfit": dfit}
+                                    _ptr(gcv), _ptr(dlogh), _ptr(dy), _ptr(dfit), _stream()), "fkr_gcv_grad")
+        return {"gcv": gcv, "dlogh": dlogh, "dy": dy, "dfit": dfit}
 
     # -- prediction and inference ---------------------------------------
     def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05):

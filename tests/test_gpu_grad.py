@@ -86,16 +86,64 @@ def test_gcv_grad_matches_oracle(orc, d, prec, tprec):
     assert err < (1e-6 if prec == "fp64" else 1e-5)   # FP64: the oracle's central differences (step 1e-4)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_gcv_y_grad_matches_finite_differences(d):
+    """FP64 path: GCV is quadratic in y, so central differences in y_i are
+    exact up to rounding; the gradient of the adjoint (type-2) path must
+    match them at every checked sample."""
+    N, Np, seed = 2000, 4, 8
+    X, y, M, h = _setup(d, N, 800 + d)
+    plan = _plan(d, M, h, N, Np, "fp64", "same")
+    plan.set_points(to_dev(X))
+    out = plan.gcv_grad(h, to_dev(y[:, None]), Np, seed)
+    dy = out["dy"].cpu().numpy()
+    scale = np.abs(dy).max()
+    for i in range(0, N, 97):
+        e = np.zeros(N)
+        e[i] = 0.05
+        up = plan.cv(h, to_dev((y + e)[:, None]), Np, seed=seed)["gcv"].item()
+        dn = plan.cv(h, to_dev((y - e)[:, None]), Np, seed=seed)["gcv"].item()
+        fd = (up - dn) / 0.1
+        assert abs(dy[i] - fd) < 1e-7 * scale, (i, dy[i], fd)
+
+
+@pytest.mark.parametrize("d,prec,tprec", [(1, "fp64", "same"), (2, "fp64", "same"), (2, "fp32", "fp64"),
+                                          (3, "fp32", "fp64")])
+def test_gcv_y_grad_matches_oracle(orc, d, prec, tprec):
+    """Against the oracle's gradient from the explicit smoother (fits of the
+    unit responses), same Philox probes."""
+    N, Np, seed = {1: 400, 2: 500, 3: 600}[d], 4, 12
+    X, y, M, h = _setup(d, N, 900 + d)
+    plan = _plan(d, M, h, N, Np, prec, tprec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    plan.set_points(to_dev(X, dt))
+    out = plan.gcv_grad(h, to_dev(y[:, None], dt), Np, seed)
+    dy = out["dy"].cpu().numpy()
+    Xr = X.astype(np.float32).astype(np.float64) if prec == "fp32" else X
+    yr = y.astype(np.float32).astype(np.float64) if prec == "fp32" else y
+    Wp = orc.probes(seed, N, Np)
+    if prec == "fp32":
+        Wp = Wp.astype(np.float32).astype(np.float64)
+    lo, hi = (0.0,) * d, (1.0,) * d
+    inc = orc.support(Xr, h, 1, M, lo, hi)[0]
+    ref = orc.gcv_y_gradient(Xr, yr, h, 1, M, lo, hi, Wp, include=inc)
+    err = np.abs(dy - ref).max() / np.abs(ref).max()
+    print(f"d={d} {prec}: dy rel err {err:.2e} ({inc.sum()} of {N} supported)")
+    assert err < (1e-8 if prec == "fp64" else 1e-5)
+
+
 def test_gcv_autograd_backward():
     from paper_2204_07716_amd import GCVLogH
     N, Np, seed, d = 2000, 4, 5, 2
     X, y, M, h = _setup(d, N, 700)
     plan = _plan(d, M, h, N, Np, "fp32", "fp64")
     plan.set_points(to_dev(X, torch.float32))
-    Y = to_dev(y[:, None], torch.float32)
+    Y = to_dev(y[:, None], torch.float32).requires_grad_(True)
     log_h = torch.tensor(np.log(h), dtype=torch.float64, requires_grad=True)
-    gcv = GCVLogH.apply(log_h, plan, Y, Np, seed)
+    gcv = GCVLogH.apply(log_h, Y, plan, Np, seed)
     gcv.backward()
-    ref = plan.gcv_grad(h, Y, Np, seed)
+    ref = plan.gcv_grad(h, Y.detach(), Np, seed)
     assert gcv.item() == pytest.approx(ref["gcv"].item(), rel=1e-12)
     np.testing.assert_allclose(log_h.grad.numpy(), ref["dlogh"].cpu().numpy(), rtol=1e-12)
+    np.testing.assert_allclose(Y.grad.cpu().numpy()[:, 0], ref["dy"].cpu().numpy(), rtol=1e-6,
+                               atol=1e-6 * ref["dy"].abs().max().item())

@@ -702,3 +702,23 @@ def test_gcv_gradient_symmetric_design(orc):
     Wp = np.concatenate([Wp0, Wp0])
     g = orc.gcv_log_h_gradient(X, y, np.array([0.2, 0.2]), 1, (9, 9), (0.0, 0.0), (1.0, 1.0), Wp)
     assert g[0] == pytest.approx(g[1], rel=1e-8)
+
+
+def test_gcv_y_gradient_matches_central_differences(orc):
+    """GCV is quadratic in y (the smoother and the Girard ratios do not
+    depend on y), so central differences in y_i are exact up to rounding;
+    some samples are unsupported (a sparse corner of the box)."""
+    rng = np.random.default_rng(14)
+    N = 160
+    X = rng.random((N, 2)) ** 1.5
+    y = np.sin(4 * X[:, 0]) * np.cos(2 * X[:, 1]) + 0.2 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi, h = (9, 8), (0.0, 0.0), (1.0, 1.0), np.array([0.12, 0.14])
+    inc = orc.support(X, h, 1, M, lo, hi)[0]
+    g = orc.gcv_y_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc)
+    for i in list(range(0, N, 23)) + [int(np.nonzero(~inc)[0][0])] if (~inc).any() else list(range(0, N, 23)):
+        e = np.zeros(N)
+        e[i] = 0.05
+        fd = (orc.gcv_criterion(X, y + e, h, 1, M, lo, hi, Wp, inc)
+              - orc.gcv_criterion(X, y - e, h, 1, M, lo, hi, Wp, inc)) / 0.1
+        assert g[i] == pytest.approx(fd, rel=1e-7, abs=1e-12)
