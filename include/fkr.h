@@ -287,8 +287,9 @@ fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const vo
                         double* vhat_dev, double* kappa_dev, void* stream);
 
 /* Gradient of the GCV criterion of eq. (22) with respect to log h (Sec. 2.1:
- * bandwidth selection minimises GCV over h) for one real response Y (N x 1,
- * type y_type) and Np Philox probes (as fkr_cv with that seed).  The fits
+ * bandwidth selection minimises GCV over h) and to the response, for one
+ * response Y (N x 1, type y_type; complex interleaved when y_complex, with
+ * |.|^2 in the RSS) and Np Philox probes (as fkr_cv with that seed).  The fits
  * are m_hat = e_0^T A^{-1} t with the bandwidth-equilibrated moments A, t of
  * eq. (11); their derivative in theta_j = log h_j is
  * e_0^T A^{-1} (dt - dA A^{-1} t), where dA, dt come from the same type-1
@@ -307,15 +308,21 @@ fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const vo
  * conjugate moment multipliers, inverse FFT to the fine grid, the spreading
  * kernel at each sample).
  * gcv_dev (optional, 1 double): GCV at h; dlogh_dev [d] doubles: the
- * gradient in log h; dy_dev (optional, [N] doubles, the order of Y): the
- * gradient in y; dfit_dev [d][1 + Np][M^d] doubles (caller-owned): d m_hat /
- * d log h_j of y and of each probe fit, NaN where the fit is not resolved.
+ * gradient in log h; dy_dev (optional, [N] doubles in the order of Y, or
+ * [N][2] for complex y): the gradient in y, for complex y
+ * d GCV / d Re y + i d GCV / d Im y (the convention of PyTorch for a real
+ * function of complex inputs); dfit_dev [d][ny + Np][M^d] doubles
+ * (caller-owned; ny = 1, or 2 for complex y): d m_hat / d log h_j of the
+ * response parts and of each probe fit, NaN where the fit is not
+ * resolved.  The plan needs room for the channels of 1 + ny + Np weights
+ * twice (see below).
  * The plan's channel buffer holds the channels at h and their derivatives
- * side by side: FKR_E_ARG unless 2 ceil((n_s + n_t (1 + Np)) / 2) <=
- * ceil((n_s + n_t (max_weights - 1)) / 2) (max_weights >= 2 (2 + Np) +
- * n_s / n_t suffices). */
-fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, const void* Y_dev, int y_type, int Np, uint64_t seed,
-                        double* gcv_dev, double* dlogh_dev, double* dy_dev, double* dfit_dev, void* stream);
+ * side by side: FKR_E_ARG unless 2 ceil((n_s + n_t (ny + Np)) / 2) <=
+ * ceil((n_s + n_t (max_weights - 1)) / 2) (max_weights >= 2 (1 + ny + Np)
+ * + n_s / n_t suffices). */
+fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, int y_complex, const void* Y_dev, int y_type, int Np,
+                        uint64_t seed, double* gcv_dev, double* dlogh_dev, double* dy_dev, double* dfit_dev,
+                        void* stream);
 
 /* Variance of the fit and pointwise confidence band (Sec. 4.2, eq. 27-28;
  * Sec. 4 fkreg_interval) at one bandwidth h (d doubles).  The fit of eq. (3)

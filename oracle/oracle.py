@@ -471,8 +471,11 @@ def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None) -> float:
     """GCV of eq. (22) at bandwidth h for one real response y, with the DF
     from the probes Wp (``dof``), over the supported samples I (``include``,
     else the support rule at h)."""
+    y = np.asarray(y).reshape(-1)
     X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
-    W = np.concatenate([np.asarray(y, dtype=np.float64).reshape(-1, 1), Wp], axis=1)
+    Yr, cplx = _split_complex(y)          # complex y: real and imaginary parts
+    ny = Yr.shape[1]
+    W = np.concatenate([Yr, Wp], axis=1)
     gp = grid_points(M, lo, hi)
     mh, S, T, r0, ill = fit(X, W, h, order, gp, return_all=True)
     d = X.shape[1]
@@ -480,8 +483,9 @@ def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None) -> float:
         include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
     include = np.asarray(include, dtype=bool)
     F = interp(mh, M, lo, hi, X)
-    rho = girard_ratios(Wp[include], F[include, 1:])
-    return float(gcv(y, F[:, 0], float(np.mean(rho)), include=include)[0])
+    rho = girard_ratios(Wp[include], F[include, ny:])
+    yhat = F[:, 0] + 1j * F[:, 1] if cplx else F[:, 0]
+    return float(gcv(y, yhat, float(np.mean(rho)), include=include)[0])
 
 
 def gcv_log_h_gradient(X, y, h, order, M, lo, hi, Wp, include=None, step: float = 1e-4) -> np.ndarray:
@@ -508,7 +512,7 @@ def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None) -> np.ndarray:
     the unit responses; the Girard ratios do not depend on y, so with
     r = (y - S y) on the supported samples I,
     d GCV / dy = 2 / (N_I rho_bar^2) (r - S_I^T r_I)."""
-    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    y = np.asarray(y).reshape(-1)
     N = len(y)
     X = np.asarray(X, dtype=np.float64).reshape(N, -1)
     d = X.shape[1]
@@ -521,8 +525,10 @@ def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None) -> np.ndarray:
     Smat = F[include, :N]                       # rows of the supported samples
     rho = girard_ratios(Wp[include], F[include, N:])
     m = float(np.mean(rho))
+    # S is real: for complex y the same formula holds for the real and the
+    # imaginary part, d/dRe y + i d/dIm y
     r = y[include] - Smat @ y
-    g = np.zeros(N)
+    g = np.zeros(N, dtype=r.dtype)
     g[include] = r
     return 2.0 / (include.sum() * m * m) * (g - Smat.T @ r)
 

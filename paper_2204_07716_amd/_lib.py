@@ -95,7 +95,7 @@ def load() -> ctypes.CDLL:
         "fkr_variance": ([P, pD, I, P, I, P, I, P, P, P, P], I),
         "fkr_interval": ([P, pD, I, D, P, P, D, P, P, P, P], I),
         "fkr_spline": ([P, I, P, P, P], I),
-        "fkr_gcv_grad": ([P, pD, P, I, I, U64, P, P, P, P, P], I),
+        "fkr_gcv_grad": ([P, pD, I, P, I, I, U64, P, P, P, P, P], I),
         "fkr_predict": ([P, I, P, I64, P, I, P, P], I),
         "fkr_get_diagnostics": ([P, ctypes.POINTER(Diag)], I),
         "fkr_status_string": ([I], ctypes.c_char_p),

@@ -884,7 +884,8 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
 // pairs, support flags, the fit of y, the sums): c = A^{-1} e_0, u = P^T r,
 // the type-2 path of v_b = u c_b to the fine grid, the gather at the samples.
 // u uses `scratch` ([M] doubles).
-fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, double* scratch, double* dy, hipStream_t s) {
+fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* scratch, double* dy,
+                  hipStream_t s) {
     const Geo g = make_geo(p);
     const int P = p->n_t;
     const int npv = (P + 1) / 2;
@@ -896,9 +897,11 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, double* scratch,
     const int wstride = wgstride ? 4 : (nr + 3) & ~3;
     const double* yfit = at<double>(p, p->lay.mhat);
     const float* sup = at<float>(p, p->lay.sup);
+    // real and imaginary parts of a complex response separately: the smoother is real
+    for (int part = 0; part < ny; ++part) {
     launch_fill_f64(scratch, p->Mtot, 0.0, s);
-    launch_adj_scatter(g, p->N, p->prec, p->ws + p->lay.xs, p->ws + p->lay.wsort, wstride, wgstride, yfit, sup,
-                       scratch, s);
+    launch_adj_scatter(g, p->N, p->prec, p->ws + p->lay.xs, p->ws + p->lay.wsort, wstride, wgstride, ny, part, yfit,
+                       sup, scratch, s);
     void* bufs[2] = {p->ws + p->lay.fftA, p->ws + p->lay.fftB};
     int cur = 0;
     launch_adj_pack(p->tprec, P, p->Mtot, scratch, at<double>(p, p->lay.r0), bufs[cur], s);
@@ -967,20 +970,23 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, double* scratch,
         cur = 1 - cur;
     }
     launch_adj_gather(g, p->tprec, p->kernel, p->N, Np, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
-                      bufs[cur], yfit, sup, p->ws + p->lay.wsort, p->prec, wstride, wgstride,
+                      bufs[cur], ny, part, yfit, sup, p->ws + p->lay.wsort, p->prec, wstride, wgstride,
                       at<double>(p, p->lay.red), dy, s);
+    }
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, const void* Y, int y_type, int Np, uint64_t seed,
-                        double* gcv, double* dlogh, double* dy, double* dfit, void* stream) {
-    fkr_status st = common_fit_checks(p, 1, h, 1, 0, Y, y_type);
+fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type, int Np,
+                        uint64_t seed, double* gcv, double* dlogh, double* dy, double* dfit, void* stream) {
+    fkr_status st = common_fit_checks(p, 1, h, 1, y_complex, Y, y_type);
     if (st != FKR_OK) return st;
     if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
-    const int nr = 2 + Np;
+    const int ny = y_complex ? 2 : 1;
+    const int nr = 1 + ny + Np;
     const int ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;
-    const int n_items = 1 + Np;
-    const int nslot = p->d * n_items;
+    const int n_items = 1 + Np;          // base sums: the response (|r|^2), then the probes
+    const int ncol = ny + Np;            // gradient sums per dimension
+    const int nslot = p->d * ncol;
     // the channels at h and their derivatives side by side; the gradient sums
     // after the base sums
     if (nr > p->max_weights || 2 * ncp > p->ncp_max) return FKR_E_ARG;
@@ -989,12 +995,12 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, const void* Y, int y_type,
     const hipStream_t s = S(stream);
     // base pass: fit, DF and GCV at h (spectra, channels in pairs [0, ncp),
     // support flags, the fit of y, the sums)
-    if ((st = cv_impl(p, 1, h, 1, 0, Y, y_type, Np, seed, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, s)) != FKR_OK)
+    if ((st = cv_impl(p, 1, h, 1, y_complex, Y, y_type, Np, seed, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, s)) != FKR_OK)
         return st;
     if (dy) {
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        if ((st = grad_y(p, h, Np, nr, dfit, dy, s)) != FKR_OK) return st;
+        if ((st = grad_y(p, h, Np, nr, ny, dfit, dy, s)) != FKR_OK) return st;
     }
     const Geo g = make_geo(p);
     double* red = at<double>(p, p->lay.red);
@@ -1014,24 +1020,25 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, const void* Y, int y_type,
             launch_dsolve(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, p->ws + p->lay.chan + ncp * pair_bytes, s);
         }
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        for (int c0 = 0; c0 < n_items; c0 += 8) {
+        for (int c0 = 0; c0 < ncol; c0 += 8) {
             GradSumArgs r{};
             r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
             r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec;
             r.wgstride = grouped_weights(p) ? 4 * p->N : 0;
             r.wstride = r.wgstride ? 4 : (nr + 3) & ~3;
+            r.ny = ny;
             r.yfit = at<double>(p, p->lay.mhat);
             r.dfit = a.out;
             r.sup = sup;
-            r.ncol = std::min(8, n_items - c0);
+            r.ncol = std::min(8, ncol - c0);
             r.col0 = c0;
-            r.slot0 = j * n_items + c0;
+            r.slot0 = j * ncol + c0;
             r.partial = partial;
             launch_grad_sums(g, r, s);
         }
     }
     launch_reduce_final(partial, nslot, gred, s);
-    launch_finalize_grad(p->d, Np, red, gred, gcv, dlogh, s);
+    launch_finalize_grad(p->d, ny, Np, red, gred, gcv, dlogh, s);
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }

@@ -66,9 +66,10 @@ struct DSolveArgs {
     double* out;                   // [nr - 1][M]; NaN where not resolved
 };
 
-// Sums over the supported samples for the log-h gradient of GCV: column 0
-// sum r_i d yhat_i (r = y - yhat), column 1 + p sum w_pi d what_pi, for the
-// derivative grids of one dimension.
+// Sums over the supported samples for the log-h gradient of GCV: columns
+// c < ny sum r_ic d yhat_ic (r = y - yhat, response part c of ny = 1 real or
+// 2 complex parts), column ny + p sum w_pi d what_pi, for the derivative
+// grids of one dimension.
 struct GradSumArgs {
     int64_t N;
     int x_type;
@@ -76,8 +77,9 @@ struct GradSumArgs {
     const void* wsorted;           // staged weights: 1, y, probes
     int w_type, wstride;
     int64_t wgstride;
-    const double* yfit;            // [M] the base fit of y
-    const double* dfit;            // [1 + Np][M] derivative grids of this dimension
+    int ny;                        // response parts (1 real, 2 complex)
+    const double* yfit;            // [M][ny] the base fit of y
+    const double* dfit;            // [ny + Np][M] derivative grids of this dimension
     const float* sup;              // [M]
     int ncol, col0;                // columns of this launch (<= 8), first column
     int slot0;                     // first partial slot
@@ -259,16 +261,18 @@ void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 void launch_dsolve(int prec, const DSolveArgs& a, const int* pidx, const void* chan_base, const void* chan_der,
                    hipStream_t s);
 void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s);
-void launch_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
+void launch_finalize_grad(int d, int ny, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
                           hipStream_t s);
 void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
-                        int64_t wgstride, const double* yfit, const float* sup, double* u, hipStream_t s);
+                        int64_t wgstride, int ny, int part, const double* yfit, const float* sup, double* u,
+                        hipStream_t s);
 void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s);
 void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
                         void* out, hipStream_t s);
 void launch_adj_gather(const Geo& g, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
-                       const int32_t* perm, const void* fgrid, const double* yfit, const float* sup, const void* W,
-                       int w_type, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s);
+                       const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,
+                       const void* W, int w_type, int wstride, int64_t wgstride, const double* red, double* grad,
+                       hipStream_t s);
 // The library-held workspace of the current device (fkr_fit_noalloc):
 // kStaticScratchBytes, 256-byte aligned.
 constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;

@@ -2310,11 +2310,11 @@ __global__ __launch_bounds__(256) void k_grad_sums(Geo g, GradSumArgs a) {
 #pragma unroll
             for (int e = 0; e < (1 << D); ++e) dv += c.w[e] * gd[c.idx[e]];
             double coef;
-            if (col == 0) {
+            if (col < a.ny) {
                 double yh = 0.0;
 #pragma unroll
-                for (int e = 0; e < (1 << D); ++e) yh += c.w[e] * a.yfit[c.idx[e]];
-                coef = wcol(s, 1) - yh;
+                for (int e = 0; e < (1 << D); ++e) yh += c.w[e] * a.yfit[c.idx[e] * a.ny + col];
+                coef = wcol(s, 1 + col) - yh;
             } else {
                 coef = wcol(s, 1 + col);
             }
@@ -2326,9 +2326,11 @@ __global__ __launch_bounds__(256) void k_grad_sums(Geo g, GradSumArgs a) {
         for (int q = 0; q < a.ncol; ++q) a.partial[(int64_t)(a.slot0 + q) * kRedBlocks + blockIdx.x] = acc[q];
 }
 
-// d GCV / d log h_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar), dRSS = -2 sum r
-// d yhat, d rho_p = -sum w_p d w_hat_p / sum w_p^2 (the supported set fixed).
-__global__ void k_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv_out,
+// d GCV / d log h_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar), dRSS = -2 sum
+// Re(conj(r) d yhat), d rho_p = -sum w_p d w_hat_p / sum w_p^2 (the supported
+// set fixed).  red: the base sums (RSS of the response, then per probe sum
+// w^2 and sum w w_hat, then N_I); gred: ny + Np gradient sums per dimension.
+__global__ void k_finalize_grad(int d, int ny, int Np, const double* red, const double* gred, double* gcv_out,
                                 double* dlogh) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int n_items = 1 + Np;
@@ -2343,10 +2345,11 @@ __global__ void k_finalize_grad(int d, int Np, const double* red, const double* 
     const double gcv = (rss / n_used) / (mean * mean);
     if (gcv_out) *gcv_out = gcv;
     for (int j = 0; j < d; ++j) {
-        const double* gj = gred + (int64_t)j * n_items;
-        const double drss = -2.0 * gj[0];
+        const double* gj = gred + (int64_t)j * (ny + Np);
+        double drss = 0.0;
+        for (int c = 0; c < ny; ++c) drss += -2.0 * gj[c];
         double dmean = 0.0;
-        for (int p = 0; p < Np; ++p) dmean += -gj[1 + p] / red[2 * (1 + p)];
+        for (int p = 0; p < Np; ++p) dmean += -gj[ny + p] / red[2 * (1 + p)];
         dmean /= Np;
         dlogh[j] = gcv * (drss / rss - 2.0 * dmean / mean);
     }
@@ -2364,8 +2367,8 @@ __global__ void k_finalize_grad(int d, int Np, const double* red, const double* 
 // ---------------------------------------------------------------------------
 template <int D, typename TW>
 __global__ __launch_bounds__(256) void k_adj_scatter(Geo g, int64_t N, int x_type, const void* X, const TW* W,
-                                                     int wstride, int64_t wgstride, const double* yfit,
-                                                     const float* sup, double* u) {
+                                                     int wstride, int64_t wgstride, int ny, int part,
+                                                     const double* yfit, const float* sup, double* u) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const Corners<D> c = corners<D>(g, x_type, X, s);
@@ -2374,10 +2377,10 @@ __global__ __launch_bounds__(256) void k_adj_scatter(Geo g, int64_t N, int x_typ
 #pragma unroll
     for (int q = 0; q < (1 << D); ++q) {
         ok &= sup[c.idx[q]] == 0.f;
-        yh += c.w[q] * yfit[c.idx[q]];
+        yh += c.w[q] * yfit[c.idx[q] * ny + part];
     }
     if (!ok) return;
-    const double y = (double)(wgstride ? W[s * 4 + 1] : W[s * wstride + 1]);
+    const double y = (double)(wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part]);
     const double r = y - yh;
 #pragma unroll
     for (int q = 0; q < (1 << D); ++q) atomicAdd(&u[c.idx[q]], c.w[q] * r);
@@ -2468,8 +2471,8 @@ __global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, const 
 template <int D, typename T, int KER>
 __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, int x_type, const void* X,
                                                     const int32_t* perm, const typename V2<T>::t* fgrid,
-                                                    const double* yfit, const float* sup, const void* Wv,
-                                                    int w_type, int wstride, int64_t wgstride,
+                                                    int ny, int part, const double* yfit, const float* sup,
+                                                    const void* Wv, int w_type, int wstride, int64_t wgstride,
                                                     const double* red, double* grad) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
@@ -2525,15 +2528,15 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, in
 #pragma unroll
     for (int q = 0; q < (1 << D); ++q) {
         ok &= sup[c.idx[q]] == 0.f;
-        yh += c.w[q] * yfit[c.idx[q]];
+        yh += c.w[q] * yfit[c.idx[q] * ny + part];
     }
     double y;
     if (w_type == FKR_F64) {
         const double* W = static_cast<const double*>(Wv);
-        y = wgstride ? W[s * 4 + 1] : W[s * wstride + 1];
+        y = wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part];
     } else {
         const float* W = static_cast<const float*>(Wv);
-        y = (double)(wgstride ? W[s * 4 + 1] : W[s * wstride + 1]);
+        y = (double)(wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part]);
     }
     const double r = ok ? y - yh : 0.0;
     const int n_items = 1 + Np;
@@ -2541,7 +2544,7 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, in
     for (int p = 0; p < Np; ++p) mean += (red[2 * (1 + p)] - red[2 * (1 + p) + 1]) / red[2 * (1 + p)];
     mean /= Np;
     const double scale = 2.0 / (red[2 * n_items] * mean * mean);
-    grad[perm[s]] = scale * (r - acc);
+    grad[(int64_t)perm[s] * ny + part] = scale * (r - acc);
 }
 
 // Residuals of the mean fit for the variance pass (Sec. 3), in sorted sample
@@ -3635,17 +3638,18 @@ void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s) {
 #undef FKR_GS
 }
 
-void launch_finalize_grad(int d, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
+void launch_finalize_grad(int d, int ny, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
                           hipStream_t s) {
-    k_finalize_grad<<<1, 64, 0, s>>>(d, Np, red, gred, gcv, dlogh);
+    k_finalize_grad<<<1, 64, 0, s>>>(d, ny, Np, red, gred, gcv, dlogh);
 }
 
 void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
-                        int64_t wgstride, const double* yfit, const float* sup, double* u, hipStream_t s) {
+                        int64_t wgstride, int ny, int part, const double* yfit, const float* sup, double* u,
+                        hipStream_t s) {
     if (N == 0) return;
     // sorted coordinates and staged weights are both in the spreading precision
 #define FKR_AS(D, TW) k_adj_scatter<D, TW><<<nblk(N), 256, 0, s>>>(g, N, prec, X, static_cast<const TW*>(W), \
-                                                                  wstride, wgstride, yfit, sup, u)
+                                                                  wstride, wgstride, ny, part, yfit, sup, u)
     if (prec == FKR_F64) {
         if (g.d == 1) FKR_AS(1, double); else if (g.d == 2) FKR_AS(2, double); else FKR_AS(3, double);
     } else {
@@ -3670,11 +3674,12 @@ void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, con
 }
 
 void launch_adj_gather(const Geo& g, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
-                       const int32_t* perm, const void* fgrid, const double* yfit, const float* sup, const void* W,
-                       int w_type, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s) {
+                       const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,
+                       const void* W, int w_type, int wstride, int64_t wgstride, const double* red, double* grad,
+                       hipStream_t s) {
     if (N == 0) return;
 #define FKR_AG(D, T, K) k_adj_gather<D, T, K><<<nblk(N), 256, 0, s>>>(g, N, Np, x_type, X, perm, \
-        static_cast<const typename V2<T>::t*>(fgrid), yfit, sup, W, w_type, wstride, wgstride, red, grad)
+        static_cast<const typename V2<T>::t*>(fgrid), ny, part, yfit, sup, W, w_type, wstride, wgstride, red, grad)
 #define FKR_AG_K(D, T) do { if (kernel == FKR_KERNEL_ES) FKR_AG(D, T, FKR_KERNEL_ES); else FKR_AG(D, T, FKR_KERNEL_GAUSS); } while (0)
 #define FKR_AG_D(T) do { if (g.d == 1) FKR_AG_K(1, T); else if (g.d == 2) FKR_AG_K(2, T); else FKR_AG_K(3, T); } while (0)
     if (tprec == FKR_F64) FKR_AG_D(double); else FKR_AG_D(float);

@@ -86,7 +86,7 @@ class GCVLogH(torch.autograd.Function):
     def forward(ctx, log_h, Y, plan, Np, seed):
         h = torch.exp(log_h.detach().to(torch.float64)).cpu().numpy()
         out = plan.gcv_grad(h, Y.detach(), Np, seed, want_dy=Y.requires_grad)
-        dy = out["dy"].to(Y.dtype).reshape(Y.shape) if out["dy"] is not None else None
+        dy = out["dy"].to(Y.dtype).reshape(Y.shape) if out["dy"] is not None else None   # complex: dRe + i dIm
         ctx.save_for_backward(out["dlogh"].to(log_h.device, log_h.dtype), dy)
         return out["gcv"][0].to(log_h.device, log_h.dtype)
 
@@ -385,13 +385,19 @@ class Plan:
         [d][1+Np][M]."""
         hb = _hbuf(h, self.d)
         assert hb.shape[0] == 1, "one bandwidth"
-        Yr = Y.reshape(-1, 1).contiguous()
+        Yr, q, cplx = _real_view(Y.reshape(-1, 1))
+        assert q == 1, "one response column"
+        ny = 2 if cplx else 1
+        N = Yr.shape[0]
         gcv = torch.empty(1, dtype=torch.float64, device=self.device)
         dlogh = torch.empty(self.d, dtype=torch.float64, device=self.device)
-        dfit = torch.empty((self.d, 1 + Np, self.Mtot), dtype=torch.float64, device=self.device)
-        dy = torch.empty(Yr.shape[0], dtype=torch.float64, device=self.device) if want_dy else None
-        check(self.lib.fkr_gcv_grad(self._plan, _hptr(hb), _ptr(Yr), _dtype_code(Yr), Np, ctypes.c_uint64(seed),
-                                    _ptr(gcv), _ptr(dlogh), _ptr(dy), _ptr(dfit), _stream()), "fkr_gcv_grad")
+        dfit = torch.empty((self.d, ny + Np, self.Mtot), dtype=torch.float64, device=self.device)
+        dy = torch.empty((N, ny), dtype=torch.float64, device=self.device) if want_dy else None
+        check(self.lib.fkr_gcv_grad(self._plan, _hptr(hb), cplx, _ptr(Yr), _dtype_code(Yr), Np,
+                                    ctypes.c_uint64(seed), _ptr(gcv), _ptr(dlogh), _ptr(dy), _ptr(dfit), _stream()),
+              "fkr_gcv_grad")
+        if dy is not None:
+            dy = torch.view_as_complex(dy) if cplx else dy[:, 0]
         return {"gcv": gcv, "dlogh": dlogh, "dy": dy, "dfit": dfit}
 
     # -- prediction and inference ---------------------------------------

@@ -147,3 +147,34 @@ def test_gcv_autograd_backward():
     np.testing.assert_allclose(log_h.grad.numpy(), ref["dlogh"].cpu().numpy(), rtol=1e-12)
     np.testing.assert_allclose(Y.grad.cpu().numpy()[:, 0], ref["dy"].cpu().numpy(), rtol=1e-6,
                                atol=1e-6 * ref["dy"].abs().max().item())
+
+
+def test_gcv_grad_complex_local_quadratic_matches_oracle(orc):
+    """Complex y (the differentiated workload's kind of response), local
+    quadratic in 2-D, FP32 spreading: GCV, its gradient in log h and its
+    gradient d/dRe y + i d/dIm y against the oracle."""
+    N, Np, seed, d = 600, 4, 19, 2
+    rng = np.random.default_rng(950)
+    X = rng.random((N, d))
+    y = (np.exp(3j * X[:, 0]) * (1 + X[:, 1]) + 0.2 * (rng.standard_normal(N) + 1j * rng.standard_normal(N)))
+    M, h = (24, 20), np.array([0.12, 0.14])
+    plan = make_plan(2, 2, M, tuple(0.9 * h), tuple(1.1 * h), 1e-6, "fp32", n_max=N, max_weights=16, tprec="fp64")
+    plan.set_points(to_dev(X, torch.float32))
+    yc = y.astype(np.complex64)
+    out = plan.gcv_grad(h, torch.as_tensor(yc, device="cuda"), Np, seed)
+    Xr = X.astype(np.float32).astype(np.float64)
+    yr = yc.astype(np.complex128)
+    Wp = orc.probes(seed, N, Np).astype(np.float32).astype(np.float64)
+    lo, hi = (0.0, 0.0), (1.0, 1.0)
+    inc = orc.support(Xr, h, 2, M, lo, hi)[0]
+    g_ref = orc.gcv_criterion(Xr, yr, h, 2, M, lo, hi, Wp, inc)
+    dl_ref = orc.gcv_log_h_gradient(Xr, yr, h, 2, M, lo, hi, Wp, include=inc)
+    dy_ref = orc.gcv_y_gradient(Xr, yr, h, 2, M, lo, hi, Wp, include=inc)
+    dl = out["dlogh"].cpu().numpy()
+    dy = out["dy"].cpu().numpy()
+    e_l = np.abs(dl - dl_ref).max() / np.abs(dl_ref).max()
+    e_y = np.abs(dy - dy_ref).max() / np.abs(dy_ref).max()
+    print(f"complex l=2: gcv {out['gcv'].item():.8e}/{g_ref:.8e}; dlogh err {e_l:.2e}; dy err {e_y:.2e}; "
+          f"{inc.sum()} of {N} supported")
+    assert out["gcv"].item() == pytest.approx(g_ref, rel=1e-5)
+    assert e_l < 1e-5 and e_y < 1e-5

@@ -722,3 +722,33 @@ def test_gcv_y_gradient_matches_central_differences(orc):
         fd = (orc.gcv_criterion(X, y + e, h, 1, M, lo, hi, Wp, inc)
               - orc.gcv_criterion(X, y - e, h, 1, M, lo, hi, Wp, inc)) / 0.1
         assert g[i] == pytest.approx(fd, rel=1e-7, abs=1e-12)
+
+
+def test_gcv_gradients_complex_response(orc):
+    """Complex y: GCV uses |y - yhat|^2; the gradient d/dRe y + i d/dIm y
+    matches central differences along the real and the imaginary axis, and
+    the log-h gradient is the sum of the two parts' contributions (the GCV
+    of a complex response is that of its real part plus that of its
+    imaginary part in the numerator)."""
+    rng = np.random.default_rng(15)
+    N = 150
+    X = rng.random((N, 2))
+    y = np.exp(2j * X[:, 0]) * X[:, 1] + 0.2 * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi, h = (8, 8), (0.0, 0.0), (1.0, 1.0), np.array([0.15, 0.15])
+    inc = orc.support(X, h, 1, M, lo, hi)[0]
+    g = orc.gcv_y_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc)
+    for i in (3, 77, 140):
+        for unit, part in ((1.0, g[i].real), (1j, g[i].imag)):
+            e = np.zeros(N, dtype=complex)
+            e[i] = 0.05 * unit
+            fd = (orc.gcv_criterion(X, y + e, h, 1, M, lo, hi, Wp, inc)
+                  - orc.gcv_criterion(X, y - e, h, 1, M, lo, hi, Wp, inc)) / 0.1
+            assert part == pytest.approx(fd, rel=1e-7, abs=1e-12)
+    G = orc.gcv_criterion(X, y, h, 1, M, lo, hi, Wp, inc)
+    Gr = orc.gcv_criterion(X, y.real, h, 1, M, lo, hi, Wp, inc)
+    Gi = orc.gcv_criterion(X, y.imag, h, 1, M, lo, hi, Wp, inc)
+    assert G == pytest.approx(Gr + Gi, rel=1e-12)
+    np.testing.assert_allclose(orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, inc),
+                               orc.gcv_log_h_gradient(X, y.real, h, 1, M, lo, hi, Wp, inc)
+                               + orc.gcv_log_h_gradient(X, y.imag, h, 1, M, lo, hi, Wp, inc), rtol=1e-9)
