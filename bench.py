@@ -93,6 +93,8 @@ def _args():
                     help="grid points per pass in the oracle's timed sample (0: 512 in 3-D, 2048 in 2-D)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch workload (256 independent regressions; 64-probe x 32-bandwidth DF sweep)")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the differentiated workload (GCV and its gradients, complex y, N=4e6)")
     ap.add_argument("--no-inference", action="store_true",
                     help="skip the variance-of-fit / band / spline-prediction timing")
     ap.add_argument("--copy-probe", action="store_true",
@@ -415,6 +417,8 @@ def main() -> int:
         line["inference"] = _inference(w, Xd, Yd, args.transform, args.sigma, args.steps)
     if not args.no_batch:
         line["batch"] = _batch_workload(min(args.steps, 5))
+    if not args.no_grad:
+        line["differentiated"] = _grad_workload(min(args.steps, 5))
 
     sample = None
     if not args.no_cpu_baseline or not args.no_fp64_single:
@@ -479,6 +483,56 @@ def _inference(w, Xd, Yd, transform, sigma, steps, n_query=1_000_000):
            "predict_points_per_s": round(n_query / (t_pred * 1e-3), 1),
            "band_halfwidth_median": float(torch.median(iv["upper"][fin] - iv["lower"][fin]).item() / 2),
            "plan": "FP32 spreading, %s transforms, h_min = h / sqrt 2" % transform}
+    del plan
+    return out
+
+
+def _grad_workload(reps):
+    """The differentiated workload (complex y = 8 Lorentzian peaks + noise,
+    N = 4e6, M = 512^2, local quadratic, h = 0.02, 10 Philox probes, FP32
+    spreading, FP64 transforms and 6x6 solves), both replayed as HIP graphs
+    with the points already sorted: the forward GCV (fit, DF and GCV in one
+    fkr_cv call) and the forward plus the hand-written backward
+    (fkr_gcv_grad: GCV, its gradient in log h and in y)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2204_07716_amd import Plan
+    w = workloads.make("cplx2d")
+    h = np.asarray(w.h[0])
+    Np, seed = w.n_probes, w.probe_seed
+    dev = torch.device("cuda:0")
+    plan = Plan(2, 2, w.M, w.lo, w.hi, tuple(h), tuple(h), w.eps, precision="fp32", n_max=w.N, max_weights=28,
+                max_h=1, transform_precision="fp64")
+    plan.set_points(torch.as_tensor(w.X.astype(np.float32), device=dev))
+    Y = torch.as_tensor(w.Y[:, 0].astype(np.complex64), device=dev)
+
+    def replay_ms(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            res = fn()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, res
+
+    t_fwd, f = replay_ms(lambda: plan.cv(h, Y, Np, seed=seed, want_mhat=False))
+    t_both, r = replay_ms(lambda: plan.gcv_grad(h, Y, Np, seed))
+    out = {"N": w.N, "M": list(w.M), "order": 2, "probes": Np, "ms_forward": round(t_fwd, 3),
+           "ms_forward_backward": round(t_both, 3), "backward_over_forward": round(t_both / t_fwd - 1, 3),
+           "samples_per_s": round(w.N / (t_both * 1e-3), 1), "gcv": float(r["gcv"].item()),
+           "gcv_forward_only": float(f["gcv"][0, 0].item()),
+           "dlogh": [float(v) for v in r["dlogh"].cpu().numpy()],
+           "note": "points sorted outside the timed graphs; forward = fkr_cv, forward + backward = fkr_gcv_grad"}
     del plan
     return out
 

@@ -178,3 +178,46 @@ def test_gcv_grad_complex_local_quadratic_matches_oracle(orc):
           f"{inc.sum()} of {N} supported")
     assert out["gcv"].item() == pytest.approx(g_ref, rel=1e-5)
     assert e_l < 1e-5 and e_y < 1e-5
+
+
+def test_cplx2d_full_size_gradients():
+    """The differentiated workload at full size (complex Lorentzian peaks,
+    N = 4e6, M = 512^2, local quadratic, h = 0.02, 10 probes, FP32
+    spreading) through GCVLogH: GCV is quadratic in y, so its central
+    difference along the gradient's own direction equals the directional
+    derivative (checked to 1e-4, the FP32 noise of GCV over the step); the
+    log-h gradient against central differences of GCV (step 1e-3, to 1e-3)."""
+    import workloads
+    from paper_2204_07716_amd import GCVLogH
+    w = workloads.make("cplx2d")
+    h = np.asarray(w.h[0])
+    Np, seed = w.n_probes, w.probe_seed
+    plan = make_plan(2, 2, w.M, tuple(0.99 * h), tuple(1.01 * h), w.eps, "fp32", n_max=w.N, max_weights=28,
+                     tprec="fp64")
+    plan.set_points(to_dev(w.X, torch.float32))
+    Y = torch.as_tensor(w.Y[:, 0].astype(np.complex64), device="cuda").requires_grad_(True)
+    log_h = torch.tensor(np.log(h), dtype=torch.float64, requires_grad=True)
+    G = GCVLogH.apply(log_h, Y, plan, Np, seed)
+    G.backward()
+    G = G.item()
+    dy = Y.grad.detach().to(torch.complex128)
+    assert np.isfinite(G) and torch.isfinite(torch.view_as_real(dy)).all()
+    v = dy / torch.linalg.vector_norm(dy)
+    eps = 0.1 * G / torch.linalg.vector_norm(dy).item()            # about a 10% change of GCV
+    Yd = Y.detach().to(torch.complex128)
+    up = plan.cv(h, (Yd + eps * v).to(torch.complex64), Np, seed=seed)["gcv"].item()
+    dn = plan.cv(h, (Yd - eps * v).to(torch.complex64), Np, seed=seed)["gcv"].item()
+    dirv = torch.linalg.vector_norm(dy).item()                    # <dy, v> for v along dy
+    fd = (up - dn) / (2 * eps)
+    print(f"cplx2d: GCV {G:.6e}; directional derivative {dirv:.6e} vs central difference {fd:.6e}")
+    assert fd == pytest.approx(dirv, rel=1e-4)
+    dl = log_h.grad.numpy()
+    Yc = Y.detach()
+    for j in range(2):
+        e = np.zeros(2)
+        e[j] = 1e-3
+        gp = plan.cv(h * np.exp(e), Yc, Np, seed=seed)["gcv"].item()
+        gm = plan.cv(h * np.exp(-e), Yc, Np, seed=seed)["gcv"].item()
+        fdl = (gp - gm) / 2e-3
+        print(f"cplx2d: d GCV / d log h_{j} {dl[j]:.6e} vs central difference {fdl:.6e}")
+        assert dl[j] == pytest.approx(fdl, rel=1e-3, abs=1e-3 * G)
