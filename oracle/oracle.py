@@ -12,6 +12,8 @@ computes, by the plain definitions, slowly and in FP64:
                     A_bc = s_{b+c}, rhs_b = t_b, equilibrated by the bandwidth
                     and solved by LAPACK's pivoted LU (``numpy.linalg.solve``);
                     the fit is the intercept (e_1 of eq. 3).
+* ``moments_full``  the moment sums of eq. (9) for a Gaussian kernel with a full
+                    bandwidth matrix H (eq. 2), and ``fit_full`` the fit.
 * ``interp``        multilinear interpolation of a grid function (the linear
                     ``griddedInterpolant`` setting of Sec. 5).
 * ``philox4x32``    the Philox4x32-10 counter-based generator (Salmon et al.,
@@ -266,6 +268,49 @@ def solve(S: np.ndarray, T: np.ndarray, h: Sequence[float], order: int, d: int):
             c = np.linalg.solve(A[ok], np.transpose(rhs[ok], (0, 2, 1)))
             mhat[ok] = c[:, 0, :]
     return mhat, r0, ill
+
+
+def moments_full(X: np.ndarray, W: Optional[np.ndarray], H: np.ndarray, order: int, gpts: np.ndarray):
+    """s_a(g) and t_{w,b}(g) of eq. (9) for the Gaussian kernel with a full
+    bandwidth matrix H (eq. 2: K_H(u) = |H|^{-1/2} K(H^{-1/2} u), K the
+    standard normal density, so K_H(u) = exp(-u^T H^{-1} u / 2) /
+    ((2 pi)^{d/2} |H|^{1/2})), by direct summation in NumPy.  Returns S
+    (G x n_s) and T (G x nw x n_t)."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    N, d = X.shape
+    H = np.asarray(H, dtype=np.float64).reshape(d, d)
+    Hi = np.linalg.inv(H)
+    norm = 1.0 / np.sqrt((2.0 * np.pi) ** d * np.linalg.det(H))
+    W = np.zeros((N, 0)) if W is None else np.asarray(W, dtype=np.float64).reshape(N, -1)
+    gpts = np.asarray(gpts, dtype=np.float64).reshape(-1, d)
+    es = np.array(multi_indices(d, 2 * order))
+    et = np.array(multi_indices(d, order))
+    S = np.zeros((len(gpts), len(es)))
+    T = np.zeros((len(gpts), W.shape[1], len(et)))
+    for g in range(len(gpts)):
+        u = X - gpts[g]                                        # z = x_i - g
+        K = norm * np.exp(-0.5 * np.einsum("ij,jk,ik->i", u, Hi, u))
+        for a, e in enumerate(es):
+            S[g, a] = np.sum(K * np.prod(u ** e, axis=1))
+        for b, e in enumerate(et):
+            T[g, :, b] = (K * np.prod(u ** e, axis=1)) @ W
+    return S, T
+
+
+def fit_full(X, Y, H, order, gpts):
+    """m_hat(g) of eq. (3) with the full bandwidth matrix H (real Y, N x q),
+    the moment matrix equilibrated by sqrt(diag H).  Returns (mhat, S, ill)."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    d = X.shape[1]
+    W = np.asarray(Y, dtype=np.float64).reshape(X.shape[0], -1)
+    S, T = moments_full(X, W, H, order, gpts)
+    s = np.sqrt(np.diag(np.asarray(H, dtype=np.float64).reshape(d, d)))
+    mhat, r0, ill = solve(S, T, s, order, d)
+    return mhat, S, ill
 
 
 def _split_complex(Y: np.ndarray):

@@ -752,3 +752,54 @@ def test_gcv_gradients_complex_response(orc):
     np.testing.assert_allclose(orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, inc),
                                orc.gcv_log_h_gradient(X, y.real, h, 1, M, lo, hi, Wp, inc)
                                + orc.gcv_log_h_gradient(X, y.imag, h, 1, M, lo, hi, Wp, inc), rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Full bandwidth matrix (eq. 2 with a general H)
+# ---------------------------------------------------------------------------
+
+def test_moments_full_diagonal_equals_product_kernel(orc):
+    """A diagonal H = diag(h^2) is the product Gaussian of the C oracle."""
+    rng = np.random.default_rng(16)
+    X = rng.random((300, 3))
+    W = rng.standard_normal((300, 2))
+    h = np.array([0.11, 0.15, 0.09])
+    g = rng.random((7, 3))
+    S1, T1 = orc.moments_full(X, W, np.diag(h ** 2), 2, g)
+    S2, T2 = orc.moments(X, W, h, 2, g)
+    np.testing.assert_allclose(S1, S2, rtol=1e-11, atol=1e-13 * np.abs(S2).max())
+    np.testing.assert_allclose(T1, T2, rtol=1e-11, atol=1e-13 * np.abs(T2).max())
+
+
+def test_moments_full_lattice_integrals(orc):
+    """On a dense unit-weight lattice s_a(g) Delta^d is the Gaussian moment
+    E[Z^a] for Z ~ N(0, H): 1, 0 for odd orders, H for the second moments,
+    and Isserlis' H_jj H_kk + 2 H_jk^2 for E[Z_j^2 Z_k^2]."""
+    H = np.array([[0.010, 0.006], [0.006, 0.016]])
+    delta = 0.012
+    ax = np.arange(-1.2, 1.2 + 1e-12, delta)
+    X = np.stack(np.meshgrid(ax, ax, indexing="ij"), -1).reshape(-1, 2)
+    S, _ = orc.moments_full(X, None, H, 2, np.array([[0.003, -0.002]]))
+    S = S[0] * delta ** 2
+    es = orc.multi_indices(2, 4)
+    want = {(0, 0): 1.0, (2, 0): H[0, 0], (1, 1): H[0, 1], (0, 2): H[1, 1],
+            (2, 2): H[0, 0] * H[1, 1] + 2 * H[0, 1] ** 2, (4, 0): 3 * H[0, 0] ** 2,
+            (3, 1): 3 * H[0, 0] * H[0, 1], (1, 3): 3 * H[1, 1] * H[0, 1], (0, 4): 3 * H[1, 1] ** 2,
+            (1, 0): 0.0, (0, 1): 0.0, (3, 0): 0.0, (2, 1): 0.0, (1, 2): 0.0, (0, 3): 0.0}
+    for a, e in enumerate(es):
+        assert S[a] == pytest.approx(want[tuple(e)], abs=1e-9)
+
+
+def test_fit_full_rotation_invariant(orc):
+    """Rotating the samples, the evaluation point and H together (H -> R H
+    R^T) leaves the local-linear fit unchanged."""
+    rng = np.random.default_rng(17)
+    X = rng.random((400, 2))
+    y = np.sin(3 * X[:, 0]) + X[:, 1] ** 2 + 0.1 * rng.standard_normal(400)
+    H = np.array([[0.02, -0.008], [-0.008, 0.012]])
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    g = np.array([[0.4, 0.55], [0.2, 0.8]])
+    m1 = orc.fit_full(X, y, H, 1, g)[0]
+    m2 = orc.fit_full(X @ R.T, y, R @ H @ R.T, 1, g @ R.T)[0]
+    np.testing.assert_allclose(m1, m2, rtol=1e-10)
