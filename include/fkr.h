@@ -215,6 +215,22 @@ fkr_status fkr_fit_noalloc(fkr_plan* plan, int64_t N, const void* X_dev, int x_t
                            const double* h, int q, int y_complex, const void* Y_dev, int y_type,
                            double* mhat_dev, double* s0_dev, void* stream);
 
+/* Moments and fits with a full bandwidth matrix (eq. 2: K_H(u) =
+ * |H|^{-1/2} K(H^{-1/2} u), K the standard Gaussian density), nh matrices H
+ * (host, nh x d x d doubles, row-major, symmetric positive definite).  The
+ * transform of u^a K_H(u) is (-i)^{|a|} He_a(w) exp(-w^T H w / 2), with the
+ * multivariate Hermite polynomials of H (He_0 = 1, He_{b+e_j} = (H w)_j He_b
+ * - sum_k b_k H_jk He_{b-e_k}), evaluated per retained mode; everything
+ * else is the path of fkr_moments / fkr_fit.  Channels are equilibrated by
+ * s^a, s_j = sqrt(H_jj).  Each H must have s_j <= h_max_j (the padding holds
+ * the kernel's reach along axis j) and 1 / sqrt((H^-1)_jj) >= h_min_j (the
+ * band holds its spectrum along frequency axis j), else FKR_E_ARG; the
+ * ill-posedness floor uses K_H(0).  Layouts as fkr_moments and fkr_fit. */
+fkr_status fkr_moments_full(fkr_plan* plan, int nh, const double* H, int nw, const void* W_dev, int w_type,
+                            double* S_dev, double* T_dev, void* stream);
+fkr_status fkr_fit_full(fkr_plan* plan, int nh, const double* H, int q, int y_complex, const void* Y_dev,
+                        int y_type, double* mhat_dev, double* s0_dev, void* stream);
+
 /* Multilinear interpolation (the linear griddedInterpolant of Sec. 1.1/5) of
  * nv grid functions G_dev ([nv][M^d] doubles) at Nq query points Xq_dev
  * (Nq x d, type x_type) -> out_dev ([nv][Nq] doubles).  The cell of a point

@@ -251,7 +251,8 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
 // channels in log h of that dimension; pair_off places the channels that
 // many pairs up in the channel buffer.
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
-                        bool reuse = false, int tag = 1, int deriv_dim = -1, int64_t pair_off = 0) {
+                        bool reuse = false, int tag = 1, int deriv_dim = -1, int64_t pair_off = 0,
+                        const FullH* full = nullptr) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
     if (ncp + pair_off > p->ncp_max) return FKR_E_ARG;
@@ -296,7 +297,11 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     // extent) and writes each row's M_j outputs contiguously, so every pass
     // stores whole rows and the last one leaves the channels pair-major,
     // [pair][M^d][re, im] with m_0 fastest.
-    launch_expand(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftB, skip_flag, c_keep, s);
+    if (full)
+        launch_expand_full(p->tprec, a, *full, dev_es(p), dev_pidx(p), p->ws + p->lay.spec, p->ws + p->lay.fftB, s);
+    else
+        launch_expand(p->tprec, a, dev_es(p), dev_et(p), p->ws + p->lay.spec, p->ws + p->lay.fftB, skip_flag, c_keep,
+                      s);
     const void* in = p->ws + p->lay.fftB;
     for (int j = p->d - 1; j >= 0; --j) {
         FftPass f = pass(j);
@@ -491,6 +496,88 @@ std::vector<std::pair<size_t, std::vector<unsigned char>>> constant_tables(const
         off += p->cover[j].size() * 4;
     }
     return out;
+}
+
+// A full bandwidth matrix (d x d, row-major): symmetric, positive definite,
+// its marginal standard deviations s_j = sqrt(H_jj) within the plan's h_max
+// (the zero padding covers the kernel's reach along each axis) and its
+// spectrum's reach along each frequency axis, 1 / sqrt((H^-1)_jj), at least
+// the plan's h_min (the band holds it).  Fills the Hermite recurrence tables
+// and heff, per-dimension widths with prod heff = sqrt(det H) (the kernel's
+// peak, for the ill-posedness floor).
+fkr_status build_full(const fkr_plan* p, const double* H, FullH* fh, double* heff) {
+    const int d = p->d;
+    *fh = FullH{};
+    double A[3][3] = {};
+    for (int j = 0; j < d; ++j)
+        for (int k = 0; k < d; ++k) {
+            const double v = H[j * d + k];
+            if (!std::isfinite(v)) return FKR_E_ARG;
+            A[j][k] = v;
+            fh->H[3 * j + k] = v;
+        }
+    for (int j = 0; j < d; ++j)
+        for (int k = 0; k < j; ++k)
+            if (std::fabs(A[j][k] - A[k][j]) > 1e-12 * std::sqrt(std::fabs(A[j][j] * A[k][k]))) return FKR_E_ARG;
+    // Cholesky H = L L^T
+    double L[3][3] = {};
+    double det = 1.0;
+    for (int c = 0; c < d; ++c) {
+        double v = A[c][c];
+        for (int q = 0; q < c; ++q) v -= L[c][q] * L[c][q];
+        if (!(v > 0.0)) return FKR_E_ARG;
+        L[c][c] = std::sqrt(v);
+        det *= v;
+        for (int b = c + 1; b < d; ++b) {
+            double u = A[b][c];
+            for (int q = 0; q < c; ++q) u -= L[b][q] * L[c][q];
+            L[b][c] = u / L[c][c];
+        }
+    }
+    // (H^-1)_jj = || L^-1 e_j ||^2
+    for (int j = 0; j < d; ++j) {
+        double y[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < d; ++b) {
+            double v = b == j ? 1.0 : 0.0;
+            for (int q = 0; q < b; ++q) v -= L[b][q] * y[q];
+            y[b] = v / L[b][b];
+        }
+        double ii = 0.0;
+        for (int b = 0; b < d; ++b) ii += y[b] * y[b];
+        const double sj = std::sqrt(A[j][j]);
+        fh->s[j] = sj;
+        if (sj > p->h_max[j] * (1 + 1e-12)) return FKR_E_ARG;
+        if (1.0 / std::sqrt(ii) < p->h_min[j] * (1 - 1e-12)) return FKR_E_ARG;
+    }
+    double sprod = 1.0;
+    for (int j = 0; j < d; ++j) sprod *= fh->s[j];
+    const double shrink = std::pow(std::sqrt(det) / sprod, 1.0 / d);
+    for (int j = 0; j < d; ++j) heff[j] = fh->s[j] * shrink;
+    auto find = [&](const int* e) {
+        for (int c = 0; c < p->n_s; ++c) {
+            bool eq = true;
+            for (int k = 0; k < d; ++k) eq &= p->es[c][k] == e[k];
+            if (eq) return c;
+        }
+        return -1;
+    };
+    for (int c = 1; c < p->n_s; ++c) {
+        int j = 0;
+        while (p->es[c][j] == 0) ++j;
+        int b[3] = {p->es[c][0], p->es[c][1], p->es[c][2]};
+        b[j] -= 1;
+        fh->rj[c] = j;
+        fh->rb[c] = find(b);
+        for (int k = 0; k < 3; ++k) {
+            fh->rbk[c][k] = -1;
+            if (k < d && b[k] > 0) {
+                int bk[3] = {b[0], b[1], b[2]};
+                bk[k] -= 1;
+                fh->rbk[c][k] = find(bk);
+            }
+        }
+    }
+    return FKR_OK;
 }
 
 // z with Phi(z) = 1 - alpha / 2 (the quantile of eq. 28): bisection on the
@@ -701,6 +788,66 @@ fkr_status fkr_fit(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
             StageTimer t(p, FKR_STAGE_SOLVE, s);
             launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
         }
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_fit_full(fkr_plan* p, int nh, const double* H, int q, int y_complex, const void* Y, int y_type,
+                        double* mhat, double* s0, void* stream) {
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if (nh < 1 || nh > p->max_h || !H || q < 1 || !mhat || (p->N > 0 && !Y) || (y_complex != 0 && y_complex != 1) ||
+        !valid_type(y_type))
+        return FKR_E_ARG;
+    const int ny = q * (y_complex ? 2 : 1);
+    if (1 + ny > p->max_weights) return FKR_E_ARG;
+    const int dd = p->d * p->d;
+    std::vector<FullH> fh(nh);
+    std::vector<double> heff(3 * nh, 0.0);
+    for (int hi = 0; hi < nh; ++hi)
+        if ((st = build_full(p, H + hi * dd, &fh[hi], &heff[3 * hi])) != FKR_OK) return st;
+    const hipStream_t s = S(stream);
+    std::vector<WSrc> srcs{src_one()};
+    add_response_sources(&srcs, q, y_complex, Y, y_type);
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
+    const int nr = (int)srcs.size();
+    for (int hi = 0; hi < nh; ++hi) {
+        if ((st = run_channels(p, fh[hi].s, nr, hi == 0 ? ill_ctr(p) : nullptr, s, false, 0, -1, 0, &fh[hi])) !=
+            FKR_OK)
+            return st;
+        SolveArgs a = solve_args(p, nr, ny, y_complex, &heff[3 * hi]);
+        a.y_out = mhat + (int64_t)hi * ny * p->Mtot;
+        a.s0_out = s0 ? s0 + (int64_t)hi * p->Mtot : nullptr;
+        StageTimer t(p, FKR_STAGE_SOLVE, s);
+        launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
+    }
+    p->last_stream = stream;
+    return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_moments_full(fkr_plan* p, int nh, const double* H, int nw, const void* W, int w_type, double* Sout,
+                            double* Tout, void* stream) {
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if (nh < 1 || nh > p->max_h || !H || nw < 0 || (nw > 0 && p->N > 0 && !W) || 1 + nw > p->max_weights) return FKR_E_ARG;
+    if (nw > 0 && !valid_type(w_type)) return FKR_E_ARG;
+    const int dd = p->d * p->d;
+    std::vector<FullH> fh(nh);
+    std::vector<double> heff(3 * nh, 0.0);
+    for (int hi = 0; hi < nh; ++hi)
+        if ((st = build_full(p, H + hi * dd, &fh[hi], &heff[3 * hi])) != FKR_OK) return st;
+    const hipStream_t s = S(stream);
+    std::vector<WSrc> srcs{src_one()};
+    for (int r = 0; r < nw; ++r) srcs.push_back(src_array(W, w_type, nw, r));
+    if ((st = run_spectra(p, srcs, s, false)) != FKR_OK) return st;
+    const int nr = 1 + nw;
+    const int ncp = (p->n_s + p->n_t * nw + 1) / 2;
+    for (int hi = 0; hi < nh; ++hi) {
+        if ((st = run_channels(p, fh[hi].s, nr, nullptr, s, false, 0, -1, 0, &fh[hi])) != FKR_OK) return st;
+        launch_chan_out(p->tprec, p->Mtot, ncp, p->n_s, p->n_t, nw, p->ws + p->lay.chan,
+                        Sout ? Sout + (int64_t)hi * p->n_s * p->Mtot : nullptr,
+                        Tout ? Tout + (int64_t)hi * nw * p->n_t * p->Mtot : nullptr, s);
     }
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;

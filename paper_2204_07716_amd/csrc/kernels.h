@@ -56,6 +56,19 @@ struct ExpandArgs {
     int deriv_dim;           // >= 0: the multipliers' derivative in log h of this dimension
 };
 
+// Moment multipliers of the Gaussian with a full bandwidth matrix H: the
+// transform of u^a K_H(u) is (-i)^{|a|} He_a(w) exp(-w^T H w / 2) with the
+// multivariate Hermite polynomials of H, He_0 = 1 and
+// He_{b + e_j} = z_j He_b - sum_k b_k H_jk He_{b - e_k}, z = H w.  Per
+// s-channel c (graded order) with |a_c| >= 1: the dimension j it is built
+// along, the channel of b = a_c - e_j, and per k the channel of b - e_k (-1
+// when b_k = 0); channels are divided by s^a, s_j = sqrt(H_jj).
+struct FullH {
+    double H[9];
+    double s[3];
+    int rj[kMaxChannels], rb[kMaxChannels], rbk[kMaxChannels][3];
+};
+
 // Derivative of the fits in log h_j (one dimension per launch), per grid
 // point from the equilibrated channels at h (A, t) and their derivatives
 // (dA, dt): d m_hat = e_0^T A^{-1} (dt - dA A^{-1} t).
@@ -282,6 +295,8 @@ hipError_t static_scratch(void** ptr);
 // groups gstride elements apart (FP32 only).
 void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t gstride, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
+void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const int* es, const int* pidx,
+                        const void* spec, void* out, hipStream_t s);
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);
 void launch_chan_untag(long long* diag, hipStream_t s);
 void launch_stage_grid(const Geo& g, int prec, const PointsCheck& pc, const void* xs, const double* G, void* rows,

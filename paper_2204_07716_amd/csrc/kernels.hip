@@ -1579,6 +1579,99 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
     }
 }
 
+// Channel spectra for a full bandwidth matrix: one thread per band index n;
+// the multipliers of all s-channels by the multivariate Hermite recurrence
+// into LDS, then every channel pair of the launch (t-channel b uses the
+// s-channel of b; the weight spectra are unpacked from the pair spectra).
+template <typename T>
+__global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, FullH fh, const int* es,
+                                                                const int* pidx, const typename V2<T>::t* spec,
+                                                                typename V2<T>::t* out) {
+    __shared__ double mf[kMaxChannels][kExpandThreads];
+    const int tid = threadIdx.x;
+    const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && a.ill_clear) *a.ill_clear = 0ull;
+    if (n >= a.Btot) return;
+    unsigned nn = 0, rem = (unsigned)n, stride = 1;
+    double w[3] = {0.0, 0.0, 0.0};
+    double tprod = 1.0;
+    for (int j = 0; j < a.d; ++j) {
+        const unsigned bj = (unsigned)a.B[j];
+        const unsigned qj = rem / bj;
+        const int ej = (int)(rem - qj * bj);
+        rem = qj;
+        nn += (bj - 1 - (unsigned)ej) * stride;
+        stride *= bj;
+        w[j] = 2.0 * M_PI * (double)(ej - a.K[j]) / a.T[j];
+        tprod *= a.T[j];
+    }
+    double z[3] = {0.0, 0.0, 0.0}, q = 0.0;
+    for (int j = 0; j < a.d; ++j) {
+        for (int k = 0; k < a.d; ++k) z[j] += fh.H[3 * j + k] * w[k];
+        q += w[j] * z[j];
+    }
+    const double G = exp(-0.5 * q) / tprod;
+    mf[0][tid] = 1.0;
+    for (int c = 1; c < a.n_s; ++c) {
+        const int j = fh.rj[c];
+        double v = z[j] * mf[fh.rb[c]][tid];
+        for (int k = 0; k < a.d; ++k) {
+            const int bk = fh.rbk[c][k];
+            if (bk >= 0) v -= (double)es[3 * fh.rb[c] + k] * fh.H[3 * j + k] * mf[bk][tid];
+        }
+        mf[c][tid] = v;
+    }
+    for (int c = 0; c < a.n_s; ++c) {
+        double sc = 1.0;
+        for (int k = 0; k < a.d; ++k)
+            for (int e = 0; e < es[3 * c + k]; ++e) sc *= fh.s[k];
+        mf[c][tid] *= G / sc;
+    }
+    for (int c = (int)blockIdx.y; c < a.ncp; c += (int)gridDim.y) {
+        double acc_re = 0.0, acc_im = 0.0;
+        for (int half = 0; half < 2; ++half) {
+            const int ch = 2 * c + half;
+            if (ch >= a.nreal) break;
+            int r, si;
+            if (ch < a.n_s) { r = 0; si = ch; }
+            else { r = 1 + (ch - a.n_s) / a.n_t; si = pidx[((ch - a.n_s) % a.n_t) * kMaxP]; }
+            int deg = 0;
+            for (int k = 0; k < a.d; ++k) deg += es[3 * si + k];
+            const typename V2<T>::t zn = spec[n * a.npairs + (r >> 1)];
+            const typename V2<T>::t zm = spec[(int64_t)nn * a.npairs + (r >> 1)];
+            double cr, ci;
+            if ((r & 1) == 0) { cr = 0.5 * ((double)zn.x + (double)zm.x); ci = 0.5 * ((double)zn.y - (double)zm.y); }
+            else { cr = 0.5 * ((double)zn.y + (double)zm.y); ci = -0.5 * ((double)zn.x - (double)zm.x); }
+            const double m = mf[si][tid];
+            double xr = cr * m, xi = ci * m;
+            switch (deg & 3) {   // multiply by i^deg
+                case 1: { const double t0 = xr; xr = -xi; xi = t0; break; }
+                case 2: xr = -xr; xi = -xi; break;
+                case 3: { const double t0 = xr; xr = xi; xi = -t0; break; }
+                default: break;
+            }
+            if (half == 0) { acc_re += xr; acc_im += xi; }
+            else { acc_re -= xi; acc_im += xr; }
+        }
+        typename V2<T>::t o;
+        o.x = (T)acc_re;
+        o.y = (T)acc_im;
+        out[(int64_t)c * a.Btot + n] = o;
+    }
+}
+
+void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const int* es, const int* pidx,
+                        const void* spec, void* out, hipStream_t s) {
+    const dim3 nbn((unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads),
+                   (unsigned)std::min(4, std::max(1, a.ncp)));
+    if (prec == FKR_F64)
+        k_expand_full<double><<<nbn, kExpandThreads, 0, s>>>(a, fh, es, pidx, static_cast<const double2*>(spec),
+                                                             static_cast<double2*>(out));
+    else
+        k_expand_full<float><<<nbn, kExpandThreads, 0, s>>>(a, fh, es, pidx, static_cast<const float2*>(spec),
+                                                            static_cast<float2*>(out));
+}
+
 void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,
                    const long long* skip_flag, int64_t c_keep, hipStream_t s) {
     // up to four workgroup rows of channel pairs (more waves for few band indices)

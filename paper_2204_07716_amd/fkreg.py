@@ -378,6 +378,33 @@ class Plan:
               "fkr_variance")
         return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
 
+    # -- full bandwidth matrices ----------------------------------------
+    def fit_full(self, H, Y: torch.Tensor, want_s0: bool = False):
+        """Fits with full bandwidth matrices H ([nh] x d x d)."""
+        Hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(-1, self.d, self.d))
+        nh = Hb.shape[0]
+        Yr, q, cplx = _real_view(Y)
+        mhat = torch.empty((nh, q, self.Mtot) + ((2,) if cplx else ()), dtype=torch.float64, device=self.device)
+        s0 = torch.empty((nh, self.Mtot), dtype=torch.float64, device=self.device) if want_s0 else None
+        check(self.lib.fkr_fit_full(self._plan, nh, Hb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), q, cplx,
+                                    _ptr(Yr), _dtype_code(Yr), _ptr(mhat), _ptr(s0), _stream()), "fkr_fit_full")
+        if cplx:
+            mhat = torch.view_as_complex(mhat)
+        return (mhat, s0) if want_s0 else mhat
+
+    def moments_full(self, H, W: Optional[torch.Tensor] = None):
+        Hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(-1, self.d, self.d))
+        nh = Hb.shape[0]
+        nw = 0 if W is None else (W.shape[1] if W.dim() > 1 else 1)
+        if W is not None:
+            W = W.reshape(W.shape[0], -1).contiguous()
+        S = torch.empty((nh, self.n_s, self.Mtot), dtype=torch.float64, device=self.device)
+        T = torch.empty((nh, nw, self.n_t, self.Mtot), dtype=torch.float64, device=self.device) if nw else None
+        check(self.lib.fkr_moments_full(self._plan, nh, Hb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nw,
+                                        _ptr(W), _dtype_code(W) if W is not None else 1, _ptr(S), _ptr(T),
+                                        _stream()), "fkr_moments_full")
+        return S, T
+
     # -- differentiation ------------------------------------------------
     def gcv_grad(self, h, Y: torch.Tensor, Np: int, seed: int = 0, want_dy: bool = True) -> dict:
         """GCV at h for one real response with Np Philox probes, its gradients
