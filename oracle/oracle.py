@@ -12,6 +12,9 @@ computes, by the plain definitions, slowly and in FP64:
                     A_bc = s_{b+c}, rhs_b = t_b, equilibrated by the bandwidth
                     and solved by LAPACK's pivoted LU (``numpy.linalg.solve``);
                     the fit is the intercept (e_1 of eq. 3).
+* ``moments_compact`` exact moment sums for the compact kernels of Table 1,
+                    ``moments_binned`` their binned approximation of eq. (11)-(13)
+                    (sampled kernel, discrete transform over the whole period).
 * ``moments_full``  the moment sums of eq. (9) for a Gaussian kernel with a full
                     bandwidth matrix H (eq. 2), and ``fit_full`` the fit.
 * ``interp``        multilinear interpolation of a grid function (the linear
@@ -311,6 +314,90 @@ def fit_full(X, Y, H, order, gpts):
     s = np.sqrt(np.diag(np.asarray(H, dtype=np.float64).reshape(d, d)))
     mhat, r0, ill = solve(S, T, s, order, d)
     return mhat, S, ill
+
+
+COMPACT_KERNELS = ("box", "triangle", "epanechnikov", "biweight", "triweight")
+
+
+def compact_kernel(name: str, u):
+    """The compact kernels of Table 1 on |u| <= 1 (each integrates to one)."""
+    u = np.asarray(u, dtype=np.float64)
+    q = 1.0 - u * u
+    inside = np.abs(u) <= 1.0
+    v = {"box": np.full_like(u, 0.5), "triangle": 1.0 - np.abs(u), "epanechnikov": 0.75 * q,
+         "biweight": 15.0 / 16.0 * q ** 2, "triweight": 35.0 / 32.0 * q ** 3}[name]
+    return np.where(inside, v, 0.0)
+
+
+def moments_compact(X, W, h, order, gpts, kernel: str):
+    """The exact moment sums of eq. (9) for the product kernel
+    K_h(u) = prod_j K(u_j / h_j) / h_j of a compact K, by direct summation."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    N, d = X.shape
+    h = np.asarray(h, dtype=np.float64)
+    W = np.zeros((N, 0)) if W is None else np.asarray(W, dtype=np.float64).reshape(N, -1)
+    gpts = np.asarray(gpts, dtype=np.float64).reshape(-1, d)
+    es, et = np.array(multi_indices(d, 2 * order)), np.array(multi_indices(d, order))
+    S = np.zeros((len(gpts), len(es)))
+    T = np.zeros((len(gpts), W.shape[1], len(et)))
+    for g in range(len(gpts)):
+        u = X - gpts[g]
+        K = np.prod(compact_kernel(kernel, u / h) / h, axis=1)
+        for a, e in enumerate(es):
+            S[g, a] = np.sum(K * np.prod(u ** e, axis=1))
+        for b, e in enumerate(et):
+            T[g, :, b] = (K * np.prod(u ** e, axis=1)) @ W
+    return S, T
+
+
+def moments_binned(X, W, h, order, gpts, kernel: str, delta, L):
+    """The binned approximation of the moment sums (eq. 11-13): the moment
+    kernels k_a(z) = z^a K_h(z) sampled at the grid offsets m delta over one
+    period T = L delta and convolved with the samples through their discrete
+    transform, which makes each sample's contribution the trigonometric
+    interpolant of the sampled kernel (the Fourier series of the periodised
+    samples over every mode |n| <= L / 2, the modes +-L/2 of an even L with
+    half the Nyquist coefficient each) at x_i - g.  Per dimension the
+    transform is NumPy's FFT of the samples; the series is summed directly."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    N, d = X.shape
+    h = np.asarray(h, dtype=np.float64)
+    delta = np.asarray(delta, dtype=np.float64).reshape(d)
+    L = np.asarray(L, dtype=np.int64).reshape(d)
+    W = np.zeros((N, 0)) if W is None else np.asarray(W, dtype=np.float64).reshape(N, -1)
+    gpts = np.asarray(gpts, dtype=np.float64).reshape(-1, d)
+    es, et = np.array(multi_indices(d, 2 * order)), np.array(multi_indices(d, order))
+    deg = 2 * order
+    # per dimension: coefficients c_{j,a}(n) of the interpolant of z^a K_h(z)
+    coef, freq = [], []
+    for j in range(d):
+        m = np.arange(L[j])
+        z = np.where(m <= L[j] // 2, m, m - L[j]) * delta[j]            # periodised offsets
+        kz = compact_kernel(kernel, z / h[j]) / h[j]
+        K = L[j] // 2
+        n = np.arange(-K, K + 1)
+        half = np.where(2 * np.abs(n) == L[j], 0.5, 1.0)                # even L: +-L/2 share the Nyquist term
+        cj = []
+        for a in range(deg + 1):
+            F = np.fft.fft(z ** a * kz) * delta[j]                      # sum_m k(z_m) e^{-2 pi i n m / L} delta
+            cj.append(half * F[n % L[j]] / (L[j] * delta[j]))
+        coef.append(np.array(cj))
+        freq.append(2.0 * np.pi * n / (L[j] * delta[j]))
+    S = np.zeros((len(gpts), len(es)))
+    T = np.zeros((len(gpts), W.shape[1], len(et)))
+    for g in range(len(gpts)):
+        u = X - gpts[g]
+        # interpolant values per dimension and degree: [d][deg+1][N]
+        vals = [np.real(np.exp(1j * np.outer(u[:, j], freq[j])) @ coef[j].T).T for j in range(d)]
+        for a, e in enumerate(es):
+            S[g, a] = np.sum(np.prod([vals[j][e[j]] for j in range(d)], axis=0))
+        for b, e in enumerate(et):
+            T[g, :, b] = np.prod([vals[j][e[j]] for j in range(d)], axis=0) @ W
+    return S, T
 
 
 def _split_complex(Y: np.ndarray):

@@ -803,3 +803,59 @@ def test_fit_full_rotation_invariant(orc):
     m1 = orc.fit_full(X, y, H, 1, g)[0]
     m2 = orc.fit_full(X @ R.T, y, R @ H @ R.T, 1, g @ R.T)[0]
     np.testing.assert_allclose(m1, m2, rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Compact kernels (Table 1 kernel_type) and the binned approximation (eq. 11-13)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["box", "triangle", "epanechnikov", "biweight", "triweight"])
+def test_compact_kernels_are_densities(orc, name):
+    """Each kernel integrates to one, is symmetric and vanishes beyond |u| = 1
+    (midpoint rule on a fine lattice)."""
+    u = np.arange(-120000, 120001) * 1e-5                        # exactly symmetric lattice
+    k = orc.compact_kernel(name, u)
+    assert np.sum(k) * 1e-5 == pytest.approx(1.0, abs=2e-5)
+    np.testing.assert_array_equal(k, k[::-1])
+    assert (k[np.abs(u) > 1] == 0).all()
+
+
+@pytest.mark.parametrize("name", ["box", "epanechnikov", "triweight"])
+def test_binned_moments_exact_for_samples_on_grid_nodes(orc, name):
+    """The trigonometric interpolant of the sampled kernel passes through its
+    samples, so for samples on grid nodes the binned moments equal the exact
+    sums (2-D, up to degree 4)."""
+    rng = np.random.default_rng(18)
+    delta = np.array([0.02, 0.025])
+    L = np.array([90, 72])
+    k = np.stack([rng.integers(10, 40, 300), rng.integers(8, 30, 300)], axis=1)
+    X = k * delta
+    W = rng.standard_normal((300, 1))
+    g = np.array([[0.4, 0.3], [0.5, 0.45]])                       # grid nodes too
+    h = np.array([0.13, 0.11])
+    S1, T1 = orc.moments_binned(X, W, h, 2, g, name, delta, L)
+    S2, T2 = orc.moments_compact(X, W, h, 2, g, name)
+    np.testing.assert_allclose(S1, S2, rtol=1e-9, atol=1e-11 * np.abs(S2).max())
+    np.testing.assert_allclose(T1, T2, rtol=1e-9, atol=1e-11 * np.abs(T2).max())
+
+
+def test_binned_moments_converge_with_kernel_smoothness(orc):
+    """Off the nodes the binned sums approach the exact ones as the grid
+    refines, faster for smoother kernels: halving delta / h cuts the error
+    of the triweight (two continuous derivatives) more than that of the box
+    (discontinuous)."""
+    rng = np.random.default_rng(19)
+    X = rng.random((400, 1)) * 0.6 + 0.2
+    g = np.array([[0.5]])
+    h = np.array([0.1])
+
+    def err(name, delta):
+        L = int(round(1.5 / delta))
+        S1, _ = orc.moments_binned(X, None, h, 0, g, name, [delta], [L])
+        S2, _ = orc.moments_compact(X, None, h, 0, g, name)
+        return abs(S1[0, 0] - S2[0, 0]) / S2[0, 0]
+
+    rb = err("box", 0.01) / err("box", 0.005)
+    rt = err("triweight", 0.01) / err("triweight", 0.005)
+    assert err("triweight", 0.005) < 1e-3
+    assert rt > rb
