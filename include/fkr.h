@@ -61,6 +61,13 @@ enum { FKR_KERNEL_ES = 0, FKR_KERNEL_GAUSS = 1 }; /* spreading (gridding) kernel
 enum { FKR_VAR_LOG = 0, FKR_VAR_DIRECT = 1 };   /* variance estimator */
 enum { FKR_TP_SAME = 0, FKR_TP_F32 = 1, FKR_TP_F64 = 2 }; /* transform precision */
 enum { FKR_SIG_SCALAR = 0, FKR_SIG_GRID = 1 };   /* error variance of fkr_interval */
+/* Regression kernel K of eq. (2) (Table 1 kernel_type).  The Gaussian is the
+ * standard normal density and h its standard deviation; the compact kernels
+ * live on |u| <= 1 with h the half-width of their support (K_h(u) =
+ * K(u / h) / h per dimension): box 1/2, triangle 1 - |u|, Epanechnikov
+ * 3/4 (1 - u^2), biweight 15/16 (1 - u^2)^2, triweight 35/32 (1 - u^2)^3. */
+enum { FKR_REG_GAUSS = 0, FKR_REG_BOX = 1, FKR_REG_TRIANGLE = 2, FKR_REG_EPANECHNIKOV = 3,
+       FKR_REG_BIWEIGHT = 4, FKR_REG_TRIWEIGHT = 5 };
 
 #define FKR_MAX_D 3
 #define FKR_MAX_ORDER 2
@@ -112,6 +119,17 @@ typedef struct {
                                FFTs, the spectra and the channel grids; with
                                precision FKR_F32 and FKR_TP_F64 the spreading
                                runs in FP32 and everything after it in FP64 */
+    int reg_kernel;         /* FKR_REG_GAUSS (0, default) or a compact kernel:
+                               then the moments are the binned approximation of
+                               eq. (11)-(13), the kernel sampled at the grid
+                               offsets and its discrete transform applied to
+                               every mode of the period (no spectral cut), so
+                               they differ from the exact kernel sums by the
+                               kernel's aliasing, which shrinks with
+                               (delta / h)^(s+1) for a kernel with s
+                               continuous derivatives; fkr_fit_full,
+                               fkr_interval and fkr_gcv_grad need the Gaussian
+                               (FKR_E_UNSUPPORTED otherwise) */
 } fkr_plan_desc;
 
 /* Geometry chosen by the planner (read-only). */

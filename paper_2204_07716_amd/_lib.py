@@ -15,6 +15,7 @@ FKR_KERNEL_ES, FKR_KERNEL_GAUSS = 0, 1
 FKR_VAR_LOG, FKR_VAR_DIRECT = 0, 1
 FKR_TP_SAME, FKR_TP_F32, FKR_TP_F64 = 0, 1, 2
 FKR_SIG_SCALAR, FKR_SIG_GRID = 0, 1
+FKR_REG = {"gauss": 0, "box": 1, "triangle": 2, "epanechnikov": 3, "biweight": 4, "triweight": 5}
 FKR_MAX_H = 64
 FKR_RESOLVE = 1e-3
 FKR_STATIC_WORKSPACE_BYTES = 64 << 20
@@ -29,7 +30,7 @@ class PlanDesc(ctypes.Structure):
                 ("precision", ctypes.c_int), ("spread_kernel", ctypes.c_int),
                 ("sigma", ctypes.c_double), ("n_max", ctypes.c_int64),
                 ("max_weights", ctypes.c_int), ("max_h", ctypes.c_int),
-                ("transform_precision", ctypes.c_int)]
+                ("transform_precision", ctypes.c_int), ("reg_kernel", ctypes.c_int)]
 
 
 class Geometry(ctypes.Structure):

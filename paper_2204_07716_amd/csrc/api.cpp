@@ -271,6 +271,12 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     a.Btot = p->Btot;
     a.ill_clear = ill_clear;
     a.deriv_dim = deriv_dim;
+    if (p->reg_kernel && !full) {
+        if (deriv_dim >= 0) return FKR_E_UNSUPPORTED;
+        a.kdeg = 2 * p->order + 1;
+        a.ktab = at<double>(p, p->lay.ktab);
+        launch_ktab(a, p->delta, p->reg_kernel, at<double>(p, p->lay.ktab), s);
+    }
     // the first inverse pass expands its rows from the pair spectra itself
     StageTimer tf(p, FKR_STAGE_FFT_INV, s);
     void* chan_out = p->ws + p->lay.chan + (size_t)pair_off * p->Mtot * 2 * elem_size(p->tprec);
@@ -340,8 +346,11 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
 // 8e-6 with FP32 spreading, absolute errors below 3.1e-12 N K_h(0) with FP64
 // transforms and below 2e-7 N K_h(0) with FP32 transforms.)
 double abs_floor(const fkr_plan* p, const double* h) {
+    // the kernel's peak K_h(0) = prod_j K(0) / h_j
+    static const double k_peak[] = {0.0, 0.5, 1.0, 0.75, 0.9375, 1.09375};
+    const double kz = p->reg_kernel ? k_peak[p->reg_kernel] : 1.0 / std::sqrt(2.0 * M_PI);
     double k0 = 1.0;
-    for (int j = 0; j < p->d; ++j) k0 *= 1.0 / (h[j] * std::sqrt(2.0 * M_PI));
+    for (int j = 0; j < p->d; ++j) k0 *= kz / h[j];
     const double u32 = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
     const double ut = p->tprec == FKR_F64 ? u64 : u32;
     const double e = std::max(16.0 * ut, 1e-5 * p->eps);
@@ -802,6 +811,7 @@ fkr_status fkr_fit_full(fkr_plan* p, int nh, const double* H, int q, int y_compl
         return FKR_E_ARG;
     const int ny = q * (y_complex ? 2 : 1);
     if (1 + ny > p->max_weights) return FKR_E_ARG;
+    if (p->reg_kernel) return FKR_E_UNSUPPORTED;
     const int dd = p->d * p->d;
     std::vector<FullH> fh(nh);
     std::vector<double> heff(3 * nh, 0.0);
@@ -832,6 +842,7 @@ fkr_status fkr_moments_full(fkr_plan* p, int nh, const double* H, int nw, const 
     if (st != FKR_OK) return st;
     if (nh < 1 || nh > p->max_h || !H || nw < 0 || (nw > 0 && p->N > 0 && !W) || 1 + nw > p->max_weights) return FKR_E_ARG;
     if (nw > 0 && !valid_type(w_type)) return FKR_E_ARG;
+    if (p->reg_kernel) return FKR_E_UNSUPPORTED;
     const int dd = p->d * p->d;
     std::vector<FullH> fh(nh);
     std::vector<double> heff(3 * nh, 0.0);
@@ -958,6 +969,7 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
     if (st != FKR_OK) return st;
     if ((st = check_h(p, 1, h)) != FKR_OK) return st;
     if (!Sigma) return FKR_E_ARG;
+    if (p->reg_kernel) return FKR_E_UNSUPPORTED;   // uses K_h^2 = c K_{h / sqrt 2} of the Gaussian
     if (sig_kind == FKR_SIG_SCALAR) {
         if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return FKR_E_ARG;
     } else if (sig_kind != FKR_SIG_GRID || !sigma2_dev) {
@@ -1128,6 +1140,7 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
     fkr_status st = common_fit_checks(p, 1, h, 1, y_complex, Y, y_type);
     if (st != FKR_OK) return st;
     if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
+    if (p->reg_kernel) return FKR_E_UNSUPPORTED;   // derivative multipliers of the Gaussian
     const int ny = y_complex ? 2 : 1;
     const int nr = 1 + ny + Np;
     const int ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;

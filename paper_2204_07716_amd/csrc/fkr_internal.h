@@ -56,6 +56,7 @@ struct Layout {                      // byte offsets into the workspace
     size_t chan = 0, mhat = 0, partial = 0, wbuf = 0, red = 0, wsort = 0;
     size_t sup = 0;                  // [M] FP32 resolved flags (0 / NaN) of the last solve
     size_t r0 = 0;                   // [P][M] FP64 row 0 of the equilibrated inverse (variance of the fit)
+    size_t ktab = 0;                 // compact kernels: per dim [2 l + 1][B_j] FP64 moment multipliers
     size_t total = 0;
     // element capacities (for checks)
     int64_t cap_jobs = 0, cap_fft = 0, cap_spec = 0, cap_chan = 0, cap_mhat = 0;
@@ -83,6 +84,7 @@ struct fkr_plan {
     double hf[fkr::kMaxD] = {1, 1, 1}, inv_hf[fkr::kMaxD] = {1, 1, 1};
     double h_min[fkr::kMaxD] = {0, 0, 0}, h_max[fkr::kMaxD] = {0, 0, 0};
     double eps = 0, sigma = 2.0, U_spec = 0, U_space = 0;
+    int reg_kernel = 0;              // FKR_REG_*: 0 the Gaussian, else a compact kernel on |u| <= 1
     int w = 0;
     double kparam = 0;               // ES beta or Gaussian a
     int64_t n_tiles = 1, Psub = 1, Mtot = 1, Btot = 1, Mrtot = 1;

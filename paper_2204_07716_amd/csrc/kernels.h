@@ -54,6 +54,8 @@ struct ExpandArgs {
     double h[3], T[3];       // bandwidth and period per dimension
     unsigned long long* ill_clear;   // cleared by the launch when given
     int deriv_dim;           // >= 0: the multipliers' derivative in log h of this dimension
+    const double* ktab;      // compact kernels: per dim [kdeg][B_j] multipliers (else null: the Gaussian)
+    int kdeg;                // degrees in ktab (2 l + 1)
 };
 
 // Moment multipliers of the Gaussian with a full bandwidth matrix H: the
@@ -295,6 +297,7 @@ hipError_t static_scratch(void** ptr);
 // groups gstride elements apart (FP32 only).
 void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t gstride, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
+void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, double* ktab, hipStream_t s);
 void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const int* es, const int* pidx,
                         const void* spec, void* out, hipStream_t s);
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);

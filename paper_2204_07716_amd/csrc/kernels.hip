@@ -1525,6 +1525,13 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
 #pragma unroll
         for (int k = 1; k < kExpandDeg; ++k) he[k + 1] = u * he[k] - k * he[k - 1];
         const bool dj = j == a.deriv_dim;
+        if (a.ktab) {   // a compact kernel: the multipliers of its sampled moments
+            int64_t off = 0;
+            for (int i = 0; i < j; ++i) off += a.kdeg * a.B[i];
+#pragma unroll
+            for (int k = 0; k < kExpandDeg; ++k) mloc[j][k][tid] = k < a.kdeg ? a.ktab[off + k * a.B[j] + ej] : 0.0;
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < kExpandDeg; ++k) mloc[j][k][tid] = (dj ? -u * he[k + 1] : he[k]) * gj;
     }
@@ -1658,6 +1665,74 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, Fu
         o.y = (T)acc_im;
         out[(int64_t)c * a.Btot + n] = o;
     }
+}
+
+// Moment multipliers of a compact kernel sampled at the grid offsets (the
+// discrete convolution of eq. 12-13 in the frequency domain): per dimension
+// j, degree a and band index e, with w = 2 pi (e - K_j) / T_j,
+// Re(i^a D(w)) / T_j, D(w) = delta sum_m (m delta / h)^a K(m delta / h) / h
+// exp(-i w m delta) over the offsets inside the support (the same phase
+// convention as the Gaussian's He_a(u) exp(-u^2/2) / T_j).  With every mode
+// |n| <= L/2 kept, each sample contributes the trigonometric interpolant of
+// the sampled moment kernel, exact at the grid offsets.
+__device__ __forceinline__ double compact_kernel(int kind, double u) {
+    const double a = fabs(u);
+    if (a > 1.0) return 0.0;
+    const double q = 1.0 - u * u;
+    switch (kind) {
+        case FKR_REG_BOX: return 0.5;
+        case FKR_REG_TRIANGLE: return 1.0 - a;
+        case FKR_REG_EPANECHNIKOV: return 0.75 * q;
+        case FKR_REG_BIWEIGHT: return 0.9375 * q * q;
+        default: return 1.09375 * q * q * q;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1, double d2, int kind, double* tab) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t off = 0, rem = id;
+    int j = 0;
+    for (; j < a.d; ++j) {
+        const int64_t nj = (int64_t)a.kdeg * a.B[j];
+        if (rem < nj) break;
+        rem -= nj;
+        off += nj;
+    }
+    if (j >= a.d) return;
+    const int deg = (int)(rem / a.B[j]);
+    const int64_t e = rem - (int64_t)deg * a.B[j];
+    const double delta = j == 0 ? d0 : (j == 1 ? d1 : d2);
+    const double h = a.h[j];
+    const double w = 2.0 * M_PI * (double)(e - a.K[j]) / a.T[j];
+    const int64_t mmax = (int64_t)floor(h / delta);
+    double re = 0.0, im = 0.0;
+    for (int64_t m = -mmax; m <= mmax; ++m) {
+        const double u = (double)m * delta / h;
+        double v = compact_kernel(kind, u) / h * delta;
+        for (int k = 0; k < deg; ++k) v *= u;
+        double sn, cs;
+        sincos(w * (double)m * delta, &sn, &cs);
+        re += v * cs;
+        im -= v * sn;
+    }
+    // i^deg (re + i im), real part
+    double r;
+    switch (deg & 3) {
+        case 0: r = re; break;
+        case 1: r = -im; break;
+        case 2: r = -re; break;
+        default: r = im; break;
+    }
+    // even L: the modes +-L/2 alias to one Nyquist term, each carries half
+    const int64_t Lj = llround(a.T[j] / delta);
+    if (2 * llabs(e - a.K[j]) == Lj) r *= 0.5;
+    tab[off + rem] = r / a.T[j];
+}
+
+void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, double* ktab, hipStream_t s) {
+    int64_t n = 0;
+    for (int j = 0; j < a.d; ++j) n += (int64_t)a.kdeg * a.B[j];
+    k_ktab<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, delta[0], a.d > 1 ? delta[1] : 1.0, a.d > 2 ? delta[2] : 1.0, reg_kernel, ktab);
 }
 
 void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const int* es, const int* pidx,

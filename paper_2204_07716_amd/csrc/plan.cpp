@@ -244,6 +244,9 @@ static void layout(fkr_plan* p) {
     L.red = take((size_t)p->max_h * (2 * p->max_weights + 4) * 8);
     L.sup = take((size_t)p->Mtot * 4);
     L.r0 = take((size_t)p->Mtot * p->n_t * 8);
+    int64_t nb = 0;
+    for (int j = 0; j < p->d; ++j) nb += p->B[j];
+    L.ktab = take((size_t)(2 * p->order + 1) * nb * 8);
     L.total = off;
 }
 
@@ -255,6 +258,7 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
     if (D.transform_precision != 0 && D.transform_precision != FKR_TP_F32 &&
         D.transform_precision != FKR_TP_F64) return FKR_E_ARG;
     if (D.spread_kernel != FKR_KERNEL_ES && D.spread_kernel != FKR_KERNEL_GAUSS) return FKR_E_ARG;
+    if (D.reg_kernel < FKR_REG_GAUSS || D.reg_kernel > FKR_REG_TRIWEIGHT) return FKR_E_ARG;
     if (D.n_max < 0 || D.n_max > INT32_MAX - 1) return FKR_E_ARG;
     if (D.max_weights < 1 || D.max_weights > 1024) return FKR_E_ARG;
     if (D.max_h < 1 || D.max_h > FKR_MAX_H) return FKR_E_ARG;
@@ -266,6 +270,7 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
     p->tprec = D.transform_precision == FKR_TP_F64 ? FKR_F64
              : D.transform_precision == FKR_TP_F32 ? FKR_F32 : D.precision;
     p->kernel = D.spread_kernel;
+    p->reg_kernel = D.reg_kernel;
     p->eps = D.eps;
     // Default oversampling: 4 in 1-D and 2-D (narrower kernel, sparser fine
     // cells; the fine grid stays small), 2 in 3-D.
@@ -332,12 +337,17 @@ fkr_status build_plan(const fkr_plan_desc* desc, fkr_plan* p) {
         p->h_min[j] = D.h_min[j];
         p->h_max[j] = D.h_max[j];
         p->delta[j] = (D.hi[j] - D.lo[j]) / (double)(D.M[j] - 1);
-        const double reach = p->U_space * D.h_max[j] / p->delta[j];
+        // the zero padding holds the kernel's reach at h_max: the Gaussian's
+        // tail down to the tolerance, a compact kernel's support
+        const double reach = (p->reg_kernel ? 1.0 : p->U_space) * D.h_max[j] / p->delta[j] + (p->reg_kernel ? 1.0 : 0.0);
         if (reach > 4.0 * (1 << 20)) return FKR_E_ARG;
         p->L[j] = smooth_up((int64_t)std::ceil((double)(D.M[j] - 1) + reach) + 1);
         p->T[j] = (double)p->L[j] * p->delta[j];
         const double omega = p->U_spec / D.h_min[j];
-        int64_t K = (int64_t)std::ceil(omega * p->T[j] / (2.0 * M_PI));
+        // a compact kernel keeps every mode of the period (eq. 12-13: the
+        // discrete convolution with the sampled kernel); for even L the
+        // modes +-L/2 share the Nyquist term, each with half its weight
+        int64_t K = p->reg_kernel ? p->L[j] / 2 : (int64_t)std::ceil(omega * p->T[j] / (2.0 * M_PI));
         p->K[j] = K;
         p->B[j] = 2 * K + 1;
         int64_t mr = smooth_up((int64_t)std::ceil(p->sigma * (double)p->B[j]));

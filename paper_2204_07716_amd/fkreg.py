@@ -198,9 +198,10 @@ class Plan:
                  hi: Sequence[float], h_min: Sequence[float], h_max: Sequence[float],
                  eps: float, precision: str = "fp32", kernel: str = "es", sigma: float = 0.0,
                  n_max: int = 0, max_weights: int = 2, max_h: int = 1, device="cuda",
-                 transform_precision: str = "same"):
+                 transform_precision: str = "same", reg_kernel: str = "gauss"):
         self.lib = _lib.load()
         desc = _lib.PlanDesc()
+        desc.reg_kernel = _lib.FKR_REG[reg_kernel]
         desc.d, desc.order = d, order
         for j in range(d):
             desc.M[j] = int(M[j])

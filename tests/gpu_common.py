@@ -148,13 +148,13 @@ def nan_close(gpu, ref, bar, mask=None, scale=None) -> float:
 
 
 def make_plan(d, order, M, h_min, h_max, eps, precision, n_max, max_weights=2, max_h=1,
-              kernel="es", lo=None, hi=None, sigma=0.0, tprec="same"):
+              kernel="es", lo=None, hi=None, sigma=0.0, tprec="same", reg_kernel="gauss"):
     from paper_2204_07716_amd import Plan
     lo = lo or (0.0,) * d
     hi = hi or (1.0,) * d
     return Plan(d, order, M, lo, hi, h_min, h_max, eps, precision=precision, kernel=kernel,
                 sigma=sigma, n_max=n_max, max_weights=max_weights, max_h=max_h,
-                transform_precision=tprec)
+                transform_precision=tprec, reg_kernel=reg_kernel)
 
 
 def to_dev(a, dtype=torch.float64):
