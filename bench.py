@@ -93,6 +93,8 @@ def _args():
                     help="grid points per pass in the oracle's timed sample (0: 512 in 3-D, 2048 in 2-D)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch workload (256 independent regressions; 64-probe x 32-bandwidth DF sweep)")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the kernel and bandwidth generality timing (full H, compact kernels)")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the differentiated workload (GCV and its gradients, complex y, N=4e6)")
     ap.add_argument("--no-inference", action="store_true",
@@ -419,6 +421,8 @@ def main() -> int:
         line["batch"] = _batch_workload(min(args.steps, 5))
     if not args.no_grad:
         line["differentiated"] = _grad_workload(min(args.steps, 5))
+    if not args.no_kernels:
+        line["kernels"] = _kernel_generality(min(args.steps, 5))
 
     sample = None
     if not args.no_cpu_baseline or not args.no_fp64_single:
@@ -484,6 +488,62 @@ def _inference(w, Xd, Yd, transform, sigma, steps, n_query=1_000_000):
            "band_halfwidth_median": float(torch.median(iv["upper"][fin] - iv["lower"][fin]).item() / 2),
            "plan": "FP32 spreading, %s transforms, h_min = h / sqrt 2" % transform}
     del plan
+    return out
+
+
+def _kernel_generality(reps):
+    """Fits on the 2-D workload's samples (N = 1e6 mixture, M = 256^2, one
+    response, FP32 spreading, FP64 transforms) with the Gaussian at
+    h = (0.03, 0.05), with a full bandwidth matrix of those marginal widths
+    and correlation 0.5, and with the Epanechnikov kernel of half-widths
+    (0.07, 0.11) (about the Gaussian's variance; the binned approximation
+    keeps every mode of the period), each replayed as a HIP graph with the
+    points already sorted."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2204_07716_amd import Plan
+    w = workloads.make("ll2d")
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(w.X.astype(np.float32), device=dev)
+    Y = torch.as_tensor(w.Y.astype(np.float32), device=dev)
+    h = np.asarray(w.h[0])
+    H = np.array([[h[0] ** 2, 0.5 * h[0] * h[1]], [0.5 * h[0] * h[1], h[1] ** 2]])
+    reach = 1.0 / np.sqrt(np.diag(np.linalg.inv(H)))
+    he = np.array([0.07, 0.11])
+
+    def replay_ms(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out = {"N": w.N, "M": list(w.M)}
+    pg = Plan(2, 1, w.M, w.lo, w.hi, tuple(reach), tuple(h), w.eps, precision="fp32", n_max=w.N,
+              transform_precision="fp64")
+    pg.set_points(X)
+    out["gauss_fit_ms"] = round(replay_ms(lambda: pg.fit(h, Y)), 4)
+    out["full_h_fit_ms"] = round(replay_ms(lambda: pg.fit_full(H, Y)), 4)
+    out["band"] = list(pg.band)
+    del pg
+    pe = Plan(2, 1, w.M, w.lo, w.hi, tuple(he), tuple(he), w.eps, precision="fp32", n_max=w.N,
+              transform_precision="fp64", reg_kernel="epanechnikov")
+    pe.set_points(X)
+    out["epanechnikov_fit_ms"] = round(replay_ms(lambda: pe.fit(he, Y)), 4)
+    out["epanechnikov_band"] = list(pe.band)
+    del pe
     return out
 
 

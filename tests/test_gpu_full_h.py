@@ -87,3 +87,29 @@ def test_full_h_argument_checks():
               [[0.01, 0.009], [0.009, 0.01]]):     # spectrum along w_0 beyond the band (1/sqrt((H^-1)_00) < h_min)
         with pytest.raises(FkrError):
             plan.fit_full(np.array(H), Y)
+
+
+def test_ll2d_full_size_full_h(orc):
+    """The 2-D workload's samples at full size (N = 1e6 mixture, M = 256^2)
+    with a full H of marginal widths (0.03, 0.05) and correlation 0.5: the
+    density moment and the fit at seeded grid points against the oracle's
+    direct sums."""
+    import workloads
+    from gpu_common import density_mask, sample_flat
+    w = workloads.make("ll2d")
+    h = np.asarray(w.h[0])
+    H = np.array([[h[0] ** 2, 0.5 * h[0] * h[1]], [0.5 * h[0] * h[1], h[1] ** 2]])
+    hmin, hmax = _h_range(H)
+    plan = make_plan(2, 1, w.M, hmin, hmax, w.eps, "fp32", n_max=w.N, tprec="fp64")
+    plan.set_points(to_dev(w.X, torch.float32))
+    mh, s0 = plan.fit_full(H, to_dev(w.Y, torch.float32), want_s0=True)
+    mh, s0 = mh.cpu().numpy()[0, 0], s0.cpu().numpy()[0]
+    flat = sample_flat(np.random.default_rng(66), w.M, 24)
+    gp = orc.grid_points(w.M, w.lo, w.hi)[flat]
+    X = w.X.astype(np.float32).astype(np.float64)
+    y = w.Y[:, 0].astype(np.float32).astype(np.float64)
+    ref, S, ill = orc.fit_full(X, y, H, 1, gp)
+    assert rel_err(s0[flat], S[:, 0]) < 1e-5
+    err = rel_err(mh[flat], ref[:, 0], density_mask(S[:, 0]))
+    print(f"ll2d full H: s0 err {rel_err(s0[flat], S[:, 0]):.2e}, fit err {err:.2e}")
+    assert err < 1e-5
