@@ -71,7 +71,9 @@ def test_full_h_diagonal_equals_product_fit():
     b = plan.fit(h, Y).cpu().numpy()
     f = np.isfinite(b)
     assert np.array_equal(np.isnan(a), np.isnan(b))
-    assert np.abs(a[f] - b[f]).max() <= 1e-9 * np.abs(b[f]).max()
+    # two launches: the FP64 tile sums are added in a varying order before
+    # their FP32 store, so the last bit of a subgrid value may differ
+    assert np.abs(a[f] - b[f]).max() <= 1e-6 * np.abs(b[f]).max()
 
 
 def test_full_h_argument_checks():

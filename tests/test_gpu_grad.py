@@ -42,7 +42,7 @@ def test_gcv_grad_matches_finite_differences(d):
     g = out["dlogh"].cpu().numpy()
     dfit = out["dfit"].cpu().numpy()
     base = plan.cv(h, Y, Np, seed=seed)
-    assert out["gcv"].item() == pytest.approx(base["gcv"].item(), rel=1e-12)
+    assert out["gcv"].item() == pytest.approx(base["gcv"].item(), rel=1e-10)
     st = 1e-4
     for j in range(d):
         e = np.zeros(d)
@@ -143,8 +143,10 @@ def test_gcv_autograd_backward():
     gcv = GCVLogH.apply(log_h, Y, plan, Np, seed)
     gcv.backward()
     ref = plan.gcv_grad(h, Y.detach(), Np, seed)
-    assert gcv.item() == pytest.approx(ref["gcv"].item(), rel=1e-12)
-    np.testing.assert_allclose(log_h.grad.numpy(), ref["dlogh"].cpu().numpy(), rtol=1e-12)
+    # two calls with FP32 spreading: the subgrids' FP32 stores may differ in
+    # the last bit (their FP64 tile sums are added in a varying order)
+    assert gcv.item() == pytest.approx(ref["gcv"].item(), rel=1e-6)
+    np.testing.assert_allclose(log_h.grad.numpy(), ref["dlogh"].cpu().numpy(), rtol=1e-5)
     np.testing.assert_allclose(Y.grad.cpu().numpy()[:, 0], ref["dy"].cpu().numpy(), rtol=1e-6,
                                atol=1e-6 * ref["dy"].abs().max().item())
 
