@@ -1056,14 +1056,15 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     const int wstride = wgstride ? 4 : (nr + 3) & ~3;
     const double* yfit = at<double>(p, p->lay.mhat);
     const float* sup = at<float>(p, p->lay.sup);
-    // real and imaginary parts of a complex response separately: the smoother is real
+    // u for every part of the response in one pass; then the real and the
+    // imaginary part of a complex response separately (the smoother is real)
+    launch_fill_f64(scratch, (int64_t)ny * p->Mtot, 0.0, s);
+    launch_adj_scatter(g, p->N, p->prec, p->ws + p->lay.xs, p->ws + p->lay.wsort, wstride, wgstride, ny, yfit, sup,
+                       scratch, s);
     for (int part = 0; part < ny; ++part) {
-    launch_fill_f64(scratch, p->Mtot, 0.0, s);
-    launch_adj_scatter(g, p->N, p->prec, p->ws + p->lay.xs, p->ws + p->lay.wsort, wstride, wgstride, ny, part, yfit,
-                       sup, scratch, s);
     void* bufs[2] = {p->ws + p->lay.fftA, p->ws + p->lay.fftB};
     int cur = 0;
-    launch_adj_pack(p->tprec, P, p->Mtot, scratch, at<double>(p, p->lay.r0), bufs[cur], s);
+    launch_adj_pack(p->tprec, P, p->Mtot, scratch + (int64_t)part * p->Mtot, at<double>(p, p->lay.r0), bufs[cur], s);
     // grid (zero-padded to the period L) -> band, each pass moving its axis
     // to the end as the forward passes of the spread do: [band index][pair]
     int64_t done_B = 1;
@@ -1128,7 +1129,7 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
         launch_fft(p->tprec, true, f, bufs[cur], bufs[1 - cur], s);
         cur = 1 - cur;
     }
-    launch_adj_gather(g, p->tprec, p->kernel, p->N, Np, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
+    launch_adj_gather(g, p->prec, p->tprec, p->kernel, p->N, Np, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
                       bufs[cur], ny, part, yfit, sup, p->ws + p->lay.wsort, p->prec, wstride, wgstride,
                       at<double>(p, p->lay.red), dy, s);
     }
@@ -1142,6 +1143,7 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
     if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
     if (p->reg_kernel) return FKR_E_UNSUPPORTED;   // derivative multipliers of the Gaussian
     const int ny = y_complex ? 2 : 1;
+    if (ny + Np > kGradCols) return FKR_E_ARG;
     const int nr = 1 + ny + Np;
     const int ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;
     const int n_items = 1 + Np;          // base sums: the response (|r|^2), then the probes
@@ -1179,8 +1181,11 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
             StageTimer t(p, FKR_STAGE_SOLVE, s);
             launch_dsolve(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, p->ws + p->lay.chan + ncp * pair_bytes, s);
         }
+    }
+    {
+        // the sums of every dimension's columns in one pass over the samples
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        for (int c0 = 0; c0 < ncol; c0 += 8) {
+        for (int c0 = 0; c0 < nslot; c0 += 32) {
             GradSumArgs r{};
             r.N = p->N; r.x_type = p->prec; r.X = p->ws + p->lay.xs;
             r.wsorted = p->ws + p->lay.wsort; r.w_type = p->prec;
@@ -1188,11 +1193,11 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
             r.wstride = r.wgstride ? 4 : (nr + 3) & ~3;
             r.ny = ny;
             r.yfit = at<double>(p, p->lay.mhat);
-            r.dfit = a.out;
+            r.dfit = dfit;
             r.sup = sup;
-            r.ncol = std::min(8, ncol - c0);
+            r.ncol = ncol;
             r.col0 = c0;
-            r.slot0 = j * ncol + c0;
+            r.nall = std::min(32, nslot - c0);
             r.partial = partial;
             launch_grad_sums(g, r, s);
         }

@@ -11,6 +11,7 @@ constexpr int kMaxPairsPerSpread = 8;
 constexpr int kRedBlocks = 1024;      // fixed grid of the two-stage reductions
 constexpr int kRedYCols = 1;          // response columns per fused cv reduction launch
 constexpr int kRedProbes = 16;        // probes per fused cv reduction launch
+constexpr int kGradCols = 32;         // response parts + probes of one GCV gradient call
 constexpr int kSortChunk = 4096;      // samples per block in the binning kernels
 constexpr int kSortThreads = 1024;    // threads per binning block
 constexpr int kLdsHistMax = 16384;    // tiles counted in LDS (else global atomics)
@@ -94,10 +95,10 @@ struct GradSumArgs {
     int64_t wgstride;
     int ny;                        // response parts (1 real, 2 complex)
     const double* yfit;            // [M][ny] the base fit of y
-    const double* dfit;            // [ny + Np][M] derivative grids of this dimension
+    const double* dfit;            // [d][ny + Np][M] derivative grids
     const float* sup;              // [M]
-    int ncol, col0;                // columns of this launch (<= 8), first column
-    int slot0;                     // first partial slot
+    int ncol;                      // columns per dimension: ny + Np
+    int col0, nall;                // columns (over all dimensions) of this launch: col0 .. col0 + nall - 1 (nall <= 32)
     double* partial;               // [slot][kRedBlocks]
 };
 
@@ -279,12 +280,11 @@ void launch_grad_sums(const Geo& g, const GradSumArgs& a, hipStream_t s);
 void launch_finalize_grad(int d, int ny, int Np, const double* red, const double* gred, double* gcv, double* dlogh,
                           hipStream_t s);
 void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
-                        int64_t wgstride, int ny, int part, const double* yfit, const float* sup, double* u,
-                        hipStream_t s);
+                        int64_t wgstride, int ny, const double* yfit, const float* sup, double* u, hipStream_t s);
 void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s);
 void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
                         void* out, hipStream_t s);
-void launch_adj_gather(const Geo& g, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
+void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
                        const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,
                        const void* W, int w_type, int wstride, int64_t wgstride, const double* red, double* grad,
                        hipStream_t s);

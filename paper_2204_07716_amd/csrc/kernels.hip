@@ -2450,12 +2450,14 @@ __global__ void k_finalize_cv(int hidx, int Np, int q, const double* red, int n_
 }
 
 // Gradient sums over the supported samples (all 2^d corners of the cell
-// resolved), in sorted order: column 0 sum r d yhat with r = y - yhat,
-// columns 1 + p sum w_p d w_hat_p, for up to eight columns per launch.
+// resolved), in sorted order, for up to 32 columns of the derivative grids
+// (all dimensions in one pass: column c of dimension j is grid j ncol + c):
+// c < ny sums r_c d yhat_c with r = y - yhat, c = ny + p sums w_p d w_hat_p.
+// Wave sums by cross-lane reduction, block sums in LDS.
 template <int D, typename TW>
 __global__ __launch_bounds__(256) void k_grad_sums(Geo g, GradSumArgs a) {
-    constexpr int NA = 8;
-    __shared__ double sh[NA * 256];
+    constexpr int NA = 32;
+    __shared__ double sh[NA][4];
     double acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
@@ -2469,29 +2471,43 @@ __global__ __launch_bounds__(256) void k_grad_sums(Geo g, GradSumArgs a) {
 #pragma unroll
         for (int q = 0; q < (1 << D); ++q) ok &= a.sup[c.idx[q]] == 0.f;
         if (!ok) continue;
+        // residuals of the (at most two) response parts
+        double r0 = 0.0, r1 = 0.0;
+        {
+            double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+            for (int e = 0; e < (1 << D); ++e) {
+                y0 += c.w[e] * a.yfit[c.idx[e] * a.ny];
+                if (a.ny > 1) y1 += c.w[e] * a.yfit[c.idx[e] * a.ny + 1];
+            }
+            r0 = wcol(s, 1) - y0;
+            if (a.ny > 1) r1 = wcol(s, 2) - y1;
+        }
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
-            if (q >= a.ncol) break;
-            const int col = a.col0 + q;
-            const double* gd = a.dfit + (int64_t)col * g.Mtot;
+            if (q >= a.nall) break;
+            const int gc = a.col0 + q;
+            const int col = gc % a.ncol;
+            const double coef = col < a.ny ? (col == 0 ? r0 : r1) : wcol(s, 1 + col);
+            const double* gd = a.dfit + (int64_t)gc * g.Mtot;
             double dv = 0.0;
 #pragma unroll
             for (int e = 0; e < (1 << D); ++e) dv += c.w[e] * gd[c.idx[e]];
-            double coef;
-            if (col < a.ny) {
-                double yh = 0.0;
-#pragma unroll
-                for (int e = 0; e < (1 << D); ++e) yh += c.w[e] * a.yfit[c.idx[e] * a.ny + col];
-                coef = wcol(s, 1 + col) - yh;
-            } else {
-                coef = wcol(s, 1 + col);
-            }
             acc[q] += coef * dv;
         }
     }
-    block_sum<NA>(acc, sh);
-    if (threadIdx.x == 0)
-        for (int q = 0; q < a.ncol; ++q) a.partial[(int64_t)(a.slot0 + q) * kRedBlocks + blockIdx.x] = acc[q];
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) sh[q][wave] = acc[q];
+    __syncthreads();
+    if ((int)threadIdx.x < a.nall)
+        a.partial[(int64_t)(a.col0 + threadIdx.x) * kRedBlocks + blockIdx.x] =
+            sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
 }
 
 // d GCV / d log h_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar), dRSS = -2 sum
@@ -2533,25 +2549,92 @@ __global__ void k_finalize_grad(int d, int ny, int Np, const double* red, const 
 // the conjugate moment multipliers and the deconvolution, summed over b, back
 // to the fine grid (inverse FFT), then the spreading kernel at each sample.
 // ---------------------------------------------------------------------------
+template <int D>
+struct AdjWindow {   // grid cells per dimension of a workgroup's LDS accumulation window
+    static constexpr int E = D == 1 ? 1024 : (D == 2 ? 32 : 12);
+    static constexpr int SIZE = D == 1 ? E : (D == 2 ? E * E : E * E * E);
+};
+
+// u_c = P^T r_c for the ny parts of the residual, one sample per thread:
+// the workgroup's samples (consecutive in sorted order, so near each other)
+// add into an LDS window of grid cells anchored at their lowest cell, and
+// the window goes to the grid with one atomic add per touched cell; corners
+// outside the window are added to the grid directly.
 template <int D, typename TW>
 __global__ __launch_bounds__(256) void k_adj_scatter(Geo g, int64_t N, int x_type, const void* X, const TW* W,
-                                                     int wstride, int64_t wgstride, int ny, int part,
-                                                     const double* yfit, const float* sup, double* u) {
+                                                     int wstride, int64_t wgstride, int ny, const double* yfit,
+                                                     const float* sup, double* u) {
+    using AW = AdjWindow<D>;
+    __shared__ double win[2][AW::SIZE];
+    __shared__ int lo_s[3];
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    const Corners<D> c = corners<D>(g, x_type, X, s);
-    bool ok = true;
-    double yh = 0.0;
+    if (threadIdx.x < 3) lo_s[threadIdx.x] = INT32_MAX;
+    for (int q = threadIdx.x; q < 2 * AW::SIZE; q += blockDim.x) (&win[0][0])[q] = 0.0;
+    __syncthreads();
+    bool ok = s < N;
+    Corners<D> c{};
+    int cell[3] = {0, 0, 0};
+    double r[2] = {0.0, 0.0};
+    if (ok) {
+        c = corners<D>(g, x_type, X, s);
+        double yh[2] = {0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < (1 << D); ++q) {
-        ok &= sup[c.idx[q]] == 0.f;
-        yh += c.w[q] * yfit[c.idx[q] * ny + part];
+        for (int q = 0; q < (1 << D); ++q) {
+            ok &= sup[c.idx[q]] == 0.f;
+            for (int p = 0; p < ny; ++p) yh[p] += c.w[q] * yfit[c.idx[q] * ny + p];
+        }
+        for (int p = 0; p < ny; ++p)
+            r[p] = (double)(wgstride ? W[s * 4 + 1 + p] : W[s * wstride + 1 + p]) - yh[p];
+        int64_t rem = c.idx[0];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            cell[j] = (int)(rem % g.M[j]);
+            rem /= g.M[j];
+        }
+        if (ok)
+#pragma unroll
+            for (int j = 0; j < D; ++j) atomicMin(&lo_s[j], cell[j]);
     }
-    if (!ok) return;
-    const double y = (double)(wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part]);
-    const double r = y - yh;
+    __syncthreads();
+    if (ok) {
 #pragma unroll
-    for (int q = 0; q < (1 << D); ++q) atomicAdd(&u[c.idx[q]], c.w[q] * r);
+        for (int q = 0; q < (1 << D); ++q) {
+            int wi = 0, wstr = 1;
+            bool inside = true;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int rj = cell[j] + ((q >> j) & 1) - lo_s[j];
+                inside &= rj < AW::E;
+                wi += rj * wstr;
+                wstr *= AW::E;
+            }
+            for (int p = 0; p < ny; ++p) {
+                const double v = c.w[q] * r[p];
+                if (inside) atomicAdd(&win[p][wi], v);
+                else atomicAdd(&u[p * g.Mtot + c.idx[q]], v);
+            }
+        }
+    }
+    __syncthreads();
+    if (lo_s[0] == INT32_MAX) return;   // no supported sample in the workgroup
+    for (int q = threadIdx.x; q < AW::SIZE; q += blockDim.x) {
+        int rem = q;
+        int64_t gi = 0, gstr = 1;
+        bool valid = true;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int cj = lo_s[j] + rem % AW::E;
+            rem /= AW::E;
+            valid &= cj < g.M[j];
+            gi += (int64_t)cj * gstr;
+            gstr *= g.M[j];
+        }
+        if (!valid) continue;
+        for (int p = 0; p < ny; ++p) {
+            const double v = win[p][q];
+            if (v != 0.0) atomicAdd(&u[p * g.Mtot + gi], v);
+        }
+    }
 }
 
 // v_b = u c_b packed two per complex grid function, [ceil(P/2)][M]; zero
@@ -2636,7 +2719,7 @@ __global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, const 
 
 // (S^T r) at each sample from the fine grid f (the spreading kernel over the
 // sample's footprint, the real part), and the gradient in original order.
-template <int D, typename T, int KER>
+template <int D, typename T, int KER, typename KT>
 __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, int x_type, const void* X,
                                                     const int32_t* perm, const typename V2<T>::t* fgrid,
                                                     int ny, int part, const double* yfit, const float* sup,
@@ -2644,6 +2727,8 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, in
                                                     const double* red, double* grad) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
+    // kernel values in the spreading precision, as the spread evaluates them
+    // (the gather is the transpose of the spread)
     double kv[D][kMaxW];
     int c0[D];
     const int w = g.w;
@@ -2651,11 +2736,11 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, in
         const double x = load_as_double(X, x_type, s * D + j);
         const double uu = (x - g.lo[j]) * g.inv_hf[j];
         const double cf = floor(uu - 0.5 * w) + 1.0;
-        const double fr = uu - cf;
+        const KT fr = (KT)(uu - cf);
         int c = (int)cf;
         const int mr = (int)g.Mr[j];
         c0[j] = c < 0 ? c + mr : (c >= mr ? c - mr : c);
-        for (int k = 0; k < w; ++k) kv[j][k] = (double)kernel_value<double, KER>((double)k - fr, w, g.kparam);
+        for (int k = 0; k < w; ++k) kv[j][k] = (double)kernel_value<KT, KER>((KT)k - fr, w, (KT)g.kparam);
     }
     double acc = 0.0;
     if (D == 1) {
@@ -3812,12 +3897,11 @@ void launch_finalize_grad(int d, int ny, int Np, const double* red, const double
 }
 
 void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
-                        int64_t wgstride, int ny, int part, const double* yfit, const float* sup, double* u,
-                        hipStream_t s) {
+                        int64_t wgstride, int ny, const double* yfit, const float* sup, double* u, hipStream_t s) {
     if (N == 0) return;
     // sorted coordinates and staged weights are both in the spreading precision
 #define FKR_AS(D, TW) k_adj_scatter<D, TW><<<nblk(N), 256, 0, s>>>(g, N, prec, X, static_cast<const TW*>(W), \
-                                                                  wstride, wgstride, ny, part, yfit, sup, u)
+                                                                  wstride, wgstride, ny, yfit, sup, u)
     if (prec == FKR_F64) {
         if (g.d == 1) FKR_AS(1, double); else if (g.d == 2) FKR_AS(2, double); else FKR_AS(3, double);
     } else {
@@ -3841,19 +3925,21 @@ void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, con
                                                           static_cast<float2*>(out));
 }
 
-void launch_adj_gather(const Geo& g, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
+void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
                        const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,
                        const void* W, int w_type, int wstride, int64_t wgstride, const double* red, double* grad,
                        hipStream_t s) {
     if (N == 0) return;
-#define FKR_AG(D, T, K) k_adj_gather<D, T, K><<<nblk(N), 256, 0, s>>>(g, N, Np, x_type, X, perm, \
+#define FKR_AG3(D, T, K, KT) k_adj_gather<D, T, K, KT><<<nblk(N), 256, 0, s>>>(g, N, Np, x_type, X, perm, \
         static_cast<const typename V2<T>::t*>(fgrid), ny, part, yfit, sup, W, w_type, wstride, wgstride, red, grad)
+#define FKR_AG(D, T, K) do { if (prec == FKR_F64) FKR_AG3(D, T, K, double); else FKR_AG3(D, T, K, float); } while (0)
 #define FKR_AG_K(D, T) do { if (kernel == FKR_KERNEL_ES) FKR_AG(D, T, FKR_KERNEL_ES); else FKR_AG(D, T, FKR_KERNEL_GAUSS); } while (0)
 #define FKR_AG_D(T) do { if (g.d == 1) FKR_AG_K(1, T); else if (g.d == 2) FKR_AG_K(2, T); else FKR_AG_K(3, T); } while (0)
     if (tprec == FKR_F64) FKR_AG_D(double); else FKR_AG_D(float);
 #undef FKR_AG_D
 #undef FKR_AG_K
 #undef FKR_AG
+#undef FKR_AG3
 }
 
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
