@@ -1129,8 +1129,9 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
         launch_fft(p->tprec, true, f, bufs[cur], bufs[1 - cur], s);
         cur = 1 - cur;
     }
-    launch_adj_gather(g, p->prec, p->tprec, p->kernel, p->N, Np, p->prec, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
-                      bufs[cur], ny, part, yfit, sup, p->ws + p->lay.wsort, p->prec, wstride, wgstride,
+    launch_adj_gather(g, p->prec, p->tprec, p->kernel, Np, p->n_jobs_max, at<int32_t>(p, p->lay.jobs),
+                      at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
+                      bufs[cur], ny, part, yfit, sup, p->ws + p->lay.wsort, wstride, wgstride,
                       at<double>(p, p->lay.red), dy, s);
     }
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;

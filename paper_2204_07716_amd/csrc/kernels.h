@@ -284,10 +284,10 @@ void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const 
 void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s);
 void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
                         void* out, hipStream_t s);
-void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
+void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int Np, int64_t n_jobs_max,
+                       const int32_t* jobs, const uint32_t* loc, const void* frac, const void* X,
                        const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,
-                       const void* W, int w_type, int wstride, int64_t wgstride, const double* red, double* grad,
-                       hipStream_t s);
+                       const void* W, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s);
 // The library-held workspace of the current device (fkr_fit_noalloc):
 // kStaticScratchBytes, 256-byte aligned.
 constexpr size_t kStaticScratchBytes = FKR_STATIC_WORKSPACE_BYTES;

@@ -2719,85 +2719,107 @@ __global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, const 
 
 // (S^T r) at each sample from the fine grid f (the spreading kernel over the
 // sample's footprint, the real part), and the gradient in original order.
+// The transpose of the tiled spread: one workgroup per spreading job stages
+// the job's padded tile of f in LDS, then its samples (first cell relative
+// to the tile and fractions from the sort) read their footprints there; the
+// kernel values are those of the spread (its precision KT).
 template <int D, typename T, int KER, typename KT>
-__global__ __launch_bounds__(256) void k_adj_gather(Geo g, int64_t N, int Np, int x_type, const void* X,
+__global__ __launch_bounds__(256) void k_adj_gather(Geo g, int Np, const int32_t* jobs, const uint32_t* loc,
+                                                    const KT* frac, int x_type, const void* X,
                                                     const int32_t* perm, const typename V2<T>::t* fgrid,
                                                     int ny, int part, const double* yfit, const float* sup,
                                                     const void* Wv, int w_type, int wstride, int64_t wgstride,
                                                     const double* red, double* grad) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    // kernel values in the spreading precision, as the spread evaluates them
-    // (the gather is the transpose of the spread)
-    double kv[D][kMaxW];
-    int c0[D];
+    extern __shared__ double tl[];
+    const int pe0 = (int)g.pe[0], pe1 = D > 1 ? (int)g.pe[1] : 1, pe2 = D > 2 ? (int)g.pe[2] : 1;
+    const int ps = pe0 * pe1 * pe2;
     const int w = g.w;
-    for (int j = 0; j < D; ++j) {
-        const double x = load_as_double(X, x_type, s * D + j);
-        const double uu = (x - g.lo[j]) * g.inv_hf[j];
-        const double cf = floor(uu - 0.5 * w) + 1.0;
-        const KT fr = (KT)(uu - cf);
-        int c = (int)cf;
-        const int mr = (int)g.Mr[j];
-        c0[j] = c < 0 ? c + mr : (c >= mr ? c - mr : c);
-        for (int k = 0; k < w; ++k) kv[j][k] = (double)kernel_value<KT, KER>((KT)k - fr, w, (KT)g.kparam);
-    }
-    double acc = 0.0;
-    if (D == 1) {
-        for (int k0 = 0; k0 < w; ++k0) {
-            int m0 = c0[0] + k0; m0 -= m0 >= g.Mr[0] ? (int)g.Mr[0] : 0;
-            acc += kv[0][k0] * (double)fgrid[m0].x;
-        }
-    } else if (D == 2) {
-        for (int k1 = 0; k1 < w; ++k1) {
-            int m1 = c0[D > 1 ? 1 : 0] + k1; m1 -= m1 >= g.Mr[1] ? (int)g.Mr[1] : 0;
-            double a1 = 0.0;
-            for (int k0 = 0; k0 < w; ++k0) {
-                int m0 = c0[0] + k0; m0 -= m0 >= g.Mr[0] ? (int)g.Mr[0] : 0;
-                a1 += kv[0][k0] * (double)fgrid[(int64_t)m1 * g.Mr[0] + m0].x;
-            }
-            acc += kv[D > 1 ? 1 : 0][k1] * a1;
-        }
-    } else {
-        for (int k2 = 0; k2 < w; ++k2) {
-            int m2 = c0[D > 2 ? 2 : 0] + k2; m2 -= m2 >= g.Mr[2] ? (int)g.Mr[2] : 0;
-            double a2 = 0.0;
-            for (int k1 = 0; k1 < w; ++k1) {
-                int m1 = c0[D > 1 ? 1 : 0] + k1; m1 -= m1 >= g.Mr[1] ? (int)g.Mr[1] : 0;
-                double a1 = 0.0;
-                for (int k0 = 0; k0 < w; ++k0) {
-                    int m0 = c0[0] + k0; m0 -= m0 >= g.Mr[0] ? (int)g.Mr[0] : 0;
-                    a1 += kv[0][k0] * (double)fgrid[((int64_t)m2 * g.Mr[1] + m1) * g.Mr[0] + m0].x;
-                }
-                a2 += kv[D > 1 ? 1 : 0][k1] * a1;
-            }
-            acc += kv[D > 2 ? 2 : 0][k2] * a2;
-        }
-    }
-    // the sample's own residual when it is supported
-    const Corners<D> c = corners<D>(g, x_type, X, s);
-    bool ok = true;
-    double yh = 0.0;
-#pragma unroll
-    for (int q = 0; q < (1 << D); ++q) {
-        ok &= sup[c.idx[q]] == 0.f;
-        yh += c.w[q] * yfit[c.idx[q] * ny + part];
-    }
-    double y;
-    if (w_type == FKR_F64) {
-        const double* W = static_cast<const double*>(Wv);
-        y = wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part];
-    } else {
-        const float* W = static_cast<const float*>(Wv);
-        y = (double)(wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part]);
-    }
-    const double r = ok ? y - yh : 0.0;
+    const KT kp = (KT)g.kparam;
     const int n_items = 1 + Np;
     double mean = 0.0;
     for (int p = 0; p < Np; ++p) mean += (red[2 * (1 + p)] - red[2 * (1 + p) + 1]) / red[2 * (1 + p)];
     mean /= Np;
     const double scale = 2.0 / (red[2 * n_items] * mean * mean);
-    grad[(int64_t)perm[s] * ny + part] = scale * (r - acc);
+    const int njobs = jobs[0];
+    for (int b = blockIdx.x; b < njobs; b += gridDim.x) {
+        const int job = jobs[4 + 4 * b + 3];
+        int tile = jobs[4 + 4 * job];
+        const int s_beg = jobs[4 + 4 * job + 1], s_end = jobs[4 + 4 * job + 2];
+        int org[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int ntj = (int)g.nt[j];
+            org[j] = (tile % ntj) * (int)g.ts[j];
+            tile /= ntj;
+        }
+        for (int c = threadIdx.x; c < ps; c += blockDim.x) {
+            int rem = c;
+            int64_t fi = 0, fs = 1;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const int pj = j == 0 ? pe0 : (j == 1 ? pe1 : pe2);
+                const int m = (org[j] + rem % pj) % (int)g.Mr[j];   // periodic fine grid
+                rem /= pj;
+                fi += (int64_t)m * fs;
+                fs *= g.Mr[j];
+            }
+            tl[c] = (double)fgrid[fi].x;
+        }
+        __syncthreads();
+        for (int64_t s = s_beg + threadIdx.x; s < s_end; s += blockDim.x) {
+            const uint32_t l = loc[s];
+            int bc[3] = {0, 0, 0};
+            double kv[D][kMaxW];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                bc[j] = (int)((l >> (10 * j)) & 1023);
+                const KT fr = frac[s * D + j];
+                for (int k = 0; k < w; ++k) kv[j][k] = (double)kernel_value<KT, KER>((KT)k - fr, w, kp);
+            }
+            double acc = 0.0;
+            if (D == 1) {
+                for (int k0 = 0; k0 < w; ++k0) acc += kv[0][k0] * tl[bc[0] + k0];
+            } else if (D == 2) {
+                for (int k1 = 0; k1 < w; ++k1) {
+                    const double* row = tl + (bc[D > 1 ? 1 : 0] + k1) * pe0 + bc[0];
+                    double a1 = 0.0;
+                    for (int k0 = 0; k0 < w; ++k0) a1 += kv[0][k0] * row[k0];
+                    acc += kv[D > 1 ? 1 : 0][k1] * a1;
+                }
+            } else {
+                for (int k2 = 0; k2 < w; ++k2) {
+                    double a2 = 0.0;
+                    for (int k1 = 0; k1 < w; ++k1) {
+                        const double* row = tl + ((bc[D > 2 ? 2 : 0] + k2) * pe1 + bc[D > 1 ? 1 : 0] + k1) * pe0 + bc[0];
+                        double a1 = 0.0;
+                        for (int k0 = 0; k0 < w; ++k0) a1 += kv[0][k0] * row[k0];
+                        a2 += kv[D > 1 ? 1 : 0][k1] * a1;
+                    }
+                    acc += kv[D > 2 ? 2 : 0][k2] * a2;
+                }
+            }
+            // the sample's own residual when it is supported
+            const Corners<D> c = corners<D>(g, x_type, X, s);
+            bool ok = true;
+            double yh = 0.0;
+#pragma unroll
+            for (int q = 0; q < (1 << D); ++q) {
+                ok &= sup[c.idx[q]] == 0.f;
+                yh += c.w[q] * yfit[c.idx[q] * ny + part];
+            }
+            double y;
+            if (w_type == FKR_F64) {
+                const double* W = static_cast<const double*>(Wv);
+                y = wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part];
+            } else {
+                const float* W = static_cast<const float*>(Wv);
+                y = (double)(wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part]);
+            }
+            const double r = ok ? y - yh : 0.0;
+            grad[(int64_t)perm[s] * ny + part] = scale * (r - acc);
+        }
+        __syncthreads();
+    }
 }
 
 // Residuals of the mean fit for the variance pass (Sec. 3), in sorted sample
@@ -3925,13 +3947,17 @@ void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, con
                                                           static_cast<float2*>(out));
 }
 
-void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int64_t N, int Np, int x_type, const void* X,
+void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int Np, int64_t n_jobs_max,
+                       const int32_t* jobs, const uint32_t* loc, const void* frac, const void* X,
                        const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,
-                       const void* W, int w_type, int wstride, int64_t wgstride, const double* red, double* grad,
-                       hipStream_t s) {
-    if (N == 0) return;
-#define FKR_AG3(D, T, K, KT) k_adj_gather<D, T, K, KT><<<nblk(N), 256, 0, s>>>(g, N, Np, x_type, X, perm, \
-        static_cast<const typename V2<T>::t*>(fgrid), ny, part, yfit, sup, W, w_type, wstride, wgstride, red, grad)
+                       const void* W, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s) {
+    int64_t ps = 1;
+    for (int j = 0; j < g.d; ++j) ps *= g.pe[j];
+    const size_t lds = (size_t)ps * 8;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_jobs_max, 4096));
+#define FKR_AG3(D, T, K, KT) k_adj_gather<D, T, K, KT><<<nb, 256, lds, s>>>(g, Np, jobs, loc, \
+        static_cast<const KT*>(frac), prec, X, perm, static_cast<const typename V2<T>::t*>(fgrid), ny, part, yfit, \
+        sup, W, prec, wstride, wgstride, red, grad)
 #define FKR_AG(D, T, K) do { if (prec == FKR_F64) FKR_AG3(D, T, K, double); else FKR_AG3(D, T, K, float); } while (0)
 #define FKR_AG_K(D, T) do { if (kernel == FKR_KERNEL_ES) FKR_AG(D, T, FKR_KERNEL_ES); else FKR_AG(D, T, FKR_KERNEL_GAUSS); } while (0)
 #define FKR_AG_D(T) do { if (g.d == 1) FKR_AG_K(1, T); else if (g.d == 2) FKR_AG_K(2, T); else FKR_AG_K(3, T); } while (0)
