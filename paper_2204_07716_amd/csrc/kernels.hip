@@ -3574,6 +3574,9 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
                     // window is block aligned)
 #pragma unroll
                     for (int tb = 0; tb < NB; ++tb) {
+                        // a block-aligned window (zb = 0, uniform over the
+                        // wave) leaves the last block zero: its MFMAs are skipped
+                        if (tb == NB - 1 && zb == 0) break;
                         const float bv = pz[ZPB * tb] * wc;
 #pragma unroll
                         for (int rb = 0; rb < 4; ++rb)
