@@ -587,13 +587,25 @@ def _grad_workload(reps):
 
     t_fwd, f = replay_ms(lambda: plan.cv(h, Y, Np, seed=seed, want_mhat=False))
     t_both, r = replay_ms(lambda: plan.gcv_grad(h, Y, Np, seed))
+    del plan
+    # the plain FP64 form: one fit of the same response (spreading,
+    # transforms and solves in FP64 at eps = 1e-9), points sorted outside
+    p64 = Plan(2, 2, w.M, w.lo, w.hi, tuple(h), tuple(h), 1e-9, precision="fp64", n_max=w.N, max_weights=3,
+               max_h=1)
+    p64.set_points(torch.as_tensor(w.X, device=dev))
+    Y64 = torch.as_tensor(w.Y[:, 0], device=dev)
+    t_64, _ = replay_ms(lambda: p64.fit(h, Y64))
+    del p64
     out = {"N": w.N, "M": list(w.M), "order": 2, "probes": Np, "ms_forward": round(t_fwd, 3),
            "ms_forward_backward": round(t_both, 3), "backward_over_forward": round(t_both / t_fwd - 1, 3),
            "samples_per_s": round(w.N / (t_both * 1e-3), 1), "gcv": float(r["gcv"].item()),
+           "fp64_single_fit_ms": round(t_64, 3),
+           "forward_over_fp64_single": round(t_64 / t_fwd, 3),
+           "forward_backward_over_fp64_single": round(t_64 / t_both, 3),
            "gcv_forward_only": float(f["gcv"][0, 0].item()),
            "dlogh": [float(v) for v in r["dlogh"].cpu().numpy()],
-           "note": "points sorted outside the timed graphs; forward = fkr_cv, forward + backward = fkr_gcv_grad"}
-    del plan
+           "note": "points sorted outside the timed graphs; forward = fkr_cv (fit, DF from 10 probes, GCV), "
+                   "forward + backward = fkr_gcv_grad; fp64_single = one FP64 fit of y alone"}
     return out
 
 
