@@ -1047,7 +1047,11 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
                   hipStream_t s) {
     const Geo g = make_geo(p);
     const int P = p->n_t;
-    const int npv = (P + 1) / 2;
+    // a complex response runs as one complex function per b (real part:
+    // the real residuals, imaginary part: the imaginary ones); a real one
+    // packs two b per complex array
+    const int cplx = ny == 2 ? 1 : 0;
+    const int npv = cplx ? P : (P + 1) / 2;
     SolveArgs a = solve_args(p, 1, 0, 0, h);
     a.r0_out = at<double>(p, p->lay.r0);
     a.ill_count = nullptr;   // counted by the base solve
@@ -1056,15 +1060,14 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     const int wstride = wgstride ? 4 : (nr + 3) & ~3;
     const double* yfit = at<double>(p, p->lay.mhat);
     const float* sup = at<float>(p, p->lay.sup);
-    // u for every part of the response in one pass; then the real and the
-    // imaginary part of a complex response separately (the smoother is real)
+    // u for every part of the response in one pass
     launch_fill_f64(scratch, (int64_t)ny * p->Mtot, 0.0, s);
     launch_adj_scatter(g, p->N, p->prec, p->ws + p->lay.xs, p->ws + p->lay.wsort, wstride, wgstride, ny, yfit, sup,
                        scratch, s);
-    for (int part = 0; part < ny; ++part) {
+    {
     void* bufs[2] = {p->ws + p->lay.fftA, p->ws + p->lay.fftB};
     int cur = 0;
-    launch_adj_pack(p->tprec, P, p->Mtot, scratch + (int64_t)part * p->Mtot, at<double>(p, p->lay.r0), bufs[cur], s);
+    launch_adj_pack(p->tprec, P, p->Mtot, scratch, at<double>(p, p->lay.r0), cplx, bufs[cur], s);
     // grid (zero-padded to the period L) -> band, each pass moving its axis
     // to the end as the forward passes of the spread do: [band index][pair]
     int64_t done_B = 1;
@@ -1101,7 +1104,7 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     for (int j = 0; j < p->d; ++j) { ea.h[j] = h[j]; ea.T[j] = p->T[j]; }
     ea.Btot = p->Btot;
     ea.deriv_dim = -1;
-    launch_adj_combine(p->tprec, ea, P, dev_et(p), at<double>(p, p->lay.deconv), bufs[cur], bufs[1 - cur], s);
+    launch_adj_combine(p->tprec, ea, P, cplx, dev_et(p), at<double>(p, p->lay.deconv), bufs[cur], bufs[1 - cur], s);
     cur = 1 - cur;
     // band -> fine grid along dimensions d-1 .. 0 (the inverse passes of the
     // channels with the fine grid's length and no crop)
@@ -1131,7 +1134,7 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     }
     launch_adj_gather(g, p->prec, p->tprec, p->kernel, Np, p->n_jobs_max, at<int32_t>(p, p->lay.jobs),
                       at<uint32_t>(p, p->lay.loc), p->ws + p->lay.frac, p->ws + p->lay.xs, at<int32_t>(p, p->lay.perm),
-                      bufs[cur], ny, part, yfit, sup, p->ws + p->lay.wsort, wstride, wgstride,
+                      bufs[cur], ny, cplx ? -1 : 0, yfit, sup, p->ws + p->lay.wsort, wstride, wgstride,
                       at<double>(p, p->lay.red), dy, s);
     }
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;

@@ -281,9 +281,10 @@ void launch_finalize_grad(int d, int ny, int Np, const double* red, const double
                           hipStream_t s);
 void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const void* W, int wstride,
                         int64_t wgstride, int ny, const double* yfit, const float* sup, double* u, hipStream_t s);
-void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s);
-void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
-                        void* out, hipStream_t s);
+void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, int cplx, void* out,
+                     hipStream_t s);
+void launch_adj_combine(int prec, const ExpandArgs& a, int P, int cplx, const int* et, const double* fac,
+                        const void* spec, void* out, hipStream_t s);
 void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int Np, int64_t n_jobs_max,
                        const int32_t* jobs, const uint32_t* loc, const void* frac, const void* X,
                        const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,

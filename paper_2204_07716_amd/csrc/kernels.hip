@@ -2637,13 +2637,27 @@ __global__ __launch_bounds__(256) void k_adj_scatter(Geo g, int64_t N, int x_typ
     }
 }
 
-// v_b = u c_b packed two per complex grid function, [ceil(P/2)][M]; zero
-// where no supported sample reaches the grid point (c may be NaN there).
+// v_b = u c_b packed two per complex grid function, [ceil(P/2)][M]; for
+// the two parts of a complex response (cplx) one complex function per b,
+// v_b = (u_re + i u_im) c_b, [P][M].  Zero where no supported sample reaches
+// the grid point (c may be NaN there).
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_pack(int P, int64_t Mtot, const double* u, const double* c,
+__global__ __launch_bounds__(256) void k_adj_pack(int P, int64_t Mtot, const double* u, const double* c, int cplx,
                                                   typename V2<T>::t* out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= Mtot) return;
+    if (cplx) {
+        const double ur = u[k], ui = u[Mtot + k];
+        const bool zero = ur == 0.0 && ui == 0.0;
+        for (int b = 0; b < P; ++b) {
+            const double cb = zero ? 0.0 : c[b * Mtot + k];
+            typename V2<T>::t v;
+            v.x = (T)(ur * cb);
+            v.y = (T)(ui * cb);
+            out[b * Mtot + k] = v;
+        }
+        return;
+    }
     const double uk = u[k];
     for (int q = 0; q < (P + 1) / 2; ++q) {
         const int b0 = 2 * q, b1 = 2 * q + 1;
@@ -2658,11 +2672,11 @@ __global__ __launch_bounds__(256) void k_adj_pack(int P, int64_t Mtot, const dou
 // prod_j He_{b_j}(u_j) exp(-u_j^2/2) / T_j V_b(n), V_b unpacked from the pair
 // spectra Z_q = V_{2q} + i V_{2q+1} ([band index][pairs]).
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, const int* et, const double* fac,
+__global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, int cplx, const int* et, const double* fac,
                                                      const typename V2<T>::t* spec, typename V2<T>::t* out) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= a.Btot) return;
-    const int npv = (P + 1) / 2;
+    const int npv = cplx ? P : (P + 1) / 2;
     double mloc[3][kExpandDeg];
     unsigned nn = 0, rem = (unsigned)n, stride = 1;
     double dec = 1.0;
@@ -2690,11 +2704,17 @@ __global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, const 
     }
     double gr = 0.0, gi = 0.0;
     for (int b = 0; b < P; ++b) {
-        const typename V2<T>::t zn = spec[n * npv + (b >> 1)];
-        const typename V2<T>::t zm = spec[(int64_t)nn * npv + (b >> 1)];
         double vr, vi;
-        if ((b & 1) == 0) { vr = 0.5 * ((double)zn.x + (double)zm.x); vi = 0.5 * ((double)zn.y - (double)zm.y); }
-        else { vr = 0.5 * ((double)zn.y + (double)zm.y); vi = -0.5 * ((double)zn.x - (double)zm.x); }
+        if (cplx) {   // the complex function of b itself (the map is linear over the complex numbers)
+            const typename V2<T>::t zb = spec[n * npv + b];
+            vr = (double)zb.x;
+            vi = (double)zb.y;
+        } else {
+            const typename V2<T>::t zn = spec[n * npv + (b >> 1)];
+            const typename V2<T>::t zm = spec[(int64_t)nn * npv + (b >> 1)];
+            if ((b & 1) == 0) { vr = 0.5 * ((double)zn.x + (double)zm.x); vi = 0.5 * ((double)zn.y - (double)zm.y); }
+            else { vr = 0.5 * ((double)zn.y + (double)zm.y); vi = -0.5 * ((double)zn.x - (double)zm.x); }
+        }
         double m = 1.0;
         int deg = 0;
         for (int j = 0; j < a.d; ++j) {
@@ -2730,6 +2750,8 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int Np, const int32_t
                                                     int ny, int part, const double* yfit, const float* sup,
                                                     const void* Wv, int w_type, int wstride, int64_t wgstride,
                                                     const double* red, double* grad) {
+    // part < 0: both parts of a complex response, from the real and the
+    // imaginary part of f (tile [2][PE^D] in LDS)
     extern __shared__ double tl[];
     const int pe0 = (int)g.pe[0], pe1 = D > 1 ? (int)g.pe[1] : 1, pe2 = D > 2 ? (int)g.pe[2] : 1;
     const int ps = pe0 * pe1 * pe2;
@@ -2763,7 +2785,9 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int Np, const int32_t
                 fi += (int64_t)m * fs;
                 fs *= g.Mr[j];
             }
-            tl[c] = (double)fgrid[fi].x;
+            const typename V2<T>::t fv = fgrid[fi];
+            tl[c] = (double)fv.x;
+            if (part < 0) tl[ps + c] = (double)fv.y;
         }
         __syncthreads();
         for (int64_t s = s_beg + threadIdx.x; s < s_end; s += blockDim.x) {
@@ -2776,47 +2800,60 @@ __global__ __launch_bounds__(256) void k_adj_gather(Geo g, int Np, const int32_t
                 const KT fr = frac[s * D + j];
                 for (int k = 0; k < w; ++k) kv[j][k] = (double)kernel_value<KT, KER>((KT)k - fr, w, kp);
             }
-            double acc = 0.0;
-            if (D == 1) {
-                for (int k0 = 0; k0 < w; ++k0) acc += kv[0][k0] * tl[bc[0] + k0];
-            } else if (D == 2) {
-                for (int k1 = 0; k1 < w; ++k1) {
-                    const double* row = tl + (bc[D > 1 ? 1 : 0] + k1) * pe0 + bc[0];
-                    double a1 = 0.0;
-                    for (int k0 = 0; k0 < w; ++k0) a1 += kv[0][k0] * row[k0];
-                    acc += kv[D > 1 ? 1 : 0][k1] * a1;
-                }
-            } else {
-                for (int k2 = 0; k2 < w; ++k2) {
-                    double a2 = 0.0;
+            const int nparts = part < 0 ? 2 : 1;
+            double accp[2] = {0.0, 0.0};
+            for (int pp = 0; pp < nparts; ++pp) {
+                const double* tp = tl + pp * ps;
+                double acc = 0.0;
+                if (D == 1) {
+                    for (int k0 = 0; k0 < w; ++k0) acc += kv[0][k0] * tp[bc[0] + k0];
+                } else if (D == 2) {
                     for (int k1 = 0; k1 < w; ++k1) {
-                        const double* row = tl + ((bc[D > 2 ? 2 : 0] + k2) * pe1 + bc[D > 1 ? 1 : 0] + k1) * pe0 + bc[0];
+                        const double* row = tp + (bc[D > 1 ? 1 : 0] + k1) * pe0 + bc[0];
                         double a1 = 0.0;
                         for (int k0 = 0; k0 < w; ++k0) a1 += kv[0][k0] * row[k0];
-                        a2 += kv[D > 1 ? 1 : 0][k1] * a1;
+                        acc += kv[D > 1 ? 1 : 0][k1] * a1;
                     }
-                    acc += kv[D > 2 ? 2 : 0][k2] * a2;
+                } else {
+                    for (int k2 = 0; k2 < w; ++k2) {
+                        double a2 = 0.0;
+                        for (int k1 = 0; k1 < w; ++k1) {
+                            const double* row =
+                                tp + ((bc[D > 2 ? 2 : 0] + k2) * pe1 + bc[D > 1 ? 1 : 0] + k1) * pe0 + bc[0];
+                            double a1 = 0.0;
+                            for (int k0 = 0; k0 < w; ++k0) a1 += kv[0][k0] * row[k0];
+                            a2 += kv[D > 1 ? 1 : 0][k1] * a1;
+                        }
+                        acc += kv[D > 2 ? 2 : 0][k2] * a2;
+                    }
                 }
+                accp[pp] = acc;
             }
             // the sample's own residual when it is supported
             const Corners<D> c = corners<D>(g, x_type, X, s);
             bool ok = true;
-            double yh = 0.0;
 #pragma unroll
-            for (int q = 0; q < (1 << D); ++q) {
-                ok &= sup[c.idx[q]] == 0.f;
-                yh += c.w[q] * yfit[c.idx[q] * ny + part];
+            for (int q = 0; q < (1 << D); ++q) ok &= sup[c.idx[q]] == 0.f;
+            for (int pp = 0; pp < nparts; ++pp) {
+                const int pt = part < 0 ? pp : part;
+                double yh = 0.0;
+#pragma unroll
+                for (int q = 0; q < (1 << D); ++q) yh += c.w[q] * yfit[c.idx[q] * ny + pt];
+                double y;
+                if (w_type == FKR_F64) {
+                    const double* W = static_cast<const double*>(Wv);
+                    y = wgstride ? W[s * 4 + 1 + pt] : W[s * wstride + 1 + pt];
+                } else {
+                    const float* W = static_cast<const float*>(Wv);
+                    y = (double)(wgstride ? W[s * 4 + 1 + pt] : W[s * wstride + 1 + pt]);
+                }
+                const double r = ok ? y - yh : 0.0;
+                accp[pp] = scale * (r - accp[pp]);
             }
-            double y;
-            if (w_type == FKR_F64) {
-                const double* W = static_cast<const double*>(Wv);
-                y = wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part];
-            } else {
-                const float* W = static_cast<const float*>(Wv);
-                y = (double)(wgstride ? W[s * 4 + 1 + part] : W[s * wstride + 1 + part]);
-            }
-            const double r = ok ? y - yh : 0.0;
-            grad[(int64_t)perm[s] * ny + part] = scale * (r - acc);
+            if (part < 0)
+                reinterpret_cast<double2*>(grad)[perm[s]] = make_double2(accp[0], accp[1]);
+            else
+                grad[(int64_t)perm[s] * ny + part] = accp[0];
         }
         __syncthreads();
     }
@@ -3935,18 +3972,19 @@ void launch_adj_scatter(const Geo& g, int64_t N, int prec, const void* X, const 
 #undef FKR_AS
 }
 
-void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, void* out, hipStream_t s) {
-    if (prec == FKR_F64) k_adj_pack<double><<<nblk(Mtot), 256, 0, s>>>(P, Mtot, u, c, static_cast<double2*>(out));
-    else k_adj_pack<float><<<nblk(Mtot), 256, 0, s>>>(P, Mtot, u, c, static_cast<float2*>(out));
+void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const double* c, int cplx, void* out,
+                     hipStream_t s) {
+    if (prec == FKR_F64) k_adj_pack<double><<<nblk(Mtot), 256, 0, s>>>(P, Mtot, u, c, cplx, static_cast<double2*>(out));
+    else k_adj_pack<float><<<nblk(Mtot), 256, 0, s>>>(P, Mtot, u, c, cplx, static_cast<float2*>(out));
 }
 
-void launch_adj_combine(int prec, const ExpandArgs& a, int P, const int* et, const double* fac, const void* spec,
-                        void* out, hipStream_t s) {
+void launch_adj_combine(int prec, const ExpandArgs& a, int P, int cplx, const int* et, const double* fac,
+                        const void* spec, void* out, hipStream_t s) {
     if (prec == FKR_F64)
-        k_adj_combine<double><<<nblk(a.Btot), 256, 0, s>>>(a, P, et, fac, static_cast<const double2*>(spec),
+        k_adj_combine<double><<<nblk(a.Btot), 256, 0, s>>>(a, P, cplx, et, fac, static_cast<const double2*>(spec),
                                                            static_cast<double2*>(out));
     else
-        k_adj_combine<float><<<nblk(a.Btot), 256, 0, s>>>(a, P, et, fac, static_cast<const float2*>(spec),
+        k_adj_combine<float><<<nblk(a.Btot), 256, 0, s>>>(a, P, cplx, et, fac, static_cast<const float2*>(spec),
                                                           static_cast<float2*>(out));
 }
 
@@ -3956,11 +3994,13 @@ void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int Np, in
                        const void* W, int wstride, int64_t wgstride, const double* red, double* grad, hipStream_t s) {
     int64_t ps = 1;
     for (int j = 0; j < g.d; ++j) ps *= g.pe[j];
-    const size_t lds = (size_t)ps * 8;
+    const size_t lds = (size_t)ps * 8 * (part < 0 ? 2 : 1);
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_jobs_max, 4096));
-#define FKR_AG3(D, T, K, KT) k_adj_gather<D, T, K, KT><<<nb, 256, lds, s>>>(g, Np, jobs, loc, \
+#define FKR_AG3(D, T, K, KT) do { if (lds > 65536) (void)hipFuncSetAttribute( \
+        reinterpret_cast<const void*>(&k_adj_gather<D, T, K, KT>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        k_adj_gather<D, T, K, KT><<<nb, 256, lds, s>>>(g, Np, jobs, loc, \
         static_cast<const KT*>(frac), prec, X, perm, static_cast<const typename V2<T>::t*>(fgrid), ny, part, yfit, \
-        sup, W, prec, wstride, wgstride, red, grad)
+        sup, W, prec, wstride, wgstride, red, grad); } while (0)
 #define FKR_AG(D, T, K) do { if (prec == FKR_F64) FKR_AG3(D, T, K, double); else FKR_AG3(D, T, K, float); } while (0)
 #define FKR_AG_K(D, T) do { if (kernel == FKR_KERNEL_ES) FKR_AG(D, T, FKR_KERNEL_ES); else FKR_AG(D, T, FKR_KERNEL_GAUSS); } while (0)
 #define FKR_AG_D(T) do { if (g.d == 1) FKR_AG_K(1, T); else if (g.d == 2) FKR_AG_K(2, T); else FKR_AG_K(3, T); } while (0)
