@@ -154,7 +154,8 @@ std::vector<WSrc> stage_weights(fkr_plan* p, const std::vector<WSrc>& srcs, hipS
 
 // Spread + fold + forward FFT of every weight pair -> spec [band][npairs].
 // With staged = true the sources already are columns of the staged rows.
-fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_t s, bool staged) {
+fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_t s, bool staged,
+                       const long long* keep_first = nullptr) {
     const std::vector<WSrc> srcs = staged ? srcs_in : stage_weights(p, srcs_in, s);   // padded to a multiple of 4
     const Geo g = make_geo(p);
     const int nr = (int)srcs_in.size();
@@ -165,6 +166,7 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
         const int gp = std::min(p->pairs_per_spread, npairs - p0);
         SpreadSrc src{};
         src.npairs = gp;
+        src.keep_first = p0 == 0 ? keep_first : nullptr;
         for (int q = 0; q < gp; ++q) {
             const int r0 = 2 * (p0 + q), r1 = r0 + 1;
             src.w[2 * q] = srcs[r0];
@@ -936,11 +938,13 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
         srcs[r].kind = W_SORTED; srcs[r].type = p->prec; srcs[r].ptr = p->ws + p->lay.wsort;
         srcs[r].stride = resid_row_stride(g, p->prec); srcs[r].col = r;
     }
-    if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
     // The density moments s_alpha depend on the points and h only: when the
     // channel buffer still holds them for these points at this h and the
     // residual pass left no sample out, the passes skip their pairs (decided
-    // on the device).
+    // on the device), and the spread skips the density column.
+    const bool keep = p->n_s % 2 == 0;
+    if (keep) launch_chan_reuse(diag_ptr(p), h, p->d, s);
+    if ((st = run_spectra(p, srcs, s, true, keep ? diag_ptr(p) + kDiagReuse : nullptr)) != FKR_OK) return st;
     if ((st = run_channels(p, h, 2, ill_ctr(p), s, true)) != FKR_OK) return st;
     SolveArgs a = solve_args(p, 2, 1, 0, h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));

@@ -46,6 +46,10 @@ struct WSrc {
 struct SpreadSrc {
     int npairs;
     WSrc w[2 * kMaxPairsPerSpread];
+    // optional device flag: when nonzero the first column's spread is not
+    // needed (its moments are kept); the 3-D spread of one pair then spreads
+    // only the second column (other paths spread both)
+    const long long* keep_first;
 };
 
 struct ExpandArgs {

@@ -3380,11 +3380,12 @@ constexpr int kCol3Batch = 32;
 // FP64 atomic adds of a flush spread over the banks (3375: 3.91 ms for the
 // step's two 3-D spread launches; 3384: 3.53 ms; 3392: 3.97 ms).
 constexpr int kCol3TileStride = 15 * 15 * 15 + 9;
-// Staged sample row (floats): psi_x[8], psi_y[8] (permuted), 16 / NC zeros,
-// psi_z[8], 16 / NC zeros, w[4]
+// Staged sample row (floats): psi_x[8], psi_y[8] (permuted), PAD zeros,
+// psi_z[8], PAD zeros, w[4]; PAD = 16 / NC covers the plane offsets a step
+// reads around psi_z (one column: the window offset is below 8)
 template <int NC>
 struct Col3Row {
-    static constexpr int PAD = 16 / NC;
+    static constexpr int PAD = NC == 1 ? 8 : 16 / NC;
     static constexpr int Z = 16 + PAD;     // psi_z[0]
     static constexpr int W = Z + 8 + PAD;  // w[0]
     static constexpr int N = W + 4;
@@ -3409,7 +3410,8 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
 }
 
 // Column blocks a step touches: its window of eight planes starts in block
-// a = z0 / ZPB and reaches block a + 8 / ZPB.
+// a = z0 / ZPB and reaches block a + 8 / ZPB (one column: the 16 planes of
+// the one block hold every window, z0 < 8).
 template <int NC>
 constexpr int col3_blocks() { return 8 / (16 / NC) + 1; }
 
@@ -3454,19 +3456,25 @@ __device__ __forceinline__ void col3_flush_first(col3_v4 (&acc)[col3_blocks<NC>(
     for (int rb = 0; rb < 4; ++rb) acc[NB - 1][rb] = col3_v4{0.f, 0.f, 0.f, 0.f};
 }
 
+// NC = 1 spreads only the second column of each pair and stores zeros as
+// the first (the variance pass when the density moments are kept).  With a
+// gate the launch runs only when (*gate != 0) == gate_on (a flag the device
+// sets, so a captured graph holds both launches and one of them returns).
 template <int KER, int NC, int NT>
 __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* __restrict__ wrow, int wstride,
                                                     int64_t gstride, int col0, const uint32_t* __restrict__ loc,
                                                     const float* __restrict__ frac,
                                                     const int32_t* __restrict__ jobs,
-                                                    float* __restrict__ subgrid) {
+                                                    float* __restrict__ subgrid, const long long* gate,
+                                                    int gate_on) {
     constexpr int W = 8, PE = 15, PSUB = kCol3TileStride, NCELL = PE * PE * PE;
     constexpr int NWAVE = NT / 64;
-    constexpr int PPP = NC / 2;
+    constexpr int PPP = NC == 1 ? 1 : NC / 2;   // pairs per pass
     constexpr int B = kCol3Batch;
     constexpr int ZPB = 16 / NC;   // planes per column block
     constexpr int NB = col3_blocks<NC>();
-    static_assert(NC == 2 || NC == 4, "columns per pass");
+    static_assert(NC == 1 || NC == 2 || NC == 4, "columns per pass");
+    if (gate && ((*gate != 0) != (gate_on != 0))) return;   // uniform over the grid
     // LDS: the tile [NC][PSUB] (cell = x + PE (y + PE z)), then one staging
     // area of B rows per wave
     extern __shared__ double tile[];
@@ -3500,7 +3508,7 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
         const int seg = (n + NWAVE - 1) / NWAVE;
         const int q0 = min(n, wave * seg), q1 = min(n, q0 + seg);
         for (int p0 = 0; p0 < np; p0 += PPP) {
-            const int nw = 2 * min(PPP, np - p0);   // columns of this pass
+            const int nw = NC == 1 ? 1 : 2 * min(PPP, np - p0);   // columns of this pass
             for (int c = threadIdx.x; c < NC * PSUB; c += blockDim.x) tile[c] = 0.0;
             __syncthreads();
             // the column's accumulators, blocks base .. base + NB - 1; planes
@@ -3515,7 +3523,7 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
             int base = 0;
             // the pass's four columns: a group of the grouped layout, or
             // four columns of the rows
-            const int cb = col0 + 2 * p0;
+            const int cb = col0 + 2 * p0 + (NC == 1 ? 1 : 0);
             const float* wp = wrow + (gstride ? (cb >> 2) * gstride + (cb & 3) : (int64_t)cb) + (int64_t)s_beg * wstride;
             // the batch in registers: sample q0 + bt + sl; lane 63 also
             // holds the key of the sample after the batch (or ~0)
@@ -3613,7 +3621,7 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
                     for (int tb = 0; tb < NB; ++tb) {
                         // a block-aligned window (zb = 0, uniform over the
                         // wave) leaves the last block zero: its MFMAs are skipped
-                        if (tb == NB - 1 && zb == 0) break;
+                        if (NB > 1 && tb == NB - 1 && zb == 0) break;
                         const float bv = pz[ZPB * tb] * wc;
 #pragma unroll
                         for (int rb = 0; rb < 4; ++rb)
@@ -3625,11 +3633,19 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
             if (cur >= 0) col3_flush<NC, NB>(acc, tile, cur, base, lane);
             __syncthreads();
             // subgrid layout [job][pair][cell][re, im]
-            for (int q = 0; 2 * q < nw; ++q) {
-                float* dst = subgrid + ((int64_t)job * np + p0 + q) * NCELL * 2;
+            if constexpr (NC == 1) {
+                float* dst = subgrid + ((int64_t)job * np + p0) * NCELL * 2;
                 for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
-                    dst[2 * c] = (float)tile[2 * q * PSUB + c];
-                    dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
+                    dst[2 * c] = 0.f;
+                    dst[2 * c + 1] = (float)tile[c];
+                }
+            } else {
+                for (int q = 0; 2 * q < nw; ++q) {
+                    float* dst = subgrid + ((int64_t)job * np + p0 + q) * NCELL * 2;
+                    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+                        dst[2 * c] = (float)tile[2 * q * PSUB + c];
+                        dst[2 * c + 1] = (float)tile[(2 * q + 1) * PSUB + c];
+                    }
                 }
             }
             __syncthreads();
@@ -3639,9 +3655,10 @@ __global__ __launch_bounds__(NT) void k_spread_col3(Geo g, int np, const float* 
 
 template <int KER, int NC>
 static void spread_col3(const Geo& g, const SpreadSrc& src, const uint32_t* loc, const void* frac,
-                        const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s) {
+                        const int32_t* jobs, unsigned nb, void* subgrid, hipStream_t s,
+                        const long long* gate = nullptr, int gate_on = 0) {
     constexpr int PSUB = kCol3TileStride;
-    constexpr int NT = NC == 2 ? 1024 : 768;
+    constexpr int NT = NC <= 2 ? 1024 : 768;
     constexpr size_t lds =
         (size_t)NC * PSUB * sizeof(double) + (size_t)(NT / 64) * kCol3Batch * Col3Row<NC>::N * sizeof(float);
     static_assert(lds <= 160 * 1024, "tile and staging rows exceed the LDS of a workgroup");
@@ -3651,7 +3668,7 @@ static void spread_col3(const Geo& g, const SpreadSrc& src, const uint32_t* loc,
     k_spread_col3<KER, NC, NT><<<nb, NT, lds, s>>>(g, src.npairs, static_cast<const float*>(src.w[0].ptr),
                                                    (int)src.w[0].stride, src.w[0].gstride, (int)src.w[0].col, loc,
                                                    static_cast<const float*>(frac), jobs,
-                                                   static_cast<float*>(subgrid));
+                                                   static_cast<float*>(subgrid), gate, gate_on);
 }
 
 template <int W, int KER, int NW>
@@ -3721,8 +3738,16 @@ static void spread_w(const Geo& g, const SpreadSrc& src, const uint32_t* loc, co
                 if constexpr (D == 3 && W == 8) {
                     // columns per pass: four (a 108 KB FP64 tile), or two for
                     // one pair (two workgroups per CU)
-                    if (src.npairs == 1) spread_col3<KER, 2>(g, src, loc, frac, jobs, nb, subgrid, s);
-                    else spread_col3<KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    if (src.npairs == 1 && src.keep_first) {
+                        // the first column's moments may be kept (decided on the
+                        // device): the pair, or only its second column
+                        spread_col3<KER, 2>(g, src, loc, frac, jobs, nb, subgrid, s, src.keep_first, 0);
+                        spread_col3<KER, 1>(g, src, loc, frac, jobs, nb, subgrid, s, src.keep_first, 1);
+                    } else if (src.npairs == 1) {
+                        spread_col3<KER, 2>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    } else {
+                        spread_col3<KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
+                    }
                 } else if constexpr (D == 3) {
                     spread_group<D, W, T, KER, 4>(g, src, loc, frac, jobs, nb, subgrid, s);
                 } else {

@@ -161,17 +161,27 @@ def test_cv_many_probes_two_responses(orc):
         assert abs(gcv[c] / g_ref - 1) < 1e-5
 
 
-def test_variance_density_channel_reuse(orc):
+@pytest.mark.parametrize("d", [2, 3])
+def test_variance_density_channel_reuse(orc, d):
     """The second pass keeps the density moments of the last fit at the same
     h on the same points, and makes them again after a fit at another h or
     after new points: every order agrees with the oracle, and the kept and
-    remade moments give the same result to spreading round-off."""
-    N = 3000
+    remade moments give the same result to spreading round-off.  In 3-D the
+    kept case spreads only the second column (the one-column MFMA pass) and
+    the remade case the pair."""
     rng = np.random.default_rng(440)
-    X = rng.random((N, 2))
+    if d == 2:
+        N = 3000
+        X = rng.random((N, 2))
+        M, h, h2 = (30, 28), (0.12, 0.11), (0.2, 0.2)
+    else:
+        N = 20000
+        X = rng.random((N, 3))
+        M, h, h2 = (18, 17, 16), (0.14, 0.15, 0.13), (0.2, 0.2, 0.2)
     y = (X ** 2).sum(axis=1) + (0.1 + 0.5 * X[:, 1]) * rng.standard_normal(N)
-    M, h, h2 = (30, 28), (0.12, 0.11), (0.2, 0.2)
-    plan = make_plan(2, 1, M, h, h2, 1e-6, "fp32", n_max=N, max_weights=3, tprec="fp64")
+    plan = make_plan(d, 1, M, h, h2, 1e-6, "fp32", n_max=N, max_weights=3, tprec="fp64")
+    if d == 3:
+        assert plan.geometry.w == 8   # the MFMA spread
     Xd = to_dev(X, torch.float32)
     Yd = to_dev(y[:, None], torch.float32)
     plan.set_points(Xd)
@@ -182,10 +192,11 @@ def test_variance_density_channel_reuse(orc):
     plan.set_points(Xd)
     fresh = plan.variance(h, Yd, mh)[0].cpu().numpy()
     again = plan.variance(h, Yd, mh)[0].cpu().numpy()
-    yhat = orc.interp(mh.cpu().numpy(), M, (0, 0), (1, 1), X)
+    lo, hi = (0,) * d, (1,) * d
+    yhat = orc.interp(mh.cpu().numpy(), M, lo, hi, X)
     y32 = y.astype(np.float32).astype(np.float64)
-    ref, _ = orc.variance(X, y32, yhat, h, 1, M, (0, 0), (1, 1), mode="log")
-    gp = orc.grid_points(M, (0, 0), (1, 1))
+    ref, _ = orc.variance(X, y32, yhat, h, 1, M, lo, hi, mode="log")
+    gp = orc.grid_points(M, lo, hi)
     S, _ = orc.moments(X, None, h, 1, gp)
     mask = density_mask(S[:, 0])
     for got in (kept, other, fresh, again):
