@@ -127,8 +127,8 @@ typedef struct {
                                they differ from the exact kernel sums by the
                                kernel's aliasing, which shrinks with
                                (delta / h)^(s+1) for a kernel with s
-                               continuous derivatives; fkr_fit_full,
-                               fkr_interval and fkr_gcv_grad need the Gaussian
+                               continuous derivatives; fkr_fit_full and
+                               fkr_gcv_grad need the Gaussian
                                (FKR_E_UNSUPPORTED otherwise) */
 } fkr_plan_desc;
 
@@ -366,7 +366,10 @@ fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, int y_complex, const vo
  * g)^{b+c} sigma_i^2.  The squared Gaussian kernel is K_{h/sqrt2} times
  * prod_j 1 / (2 sqrt(pi) h_j), so Q comes from one more pass of the moment
  * path at h / sqrt 2, which must lie within the plan's bandwidth range
- * (create the plan with h_min <= h / sqrt 2), else FKR_E_ARG.
+ * (create the plan with h_min <= h / sqrt 2), else FKR_E_ARG.  With a
+ * compact reg_kernel the squared kernel prod_j (K(u_j / h_j)^2 / h_j) /
+ * h_j is sampled at h like the kernel (the binned approximation of both
+ * A and Q; exact for samples on grid nodes).
  *   sig_kind FKR_SIG_SCALAR: sigma_i^2 = sigma2 (homoscedastic model);
  *   FKR_SIG_GRID: sigma_i^2 = multilinear interpolation at x_i of the grid
  *   sigma2_dev ([M^d] doubles, e.g. fkr_variance's output); samples where it

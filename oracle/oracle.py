@@ -352,7 +352,7 @@ def moments_compact(X, W, h, order, gpts, kernel: str):
     return S, T
 
 
-def moments_binned(X, W, h, order, gpts, kernel: str, delta, L):
+def moments_binned(X, W, h, order, gpts, kernel: str, delta, L, square: bool = False, sw=None):
     """The binned approximation of the moment sums (eq. 11-13): the moment
     kernels k_a(z) = z^a K_h(z) sampled at the grid offsets m delta over one
     period T = L delta and convolved with the samples through their discrete
@@ -360,7 +360,10 @@ def moments_binned(X, W, h, order, gpts, kernel: str, delta, L):
     interpolant of the sampled kernel (the Fourier series of the periodised
     samples over every mode |n| <= L / 2, the modes +-L/2 of an even L with
     half the Nyquist coefficient each) at x_i - g.  Per dimension the
-    transform is NumPy's FFT of the samples; the series is summed directly."""
+    transform is NumPy's FFT of the samples; the series is summed directly.
+    square: the sampled kernel is K(z / h)^2 / h per dimension (the squared
+    kernel of the variance of the fit, up to prod_j 1 / h_j); sw: weights of
+    the samples in S (default one)."""
     X = np.asarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X[:, None]
@@ -377,7 +380,7 @@ def moments_binned(X, W, h, order, gpts, kernel: str, delta, L):
     for j in range(d):
         m = np.arange(L[j])
         z = np.where(m <= L[j] // 2, m, m - L[j]) * delta[j]            # periodised offsets
-        kz = compact_kernel(kernel, z / h[j]) / h[j]
+        kz = compact_kernel(kernel, z / h[j]) ** (2 if square else 1) / h[j]
         K = L[j] // 2
         n = np.arange(-K, K + 1)
         half = np.where(2 * np.abs(n) == L[j], 0.5, 1.0)                # even L: +-L/2 share the Nyquist term
@@ -389,12 +392,13 @@ def moments_binned(X, W, h, order, gpts, kernel: str, delta, L):
         freq.append(2.0 * np.pi * n / (L[j] * delta[j]))
     S = np.zeros((len(gpts), len(es)))
     T = np.zeros((len(gpts), W.shape[1], len(et)))
+    sw = np.ones(N) if sw is None else np.asarray(sw, dtype=np.float64).reshape(N)
     for g in range(len(gpts)):
         u = X - gpts[g]
         # interpolant values per dimension and degree: [d][deg+1][N]
         vals = [np.real(np.exp(1j * np.outer(u[:, j], freq[j])) @ coef[j].T).T for j in range(d)]
         for a, e in enumerate(es):
-            S[g, a] = np.sum(np.prod([vals[j][e[j]] for j in range(d)], axis=0))
+            S[g, a] = np.sum(sw * np.prod([vals[j][e[j]] for j in range(d)], axis=0))
         for b, e in enumerate(et):
             T[g, :, b] = np.prod([vals[j][e[j]] for j in range(d)], axis=0) @ W
     return S, T
@@ -844,14 +848,15 @@ def spline_predict(values: np.ndarray, M, lo, hi, Xq: np.ndarray) -> np.ndarray:
     return out
 
 
-def fit_variance(X, sigma2_i, h, order, gpts) -> np.ndarray:
+def fit_variance(X, sigma2_i, h, order, gpts, kernel: str = "gauss") -> np.ndarray:
     """Variance of the linear fit m_hat(g) = sum_i S_gi y_i for independent
     errors of variance sigma2_i (the Sigma of eq. 27):
     Sigma(g) = sum_i S_gi^2 sigma2_i, with the smoother weights of eq. (3),
     S_gi = e_1^T A(g)^{-1} K_h(x_i - g) d(x_i - g), d the monomial row of
     eq. (4)/(14).  Computed from its definition: row 0 of the inverse of the
     (equilibrated) moment matrix, then every weight S_gi.  NaN where the fit
-    is ill-posed; samples with undefined sigma2_i are left out."""
+    is ill-posed; samples with undefined sigma2_i are left out.  kernel: the
+    Gaussian, or a compact kernel of Table 1 (exact sums)."""
     X = np.asarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X[:, None]
@@ -860,7 +865,10 @@ def fit_variance(X, sigma2_i, h, order, gpts) -> np.ndarray:
     h = np.asarray(h, dtype=np.float64)
     s2 = np.broadcast_to(np.asarray(sigma2_i, dtype=np.float64), (N,))
     keep = np.isfinite(s2)
-    S, _ = moments(X, None, h, order, gpts)
+    if kernel == "gauss":
+        S, _ = moments(X, None, h, order, gpts)
+    else:
+        S, _ = moments_compact(X, None, h, order, gpts, kernel)
     _, r0, ill = solve(S, np.zeros((len(gpts), 0, len(multi_indices(d, order)))), h, order, d)
     et = np.array(multi_indices(d, order))
     norm = 1.0 / np.prod(h * np.sqrt(2.0 * np.pi))
@@ -873,7 +881,10 @@ def fit_variance(X, sigma2_i, h, order, gpts) -> np.ndarray:
         acc = 0.0
         for c0 in range(0, len(Xk), chunk):                     # the sum over samples, in pieces
             u = (Xk[c0:c0 + chunk] - gpts[g]) / h               # (x_i - g) / h per dimension
-            K = norm * np.exp(-0.5 * np.sum(u * u, axis=1))
+            if kernel == "gauss":
+                K = norm * np.exp(-0.5 * np.sum(u * u, axis=1))
+            else:
+                K = np.prod(compact_kernel(kernel, u) / h, axis=1)
             pw = [[np.ones(len(u))] for _ in range(d)]          # powers u_j^a, a <= order
             for j in range(d):
                 for a in range(order):
@@ -887,6 +898,30 @@ def fit_variance(X, sigma2_i, h, order, gpts) -> np.ndarray:
             w = row * K
             acc += float(np.sum(w * w * sk[c0:c0 + chunk]))
         out[g] = acc
+    return out
+
+
+def fit_variance_binned(X, sigma2_i, h, order, gpts, kernel: str, delta, L) -> np.ndarray:
+    """Sigma(g) = r^T Q r (eq. 27) under the binned approximation of a
+    compact kernel (eq. 11-13): r = row 0 of the inverse of the equilibrated
+    binned moment matrix of K_h, Q_bc the sigma_i^2-weighted binned moment of
+    degree b + c of the squared kernel K_h^2 = prod_j (K(z_j / h_j)^2 / h_j)
+    / h_j, brought to the same equilibration.  NaN where the fit is
+    ill-posed."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    N, d = X.shape
+    h = np.asarray(h, dtype=np.float64)
+    gpts = np.asarray(gpts, dtype=np.float64).reshape(-1, d)
+    s2 = np.broadcast_to(np.asarray(sigma2_i, dtype=np.float64), (N,))
+    keep = np.isfinite(s2)
+    S, _ = moments_binned(X, None, h, order, gpts, kernel, delta, L)
+    _, r0, ill = solve(S, np.zeros((len(gpts), 0, len(multi_indices(d, order)))), h, order, d)
+    Q, _ = moments_binned(X[keep], None, h, order, gpts, kernel, delta, L, square=True, sw=s2[keep])
+    A = assemble(Q, h, order, d)                                # Q_bc / h^{b+c}
+    out = np.einsum("gb,gbc,gc->g", r0, A, r0) / np.prod(h)
+    out[ill] = np.nan
     return out
 
 

@@ -251,10 +251,11 @@ fkr_status run_spectra(fkr_plan* p, const std::vector<WSrc>& srcs_in, hipStream_
 // it (weight 0 is not the density), 2 leaves it (the call writes only pairs
 // above the density moments).  deriv_dim >= 0 expands the derivatives of the
 // channels in log h of that dimension; pair_off places the channels that
-// many pairs up in the channel buffer.
+// many pairs up in the channel buffer.  ksq (compact kernels): the moments
+// of the squared kernel prod_j K(u_j / h_j)^2 / h_j (the caller untags).
 fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long* ill_clear, hipStream_t s,
                         bool reuse = false, int tag = 1, int deriv_dim = -1, int64_t pair_off = 0,
-                        const FullH* full = nullptr) {
+                        const FullH* full = nullptr, bool ksq = false) {
     const int nreal = p->n_s + p->n_t * (nr - 1);
     const int ncp = (nreal + 1) / 2;
     if (ncp + pair_off > p->ncp_max) return FKR_E_ARG;
@@ -277,7 +278,7 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
         if (deriv_dim >= 0) return FKR_E_UNSUPPORTED;
         a.kdeg = 2 * p->order + 1;
         a.ktab = at<double>(p, p->lay.ktab);
-        launch_ktab(a, p->delta, p->reg_kernel, at<double>(p, p->lay.ktab), s);
+        launch_ktab(a, p->delta, p->reg_kernel, ksq ? 1 : 0, at<double>(p, p->lay.ktab), s);
     }
     // the first inverse pass expands its rows from the pair spectra itself
     StageTimer tf(p, FKR_STAGE_FFT_INV, s);
@@ -973,16 +974,17 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
     if (st != FKR_OK) return st;
     if ((st = check_h(p, 1, h)) != FKR_OK) return st;
     if (!Sigma) return FKR_E_ARG;
-    if (p->reg_kernel) return FKR_E_UNSUPPORTED;   // uses K_h^2 = c K_{h / sqrt 2} of the Gaussian
     if (sig_kind == FKR_SIG_SCALAR) {
         if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return FKR_E_ARG;
     } else if (sig_kind != FKR_SIG_GRID || !sigma2_dev) {
         return FKR_E_ARG;
     }
     if ((lower || upper) && (!mhat || !(alpha > 0.0 && alpha < 1.0))) return FKR_E_ARG;
-    // the squared Gaussian kernel is a Gaussian of bandwidth h / sqrt 2
+    // the squared Gaussian kernel is a Gaussian of bandwidth h / sqrt 2; a
+    // compact kernel's square is sampled at h like the kernel itself
+    const bool compact = p->reg_kernel != 0;
     double h2[3] = {0.0, 0.0, 0.0};
-    for (int j = 0; j < p->d; ++j) h2[j] = h[j] / std::sqrt(2.0);
+    for (int j = 0; j < p->d; ++j) h2[j] = compact ? h[j] : h[j] / std::sqrt(2.0);
     if (check_h(p, 1, h2) != FKR_OK) return FKR_E_ARG;
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
@@ -997,13 +999,17 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
         launch_solve2(p->tprec, a, dev_pidx(p), p->ws + p->lay.chan, s);
     }
     // 2. moments of the weights sigma_i^2 under the squared kernel (the
-    // Gaussian at h / sqrt 2): the same density spectra for a constant
-    // sigma^2, else the interpolated grid staged as the weights of a spread
+    // Gaussian at h / sqrt 2, K_h^2 = K_{h/sqrt2} prod_j 1 / (2 sqrt(pi) h_j);
+    // a compact kernel: prod_j (K(u_j / h_j)^2 / h_j) prod_j 1 / h_j): the
+    // same density spectra for a constant sigma^2, else the interpolated grid
+    // staged as the weights of a spread
     IntervalArgs iv{};
     double scale = 1.0;
-    for (int j = 0; j < p->d; ++j) scale *= 1.0 / (2.0 * std::sqrt(M_PI) * h[j]);
+    for (int j = 0; j < p->d; ++j) scale *= compact ? 1.0 / h[j] : 1.0 / (2.0 * std::sqrt(M_PI) * h[j]);
     if (sig_kind == FKR_SIG_SCALAR) {
-        if ((st = run_channels(p, h2, 1, nullptr, s)) != FKR_OK) return st;
+        // the squared compact kernel's moments are no density moments: untagged
+        if ((st = run_channels(p, h2, 1, nullptr, s, false, compact ? 0 : 1, -1, 0, nullptr, compact)) != FKR_OK)
+            return st;
         scale *= sigma2;
     } else {
         {
@@ -1016,7 +1022,7 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
             srcs[r].stride = resid_row_stride(g, p->prec); srcs[r].col = r;
         }
         if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
-        if ((st = run_channels(p, h2, 1, nullptr, s, false, 0)) != FKR_OK) return st;
+        if ((st = run_channels(p, h2, 1, nullptr, s, false, 0, -1, 0, nullptr, compact)) != FKR_OK) return st;
     }
     // 3. Sigma = scale r0^T Q r0, with Q re-equilibrated from h / sqrt 2 to h
     iv.P = p->n_t;
@@ -1027,7 +1033,7 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
             int deg = 0;
             for (int j = 0; j < p->d; ++j) deg += p->et[b][j] + p->et[c][j];
             iv.sidx[b * kMaxP + c] = p->pair_index[b][c];
-            iv.fac[b * kMaxP + c] = std::pow(2.0, -0.5 * deg);
+            iv.fac[b * kMaxP + c] = compact ? 1.0 : std::pow(2.0, -0.5 * deg);   // h / sqrt 2 -> h
         }
     iv.scale = scale;
     iv.mhat = mhat;

@@ -302,7 +302,7 @@ hipError_t static_scratch(void** ptr);
 // groups gstride elements apart (FP32 only).
 void launch_stage_weights(int prec, const SpreadSrc& src, int nsrc, int r0, int nr, int64_t gstride, const PointsCheck& pc,
                           const int32_t* perm, void* out, hipStream_t s);
-void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, double* ktab, hipStream_t s);
+void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, int square, double* ktab, hipStream_t s);
 void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const int* es, const int* pidx,
                         const void* spec, void* out, hipStream_t s);
 void launch_chan_tag(long long* diag, const double* h, int d, hipStream_t s);

@@ -1674,7 +1674,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, Fu
 // exp(-i w m delta) over the offsets inside the support (the same phase
 // convention as the Gaussian's He_a(u) exp(-u^2/2) / T_j).  With every mode
 // |n| <= L/2 kept, each sample contributes the trigonometric interpolant of
-// the sampled moment kernel, exact at the grid offsets.
+// the sampled moment kernel, exact at the grid offsets.  square: K^2 in
+// place of K (the squared kernel of the variance of the fit, eq. 27, up to
+// prod_j 1 / h_j).
 __device__ __forceinline__ double compact_kernel(int kind, double u) {
     const double a = fabs(u);
     if (a > 1.0) return 0.0;
@@ -1688,7 +1690,8 @@ __device__ __forceinline__ double compact_kernel(int kind, double u) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1, double d2, int kind, double* tab) {
+__global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1, double d2, int kind, int square,
+                                              double* tab) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t off = 0, rem = id;
     int j = 0;
@@ -1708,7 +1711,8 @@ __global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1
     double re = 0.0, im = 0.0;
     for (int64_t m = -mmax; m <= mmax; ++m) {
         const double u = (double)m * delta / h;
-        double v = compact_kernel(kind, u) / h * delta;
+        const double kv = compact_kernel(kind, u);
+        double v = (square ? kv * kv : kv) / h * delta;
         for (int k = 0; k < deg; ++k) v *= u;
         double sn, cs;
         sincos(w * (double)m * delta, &sn, &cs);
@@ -1729,10 +1733,11 @@ __global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1
     tab[off + rem] = r / a.T[j];
 }
 
-void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, double* ktab, hipStream_t s) {
+void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, int square, double* ktab, hipStream_t s) {
     int64_t n = 0;
     for (int j = 0; j < a.d; ++j) n += (int64_t)a.kdeg * a.B[j];
-    k_ktab<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, delta[0], a.d > 1 ? delta[1] : 1.0, a.d > 2 ? delta[2] : 1.0, reg_kernel, ktab);
+    k_ktab<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, delta[0], a.d > 1 ? delta[1] : 1.0, a.d > 2 ? delta[2] : 1.0,
+                                                      reg_kernel, square, ktab);
 }
 
 void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const int* es, const int* pidx,

@@ -62,8 +62,55 @@ def test_compact_kernel_unsupported_calls():
                      tprec="fp64", reg_kernel="epanechnikov")
     plan.set_points(to_dev(X, torch.float32))
     Y = to_dev(np.zeros((N, 1)), torch.float32)
-    for call in (lambda: plan.interval((0.1, 0.1), 0.1), lambda: plan.gcv_grad((0.1, 0.1), Y, 2),
-                 lambda: plan.fit_full(np.diag([0.01, 0.01]), Y)):
+    for call in (lambda: plan.gcv_grad((0.1, 0.1), Y, 2), lambda: plan.fit_full(np.diag([0.01, 0.01]), Y)):
         with pytest.raises(FkrError) as e:
             call()
         assert e.value.status == FKR_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["box", "epanechnikov", "triweight"])
+def test_compact_interval_matches_oracle(orc, name):
+    """Variance of the fit (eq. 27) and its band (eq. 28) with a compact
+    kernel: Q from the sampled squared kernel at h.  Samples on grid nodes:
+    equal to the variance from its definition (exact kernel sums, explicit
+    smoother weights); random samples: equal to r^T Q r of the oracle's binned
+    moments, for a constant sigma^2 and for a sigma^2 grid interpolated to the
+    samples."""
+    d, order = 2, 1
+    M, h = (40, 36), (0.12, 0.14)
+    rng = np.random.default_rng(1200 + KERNELS.index(name))
+    plan = make_plan(d, order, M, h, h, 1e-10, "fp64", n_max=4000, max_weights=3, reg_kernel=name)
+    g = plan.geometry
+    L = [g.L[j] for j in range(d)]
+    delta = [g.delta[j] for j in range(d)]
+    flat = sample_flat(np.random.default_rng(6), M, 40)
+    gp = orc.grid_points(M, (0,) * d, (1,) * d)
+    # samples on the grid nodes
+    k = np.stack([rng.integers(0, M[0], 3000), rng.integers(0, M[1], 3000)], axis=1)
+    Xn = k / (np.array(M) - 1.0)
+    plan.set_points(to_dev(Xn))
+    sig = plan.interval(h, 0.3)["Sigma"].cpu().numpy()
+    ref = orc.fit_variance(Xn, 0.3, h, order, gp[flat], kernel=name)
+    ok = np.isfinite(ref) & np.isfinite(sig[flat])
+    assert ok.sum() > 20
+    e_node = rel_err(sig[flat], ref, ok)
+    # random samples: the binned approximation of A and Q
+    X = rng.random((4000, d))
+    y = np.sin(3 * X).sum(axis=1) + 0.2 * rng.standard_normal(4000)
+    plan.set_points(to_dev(X))
+    mh = plan.fit(h, to_dev(y[:, None]))[0, 0]
+    out = plan.interval(h, 0.3, mhat=mh, alpha=0.05)
+    ref_c = orc.fit_variance_binned(X, 0.3, h, order, gp[flat], name, delta, L)
+    s2_grid = 0.1 + gp[:, 0] ** 2 + 0.5 * gp[:, 1]
+    out_g = plan.interval(h, to_dev(s2_grid))
+    s2_i = orc.interp(s2_grid, M, (0,) * d, (1,) * d, X)
+    ref_g = orc.fit_variance_binned(X, s2_i, h, order, gp[flat], name, delta, L)
+    got_c = out["Sigma"].cpu().numpy()[flat]
+    got_g = out_g["Sigma"].cpu().numpy()[flat]
+    okc = np.isfinite(ref_c) & np.isfinite(got_c)
+    e_c = rel_err(got_c, ref_c, okc)
+    e_g = rel_err(got_g, ref_g, okc)
+    lo_r, up_r = orc.interval(mh.cpu().numpy()[flat], ref_c, alpha=0.05)
+    e_band = rel_err(out["upper"].cpu().numpy()[flat] - out["lower"].cpu().numpy()[flat], up_r - lo_r, okc)
+    print(f"{name}: Sigma on nodes {e_node:.2e}, binned const {e_c:.2e}, grid sigma^2 {e_g:.2e}, band {e_band:.2e}")
+    assert e_node < 1e-9 and e_c < 1e-9 and e_g < 1e-9 and e_band < 1e-9

@@ -839,6 +839,50 @@ def test_binned_moments_exact_for_samples_on_grid_nodes(orc, name):
     np.testing.assert_allclose(T1, T2, rtol=1e-9, atol=1e-11 * np.abs(T2).max())
 
 
+@pytest.mark.parametrize("name", ["box", "triangle", "epanechnikov", "triweight"])
+def test_fit_variance_compact_equals_explicit_smoother_rows(orc, name):
+    """For a compact kernel Sigma(g) = sum_i S_gi^2 sigma_i^2 with the rows
+    of the smoother built from the fits of the unit responses e_i (exact
+    kernel sums), and for l = 0 it is the variance of the weighted mean,
+    sigma^2 sum K^2 / (sum K)^2."""
+    rng = np.random.default_rng(28)
+    N = 140
+    X = rng.uniform(0, 1, (N, 2))
+    h = [0.3, 0.35]
+    gp = orc.grid_points([4, 3], [0.0, 0.0], [1.0, 1.0])
+    s2 = 0.1 + X[:, 0] ** 2
+    for order in (0, 1):
+        S, T = orc.moments_compact(X, np.eye(N), h, order, gp, name)
+        rows, _, ill = orc.solve(S, T, h, order, 2)
+        want = (rows ** 2 * s2).sum(1)
+        got = orc.fit_variance(X, s2, h, order, gp, kernel=name)
+        np.testing.assert_allclose(got[~ill], want[~ill], rtol=1e-10)
+    K = np.prod(orc.compact_kernel(name, (X[None, :, :] - gp[:, None, :]) / np.array(h)), axis=2)
+    wm = 0.3 * (K ** 2).sum(1) / K.sum(1) ** 2
+    got0 = orc.fit_variance(X, 0.3, h, 0, gp, kernel=name)
+    ok = K.sum(1) > 0
+    np.testing.assert_allclose(got0[ok], wm[ok], rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["box", "epanechnikov", "triweight"])
+def test_fit_variance_binned_exact_for_samples_on_grid_nodes(orc, name):
+    """Samples on grid nodes: the binned moments of K and of K^2 are the exact
+    sums, so r^T Q r from them equals the variance of the fit from its
+    definition (2-D, local linear, per-sample sigma^2)."""
+    rng = np.random.default_rng(29)
+    delta = np.array([0.02, 0.025])
+    L = np.array([90, 72])
+    k = np.stack([rng.integers(10, 40, 400), rng.integers(8, 30, 400)], axis=1)
+    X = k * delta
+    s2 = 0.05 + rng.random(400)
+    g = np.array([[0.4, 0.3], [0.5, 0.45], [0.3, 0.5]])
+    h = np.array([0.13, 0.11])
+    got = orc.fit_variance_binned(X, s2, h, 1, g, name, delta, L)
+    want = orc.fit_variance(X, s2, h, 1, g, kernel=name)
+    assert np.isfinite(want).all()
+    np.testing.assert_allclose(got, want, rtol=1e-9)
+
+
 def test_binned_moments_converge_with_kernel_smoothness(orc):
     """Off the nodes the binned sums approach the exact ones as the grid
     refines, faster for smoother kernels: halving delta / h cuts the error
