@@ -413,7 +413,17 @@ def _split_complex(Y: np.ndarray):
     return Y.astype(np.float64), False
 
 
-def fit(X, Y, h, order, gpts, return_all: bool = False):
+def _moments_of(X, W, h, order, gpts, binned):
+    """The Gaussian moment sums (``moments``), or with binned = (kernel,
+    delta, L) those of the binned approximation of a compact kernel
+    (``moments_binned``)."""
+    if binned is None:
+        return moments(X, W, h, order, gpts)
+    name, delta, L = binned
+    return moments_binned(X, W, h, order, gpts, name, delta, L)
+
+
+def fit(X, Y, h, order, gpts, return_all: bool = False, binned=None):
     """m_hat(g; l) of eq. (11) at the given grid points, for each response
     column (complex responses: real and imaginary parts share the real moment
     matrix).  Returns mhat (G x q) [, S, T, r0, ill]."""
@@ -422,7 +432,7 @@ def fit(X, Y, h, order, gpts, return_all: bool = False):
         X = X[:, None]
     d = X.shape[1]
     W, cplx = _split_complex(Y)
-    S, T = moments(X, W, h, order, gpts)
+    S, T = _moments_of(X, W, h, order, gpts, binned)
     mhat, r0, ill = solve(S, T, h, order, d)
     if cplx:
         q = W.shape[1] // 2
@@ -555,7 +565,7 @@ def girard_ratios(Wp: np.ndarray, What: np.ndarray) -> np.ndarray:
     return np.einsum("ip,ip->p", Wp, Wp - What) / np.einsum("ip,ip->p", Wp, Wp)
 
 
-def support(X, h, order, M, lo, hi, kappa: float = RESOLVE):
+def support(X, h, order, M, lo, hi, kappa: float = RESOLVE, binned=None):
     """Supported samples at bandwidth h (see the module docstring): the grid
     fit of the density moments, the resolved points, and the samples whose
     cell corners are all resolved.  Returns (supported samples, resolved
@@ -564,7 +574,7 @@ def support(X, h, order, M, lo, hi, kappa: float = RESOLVE):
     if X.ndim == 1:
         X = X[:, None]
     d = X.shape[1]
-    S, _ = moments(X, None, h, order, grid_points(M, lo, hi))
+    S, _ = _moments_of(X, None, h, order, grid_points(M, lo, hi), binned)
     ok = resolved(S, h, order, d, kappa)
     return supported(ok, M, lo, hi, X), ok
 
@@ -603,17 +613,18 @@ def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float, include=None) -> np.nd
     return np.mean(np.abs(r) ** 2, axis=0) / rho_mean ** 2
 
 
-def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None) -> float:
+def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None, binned=None) -> float:
     """GCV of eq. (22) at bandwidth h for one real response y, with the DF
     from the probes Wp (``dof``), over the supported samples I (``include``,
-    else the support rule at h)."""
+    else the support rule at h).  binned: a compact kernel's binned moments
+    (see ``fit``)."""
     y = np.asarray(y).reshape(-1)
     X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
     Yr, cplx = _split_complex(y)          # complex y: real and imaginary parts
     ny = Yr.shape[1]
     W = np.concatenate([Yr, Wp], axis=1)
     gp = grid_points(M, lo, hi)
-    mh, S, T, r0, ill = fit(X, W, h, order, gp, return_all=True)
+    mh, S, T, r0, ill = fit(X, W, h, order, gp, return_all=True, binned=binned)
     d = X.shape[1]
     if include is None:
         include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
@@ -624,24 +635,25 @@ def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None) -> float:
     return float(gcv(y, yhat, float(np.mean(rho)), include=include)[0])
 
 
-def gcv_log_h_gradient(X, y, h, order, M, lo, hi, Wp, include=None, step: float = 1e-4) -> np.ndarray:
+def gcv_log_h_gradient(X, y, h, order, M, lo, hi, Wp, include=None, step: float = 1e-4,
+                       binned=None) -> np.ndarray:
     """d GCV / d log h_j by central differences of ``gcv_criterion`` (step
     in log h), with the supported set held at that of h."""
     h = np.asarray(h, dtype=np.float64)
     X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
     if include is None:
-        include = support(X, h, order, M, lo, hi)[0]
+        include = support(X, h, order, M, lo, hi, binned=binned)[0]
     out = np.empty(len(h))
     for j in range(len(h)):
         e = np.zeros(len(h))
         e[j] = step
-        gp_ = gcv_criterion(X, y, h * np.exp(e), order, M, lo, hi, Wp, include)
-        gm_ = gcv_criterion(X, y, h * np.exp(-e), order, M, lo, hi, Wp, include)
+        gp_ = gcv_criterion(X, y, h * np.exp(e), order, M, lo, hi, Wp, include, binned)
+        gm_ = gcv_criterion(X, y, h * np.exp(-e), order, M, lo, hi, Wp, include, binned)
         out[j] = (gp_ - gm_) / (2.0 * step)
     return out
 
 
-def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None) -> np.ndarray:
+def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None, binned=None) -> np.ndarray:
     """d GCV / dy of ``gcv_criterion`` from its definition: the fitted
     values are yhat = S y with the smoother S (samples to samples through the
     grid fit and the interpolation) built column by column from the fits of
@@ -653,7 +665,8 @@ def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None) -> np.ndarray:
     X = np.asarray(X, dtype=np.float64).reshape(N, -1)
     d = X.shape[1]
     gp = grid_points(M, lo, hi)
-    mh, S, T, r0, ill = fit(X, np.concatenate([np.eye(N), Wp], axis=1), h, order, gp, return_all=True)
+    mh, S, T, r0, ill = fit(X, np.concatenate([np.eye(N), Wp], axis=1), h, order, gp, return_all=True,
+                            binned=binned)
     if include is None:
         include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
     include = np.asarray(include, dtype=bool)

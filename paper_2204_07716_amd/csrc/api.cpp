@@ -275,7 +275,7 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     a.ill_clear = ill_clear;
     a.deriv_dim = deriv_dim;
     if (p->reg_kernel && !full) {
-        if (deriv_dim >= 0) return FKR_E_UNSUPPORTED;
+        if (deriv_dim >= 0 && p->reg_kernel == FKR_REG_BOX) return FKR_E_UNSUPPORTED;   // steps at |u| = 1
         a.kdeg = 2 * p->order + 1;
         a.ktab = at<double>(p, p->lay.ktab);
         launch_ktab(a, p->delta, p->reg_kernel, ksq ? 1 : 0, at<double>(p, p->lay.ktab), s);
@@ -1114,6 +1114,10 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     for (int j = 0; j < p->d; ++j) { ea.h[j] = h[j]; ea.T[j] = p->T[j]; }
     ea.Btot = p->Btot;
     ea.deriv_dim = -1;
+    if (p->reg_kernel) {   // the base pass left the kernel's tables at h
+        ea.kdeg = 2 * p->order + 1;
+        ea.ktab = at<double>(p, p->lay.ktab);
+    }
     launch_adj_combine(p->tprec, ea, P, cplx, dev_et(p), at<double>(p, p->lay.deconv), bufs[cur], bufs[1 - cur], s);
     cur = 1 - cur;
     // band -> fine grid along dimensions d-1 .. 0 (the inverse passes of the
@@ -1155,7 +1159,8 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
     fkr_status st = common_fit_checks(p, 1, h, 1, y_complex, Y, y_type);
     if (st != FKR_OK) return st;
     if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
-    if (p->reg_kernel) return FKR_E_UNSUPPORTED;   // derivative multipliers of the Gaussian
+    // the box kernel's steps at the support's edge have no derivative in h
+    if (p->reg_kernel == FKR_REG_BOX) return FKR_E_UNSUPPORTED;
     const int ny = y_complex ? 2 : 1;
     if (ny + Np > kGradCols) return FKR_E_ARG;
     const int nr = 1 + ny + Np;

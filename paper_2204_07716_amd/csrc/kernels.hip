@@ -1526,8 +1526,8 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
         for (int k = 1; k < kExpandDeg; ++k) he[k + 1] = u * he[k] - k * he[k - 1];
         const bool dj = j == a.deriv_dim;
         if (a.ktab) {   // a compact kernel: the multipliers of its sampled moments
-            int64_t off = 0;
-            for (int i = 0; i < j; ++i) off += a.kdeg * a.B[i];
+            int64_t off = 0;   // dimension j's table, or the derivative block after all d
+            for (int i = 0; i < (dj ? a.d : j); ++i) off += a.kdeg * a.B[i];
 #pragma unroll
             for (int k = 0; k < kExpandDeg; ++k) mloc[j][k][tid] = k < a.kdeg ? a.ktab[off + k * a.B[j] + ej] : 0.0;
             continue;
@@ -1690,6 +1690,24 @@ __device__ __forceinline__ double compact_kernel(int kind, double u) {
     }
 }
 
+// u K'(u) of the compact kernels (the box's is zero inside the support; its
+// steps at |u| = 1 have no derivative, and callers refuse it)
+__device__ __forceinline__ double compact_kernel_udu(int kind, double u) {
+    if (fabs(u) > 1.0) return 0.0;
+    const double q = 1.0 - u * u;
+    switch (kind) {
+        case FKR_REG_BOX: return 0.0;
+        case FKR_REG_TRIANGLE: return -fabs(u);
+        case FKR_REG_EPANECHNIKOV: return -1.5 * u * u;
+        case FKR_REG_BIWEIGHT: return -3.75 * u * u * q;
+        default: return -6.5625 * u * u * q * q;
+    }
+}
+
+// Tables per dimension [d][kdeg][B_j]; with a.deriv_dim >= 0 one more block
+// [kdeg][B_j] for that dimension holds the derivative in log h_j of the
+// sampled moment kernel, d/dlog h (K(u/h) / h (u/h)^a) =
+// -((1 + a) K(v) + v K'(v)) v^a / h with v = u / h.
 __global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1, double d2, int kind, int square,
                                               double* tab) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1701,7 +1719,12 @@ __global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1
         rem -= nj;
         off += nj;
     }
-    if (j >= a.d) return;
+    bool deriv = false;
+    if (j >= a.d) {   // the derivative block
+        if (a.deriv_dim < 0 || rem >= (int64_t)a.kdeg * a.B[a.deriv_dim]) return;
+        j = a.deriv_dim;
+        deriv = true;
+    }
     const int deg = (int)(rem / a.B[j]);
     const int64_t e = rem - (int64_t)deg * a.B[j];
     const double delta = j == 0 ? d0 : (j == 1 ? d1 : d2);
@@ -1713,6 +1736,7 @@ __global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1
         const double u = (double)m * delta / h;
         const double kv = compact_kernel(kind, u);
         double v = (square ? kv * kv : kv) / h * delta;
+        if (deriv) v = -((1.0 + deg) * kv + compact_kernel_udu(kind, u)) / h * delta;
         for (int k = 0; k < deg; ++k) v *= u;
         double sn, cs;
         sincos(w * (double)m * delta, &sn, &cs);
@@ -1736,6 +1760,7 @@ __global__ __launch_bounds__(256) void k_ktab(ExpandArgs a, double d0, double d1
 void launch_ktab(const ExpandArgs& a, const double* delta, int reg_kernel, int square, double* ktab, hipStream_t s) {
     int64_t n = 0;
     for (int j = 0; j < a.d; ++j) n += (int64_t)a.kdeg * a.B[j];
+    if (a.deriv_dim >= 0) n += (int64_t)a.kdeg * a.B[a.deriv_dim];
     k_ktab<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, delta[0], a.d > 1 ? delta[1] : 1.0, a.d > 2 ? delta[2] : 1.0,
                                                       reg_kernel, square, ktab);
 }
@@ -2697,6 +2722,12 @@ __global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, int cp
         foff += a.B[j];
         const double u = a.h[j] * (2.0 * M_PI * (double)(ej - a.K[j]) / a.T[j]);
         const double gj = exp(-0.5 * u * u) / a.T[j];
+        if (a.ktab) {   // a compact kernel: the multipliers of its sampled moments
+            int64_t off = 0;
+            for (int i = 0; i < j; ++i) off += a.kdeg * a.B[i];
+            for (int k = 0; k < kExpandDeg; ++k) mloc[j][k] = k < a.kdeg ? a.ktab[off + k * a.B[j] + ej] : 0.0;
+            continue;
+        }
         double hm = 1.0, he = u;
         mloc[j][0] = gj;
         mloc[j][1] = u * gj;

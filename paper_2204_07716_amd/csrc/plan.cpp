@@ -244,9 +244,9 @@ static void layout(fkr_plan* p) {
     L.red = take((size_t)p->max_h * (2 * p->max_weights + 4) * 8);
     L.sup = take((size_t)p->Mtot * 4);
     L.r0 = take((size_t)p->Mtot * p->n_t * 8);
-    int64_t nb = 0;
-    for (int j = 0; j < p->d; ++j) nb += p->B[j];
-    L.ktab = take((size_t)(2 * p->order + 1) * nb * 8);
+    int64_t nb = 0, nbmax = 0;
+    for (int j = 0; j < p->d; ++j) { nb += p->B[j]; nbmax = std::max<int64_t>(nbmax, p->B[j]); }
+    L.ktab = take((size_t)(2 * p->order + 1) * (nb + nbmax) * 8);   // + one derivative block
     L.total = off;
 }
 

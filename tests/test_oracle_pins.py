@@ -724,6 +724,34 @@ def test_gcv_y_gradient_matches_central_differences(orc):
         assert g[i] == pytest.approx(fd, rel=1e-7, abs=1e-12)
 
 
+def test_gcv_gradients_binned_compact_kernel(orc):
+    """Under the binned approximation of a compact kernel the GCV is still
+    quadratic in y: the y gradient (explicit smoother of the binned fits)
+    matches central differences; in log h, away from the bandwidths where a
+    grid offset enters the support, the central-difference gradient does not
+    depend on the step."""
+    rng = np.random.default_rng(15)
+    N = 150
+    X = rng.random((N, 2))
+    y = np.sin(4 * X[:, 0]) * np.cos(2 * X[:, 1]) + 0.2 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi = (9, 8), (0.0, 0.0), (1.0, 1.0)
+    delta = [1.0 / 8, 1.0 / 7]
+    h = np.array([2.5 / 8, 2.5 / 7])
+    binned = ("epanechnikov", delta, [24, 22])
+    inc = orc.support(X, h, 1, M, lo, hi, binned=binned)[0]
+    g = orc.gcv_y_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc, binned=binned)
+    for i in range(0, N, 19):
+        e = np.zeros(N)
+        e[i] = 0.05
+        fd = (orc.gcv_criterion(X, y + e, h, 1, M, lo, hi, Wp, inc, binned=binned)
+              - orc.gcv_criterion(X, y - e, h, 1, M, lo, hi, Wp, inc, binned=binned)) / 0.1
+        assert g[i] == pytest.approx(fd, rel=1e-7, abs=1e-12)
+    g1 = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc, step=1e-3, binned=binned)
+    g2 = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc, step=5e-4, binned=binned)
+    np.testing.assert_allclose(g1, g2, rtol=2e-5, atol=2e-5 * np.abs(g1).max())
+
+
 def test_gcv_gradients_complex_response(orc):
     """Complex y: GCV uses |y - yhat|^2; the gradient d/dRe y + i d/dIm y
     matches central differences along the real and the imaginary axis, and
