@@ -248,6 +248,12 @@ fkr_status fkr_moments_full(fkr_plan* plan, int nh, const double* H, int nw, con
                             double* S_dev, double* T_dev, void* stream);
 fkr_status fkr_fit_full(fkr_plan* plan, int nh, const double* H, int q, int y_complex, const void* Y_dev,
                         int y_type, double* mhat_dev, double* s0_dev, void* stream);
+/* fkr_cv (fits, Monte-Carlo DF, RSS and GCV of eq. 22, Sec. 2.1) over a
+ * list of nh full bandwidth matrices H (as fkr_fit_full), for choosing H by
+ * GCV; arguments and outputs as fkr_cv with H in place of h. */
+fkr_status fkr_cv_full(fkr_plan* plan, int nh, const double* H, int q, int y_complex, const void* Y_dev,
+                       int y_type, int Np, uint64_t seed, const void* probes_dev, double* mhat_dev,
+                       double* rho_dev, double* rss_dev, double* gcv_dev, double* nused_dev, void* stream);
 
 /* Multilinear interpolation (the linear griddedInterpolant of Sec. 1.1/5) of
  * nv grid functions G_dev ([nv][M^d] doubles) at Nq query points Xq_dev

@@ -413,17 +413,28 @@ def _split_complex(Y: np.ndarray):
     return Y.astype(np.float64), False
 
 
-def _moments_of(X, W, h, order, gpts, binned):
-    """The Gaussian moment sums (``moments``), or with binned = (kernel,
-    delta, L) those of the binned approximation of a compact kernel
-    (``moments_binned``)."""
+def _moments_of(X, W, h, order, gpts, binned, H=None):
+    """The Gaussian moment sums (``moments``), with binned = (kernel, delta,
+    L) those of the binned approximation of a compact kernel
+    (``moments_binned``), or with H those of the Gaussian with the full
+    bandwidth matrix H (``moments_full``)."""
+    if H is not None:
+        return moments_full(X, W, H, order, gpts)
     if binned is None:
         return moments(X, W, h, order, gpts)
     name, delta, L = binned
     return moments_binned(X, W, h, order, gpts, name, delta, L)
 
 
-def fit(X, Y, h, order, gpts, return_all: bool = False, binned=None):
+def _equilibration(h, H, d):
+    """The equilibration of the moment matrix: h, or sqrt(diag H) for a full
+    bandwidth matrix."""
+    if H is None:
+        return h
+    return np.sqrt(np.diag(np.asarray(H, dtype=np.float64).reshape(d, d)))
+
+
+def fit(X, Y, h, order, gpts, return_all: bool = False, binned=None, H=None):
     """m_hat(g; l) of eq. (11) at the given grid points, for each response
     column (complex responses: real and imaginary parts share the real moment
     matrix).  Returns mhat (G x q) [, S, T, r0, ill]."""
@@ -432,8 +443,8 @@ def fit(X, Y, h, order, gpts, return_all: bool = False, binned=None):
         X = X[:, None]
     d = X.shape[1]
     W, cplx = _split_complex(Y)
-    S, T = _moments_of(X, W, h, order, gpts, binned)
-    mhat, r0, ill = solve(S, T, h, order, d)
+    S, T = _moments_of(X, W, h, order, gpts, binned, H)
+    mhat, r0, ill = solve(S, T, _equilibration(h, H, d), order, d)
     if cplx:
         q = W.shape[1] // 2
         mhat = mhat[:, :q] + 1j * mhat[:, q:]
@@ -565,7 +576,7 @@ def girard_ratios(Wp: np.ndarray, What: np.ndarray) -> np.ndarray:
     return np.einsum("ip,ip->p", Wp, Wp - What) / np.einsum("ip,ip->p", Wp, Wp)
 
 
-def support(X, h, order, M, lo, hi, kappa: float = RESOLVE, binned=None):
+def support(X, h, order, M, lo, hi, kappa: float = RESOLVE, binned=None, H=None):
     """Supported samples at bandwidth h (see the module docstring): the grid
     fit of the density moments, the resolved points, and the samples whose
     cell corners are all resolved.  Returns (supported samples, resolved
@@ -574,8 +585,8 @@ def support(X, h, order, M, lo, hi, kappa: float = RESOLVE, binned=None):
     if X.ndim == 1:
         X = X[:, None]
     d = X.shape[1]
-    S, _ = _moments_of(X, None, h, order, grid_points(M, lo, hi), binned)
-    ok = resolved(S, h, order, d, kappa)
+    S, _ = _moments_of(X, None, h, order, grid_points(M, lo, hi), binned, H)
+    ok = resolved(S, _equilibration(h, H, d), order, d, kappa)
     return supported(ok, M, lo, hi, X), ok
 
 
@@ -613,21 +624,21 @@ def gcv(y: np.ndarray, yhat: np.ndarray, rho_mean: float, include=None) -> np.nd
     return np.mean(np.abs(r) ** 2, axis=0) / rho_mean ** 2
 
 
-def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None, binned=None) -> float:
+def gcv_criterion(X, y, h, order, M, lo, hi, Wp, include=None, binned=None, H=None) -> float:
     """GCV of eq. (22) at bandwidth h for one real response y, with the DF
     from the probes Wp (``dof``), over the supported samples I (``include``,
-    else the support rule at h).  binned: a compact kernel's binned moments
-    (see ``fit``)."""
+    else the support rule at h).  binned: a compact kernel's binned moments;
+    H: a full bandwidth matrix in place of h (see ``fit``)."""
     y = np.asarray(y).reshape(-1)
     X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
     Yr, cplx = _split_complex(y)          # complex y: real and imaginary parts
     ny = Yr.shape[1]
     W = np.concatenate([Yr, Wp], axis=1)
     gp = grid_points(M, lo, hi)
-    mh, S, T, r0, ill = fit(X, W, h, order, gp, return_all=True, binned=binned)
+    mh, S, T, r0, ill = fit(X, W, h, order, gp, return_all=True, binned=binned, H=H)
     d = X.shape[1]
     if include is None:
-        include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
+        include = supported(~ill & resolved(S, _equilibration(h, H, d), order, d), M, lo, hi, X)
     include = np.asarray(include, dtype=bool)
     F = interp(mh, M, lo, hi, X)
     rho = girard_ratios(Wp[include], F[include, ny:])

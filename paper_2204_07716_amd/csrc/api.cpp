@@ -402,10 +402,13 @@ fkr_status common_fit_checks(fkr_plan* p, int nh, const double* h, int q, int y_
 
 // Fits, DF and RSS of a bandwidth list (the batched loop of Sec. 2 and
 // Fig. 3).  With rho_in the DF is given (fkr_gcv): no probes are spread and
-// the GCV uses the given Girard ratios.
+// the GCV uses the given Girard ratios.  With fh (and heff) the list is one
+// of full bandwidth matrices: the channels of matrix hi use fh[hi], the
+// solve heff[3 hi ..].
 fkr_status cv_impl(fkr_plan* p, int nh, const double* h, int q, int y_complex, const void* Y, int y_type, int Np,
                    uint64_t seed, const void* probes, const double* rho_in, double* mhat, double* rho, double* rss,
-                   double* gcv, double* nused, hipStream_t s) {
+                   double* gcv, double* nused, hipStream_t s, const FullH* fh = nullptr,
+                   const double* heff = nullptr) {
     fkr_status st;
     const int cpl = y_complex ? 2 : 1;
     const int ny = q * cpl;
@@ -432,8 +435,13 @@ fkr_status cv_impl(fkr_plan* p, int nh, const double* h, int q, int y_complex, c
     float* sup = at<float>(p, p->lay.sup);
     const int n_items = q + Ns;
     for (int hi = 0; hi < nh; ++hi) {
-        if ((st = run_channels(p, h + hi * p->d, nr, hi == 0 ? ill_ctr(p) : nullptr, s)) != FKR_OK) return st;
-        SolveArgs a = solve_args(p, nr, ny, y_complex, h + hi * p->d);
+        unsigned long long* ill = hi == 0 ? ill_ctr(p) : nullptr;
+        // full H: channels under K_H (no density tag: they are not the
+        // moments of a diagonal bandwidth)
+        st = fh ? run_channels(p, fh[hi].s, nr, ill, s, false, 0, -1, 0, &fh[hi])
+                : run_channels(p, h + hi * p->d, nr, ill, s);
+        if (st != FKR_OK) return st;
+        SolveArgs a = solve_args(p, nr, ny, y_complex, fh ? heff + 3 * hi : h + hi * p->d);
         double* yfit = mhat ? mhat + (int64_t)hi * ny * p->Mtot : internal;
         a.y_out = yfit;
         a.probe_out = (yrow || Ns > 0) ? pfit : nullptr;
@@ -837,6 +845,31 @@ fkr_status fkr_fit_full(fkr_plan* p, int nh, const double* H, int q, int y_compl
     }
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_cv_full(fkr_plan* p, int nh, const double* H, int q, int y_complex, const void* Y, int y_type, int Np,
+                       uint64_t seed, const void* probes, double* mhat, double* rho, double* rss, double* gcv,
+                       double* nused, void* stream) {
+    fkr_status st = ready(p);
+    if (st != FKR_OK) return st;
+    if (nh < 1 || nh > p->max_h || !H) return FKR_E_ARG;
+    if (q < 0 || (q > 0 && !Y && p->N > 0) || (y_complex != 0 && y_complex != 1)) return FKR_E_ARG;
+    if (q > 0 && !valid_type(y_type)) return FKR_E_ARG;
+    if (Np < 0 || (q == 0 && Np == 0)) return FKR_E_ARG;
+    if (gcv && (Np < 1 || q < 1)) return FKR_E_ARG;
+    const int ny = q * (y_complex ? 2 : 1);
+    if (1 + ny + Np > p->max_weights) return FKR_E_ARG;
+    if (probes && !valid_type(y_type)) return FKR_E_ARG;
+    if (p->reg_kernel) return FKR_E_UNSUPPORTED;
+    const int dd = p->d * p->d;
+    std::vector<FullH> fh(nh);
+    std::vector<double> heff(3 * nh, 0.0);
+    for (int hi = 0; hi < nh; ++hi)
+        if ((st = build_full(p, H + hi * dd, &fh[hi], &heff[3 * hi])) != FKR_OK) return st;
+    st = cv_impl(p, nh, nullptr, q, y_complex, Y, y_type, Np, seed, probes, nullptr, mhat, rho, rss, gcv, nused,
+                 S(stream), fh.data(), heff.data());
+    p->last_stream = stream;
+    return st;
 }
 
 fkr_status fkr_moments_full(fkr_plan* p, int nh, const double* H, int nw, const void* W, int w_type, double* Sout,

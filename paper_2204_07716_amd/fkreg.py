@@ -393,6 +393,28 @@ class Plan:
             mhat = torch.view_as_complex(mhat)
         return (mhat, s0) if want_s0 else mhat
 
+    def cv_full(self, H, Y: torch.Tensor, Np: int, seed: int = 0,
+                probes: Optional[torch.Tensor] = None, want_mhat: bool = True):
+        """fkr_cv over full bandwidth matrices H ([nh] x d x d): fits, DF, RSS, GCV."""
+        Hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(-1, self.d, self.d))
+        nh = Hb.shape[0]
+        Yr, q, cplx = _real_view(Y)
+        if probes is not None:
+            probes = probes.to(Yr.dtype).contiguous()
+        mhat = (torch.empty((nh, q, self.Mtot) + ((2,) if cplx else ()), dtype=torch.float64,
+                            device=self.device) if want_mhat else None)
+        rho = torch.empty((nh, Np), dtype=torch.float64, device=self.device) if Np else None
+        rss = torch.empty((nh, q), dtype=torch.float64, device=self.device)
+        gcv = torch.empty((nh, q), dtype=torch.float64, device=self.device) if Np else None
+        nused = torch.empty(nh, dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_cv_full(self._plan, nh, Hb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), q, cplx,
+                                   _ptr(Yr), _dtype_code(Yr), Np, ctypes.c_uint64(seed), _ptr(probes),
+                                   _ptr(mhat), _ptr(rho), _ptr(rss), _ptr(gcv), _ptr(nused), _stream()),
+              "fkr_cv_full")
+        if mhat is not None and cplx:
+            mhat = torch.view_as_complex(mhat)
+        return {"mhat": mhat, "rho": rho, "rss": rss, "gcv": gcv, "nused": nused}
+
     def moments_full(self, H, W: Optional[torch.Tensor] = None):
         Hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(-1, self.d, self.d))
         nh = Hb.shape[0]

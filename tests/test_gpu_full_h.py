@@ -115,3 +115,35 @@ def test_ll2d_full_size_full_h(orc):
     err = rel_err(mh[flat], ref[:, 0], density_mask(S[:, 0]))
     print(f"ll2d full H: s0 err {rel_err(s0[flat], S[:, 0]):.2e}, fit err {err:.2e}")
     assert err < 1e-5
+
+
+def test_full_h_cv_matches_oracle(orc):
+    """DF, RSS and GCV (eq. 22, Sec. 2.1) over a list of full bandwidth
+    matrices, for choosing H by GCV: against the oracle's GCV with the same
+    Philox probes; a diagonal H gives what fkr_cv gives at h = sqrt(diag H)."""
+    d, order, M, N, Np, seed = 2, 1, (30, 28), 2500, 4, 77
+    Hs = np.array([[[0.010, 0.006], [0.006, 0.016]], [[0.012, -0.005], [-0.005, 0.009]], [[0.011, 0.0], [0.0, 0.014]]])
+    rng = np.random.default_rng(1010)
+    X = rng.random((N, d))
+    y = np.sin(3 * X).sum(axis=1) + 0.2 * rng.standard_normal(N)
+    lo_r = [min(_h_range(H)[0][j] for H in Hs) for j in range(d)]
+    hi_r = [max(_h_range(H)[1][j] for H in Hs) for j in range(d)]
+    plan = make_plan(d, order, M, tuple(lo_r), tuple(hi_r), 1e-10, "fp64", n_max=N, max_weights=2 + Np, max_h=3)
+    plan.set_points(to_dev(X))
+    Y = to_dev(y[:, None])
+    out = plan.cv_full(Hs, Y, Np, seed=seed)
+    Wp = orc.probes(seed, N, Np)
+    lo, hi = (0.0,) * d, (1.0,) * d
+    for k, H in enumerate(Hs):
+        inc = orc.support(X, None, order, M, lo, hi, H=H)[0]
+        ref = orc.gcv_criterion(X, y, None, order, M, lo, hi, Wp, inc, H=H)
+        rho, _, _, _ = orc.dof(X, np.sqrt(np.diag(H)), order, M, lo, hi, Wp, include=inc) if k == 2 else (None,) * 4
+        got = out["gcv"][k, 0].item()
+        print(f"H {k}: gcv {got:.12e} / {ref:.12e}; N_I {out['nused'][k].item():.0f} / {inc.sum()}")
+        assert out["nused"][k].item() == inc.sum()
+        assert got == pytest.approx(ref, rel=1e-9)
+        if rho is not None:
+            np.testing.assert_allclose(out["rho"][k].cpu().numpy(), rho, rtol=1e-9)
+    # the diagonal matrix through fkr_cv at h = sqrt(diag H)
+    base = plan.cv(tuple(np.sqrt(np.diag(Hs[2]))), Y, Np, seed=seed)
+    assert out["gcv"][2, 0].item() == pytest.approx(base["gcv"][0, 0].item(), rel=1e-10)

@@ -752,6 +752,24 @@ def test_gcv_gradients_binned_compact_kernel(orc):
     np.testing.assert_allclose(g1, g2, rtol=2e-5, atol=2e-5 * np.abs(g1).max())
 
 
+def test_gcv_full_h_diagonal_reduces_to_product_kernel(orc):
+    """A diagonal bandwidth matrix H = diag(h^2) gives the product-kernel
+    GCV at h (the full-H moments by NumPy sums, the diagonal ones by the C
+    sums), and a rotated H changes it."""
+    rng = np.random.default_rng(16)
+    N = 300
+    X = rng.random((N, 2))
+    y = np.sin(3 * X[:, 0]) + X[:, 1] ** 2 + 0.2 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi = (10, 9), (0.0, 0.0), (1.0, 1.0)
+    h = np.array([0.14, 0.17])
+    g_diag = orc.gcv_criterion(X, y, h, 1, M, lo, hi, Wp)
+    g_full = orc.gcv_criterion(X, y, None, 1, M, lo, hi, Wp, H=np.diag(h ** 2))
+    assert g_full == pytest.approx(g_diag, rel=1e-10)
+    g_rot = orc.gcv_criterion(X, y, None, 1, M, lo, hi, Wp, H=np.array([[0.02, 0.012], [0.012, 0.03]]))
+    assert abs(g_rot / g_diag - 1) > 1e-4
+
+
 def test_gcv_gradients_complex_response(orc):
     """Complex y: GCV uses |y - yhat|^2; the gradient d/dRe y + i d/dIm y
     matches central differences along the real and the imaginary axis, and
