@@ -392,6 +392,14 @@ fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, int y_complex, const vo
 fkr_status fkr_interval(fkr_plan* plan, const double* h, int sig_kind, double sigma2,
                         const double* sigma2_dev, const double* mhat_dev, double alpha,
                         double* Sigma_dev, double* lower_dev, double* upper_dev, void* stream);
+/* fkr_interval at a full bandwidth matrix H (host, d x d, as fkr_fit_full;
+ * Gaussian kernel): K_H^2 = K_{H/2} (4 pi)^{-d/2} |H|^{-1/2}, so Q comes from
+ * one more pass at H / 2, which must lie within the plan's bandwidth range
+ * (the conditions of fkr_fit_full for H / 2), else FKR_E_ARG.  Arguments
+ * and outputs as fkr_interval. */
+fkr_status fkr_interval_full(fkr_plan* plan, const double* H, int sig_kind, double sigma2,
+                             const double* sigma2_dev, const double* mhat_dev, double alpha,
+                             double* Sigma_dev, double* lower_dev, double* upper_dev, void* stream);
 
 /* Prediction at new points by tensor-product cubic spline interpolation of
  * grid functions (Sec. 4 fkreg_compact / fkreg_predict; Table 1 y_grid_opt:

@@ -872,7 +872,7 @@ def spline_predict(values: np.ndarray, M, lo, hi, Xq: np.ndarray) -> np.ndarray:
     return out
 
 
-def fit_variance(X, sigma2_i, h, order, gpts, kernel: str = "gauss") -> np.ndarray:
+def fit_variance(X, sigma2_i, h, order, gpts, kernel: str = "gauss", H=None) -> np.ndarray:
     """Variance of the linear fit m_hat(g) = sum_i S_gi y_i for independent
     errors of variance sigma2_i (the Sigma of eq. 27):
     Sigma(g) = sum_i S_gi^2 sigma2_i, with the smoother weights of eq. (3),
@@ -880,16 +880,24 @@ def fit_variance(X, sigma2_i, h, order, gpts, kernel: str = "gauss") -> np.ndarr
     eq. (4)/(14).  Computed from its definition: row 0 of the inverse of the
     (equilibrated) moment matrix, then every weight S_gi.  NaN where the fit
     is ill-posed; samples with undefined sigma2_i are left out.  kernel: the
-    Gaussian, or a compact kernel of Table 1 (exact sums)."""
+    Gaussian, or a compact kernel of Table 1 (exact sums); H: the Gaussian
+    with a full bandwidth matrix (h unused), equilibrated by sqrt(diag H)."""
     X = np.asarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X[:, None]
     N, d = X.shape
     gpts = np.asarray(gpts, dtype=np.float64).reshape(-1, d)
+    if H is not None:
+        H = np.asarray(H, dtype=np.float64).reshape(d, d)
+        h = np.sqrt(np.diag(H))
+        Hi = np.linalg.inv(H)
+        hnorm = 1.0 / np.sqrt((2.0 * np.pi) ** d * np.linalg.det(H))
     h = np.asarray(h, dtype=np.float64)
     s2 = np.broadcast_to(np.asarray(sigma2_i, dtype=np.float64), (N,))
     keep = np.isfinite(s2)
-    if kernel == "gauss":
+    if H is not None:
+        S, _ = moments_full(X, None, H, order, gpts)
+    elif kernel == "gauss":
         S, _ = moments(X, None, h, order, gpts)
     else:
         S, _ = moments_compact(X, None, h, order, gpts, kernel)
@@ -905,7 +913,10 @@ def fit_variance(X, sigma2_i, h, order, gpts, kernel: str = "gauss") -> np.ndarr
         acc = 0.0
         for c0 in range(0, len(Xk), chunk):                     # the sum over samples, in pieces
             u = (Xk[c0:c0 + chunk] - gpts[g]) / h               # (x_i - g) / h per dimension
-            if kernel == "gauss":
+            if H is not None:
+                z = Xk[c0:c0 + chunk] - gpts[g]
+                K = hnorm * np.exp(-0.5 * np.einsum("ij,jk,ik->i", z, Hi, z))
+            elif kernel == "gauss":
                 K = norm * np.exp(-0.5 * np.sum(u * u, axis=1))
             else:
                 K = np.prod(compact_kernel(kernel, u) / h, axis=1)

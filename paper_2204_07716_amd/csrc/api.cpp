@@ -1000,13 +1000,16 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma2, const double* sigma2_dev,
-                        const double* mhat, double alpha, double* Sigma, double* lower, double* upper,
-                        void* stream) {
+// The variance of the fit at a diagonal bandwidth h, or (H non-null) at
+// the full bandwidth matrix H.
+fkr_status interval_impl(fkr_plan* p, const double* h, const double* H, int sig_kind, double sigma2,
+                         const double* sigma2_dev, const double* mhat, double alpha, double* Sigma, double* lower,
+                         double* upper, void* stream) {
     fkr_status st = ready(p);
     if (st != FKR_OK) return st;
-    if ((st = check_h(p, 1, h)) != FKR_OK) return st;
+    if (!H && (st = check_h(p, 1, h)) != FKR_OK) return st;
     if (!Sigma) return FKR_E_ARG;
+    if (H && p->reg_kernel) return FKR_E_UNSUPPORTED;
     if (sig_kind == FKR_SIG_SCALAR) {
         if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return FKR_E_ARG;
     } else if (sig_kind != FKR_SIG_GRID || !sigma2_dev) {
@@ -1017,15 +1020,41 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
     // compact kernel's square is sampled at h like the kernel itself
     const bool compact = p->reg_kernel != 0;
     double h2[3] = {0.0, 0.0, 0.0};
-    for (int j = 0; j < p->d; ++j) h2[j] = compact ? h[j] : h[j] / std::sqrt(2.0);
-    if (check_h(p, 1, h2) != FKR_OK) return FKR_E_ARG;
+    // full H: the squared kernel is K_{H/2} (4 pi)^{-d/2} |H|^{-1/2}
+    FullH fh{}, fh2{};
+    double heff[3] = {0.0, 0.0, 0.0}, heff2[3] = {0.0, 0.0, 0.0};
+    double detH = 1.0;
+    if (H) {
+        const int dd = p->d * p->d;
+        std::vector<double> Hh(dd);
+        for (int k = 0; k < dd; ++k) Hh[k] = 0.5 * H[k];
+        if ((st = build_full(p, H, &fh, heff)) != FKR_OK) return st;
+        if (build_full(p, Hh.data(), &fh2, heff2) != FKR_OK) return FKR_E_ARG;
+        // |H| from its Cholesky factor (H = L L^T, positive definite: build_full checked)
+        double Lc[3][3] = {};
+        for (int c = 0; c < p->d; ++c) {
+            double v = H[c * p->d + c];
+            for (int q = 0; q < c; ++q) v -= Lc[c][q] * Lc[c][q];
+            Lc[c][c] = std::sqrt(v);
+            detH *= v;
+            for (int b = c + 1; b < p->d; ++b) {
+                double u = H[b * p->d + c];
+                for (int q = 0; q < c; ++q) u -= Lc[b][q] * Lc[c][q];
+                Lc[b][c] = u / Lc[c][c];
+            }
+        }
+    } else {
+        for (int j = 0; j < p->d; ++j) h2[j] = compact ? h[j] : h[j] / std::sqrt(2.0);
+        if (check_h(p, 1, h2) != FKR_OK) return FKR_E_ARG;
+    }
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
     // 1. density moments at h -> row 0 of the equilibrated inverse per point
     std::vector<WSrc> dens{src_one()};
     if ((st = run_spectra(p, dens, s, false)) != FKR_OK) return st;
-    if ((st = run_channels(p, h, 1, ill_ctr(p), s)) != FKR_OK) return st;
-    SolveArgs a = solve_args(p, 1, 0, 0, h);
+    st = H ? run_channels(p, fh.s, 1, ill_ctr(p), s, false, 0, -1, 0, &fh) : run_channels(p, h, 1, ill_ctr(p), s);
+    if (st != FKR_OK) return st;
+    SolveArgs a = solve_args(p, 1, 0, 0, H ? heff : h);
     a.r0_out = at<double>(p, p->lay.r0);
     {
         StageTimer t(p, FKR_STAGE_SOLVE, s);
@@ -1038,11 +1067,20 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
     // staged as the weights of a spread
     IntervalArgs iv{};
     double scale = 1.0;
-    for (int j = 0; j < p->d; ++j) scale *= compact ? 1.0 / h[j] : 1.0 / (2.0 * std::sqrt(M_PI) * h[j]);
+    if (H)
+        scale = std::pow(4.0 * M_PI, -0.5 * p->d) / std::sqrt(detH);
+    else
+        for (int j = 0; j < p->d; ++j) scale *= compact ? 1.0 / h[j] : 1.0 / (2.0 * std::sqrt(M_PI) * h[j]);
+    // the squared kernel's channels: at h / sqrt 2 (tagged as the density
+    // moments there), at H / 2, or a compact kernel's square at h (neither
+    // is a diagonal-bandwidth density moment: untagged)
+    auto q_channels = [&]() {
+        if (H) return run_channels(p, fh2.s, 1, nullptr, s, false, 0, -1, 0, &fh2);
+        return run_channels(p, h2, 1, nullptr, s, false, compact || sig_kind != FKR_SIG_SCALAR ? 0 : 1, -1, 0,
+                            nullptr, compact);
+    };
     if (sig_kind == FKR_SIG_SCALAR) {
-        // the squared compact kernel's moments are no density moments: untagged
-        if ((st = run_channels(p, h2, 1, nullptr, s, false, compact ? 0 : 1, -1, 0, nullptr, compact)) != FKR_OK)
-            return st;
+        if ((st = q_channels()) != FKR_OK) return st;
         scale *= sigma2;
     } else {
         {
@@ -1055,7 +1093,7 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
             srcs[r].stride = resid_row_stride(g, p->prec); srcs[r].col = r;
         }
         if ((st = run_spectra(p, srcs, s, true)) != FKR_OK) return st;
-        if ((st = run_channels(p, h2, 1, nullptr, s, false, 0, -1, 0, nullptr, compact)) != FKR_OK) return st;
+        if ((st = q_channels()) != FKR_OK) return st;
     }
     // 3. Sigma = scale r0^T Q r0, with Q re-equilibrated from h / sqrt 2 to h
     iv.P = p->n_t;
@@ -1066,7 +1104,7 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
             int deg = 0;
             for (int j = 0; j < p->d; ++j) deg += p->et[b][j] + p->et[c][j];
             iv.sidx[b * kMaxP + c] = p->pair_index[b][c];
-            iv.fac[b * kMaxP + c] = compact ? 1.0 : std::pow(2.0, -0.5 * deg);   // h / sqrt 2 -> h
+            iv.fac[b * kMaxP + c] = compact ? 1.0 : std::pow(2.0, -0.5 * deg);   // s / sqrt 2 -> s
         }
     iv.scale = scale;
     iv.mhat = mhat;
@@ -1080,6 +1118,20 @@ fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma
     }
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_interval(fkr_plan* p, const double* h, int sig_kind, double sigma2, const double* sigma2_dev,
+                        const double* mhat, double alpha, double* Sigma, double* lower, double* upper,
+                        void* stream) {
+    if (!h) return FKR_E_ARG;
+    return interval_impl(p, h, nullptr, sig_kind, sigma2, sigma2_dev, mhat, alpha, Sigma, lower, upper, stream);
+}
+
+fkr_status fkr_interval_full(fkr_plan* p, const double* H, int sig_kind, double sigma2, const double* sigma2_dev,
+                             const double* mhat, double alpha, double* Sigma, double* lower, double* upper,
+                             void* stream) {
+    if (!H) return FKR_E_ARG;
+    return interval_impl(p, nullptr, H, sig_kind, sigma2, sigma2_dev, mhat, alpha, Sigma, lower, upper, stream);
 }
 
 // Gradient of GCV in y after the base pass at h (channels at h in the first

@@ -451,11 +451,15 @@ class Plan:
         return {"gcv": gcv, "dlogh": dlogh, "dy": dy, "dfit": dfit}
 
     # -- prediction and inference ---------------------------------------
-    def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05):
+    def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05, H=None):
         """Variance of the fit Sigma [M] (eq. 27) for error variance sigma2 (a
         number, or a grid [M] interpolated to the samples), and with mhat the
-        band mhat -/+ z_{1-alpha/2} sqrt(Sigma) (eq. 28)."""
-        hb = _hbuf(h, self.d)
+        band mhat -/+ z_{1-alpha/2} sqrt(Sigma) (eq. 28).  With H (d x d) the
+        full bandwidth matrix H in place of h."""
+        if H is not None:
+            hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(self.d, self.d))
+        else:
+            hb = _hbuf(h, self.d)
         Sigma = torch.empty(self.Mtot, dtype=torch.float64, device=self.device)
         band = mhat is not None
         lower = torch.empty_like(Sigma) if band else None
@@ -466,8 +470,9 @@ class Plan:
             kind, val = _lib.FKR_SIG_GRID, 0.0
         else:
             g, kind, val = None, _lib.FKR_SIG_SCALAR, float(sigma2)
-        check(self.lib.fkr_interval(self._plan, _hptr(hb), kind, val, _ptr(g), _ptr(m), float(alpha),
-                                    _ptr(Sigma), _ptr(lower), _ptr(upper), _stream()), "fkr_interval")
+        fn = self.lib.fkr_interval_full if H is not None else self.lib.fkr_interval
+        check(fn(self._plan, _hptr(hb), kind, val, _ptr(g), _ptr(m), float(alpha), _ptr(Sigma), _ptr(lower),
+                 _ptr(upper), _stream()), "fkr_interval_full" if H is not None else "fkr_interval")
         return {"Sigma": Sigma, "lower": lower, "upper": upper}
 
     def spline(self, G: torch.Tensor) -> torch.Tensor:

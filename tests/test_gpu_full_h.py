@@ -147,3 +147,45 @@ def test_full_h_cv_matches_oracle(orc):
     # the diagonal matrix through fkr_cv at h = sqrt(diag H)
     base = plan.cv(tuple(np.sqrt(np.diag(Hs[2]))), Y, Np, seed=seed)
     assert out["gcv"][2, 0].item() == pytest.approx(base["gcv"][0, 0].item(), rel=1e-10)
+
+
+@pytest.mark.parametrize("prec,tprec", [("fp64", "same"), ("fp32", "fp64")])
+def test_full_h_interval_matches_oracle(orc, prec, tprec):
+    """Variance of the fit and band (eq. 27-28) at a full bandwidth matrix:
+    Q from the pass at H / 2; against the oracle's Sigma from its definition
+    (full-H smoother weights), for a constant and a gridded sigma^2, and the
+    diagonal H against fkr_interval at h = sqrt(diag H)."""
+    d, order, M, N = 2, 1, (26, 24), 3000
+    H = np.array([[0.012, 0.005], [0.005, 0.016]])
+    Hd = np.diag([0.011, 0.014])
+    lo_r = tuple(np.minimum(_h_range(H / 2)[0], _h_range(Hd / 2)[0]))
+    hi_r = tuple(np.maximum(_h_range(H)[1], _h_range(Hd)[1]))
+    rng = np.random.default_rng(1020)
+    X = rng.random((N, d))
+    y = np.sin(3 * X).sum(axis=1) + 0.2 * rng.standard_normal(N)
+    plan = make_plan(d, order, M, lo_r, hi_r, 1e-10 if prec == "fp64" else 1e-6, prec, n_max=N, max_weights=2,
+                     tprec=tprec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Xr = X.astype(np.float32).astype(np.float64) if prec == "fp32" else X
+    plan.set_points(to_dev(X, dt))
+    mh = plan.fit_full(H, to_dev(y[:, None], dt))[0, 0]
+    gp = orc.grid_points(M, (0,) * d, (1,) * d)
+    flat = np.arange(0, gp.shape[0], 7)
+    out = plan.interval(None, 0.3, mhat=mh, alpha=0.05, H=H)
+    ref = orc.fit_variance(Xr, 0.3, None, order, gp[flat], H=H)
+    s2_grid = 0.1 + gp[:, 0] ** 2
+    out_g = plan.interval(None, to_dev(s2_grid), H=H)
+    ref_g = orc.fit_variance(Xr, orc.interp(s2_grid, M, (0,) * d, (1,) * d, Xr), None, order, gp[flat], H=H)
+    got = out["Sigma"].cpu().numpy()[flat]
+    ok = np.isfinite(ref) & np.isfinite(got)
+    bar = 1e-8 if prec == "fp64" else 1e-5
+    e_c = rel_err(got, ref, ok)
+    e_g = rel_err(out_g["Sigma"].cpu().numpy()[flat], ref_g, ok)
+    half = 0.5 * (out["upper"] - out["lower"]).cpu().numpy()[flat]
+    e_b = rel_err(half, 1.959963984540054 * np.sqrt(np.maximum(ref, 0.0)), ok)
+    print(f"full-H interval {prec}: Sigma {e_c:.2e}, gridded sigma^2 {e_g:.2e}, band {e_b:.2e}")
+    assert e_c < bar and e_g < bar and e_b < bar
+    d1 = plan.interval(None, 0.3, H=Hd)["Sigma"].cpu().numpy()
+    d2 = plan.interval(tuple(np.sqrt(np.diag(Hd))), 0.3)["Sigma"].cpu().numpy()
+    fin = np.isfinite(d2)
+    assert rel_err(d1, d2, fin) < (1e-10 if prec == "fp64" else 1e-5)

@@ -624,6 +624,24 @@ def test_fit_variance_equals_explicit_smoother_rows(orc):
         np.testing.assert_allclose(orc.fit_variance(X, s2, h, order, gp), (rows ** 2 * s2).sum(1), rtol=1e-10)
 
 
+def test_fit_variance_full_h_equals_explicit_smoother_rows(orc):
+    """With a full bandwidth matrix: Sigma from the smoother rows of the
+    full-H fits of the unit responses, and a diagonal H gives the product
+    kernel's Sigma at h = sqrt(diag H)."""
+    rng = np.random.default_rng(30)
+    N = 140
+    X = rng.uniform(0, 1, (N, 2))
+    gp = orc.grid_points([5, 4], [0.0, 0.0], [1.0, 1.0])
+    s2 = 0.1 + X[:, 0] ** 2
+    H = np.array([[0.03, 0.012], [0.012, 0.045]])
+    rows, _, ill = orc.fit_full(X, np.eye(N), H, 1, gp)
+    got = orc.fit_variance(X, s2, None, 1, gp, H=H)
+    np.testing.assert_allclose(got[~ill], (rows ** 2 * s2).sum(1)[~ill], rtol=1e-10)
+    h = np.array([0.17, 0.21])
+    np.testing.assert_allclose(orc.fit_variance(X, s2, None, 1, gp, H=np.diag(h ** 2)),
+                               orc.fit_variance(X, s2, h, 1, gp), rtol=1e-10)
+
+
 def test_fit_variance_is_the_variance_of_the_fit(orc):
     """eq. (27): Sigma is var[m_hat(g)].  Simulated responses y = m + sigma eps
     (8000 replicas): the sample variance of the fits agrees within five
