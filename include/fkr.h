@@ -325,6 +325,13 @@ fkr_status fkr_gcv(fkr_plan* plan, int nh, const double* h, int q, int y_complex
 fkr_status fkr_variance(fkr_plan* plan, const double* h, int y_complex, const void* Y_dev,
                         int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
                         double* vhat_dev, double* kappa_dev, void* stream);
+/* fkr_variance with the second fit at a full bandwidth matrix H (host,
+ * d x d, as fkr_fit_full; Gaussian kernel); mhat_dev is the fit at H
+ * (fkr_fit_full).  Nothing is kept between calls: the density moments under
+ * K_H are made again. */
+fkr_status fkr_variance_full(fkr_plan* plan, const double* H, int y_complex, const void* Y_dev,
+                             int y_type, const double* mhat_dev, int mode, double* sigma2_dev,
+                             double* vhat_dev, double* kappa_dev, void* stream);
 
 /* Gradient of the GCV criterion of eq. (22) with respect to log h (Sec. 2.1:
  * bandwidth selection minimises GCV over h) and to the response, for one

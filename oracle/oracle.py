@@ -733,7 +733,7 @@ def get_hlist(n, rng, kind: str = "log") -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
-             gpts: Optional[np.ndarray] = None):
+             gpts: Optional[np.ndarray] = None, H=None):
     """Second pass on squared residuals r_i = |y_i - yhat(x_i)|^2.
 
     Samples whose residual is undefined (NaN mean fit at their cell) are left
@@ -741,7 +741,8 @@ def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
     mode "log" (eq. 24-26): v = local fit of log(r_i + 1/N); kappa =
     [mean_i r_i exp(-v(x_i))]^-1 with v(x_i) interpolated from the full grid,
     over the samples where that term is defined; sigma^2(g) = exp(v(g)) / kappa.
-    mode "direct" (eq. 23): sigma^2(g) = local fit of r_i.
+    mode "direct" (eq. 23): sigma^2(g) = local fit of r_i.  H: the second
+    fit with that full bandwidth matrix (h unused).
     Returns (sigma2 at gpts (or the full grid), extras dict)."""
     X = np.asarray(X, dtype=np.float64).reshape(len(yhat_at_samples), -1)
     N = X.shape[0]
@@ -749,14 +750,14 @@ def variance(X, y, yhat_at_samples, h, order, M, lo, hi, mode: str = "log",
     keep = np.isfinite(r)
     full = grid_points(M, lo, hi)
     if mode == "direct":
-        s2 = fit(X[keep], r[keep], h, order, full if gpts is None else gpts)[:, 0]
+        s2 = fit(X[keep], r[keep], h, order, full if gpts is None else gpts, H=H)[:, 0]
         return s2, {"r": r}
     z = np.log(r + 1.0 / N)
-    v_full = fit(X[keep], z[keep], h, order, full)[:, 0]
+    v_full = fit(X[keep], z[keep], h, order, full, H=H)[:, 0]
     v_i = interp(v_full, M, lo, hi, X)
     term = r * np.exp(-v_i)
     kappa = 1.0 / np.mean(term[np.isfinite(term)])
-    v = v_full if gpts is None else fit(X[keep], z[keep], h, order, gpts)[:, 0]
+    v = v_full if gpts is None else fit(X[keep], z[keep], h, order, gpts, H=H)[:, 0]
     return np.exp(v) / kappa, {"r": r, "z": z, "v": v_full, "kappa": kappa}
 
 

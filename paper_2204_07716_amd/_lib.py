@@ -49,7 +49,7 @@ class Diag(ctypes.Structure):
 
 EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_workspace_size",
            "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit", "fkr_fit_noalloc",
-           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_interval", "fkr_interval_full", "fkr_gcv_grad", "fkr_fit_full", "fkr_cv_full", "fkr_moments_full", "fkr_spline",
+           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_variance_full", "fkr_interval", "fkr_interval_full", "fkr_gcv_grad", "fkr_fit_full", "fkr_cv_full", "fkr_moments_full", "fkr_spline",
            "fkr_predict", "fkr_get_diagnostics",
            "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
            "fkr_profile_read", "fkr_batch_create", "fkr_batch_destroy", "fkr_batch_workspace_size",
@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
         "fkr_cv": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P, P], I),
         "fkr_gcv": ([P, I, pD, I, I, P, I, I, P, P, P, P, P, P], I),
         "fkr_variance": ([P, pD, I, P, I, P, I, P, P, P, P], I),
+        "fkr_variance_full": ([P, pD, I, P, I, P, I, P, P, P, P], I),
         "fkr_interval": ([P, pD, I, D, P, P, D, P, P, P, P], I),
         "fkr_interval_full": ([P, pD, I, D, P, P, D, P, P, P, P], I),
         "fkr_spline": ([P, I, P, P, P], I),

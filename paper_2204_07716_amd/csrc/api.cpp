@@ -951,13 +951,22 @@ fkr_status fkr_dof(fkr_plan* p, int nh, const double* h, int Np, uint64_t seed, 
     return fkr_cv(p, nh, h, 0, 0, probes, w_type, Np, seed, probes, nullptr, rho, nullptr, nullptr, nused, stream);
 }
 
-fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type,
-                        const double* mhat, int mode, double* sigma2, double* vhat, double* kappa,
-                        void* stream) {
-    fkr_status st = common_fit_checks(p, 1, h, 1, y_complex, Y, y_type);
+// The second pass at a diagonal bandwidth h, or (H non-null) at the full
+// bandwidth matrix H.
+fkr_status variance_impl(fkr_plan* p, const double* h, const double* H, int y_complex, const void* Y, int y_type,
+                         const double* mhat, int mode, double* sigma2, double* vhat, double* kappa, void* stream) {
+    fkr_status st = ready(p);
     if (st != FKR_OK) return st;
+    if (!H && (st = check_h(p, 1, h)) != FKR_OK) return st;
+    if ((!Y && p->N > 0) || (y_complex != 0 && y_complex != 1) || !valid_type(y_type)) return FKR_E_ARG;
     if (!mhat || !sigma2 || (mode != FKR_VAR_LOG && mode != FKR_VAR_DIRECT)) return FKR_E_ARG;
     if (p->max_weights < 2) return FKR_E_ARG;
+    FullH fh{};
+    double heff[3] = {0.0, 0.0, 0.0};
+    if (H) {
+        if (p->reg_kernel) return FKR_E_UNSUPPORTED;
+        if ((st = build_full(p, H, &fh, heff)) != FKR_OK) return st;
+    }
     const hipStream_t s = S(stream);
     const Geo g = make_geo(p);
     double* wbuf = at<double>(p, p->lay.wbuf);
@@ -976,11 +985,13 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     // channel buffer still holds them for these points at this h and the
     // residual pass left no sample out, the passes skip their pairs (decided
     // on the device), and the spread skips the density column.
-    const bool keep = p->n_s % 2 == 0;
+    // (a full H: its channels carry no density tag, so nothing is kept)
+    const bool keep = !H && p->n_s % 2 == 0;
     if (keep) launch_chan_reuse(diag_ptr(p), h, p->d, s);
     if ((st = run_spectra(p, srcs, s, true, keep ? diag_ptr(p) + kDiagReuse : nullptr)) != FKR_OK) return st;
-    if ((st = run_channels(p, h, 2, ill_ctr(p), s, true)) != FKR_OK) return st;
-    SolveArgs a = solve_args(p, 2, 1, 0, h);
+    st = H ? run_channels(p, fh.s, 2, ill_ctr(p), s, false, 0, -1, 0, &fh) : run_channels(p, h, 2, ill_ctr(p), s, true);
+    if (st != FKR_OK) return st;
+    SolveArgs a = solve_args(p, 2, 1, 0, H ? heff : h);
     double* v = mode == FKR_VAR_DIRECT ? sigma2 : (vhat ? vhat : at<double>(p, p->lay.mhat));
     a.y_out = v;
     {
@@ -998,6 +1009,20 @@ fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void*
     }
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_variance(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type,
+                        const double* mhat, int mode, double* sigma2, double* vhat, double* kappa,
+                        void* stream) {
+    if (!h) return FKR_E_ARG;
+    return variance_impl(p, h, nullptr, y_complex, Y, y_type, mhat, mode, sigma2, vhat, kappa, stream);
+}
+
+fkr_status fkr_variance_full(fkr_plan* p, const double* H, int y_complex, const void* Y, int y_type,
+                             const double* mhat, int mode, double* sigma2, double* vhat, double* kappa,
+                             void* stream) {
+    if (!H) return FKR_E_ARG;
+    return variance_impl(p, nullptr, H, y_complex, Y, y_type, mhat, mode, sigma2, vhat, kappa, stream);
 }
 
 // The variance of the fit at a diagonal bandwidth h, or (H non-null) at

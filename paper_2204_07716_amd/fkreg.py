@@ -365,8 +365,12 @@ class Plan:
         return {"mhat": mhat, "rho": rho, "rss": rss, "gcv": gcv, "nused": nused}
 
     # -- a11 ------------------------------------------------------------
-    def variance(self, h, Y: torch.Tensor, mhat: torch.Tensor, mode: str = "log"):
-        hb = _hbuf(h, self.d)
+    def variance(self, h, Y: torch.Tensor, mhat: torch.Tensor, mode: str = "log", H=None):
+        """The second pass (Sec. 3) at h, or with H (d x d) at that full bandwidth matrix."""
+        if H is not None:
+            hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(self.d, self.d))
+        else:
+            hb = _hbuf(h, self.d)
         Yr, q, cplx = _real_view(Y)
         assert q == 1, "one response column"
         m = torch.view_as_real(mhat).contiguous() if mhat.is_complex() else mhat.contiguous()
@@ -374,9 +378,9 @@ class Plan:
         vhat = torch.empty(self.Mtot, dtype=torch.float64, device=self.device)
         kappa = torch.empty(1, dtype=torch.float64, device=self.device)
         md = _lib.FKR_VAR_LOG if mode == "log" else _lib.FKR_VAR_DIRECT
-        check(self.lib.fkr_variance(self._plan, _hptr(hb), cplx, _ptr(Yr), _dtype_code(Yr), _ptr(m),
-                                    md, _ptr(sigma2), _ptr(vhat), _ptr(kappa), _stream()),
-              "fkr_variance")
+        fn = self.lib.fkr_variance_full if H is not None else self.lib.fkr_variance
+        check(fn(self._plan, _hptr(hb), cplx, _ptr(Yr), _dtype_code(Yr), _ptr(m), md, _ptr(sigma2), _ptr(vhat),
+                 _ptr(kappa), _stream()), "fkr_variance_full" if H is not None else "fkr_variance")
         return sigma2, (vhat if mode == "log" else None), (kappa if mode == "log" else None)
 
     # -- full bandwidth matrices ----------------------------------------

@@ -189,3 +189,30 @@ def test_full_h_interval_matches_oracle(orc, prec, tprec):
     d2 = plan.interval(tuple(np.sqrt(np.diag(Hd))), 0.3)["Sigma"].cpu().numpy()
     fin = np.isfinite(d2)
     assert rel_err(d1, d2, fin) < (1e-10 if prec == "fp64" else 1e-5)
+
+
+def test_full_h_variance_pass_matches_oracle(orc):
+    """The conditional-variance pass (Sec. 3, eq. 23-26) with the second fit
+    at a full bandwidth matrix, after the fit at that matrix: against the
+    oracle's pass (the same residuals from the GPU fit)."""
+    d, order, M, N = 2, 1, (26, 24), 4000
+    H = np.array([[0.012, 0.005], [0.005, 0.016]])
+    hmin, hmax = _h_range(H)
+    rng = np.random.default_rng(1030)
+    X = rng.random((N, d))
+    y = X[:, 0] ** 2 + (0.2 + 0.5 * X[:, 1]) * rng.standard_normal(N)
+    plan = make_plan(d, order, M, hmin, hmax, 1e-10, "fp64", n_max=N, max_weights=2)
+    plan.set_points(to_dev(X))
+    Y = to_dev(y[:, None])
+    mh = plan.fit_full(H, Y)[0, 0]
+    lo, hi = (0.0,) * d, (1.0,) * d
+    yhat = orc.interp(mh.cpu().numpy(), M, lo, hi, X)
+    gp = orc.grid_points(M, lo, hi)
+    fin = np.isfinite(orc.fit_full(X, y, H, order, gp)[0][:, 0])
+    for mode in ("log", "direct"):
+        s2 = plan.variance(None, Y, mh, mode=mode, H=H)[0].cpu().numpy()
+        ref, _ = orc.variance(X, y, yhat, None, order, M, lo, hi, mode=mode, H=H)
+        ok = fin & np.isfinite(ref) & np.isfinite(s2)
+        err = rel_err(s2, ref, ok)
+        print(f"full-H variance pass {mode}: rel err {err:.2e} over {ok.sum()} points")
+        assert ok.sum() > 0.9 * fin.sum() and err < 1e-8

@@ -403,6 +403,22 @@ def test_variance_constant_residuals(orc, order):
     assert np.allclose(s2d, c, rtol=1e-10)
 
 
+def test_variance_full_h_diagonal_equals_product_kernel(orc):
+    """The second pass with a diagonal full bandwidth matrix equals the
+    product-kernel pass at h = sqrt(diag H) (both modes)."""
+    rng = np.random.default_rng(31)
+    N = 400
+    X = rng.random((N, 2))
+    y = X[:, 0] + (0.2 + 0.5 * X[:, 1]) * rng.standard_normal(N)
+    M, lo, hi = (9, 8), (0.0, 0.0), (1.0, 1.0)
+    h = np.array([0.15, 0.2])
+    yhat = orc.interp(orc.fit(X, y, h, 1, orc.grid_points(M, lo, hi))[:, 0], M, lo, hi, X)
+    for mode in ("log", "direct"):
+        a, _ = orc.variance(X, y, yhat, h, 1, M, lo, hi, mode=mode)
+        b, _ = orc.variance(X, y, yhat, None, 1, M, lo, hi, mode=mode, H=np.diag(h ** 2))
+        np.testing.assert_allclose(b, a, rtol=1e-10)
+
+
 def test_variance_log_linear_reproduction(orc):
     """If log(r + 1/N) is linear in x, the local-linear v reproduces it."""
     rng = np.random.default_rng(51)
