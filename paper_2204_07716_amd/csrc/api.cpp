@@ -1048,26 +1048,12 @@ fkr_status interval_impl(fkr_plan* p, const double* h, const double* H, int sig_
     // full H: the squared kernel is K_{H/2} (4 pi)^{-d/2} |H|^{-1/2}
     FullH fh{}, fh2{};
     double heff[3] = {0.0, 0.0, 0.0}, heff2[3] = {0.0, 0.0, 0.0};
-    double detH = 1.0;
     if (H) {
         const int dd = p->d * p->d;
         std::vector<double> Hh(dd);
         for (int k = 0; k < dd; ++k) Hh[k] = 0.5 * H[k];
         if ((st = build_full(p, H, &fh, heff)) != FKR_OK) return st;
         if (build_full(p, Hh.data(), &fh2, heff2) != FKR_OK) return FKR_E_ARG;
-        // |H| from its Cholesky factor (H = L L^T, positive definite: build_full checked)
-        double Lc[3][3] = {};
-        for (int c = 0; c < p->d; ++c) {
-            double v = H[c * p->d + c];
-            for (int q = 0; q < c; ++q) v -= Lc[c][q] * Lc[c][q];
-            Lc[c][c] = std::sqrt(v);
-            detH *= v;
-            for (int b = c + 1; b < p->d; ++b) {
-                double u = H[b * p->d + c];
-                for (int q = 0; q < c; ++q) u -= Lc[b][q] * Lc[c][q];
-                Lc[b][c] = u / Lc[c][c];
-            }
-        }
     } else {
         for (int j = 0; j < p->d; ++j) h2[j] = compact ? h[j] : h[j] / std::sqrt(2.0);
         if (check_h(p, 1, h2) != FKR_OK) return FKR_E_ARG;
@@ -1092,9 +1078,10 @@ fkr_status interval_impl(fkr_plan* p, const double* h, const double* H, int sig_
     // staged as the weights of a spread
     IntervalArgs iv{};
     double scale = 1.0;
-    if (H)
-        scale = std::pow(4.0 * M_PI, -0.5 * p->d) / std::sqrt(detH);
-    else
+    if (H) {
+        scale = std::pow(4.0 * M_PI, -0.5 * p->d);
+        for (int j = 0; j < p->d; ++j) scale /= heff[j];   // prod_j heff_j = |H|^{1/2}
+    } else
         for (int j = 0; j < p->d; ++j) scale *= compact ? 1.0 / h[j] : 1.0 / (2.0 * std::sqrt(M_PI) * h[j]);
     // the squared kernel's channels: at h / sqrt 2 (tagged as the density
     // moments there), at H / 2, or a compact kernel's square at h (neither
