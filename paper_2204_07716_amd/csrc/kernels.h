@@ -61,6 +61,7 @@ struct ExpandArgs {
     int deriv_dim;           // >= 0: the multipliers' derivative in log h of this dimension
     const double* ktab;      // compact kernels: per dim [kdeg][B_j] multipliers (else null: the Gaussian)
     int kdeg;                // degrees in ktab (2 l + 1)
+    int cpr;                 // channel pairs per workgroup row (set by the launcher)
 };
 
 // Moment multipliers of the Gaussian with a full bandwidth matrix H: the

@@ -1486,13 +1486,12 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
 // pair spectra Z_p = C_{2p} + i C_{2p+1}, and channel pair c is
 // X_{2c} + i X_{2c+1}.
 // ---------------------------------------------------------------------------
-// One thread per band index n: workgroup row blockIdx.y forms channel pairs
-// blockIdx.y, blockIdx.y + gridDim.y, ..  The thread reads the pair spectra
-// at n and at its mirror once (the pairs of one band index are adjacent) and
-// keeps the unpacked real-weight spectra C_r(n) and its moment multipliers
-// (one exponential per dimension, the degrees by the Hermite recurrence) in
-// LDS (the first kExpandCols real weights; later ones are unpacked from the
-// pair spectra where a channel needs them).
+// One thread per band index n: workgroup row blockIdx.y forms the channel
+// pairs [y cpr, (y + 1) cpr), whose real weights (at most kExpandCols, the
+// launcher sizes the rows) it reads once from the pair spectra at n and at
+// its mirror (the pairs of one band index are adjacent), keeping the
+// unpacked real-weight spectra C_r(n) and its moment multipliers (one
+// exponential per dimension, the degrees by the Hermite recurrence) in LDS.
 constexpr int kExpandThreads = 128;
 constexpr int kExpandCols = 16;
 constexpr int kExpandDeg = 5;   // moment degrees per dimension (<= 2 l = 4)
@@ -1535,40 +1534,36 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
 #pragma unroll
         for (int k = 0; k < kExpandDeg; ++k) mloc[j][k][tid] = (dj ? -u * he[k + 1] : he[k]) * gj;
     }
+    // the row's channel pairs [c_lo, c_hi) and the real weights they use,
+    // r of channel ch: 0 for the s-channels, then n_t channels per weight
+    const int c_lo = (int)blockIdx.y * a.cpr, c_hi = min(a.ncp, c_lo + a.cpr);
+    auto weight_of = [&](int ch) { return ch < a.n_s ? 0 : 1 + (ch - a.n_s) / a.n_t; };
+    const int p_lo = weight_of(2 * c_lo) >> 1;
+    const int p_hi = min(a.npairs - 1, weight_of(min(2 * c_hi, a.nreal) - 1) >> 1);   // p_hi - p_lo < kExpandCols / 2
     // real weight spectra C_r(n), r = 2 p + half, from Z_p(n) and Z_p(-n)
-    const int np_lds = min(a.npairs, kExpandCols / 2);
-    for (int p = 0; p < np_lds; ++p) {
+    // (a thread reads its band index's adjacent pairs: whole cache lines)
+    for (int p = p_lo; p <= p_hi; ++p) {
         const typename V2<T>::t zn = spec[n * a.npairs + p];
         const typename V2<T>::t zm = spec[(int64_t)nn * a.npairs + p];
-        cw[2 * p][tid] = make_double2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
-        cw[2 * p + 1][tid] = make_double2(0.5 * ((double)zn.y + (double)zm.y), -0.5 * ((double)zn.x - (double)zm.x));
+        const int q = 2 * (p - p_lo);
+        cw[q][tid] = make_double2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
+        cw[q + 1][tid] = make_double2(0.5 * ((double)zn.y + (double)zm.y), -0.5 * ((double)zn.x - (double)zm.x));
     }
     const int c_first = (skip_flag && *skip_flag) ? (int)c_keep : 0;
-    for (int c = (int)blockIdx.y; c < a.ncp; c += (int)gridDim.y) {
-        if (c < c_first) continue;
+    for (int c = max(c_lo, c_first); c < c_hi; ++c) {
         double acc_re = 0.0, acc_im = 0.0;
         for (int half = 0; half < 2; ++half) {
             const int ch = 2 * c + half;
             if (ch >= a.nreal) break;
-            int r;
-            const int* ex;
-            if (ch < a.n_s) { r = 0; ex = es + 3 * ch; }
-            else { r = 1 + (ch - a.n_s) / a.n_t; ex = et + 3 * ((ch - a.n_s) % a.n_t); }
+            const int r = weight_of(ch);
+            const int* ex = ch < a.n_s ? es + 3 * ch : et + 3 * ((ch - a.n_s) % a.n_t);
             double m = 1.0;
             int deg = 0;
             for (int j = 0; j < a.d; ++j) {
                 m *= mloc[j][ex[j]][tid];
                 deg += ex[j];
             }
-            double2 cr;
-            if (r < kExpandCols) {
-                cr = cw[r][tid];
-            } else {
-                const typename V2<T>::t zn = spec[n * a.npairs + (r >> 1)];
-                const typename V2<T>::t zm = spec[(int64_t)nn * a.npairs + (r >> 1)];
-                if ((r & 1) == 0) cr = make_double2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
-                else cr = make_double2(0.5 * ((double)zn.y + (double)zm.y), -0.5 * ((double)zn.x - (double)zm.x));
-            }
+            const double2 cr = cw[r - 2 * p_lo][tid];
             double xr = cr.x * m, xi = cr.y * m;
             switch (deg & 3) {   // multiply by i^deg
                 case 1: { const double t0 = xr; xr = -xi; xi = t0; break; }
@@ -1779,14 +1774,28 @@ void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const in
 
 void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,
                    const long long* skip_flag, int64_t c_keep, hipStream_t s) {
-    // up to four workgroup rows of channel pairs (more waves for few band indices)
-    const dim3 nbn((unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads),
-                   (unsigned)std::min(4, std::max(1, a.ncp)));
+    // workgroup rows of contiguous channel pairs: at least four (more waves
+    // for few band indices), and enough that each row's channels use at most
+    // kExpandCols real weights (their spectra staged in LDS)
+    ExpandArgs b = a;
+    auto weight_of = [&](int ch) { return ch < a.n_s ? 0 : 1 + (ch - a.n_s) / a.n_t; };
+    auto pair_span = [&](int c_lo, int c_hi) {
+        return (weight_of(std::min(2 * c_hi, a.nreal) - 1) >> 1) - (weight_of(2 * c_lo) >> 1) + 1;
+    };
+    int rows = std::min(4, std::max(1, a.ncp));
+    for (;;) {
+        const int cpr = (a.ncp + rows - 1) / rows;
+        bool fits = true;
+        for (int c = 0; c < a.ncp && fits; c += cpr) fits = pair_span(c, std::min(a.ncp, c + cpr)) <= kExpandCols / 2;
+        if (fits || cpr == 1) { b.cpr = cpr; rows = (a.ncp + cpr - 1) / cpr; break; }
+        ++rows;
+    }
+    const dim3 nbn((unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads), (unsigned)std::max(1, rows));
     if (prec == FKR_F64)
-        k_expand_n<double><<<nbn, kExpandThreads, 0, s>>>(a, es, et, static_cast<const double2*>(spec),
+        k_expand_n<double><<<nbn, kExpandThreads, 0, s>>>(b, es, et, static_cast<const double2*>(spec),
                                                           static_cast<double2*>(out), skip_flag, c_keep);
     else
-        k_expand_n<float><<<nbn, kExpandThreads, 0, s>>>(a, es, et, static_cast<const float2*>(spec),
+        k_expand_n<float><<<nbn, kExpandThreads, 0, s>>>(b, es, et, static_cast<const float2*>(spec),
                                                          static_cast<float2*>(out), skip_flag, c_keep);
 }
 
