@@ -1487,20 +1487,17 @@ __global__ __launch_bounds__(1024) void k_fft(const typename V2<T>::t* __restric
 // X_{2c} + i X_{2c+1}.
 // ---------------------------------------------------------------------------
 // One thread per band index n: workgroup row blockIdx.y forms the channel
-// pairs [y cpr, (y + 1) cpr), whose real weights (at most kExpandCols, the
-// launcher sizes the rows) it reads once from the pair spectra at n and at
-// its mirror (the pairs of one band index are adjacent), keeping the
-// unpacked real-weight spectra C_r(n) and its moment multipliers (one
-// exponential per dimension, the degrees by the Hermite recurrence) in LDS.
+// pairs [y cpr, (y + 1) cpr) in weight order, reading each weight pair's
+// spectra at n and at its mirror once (the pairs of one band index are
+// adjacent); its moment multipliers (one exponential per dimension, the
+// degrees by the Hermite recurrence) are kept in LDS.
 constexpr int kExpandThreads = 128;
-constexpr int kExpandCols = 16;
 constexpr int kExpandDeg = 5;   // moment degrees per dimension (<= 2 l = 4)
 template <typename T>
 __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const int* es, const int* et,
                                                              const typename V2<T>::t* spec,
                                                              typename V2<T>::t* out, const long long* skip_flag,
                                                              int64_t c_keep) {
-    __shared__ double2 cw[kExpandCols][kExpandThreads];
     __shared__ double mloc[3][kExpandDeg][kExpandThreads];
     const int tid = threadIdx.x;
     const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
@@ -1538,17 +1535,10 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
     // r of channel ch: 0 for the s-channels, then n_t channels per weight
     const int c_lo = (int)blockIdx.y * a.cpr, c_hi = min(a.ncp, c_lo + a.cpr);
     auto weight_of = [&](int ch) { return ch < a.n_s ? 0 : 1 + (ch - a.n_s) / a.n_t; };
-    const int p_lo = weight_of(2 * c_lo) >> 1;
-    const int p_hi = min(a.npairs - 1, weight_of(min(2 * c_hi, a.nreal) - 1) >> 1);   // p_hi - p_lo < kExpandCols / 2
-    // real weight spectra C_r(n), r = 2 p + half, from Z_p(n) and Z_p(-n)
-    // (a thread reads its band index's adjacent pairs: whole cache lines)
-    for (int p = p_lo; p <= p_hi; ++p) {
-        const typename V2<T>::t zn = spec[n * a.npairs + p];
-        const typename V2<T>::t zm = spec[(int64_t)nn * a.npairs + p];
-        const int q = 2 * (p - p_lo);
-        cw[q][tid] = make_double2(0.5 * ((double)zn.x + (double)zm.x), 0.5 * ((double)zn.y - (double)zm.y));
-        cw[q + 1][tid] = make_double2(0.5 * ((double)zn.y + (double)zm.y), -0.5 * ((double)zn.x - (double)zm.x));
-    }
+    // the channels run in weight order, so the thread keeps one pair's
+    // spectra Z_p(n), Z_p(-n) in registers and reads each pair once
+    int cur_p = -1;
+    double2 zn = make_double2(0.0, 0.0), zm = make_double2(0.0, 0.0);
     const int c_first = (skip_flag && *skip_flag) ? (int)c_keep : 0;
     for (int c = max(c_lo, c_first); c < c_hi; ++c) {
         double acc_re = 0.0, acc_im = 0.0;
@@ -1563,7 +1553,16 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
                 m *= mloc[j][ex[j]][tid];
                 deg += ex[j];
             }
-            const double2 cr = cw[r - 2 * p_lo][tid];
+            if ((r >> 1) != cur_p) {
+                cur_p = r >> 1;
+                const typename V2<T>::t a0 = spec[n * a.npairs + cur_p];
+                const typename V2<T>::t a1 = spec[(int64_t)nn * a.npairs + cur_p];
+                zn = make_double2((double)a0.x, (double)a0.y);
+                zm = make_double2((double)a1.x, (double)a1.y);
+            }
+            // real weight spectrum C_r(n), r = 2 p + half, from Z_p(n) and Z_p(-n)
+            const double2 cr = (r & 1) == 0 ? make_double2(0.5 * (zn.x + zm.x), 0.5 * (zn.y - zm.y))
+                                            : make_double2(0.5 * (zn.y + zm.y), -0.5 * (zn.x - zm.x));
             double xr = cr.x * m, xi = cr.y * m;
             switch (deg & 3) {   // multiply by i^deg
                 case 1: { const double t0 = xr; xr = -xi; xi = t0; break; }
@@ -1775,21 +1774,12 @@ void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const in
 void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,
                    const long long* skip_flag, int64_t c_keep, hipStream_t s) {
     // workgroup rows of contiguous channel pairs: at least four (more waves
-    // for few band indices), and enough that each row's channels use at most
-    // kExpandCols real weights (their spectra staged in LDS)
+    // for few band indices), at most eight pairs each
     ExpandArgs b = a;
-    auto weight_of = [&](int ch) { return ch < a.n_s ? 0 : 1 + (ch - a.n_s) / a.n_t; };
-    auto pair_span = [&](int c_lo, int c_hi) {
-        return (weight_of(std::min(2 * c_hi, a.nreal) - 1) >> 1) - (weight_of(2 * c_lo) >> 1) + 1;
-    };
-    int rows = std::min(4, std::max(1, a.ncp));
-    for (;;) {
-        const int cpr = (a.ncp + rows - 1) / rows;
-        bool fits = true;
-        for (int c = 0; c < a.ncp && fits; c += cpr) fits = pair_span(c, std::min(a.ncp, c + cpr)) <= kExpandCols / 2;
-        if (fits || cpr == 1) { b.cpr = cpr; rows = (a.ncp + cpr - 1) / cpr; break; }
-        ++rows;
-    }
+    const int ncp = std::max(1, a.ncp);
+    int rows = std::max(std::min(4, ncp), (ncp + 7) / 8);
+    b.cpr = (ncp + rows - 1) / rows;
+    rows = (ncp + b.cpr - 1) / b.cpr;
     const dim3 nbn((unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads), (unsigned)std::max(1, rows));
     if (prec == FKR_F64)
         k_expand_n<double><<<nbn, kExpandThreads, 0, s>>>(b, es, et, static_cast<const double2*>(spec),
