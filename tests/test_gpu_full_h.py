@@ -216,3 +216,38 @@ def test_full_h_variance_pass_matches_oracle(orc):
         err = rel_err(s2, ref, ok)
         print(f"full-H variance pass {mode}: rel err {err:.2e} over {ok.sum()} points")
         assert ok.sum() > 0.9 * fin.sum() and err < 1e-8
+
+
+def test_full_h_argument_errors():
+    """The full-H calls refuse what they cannot serve before enqueuing work:
+    a non-symmetric or indefinite H, an H outside the plan's bandwidth range,
+    more matrices than the plan holds (FKR_E_ARG); a compact kernel
+    (FKR_E_UNSUPPORTED)."""
+    from paper_2204_07716_amd._lib import FKR_E_ARG, FKR_E_UNSUPPORTED, FkrError
+    N = 500
+    X = np.random.default_rng(5).random((N, 2))
+    H = np.array([[0.010, 0.004], [0.004, 0.012]])
+    hmin, hmax = _h_range(H / 2)[0], _h_range(H)[1]
+    plan = make_plan(2, 1, (24, 24), hmin, hmax, 1e-6, "fp64", n_max=N, max_weights=4, max_h=1)
+    plan.set_points(to_dev(X))
+    Y = to_dev(np.sin(X[:, 0])[:, None])
+    bad = [np.array([[0.010, 0.004], [0.001, 0.012]]),            # not symmetric
+           np.array([[0.010, 0.012], [0.012, 0.012]]),            # not positive definite
+           4.0 * H]                                               # wider than the plan's h_max
+    for B in bad:
+        for call in (lambda: plan.cv_full(B, Y, 2), lambda: plan.interval(None, 0.1, H=B),
+                     lambda: plan.fit_full(B, Y)):
+            with pytest.raises(FkrError) as e:
+                call()
+            assert e.value.status == FKR_E_ARG
+    with pytest.raises(FkrError) as e:
+        plan.cv_full(np.stack([H, H]), Y, 2)                      # max_h = 1
+    assert e.value.status == FKR_E_ARG
+    pc = make_plan(2, 1, (24, 24), hmin, hmax, 1e-6, "fp64", n_max=N, max_weights=4, reg_kernel="epanechnikov")
+    pc.set_points(to_dev(X))
+    mh = torch.zeros(24 * 24, dtype=torch.float64, device="cuda")
+    for call in (lambda: pc.cv_full(H, Y, 2), lambda: pc.interval(None, 0.1, H=H),
+                 lambda: pc.variance(None, Y, mh, H=H)):
+        with pytest.raises(FkrError) as e:
+            call()
+        assert e.value.status == FKR_E_UNSUPPORTED
