@@ -664,6 +664,28 @@ def gcv_log_h_gradient(X, y, h, order, M, lo, hi, Wp, include=None, step: float 
     return out
 
 
+def gcv_H_gradient(X, y, H, order, M, lo, hi, Wp, include=None, step: float = 1e-4) -> np.ndarray:
+    """d GCV / d H_pq (p <= q, row-major upper triangle; an off-diagonal
+    entry moves H_pq and H_qp together) at a full bandwidth matrix, by
+    central differences of ``gcv_criterion`` with step * H_pq' where
+    H_pq' = sqrt(H_pp H_qq), with the supported set held at that of H."""
+    X = np.asarray(X, dtype=np.float64).reshape(len(y), -1)
+    d = X.shape[1]
+    H = np.asarray(H, dtype=np.float64).reshape(d, d)
+    if include is None:
+        include = support(X, None, order, M, lo, hi, H=H)[0]
+    out = []
+    for p in range(d):
+        for q in range(p, d):
+            E = np.zeros((d, d))
+            E[p, q] = E[q, p] = 1.0
+            eps = step * np.sqrt(H[p, p] * H[q, q])
+            gp_ = gcv_criterion(X, y, None, order, M, lo, hi, Wp, include, H=H + eps * E)
+            gm_ = gcv_criterion(X, y, None, order, M, lo, hi, Wp, include, H=H - eps * E)
+            out.append((gp_ - gm_) / (2.0 * eps))
+    return np.array(out)
+
+
 def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None, binned=None) -> np.ndarray:
     """d GCV / dy of ``gcv_criterion`` from its definition: the fitted
     values are yhat = S y with the smoother S (samples to samples through the

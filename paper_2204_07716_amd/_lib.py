@@ -49,7 +49,7 @@ class Diag(ctypes.Structure):
 
 EXPORTS = ["fkr_plan_create", "fkr_plan_destroy", "fkr_plan_geometry", "fkr_workspace_size",
            "fkr_set_workspace", "fkr_set_points", "fkr_spectrum", "fkr_moments", "fkr_fit", "fkr_fit_noalloc",
-           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_variance_full", "fkr_interval", "fkr_interval_full", "fkr_gcv_grad", "fkr_fit_full", "fkr_cv_full", "fkr_moments_full", "fkr_spline",
+           "fkr_interp", "fkr_dof", "fkr_cv", "fkr_gcv", "fkr_variance", "fkr_variance_full", "fkr_interval", "fkr_interval_full", "fkr_gcv_grad", "fkr_gcv_grad_full", "fkr_fit_full", "fkr_cv_full", "fkr_moments_full", "fkr_spline",
            "fkr_predict", "fkr_get_diagnostics",
            "fkr_status_string", "fkr_hlist", "fkr_select_bandwidth", "fkr_profile_enable",
            "fkr_profile_read", "fkr_batch_create", "fkr_batch_destroy", "fkr_batch_workspace_size",
@@ -102,6 +102,7 @@ def load() -> ctypes.CDLL:
         "fkr_cv_full": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P, P], I),
         "fkr_moments_full": ([P, I, pD, I, P, I, P, P, P], I),
         "fkr_gcv_grad": ([P, pD, I, P, I, I, U64, P, P, P, P, P], I),
+        "fkr_gcv_grad_full": ([P, pD, I, P, I, I, U64, P, P, P, P], I),
         "fkr_predict": ([P, I, P, I64, P, I, P, P], I),
         "fkr_get_diagnostics": ([P, ctypes.POINTER(Diag)], I),
         "fkr_status_string": ([I], ctypes.c_char_p),

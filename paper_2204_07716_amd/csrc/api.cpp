@@ -1251,20 +1251,31 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
 }
 
-fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type, int Np,
-                        uint64_t seed, double* gcv, double* dlogh, double* dy, double* dfit, void* stream) {
-    fkr_status st = common_fit_checks(p, 1, h, 1, y_complex, Y, y_type);
+// GCV and its gradient: in log h_j at a diagonal bandwidth h (nd = d
+// directions), or (H non-null) in the upper-triangle entries H_pq, p <= q,
+// row-major, of a full bandwidth matrix (nd = d (d + 1) / 2; an
+// off-diagonal entry moves H_pq and H_qp together).
+fkr_status grad_impl(fkr_plan* p, const double* h, const double* H, int y_complex, const void* Y, int y_type,
+                     int Np, uint64_t seed, double* gcv, double* dtheta, double* dy, double* dfit, void* stream) {
+    fkr_status st = ready(p);
     if (st != FKR_OK) return st;
-    if (Np < 1 || !dlogh || !dfit) return FKR_E_ARG;
+    if (!H && (st = check_h(p, 1, h)) != FKR_OK) return st;
+    if ((!Y && p->N > 0) || (y_complex != 0 && y_complex != 1) || !valid_type(y_type)) return FKR_E_ARG;
+    if (Np < 1 || !dtheta || !dfit) return FKR_E_ARG;
     // the box kernel's steps at the support's edge have no derivative in h
     if (p->reg_kernel == FKR_REG_BOX) return FKR_E_UNSUPPORTED;
+    if (H && (p->reg_kernel || dy)) return FKR_E_UNSUPPORTED;   // full H: Gaussian, gradient in H only
+    FullH fh{};
+    double heff[3] = {0.0, 0.0, 0.0};
+    if (H && (st = build_full(p, H, &fh, heff)) != FKR_OK) return st;
+    const int nd = H ? p->d * (p->d + 1) / 2 : p->d;
     const int ny = y_complex ? 2 : 1;
     if (ny + Np > kGradCols) return FKR_E_ARG;
     const int nr = 1 + ny + Np;
     const int ncp = (p->n_s + p->n_t * (nr - 1) + 1) / 2;
     const int n_items = 1 + Np;          // base sums: the response (|r|^2), then the probes
-    const int ncol = ny + Np;            // gradient sums per dimension
-    const int nslot = p->d * ncol;
+    const int ncol = ny + Np;            // gradient sums per direction
+    const int nslot = nd * ncol;
     // the channels at h and their derivatives side by side; the gradient sums
     // after the base sums
     if (nr > p->max_weights || 2 * ncp > p->ncp_max) return FKR_E_ARG;
@@ -1274,7 +1285,7 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
     // base pass: fit, DF and GCV at h (spectra, channels in pairs [0, ncp),
     // support flags, the fit of y, the sums)
     if ((st = cv_impl(p, 1, h, 1, y_complex, Y, y_type, Np, seed, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, nullptr, s)) != FKR_OK)
+                      nullptr, nullptr, s, H ? &fh : nullptr, H ? heff : nullptr)) != FKR_OK)
         return st;
     if (dy) {
         StageTimer t(p, FKR_STAGE_REDUCE, s);
@@ -1286,8 +1297,22 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
     double* partial = at<double>(p, p->lay.partial);
     const float* sup = at<float>(p, p->lay.sup);
     const size_t pair_bytes = (size_t)p->Mtot * 2 * elem_size(p->tprec);
-    for (int j = 0; j < p->d; ++j) {
-        if ((st = run_channels(p, h, nr, nullptr, s, false, 2, j, ncp)) != FKR_OK) return st;
+    for (int j = 0; j < nd; ++j) {
+        if (H) {
+            // direction j: the j-th upper-triangle entry (pq), symmetric
+            int pp = 0, qq = 0, k = j;
+            while (k >= p->d - pp) { k -= p->d - pp; ++pp; }
+            qq = pp + k;
+            FullH fd = fh;
+            fd.deriv = 1;
+            for (int e = 0; e < 9; ++e) fd.dH[e] = 0.0;
+            fd.dH[3 * pp + qq] = 1.0;
+            fd.dH[3 * qq + pp] = 1.0;
+            st = run_channels(p, fh.s, nr, nullptr, s, false, 2, -1, ncp, &fd);
+        } else {
+            st = run_channels(p, h, nr, nullptr, s, false, 2, j, ncp);
+        }
+        if (st != FKR_OK) return st;
         DSolveArgs a{};
         a.P = p->n_t; a.n_s = p->n_s; a.n_t = p->n_t; a.ncp = ncp; a.nr = nr;
         a.Mtot = p->Mtot;
@@ -1319,9 +1344,21 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
         }
     }
     launch_reduce_final(partial, nslot, gred, s);
-    launch_finalize_grad(p->d, ny, Np, red, gred, gcv, dlogh, s);
+    launch_finalize_grad(nd, ny, Np, red, gred, gcv, dtheta, s);
     p->last_stream = stream;
     return hipGetLastError() == hipSuccess ? FKR_OK : FKR_E_DEVICE;
+}
+
+fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void* Y, int y_type, int Np,
+                        uint64_t seed, double* gcv, double* dlogh, double* dy, double* dfit, void* stream) {
+    if (!h) return FKR_E_ARG;
+    return grad_impl(p, h, nullptr, y_complex, Y, y_type, Np, seed, gcv, dlogh, dy, dfit, stream);
+}
+
+fkr_status fkr_gcv_grad_full(fkr_plan* p, const double* H, int y_complex, const void* Y, int y_type, int Np,
+                             uint64_t seed, double* gcv, double* dH, double* dfit, void* stream) {
+    if (!H) return FKR_E_ARG;
+    return grad_impl(p, nullptr, H, y_complex, Y, y_type, Np, seed, gcv, dH, nullptr, dfit, stream);
 }
 
 fkr_status fkr_spline(fkr_plan* p, int nv, const double* G, double* coef, void* stream) {

@@ -75,6 +75,10 @@ struct FullH {
     double H[9];
     double s[3];
     int rj[kMaxChannels], rb[kMaxChannels], rbk[kMaxChannels][3];
+    // deriv != 0: the multipliers' derivative along the symmetric direction
+    // dH (the channels d/dtheta of the equilibrated moments, H + theta dH)
+    int deriv;
+    double dH[9];
 };
 
 // Derivative of the fits in log h_j (one dimension per launch), per grid

@@ -1584,11 +1584,17 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
 // the multipliers of all s-channels by the multivariate Hermite recurrence
 // into LDS, then every channel pair of the launch (t-channel b uses the
 // s-channel of b; the weight spectra are unpacked from the pair spectra).
-template <typename T>
+// DER: the derivative along fh.dH of every multiplier M_c = m_c G / sc_c
+// (m_c the Hermite recurrence, G = exp(-w^T H w / 2) / prod T, sc_c the
+// equilibration prod_k s_k^{a_k}, s_k = sqrt(H_kk)), by forward
+// differentiation of the recurrence: dM_c = (G / sc_c) (dm_c - m_c
+// (w^T dH w / 2 + sum_k a_k dH_kk / (2 H_kk))).
+template <typename T, bool DER>
 __global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, FullH fh, const int* es,
                                                                 const int* pidx, const typename V2<T>::t* spec,
                                                                 typename V2<T>::t* out) {
     __shared__ double mf[kMaxChannels][kExpandThreads];
+    __shared__ double dmf[DER ? kMaxChannels : 1][kExpandThreads];
     const int tid = threadIdx.x;
     const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && a.ill_clear) *a.ill_clear = 0ull;
@@ -1612,21 +1618,42 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, Fu
         q += w[j] * z[j];
     }
     const double G = exp(-0.5 * q) / tprod;
+    double dz[3] = {0.0, 0.0, 0.0}, dq = 0.0;
+    if constexpr (DER) {
+        for (int j = 0; j < a.d; ++j) {
+            for (int k = 0; k < a.d; ++k) dz[j] += fh.dH[3 * j + k] * w[k];
+            dq += w[j] * dz[j];
+        }
+        dmf[0][tid] = 0.0;
+    }
     mf[0][tid] = 1.0;
     for (int c = 1; c < a.n_s; ++c) {
         const int j = fh.rj[c];
         double v = z[j] * mf[fh.rb[c]][tid];
+        double dv = 0.0;
+        if constexpr (DER) dv = dz[j] * mf[fh.rb[c]][tid] + z[j] * dmf[fh.rb[c]][tid];
         for (int k = 0; k < a.d; ++k) {
             const int bk = fh.rbk[c][k];
-            if (bk >= 0) v -= (double)es[3 * fh.rb[c] + k] * fh.H[3 * j + k] * mf[bk][tid];
+            if (bk >= 0) {
+                const double bkk = (double)es[3 * fh.rb[c] + k];
+                v -= bkk * fh.H[3 * j + k] * mf[bk][tid];
+                if constexpr (DER) dv -= bkk * (fh.dH[3 * j + k] * mf[bk][tid] + fh.H[3 * j + k] * dmf[bk][tid]);
+            }
         }
         mf[c][tid] = v;
+        if constexpr (DER) dmf[c][tid] = dv;
     }
     for (int c = 0; c < a.n_s; ++c) {
-        double sc = 1.0;
+        double sc = 1.0, dls = 0.0;   // dls: d log(sc) along dH
         for (int k = 0; k < a.d; ++k)
-            for (int e = 0; e < es[3 * c + k]; ++e) sc *= fh.s[k];
-        mf[c][tid] *= G / sc;
+            for (int e = 0; e < es[3 * c + k]; ++e) {
+                sc *= fh.s[k];
+                if constexpr (DER) dls += 0.5 * fh.dH[4 * k] / fh.H[4 * k];
+            }
+        if constexpr (DER)
+            mf[c][tid] = G / sc * (dmf[c][tid] - mf[c][tid] * (0.5 * dq + dls));
+        else
+            mf[c][tid] *= G / sc;
     }
     for (int c = (int)blockIdx.y; c < a.ncp; c += (int)gridDim.y) {
         double acc_re = 0.0, acc_im = 0.0;
@@ -1763,12 +1790,14 @@ void launch_expand_full(int prec, const ExpandArgs& a, const FullH& fh, const in
                         const void* spec, void* out, hipStream_t s) {
     const dim3 nbn((unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads),
                    (unsigned)std::min(4, std::max(1, a.ncp)));
-    if (prec == FKR_F64)
-        k_expand_full<double><<<nbn, kExpandThreads, 0, s>>>(a, fh, es, pidx, static_cast<const double2*>(spec),
-                                                             static_cast<double2*>(out));
-    else
-        k_expand_full<float><<<nbn, kExpandThreads, 0, s>>>(a, fh, es, pidx, static_cast<const float2*>(spec),
-                                                            static_cast<float2*>(out));
+#define FKR_EXF(T, D) k_expand_full<T, D><<<nbn, kExpandThreads, 0, s>>>(a, fh, es, pidx, \
+        static_cast<const typename V2<T>::t*>(spec), static_cast<typename V2<T>::t*>(out))
+    if (prec == FKR_F64) {
+        if (fh.deriv) FKR_EXF(double, true); else FKR_EXF(double, false);
+    } else {
+        if (fh.deriv) FKR_EXF(float, true); else FKR_EXF(float, false);
+    }
+#undef FKR_EXF
 }
 
 void launch_expand(int prec, const ExpandArgs& a, const int* es, const int* et, const void* spec, void* out,

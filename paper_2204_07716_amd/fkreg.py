@@ -454,6 +454,23 @@ class Plan:
             dy = torch.view_as_complex(dy) if cplx else dy[:, 0]
         return {"gcv": gcv, "dlogh": dlogh, "dy": dy, "dfit": dfit}
 
+    def gcv_grad_full(self, H, Y: torch.Tensor, Np: int, seed: int = 0) -> dict:
+        """GCV at the full bandwidth matrix H (d x d) for one response with Np
+        Philox probes, its gradient in the upper-triangle entries H_pq (p <= q,
+        row-major), and d m_hat / d H_pq of y and the probes."""
+        Hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(self.d, self.d))
+        Yr, q, cplx = _real_view(Y.reshape(-1, 1))
+        assert q == 1, "one response column"
+        ny = 2 if cplx else 1
+        nd = self.d * (self.d + 1) // 2
+        gcv = torch.empty(1, dtype=torch.float64, device=self.device)
+        dH = torch.empty(nd, dtype=torch.float64, device=self.device)
+        dfit = torch.empty((nd, ny + Np, self.Mtot), dtype=torch.float64, device=self.device)
+        check(self.lib.fkr_gcv_grad_full(self._plan, _hptr(Hb), cplx, _ptr(Yr), _dtype_code(Yr), Np,
+                                         ctypes.c_uint64(seed), _ptr(gcv), _ptr(dH), _ptr(dfit), _stream()),
+              "fkr_gcv_grad_full")
+        return {"gcv": gcv, "dH": dH, "dfit": dfit}
+
     # -- prediction and inference ---------------------------------------
     def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05, H=None):
         """Variance of the fit Sigma [M] (eq. 27) for error variance sigma2 (a

@@ -251,3 +251,39 @@ def test_full_h_argument_errors():
         with pytest.raises(FkrError) as e:
             call()
         assert e.value.status == FKR_E_UNSUPPORTED
+
+
+def test_full_h_gcv_grad_matches_oracle(orc):
+    """GCV gradient in the entries of a full bandwidth matrix (the derivative
+    of the multivariate Hermite multipliers, the Gaussian factor and the
+    equilibration, then the derivative of the solve and the sums): against
+    central differences of the oracle's GCV with the same Philox probes; at a
+    diagonal H, the log-h gradient of fkr_gcv_grad over 2 H_jj."""
+    d, order, M, N, Np, seed = 2, 1, (28, 26), 2000, 4, 91
+    H = np.array([[0.012, 0.005], [0.005, 0.016]])
+    Hd = np.diag([0.011, 0.015])
+    lo_r = tuple(np.minimum(_h_range(H)[0], _h_range(Hd)[0]) * 0.99)
+    hi_r = tuple(np.maximum(_h_range(H)[1], _h_range(Hd)[1]) * 1.01)
+    rng = np.random.default_rng(1040)
+    X = rng.random((N, d))
+    y = np.sin(3 * (X[:, 0] + 0.5 * X[:, 1])) + 0.3 * rng.standard_normal(N)
+    plan = make_plan(d, order, M, lo_r, hi_r, 1e-10, "fp64", n_max=N, max_weights=16)
+    plan.set_points(to_dev(X))
+    Y = to_dev(y[:, None])
+    out = plan.gcv_grad_full(H, Y, Np, seed)
+    Wp = orc.probes(seed, N, Np)
+    lo, hi = (0.0,) * d, (1.0,) * d
+    inc = orc.support(X, None, order, M, lo, hi, H=H)[0]
+    assert inc.all()
+    ref_g = orc.gcv_criterion(X, y, None, order, M, lo, hi, Wp, inc, H=H)
+    ref = orc.gcv_H_gradient(X, y, H, order, M, lo, hi, Wp, include=inc, step=1e-4)
+    got = out["dH"].cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"full-H gradient: gcv {out['gcv'].item():.10e} / {ref_g:.10e}; dGCV/dH {got} / {ref}; rel err {err:.2e}")
+    assert out["gcv"].item() == pytest.approx(ref_g, rel=1e-9)
+    assert err < 1e-6
+    # the diagonal matrix against the log-h gradient
+    gd = plan.gcv_grad_full(Hd, Y, Np, seed)["dH"].cpu().numpy()
+    gl = plan.gcv_grad(tuple(np.sqrt(np.diag(Hd))), Y, Np, seed, want_dy=False)["dlogh"].cpu().numpy()
+    np.testing.assert_allclose([2 * Hd[0, 0] * gd[0], 2 * Hd[1, 1] * gd[2]], gl, rtol=1e-8,
+                               atol=1e-10 * np.abs(gl).max())

@@ -804,6 +804,25 @@ def test_gcv_full_h_diagonal_reduces_to_product_kernel(orc):
     assert abs(g_rot / g_diag - 1) > 1e-4
 
 
+def test_gcv_H_gradient_diagonal_matches_log_h_gradient(orc):
+    """At a diagonal H = diag(h^2) the gradient in the diagonal entries is the
+    log-h gradient over 2 H_jj (h_j = sqrt(H_jj)), by two different
+    central-difference paths; the off-diagonal derivative does not vanish
+    for a correlated response."""
+    rng = np.random.default_rng(17)
+    N = 300
+    X = rng.random((N, 2))
+    y = np.sin(3 * (X[:, 0] + X[:, 1])) + 0.2 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi = (10, 9), (0.0, 0.0), (1.0, 1.0)
+    h = np.array([0.15, 0.18])
+    inc = orc.support(X, h, 1, M, lo, hi)[0]
+    gH = orc.gcv_H_gradient(X, y, np.diag(h ** 2), 1, M, lo, hi, Wp, include=inc)
+    gl = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc)
+    np.testing.assert_allclose([gH[0] * 2 * h[0] ** 2, gH[2] * 2 * h[1] ** 2], gl, rtol=1e-5)
+    assert abs(gH[1]) > 1e-3 * np.abs(gH).max()
+
+
 def test_gcv_gradients_complex_response(orc):
     """Complex y: GCV uses |y - yhat|^2; the gradient d/dRe y + i d/dIm y
     matches central differences along the real and the imaginary axis, and
