@@ -5,6 +5,6 @@ The compute path is the HIP library ``libfkr.so`` (C ABI in include/fkr.h);
 this package is its thin Python binding.  Importing it does not load the
 library; the first ``Plan`` does, and fails loudly if it was not built.
 """
-from .fkreg import Batch, GCVLogH, Plan, get_hlist, select_bandwidth  # noqa: F401
+from .fkreg import Batch, GCVFullH, GCVLogH, Plan, get_hlist, select_bandwidth  # noqa: F401
 
-__all__ = ["Batch", "GCVLogH", "Plan", "get_hlist", "select_bandwidth"]
+__all__ = ["Batch", "GCVFullH", "GCVLogH", "Plan", "get_hlist", "select_bandwidth"]

@@ -97,6 +97,36 @@ class GCVLogH(torch.autograd.Function):
         return grad_out * dl, g_y, None, None, None
 
 
+class GCVFullH(torch.autograd.Function):
+    """GCV (eq. 22) of one real response as a function of a full bandwidth
+    matrix H (d x d, symmetric), with the library's hand-written gradient as
+    its backward: ``GCVFullH.apply(H, Y, plan, Np, seed)``.  The gradient is
+    returned as a symmetric matrix G with G_pq = dGCV/dH_pq for H_pq and H_qp
+    taken as separate entries (half the symmetric derivative off the
+    diagonal), so that a symmetric step dH changes GCV by sum(G * dH)."""
+
+    @staticmethod
+    def forward(ctx, H, Y, plan, Np, seed):
+        Hn = H.detach().to(torch.float64).cpu().numpy()
+        out = plan.gcv_grad_full(Hn, Y.detach(), Np, seed)
+        d = Hn.shape[0]
+        g = torch.zeros((d, d), dtype=torch.float64)
+        k = 0
+        dH = out["dH"].cpu()
+        for p in range(d):
+            for q in range(p, d):
+                g[p, q] = dH[k] if p == q else 0.5 * dH[k]
+                g[q, p] = g[p, q]
+                k += 1
+        ctx.save_for_backward(g.to(H.device, H.dtype))
+        return out["gcv"][0].to(H.device, H.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out * g, None, None, None, None
+
+
 def _plan_desc(d, order, M, lo, hi, h_min, h_max, eps, precision, kernel, sigma, n_max, max_weights,
                max_h, transform_precision):
     desc = _lib.PlanDesc()

@@ -287,3 +287,31 @@ def test_full_h_gcv_grad_matches_oracle(orc):
     gl = plan.gcv_grad(tuple(np.sqrt(np.diag(Hd))), Y, Np, seed, want_dy=False)["dlogh"].cpu().numpy()
     np.testing.assert_allclose([2 * Hd[0, 0] * gd[0], 2 * Hd[1, 1] * gd[2]], gl, rtol=1e-8,
                                atol=1e-10 * np.abs(gl).max())
+
+
+def test_full_h_autograd():
+    """GCVFullH through torch.autograd: the gradient of GCV(H(t)) for a
+    symmetric path H(t) = H0 + t D equals sum(G * D), checked against central
+    differences of the GPU's own GCV along D."""
+    from paper_2204_07716_amd import GCVFullH
+    d, M, N, Np, seed = 2, (24, 22), 1500, 4, 5
+    H0 = np.array([[0.012, 0.004], [0.004, 0.015]])
+    D = np.array([[0.3, -0.5], [-0.5, 0.8]]) * 1e-3
+    lo_r = tuple(np.array(_h_range(H0)[0]) * 0.9)
+    hi_r = tuple(np.array(_h_range(H0)[1]) * 1.1)
+    rng = np.random.default_rng(1050)
+    X = rng.random((N, d))
+    y = np.cos(2 * X[:, 0] * X[:, 1] + X[:, 0]) + 0.3 * rng.standard_normal(N)
+    plan = make_plan(d, 1, M, lo_r, hi_r, 1e-10, "fp64", n_max=N, max_weights=16)
+    plan.set_points(to_dev(X))
+    Y = to_dev(y[:, None])
+    t = torch.zeros((), dtype=torch.float64, requires_grad=True)
+    H = torch.as_tensor(H0) + t * torch.as_tensor(D)
+    g = GCVFullH.apply(H, Y, plan, Np, seed)
+    g.backward()
+    e = 1e-2
+    up = plan.cv_full(H0 + e * D, Y, Np, seed=seed)["gcv"][0, 0].item()
+    dn = plan.cv_full(H0 - e * D, Y, Np, seed=seed)["gcv"][0, 0].item()
+    fd = (up - dn) / (2 * e)
+    print(f"autograd dGCV/dt {t.grad.item():.8e}, central differences {fd:.8e}")
+    assert t.grad.item() == pytest.approx(fd, rel=1e-5)
