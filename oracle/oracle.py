@@ -686,22 +686,23 @@ def gcv_H_gradient(X, y, H, order, M, lo, hi, Wp, include=None, step: float = 1e
     return np.array(out)
 
 
-def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None, binned=None) -> np.ndarray:
+def gcv_y_gradient(X, y, h, order, M, lo, hi, Wp, include=None, binned=None, H=None) -> np.ndarray:
     """d GCV / dy of ``gcv_criterion`` from its definition: the fitted
     values are yhat = S y with the smoother S (samples to samples through the
     grid fit and the interpolation) built column by column from the fits of
     the unit responses; the Girard ratios do not depend on y, so with
     r = (y - S y) on the supported samples I,
-    d GCV / dy = 2 / (N_I rho_bar^2) (r - S_I^T r_I)."""
+    d GCV / dy = 2 / (N_I rho_bar^2) (r - S_I^T r_I).  H: a full bandwidth
+    matrix in place of h (see ``fit``)."""
     y = np.asarray(y).reshape(-1)
     N = len(y)
     X = np.asarray(X, dtype=np.float64).reshape(N, -1)
     d = X.shape[1]
     gp = grid_points(M, lo, hi)
     mh, S, T, r0, ill = fit(X, np.concatenate([np.eye(N), Wp], axis=1), h, order, gp, return_all=True,
-                            binned=binned)
+                            binned=binned, H=H)
     if include is None:
-        include = supported(~ill & resolved(S, h, order, d), M, lo, hi, X)
+        include = supported(~ill & resolved(S, _equilibration(h, H, d), order, d), M, lo, hi, X)
     include = np.asarray(include, dtype=bool)
     F = interp(mh, M, lo, hi, X)
     Smat = F[include, :N]                       # rows of the supported samples

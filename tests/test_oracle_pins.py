@@ -823,6 +823,32 @@ def test_gcv_H_gradient_diagonal_matches_log_h_gradient(orc):
     assert abs(gH[1]) > 1e-3 * np.abs(gH).max()
 
 
+def test_gcv_y_gradient_full_h(orc):
+    """With a full bandwidth matrix GCV is still quadratic in y: the y
+    gradient from the explicit smoother matches central differences; at a
+    diagonal H = diag(h^2) it is the product kernel's y gradient at h."""
+    rng = np.random.default_rng(18)
+    N = 150
+    X = rng.random((N, 2))
+    y = np.sin(3 * (X[:, 0] + 0.5 * X[:, 1])) + 0.2 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi = (9, 8), (0.0, 0.0), (1.0, 1.0)
+    H = np.array([[0.03, 0.012], [0.012, 0.04]])
+    inc = orc.support(X, None, 1, M, lo, hi, H=H)[0]
+    g = orc.gcv_y_gradient(X, y, None, 1, M, lo, hi, Wp, include=inc, H=H)
+    for i in range(0, N, 17):
+        e = np.zeros(N)
+        e[i] = 0.05
+        fd = (orc.gcv_criterion(X, y + e, None, 1, M, lo, hi, Wp, inc, H=H)
+              - orc.gcv_criterion(X, y - e, None, 1, M, lo, hi, Wp, inc, H=H)) / 0.1
+        assert g[i] == pytest.approx(fd, rel=1e-7, abs=1e-12)
+    h = np.array([0.16, 0.19])
+    inc_d = orc.support(X, h, 1, M, lo, hi)[0]
+    gd = orc.gcv_y_gradient(X, y, None, 1, M, lo, hi, Wp, include=inc_d, H=np.diag(h ** 2))
+    gh = orc.gcv_y_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc_d)
+    np.testing.assert_allclose(gd, gh, rtol=1e-9, atol=1e-12 * np.abs(gh).max())
+
+
 def test_gcv_gradients_complex_response(orc):
     """Complex y: GCV uses |y - yhat|^2; the gradient d/dRe y + i d/dIm y
     matches central differences along the real and the imaginary axis, and
