@@ -378,11 +378,12 @@ fkr_status fkr_gcv_grad(fkr_plan* plan, const double* h, int y_complex, const vo
  * row-major upper-triangle order (dH_dev: d (d + 1) / 2 doubles; an
  * off-diagonal entry moves H_pq and H_qp together).  The multipliers'
  * derivative follows the Hermite recurrence of fkr_fit_full forward, with
- * the Gaussian factor and the equilibration by sqrt(diag H); dfit_dev
- * [d (d + 1) / 2][ny + Np][M^d] as in fkr_gcv_grad.  No gradient in y. */
+ * the Gaussian factor and the equilibration by sqrt(diag H); dy_dev
+ * (optional) as in fkr_gcv_grad, its adjoint with the full-H multipliers;
+ * dfit_dev [d (d + 1) / 2][ny + Np][M^d] as in fkr_gcv_grad. */
 fkr_status fkr_gcv_grad_full(fkr_plan* plan, const double* H, int y_complex, const void* Y_dev, int y_type,
-                             int Np, uint64_t seed, double* gcv_dev, double* dH_dev, double* dfit_dev,
-                             void* stream);
+                             int Np, uint64_t seed, double* gcv_dev, double* dH_dev, double* dy_dev,
+                             double* dfit_dev, void* stream);
 
 /* Variance of the fit and pointwise confidence band (Sec. 4.2, eq. 27-28;
  * Sec. 4 fkreg_interval) at one bandwidth h (d doubles).  The fit of eq. (3)

@@ -102,7 +102,7 @@ def load() -> ctypes.CDLL:
         "fkr_cv_full": ([P, I, pD, I, I, P, I, I, U64, P, P, P, P, P, P, P], I),
         "fkr_moments_full": ([P, I, pD, I, P, I, P, P, P], I),
         "fkr_gcv_grad": ([P, pD, I, P, I, I, U64, P, P, P, P, P], I),
-        "fkr_gcv_grad_full": ([P, pD, I, P, I, I, U64, P, P, P, P], I),
+        "fkr_gcv_grad_full": ([P, pD, I, P, I, I, U64, P, P, P, P, P], I),
         "fkr_predict": ([P, I, P, I64, P, I, P, P], I),
         "fkr_get_diagnostics": ([P, ctypes.POINTER(Diag)], I),
         "fkr_status_string": ([I], ctypes.c_char_p),

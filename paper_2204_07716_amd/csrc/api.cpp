@@ -1150,8 +1150,8 @@ fkr_status fkr_interval_full(fkr_plan* p, const double* H, int sig_kind, double 
 // pairs, support flags, the fit of y, the sums): c = A^{-1} e_0, u = P^T r,
 // the type-2 path of v_b = u c_b to the fine grid, the gather at the samples.
 // u uses `scratch` ([M] doubles).
-fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* scratch, double* dy,
-                  hipStream_t s) {
+fkr_status grad_y(fkr_plan* p, const double* h, const FullH* fh, int Np, int nr, int ny, double* scratch,
+                  double* dy, hipStream_t s) {
     const Geo g = make_geo(p);
     const int P = p->n_t;
     // a complex response runs as one complex function per b (real part:
@@ -1210,12 +1210,19 @@ fkr_status grad_y(fkr_plan* p, const double* h, int Np, int nr, int ny, double* 
     for (int j = 0; j < 3; ++j) { ea.B[j] = p->B[j]; ea.K[j] = p->K[j]; }
     for (int j = 0; j < p->d; ++j) { ea.h[j] = h[j]; ea.T[j] = p->T[j]; }
     ea.Btot = p->Btot;
+    ea.n_s = p->n_s;
+    ea.n_t = p->n_t;
     ea.deriv_dim = -1;
     if (p->reg_kernel) {   // the base pass left the kernel's tables at h
         ea.kdeg = 2 * p->order + 1;
         ea.ktab = at<double>(p, p->lay.ktab);
     }
-    launch_adj_combine(p->tprec, ea, P, cplx, dev_et(p), at<double>(p, p->lay.deconv), bufs[cur], bufs[1 - cur], s);
+    if (fh)
+        launch_adj_combine_full(p->tprec, ea, *fh, P, cplx, dev_es(p), dev_pidx(p), at<double>(p, p->lay.deconv),
+                                bufs[cur], bufs[1 - cur], s);
+    else
+        launch_adj_combine(p->tprec, ea, P, cplx, dev_et(p), at<double>(p, p->lay.deconv), bufs[cur], bufs[1 - cur],
+                           s);
     cur = 1 - cur;
     // band -> fine grid along dimensions d-1 .. 0 (the inverse passes of the
     // channels with the fine grid's length and no crop)
@@ -1264,7 +1271,7 @@ fkr_status grad_impl(fkr_plan* p, const double* h, const double* H, int y_comple
     if (Np < 1 || !dtheta || !dfit) return FKR_E_ARG;
     // the box kernel's steps at the support's edge have no derivative in h
     if (p->reg_kernel == FKR_REG_BOX) return FKR_E_UNSUPPORTED;
-    if (H && (p->reg_kernel || dy)) return FKR_E_UNSUPPORTED;   // full H: Gaussian, gradient in H only
+    if (H && p->reg_kernel) return FKR_E_UNSUPPORTED;   // full H: the Gaussian only
     FullH fh{};
     double heff[3] = {0.0, 0.0, 0.0};
     if (H && (st = build_full(p, H, &fh, heff)) != FKR_OK) return st;
@@ -1289,7 +1296,7 @@ fkr_status grad_impl(fkr_plan* p, const double* h, const double* H, int y_comple
         return st;
     if (dy) {
         StageTimer t(p, FKR_STAGE_REDUCE, s);
-        if ((st = grad_y(p, h, Np, nr, ny, dfit, dy, s)) != FKR_OK) return st;
+        if ((st = grad_y(p, H ? heff : h, H ? &fh : nullptr, Np, nr, ny, dfit, dy, s)) != FKR_OK) return st;
     }
     const Geo g = make_geo(p);
     double* red = at<double>(p, p->lay.red);
@@ -1356,9 +1363,9 @@ fkr_status fkr_gcv_grad(fkr_plan* p, const double* h, int y_complex, const void*
 }
 
 fkr_status fkr_gcv_grad_full(fkr_plan* p, const double* H, int y_complex, const void* Y, int y_type, int Np,
-                             uint64_t seed, double* gcv, double* dH, double* dfit, void* stream) {
+                             uint64_t seed, double* gcv, double* dH, double* dy, double* dfit, void* stream) {
     if (!H) return FKR_E_ARG;
-    return grad_impl(p, nullptr, H, y_complex, Y, y_type, Np, seed, gcv, dH, nullptr, dfit, stream);
+    return grad_impl(p, nullptr, H, y_complex, Y, y_type, Np, seed, gcv, dH, dy, dfit, stream);
 }
 
 fkr_status fkr_spline(fkr_plan* p, int nv, const double* G, double* coef, void* stream) {

@@ -294,6 +294,10 @@ void launch_adj_pack(int prec, int P, int64_t Mtot, const double* u, const doubl
                      hipStream_t s);
 void launch_adj_combine(int prec, const ExpandArgs& a, int P, int cplx, const int* et, const double* fac,
                         const void* spec, void* out, hipStream_t s);
+// k_adj_combine with the multipliers of a full bandwidth matrix fh (es, pidx:
+// the s-channel exponents and the t-to-s channel map)
+void launch_adj_combine_full(int prec, const ExpandArgs& a, const FullH& fh, int P, int cplx, const int* es,
+                             const int* pidx, const double* fac, const void* spec, void* out, hipStream_t s);
 void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int Np, int64_t n_jobs_max,
                        const int32_t* jobs, const uint32_t* loc, const void* frac, const void* X,
                        const int32_t* perm, const void* fgrid, int ny, int part, const double* yfit, const float* sup,

@@ -1589,16 +1589,12 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_n(ExpandArgs a, const
 // equilibration prod_k s_k^{a_k}, s_k = sqrt(H_kk)), by forward
 // differentiation of the recurrence: dM_c = (G / sc_c) (dm_c - m_c
 // (w^T dH w / 2 + sum_k a_k dH_kk / (2 H_kk))).
-template <typename T, bool DER>
-__global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, FullH fh, const int* es,
-                                                                const int* pidx, const typename V2<T>::t* spec,
-                                                                typename V2<T>::t* out) {
-    __shared__ double mf[kMaxChannels][kExpandThreads];
-    __shared__ double dmf[DER ? kMaxChannels : 1][kExpandThreads];
-    const int tid = threadIdx.x;
-    const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && a.ill_clear) *a.ill_clear = 0ull;
-    if (n >= a.Btot) return;
+// The multipliers M_c of every s-channel at band index n into mf[c][tid]
+// (DER: their derivatives along fh.dH); returns the band index of -n.
+template <bool DER>
+__device__ __forceinline__ unsigned full_multipliers(const ExpandArgs& a, const FullH& fh, const int* es, int64_t n,
+                                                     int tid, double (*mf)[kExpandThreads],
+                                                     double (*dmf)[kExpandThreads]) {
     unsigned nn = 0, rem = (unsigned)n, stride = 1;
     double w[3] = {0.0, 0.0, 0.0};
     double tprod = 1.0;
@@ -1655,6 +1651,20 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, Fu
         else
             mf[c][tid] *= G / sc;
     }
+    return nn;
+}
+
+template <typename T, bool DER>
+__global__ __launch_bounds__(kExpandThreads) void k_expand_full(ExpandArgs a, FullH fh, const int* es,
+                                                                const int* pidx, const typename V2<T>::t* spec,
+                                                                typename V2<T>::t* out) {
+    __shared__ double mf[kMaxChannels][kExpandThreads];
+    __shared__ double dmf[DER ? kMaxChannels : 1][kExpandThreads];
+    const int tid = threadIdx.x;
+    const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && a.ill_clear) *a.ill_clear = 0ull;
+    if (n >= a.Btot) return;
+    const unsigned nn = full_multipliers<DER>(a, fh, es, n, tid, mf, dmf);
     for (int c = (int)blockIdx.y; c < a.ncp; c += (int)gridDim.y) {
         double acc_re = 0.0, acc_im = 0.0;
         for (int half = 0; half < 2; ++half) {
@@ -2785,6 +2795,66 @@ __global__ __launch_bounds__(256) void k_adj_combine(ExpandArgs a, int P, int cp
             m *= mloc[j][et[3 * b + j]];
             deg += et[3 * b + j];
         }
+        double xr = vr * m, xi = vi * m;
+        switch (deg & 3) {   // multiply by (-i)^deg
+            case 1: { const double t0 = xr; xr = xi; xi = -t0; break; }
+            case 2: xr = -xr; xi = -xi; break;
+            case 3: { const double t0 = xr; xr = -xi; xi = t0; break; }
+            default: break;
+        }
+        gr += xr;
+        gi += xi;
+    }
+    typename V2<T>::t o;
+    o.x = (T)(gr * dec);
+    o.y = (T)(gi * dec);
+    out[n] = o;
+}
+
+// The same band spectrum for a full bandwidth matrix: G(n) = prod_j
+// fac_j(e_j) sum_b (-i)^{|b|} M_{s(b)}(w_n) V_b(n) with M the forward
+// channels' multipliers (the multivariate Hermite recurrence, the Gaussian
+// factor and the equilibration) of the s-channel of multi-index b.
+template <typename T>
+__global__ __launch_bounds__(kExpandThreads) void k_adj_combine_full(ExpandArgs a, FullH fh, int P, int cplx,
+                                                                     const int* es, const int* pidx,
+                                                                     const double* fac,
+                                                                     const typename V2<T>::t* spec,
+                                                                     typename V2<T>::t* out) {
+    __shared__ double mf[kMaxChannels][kExpandThreads];
+    __shared__ double dmf[1][kExpandThreads];
+    const int tid = threadIdx.x;
+    const int64_t n = (int64_t)blockIdx.x * kExpandThreads + tid;
+    if (n >= a.Btot) return;
+    const int npv = cplx ? P : (P + 1) / 2;
+    const unsigned nn = full_multipliers<false>(a, fh, es, n, tid, mf, dmf);
+    double dec = 1.0;
+    unsigned rem = (unsigned)n;
+    int64_t foff = 0;
+    for (int j = 0; j < a.d; ++j) {
+        const unsigned bj = (unsigned)a.B[j];
+        const unsigned qj = rem / bj;
+        dec *= fac[foff + (int64_t)(rem - qj * bj)];
+        rem = qj;
+        foff += a.B[j];
+    }
+    double gr = 0.0, gi = 0.0;
+    for (int b = 0; b < P; ++b) {
+        double vr, vi;
+        if (cplx) {
+            const typename V2<T>::t zb = spec[n * npv + b];
+            vr = (double)zb.x;
+            vi = (double)zb.y;
+        } else {
+            const typename V2<T>::t zn = spec[n * npv + (b >> 1)];
+            const typename V2<T>::t zm = spec[(int64_t)nn * npv + (b >> 1)];
+            if ((b & 1) == 0) { vr = 0.5 * ((double)zn.x + (double)zm.x); vi = 0.5 * ((double)zn.y - (double)zm.y); }
+            else { vr = 0.5 * ((double)zn.y + (double)zm.y); vi = -0.5 * ((double)zn.x - (double)zm.x); }
+        }
+        const int si = pidx[b * kMaxP];
+        int deg = 0;
+        for (int k = 0; k < a.d; ++k) deg += es[3 * si + k];
+        const double m = mf[si][tid];
         double xr = vr * m, xi = vi * m;
         switch (deg & 3) {   // multiply by (-i)^deg
             case 1: { const double t0 = xr; xr = xi; xi = -t0; break; }
@@ -4075,6 +4145,19 @@ void launch_adj_combine(int prec, const ExpandArgs& a, int P, int cplx, const in
     else
         k_adj_combine<float><<<nblk(a.Btot), 256, 0, s>>>(a, P, cplx, et, fac, static_cast<const float2*>(spec),
                                                           static_cast<float2*>(out));
+}
+
+void launch_adj_combine_full(int prec, const ExpandArgs& a, const FullH& fh, int P, int cplx, const int* es,
+                             const int* pidx, const double* fac, const void* spec, void* out, hipStream_t s) {
+    const unsigned nb = (unsigned)((a.Btot + kExpandThreads - 1) / kExpandThreads);
+    if (prec == FKR_F64)
+        k_adj_combine_full<double><<<nb, kExpandThreads, 0, s>>>(a, fh, P, cplx, es, pidx, fac,
+                                                                  static_cast<const double2*>(spec),
+                                                                  static_cast<double2*>(out));
+    else
+        k_adj_combine_full<float><<<nb, kExpandThreads, 0, s>>>(a, fh, P, cplx, es, pidx, fac,
+                                                                 static_cast<const float2*>(spec),
+                                                                 static_cast<float2*>(out));
 }
 
 void launch_adj_gather(const Geo& g, int prec, int tprec, int kernel, int Np, int64_t n_jobs_max,

@@ -99,8 +99,9 @@ class GCVLogH(torch.autograd.Function):
 
 class GCVFullH(torch.autograd.Function):
     """GCV (eq. 22) of one real response as a function of a full bandwidth
-    matrix H (d x d, symmetric), with the library's hand-written gradient as
-    its backward: ``GCVFullH.apply(H, Y, plan, Np, seed)``.  The gradient is
+    matrix H (d x d, symmetric) and of the response y, with the library's
+    hand-written gradients as its backward: ``GCVFullH.apply(H, Y, plan, Np,
+    seed)`` (either may require grad).  The gradient in H is
     returned as a symmetric matrix G with G_pq = dGCV/dH_pq for H_pq and H_qp
     taken as separate entries (half the symmetric derivative off the
     diagonal), so that a symmetric step dH changes GCV by sum(G * dH)."""
@@ -108,7 +109,8 @@ class GCVFullH(torch.autograd.Function):
     @staticmethod
     def forward(ctx, H, Y, plan, Np, seed):
         Hn = H.detach().to(torch.float64).cpu().numpy()
-        out = plan.gcv_grad_full(Hn, Y.detach(), Np, seed)
+        out = plan.gcv_grad_full(Hn, Y.detach(), Np, seed, want_dy=Y.requires_grad)
+        dy = out["dy"].to(Y.dtype).reshape(Y.shape) if out["dy"] is not None else None   # complex: dRe + i dIm
         d = Hn.shape[0]
         g = torch.zeros((d, d), dtype=torch.float64)
         k = 0
@@ -118,13 +120,14 @@ class GCVFullH(torch.autograd.Function):
                 g[p, q] = dH[k] if p == q else 0.5 * dH[k]
                 g[q, p] = g[p, q]
                 k += 1
-        ctx.save_for_backward(g.to(H.device, H.dtype))
+        ctx.save_for_backward(g.to(H.device, H.dtype), dy)
         return out["gcv"][0].to(H.device, H.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):
-        (g,) = ctx.saved_tensors
-        return grad_out * g, None, None, None, None
+        g, dy = ctx.saved_tensors
+        g_y = grad_out.to(dy.device, dy.dtype) * dy if dy is not None else None
+        return grad_out * g, g_y, None, None, None
 
 
 def _plan_desc(d, order, M, lo, hi, h_min, h_max, eps, precision, kernel, sigma, n_max, max_weights,
@@ -484,10 +487,10 @@ class Plan:
             dy = torch.view_as_complex(dy) if cplx else dy[:, 0]
         return {"gcv": gcv, "dlogh": dlogh, "dy": dy, "dfit": dfit}
 
-    def gcv_grad_full(self, H, Y: torch.Tensor, Np: int, seed: int = 0) -> dict:
+    def gcv_grad_full(self, H, Y: torch.Tensor, Np: int, seed: int = 0, want_dy: bool = True) -> dict:
         """GCV at the full bandwidth matrix H (d x d) for one response with Np
-        Philox probes, its gradient in the upper-triangle entries H_pq (p <= q,
-        row-major), and d m_hat / d H_pq of y and the probes."""
+        Philox probes, its gradients in the upper-triangle entries H_pq (p <= q,
+        row-major) and in y [N], and d m_hat / d H_pq of y and the probes."""
         Hb = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(self.d, self.d))
         Yr, q, cplx = _real_view(Y.reshape(-1, 1))
         assert q == 1, "one response column"
@@ -496,10 +499,14 @@ class Plan:
         gcv = torch.empty(1, dtype=torch.float64, device=self.device)
         dH = torch.empty(nd, dtype=torch.float64, device=self.device)
         dfit = torch.empty((nd, ny + Np, self.Mtot), dtype=torch.float64, device=self.device)
+        dy = torch.empty((Yr.shape[0], ny), dtype=torch.float64, device=self.device) if want_dy else None
         check(self.lib.fkr_gcv_grad_full(self._plan, _hptr(Hb), cplx, _ptr(Yr), _dtype_code(Yr), Np,
-                                         ctypes.c_uint64(seed), _ptr(gcv), _ptr(dH), _ptr(dfit), _stream()),
+                                         ctypes.c_uint64(seed), _ptr(gcv), _ptr(dH), _ptr(dy), _ptr(dfit),
+                                         _stream()),
               "fkr_gcv_grad_full")
-        return {"gcv": gcv, "dH": dH, "dfit": dfit}
+        if dy is not None:
+            dy = torch.view_as_complex(dy) if cplx else dy[:, 0]
+        return {"gcv": gcv, "dH": dH, "dy": dy, "dfit": dfit}
 
     # -- prediction and inference ---------------------------------------
     def interval(self, h, sigma2, mhat: Optional[torch.Tensor] = None, alpha: float = 0.05, H=None):

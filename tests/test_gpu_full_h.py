@@ -289,6 +289,46 @@ def test_full_h_gcv_grad_matches_oracle(orc):
                                atol=1e-10 * np.abs(gl).max())
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_full_h_gcv_y_gradient_matches_oracle(orc, cplx):
+    """GCV gradient in y at a full bandwidth matrix (the adjoint of the
+    smoother: residuals scattered to the grid, the full-H multipliers with
+    the conjugate phase, the type-2 transform to the samples) against the
+    oracle's explicit smoother of the full-H fits; real and complex y.  At a
+    diagonal H it is fkr_gcv_grad's y gradient at h = sqrt(diag H)."""
+    d, order, M, N, Np, seed = 2, 1, (26, 24), 500, 4, 93
+    H = np.array([[0.014, 0.006], [0.006, 0.018]])
+    Hd = np.diag([0.013, 0.017])
+    lo_r = tuple(np.minimum(_h_range(H)[0], _h_range(Hd)[0]) * 0.99)
+    hi_r = tuple(np.maximum(_h_range(H)[1], _h_range(Hd)[1]) * 1.01)
+    rng = np.random.default_rng(1045 + cplx)
+    X = rng.random((N, d))
+    y = np.sin(3 * (X[:, 0] + 0.5 * X[:, 1])) + 0.3 * rng.standard_normal(N)
+    if cplx:
+        y = y + 1j * (np.cos(2 * X[:, 1]) + 0.3 * rng.standard_normal(N))
+    plan = make_plan(d, order, M, lo_r, hi_r, 1e-10, "fp64", n_max=N, max_weights=16)
+    plan.set_points(to_dev(X))
+    Y = torch.as_tensor(y[:, None]).to("cuda")
+    out = plan.gcv_grad_full(H, Y, Np, seed)
+    Wp = orc.probes(seed, N, Np)
+    lo, hi = (0.0,) * d, (1.0,) * d
+    inc = orc.support(X, None, order, M, lo, hi, H=H)[0]
+    assert inc.all()
+    ref = orc.gcv_y_gradient(X, y, None, order, M, lo, hi, Wp, include=inc, H=H)
+    got = out["dy"].cpu().numpy().reshape(-1)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"full-H d GCV / dy ({'complex' if cplx else 'real'} y): rel err {err:.2e}")
+    assert err < 1e-9
+    gd = plan.gcv_grad_full(Hd, Y, Np, seed)["dy"].cpu().numpy()
+    gh = plan.gcv_grad(tuple(np.sqrt(np.diag(Hd))), Y, Np, seed)["dy"].cpu().numpy()
+    assert np.abs(gd - gh).max() <= 1e-10 * np.abs(gh).max()
+    # dy is optional: the same GCV and H gradient without it
+    nody = plan.gcv_grad_full(H, Y, Np, seed, want_dy=False)
+    assert nody["dy"] is None
+    assert nody["gcv"].item() == pytest.approx(out["gcv"].item(), rel=1e-13)   # atomic sums: rounding order
+    np.testing.assert_allclose(nody["dH"].cpu().numpy(), out["dH"].cpu().numpy(), rtol=1e-9)
+
+
 def test_full_h_autograd():
     """GCVFullH through torch.autograd: the gradient of GCV(H(t)) for a
     symmetric path H(t) = H0 + t D equals sum(G * D), checked against central
@@ -315,3 +355,15 @@ def test_full_h_autograd():
     fd = (up - dn) / (2 * e)
     print(f"autograd dGCV/dt {t.grad.item():.8e}, central differences {fd:.8e}")
     assert t.grad.item() == pytest.approx(fd, rel=1e-5)
+    # the response: GCV is quadratic in y, so central differences along a
+    # direction v are exact up to rounding
+    Yg = Y[:, 0].clone().requires_grad_(True)
+    GCVFullH.apply(torch.as_tensor(H0), Yg, plan, Np, seed).backward()
+    v = to_dev(np.random.default_rng(7).standard_normal(N))
+    e = 1e-2
+    up = plan.cv_full(H0, (Y[:, 0] + e * v)[:, None], Np, seed=seed)["gcv"][0, 0].item()
+    dn = plan.cv_full(H0, (Y[:, 0] - e * v)[:, None], Np, seed=seed)["gcv"][0, 0].item()
+    fd_y = (up - dn) / (2 * e)
+    dd = float((Yg.grad * v).sum())
+    print(f"autograd dGCV/dy . v {dd:.8e}, central differences {fd_y:.8e}")
+    assert dd == pytest.approx(fd_y, rel=1e-7)
