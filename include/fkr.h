@@ -127,9 +127,9 @@ typedef struct {
                                they differ from the exact kernel sums by the
                                kernel's aliasing, which shrinks with
                                (delta / h)^(s+1) for a kernel with s
-                               continuous derivatives; fkr_fit_full needs
-                               the Gaussian and fkr_gcv_grad a kernel other
-                               than the box (FKR_E_UNSUPPORTED otherwise) */
+                               continuous derivatives; the calls taking a
+                               full H need the Gaussian
+                               (FKR_E_UNSUPPORTED otherwise) */
 } fkr_plan_desc;
 
 /* Geometry chosen by the planner (read-only). */
@@ -343,8 +343,11 @@ fkr_status fkr_variance_full(fkr_plan* plan, const double* H, int y_complex, con
  * spectra multiplied by the derivative of the Gaussian moment multipliers,
  * d/dtheta_j [He_a(u) exp(-u^2/2)] = -u He_{a+1}(u) exp(-u^2/2), u = h_j w_j
  * (a compact kernel: the transform of the derivative of its sampled moment
- * kernel, -((1 + a) K(v) + v K'(v)) v^a / h_j, v = u / h_j; the box has
- * none, FKR_E_UNSUPPORTED).
+ * kernel, -((1 + a) K(v) + v K'(v)) v^a / h_j, v = u / h_j, K' = 0 inside
+ * the box kernel's support.  The binned box fit weighs the same window
+ * equally for every h between the bandwidths where a grid offset crosses
+ * the support's edge, so its GCV is piecewise constant there and its log-h
+ * gradient zero up to rounding; at those bandwidths GCV jumps).
  * With the supported set I held fixed, dRSS = -2 sum_I r_i d yhat_i and
  * d rho_p = -sum_I w_pi d what_pi / sum_I w_pi^2, so
  * d GCV / d theta_j = GCV (dRSS / RSS - 2 d rho_bar / rho_bar).

@@ -275,7 +275,6 @@ fkr_status run_channels(fkr_plan* p, const double* h, int nr, unsigned long long
     a.ill_clear = ill_clear;
     a.deriv_dim = deriv_dim;
     if (p->reg_kernel && !full) {
-        if (deriv_dim >= 0 && p->reg_kernel == FKR_REG_BOX) return FKR_E_UNSUPPORTED;   // steps at |u| = 1
         a.kdeg = 2 * p->order + 1;
         a.ktab = at<double>(p, p->lay.ktab);
         launch_ktab(a, p->delta, p->reg_kernel, ksq ? 1 : 0, at<double>(p, p->lay.ktab), s);
@@ -1269,8 +1268,6 @@ fkr_status grad_impl(fkr_plan* p, const double* h, const double* H, int y_comple
     if (!H && (st = check_h(p, 1, h)) != FKR_OK) return st;
     if ((!Y && p->N > 0) || (y_complex != 0 && y_complex != 1) || !valid_type(y_type)) return FKR_E_ARG;
     if (Np < 1 || !dtheta || !dfit) return FKR_E_ARG;
-    // the box kernel's steps at the support's edge have no derivative in h
-    if (p->reg_kernel == FKR_REG_BOX) return FKR_E_UNSUPPORTED;
     if (H && p->reg_kernel) return FKR_E_UNSUPPORTED;   // full H: the Gaussian only
     FullH fh{};
     double heff[3] = {0.0, 0.0, 0.0};

@@ -1721,8 +1721,9 @@ __device__ __forceinline__ double compact_kernel(int kind, double u) {
     }
 }
 
-// u K'(u) of the compact kernels (the box's is zero inside the support; its
-// steps at |u| = 1 have no derivative, and callers refuse it)
+// u K'(u) of the compact kernels (the box's is zero inside the support; the
+// sampled box kernel changes only by steps, where a grid offset crosses
+// |u| = 1, which a derivative in h does not see)
 __device__ __forceinline__ double compact_kernel_udu(int kind, double u) {
     if (fabs(u) > 1.0) return 0.0;
     const double q = 1.0 - u * u;

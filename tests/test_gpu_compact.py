@@ -55,14 +55,13 @@ def test_compact_moments_and_fit_match_binned_oracle(orc, name, d, order, prec, 
 
 
 def test_compact_kernel_unsupported_calls():
-    """A full H needs the Gaussian; the box kernel's steps at the edge of its
-    support have no derivative in h, so it has no GCV gradient."""
+    """A full H needs the Gaussian."""
     from paper_2204_07716_amd._lib import FKR_E_UNSUPPORTED, FkrError
     N = 500
     X = np.random.default_rng(4).random((N, 2))
     Y = to_dev(np.zeros((N, 1)), torch.float32)
     for name, call in (("epanechnikov", lambda pl: pl.fit_full(np.diag([0.01, 0.01]), Y)),
-                       ("box", lambda pl: pl.gcv_grad((0.1, 0.1), Y, 2))):
+                       ("box", lambda pl: pl.gcv_grad_full(np.diag([0.01, 0.01]), Y, 2))):
         plan = make_plan(2, 1, (32, 32), (0.05, 0.05), (0.15, 0.15), 1e-6, "fp32", n_max=N, max_weights=16,
                          tprec="fp64", reg_kernel=name)
         plan.set_points(to_dev(X, torch.float32))
@@ -71,13 +70,14 @@ def test_compact_kernel_unsupported_calls():
         assert e.value.status == FKR_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("name", ["triangle", "epanechnikov", "triweight"])
+@pytest.mark.parametrize("name", ["box", "triangle", "epanechnikov", "triweight"])
 def test_compact_gcv_grad_matches_oracle(orc, name):
     """GCV gradients (eq. 22) with a compact kernel: in log h from the
     derivative of the sampled kernel table, against central differences of
     the oracle's GCV under the binned approximation (h at non-integer
     multiples of the spacing, away from the kinks where a grid offset enters
-    the support); in y through the adjoint with the kernel's tables, against
+    the support; the box's binned GCV is flat there, so both are zero up to
+    rounding); in y through the adjoint with the kernel's tables, against
     the oracle's explicit smoother.  FP64, same Philox probes."""
     d, Np, seed = 2, 4, 37
     M = (30, 26)
@@ -101,6 +101,10 @@ def test_compact_gcv_grad_matches_oracle(orc, name):
         if part == "logh":
             gl = out["dlogh"].cpu().numpy()
             ref = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc, step=1e-4, binned=binned)
+            if name == "box":
+                print(f"box: d GCV / d log h {gl} / {ref} (GCV {ref_g:.6e})")
+                assert np.abs(gl).max() <= 1e-9 * ref_g and np.abs(ref).max() <= 1e-9 * ref_g
+                continue
             err = np.abs(gl - ref).max() / np.abs(ref).max()
             print(f"{name}: d GCV / d log h {gl} / {ref}; rel err {err:.2e}")
             assert err < 1e-6

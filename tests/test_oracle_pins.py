@@ -786,6 +786,31 @@ def test_gcv_gradients_binned_compact_kernel(orc):
     np.testing.assert_allclose(g1, g2, rtol=2e-5, atol=2e-5 * np.abs(g1).max())
 
 
+def test_gcv_binned_box_is_flat_between_jumps(orc):
+    """The binned box kernel weighs the grid offsets |m delta| <= h equally,
+    and a local polynomial fit does not change when all its weights scale
+    together or when its monomials are rescaled (the equilibration), so the
+    GCV does not depend on h until an offset crosses the support's edge,
+    where it jumps."""
+    rng = np.random.default_rng(19)
+    N = 150
+    X = rng.random((N, 2))
+    y = np.sin(4 * X[:, 0]) * np.cos(2 * X[:, 1]) + 0.2 * rng.standard_normal(N)
+    Wp = rng.standard_normal((N, 3))
+    M, lo, hi = (9, 8), (0.0, 0.0), (1.0, 1.0)
+    delta = [1.0 / 8, 1.0 / 7]
+    binned = ("box", delta, [24, 22])
+    h = np.array([2.3 / 8, 2.4 / 7])
+    inc = orc.support(X, h, 1, M, lo, hi, binned=binned)[0]
+    g0 = orc.gcv_criterion(X, y, h, 1, M, lo, hi, Wp, inc, binned=binned)
+    g1 = orc.gcv_criterion(X, y, h * 1.2, 1, M, lo, hi, Wp, inc, binned=binned)      # offsets 2 delta still inside
+    g2 = orc.gcv_criterion(X, y, h * 1.35, 1, M, lo, hi, Wp, inc, binned=binned)     # 3 delta enters
+    assert g1 == pytest.approx(g0, rel=1e-12)
+    assert abs(g2 / g0 - 1) > 1e-4
+    gl = orc.gcv_log_h_gradient(X, y, h, 1, M, lo, hi, Wp, include=inc, step=1e-3, binned=binned)
+    assert np.abs(gl).max() <= 1e-9 * g0
+
+
 def test_gcv_full_h_diagonal_reduces_to_product_kernel(orc):
     """A diagonal bandwidth matrix H = diag(h^2) gives the product-kernel
     GCV at h (the full-H moments by NumPy sums, the diagonal ones by the C
