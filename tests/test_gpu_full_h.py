@@ -329,6 +329,36 @@ def test_full_h_gcv_y_gradient_matches_oracle(orc, cplx):
     np.testing.assert_allclose(nody["dH"].cpu().numpy(), out["dH"].cpu().numpy(), rtol=1e-9)
 
 
+def test_full_h_gcv_gradients_3d(orc):
+    """Both GCV gradients at a 3-D full bandwidth matrix with three nonzero
+    off-diagonal entries (six directions of the Hermite recurrence's
+    derivative; the adjoint with the 3-D multipliers): in H against central
+    differences of the oracle's GCV, in y against its explicit smoother."""
+    d, order, M, N, Np, seed = 3, 1, (14, 13, 12), 700, 3, 95
+    H = np.array([[0.030, 0.010, -0.008], [0.010, 0.025, 0.006], [-0.008, 0.006, 0.028]])
+    lo_r, hi_r = _h_range(H)
+    rng = np.random.default_rng(1047)
+    X = rng.random((N, d))
+    y = np.sin(2 * (X[:, 0] + X[:, 1] - X[:, 2])) + 0.3 * rng.standard_normal(N)
+    plan = make_plan(d, order, M, lo_r, hi_r, 1e-10, "fp64", n_max=N, max_weights=16)
+    plan.set_points(to_dev(X))
+    out = plan.gcv_grad_full(H, to_dev(y[:, None]), Np, seed)
+    Wp = orc.probes(seed, N, Np)
+    lo, hi = (0.0,) * d, (1.0,) * d
+    inc = orc.support(X, None, order, M, lo, hi, H=H)[0]
+    ref_g = orc.gcv_criterion(X, y, None, order, M, lo, hi, Wp, inc, H=H)
+    ref_H = orc.gcv_H_gradient(X, y, H, order, M, lo, hi, Wp, include=inc, step=1e-4)
+    ref_y = orc.gcv_y_gradient(X, y, None, order, M, lo, hi, Wp, include=inc, H=H)
+    got_H = out["dH"].cpu().numpy()
+    got_y = out["dy"].cpu().numpy()
+    e_H = np.abs(got_H - ref_H).max() / np.abs(ref_H).max()
+    e_y = np.abs(got_y - ref_y).max() / np.abs(ref_y).max()
+    print(f"3-D full H ({inc.sum()} of {N} supported): gcv {out['gcv'].item():.10e} / {ref_g:.10e}; "
+          f"dGCV/dH rel err {e_H:.2e}; dGCV/dy rel err {e_y:.2e}")
+    assert out["gcv"].item() == pytest.approx(ref_g, rel=1e-9)
+    assert e_H < 1e-6 and e_y < 1e-9
+
+
 def test_full_h_autograd():
     """GCVFullH through torch.autograd: the gradient of GCV(H(t)) for a
     symmetric path H(t) = H0 + t D equals sum(G * D), checked against central
