@@ -322,6 +322,11 @@ def test_full_h_gcv_y_gradient_matches_oracle(orc, cplx):
     gd = plan.gcv_grad_full(Hd, Y, Np, seed)["dy"].cpu().numpy()
     gh = plan.gcv_grad(tuple(np.sqrt(np.diag(Hd))), Y, Np, seed)["dy"].cpu().numpy()
     assert np.abs(gd - gh).max() <= 1e-10 * np.abs(gh).max()
+    if cplx:   # GCV of a complex y is that of its real part plus that of its imaginary part
+        parts = [plan.gcv_grad_full(H, to_dev(v[:, None]), Np, seed, want_dy=False) for v in (y.real, y.imag)]
+        assert out["gcv"].item() == pytest.approx(sum(q["gcv"].item() for q in parts), rel=1e-12)
+        np.testing.assert_allclose(out["dH"].cpu().numpy(), sum(q["dH"].cpu().numpy() for q in parts),
+                                   rtol=1e-10, atol=1e-12 * np.abs(out["dH"].cpu().numpy()).max())
     # dy is optional: the same GCV and H gradient without it
     nody = plan.gcv_grad_full(H, Y, Np, seed, want_dy=False)
     assert nody["dy"] is None
